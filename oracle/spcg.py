@@ -1,0 +1,106 @@
+"""Algorithm 1 (SPCG) and full-data PCG in FP64 (test infrastructure).
+
+Stage I runs PCG for a_i iterations on each sketched problem
+(S_i X, S_i Y), warm-started from the previous stage's output (Sec. 2.2 and
+the warm-start relation at the start of Sec. 3); Stage II runs PCG on the
+full problem (X, Y) from the Stage I result.  One preconditioner
+H_hat = R^T R, from the QR factor of S_hat X, serves every solve.
+
+Readings (where the paper leaves a choice open):
+
+* schedule: m_i = m0 * growth^(i-1) while m_i < N (or <= m_max); the paper's
+  experiments use m0 = 8d, growth 2 and m_K = N/2 (Sec. 4), which is this
+  rule for N a power of two; the default here is m0 = 4d;
+* r = 6d rows for S_hat, a_i = 3 (Sec. 4.1), beta_0 = 0, total budget T = 100;
+* Stage II stops when sqrt(rho) <= tol * ||X x|| (see ``pcg``) or when the
+  total iteration count reaches T; tol defaults to 5e-7 so that the relative
+  prediction error ||X(x - beta_hat)|| / ||X beta_hat|| lands below 1e-6.
+"""
+import numpy as np
+
+from .linalg import householder_qr
+from .pcg import pcg
+from .sketch import nested_srht, padded_bits
+
+
+def schedule(N, d, m0=None, m_max=None, growth=2):
+    """Sketch sizes m_1 < ... < m_K (Stage I); empty if m0 >= N."""
+    m = 4 * d if m0 is None else int(m0)
+    limit = N - 1 if m_max is None else min(int(m_max), N - 1)
+    sizes = []
+    while m <= limit:
+        sizes.append(m)
+        m *= growth
+    return sizes
+
+
+def precond_from_sketch(B_hat):
+    """R with R^T R = B_hat^T B_hat / r (Householder QR of S_hat X)."""
+    r = B_hat.shape[0]
+    return householder_qr(np.asarray(B_hat, dtype=np.float64) / np.sqrt(r))
+
+
+def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
+         growth=2, history=False):
+    """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    N, d = X.shape
+    r = 6 * d if r is None else int(r)
+    sizes = schedule(N, d, m0, m_max, growth)
+    a_list = [a] * len(sizes) if np.isscalar(a) else list(a)
+    mK = sizes[-1] if sizes else 1
+    B, BY, B_hat, sk = nested_srht(X, Y, seed, mK, r)
+    R = precond_from_sketch(B_hat)
+    multi = Y.ndim == 2
+    Ys = Y if multi else Y[:, None]
+    BYs = BY if multi else BY[:, None]
+    betas, infos = [], []
+    for c in range(Ys.shape[1]):
+        x = np.zeros(d)
+        stage_x = []
+        t = 0
+        for m, ai in zip(sizes, a_list):
+            x, _ = pcg(B[:m], BYs[:m, c], 1.0 / m, R, x, ai)
+            t += ai
+            stage_x.append(x.copy())
+        x, inf2 = pcg(X, Ys[:, c], 1.0, R, x, max(T - t, 0), tol=tol, history=history)
+        betas.append(x)
+        infos.append({"stage_x": stage_x, "stage2": inf2, "T_stage1": t,
+                      "T": t + inf2["iters"]})
+    beta = np.stack(betas, axis=1) if multi else betas[0]
+    info = {"sizes": sizes, "R": R, "per_rhs": infos, "L": sk["L"], "Np": sk["Np"]}
+    return beta, info
+
+
+def full_pcg(X, Y, seed, r=None, tol=5e-7, T=100):
+    """Full-data PCG from beta_0 = 0 with the same S_hat preconditioner."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    N, d = X.shape
+    r = 6 * d if r is None else int(r)
+    _, _, B_hat, _ = nested_srht(X, Y, seed, 1, r)
+    R = precond_from_sketch(B_hat)
+    multi = Y.ndim == 2
+    Ys = Y if multi else Y[:, None]
+    betas, infos = [], []
+    for c in range(Ys.shape[1]):
+        x, inf = pcg(X, Ys[:, c], 1.0, R, np.zeros(d), T, tol=tol)
+        betas.append(x)
+        infos.append(inf)
+    beta = np.stack(betas, axis=1) if multi else betas[0]
+    return beta, {"R": R, "per_rhs": infos}
+
+
+def rel_pred_error(X, beta, beta_ref):
+    """||X (beta - beta_ref)|| / ||X beta_ref|| (columnwise max for k > 1)."""
+    X = np.asarray(X, dtype=np.float64)
+    D = X @ (np.asarray(beta, dtype=np.float64) - np.asarray(beta_ref, dtype=np.float64))
+    Rf = X @ np.asarray(beta_ref, dtype=np.float64)
+    num = np.linalg.norm(D, axis=0)
+    den = np.linalg.norm(Rf, axis=0)
+    return float(np.max(num / den))
+
+
+__all__ = ["schedule", "precond_from_sketch", "spcg", "full_pcg",
+           "rel_pred_error", "padded_bits"]
