@@ -1,0 +1,249 @@
+/*
+ * spcg.h - C ABI of the MI355X (gfx950) SPCG library.
+ *
+ * SPCG solves the ordinary least-squares problem of the linear model
+ * Y = X beta + zeta (Sec. 1, eqs. (model) and (ols) of Chen, Xie, Yang,
+ * Zheng, "Sequential Preconditioned Conjugate Gradient Method for Linear
+ * Statistical Models"):
+ *
+ *     beta_hat = argmin_u 1/2 ||Y - X u||^2,   X: N x d, full column rank.
+ *
+ * Algorithm 1: Stage I runs a_i PCG iterations on each sketched problem
+ * (S_i X, S_i Y), i = 1..K, with nested SRHT sketches of doubling size,
+ * warm-starting every stage from the previous one; Stage II runs PCG on
+ * the full problem.  All PCG solves share one preconditioner
+ * H_hat = (S_hat X)^T (S_hat X) = R^T R built from an independent sketch.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Matrices are row-major: element (i, j) of an spcg_mat lives at
+ *   data + (i * ld + j) * sizeof(element).  ld >= cols.
+ * - All data pointers (matrix data, beta, col_scale, R) are DEVICE
+ *   pointers on the context's device unless a parameter says "host".
+ * - The caller owns X, Y and beta; the library never writes X or Y.
+ *   Handles (spcg_ctx, spcg_sketch_t, spcg_precond_t) and the workspaces they
+ *   hold are owned by the library and released by the matching *_free /
+ *   spcg_ctx_destroy call.
+ * - Work is queued on the context's HIP stream; a call returns after its
+ *   work is queued, except where it must read a device scalar (stopping
+ *   tests, error checks), which synchronises that stream.
+ * - Return value: SPCG_OK (0) on success, a positive warning
+ *   (SPCG_W_NOT_CONVERGED: beta is still written) or a negative error
+ *   code.  spcg_last_error() gives a message for the last failing call on
+ *   that context.  No C++ exception crosses this interface.
+ * - One context per host thread; calls on one context are not reentrant.
+ */
+#ifndef SPCG_H
+#define SPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define SPCG_OK 0
+#define SPCG_W_NOT_CONVERGED 1   /* budget T exhausted before the stopping test passed */
+#define SPCG_E_INVALID_ARG (-1)  /* null handle/pointer or out-of-range option */
+#define SPCG_E_SHAPE (-2)        /* N <= d, m_1 <= d, r < d, k < 1, mismatched sizes */
+#define SPCG_E_DTYPE (-3)        /* unsupported or mismatched element type */
+#define SPCG_E_RANK (-4)         /* S_hat X numerically rank deficient (QR pivot test) */
+#define SPCG_E_BREAKDOWN (-5)    /* PCG breakdown: p^T s <= 0 or a non-finite scalar */
+#define SPCG_E_HIP (-6)          /* a HIP runtime call failed */
+#define SPCG_E_NOMEM (-7)        /* device allocation failed */
+
+/* ---- element types ----------------------------------------------------- */
+#define SPCG_F64 0      /* IEEE binary64 */
+#define SPCG_F32 1      /* IEEE binary32 */
+#define SPCG_BF16 2     /* bfloat16 (upper half of binary32) */
+#define SPCG_FP8E4M3 3  /* OCP float8 e4m3fn (bias 7, max 448, no inf), value = decode * col_scale[j] */
+
+typedef struct spcg_ctx spcg_ctx;
+typedef struct spcg_sketch_s spcg_sketch_t;
+typedef struct spcg_precond_s spcg_precond_t;
+
+/* A dense row-major matrix view.  col_scale is used only for SPCG_FP8E4M3
+ * (device array of cols floats, must be non-null then) and ignored
+ * otherwise. */
+typedef struct spcg_mat {
+    const void* data;
+    int32_t dtype;
+    int32_t reserved;
+    int64_t rows;
+    int64_t cols;
+    int64_t ld;
+    const float* col_scale;
+} spcg_mat;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Creates a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL selects the null stream).  The stream is borrowed,
+ * not owned. */
+int spcg_ctx_create(int device, void* hip_stream, spcg_ctx** out);
+/* Releases the context and every workspace it holds.  Outstanding
+ * sketches and preconditioners created on it must be freed first. */
+int spcg_ctx_destroy(spcg_ctx* ctx);
+/* Message of the last failing call on ctx ("" if none).  The pointer is
+ * valid until the next call on ctx. */
+const char* spcg_last_error(const spcg_ctx* ctx);
+/* Library version string (static storage). */
+const char* spcg_version(void);
+
+/* ---- sketch (Sec. 2.1 SRHT, Sec. 2.2 nested construction) --------------- */
+
+typedef struct spcg_sketch_opts {
+    uint64_t seed;    /* key of the Philox4x64-10 streams drawing D, P, pi, pi_hat */
+    int64_t m0;       /* m_1, the first sketch size (0: 4 d) */
+    int64_t m_max;    /* largest allowed m_K (0: largest m0 * growth^j < N) */
+    int64_t r;        /* rows of S_hat, the preconditioner sketch (0: 6 d) */
+    int32_t growth;   /* m_{i+1} / m_i (0: 2) */
+    int32_t hat_only; /* 1: build only S_hat X (what full-data PCG needs); K = 0 */
+} spcg_sketch_opts;
+
+/* Shape of a built sketch. */
+typedef struct spcg_sketch_info {
+    int64_t N, Np, d, k, r, K;
+    int32_t L;              /* Np = 2^L, the padded row count */
+    int32_t sketch_dtype;   /* SPCG_F64 for F64 input, SPCG_F32 otherwise */
+    int64_t ld;             /* leading dimension of the stored sketch rows */
+    int64_t m[64];          /* m_1 .. m_K */
+} spcg_sketch_info;
+
+/* Nested SRHT of (X, Y).  With N' = 2^ceil(log2 N) and X, Y zero-padded to
+ * N' rows, computes Z = H_un D P [X | Y] once (H_un the unnormalised
+ * Walsh-Hadamard matrix, D random signs, P a random permutation) and keeps
+ * the rows pi(0..m_K) (nested prefixes: S_i X = rows 0..m_i, scaled by
+ * 1/sqrt(m_i)) and pi_hat(0..r) (S_hat X, scaled by 1/sqrt(r)).
+ * X: N x d, any element type.  Y: N x k, SPCG_F64, k >= 1.
+ * Errors: SHAPE if N <= d, m_1 <= d, r < d or r > N', k < 1, or Y.rows != N.
+ * The handle owns the sketch rows; release with spcg_sketch_free. */
+int spcg_sketch(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y,
+                const spcg_sketch_opts* opts, spcg_sketch_t** out);
+int spcg_sketch_get_info(const spcg_sketch_t* sk, spcg_sketch_info* info);
+/* Stage view: A = rows 0..m_i of the stored sketch of X (unscaled),
+ * b = the same rows of the sketch of Y, *c2 = 1 / m_i, so that
+ * c2 A^T A = (S_i X)^T (S_i X).  stage in [0, K); stage = -1 returns the
+ * preconditioner sketch rows (b->data = NULL, *c2 = 1 / r).  Views borrow
+ * the sketch's memory. */
+int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* b, double* c2);
+/* Copies the sketch randomness to HOST arrays for reproducibility checks
+ * (any pointer may be NULL): slot_rows[t] = pi(t) for t < m_K,
+ * hat_rows[t] = pi_hat(t) for t < r, input_perm[k] = p(k) for k < N'
+ * (W[k] = sign(k) * X[p(k)]), sign_bits[k/8] bit (k%8) set when D_kk = -1.
+ * Synchronises the stream. */
+int spcg_sketch_export(spcg_ctx* ctx, const spcg_sketch_t* sk, int32_t* slot_rows,
+                       int32_t* hat_rows, int32_t* input_perm, uint8_t* sign_bits);
+void spcg_sketch_free(spcg_sketch_t* sk);
+
+/* Same randomness computed by the library's host code (no device needed):
+ * fills any non-null HOST array exactly as spcg_sketch_export would for a
+ * sketch with these parameters (Np = 2^L, m_K = m, r rows). */
+int spcg_sketch_tables_host(uint64_t seed, int32_t L, int64_t m, int64_t r, int32_t* slot_rows,
+                            int32_t* hat_rows, int32_t* input_perm, uint8_t* sign_bits);
+
+/* ---- preconditioner (Sec. 2.2 H_hat; Sec. 4: applied through QR) -------- */
+
+typedef struct spcg_precond_opts {
+    int32_t qr_passes; /* 0: auto (1 if the Gram's Cholesky succeeds with a
+                          diagonal ratio below 1e5, else 3); 1: Cholesky of the
+                          Gram; 2: CholeskyQR2; 3: shifted CholeskyQR3 */
+    int32_t reserved;
+} spcg_precond_opts;
+
+/* FP64 QR of S_hat X = Q R (diag(R) > 0) from the sketch's S_hat rows, and
+ * the operator H_hat^{-1} = R^{-1} R^{-T} it applies.
+ * Errors: RANK when a Cholesky pivot of the orthogonalised Gram falls
+ * below 1e-12 (relative) or is not positive. */
+int spcg_precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opts* opts,
+                       spcg_precond_t** out);
+/* Preconditioner from a caller-supplied upper-triangular R (DEVICE, d x d
+ * row-major FP64, diag(R) != 0); the library copies it. */
+int spcg_precond_from_r(spcg_ctx* ctx, const double* R, int64_t d, spcg_precond_t** out);
+/* Copies R (d x d row-major, zero below the diagonal) to a HOST array,
+ * and the number of QR passes used (may be NULL).  Synchronises. */
+int spcg_precond_export(spcg_ctx* ctx, const spcg_precond_t* pc, double* R_host, int32_t* passes);
+void spcg_precond_free(spcg_precond_t* pc);
+
+/* ---- one PCG solve (Sec. 2.2: PCG(A, b, H_hat, beta_init, a)) ---------- */
+
+typedef struct spcg_stage_opts {
+    int32_t iters;            /* iteration count (the maximum if tol > 0) */
+    int32_t refresh_gradient; /* 1: every product pass also recomputes
+                                 g = c2 A^T (b - A x) with FP64 accumulation and
+                                 the next gradient is that minus alpha s */
+    double tol;               /* 0: exactly `iters` iterations; > 0: stop once
+                                 sqrt(g^T H^-1 g) <= tol * ||sqrt(c2) A x|| */
+    int32_t check_every;      /* iterations between stopping tests (0: 1) */
+    int32_t reserved;
+} spcg_stage_opts;
+
+typedef struct spcg_stage_stats {
+    int32_t iters;       /* iterations taken */
+    int32_t converged;   /* stopping test passed (or rho reached exactly 0) */
+    double rho0;         /* g^T H^-1 g at the start (RHS 0) */
+    double rho;          /* at the end (RHS 0) */
+    double ax_norm;      /* ||sqrt(c2) A x|| at the last product pass (RHS 0) */
+    double resid_norm2;  /* c2 ||b - A x_start||^2 (RHS 0) */
+} spcg_stage_stats;
+
+/* PCG on c2 A^T A x = c2 A^T b, x = beta (DEVICE, d x k row-major FP64: in =
+ * warm start, out = iterate), preconditioned by pc.  A: m x d (any element
+ * type), b: m x k SPCG_F64.  stats may be NULL.
+ * Returns BREAKDOWN (beta holds the last good iterate) or
+ * W_NOT_CONVERGED when tol > 0 was not met within iters. */
+int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
+                   const spcg_precond_t* pc, double* beta, const spcg_stage_opts* opts,
+                   spcg_stage_stats* stats);
+
+/* ---- whole solve (Algorithm 1) ------------------------------------------ */
+
+#define SPCG_METHOD_SPCG 0      /* Algorithm 1 */
+#define SPCG_METHOD_FULL_PCG 1  /* full-data PCG from beta = 0, same preconditioner */
+
+typedef struct spcg_solve_opts {
+    spcg_sketch_opts sketch;
+    spcg_precond_opts precond;
+    int32_t method;       /* SPCG_METHOD_* */
+    int32_t a;            /* a_i for every sketched stage (0: 3) */
+    int32_t T;            /* total PCG iteration budget, Stage I + II (0: 100) */
+    int32_t check_every;  /* Stage II stopping-test interval (0: 1) */
+    double tol;           /* Stage II stopping tolerance (0: 5e-7) */
+    const int32_t* a_list;/* optional HOST array of per-stage a_i (length a_list_len) */
+    int32_t a_list_len;
+    int32_t time_phases;  /* 1: record phase times (adds stream syncs) */
+    int32_t time_products;/* 1: time every full-data product launch with events */
+    int32_t reserved;
+} spcg_solve_opts;
+
+typedef struct spcg_solve_stats {
+    int32_t K;              /* sketched stages run */
+    int32_t T_stage1;       /* Sum a_i */
+    int32_t T_stage2;       /* full-data iterations */
+    int32_t converged;
+    int32_t qr_passes;
+    int32_t product_launches;   /* full-data product launches timed */
+    double rho_final;
+    double ax_norm;
+    double t_sketch_ms, t_precond_ms, t_stage1_ms, t_stage2_ms, t_total_ms;
+    double product_ms_sum;      /* summed duration of the timed product launches */
+    double product_bytes;       /* algorithmic bytes of one full-data product launch */
+} spcg_solve_stats;
+
+/* beta (DEVICE, d x k row-major FP64) <- Algorithm 1 (or full-data PCG)
+ * for (X, Y).  X: N x d any element type; Y: N x k SPCG_F64.  Stage II
+ * stops when sqrt(g^T H^-1 g) <= tol ||X beta|| or at T total iterations.
+ * Workspaces are cached in ctx and reused by later solves of the same or
+ * smaller size. */
+int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
+               double* beta, spcg_solve_stats* stats);
+
+/* Default option values (all zero fields mean "default"). */
+void spcg_solve_opts_default(spcg_solve_opts* opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPCG_H */

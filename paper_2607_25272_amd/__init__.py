@@ -1,0 +1,270 @@
+"""SPCG (Sequential Preconditioned Conjugate Gradient) on MI355X / gfx950.
+
+Python binding of the C ABI in ``include/spcg.h``: the functions below carry
+the ABI's names and only marshal arguments (torch tensors give device
+pointers and the stream); every step of the method runs in the HIP library
+``libspcg.so``.  There is no fallback: if the library is not built, the
+first call raises.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (SPCG_BF16, SPCG_E_BREAKDOWN, SPCG_E_DTYPE, SPCG_E_HIP, SPCG_E_INVALID_ARG,
+                   SPCG_E_NOMEM, SPCG_E_RANK, SPCG_E_SHAPE, SPCG_F32, SPCG_F64, SPCG_FP8E4M3,
+                   SPCG_METHOD_FULL_PCG, SPCG_METHOD_SPCG, SPCG_OK, SPCG_W_NOT_CONVERGED)
+
+__all__ = ["Context", "SpcgError", "spcg_sketch", "spcg_precond_build", "spcg_precond_from_r",
+           "spcg_pcg_stage", "spcg_solve", "spcg_sketch_tables_host", "mat", "load"]
+
+_DTYPES = {
+    torch.float64: SPCG_F64,
+    torch.float32: SPCG_F32,
+    torch.bfloat16: SPCG_BF16,
+    torch.float8_e4m3fn: SPCG_FP8E4M3,
+}
+
+
+def load():
+    return L.load()
+
+
+class SpcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"SPCG error {code}: {msg}")
+        self.code = code
+
+
+def mat(t, col_scale=None):
+    """spcg_mat view of a 2-D device tensor with unit column stride."""
+    if t.dim() == 1:
+        t = t.unsqueeze(1)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D row-major with unit column stride")
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    m = L.SpcgMat()
+    m.data = t.data_ptr() if t.numel() else None
+    m.dtype = _DTYPES[t.dtype]
+    m.rows, m.cols = t.shape
+    m.ld = max(t.stride(0), t.shape[1])
+    m.col_scale = col_scale.data_ptr() if col_scale is not None else None
+    return m
+
+
+class Context:
+    """spcg_ctx bound to a device and the current torch stream."""
+
+    def __init__(self, device=0, stream=None):
+        lib = load()
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        rc = lib.spcg_ctx_create(dev.index or 0, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h))
+        if rc != SPCG_OK:
+            raise SpcgError(rc, "spcg_ctx_create failed")
+        self.h = h
+        self.lib = lib
+
+    def check(self, rc):
+        if rc < 0:
+            raise SpcgError(rc, self.lib.spcg_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spcg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sketch:
+    def __init__(self, ctx, h, keep):
+        self.ctx, self.h, self._keep = ctx, h, keep
+        info = L.SketchInfo()
+        ctx.check(ctx.lib.spcg_sketch_get_info(h, ctypes.byref(info)))
+        self.info = info
+        self.sizes = [info.m[i] for i in range(info.K)]
+
+    def view(self, stage):
+        """(A, b, c2) spcg_mat views of sketched stage ``stage`` (-1: S_hat)."""
+        A, b, c2 = L.SpcgMat(), L.SpcgMat(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.spcg_sketch_view(self.h, stage, ctypes.byref(A),
+                                                     ctypes.byref(b), ctypes.byref(c2)))
+        return A, b, c2.value
+
+    def view_tensor(self, stage):
+        """Copies of the stored (unscaled) sketch rows of a stage as tensors."""
+        A, b, c2 = self.view(stage)
+        dt = torch.float64 if A.dtype == SPCG_F64 else torch.float32
+        es = 8 if A.dtype == SPCG_F64 else 4
+        Ah = _tensor_from_ptr(A.data, (A.rows, A.ld), dt, es, self.ctx.device)[:, :A.cols]
+        bh = None
+        if b.data:
+            bh = _tensor_from_ptr(b.data, (b.rows, b.ld), torch.float64, 8,
+                                  self.ctx.device)[:, :b.cols]
+        return Ah.clone(), (bh.clone() if bh is not None else None), c2
+
+    def export(self):
+        info = self.info
+        mK = self.sizes[-1] if self.sizes else 0
+        slot = np.zeros(max(mK, 1), np.int32)
+        hat = np.zeros(info.r, np.int32)
+        perm = np.zeros(info.Np, np.int32)
+        sign = np.zeros(max(info.Np // 8, 1), np.uint8)
+        self.ctx.check(self.ctx.lib.spcg_sketch_export(
+            self.ctx.h, self.h, slot.ctypes.data, hat.ctypes.data, perm.ctypes.data,
+            sign.ctypes.data))
+        return {"slot_rows": slot[:mK], "hat_rows": hat, "input_perm": perm, "sign_bits": sign}
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.spcg_sketch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _tensor_from_ptr(ptr, shape, dtype, es, device):
+    n = int(np.prod(shape))
+    if n == 0:
+        return torch.empty(shape, dtype=dtype, device=device)
+    # wrap the device pointer without copying via a DLPack-free route:
+    # allocate a tensor and copy with the HIP runtime through torch
+    out = torch.empty(shape, dtype=dtype, device=device)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    torch.cuda.current_stream(device).synchronize()
+    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), n * es, 3)
+    if rc != 0:
+        raise SpcgError(-6, f"hipMemcpy failed ({rc})")
+    return out
+
+
+class Precond:
+    def __init__(self, ctx, h, d):
+        self.ctx, self.h, self.d = ctx, h, d
+
+    def export(self):
+        R = np.zeros((self.d, self.d), np.float64)
+        passes = ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.spcg_precond_export(self.ctx.h, self.h, R.ctypes.data,
+                                                        ctypes.byref(passes)))
+        return R, passes.value
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.spcg_precond_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def spcg_sketch(ctx, X, Y=None, seed=1, m0=0, m_max=0, r=0, growth=2, hat_only=False,
+                col_scale=None):
+    o = L.SketchOpts(seed=seed, m0=m0, m_max=m_max, r=r, growth=growth, hat_only=int(hat_only))
+    Xm = mat(X, col_scale)
+    Ym = mat(Y) if Y is not None else None
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.spcg_sketch(ctx.h, ctypes.byref(Xm), ctypes.byref(Ym) if Ym else None,
+                                  ctypes.byref(o), ctypes.byref(h)))
+    return Sketch(ctx, h, (X, Y, col_scale))
+
+
+def spcg_precond_build(ctx, sketch, qr_passes=0):
+    h = ctypes.c_void_p()
+    o = L.PrecondOpts(qr_passes=qr_passes)
+    ctx.check(ctx.lib.spcg_precond_build(ctx.h, sketch.h, ctypes.byref(o), ctypes.byref(h)))
+    return Precond(ctx, h, sketch.info.d)
+
+
+def spcg_precond_from_r(ctx, R):
+    R = R.to(device=ctx.device, dtype=torch.float64).contiguous()
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.spcg_precond_from_r(ctx.h, ctypes.c_void_p(R.data_ptr()), R.shape[0],
+                                          ctypes.byref(h)))
+    torch.cuda.current_stream(ctx.device).synchronize()
+    return Precond(ctx, h, R.shape[0])
+
+
+def _as_mat(a, col_scale=None):
+    return a if isinstance(a, L.SpcgMat) else mat(a, col_scale)
+
+
+def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, check_every=1,
+                   col_scale=None):
+    """PCG on c2 A^T A x = c2 A^T b from x = beta (updated in place)."""
+    Am, bm = _as_mat(A, col_scale), _as_mat(b)
+    o = L.StageOpts(iters=iters, refresh_gradient=int(refresh), tol=tol, check_every=check_every)
+    st = L.StageStats()
+    rc = ctx.check(ctx.lib.spcg_pcg_stage(ctx.h, ctypes.byref(Am), ctypes.byref(bm), c2, precond.h,
+                                          ctypes.c_void_p(beta.data_ptr()), ctypes.byref(o),
+                                          ctypes.byref(st)))
+    return {"iters": st.iters, "converged": bool(st.converged), "rho0": st.rho0, "rho": st.rho,
+            "ax_norm": st.ax_norm, "resid_norm2": st.resid_norm2, "rc": rc}
+
+
+def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, growth=2,
+               qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None):
+    o = L.SolveOpts()
+    ctx_lib = load()
+    ctx_lib.spcg_solve_opts_default(ctypes.byref(o))
+    o.sketch.seed, o.sketch.m0, o.sketch.m_max, o.sketch.r, o.sketch.growth = seed, m0, m_max, r, growth
+    o.precond.qr_passes = qr_passes
+    o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
+    o.a, o.T, o.tol, o.check_every = a, T, tol, check_every
+    o.time_phases, o.time_products = int(time_phases), int(time_products)
+    keep = None
+    if a_list is not None:
+        keep = (ctypes.c_int32 * len(a_list))(*a_list)
+        o.a_list = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+        o.a_list_len = len(a_list)
+    return o, keep
+
+
+def spcg_solve(ctx, X, Y, beta=None, col_scale=None, **kw):
+    """Algorithm 1 (or full-data PCG with method='pcg'); returns (beta, stats)."""
+    o, keep = solve_opts(**kw)
+    Xm, Ym = mat(X, col_scale), mat(Y)
+    if beta is None:
+        beta = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
+    st = L.SolveStats()
+    rc = ctx.check(ctx.lib.spcg_solve(ctx.h, ctypes.byref(Xm), ctypes.byref(Ym), ctypes.byref(o),
+                                      ctypes.c_void_p(beta.data_ptr()), ctypes.byref(st)))
+    del keep
+    stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
+    stats["rc"] = rc
+    return beta, stats
+
+
+def spcg_sketch_tables_host(seed, L_bits, m, r):
+    """Sketch randomness from the library's host code (no GPU needed)."""
+    lib = load()
+    np_ = 1 << L_bits
+    slot = np.zeros(max(m, 1), np.int32)
+    hat = np.zeros(max(r, 1), np.int32)
+    perm = np.zeros(np_, np.int32)
+    sign = np.zeros(max(np_ // 8, 1), np.uint8)
+    rc = lib.spcg_sketch_tables_host(seed, L_bits, m, r, slot.ctypes.data, hat.ctypes.data,
+                                     perm.ctypes.data, sign.ctypes.data)
+    if rc != SPCG_OK:
+        raise SpcgError(rc, "spcg_sketch_tables_host failed")
+    return {"slot_rows": slot[:m], "hat_rows": hat[:r], "input_perm": perm,
+            "sign_bits": sign[:np_ // 8]}

@@ -1,0 +1,870 @@
+// Host driver and C ABI of the SPCG library: argument checking, handles,
+// workspaces, the PCG stage runner and Algorithm 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "rng.hpp"
+#include "spcg.h"
+
+using namespace spcg;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        release();
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return e;
+        }
+        n = bytes;
+        return hipSuccess;
+    }
+    template <typename T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+constexpr int MAX_TIMED = 256;
+
+}  // namespace
+
+struct spcg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string err;
+    // product partials and d-space state
+    DevBuf part_s, part_g, part_scal;
+    DevBuf dvec;      // g z p s gt (5 * dpad) + blk (1024)
+    DevBuf scal;      // PcgScalars + counters
+    int64_t dvec_dpad = 0;
+    // sketch and preconditioner workspaces used by spcg_solve
+    DevBuf zbuf, tables, wsB, wsBY, wsBh;
+    DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status;
+    // events for timing
+    hipEvent_t ev_phase[8] = {};
+    hipEvent_t ev_prod[2 * MAX_TIMED] = {};
+    bool events_ready = false;
+};
+
+struct spcg_sketch_s {
+    spcg_ctx* ctx = nullptr;
+    int64_t N = 0, Np = 0, d = 0, k = 0, r = 0, K = 0, ld = 0, ldy = 0;
+    int L = 0;
+    int dtype = DT_F32;
+    uint64_t seed = 0;
+    int64_t m[64] = {};
+    bool owns = true;
+    DevBuf B, BY, Bh;          // owned storage (when owns)
+    void* pB = nullptr;        // active pointers (owned or ctx workspace)
+    double* pBY = nullptr;
+    void* pBh = nullptr;
+};
+
+struct spcg_precond_s {
+    int64_t d = 0;
+    int passes = 0;
+    bool owns = true;
+    DevBuf R, Minv;
+    double* pR = nullptr;
+    double* pMinv = nullptr;
+};
+
+namespace {
+
+int fail(spcg_ctx* ctx, int code, const char* fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail((ctx), _e == hipErrorOutOfMemory ? SPCG_E_NOMEM : SPCG_E_HIP,       \
+                        "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                        __LINE__);                                                          \
+    } while (0)
+
+int check_mat(spcg_ctx* ctx, const spcg_mat* M, const char* name) {
+    if (!M) return fail(ctx, SPCG_E_INVALID_ARG, "%s is NULL", name);
+    if (M->dtype < SPCG_F64 || M->dtype > SPCG_FP8E4M3)
+        return fail(ctx, SPCG_E_DTYPE, "%s: unknown dtype %d", name, M->dtype);
+    if (M->rows < 0 || M->cols < 1 || M->ld < M->cols)
+        return fail(ctx, SPCG_E_SHAPE, "%s: bad shape rows=%lld cols=%lld ld=%lld", name,
+                    (long long)M->rows, (long long)M->cols, (long long)M->ld);
+    if (!M->data && M->rows > 0) return fail(ctx, SPCG_E_INVALID_ARG, "%s: data is NULL", name);
+    if (M->dtype == SPCG_FP8E4M3 && !M->col_scale)
+        return fail(ctx, SPCG_E_INVALID_ARG, "%s: FP8 storage needs col_scale", name);
+    return SPCG_OK;
+}
+
+int ceil_log2(int64_t n) {
+    int L = 0;
+    while ((1ll << L) < n) ++L;
+    return L < 1 ? 1 : L;
+}
+
+int ensure_events(spcg_ctx* ctx) {
+    if (ctx->events_ready) return SPCG_OK;
+    for (auto& e : ctx->ev_phase) HIP_TRY(ctx, hipEventCreate(&e));
+    for (auto& e : ctx->ev_prod) HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->events_ready = true;
+    return SPCG_OK;
+}
+
+// ------------------------------------------------------------------ sketch
+
+int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_sketch_opts* o,
+                 bool borrow, spcg_sketch_t* sk) {
+    int rc;
+    if ((rc = check_mat(ctx, X, "X")) != SPCG_OK) return rc;
+    const bool hat_only = o && o->hat_only;
+    if (!hat_only) {
+        if ((rc = check_mat(ctx, Y, "Y")) != SPCG_OK) return rc;
+        if (Y->dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "Y must be SPCG_F64");
+        if (Y->rows != X->rows) return fail(ctx, SPCG_E_SHAPE, "Y has %lld rows, X has %lld",
+                                            (long long)Y->rows, (long long)X->rows);
+    }
+    const int64_t N = X->rows, d = X->cols;
+    if (N <= d) return fail(ctx, SPCG_E_SHAPE, "need N > d (N=%lld, d=%lld)", (long long)N, (long long)d);
+    if (d > product_max_d(X->dtype))
+        return fail(ctx, SPCG_E_SHAPE, "d=%lld exceeds the supported maximum %lld", (long long)d,
+                    (long long)product_max_d(X->dtype));
+    const int L = ceil_log2(N);
+    if (L > 30) return fail(ctx, SPCG_E_SHAPE, "N too large (2^30 rows max)");
+    const int64_t Np = 1ll << L;
+    const int64_t m0 = (o && o->m0 > 0) ? o->m0 : 4 * d;
+    const int64_t growth = (o && o->growth > 0) ? o->growth : 2;
+    const int64_t r = (o && o->r > 0) ? o->r : 6 * d;
+    if (growth < 2) return fail(ctx, SPCG_E_INVALID_ARG, "growth must be >= 2");
+    if (r < d || r > Np) return fail(ctx, SPCG_E_SHAPE, "need d <= r <= N' (r=%lld)", (long long)r);
+    sk->ctx = ctx;
+    sk->N = N;
+    sk->Np = Np;
+    sk->d = d;
+    sk->L = L;
+    sk->r = r;
+    sk->seed = o ? o->seed : 0;
+    sk->dtype = X->dtype == SPCG_F64 ? DT_F64 : DT_F32;
+    sk->ld = round_up(d, 16);
+    sk->K = 0;
+    if (!hat_only) {
+        if (m0 <= d) return fail(ctx, SPCG_E_SHAPE, "need m_1 > d (m_1=%lld)", (long long)m0);
+        const int64_t limit = (o && o->m_max > 0) ? std::min<int64_t>(o->m_max, N - 1) : N - 1;
+        for (int64_t m = m0; m <= limit; m *= growth) {
+            if (sk->K >= 64) return fail(ctx, SPCG_E_SHAPE, "more than 64 stages");
+            sk->m[sk->K++] = m;
+        }
+        if (sk->K == 0) return fail(ctx, SPCG_E_SHAPE, "no sketch size fits: m_1=%lld >= N", (long long)m0);
+        sk->k = Y->cols;
+    }
+    const int64_t mK = sk->K ? sk->m[sk->K - 1] : 0;
+    const size_t es = sk->dtype == DT_F64 ? 8 : 4;
+    sk->ldy = sk->k == 1 ? 1 : round_up(sk->k, 8);
+    sk->owns = !borrow;
+    DevBuf& bB = borrow ? ctx->wsB : sk->B;
+    DevBuf& bBY = borrow ? ctx->wsBY : sk->BY;
+    DevBuf& bBh = borrow ? ctx->wsBh : sk->Bh;
+    if (mK) {
+        HIP_TRY(ctx, bB.ensure((size_t)mK * sk->ld * es));
+        HIP_TRY(ctx, bBY.ensure((size_t)mK * sk->ldy * 8));
+    }
+    HIP_TRY(ctx, bBh.ensure((size_t)r * sk->ld * es));
+    sk->pB = mK ? bB.p : nullptr;
+    sk->pBY = mK ? bBY.as<double>() : nullptr;
+    sk->pBh = bBh.p;
+    // randomness tables and transform scratch (always context workspace)
+    HIP_TRY(ctx, ctx->tables.ensure((size_t)3 * Np * sizeof(int32_t)));
+    int32_t* perm_sign = ctx->tables.as<int32_t>();
+    int32_t* inv_slot = perm_sign + Np;
+    int32_t* inv_hat = perm_sign + 2 * Np;
+    const size_t zx = (size_t)Np * sk->ld * es;
+    const size_t zy = (size_t)Np * sk->ldy * 8;
+    HIP_TRY(ctx, ctx->zbuf.ensure(std::max(zx, zy)));
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, mK ? inv_slot : nullptr, inv_hat));
+    FwhtJob jx{};
+    jx.x = X->data;
+    jx.in_dtype = X->dtype;
+    jx.N = N;
+    jx.d = d;
+    jx.ldx = X->ld;
+    jx.col_scale = X->col_scale;
+    jx.L = L;
+    jx.perm_sign = perm_sign;
+    jx.inv_slot = mK ? inv_slot : nullptr;
+    jx.inv_hat = inv_hat;
+    jx.zbuf = ctx->zbuf.p;
+    jx.ldz = sk->ld;
+    jx.B = sk->pB;
+    jx.ldb = sk->ld;
+    jx.Bh = sk->pBh;
+    jx.ldbh = sk->ld;
+    jx.narrow = 0;
+    HIP_TRY(ctx, run_fwht(st, jx));
+    if (mK) {
+        FwhtJob jy{};
+        jy.x = Y->data;
+        jy.in_dtype = DT_F64;
+        jy.N = N;
+        jy.d = sk->k;
+        jy.ldx = Y->ld;
+        jy.L = L;
+        jy.perm_sign = perm_sign;
+        jy.inv_slot = inv_slot;
+        jy.inv_hat = nullptr;
+        jy.zbuf = ctx->zbuf.p;
+        jy.ldz = sk->ldy;
+        jy.B = sk->pBY;
+        jy.ldb = sk->ldy;
+        jy.narrow = sk->k == 1;
+        HIP_TRY(ctx, run_fwht(st, jy));
+    }
+    return SPCG_OK;
+}
+
+// --------------------------------------------------------- preconditioner
+
+int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, DenseStatus* host) {
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, dense_status_reset(st, dev_status));
+    HIP_TRY(ctx, cholesky_upper(st, G, d, d, dev_status));
+    HIP_TRY(ctx, hipMemcpyAsync(host, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return SPCG_OK;
+}
+
+// R -> (R, M = R^{-1} R^{-T})
+int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
+    const int64_t d = pc->d;
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
+    double* W = ctx->dense_a.as<double>();
+    HIP_TRY(ctx, dense_fill_identity(st, W, d));
+    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d));
+    HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0));
+    return SPCG_OK;
+}
+
+int precond_alloc(spcg_ctx* ctx, spcg_precond_t* pc, int64_t d, bool borrow) {
+    pc->d = d;
+    pc->owns = !borrow;
+    DevBuf& bR = borrow ? ctx->wsR : pc->R;
+    DevBuf& bM = borrow ? ctx->wsMinv : pc->Minv;
+    HIP_TRY(ctx, bR.ensure((size_t)d * d * 8));
+    HIP_TRY(ctx, bM.ensure((size_t)d * d * 8));
+    pc->pR = bR.as<double>();
+    pc->pMinv = bM.as<double>();
+    return SPCG_OK;
+}
+
+int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opts* o, bool borrow,
+                  spcg_precond_t* pc) {
+    int rc;
+    const int64_t d = sk->d, r = sk->r, ld = sk->ld;
+    const int mode = o ? o->qr_passes : 0;
+    if (mode < 0 || mode > 3) return fail(ctx, SPCG_E_INVALID_ARG, "qr_passes must be 0..3");
+    if ((rc = precond_alloc(ctx, pc, d, borrow)) != SPCG_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const int bf32 = sk->dtype == DT_F32;
+    HIP_TRY(ctx, ctx->dense_status.ensure(sizeof(DenseStatus)));
+    DenseStatus* dst = ctx->dense_status.as<DenseStatus>();
+    DenseStatus hs{};
+    double* R = pc->pR;
+    const double inv_r = 1.0 / (double)r;
+    // Gram of S_hat X = B_hat / sqrt(r): upper 64x64 tiles only
+    auto gram_hat = [&](double* C) {
+        return gemm_f64(st, d, d, r, inv_r, sk->pBh, bf32, 1, ld, sk->pBh, bf32, ld, 1, 0.0, C, d, 1);
+    };
+    if (mode == 0 || mode == 1) {
+        HIP_TRY(ctx, gram_hat(R));
+        if ((rc = chol_checked(ctx, R, d, dst, &hs)) != SPCG_OK) return rc;
+        const bool ok = hs.fail == 0 && hs.min_diag > 0.0;
+        const double ratio = ok ? hs.max_diag / hs.min_diag : INFINITY;
+        if (ok && (mode == 1 || ratio <= 1e5)) {
+            pc->passes = 1;
+            return precond_finish(ctx, pc);
+        }
+        if (mode == 1)
+            return fail(ctx, SPCG_E_RANK, "Cholesky of the sketched Gram failed at pivot %d", hs.fail);
+    }
+    // CholeskyQR2 (mode 2) or shifted CholeskyQR3 (mode 0 fallback, 3)
+    const int passes = mode == 2 ? 2 : 3;
+    HIP_TRY(ctx, ctx->dense_b.ensure((size_t)d * d * 8));
+    HIP_TRY(ctx, ctx->dense_c.ensure((size_t)d * d * 8));
+    HIP_TRY(ctx, ctx->dense_q.ensure((size_t)r * d * 8));
+    double* R1 = ctx->dense_b.as<double>();
+    double* R2 = ctx->dense_c.as<double>();
+    double* Q = ctx->dense_q.as<double>();
+    HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
+    double* T = ctx->dense_a.as<double>();
+    HIP_TRY(ctx, gram_hat(R1));
+    if (passes == 3) {
+        const double u = std::ldexp(1.0, -53);
+        HIP_TRY(ctx, dense_add_trace_shift(st, R1, d, 11.0 * ((double)r * d + (double)d * (d + 1)) * u));
+    }
+    if ((rc = chol_checked(ctx, R1, d, dst, &hs)) != SPCG_OK) return rc;
+    if (hs.fail) return fail(ctx, SPCG_E_RANK, "Cholesky of the (shifted) sketched Gram failed");
+    HIP_TRY(ctx, dense_convert(st, sk->pBh, bf32, r, d, ld, std::sqrt(inv_r), Q, d));
+    HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R1, d));
+    // second pass
+    HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R2, d, 1));
+    if ((rc = chol_checked(ctx, R2, d, dst, &hs)) != SPCG_OK) return rc;
+    if (hs.fail || hs.min_pivot < 1e-12)
+        return fail(ctx, SPCG_E_RANK, "S_hat X is numerically rank deficient (pivot %.3g)", hs.min_pivot);
+    if (passes == 3) {
+        HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R2, d));
+        HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R, d, 1));
+        if ((rc = chol_checked(ctx, R, d, dst, &hs)) != SPCG_OK) return rc;
+        if (hs.fail || hs.min_pivot < 1e-12)
+            return fail(ctx, SPCG_E_RANK, "S_hat X is numerically rank deficient (pivot %.3g)", hs.min_pivot);
+        // R <- R3 R2 R1
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R, 0, d, 1, R2, 0, d, 1, 0.0, T, d, 0));
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, T, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0));
+    } else {
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R2, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0));
+    }
+    pc->passes = passes;
+    return precond_finish(ctx, pc);
+}
+
+// -------------------------------------------------------------- PCG stage
+
+struct StageRun {
+    int iters_done = 0;
+    bool converged = false;
+    PcgScalars sc{};
+};
+
+int ensure_stage_ws(spcg_ctx* ctx, int64_t d, DspaceState* S, double* x, const double* Minv) {
+    const int64_t dpad = round_up(d, 64);
+    const size_t mb = (size_t)product_max_blocks(ctx->num_cu);
+    HIP_TRY(ctx, ctx->part_s.ensure(mb * dpad * 8));
+    HIP_TRY(ctx, ctx->part_g.ensure(mb * dpad * 8));
+    HIP_TRY(ctx, ctx->part_scal.ensure(mb * 2 * 8));
+    if (ctx->dvec_dpad < dpad || !ctx->dvec.p) {
+        HIP_TRY(ctx, ctx->dvec.ensure((size_t)(5 * dpad + 1024) * 8));
+        ctx->dvec_dpad = dpad;
+    }
+    if (!ctx->scal.p) {
+        HIP_TRY(ctx, ctx->scal.ensure(sizeof(PcgScalars) + 64));
+        HIP_TRY(ctx, run_counters_reset(ctx->stream,
+                                        reinterpret_cast<unsigned int*>(ctx->scal.as<char>() + sizeof(PcgScalars)), 16));
+    }
+    double* v = ctx->dvec.as<double>();
+    const int64_t stride = ctx->dvec_dpad;
+    S->x = x;
+    S->g = v;
+    S->z = v + stride;
+    S->p = v + 2 * stride;
+    S->s = v + 3 * stride;
+    S->gt = v + 4 * stride;
+    S->blk = v + 5 * stride;
+    S->sc = ctx->scal.as<PcgScalars>();
+    S->counters = reinterpret_cast<unsigned int*>(ctx->scal.as<char>() + sizeof(PcgScalars));
+    S->Minv = Minv;
+    S->d = d;
+    return SPCG_OK;
+}
+
+int read_scalars(spcg_ctx* ctx, const DspaceState& S, PcgScalars* out) {
+    HIP_TRY(ctx, hipMemcpyAsync(out, S.sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return SPCG_OK;
+}
+
+bool stop_test(const PcgScalars& sc, double tol) {
+    if (sc.exact) return true;
+    return std::sqrt(std::max(sc.rho, 0.0)) <= tol * std::sqrt(std::max(sc.ax2, 0.0));
+}
+
+struct ProductTimer {
+    spcg_ctx* ctx = nullptr;
+    int used = 0;
+};
+
+int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const DspaceState& S, int mode,
+                 int* nparts, ProductTimer* timer) {
+    ProdJob j{};
+    j.A = A->data;
+    j.dtype = A->dtype;
+    j.m = A->rows;
+    j.d = A->cols;
+    j.lda = A->ld;
+    j.dmem = A->cols;
+    j.col_scale = A->col_scale;
+    j.b = b ? static_cast<const double*>(b->data) : nullptr;
+    j.ldbv = b ? b->ld : 0;
+    j.x = S.x;
+    j.p = S.p;
+    j.mode = mode;
+    j.part_s = ctx->part_s.as<double>();
+    j.part_g = ctx->part_g.as<double>();
+    j.part_scal = ctx->part_scal.as<double>();
+    j.dpad = round_up(A->cols, 64);
+    j.num_cu = ctx->num_cu;
+    const bool timed = timer && timer->used < MAX_TIMED;
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], ctx->stream));
+    HIP_TRY(ctx, run_product(ctx->stream, j, nparts));
+    if (timed) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used + 1], ctx->stream));
+        timer->used++;
+    }
+    return SPCG_OK;
+}
+
+// PCG(A, b, c2, M, x, iters) with optional stopping test; x is device memory.
+int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const spcg_precond_t* pc,
+              double* x, int iters, double tol, bool refresh, int check_every, StageRun* out,
+              ProductTimer* timer) {
+    int rc;
+    DspaceState S{};
+    if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const int64_t dpad = round_up(A->cols, 64);
+    int np = 0;
+    // stage start: g = c2 A^T (b - A x), z = M g, p = z, rho = g^T z
+    if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
+                             np, dpad, c2));
+    HIP_TRY(ctx, run_phase_b(st, S, 1));
+    const bool testing = tol > 0.0;
+    if (check_every < 1) check_every = 1;
+    out->iters_done = 0;
+    out->converged = false;
+    if (testing) {
+        if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
+        if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown at stage start");
+        if (stop_test(out->sc, tol)) {
+            out->converged = true;
+            return SPCG_OK;
+        }
+    }
+    const int pmode = refresh ? PM_SG : PM_S;
+    for (int it = 0; it < iters; ++it) {
+        if ((rc = product_pass(ctx, A, b, S, pmode, &np, timer)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, run_phase_a(st, S, refresh ? PA_REFRESH : PA_STEP, ctx->part_s.as<double>(),
+                                 ctx->part_g.as<double>(), ctx->part_scal.as<double>(), np, dpad, c2));
+        HIP_TRY(ctx, run_phase_b(st, S, 0));
+        out->iters_done = it + 1;
+        if (testing && ((it + 1) % check_every == 0 || it + 1 == iters)) {
+            if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
+            if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown: p^T s <= 0 or non-finite");
+            if (stop_test(out->sc, tol)) {
+                out->converged = true;
+                return SPCG_OK;
+            }
+        }
+    }
+    if (!testing) {
+        if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
+        if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown: p^T s <= 0 or non-finite");
+        out->converged = out->sc.exact != 0;
+    }
+    return SPCG_OK;
+}
+
+int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
+                     const spcg_precond_t* pc, double* x, int iters) {
+    int rc;
+    DspaceState S{};
+    if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const int64_t dpad = round_up(A->cols, 64);
+    int np = 0;
+    if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
+                             np, dpad, c2));
+    HIP_TRY(ctx, run_phase_b(st, S, 1));
+    for (int it = 0; it < iters; ++it) {
+        if ((rc = product_pass(ctx, A, b, S, PM_S, &np, nullptr)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, run_phase_a(st, S, PA_STEP, ctx->part_s.as<double>(), nullptr, nullptr, np, dpad, c2));
+        HIP_TRY(ctx, run_phase_b(st, S, 0));
+    }
+    return SPCG_OK;
+}
+
+int check_stage_args(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const spcg_precond_t* pc,
+                     const double* beta) {
+    int rc;
+    if ((rc = check_mat(ctx, A, "A")) != SPCG_OK) return rc;
+    if ((rc = check_mat(ctx, b, "b")) != SPCG_OK) return rc;
+    if (!pc) return fail(ctx, SPCG_E_INVALID_ARG, "preconditioner is NULL");
+    if (!beta) return fail(ctx, SPCG_E_INVALID_ARG, "beta is NULL");
+    if (b->dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "b must be SPCG_F64");
+    if (b->rows != A->rows) return fail(ctx, SPCG_E_SHAPE, "b has %lld rows, A has %lld",
+                                        (long long)b->rows, (long long)A->rows);
+    if (A->cols != pc->d) return fail(ctx, SPCG_E_SHAPE, "A has %lld columns, preconditioner %lld",
+                                      (long long)A->cols, (long long)pc->d);
+    if (b->cols != 1)
+        return fail(ctx, SPCG_E_SHAPE, "multiple right-hand sides are not supported by this entry point");
+    if (A->cols > product_max_d(A->dtype)) return fail(ctx, SPCG_E_SHAPE, "d too large");
+    return SPCG_OK;
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return ms;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* spcg_version(void) { return "spcg-mi355x 0.1 (gfx950)"; }
+
+int spcg_ctx_create(int device, void* hip_stream, spcg_ctx** out) {
+    if (!out) return SPCG_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SPCG_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SPCG_E_HIP;
+    spcg_ctx* c = new (std::nothrow) spcg_ctx();
+    if (!c) return SPCG_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return SPCG_OK;
+}
+
+int spcg_ctx_destroy(spcg_ctx* ctx) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->events_ready) {
+        for (auto& e : ctx->ev_phase) (void)hipEventDestroy(e);
+        for (auto& e : ctx->ev_prod) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+    return SPCG_OK;
+}
+
+const char* spcg_last_error(const spcg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int spcg_sketch(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_sketch_opts* opts,
+                spcg_sketch_t** out) {
+    if (!ctx || !out) return SPCG_E_INVALID_ARG;
+    *out = nullptr;
+    spcg_sketch_t* sk = new (std::nothrow) spcg_sketch_t();
+    if (!sk) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    const int rc = sketch_build(ctx, X, Y, opts, false, sk);
+    if (rc != SPCG_OK) {
+        delete sk;
+        return rc;
+    }
+    *out = sk;
+    return SPCG_OK;
+}
+
+int spcg_sketch_get_info(const spcg_sketch_t* sk, spcg_sketch_info* info) {
+    if (!sk || !info) return SPCG_E_INVALID_ARG;
+    std::memset(info, 0, sizeof *info);
+    info->N = sk->N;
+    info->Np = sk->Np;
+    info->d = sk->d;
+    info->k = sk->k;
+    info->r = sk->r;
+    info->K = sk->K;
+    info->L = sk->L;
+    info->sketch_dtype = sk->dtype;
+    info->ld = sk->ld;
+    for (int64_t i = 0; i < sk->K; ++i) info->m[i] = sk->m[i];
+    return SPCG_OK;
+}
+
+int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* b, double* c2) {
+    if (!sk || !A) return SPCG_E_INVALID_ARG;
+    if (stage < -1 || stage >= sk->K) return SPCG_E_INVALID_ARG;
+    const int64_t rows = stage < 0 ? sk->r : sk->m[stage];
+    A->data = stage < 0 ? sk->pBh : sk->pB;
+    A->dtype = sk->dtype;
+    A->reserved = 0;
+    A->rows = rows;
+    A->cols = sk->d;
+    A->ld = sk->ld;
+    A->col_scale = nullptr;
+    if (b) {
+        b->data = stage < 0 ? nullptr : sk->pBY;
+        b->dtype = SPCG_F64;
+        b->reserved = 0;
+        b->rows = stage < 0 ? 0 : rows;
+        b->cols = sk->k < 1 ? 1 : sk->k;
+        b->ld = sk->ldy;
+        b->col_scale = nullptr;
+    }
+    if (c2) *c2 = 1.0 / (double)rows;
+    return SPCG_OK;
+}
+
+int spcg_sketch_export(spcg_ctx* ctx, const spcg_sketch_t* sk, int32_t* slot_rows, int32_t* hat_rows,
+                       int32_t* input_perm, uint8_t* sign_bits) {
+    if (!ctx || !sk) return SPCG_E_INVALID_ARG;
+    const int64_t mK = sk->K ? sk->m[sk->K - 1] : 0;
+    const size_t n_slot = (size_t)mK, n_hat = (size_t)sk->r, n_perm = (size_t)sk->Np,
+                 n_sign = (size_t)(sk->Np / 8 > 0 ? sk->Np / 8 : 1);
+    DevBuf buf;
+    HIP_TRY(ctx, buf.ensure((n_slot + n_hat + n_perm) * 4 + n_sign + 64));
+    int32_t* d_slot = buf.as<int32_t>();
+    int32_t* d_hat = d_slot + n_slot;
+    int32_t* d_perm = d_hat + n_hat;
+    uint8_t* d_sign = reinterpret_cast<uint8_t*>(d_perm + n_perm);
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, launch_sketch_export(st, sk->seed, sk->L, mK, sk->r, slot_rows ? d_slot : nullptr,
+                                      hat_rows ? d_hat : nullptr, input_perm ? d_perm : nullptr,
+                                      sign_bits ? d_sign : nullptr));
+    if (slot_rows && n_slot) HIP_TRY(ctx, hipMemcpyAsync(slot_rows, d_slot, n_slot * 4, hipMemcpyDeviceToHost, st));
+    if (hat_rows) HIP_TRY(ctx, hipMemcpyAsync(hat_rows, d_hat, n_hat * 4, hipMemcpyDeviceToHost, st));
+    if (input_perm) HIP_TRY(ctx, hipMemcpyAsync(input_perm, d_perm, n_perm * 4, hipMemcpyDeviceToHost, st));
+    if (sign_bits) HIP_TRY(ctx, hipMemcpyAsync(sign_bits, d_sign, (size_t)(sk->Np / 8), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return SPCG_OK;
+}
+
+void spcg_sketch_free(spcg_sketch_t* sk) { delete sk; }
+
+int spcg_sketch_tables_host(uint64_t seed, int32_t L, int64_t m, int64_t r, int32_t* slot_rows,
+                            int32_t* hat_rows, int32_t* input_perm, uint8_t* sign_bits) {
+    if (L < 1 || L > 30 || m < 0 || r < 0) return SPCG_E_INVALID_ARG;
+    const int64_t np = 1ll << L;
+    if (m > np || r > np) return SPCG_E_SHAPE;
+    if (slot_rows)
+        for (int64_t t = 0; t < m; ++t) slot_rows[t] = (int32_t)feistel_fwd((uint64_t)t, L, seed, STREAM_PI);
+    if (hat_rows)
+        for (int64_t t = 0; t < r; ++t) hat_rows[t] = (int32_t)feistel_fwd((uint64_t)t, L, seed, STREAM_PIHAT);
+    if (input_perm)
+        for (int64_t k = 0; k < np; ++k) input_perm[k] = (int32_t)feistel_fwd((uint64_t)k, L, seed, STREAM_P);
+    if (sign_bits)
+        for (int64_t i = 0; i < np / 8; ++i) {
+            uint32_t byte = 0;
+            for (int b = 0; b < 8; ++b) byte |= sign_bit(seed, (uint64_t)(i * 8 + b)) << b;
+            sign_bits[i] = (uint8_t)byte;
+        }
+    return SPCG_OK;
+}
+
+int spcg_precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opts* opts,
+                       spcg_precond_t** out) {
+    if (!ctx || !sk || !out) return SPCG_E_INVALID_ARG;
+    *out = nullptr;
+    spcg_precond_t* pc = new (std::nothrow) spcg_precond_t();
+    if (!pc) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    const int rc = precond_build(ctx, sk, opts, false, pc);
+    if (rc != SPCG_OK) {
+        delete pc;
+        return rc;
+    }
+    *out = pc;
+    return SPCG_OK;
+}
+
+int spcg_precond_from_r(spcg_ctx* ctx, const double* R, int64_t d, spcg_precond_t** out) {
+    if (!ctx || !R || !out || d < 1) return SPCG_E_INVALID_ARG;
+    *out = nullptr;
+    spcg_precond_t* pc = new (std::nothrow) spcg_precond_t();
+    if (!pc) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    int rc = precond_alloc(ctx, pc, d, false);
+    if (rc == SPCG_OK) {
+        hipError_t e = hipMemcpyAsync(pc->pR, R, (size_t)d * d * 8, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) rc = fail(ctx, SPCG_E_HIP, "copy of R failed: %s", hipGetErrorString(e));
+    }
+    if (rc == SPCG_OK) rc = precond_finish(ctx, pc);
+    if (rc != SPCG_OK) {
+        delete pc;
+        return rc;
+    }
+    pc->passes = 0;
+    *out = pc;
+    return SPCG_OK;
+}
+
+int spcg_precond_export(spcg_ctx* ctx, const spcg_precond_t* pc, double* R_host, int32_t* passes) {
+    if (!ctx || !pc) return SPCG_E_INVALID_ARG;
+    if (R_host) {
+        HIP_TRY(ctx, hipMemcpyAsync(R_host, pc->pR, (size_t)pc->d * pc->d * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (passes) *passes = pc->passes;
+    return SPCG_OK;
+}
+
+void spcg_precond_free(spcg_precond_t* pc) { delete pc; }
+
+int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const spcg_precond_t* pc,
+                   double* beta, const spcg_stage_opts* opts, spcg_stage_stats* stats) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    int rc;
+    if ((rc = check_stage_args(ctx, A, b, pc, beta)) != SPCG_OK) return rc;
+    if (!opts || opts->iters < 0 || opts->tol < 0.0 || !(c2 > 0.0))
+        return fail(ctx, SPCG_E_INVALID_ARG, "bad stage options (iters >= 0, tol >= 0, c2 > 0)");
+    int64_t d = A->cols;
+    DspaceState S{};
+    if ((rc = ensure_stage_ws(ctx, d, &S, beta, pc->pMinv)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_scalars_reset(ctx->stream, S.sc));
+    StageRun run;
+    const bool refresh = opts->refresh_gradient || opts->tol > 0.0;
+    rc = stage_run(ctx, A, b, c2, pc, beta, opts->iters, opts->tol, refresh, opts->check_every, &run, nullptr);
+    if (stats) {
+        stats->iters = run.iters_done;
+        stats->converged = run.converged;
+        stats->rho0 = run.sc.rho0;
+        stats->rho = run.sc.rho;
+        stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
+        stats->resid_norm2 = run.sc.resid2;
+    }
+    if (rc != SPCG_OK) return rc;
+    if (opts->tol > 0.0 && !run.converged) {
+        fail(ctx, SPCG_W_NOT_CONVERGED, "stopping test not met in %d iterations", opts->iters);
+        return SPCG_W_NOT_CONVERGED;
+    }
+    return SPCG_OK;
+}
+
+void spcg_solve_opts_default(spcg_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->sketch.seed = 1;
+    o->sketch.growth = 2;
+    o->method = SPCG_METHOD_SPCG;
+    o->a = 3;
+    o->T = 100;
+    o->check_every = 1;
+    o->tol = 5e-7;
+}
+
+int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
+               double* beta, spcg_solve_stats* stats) {
+    if (!ctx || !opts) return SPCG_E_INVALID_ARG;
+    int rc;
+    if ((rc = check_mat(ctx, X, "X")) != SPCG_OK) return rc;
+    if ((rc = check_mat(ctx, Y, "Y")) != SPCG_OK) return rc;
+    if (!beta) return fail(ctx, SPCG_E_INVALID_ARG, "beta is NULL");
+    if (Y->dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "Y must be SPCG_F64");
+    if (Y->rows != X->rows) return fail(ctx, SPCG_E_SHAPE, "X and Y row counts differ");
+    if (Y->cols != 1)
+        return fail(ctx, SPCG_E_SHAPE, "multiple right-hand sides are not supported by this entry point");
+    if (opts->method != SPCG_METHOD_SPCG && opts->method != SPCG_METHOD_FULL_PCG)
+        return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
+    if (opts->a < 0 || opts->T < 0 || opts->tol < 0.0 || opts->a_list_len < 0 ||
+        (opts->a_list_len > 0 && !opts->a_list))
+        return fail(ctx, SPCG_E_INVALID_ARG, "bad solve options");
+    const int a = opts->a > 0 ? opts->a : 3;
+    const int T = opts->T > 0 ? opts->T : 100;
+    const double tol = opts->tol > 0.0 ? opts->tol : 5e-7;
+    const bool timing = opts->time_phases != 0;
+    if (timing || opts->time_products) {
+        if ((rc = ensure_events(ctx)) != SPCG_OK) return rc;
+    }
+    hipStream_t st = ctx->stream;
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
+    spcg_sketch_opts so = opts->sketch;
+    so.hat_only = opts->method == SPCG_METHOD_FULL_PCG ? 1 : 0;
+    spcg_sketch_t sk;
+    if ((rc = sketch_build(ctx, X, Y, &so, true, &sk)) != SPCG_OK) return rc;
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
+    spcg_precond_t pc;
+    if ((rc = precond_build(ctx, &sk, &opts->precond, true, &pc)) != SPCG_OK) return rc;
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
+    const int64_t d = X->cols;
+    DspaceState S{};
+    if ((rc = ensure_stage_ws(ctx, d, &S, beta, pc.pMinv)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_scalars_reset(st, S.sc));
+    HIP_TRY(ctx, run_fill(st, beta, d, 0.0));
+    // Stage I
+    int t1 = 0;
+    for (int64_t i = 0; i < sk.K; ++i) {
+        int ai = a;
+        if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
+        if (ai < 0) return fail(ctx, SPCG_E_INVALID_ARG, "negative a_i");
+        if (t1 + ai > T) ai = std::max(0, T - t1);
+        spcg_mat A{}, b{};
+        double c2 = 1.0;
+        spcg_sketch_view(&sk, (int)i, &A, &b, &c2);
+        if ((rc = stage_run_nosync(ctx, &A, &b, c2, &pc, beta, ai)) != SPCG_OK) return rc;
+        t1 += ai;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[3], st));
+    // Stage II: full data, refreshed gradient, stopping test
+    ProductTimer timer;
+    timer.ctx = ctx;
+    StageRun run;
+    rc = stage_run(ctx, X, Y, 1.0, &pc, beta, std::max(0, T - t1), tol, true, opts->check_every, &run,
+                   opts->time_products ? &timer : nullptr);
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[4], st));
+    if (rc != SPCG_OK && rc != SPCG_E_BREAKDOWN) return rc;
+    const int rc_stage = rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->K = (int32_t)sk.K;
+        stats->T_stage1 = t1;
+        stats->T_stage2 = run.iters_done;
+        stats->converged = run.converged;
+        stats->qr_passes = pc.passes;
+        stats->rho_final = run.sc.rho;
+        stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
+        const int64_t es = dtype_bytes(X->dtype);
+        stats->product_bytes = (double)X->rows * X->cols * es + (double)X->rows * 8.0;
+        if (timing || opts->time_products) HIP_TRY(ctx, hipStreamSynchronize(st));
+        if (timing) {
+            stats->t_sketch_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[1]);
+            stats->t_precond_ms = elapsed_ms(ctx->ev_phase[1], ctx->ev_phase[2]);
+            stats->t_stage1_ms = elapsed_ms(ctx->ev_phase[2], ctx->ev_phase[3]);
+            stats->t_stage2_ms = elapsed_ms(ctx->ev_phase[3], ctx->ev_phase[4]);
+            stats->t_total_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[4]);
+        }
+        if (opts->time_products) {
+            double sum = 0.0;
+            for (int i = 0; i < timer.used; ++i) sum += elapsed_ms(ctx->ev_prod[2 * i], ctx->ev_prod[2 * i + 1]);
+            stats->product_ms_sum = sum;
+            stats->product_launches = timer.used;
+        }
+    }
+    if (rc_stage == SPCG_E_BREAKDOWN) return rc_stage;
+    if (!run.converged) {
+        fail(ctx, SPCG_W_NOT_CONVERGED, "Stage II did not meet tol=%g within T=%d", tol, T);
+        return SPCG_W_NOT_CONVERGED;
+    }
+    return SPCG_OK;
+}
+
+}  // extern "C"

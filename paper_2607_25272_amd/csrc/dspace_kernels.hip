@@ -1,0 +1,288 @@
+// d-space part of a PCG iteration on gfx950 (all FP64).
+//
+// Phase A reduces the per-block product partials in a fixed order and
+// performs the step  alpha = rho / (p^T s),  x += alpha p,  g -= alpha s
+// (or g = g_true - alpha s when the product pass refreshed the gradient).
+// Phase B applies the preconditioner, z = H_hat^{-1} g = R^{-1} R^{-T} g,
+// as one symmetric matrix-vector product with the precomputed FP64
+// operator M = R^{-1} R^{-T}, and performs  rho' = g^T z,
+// p = z + (rho'/rho) p.  Both phases spread the O(d) / O(d^2) work over
+// many blocks and let the last block to finish (device-scope counter) form
+// the scalars, so a whole PCG iteration is three kernel launches and no
+// host synchronisation.
+//
+// Guard rules (shared with the oracle's PCG): rho == 0 means the current
+// iterate is exact and no step is taken; p^T s <= 0 or a non-finite scalar
+// is a breakdown: the step is skipped, x keeps its last good value and a
+// sticky flag is raised for the host.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace spcg {
+
+namespace {
+
+constexpr int A_COLS = 64;   // columns per phase-A block
+constexpr int B_ROWS = 4;    // rows of M per phase-B block (one per wave)
+
+struct PhaseAArgs {
+    DspaceState S;
+    const double* part_s;
+    const double* part_g;
+    const double* part_scal;
+    int nparts;
+    int64_t dpad;
+    double c2;
+    int variant;
+};
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+__global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
+    __shared__ double sh_s[4][A_COLS];
+    __shared__ double sh_g[4][A_COLS];
+    __shared__ double sh_r[256];
+    __shared__ double sh_t[256];
+    __shared__ int is_last;
+    const DspaceState& S = a.S;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * A_COLS + tx;
+    const bool want_s = a.variant != PA_START;
+    const bool want_g = a.variant != PA_STEP;
+    double ss = 0.0, gg = 0.0;
+    if (col < S.d) {
+        for (int b = ty; b < a.nparts; b += 4) {
+            if (want_s) ss += a.part_s[(int64_t)b * a.dpad + col];
+            if (want_g) gg += a.part_g[(int64_t)b * a.dpad + col];
+        }
+    }
+    sh_s[ty][tx] = ss;
+    sh_g[ty][tx] = gg;
+    __syncthreads();
+    double dot = 0.0;
+    if (ty == 0 && col < S.d) {
+        const double s_col = (((sh_s[0][tx] + sh_s[1][tx]) + sh_s[2][tx]) + sh_s[3][tx]) * a.c2;
+        const double g_col = (((sh_g[0][tx] + sh_g[1][tx]) + sh_g[2][tx]) + sh_g[3][tx]) * a.c2;
+        if (a.variant == PA_START) {
+            S.g[col] = g_col;
+        } else {
+            S.s[col] = s_col;
+            dot = S.p[col] * s_col;
+            if (a.variant == PA_REFRESH) S.gt[col] = g_col;
+        }
+    }
+    if (ty == 0) {
+        dot = group_sum<64>(dot);
+        if (tx == 0) S.blk[blockIdx.x] = dot;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(&S.counters[0], 1u);
+        is_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+
+    // ---- last block: scalars and the x / g update
+    PcgScalars* sc = S.sc;
+    if (want_g) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int b = threadIdx.x; b < a.nparts; b += 256) {
+            t0 += a.part_scal[2 * b];
+            t1 += a.part_scal[2 * b + 1];
+        }
+        sh_r[threadIdx.x] = t0;
+        sh_t[threadIdx.x] = t1;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                sh_r[threadIdx.x] += sh_r[threadIdx.x + w];
+                sh_t[threadIdx.x] += sh_t[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+    }
+    __shared__ double alpha_sh;
+    __shared__ int do_step;
+    if (threadIdx.x == 0) {
+        if (want_g) {
+            sc->resid2 = sh_r[0] * a.c2;
+            sc->ax2 = sh_t[0] * a.c2;
+        }
+        do_step = 0;
+        if (a.variant == PA_START) {
+            sc->exact = 0;
+        } else {
+            double pts = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) pts += S.blk[b];
+            sc->pts = pts;
+            const double rho = sc->rho;
+            if (sc->breakdown || sc->exact) {
+                sc->alpha = 0.0;
+            } else if (rho == 0.0) {
+                sc->exact = 1;
+                sc->alpha = 0.0;
+            } else if (!(pts > 0.0) || !finite(pts) || !finite(rho)) {
+                sc->breakdown = 1;
+                sc->alpha = 0.0;
+            } else {
+                alpha_sh = rho / pts;
+                sc->alpha = alpha_sh;
+                do_step = 1;
+            }
+        }
+        S.counters[0] = 0u;
+    }
+    __syncthreads();
+    if (do_step) {
+        const double al = alpha_sh;
+        const bool refresh = a.variant == PA_REFRESH;
+        for (int64_t c = threadIdx.x; c < S.d; c += 256) {
+            S.x[c] = fma(al, S.p[c], S.x[c]);
+            const double gbase = refresh ? S.gt[c] : S.g[c];
+            S.g[c] = fma(-al, S.s[c], gbase);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
+    __shared__ double sh[B_ROWS];
+    __shared__ double red[256];
+    __shared__ int is_last;
+    PcgScalars* sc = S.sc;
+    const bool skip = sc->breakdown || (!init && sc->exact);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * B_ROWS + wave;
+    double gz = 0.0;
+    if (!skip && i < S.d) {
+        const double* row = S.Minv + i * S.d;
+        double acc = 0.0;
+        for (int64_t j = lane; j < S.d; j += 64) acc = fma(row[j], S.g[j], acc);
+        acc = group_sum<64>(acc);
+        if (lane == 0) {
+            S.z[i] = acc;
+            gz = S.g[i] * acc;
+        }
+    }
+    if (lane == 0) sh[wave] = gz;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < B_ROWS; ++w) t += sh[w];
+        S.blk[blockIdx.x] = t;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(&S.counters[1], 1u);
+        is_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    // fixed-order reduction of the block partials
+    double t = 0.0;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) t += S.blk[b];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    __shared__ double gamma_sh;
+    __shared__ int mode;  // 0 skip, 1 p = z, 2 p = z + gamma p
+    if (threadIdx.x == 0) {
+        const double rho_new = red[0];
+        mode = 0;
+        if (!skip) {
+            if (!finite(rho_new)) {
+                sc->breakdown = 1;
+            } else if (init) {
+                sc->rho = rho_new;
+                sc->rho0 = rho_new;
+                sc->exact = rho_new == 0.0;
+                mode = 1;
+            } else {
+                gamma_sh = rho_new / sc->rho;
+                sc->rho = rho_new;
+                if (rho_new == 0.0) sc->exact = 1;
+                mode = 2;
+            }
+        }
+        S.counters[1] = 0u;
+    }
+    __syncthreads();
+    if (mode == 1) {
+        for (int64_t c = threadIdx.x; c < S.d; c += 256) S.p[c] = S.z[c];
+    } else if (mode == 2) {
+        const double gm = gamma_sh;
+        for (int64_t c = threadIdx.x; c < S.d; c += 256) S.p[c] = fma(gm, S.p[c], S.z[c]);
+    }
+}
+
+__global__ void scalars_reset_kernel(PcgScalars* sc) {
+    sc->rho = 0.0;
+    sc->alpha = 0.0;
+    sc->pts = 0.0;
+    sc->resid2 = 0.0;
+    sc->ax2 = 0.0;
+    sc->rho0 = 0.0;
+    sc->exact = 0;
+    sc->breakdown = 0;
+    sc->iters = 0;
+    sc->pad = 0;
+}
+
+__global__ void fill_kernel(double* v, int64_t n, double value) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = value;
+}
+
+__global__ void counters_reset_kernel(unsigned int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
+}  // namespace
+
+hipError_t run_scalars_reset(hipStream_t st, PcgScalars* sc) {
+    scalars_reset_kernel<<<1, 1, 0, st>>>(sc);
+    return hipGetLastError();
+}
+
+hipError_t run_fill(hipStream_t st, double* v, int64_t n, double value) {
+    if (n <= 0) return hipSuccess;
+    fill_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(v, n, value);
+    return hipGetLastError();
+}
+
+hipError_t run_counters_reset(hipStream_t st, unsigned int* c, int n) {
+    counters_reset_kernel<<<1, 64, 0, st>>>(c, n);
+    return hipGetLastError();
+}
+
+hipError_t run_phase_a(hipStream_t st, const DspaceState& S, int variant, const double* part_s,
+                       const double* part_g, const double* part_scal, int nparts, int64_t dpad,
+                       double c2) {
+    PhaseAArgs a;
+    a.S = S;
+    a.part_s = part_s;
+    a.part_g = part_g;
+    a.part_scal = part_scal;
+    a.nparts = nparts;
+    a.dpad = dpad;
+    a.c2 = c2;
+    a.variant = variant;
+    const int64_t grid = ceil_div(S.d, A_COLS);
+    phase_a_kernel<<<(unsigned)grid, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t run_phase_b(hipStream_t st, const DspaceState& S, int init) {
+    const int64_t grid = ceil_div(S.d, B_ROWS);
+    phase_b_kernel<<<(unsigned)grid, 256, 0, st>>>(S, init);
+    return hipGetLastError();
+}
+
+}  // namespace spcg

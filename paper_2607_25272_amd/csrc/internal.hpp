@@ -1,0 +1,133 @@
+// Internal launch interface between the host driver (api.hip) and the
+// kernel files.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace spcg {
+
+// ---------------------------------------------------------------- sketch
+// Per-row randomness tables for a padded size Np = 2^L:
+//   perm_sign[k] = p(k) | (sign_bit(k) << 31)
+//   inv_slot[k]  = pi^{-1}(k)     if < mK, else -1
+//   inv_hat[k]   = pi_hat^{-1}(k) if < r,  else -1
+hipError_t launch_sketch_tables(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
+                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat);
+// Forward maps for export (device arrays, any may be null).
+hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
+                                int32_t* slot_rows, int32_t* hat_rows, int32_t* input_perm,
+                                uint8_t* sign_bits);
+
+struct FwhtJob {
+    const void* x;          // N x d input rows, element type in_dtype, leading dim ldx
+    int in_dtype;           // DT_*; TZ is double for DT_F64, float otherwise
+    int64_t N, d, ldx;
+    const float* col_scale; // FP8 only
+    int L;
+    const int32_t* perm_sign;
+    const int32_t* inv_slot;  // may be null (no stage sketch output)
+    const int32_t* inv_hat;   // may be null (no S_hat output)
+    void* zbuf;               // Np x ldz scratch of TZ (unused when L fits one pass)
+    int64_t ldz;
+    void* B;                  // mK x ldb of TZ (rows pi(t)), or null
+    int64_t ldb;
+    void* Bh;                 // r x ldbh of TZ (rows pi_hat(t)), or null
+    int64_t ldbh;
+    int narrow;               // 1: single-column FP64 transform (the response vector)
+};
+// Column-chunk width of the transform: every row width used by a job
+// (ldz, ldb, ldbh) must be equal and a multiple of it.
+inline int fwht_chunk_cols(int in_dtype, int narrow) {
+    return narrow ? 1 : (in_dtype == DT_F64 ? 8 : 16);
+}
+hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
+
+// --------------------------------------------------------------- product
+enum ProdMode : int { PM_S = 0, PM_G = 1, PM_SG = 2 };
+
+struct ProdJob {
+    const void* A;
+    int dtype;
+    int64_t m, d, lda;
+    int64_t dmem;            // columns readable in every row (>= d; padding of library buffers)
+    const float* col_scale;  // FP8 only
+    const double* b;         // m rows (G/SG), stride ldbv
+    int64_t ldbv;
+    const double* x;         // d (G/SG)
+    const double* p;         // d (S/SG)
+    int mode;
+    double* part_s;          // [nblocks][dpad]
+    double* part_g;          // [nblocks][dpad]
+    double* part_scal;       // [nblocks][2]: sum (b - a.x)^2, sum (a.x)^2
+    int64_t dpad;
+    int num_cu;
+};
+// Chooses the launch shape, returns the number of blocks (partials) used.
+hipError_t run_product(hipStream_t st, const ProdJob& job, int* nblocks_out);
+int64_t product_max_blocks(int num_cu);
+int64_t product_max_d(int dtype);
+
+// ---------------------------------------------------------------- d-space
+struct PcgScalars {
+    double rho;       // g^T H^-1 g (current)
+    double alpha;
+    double pts;       // p^T s
+    double resid2;    // c2 ||b - A x||^2 from the last G/SG pass
+    double ax2;       // c2 ||A x||^2 from the last G/SG pass
+    double rho0;
+    int32_t exact;    // rho reached exactly zero in this stage
+    int32_t breakdown;// sticky: p^T s <= 0 or non-finite
+    int32_t iters;
+    int32_t pad;
+};
+
+struct DspaceState {
+    double* x;        // d (caller beta for k = 1)
+    double* g;        // d
+    double* z;        // d
+    double* p;        // d
+    double* s;        // d
+    double* gt;       // d (refreshed gradient)
+    double* blk;      // per-block partial scalars (>= 1024)
+    unsigned int* counters;  // 2 counters, zero between launches
+    PcgScalars* sc;
+    const double* Minv;  // d x d
+    int64_t d;
+};
+// phase A: reduce the product partials; start / step / refresh variants
+enum PhaseA : int { PA_START = 0, PA_STEP = 1, PA_REFRESH = 2 };
+hipError_t run_phase_a(hipStream_t st, const DspaceState& S, int variant, const double* part_s,
+                       const double* part_g, const double* part_scal, int nparts, int64_t dpad,
+                       double c2);
+// phase B: z = H^-1 g, rho' = g^T z, p update (init or CG step)
+hipError_t run_phase_b(hipStream_t st, const DspaceState& S, int init);
+hipError_t run_scalars_reset(hipStream_t st, PcgScalars* sc);
+hipError_t run_fill(hipStream_t st, double* v, int64_t n, double value);
+hipError_t run_counters_reset(hipStream_t st, unsigned int* c, int n);
+
+// --------------------------------------------------------- dense FP64
+struct DenseStatus {
+    int32_t fail;        // first failing pivot index + 1, 0 if none
+    int32_t pad;
+    double min_diag, max_diag;   // of the computed factor
+    double min_pivot;            // smallest pivot (before sqrt)
+};
+// C = alpha op(A) op(B) + beta C; A(i,l) = A[i*sai + l*sal], B(l,j) = B[l*sbl + j*sbj]
+// upper = 1: only 64x64 tiles on or above the block diagonal are computed.
+hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
+                    int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
+                    int64_t sbj, double beta, double* C, int64_t ldc, int upper);
+// In-place upper Cholesky G = U^T U (row-major d x d, ld); lower part zeroed.
+hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status);
+// In-place A <- A U^{-1} for A (n x d, lda) and upper-triangular U (d x d, ldu).
+hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int64_t lda,
+                            const double* U, int64_t ldu);
+hipError_t dense_fill_identity(hipStream_t st, double* A, int64_t d);
+hipError_t dense_convert(hipStream_t st, const void* src, int src_f32, int64_t rows, int64_t cols,
+                         int64_t lds, double scale, double* dst, int64_t ldd);
+hipError_t dense_add_trace_shift(hipStream_t st, double* G, int64_t d, double factor);
+hipError_t dense_status_reset(hipStream_t st, DenseStatus* status);
+
+}  // namespace spcg

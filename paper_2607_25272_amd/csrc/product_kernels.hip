@@ -1,0 +1,410 @@
+// PCG products on gfx950: one HBM pass over a row-major m x d matrix A.
+//
+// The two tall-skinny products of a PCG iteration (Sec. 2.2: 4 m d of the
+// (4m + 13) d + 2 d^2 flops) are fused into one read of A:
+//
+//   S  mode: s = A^T (A p)                      (the CG product)
+//   G  mode: g = A^T (b - A x), ||b - A x||^2, ||A x||^2   (stage start)
+//   SG mode: both in the same pass              (full-data refinement)
+//
+// Layout: each row is covered by LPR lanes (a power of two <= 64) that
+// load VEC-element 16-byte vectors, NSLOT per lane; 64 / LPR rows share a
+// wavefront.  For each row the lanes form the dot product(s) with a group
+// shuffle reduction and then accumulate w * a_row into per-lane column
+// accumulators held in registers, so A is read exactly once and never
+// staged.  Each block owns a contiguous range of rows and writes one FP64
+// partial per column; the partials are summed in a fixed order by the
+// d-space kernel (deterministic results).
+//
+// Accumulation: the p-product uses float for FP32/BF16/FP8 storage and
+// double for FP64 storage; everything involving x and b (the residual and
+// the gradient) accumulates in double, with the stored values widened
+// exactly.  FP8 per-column scales are folded into p and x on entry and
+// into the partial columns on exit.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace spcg {
+
+namespace {
+
+constexpr int NW = 4;        // waves per block
+constexpr int DMAX_LDS = 4096;
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+template <int BYTES>
+struct RawVec;
+template <>
+struct RawVec<16> {
+    typedef uint4 T;
+};
+template <>
+struct RawVec<8> {
+    typedef uint2 T;
+};
+template <>
+struct RawVec<4> {
+    typedef uint32_t T;
+};
+template <>
+struct RawVec<2> {
+    typedef uint16_t T;
+};
+template <>
+struct RawVec<1> {
+    typedef uint8_t T;
+};
+
+template <typename TS>
+struct Store;
+template <>
+struct Store<double> {
+    typedef double CT;
+    static constexpr int BYTES = 8;
+    static constexpr int VMAX = 2;
+};
+template <>
+struct Store<float> {
+    typedef float CT;
+    static constexpr int BYTES = 4;
+    static constexpr int VMAX = 4;
+};
+template <>
+struct Store<bf16_t> {
+    typedef float CT;
+    static constexpr int BYTES = 2;
+    static constexpr int VMAX = 8;
+};
+template <>
+struct Store<fp8_t> {
+    typedef float CT;
+    static constexpr int BYTES = 1;
+    static constexpr int VMAX = 16;
+};
+
+__device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ uint32_t word_of(const uint2& v, int i) { return i == 0 ? v.x : v.y; }
+__device__ __forceinline__ uint32_t word_of(const uint32_t& v, int) { return v; }
+__device__ __forceinline__ uint32_t word_of(const uint16_t& v, int) { return v; }
+__device__ __forceinline__ uint32_t word_of(const uint8_t& v, int) { return v; }
+
+// Widen the VEC elements of a raw vector into out[0..VEC).
+template <typename TS, int VEC, typename R>
+struct Widen;
+
+template <int VEC, typename R>
+struct Widen<double, VEC, R> {
+    __device__ static void run(const R& raw, double* out) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            uint32_t lo = word_of(raw, 2 * e), hi = word_of(raw, 2 * e + 1);
+            out[e] = __hiloint2double((int)hi, (int)lo);
+        }
+    }
+};
+template <int VEC, typename R>
+struct Widen<float, VEC, R> {
+    __device__ static void run(const R& raw, float* out) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) out[e] = __uint_as_float(word_of(raw, e));
+    }
+};
+template <int VEC, typename R>
+struct Widen<bf16_t, VEC, R> {
+    __device__ static void run(const R& raw, float* out) {
+        if constexpr (VEC == 1) {
+            out[0] = __uint_as_float((uint32_t)raw << 16);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; e += 2) {
+                uint32_t w = word_of(raw, e / 2);
+                out[e] = __uint_as_float(w << 16);
+                out[e + 1] = __uint_as_float(w & 0xffff0000u);
+            }
+        }
+    }
+};
+template <int VEC, typename R>
+struct Widen<fp8_t, VEC, R> {
+    __device__ static void run(const R& raw, float* out) {
+        if constexpr (VEC == 1) {
+            out[0] = __builtin_amdgcn_cvt_f32_fp8((int)(uint32_t)raw, 0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; e += 4) {
+                int w = (int)word_of(raw, e / 4);
+                v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+                v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+                out[e] = lo.x;
+                out[e + 1] = lo.y;
+                out[e + 2] = hi.x;
+                out[e + 3] = hi.y;
+            }
+        }
+    }
+};
+
+struct ProdArgs {
+    const void* A;
+    int64_t m, lda, rpb;
+    int d, nvec;
+    const float* col_scale;
+    const double* b;
+    int64_t ldbv;
+    const double* x;
+    const double* p;
+    double* part_s;
+    double* part_g;
+    double* part_scal;
+    int64_t dpad;
+};
+
+template <typename TS, int VEC, int LPR, int NSLOT, int MODE, int U>
+__global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
+    typedef typename Store<TS>::CT CT;
+    typedef typename RawVec<VEC * Store<TS>::BYTES>::T Raw;
+    constexpr bool DO_S = MODE != PM_G;
+    constexpr bool DO_G = MODE != PM_S;
+    constexpr bool FP8 = std::is_same<TS, fp8_t>::value;
+    constexpr int RPW = 64 / LPR;
+    constexpr int NC = NSLOT * VEC;
+    constexpr int DCOLS = NSLOT * VEC * LPR;
+    __shared__ double red_s[DO_S ? DCOLS : 1];
+    __shared__ double red_g[DO_G ? DCOLS : 1];
+    __shared__ double red_scal[2 * NW];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lir = lane & (LPR - 1), rs = lane / LPR;
+    const int d = a.d;
+
+    CT preg[NC];
+    double xreg[NC];
+    CT sacc[NC];
+    double gacc[NC];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int i = s * VEC + e;
+            const int col = (lir + s * LPR) * VEC + e;
+            const bool ok = col < d;
+            double sc = 1.0;
+            if (FP8 && ok) sc = (double)a.col_scale[col];
+            preg[i] = (DO_S && ok) ? (CT)(a.p[col] * sc) : CT(0);
+            xreg[i] = (DO_G && ok) ? a.x[col] * sc : 0.0;
+            sacc[i] = CT(0);
+            gacc[i] = 0.0;
+        }
+    }
+    double r2 = 0.0, ax2 = 0.0;
+
+    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
+    const int64_t r1 = min(a.m, r0 + a.rpb);
+    const char* Abase = static_cast<const char*>(a.A);
+    const int64_t row_bytes = a.lda * Store<TS>::BYTES;
+
+    for (int64_t base = r0 + (int64_t)wave * (U * RPW); base < r1; base += NW * U * RPW) {
+        Raw raw[U][NSLOT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = base + u * RPW + rs;
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const int vi = lir + s * LPR;
+                if (row < r1 && vi < a.nvec) {
+                    raw[u][s] = *reinterpret_cast<const Raw*>(Abase + row * row_bytes +
+                                                              (int64_t)vi * (VEC * Store<TS>::BYTES));
+                } else {
+                    raw[u][s] = Raw{};
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = base + u * RPW + rs;
+            const bool valid = row < r1;
+            CT v[NC];
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) Widen<TS, VEC, Raw>::run(raw[u][s], v + s * VEC);
+            CT dp = CT(0);
+            double dx = 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (DO_S) dp = fma(v[i], preg[i], dp);
+                if (DO_G) dx = fma((double)v[i], xreg[i], dx);
+            }
+            if (DO_S) dp = group_sum<LPR>(dp);
+            double w = 0.0;
+            if (DO_G) {
+                dx = group_sum<LPR>(dx);
+                const double bb = valid ? a.b[row * a.ldbv] : 0.0;
+                w = valid ? bb - dx : 0.0;
+                if (lir == 0 && valid) {
+                    r2 = fma(w, w, r2);
+                    ax2 = fma(dx, dx, ax2);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (DO_S) sacc[i] = fma(dp, v[i], sacc[i]);
+                if (DO_G) gacc[i] = fma(w, (double)v[i], gacc[i]);
+            }
+        }
+    }
+
+    // lanes with the same lir in different row slots hold the same columns
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            if (DO_S) sacc[i] += __shfl_xor(sacc[i], o);
+            if (DO_G) gacc[i] += __shfl_xor(gacc[i], o);
+        }
+    }
+    // fixed wave order into LDS
+    for (int wv = 0; wv < NW; ++wv) {
+        if (wave == wv && rs == 0) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int col = (lir + s * LPR) * VEC + e;
+                    if (col < d) {
+                        const int i = s * VEC + e;
+                        if (DO_S) red_s[col] = (wv == 0 ? 0.0 : red_s[col]) + (double)sacc[i];
+                        if (DO_G) red_g[col] = (wv == 0 ? 0.0 : red_g[col]) + gacc[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (DO_G) {
+        r2 = group_sum<64>(r2);
+        ax2 = group_sum<64>(ax2);
+        if (lane == 0) {
+            red_scal[2 * wave] = r2;
+            red_scal[2 * wave + 1] = ax2;
+        }
+    }
+    __syncthreads();
+    const int64_t prow = (int64_t)blockIdx.x * a.dpad;
+    for (int col = threadIdx.x; col < d; col += 64 * NW) {
+        const double sc = FP8 ? (double)a.col_scale[col] : 1.0;
+        if (DO_S) a.part_s[prow + col] = red_s[col] * sc;
+        if (DO_G) a.part_g[prow + col] = red_g[col] * sc;
+    }
+    if (DO_G && threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int wv = 0; wv < NW; ++wv) {
+            t0 += red_scal[2 * wv];
+            t1 += red_scal[2 * wv + 1];
+        }
+        a.part_scal[2 * blockIdx.x] = t0;
+        a.part_scal[2 * blockIdx.x + 1] = t1;
+    }
+}
+
+template <typename TS, int VEC, int LPR, int NSLOT>
+hipError_t launch_shape(hipStream_t st, const ProdArgs& a, int mode, int nblocks) {
+    constexpr int U = NSLOT <= 2 ? 4 : (NSLOT <= 4 ? 2 : 1);
+    dim3 grid(nblocks), block(64 * NW);
+    switch (mode) {
+        case PM_S: product_kernel<TS, VEC, LPR, NSLOT, PM_S, U><<<grid, block, 0, st>>>(a); break;
+        case PM_G: product_kernel<TS, VEC, LPR, NSLOT, PM_G, U><<<grid, block, 0, st>>>(a); break;
+        default: product_kernel<TS, VEC, LPR, NSLOT, PM_SG, U><<<grid, block, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename TS, int VEC>
+hipError_t launch_vec(hipStream_t st, const ProdArgs& a, int mode, int nblocks, int lpr, int nslot) {
+    if (lpr == 4) return launch_shape<TS, VEC, 4, 1>(st, a, mode, nblocks);
+    if (lpr == 8) return launch_shape<TS, VEC, 8, 1>(st, a, mode, nblocks);
+    if (lpr == 16) return launch_shape<TS, VEC, 16, 1>(st, a, mode, nblocks);
+    if (lpr == 32) return launch_shape<TS, VEC, 32, 1>(st, a, mode, nblocks);
+    if (nslot == 1) return launch_shape<TS, VEC, 64, 1>(st, a, mode, nblocks);
+    if (nslot == 2) return launch_shape<TS, VEC, 64, 2>(st, a, mode, nblocks);
+    if (nslot == 4) return launch_shape<TS, VEC, 64, 4>(st, a, mode, nblocks);
+    if constexpr (VEC * 64 * 8 <= DMAX_LDS) {
+        if (nslot == 8) return launch_shape<TS, VEC, 64, 8>(st, a, mode, nblocks);
+    }
+    if constexpr (VEC * 64 * 16 <= DMAX_LDS) {
+        if (nslot == 16) return launch_shape<TS, VEC, 64, 16>(st, a, mode, nblocks);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename TS>
+hipError_t launch_type(hipStream_t st, const ProdArgs& a, int mode, int nblocks, int vec, int lpr,
+                       int nslot) {
+    if (vec == Store<TS>::VMAX) return launch_vec<TS, Store<TS>::VMAX>(st, a, mode, nblocks, lpr, nslot);
+    if (vec == 1) return launch_vec<TS, 1>(st, a, mode, nblocks, lpr, nslot);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int64_t product_max_blocks(int num_cu) { return (int64_t)(num_cu > 0 ? num_cu : 256) * 4; }
+
+int64_t product_max_d(int dtype) { return dtype == DT_F64 ? 2048 : 4096; }
+
+hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
+    *nblocks_out = 0;
+    const int bytes = dtype_bytes(j.dtype);
+    if (bytes == 0 || j.d < 1 || j.m < 0) return hipErrorInvalidValue;
+    if (j.m == 0) return hipSuccess;
+    int vec = 16 / bytes;
+    int64_t nvec = ceil_div(j.d, vec);
+    const bool aligned = (j.lda % vec == 0) && ((uintptr_t)j.A % 16 == 0) && (nvec * vec <= j.dmem);
+    if (!aligned) {
+        vec = 1;
+        nvec = j.d;
+    }
+    int lpr = 4;
+    while (lpr < 64 && lpr < nvec) lpr <<= 1;
+    int64_t ns = ceil_div(nvec, lpr);
+    int nslot = 1;
+    while (nslot < ns) nslot <<= 1;
+    if (nslot > 16 || (int64_t)nslot * vec * lpr > DMAX_LDS) return hipErrorInvalidValue;
+    const int U = nslot <= 2 ? 4 : (nslot <= 4 ? 2 : 1);
+    const int64_t rows_per_sweep = (int64_t)NW * U * (64 / lpr);
+    int64_t nb = ceil_div(j.m, rows_per_sweep * 4);
+    nb = std::max<int64_t>(1, std::min<int64_t>(nb, product_max_blocks(j.num_cu)));
+    int64_t rpb = ceil_div(j.m, nb);
+    nb = ceil_div(j.m, rpb);
+    ProdArgs a{};
+    a.A = j.A;
+    a.m = j.m;
+    a.lda = j.lda;
+    a.rpb = rpb;
+    a.d = (int)j.d;
+    a.nvec = (int)nvec;
+    a.col_scale = j.col_scale;
+    a.b = j.b;
+    a.ldbv = j.ldbv;
+    a.x = j.x;
+    a.p = j.p;
+    a.part_s = j.part_s;
+    a.part_g = j.part_g;
+    a.part_scal = j.part_scal;
+    a.dpad = j.dpad;
+    hipError_t e;
+    switch (j.dtype) {
+        case DT_F64: e = launch_type<double>(st, a, j.mode, (int)nb, vec, lpr, nslot); break;
+        case DT_F32: e = launch_type<float>(st, a, j.mode, (int)nb, vec, lpr, nslot); break;
+        case DT_BF16: e = launch_type<bf16_t>(st, a, j.mode, (int)nb, vec, lpr, nslot); break;
+        case DT_FP8: e = launch_type<fp8_t>(st, a, j.mode, (int)nb, vec, lpr, nslot); break;
+        default: e = hipErrorInvalidValue;
+    }
+    if (e == hipSuccess) *nblocks_out = (int)nb;
+    return e;
+}
+
+}  // namespace spcg

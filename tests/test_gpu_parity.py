@@ -1,0 +1,327 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sketch randomness and FP64 sketch rows are compared bit for bit; FP32
+sketch rows, the QR factor, PCG stages and whole solves within stated
+tolerances; whole solves must reach the OLS estimator of the stored data to
+a relative prediction error of 1e-6 (Sec. 1 eq. (ols); Algorithm 1).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle.linalg import householder_qr
+from oracle.ols import ols_householder, ols_tsqr
+from oracle.pcg import pcg
+from oracle.sketch import (hat_slot_rows, input_perm, nested_srht, padded_bits, sign_vector,
+                           slot_rows)
+from oracle.spcg import precond_from_sketch, rel_pred_error, schedule, spcg
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2607_25272_amd as spcg_mod
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    return spcg_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _problem(N, d, cond=1e3, sigma=0.1, storage="f64", seed=5, k=1):
+    p = workloads.gauss_colscale(N, d, cond, sigma, storage=storage, k=k, seed=seed, device=DEV)
+    return p
+
+
+# ------------------------------------------------------------ randomness
+
+@pytest.mark.parametrize("N,d,seed", [(20000, 50, 1), (3000, 10, 77)])
+def test_device_randomness_bit_exact(S, ctx, N, d, seed):
+    _log(f"randomness N={N} d={d} seed={seed}")
+    p = _problem(N, d, seed=seed)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=seed)
+    ex = sk.export()
+    L = sk.info.L
+    mK = sk.sizes[-1]
+    assert np.array_equal(ex["slot_rows"], slot_rows(seed, L, mK))
+    assert np.array_equal(ex["hat_rows"], hat_slot_rows(seed, L, sk.info.r))
+    assert np.array_equal(ex["input_perm"], input_perm(seed, L))
+    bits = np.unpackbits(ex["sign_bits"], bitorder="little")[: 1 << L]
+    assert np.array_equal(1.0 - 2.0 * bits, sign_vector(seed, L))
+
+
+def test_device_randomness_large_sampled(S, ctx):
+    # N' = 2^22 (the 4e6-row workload): every exported slot and sign is
+    # compared at 20000 sampled positions
+    N, d, seed = 4_000_000, 4, 3
+    _log("randomness N'=2^22 sampled")
+    X = torch.zeros(N, d, dtype=torch.float32, device=DEV)
+    X[:, 0] = 1.0
+    Y = torch.zeros(N, 1, dtype=torch.float64, device=DEV)
+    sk = S.spcg_sketch(ctx, X, Y, seed=seed, m0=1 << 20)
+    ex = sk.export()
+    L = sk.info.L
+    assert L == 22
+    rng = np.random.default_rng(0)
+    t = rng.integers(0, sk.sizes[-1], 20000)
+    from oracle.feistel import feistel_forward
+    from oracle.sketch import STREAM_P, STREAM_PI
+    assert np.array_equal(ex["slot_rows"][t], feistel_forward(t.astype(np.uint64), L, seed, STREAM_PI).astype(np.int64))
+    k = rng.integers(0, 1 << L, 20000)
+    assert np.array_equal(ex["input_perm"][k], feistel_forward(k.astype(np.uint64), L, seed, STREAM_P).astype(np.int64))
+    bits = np.unpackbits(ex["sign_bits"], bitorder="little")
+    assert np.array_equal(1.0 - 2.0 * bits[k], sign_vector(seed, L, k))
+
+
+# ---------------------------------------------------------------- sketch
+
+@pytest.mark.parametrize("N,d", [(20000, 50), (2500, 7), (4096, 64), (70000, 24)])
+def test_sketch_rows_f64_bit_exact(S, ctx, N, d):
+    # FP64 path: same butterflies in the same stage order -> identical bits
+    _log(f"sketch f64 N={N} d={d}")
+    p = _problem(N, d, seed=N + d)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=11)
+    B, BY, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 11, sk.sizes[-1], sk.info.r)
+    Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    Hg, _, _ = sk.view_tensor(-1)
+    assert np.array_equal(Ag.cpu().numpy(), B)
+    assert np.array_equal(bg.cpu().numpy(), BY)
+    assert np.array_equal(Hg.cpu().numpy(), Bh)
+    # prefix views: stage i = first m_i rows
+    A0, b0, c2 = sk.view_tensor(0)
+    assert A0.shape[0] == sk.sizes[0] and c2 == 1.0 / sk.sizes[0]
+    assert np.array_equal(A0.cpu().numpy(), B[: sk.sizes[0]])
+
+
+@pytest.mark.parametrize("storage,N,d,tol", [("f32", 9000, 37, 2e-6), ("bf16", 6000, 40, 2e-6),
+                                             ("fp8", 5000, 48, 2e-6)])
+def test_sketch_rows_reduced_precision(S, ctx, storage, N, d, tol):
+    # FP32 transform of exactly-widened stored values vs the FP64 oracle on
+    # the same stored values; error bounded by L * u32 * row-norm scale
+    _log(f"sketch {storage} N={N} d={d}")
+    p = _problem(N, d, storage=storage, seed=3)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=5, col_scale=p.col_scale)
+    Xd = p.x_f64().cpu().numpy()
+    B, BY, Bh, info = nested_srht(Xd, p.Y.cpu().numpy(), 5, sk.sizes[-1], sk.info.r)
+    Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    Hg, _, _ = sk.view_tensor(-1)
+    scale = np.sqrt(info["Np"]) * np.abs(Xd).max(axis=0)   # |Z| <= sqrt(N') * column max
+    err = np.abs(Ag.cpu().numpy().astype(np.float64) - B) / scale
+    assert err.max() < tol * info["L"]
+    errh = np.abs(Hg.cpu().numpy().astype(np.float64) - Bh) / scale
+    assert errh.max() < tol * info["L"]
+    assert np.array_equal(bg.cpu().numpy(), BY)   # Y is always FP64
+
+
+# ------------------------------------------------------- preconditioner
+
+@pytest.mark.parametrize("passes", [0, 1, 2, 3])
+def test_precond_qr_matches_householder(S, ctx, passes):
+    N, d, cond = 30000, 60, 1e4
+    _log(f"precond passes={passes}")
+    p = _problem(N, d, cond=cond, seed=8)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=2)
+    _, _, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 2, sk.sizes[-1], sk.info.r)
+    R_or = precond_from_sketch(Bh)
+    pc = S.spcg_precond_build(ctx, sk, qr_passes=passes)
+    R, used = pc.export()
+    assert used == (1 if passes in (0, 1) else passes)
+    assert np.all(np.diag(R) > 0) and np.allclose(np.tril(R, -1), 0)
+    kappa = np.linalg.cond(R_or)
+    u = 2.0 ** -53
+    bound = 50 * d * (kappa ** 2 if used == 1 else kappa) * u
+    rel = np.linalg.norm(R - R_or) / np.linalg.norm(R_or)
+    assert rel < bound, (rel, bound)
+
+
+def test_precond_ill_conditioned_falls_back_to_three_passes(S, ctx):
+    N, d = 1 << 14, 16
+    _log("precond kappa=1e8")
+    p = _problem(N, d, cond=1e8, storage="f64", seed=9)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=4)
+    pc = S.spcg_precond_build(ctx, sk, qr_passes=0)
+    R, used = pc.export()
+    assert used == 3
+    _, _, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 4, sk.sizes[-1], sk.info.r)
+    R_or = precond_from_sketch(Bh)
+    # the factor is accurate column-relative (it preconditions to kappa ~ 1)
+    Mi = np.linalg.solve(R.T, (Bh / np.sqrt(sk.info.r)).T).T
+    sv = np.linalg.svd(Mi, compute_uv=False)
+    assert sv.max() / sv.min() < 1.01
+    assert np.linalg.norm(R - R_or) / np.linalg.norm(R_or) < 1e-6
+
+
+def test_precond_rank_deficient_is_reported(S, ctx):
+    p = _problem(5000, 12, seed=10, storage="f64")
+    X = p.X.clone()
+    X[:, 5] = X[:, 3]
+    sk = S.spcg_sketch(ctx, X, p.Y, seed=1)
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_precond_build(ctx, sk, qr_passes=3)
+    assert e.value.code == S.SPCG_E_RANK
+
+
+# ------------------------------------------------------------ PCG stage
+
+@pytest.mark.parametrize("storage,rtol", [("f64", 1e-9), ("f32", 2e-3)])
+def test_pcg_stage_matches_oracle(S, ctx, storage, rtol):
+    # isolate the stage: the oracle's sketch rows and R are fed to both sides
+    N, d, a = 20000, 50, 3
+    _log(f"stage {storage}")
+    p = workloads.make_config(0, device=DEV, storage=storage)
+    Xd = p.x_f64().cpu().numpy()
+    Yd = p.Y.cpu().numpy()[:, 0]
+    sizes = schedule(N, d)
+    B, BY, Bh, _ = nested_srht(Xd, Yd, 1, sizes[-1], 6 * d)
+    R = precond_from_sketch(Bh)
+    pc = S.spcg_precond_from_r(ctx, torch.from_numpy(R))
+    x_or = np.zeros(d)
+    beta = torch.zeros(d, dtype=torch.float64, device=DEV)
+    tdt = torch.float64 if storage == "f64" else torch.float32
+    for i, m in enumerate(sizes):
+        A = torch.from_numpy(B[:m]).to(DEV, tdt)
+        b = torch.from_numpy(BY[:m]).to(DEV).unsqueeze(1)
+        x_or, _ = pcg(A.double().cpu().numpy(), BY[:m], 1.0 / m, R, x_or, a)
+        st = S.spcg_pcg_stage(ctx, A, b, 1.0 / m, pc, beta, a)
+        assert st["iters"] == a
+        xg = beta.cpu().numpy()
+        err = np.linalg.norm(Xd @ (xg - x_or)) / np.linalg.norm(Xd @ x_or)
+        assert err < rtol, (i, err)
+    # Stage II with the stopping test on the full data
+    st = S.spcg_pcg_stage(ctx, p.X, p.Y, 1.0, pc, beta, 80, tol=5e-7)
+    assert st["converged"]
+    bh = ols_householder(Xd, Yd)
+    assert rel_pred_error(Xd, beta.cpu().numpy(), bh) < 1e-6
+
+
+def test_pcg_stage_exact_preconditioner_one_step(S, ctx):
+    N, d = 5000, 20
+    p = _problem(N, d, seed=12)
+    Xd = p.x_f64().cpu().numpy()
+    R = householder_qr(Xd)
+    pc = S.spcg_precond_from_r(ctx, torch.from_numpy(R))
+    beta = torch.zeros(d, dtype=torch.float64, device=DEV)
+    S.spcg_pcg_stage(ctx, p.X, p.Y, 1.0, pc, beta, 1)
+    bh = ols_householder(Xd, p.Y.cpu().numpy()[:, 0])
+    assert rel_pred_error(Xd, beta.cpu().numpy(), bh) < 1e-12
+
+
+def test_pcg_stage_zero_rhs_and_breakdown(S, ctx):
+    N, d = 3000, 8
+    p = _problem(N, d, seed=13)
+    R = householder_qr(p.x_f64().cpu().numpy())
+    pc = S.spcg_precond_from_r(ctx, torch.from_numpy(R))
+    beta = torch.zeros(d, dtype=torch.float64, device=DEV)
+    st = S.spcg_pcg_stage(ctx, p.X, torch.zeros_like(p.Y), 1.0, pc, beta, 5, tol=1e-6)
+    assert st["converged"] and st["iters"] == 0 and torch.all(beta == 0)
+    Ybad = p.Y.clone()
+    Ybad[17] = float("nan")
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_pcg_stage(ctx, p.X, Ybad, 1.0, pc, beta, 3)
+    assert e.value.code == S.SPCG_E_BREAKDOWN
+
+
+# -------------------------------------------------------------- solves
+
+@pytest.mark.parametrize("method", ["spcg", "pcg"])
+def test_solve_config0_matches_ols(S, ctx, method):
+    _log(f"solve cfg0 {method}")
+    p = workloads.make_config(0, device=DEV)
+    Xd = p.x_f64().cpu().numpy()
+    Yd = p.Y.cpu().numpy()[:, 0]
+    beta, st = S.spcg_solve(ctx, p.X, p.Y, method=method, seed=1)
+    assert st["rc"] == 0 and st["converged"]
+    bh = ols_householder(Xd, Yd)
+    assert rel_pred_error(Xd, beta.cpu().numpy(), bh) <= 1e-6
+    if method == "spcg":
+        assert st["K"] == 7 and st["T_stage1"] == 21
+        b_or, info = spcg(Xd, Yd, seed=1)
+        # same algorithm on both sides: the Stage II iteration counts agree
+        assert abs(st["T_stage2"] - info["per_rhs"][0]["stage2"]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("storage,N,d", [("f32", 1 << 17, 100), ("f32", 100_003, 33),
+                                         ("bf16", 1 << 17, 128), ("fp8", 1 << 16, 64)])
+def test_solve_reduced_precision_storage(S, ctx, storage, N, d):
+    _log(f"solve {storage} N={N} d={d}")
+    p = _problem(N, d, cond=1e4, sigma=1.0, storage=storage, seed=21)
+    beta, st = S.spcg_solve(ctx, p.X, p.Y, col_scale=p.col_scale, seed=3)
+    assert st["converged"]
+    Xd = p.x_f64().cpu().numpy()
+    bh = ols_tsqr(Xd, p.Y.cpu().numpy()[:, 0])
+    assert rel_pred_error(Xd, beta.cpu().numpy(), bh) <= 1e-6
+
+
+def test_solve_argument_errors(S, ctx):
+    p = _problem(100, 8, seed=1)
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve(ctx, p.X[:8], p.Y[:8])
+    assert e.value.code == S.SPCG_E_SHAPE
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve(ctx, p.X, p.Y[:50])
+    assert e.value.code == S.SPCG_E_SHAPE
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve(ctx, p.X, p.Y.float())
+    assert e.value.code == S.SPCG_E_DTYPE
+
+
+# ------------------------------------------------ full-size workload
+
+def test_full_size_config1_against_ols(S, ctx):
+    """The benchmark workload (N = 1e6, d = 500, FP32, kappa 1e4) in the
+    benchmark's launch configuration: the solve must reach the OLS of the
+    stored data (oracle TSQR) to 1e-6, and 32 sampled sketch rows must equal
+    the oracle's H_un D P X rows computed one by one."""
+    _log("full size cfg1: generate")
+    p = workloads.make_config(1, device=DEV)
+    N, d = p.N, p.d
+    _log("full size cfg1: solve")
+    beta, st = S.spcg_solve(ctx, p.X, p.Y, seed=1)
+    assert st["converged"] and st["K"] == 9
+    _log("full size cfg1: oracle TSQR")
+    Xh = p.X.cpu().numpy()
+    Yh = p.Y.cpu().numpy()[:, 0]
+    bh = ols_tsqr(Xh, Yh, block=1 << 16)
+    Xb = beta.cpu().numpy()
+    num = np.linalg.norm(Xh.astype(np.float64) @ (Xb - bh))
+    den = np.linalg.norm(Xh.astype(np.float64) @ bh)
+    assert num / den <= 1e-6
+    _log("full size cfg1: sampled sketch rows")
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=1)
+    A_last, _, _ = sk.view_tensor(len(sk.sizes) - 1)
+    L, Np = padded_bits(N)
+    rng = np.random.default_rng(1)
+    t = rng.choice(sk.sizes[-1], 32, replace=False)
+    rows = slot_rows(1, L, sk.sizes[-1])[t]
+    perm = input_perm(1, L)
+    sg = sign_vector(1, L)
+    valid = perm < N
+    k = np.arange(Np)
+    # Z[i] = sum_k (-1)^{popcount(i & k)} sign(k) X[p(k)]
+    W_idx = k[valid]
+    Xp = Xh[perm[valid]].astype(np.float64) * sg[valid, None]
+    for i, row in enumerate(rows):
+        par = np.zeros(W_idx.size, dtype=np.int64)
+        v = W_idx & row
+        while np.any(v):
+            par ^= v & 1
+            v >>= 1
+        z = (1.0 - 2.0 * par) @ Xp
+        got = A_last[t[i]].cpu().numpy().astype(np.float64)
+        scale = math.sqrt(Np) * np.abs(Xh).max(axis=0)
+        assert np.max(np.abs(got - z) / scale) < 2e-6 * L
