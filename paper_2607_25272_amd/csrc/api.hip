@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -67,7 +68,8 @@ struct spcg_ctx {
     int64_t dvec_dpad = 0;
     // sketch and preconditioner workspaces used by spcg_solve
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
-    DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status;
+    DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w;
+    int64_t dense_w_elems = 0;
     // events for timing
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
@@ -181,7 +183,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     sk->r = r;
     sk->seed = o ? o->seed : 0;
     sk->dtype = X->dtype == SPCG_F64 ? DT_F64 : DT_F32;
-    sk->ld = round_up(d, 16);
+    sk->ld = sketch_ld(d, sk->dtype == DT_F64);
     sk->K = 0;
     if (!hat_only) {
         if (m0 <= d) return fail(ctx, SPCG_E_SHAPE, "need m_1 > d (m_1=%lld)", (long long)m0);
@@ -195,7 +197,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     }
     const int64_t mK = sk->K ? sk->m[sk->K - 1] : 0;
     const size_t es = sk->dtype == DT_F64 ? 8 : 4;
-    sk->ldy = sk->k == 1 ? 1 : round_up(sk->k, 8);
+    sk->ldy = sk->k == 1 ? 1 : round_up(sk->k, fwht_chunk_cols(DT_F64, 0));
     sk->owns = !borrow;
     DevBuf& bB = borrow ? ctx->wsB : sk->B;
     DevBuf& bBY = borrow ? ctx->wsBY : sk->BY;
@@ -269,15 +271,29 @@ int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, D
     return SPCG_OK;
 }
 
+// split-K workspace of the dense kernels: 8 partial d x d (or r x 64) products
+int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
+    const int64_t elems = 8 * std::max<int64_t>(d * d, r * 64);
+    if (ctx->dense_w_elems < elems) {
+        HIP_TRY(ctx, ctx->dense_w.ensure((size_t)elems * 8));
+        ctx->dense_w_elems = elems;
+    }
+    return SPCG_OK;
+}
+
 // R -> (R, M = R^{-1} R^{-T})
 int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
     const int64_t d = pc->d;
     hipStream_t st = ctx->stream;
+    int rc;
+    if ((rc = ensure_dense_work(ctx, d, d)) != SPCG_OK) return rc;
+    double* wk = ctx->dense_w.as<double>();
+    const int64_t we = ctx->dense_w_elems;
     HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
     double* W = ctx->dense_a.as<double>();
     HIP_TRY(ctx, dense_fill_identity(st, W, d));
-    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d));
-    HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0));
+    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d, wk, we));
+    HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0, wk, we));
     return SPCG_OK;
 }
 
@@ -307,9 +323,12 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
     DenseStatus hs{};
     double* R = pc->pR;
     const double inv_r = 1.0 / (double)r;
+    if ((rc = ensure_dense_work(ctx, d, r)) != SPCG_OK) return rc;
+    double* wk = ctx->dense_w.as<double>();
+    const int64_t we = ctx->dense_w_elems;
     // Gram of S_hat X = B_hat / sqrt(r): upper 64x64 tiles only
     auto gram_hat = [&](double* C) {
-        return gemm_f64(st, d, d, r, inv_r, sk->pBh, bf32, 1, ld, sk->pBh, bf32, ld, 1, 0.0, C, d, 1);
+        return gemm_f64(st, d, d, r, inv_r, sk->pBh, bf32, 1, ld, sk->pBh, bf32, ld, 1, 0.0, C, d, 1, wk, we);
     };
     if (mode == 0 || mode == 1) {
         HIP_TRY(ctx, gram_hat(R));
@@ -341,23 +360,23 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
     if ((rc = chol_checked(ctx, R1, d, dst, &hs)) != SPCG_OK) return rc;
     if (hs.fail) return fail(ctx, SPCG_E_RANK, "Cholesky of the (shifted) sketched Gram failed");
     HIP_TRY(ctx, dense_convert(st, sk->pBh, bf32, r, d, ld, std::sqrt(inv_r), Q, d));
-    HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R1, d));
+    HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R1, d, wk, we));
     // second pass
-    HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R2, d, 1));
+    HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R2, d, 1, wk, we));
     if ((rc = chol_checked(ctx, R2, d, dst, &hs)) != SPCG_OK) return rc;
     if (hs.fail || hs.min_pivot < 1e-12)
         return fail(ctx, SPCG_E_RANK, "S_hat X is numerically rank deficient (pivot %.3g)", hs.min_pivot);
     if (passes == 3) {
-        HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R2, d));
-        HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R, d, 1));
+        HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R2, d, wk, we));
+        HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R, d, 1, wk, we));
         if ((rc = chol_checked(ctx, R, d, dst, &hs)) != SPCG_OK) return rc;
         if (hs.fail || hs.min_pivot < 1e-12)
             return fail(ctx, SPCG_E_RANK, "S_hat X is numerically rank deficient (pivot %.3g)", hs.min_pivot);
         // R <- R3 R2 R1
-        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R, 0, d, 1, R2, 0, d, 1, 0.0, T, d, 0));
-        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, T, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0));
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R, 0, d, 1, R2, 0, d, 1, 0.0, T, d, 0, wk, we));
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, T, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0, wk, we));
     } else {
-        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R2, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0));
+        HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, R2, 0, d, 1, R1, 0, d, 1, 0.0, R, d, 0, wk, we));
     }
     pc->passes = passes;
     return precond_finish(ctx, pc);
@@ -564,6 +583,7 @@ int spcg_ctx_create(int device, void* hip_stream, spcg_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
+
     *out = c;
     return SPCG_OK;
 }

@@ -32,6 +32,8 @@ struct GemmArgs {
     double* C;
     int64_t ldc;
     int upper;
+    int64_t kchunk;     // K range per blockIdx.z
+    double* part;       // split-K: [gridDim.z][M][N] partial products (or null)
 };
 
 template <bool F32>
@@ -56,7 +58,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
     const bool a_icontig = g.sai == 1;
     const bool b_jcontig = g.sbj == 1;
-    for (int64_t l0 = 0; l0 < g.K; l0 += GK) {
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = min(g.K, kbeg + g.kchunk);
+    for (int64_t l0 = kbeg; l0 < kend; l0 += GK) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * 256;
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 i = e >> 4;
             }
             const int64_t gi = i0 + i, gl = l0 + l;
-            As[l][i] = (gi < g.M && gl < g.K) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
+            As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
             int j;
             if (b_jcontig) {
                 j = e & 63;
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 j = e >> 4;
             }
             const int64_t gj = j0 + j, gl2 = l0 + l;
-            Bs[l][j] = (gj < g.N && gl2 < g.K) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+            Bs[l][j] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -104,11 +108,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         for (int c = 0; c < 4; ++c) {
             const int64_t gj = j0 + tx * 4 + c;
             if (gj >= g.N) continue;
+            if (g.part) {
+                g.part[((int64_t)blockIdx.z * g.M + gi) * g.N + gj] = acc[r][c];
+                continue;
+            }
             double* cp = g.C + gi * g.ldc + gj;
             const double v = g.alpha * acc[r][c];
             *cp = g.beta == 0.0 ? v : fma(g.beta, *cp, v);
         }
     }
+}
+
+// C = alpha * sum_z part[z] + beta * C (fixed order over z)
+__global__ void splitk_reduce_kernel(const double* part, int nz, int64_t M, int64_t N, double alpha,
+                                     double beta, double* C, int64_t ldc, int upper) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * N) return;
+    const int64_t i = e / N, j = e - i * N;
+    if (upper && (i / GT) > (j / GT)) return;
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * M * N + e];
+    double* cp = C + i * ldc + j;
+    const double v = alpha * s;
+    *cp = beta == 0.0 ? v : fma(beta, *cp, v);
 }
 
 // Unblocked upper Cholesky of the nb x nb diagonal block at (k0, k0).
@@ -117,6 +139,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, 
     __shared__ double T[CB][CB + 1];
     __shared__ double piv_sh;
     const int tid = threadIdx.x;
+    double min_piv = 0.0, min_d = 0.0, max_d = 0.0;
+    int first_fail = 0;
+    if (tid == 0) {
+        min_piv = st->min_pivot;
+        min_d = st->min_diag;
+        max_d = st->max_diag;
+        first_fail = st->fail;
+    }
     for (int e = tid; e < nb * nb; e += 256) {
         const int i = e / nb, j = e - i * nb;
         T[i][j] = (j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
@@ -125,15 +155,15 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, 
     for (int j = 0; j < nb; ++j) {
         if (tid == 0) {
             double piv = T[j][j];
-            if (piv < st->min_pivot) st->min_pivot = piv;
+            min_piv = piv < min_piv ? piv : min_piv;
             if (!(piv > 0.0) || !__builtin_isfinite(piv)) {
-                if (st->fail == 0) st->fail = (int)(k0 + j) + 1;
+                if (first_fail == 0) first_fail = (int)(k0 + j) + 1;
                 piv = 1.0;
             }
             const double u = sqrt(piv);
             T[j][j] = u;
-            if (u < st->min_diag) st->min_diag = u;
-            if (u > st->max_diag) st->max_diag = u;
+            min_d = u < min_d ? u : min_d;
+            max_d = u > max_d ? u : max_d;
             piv_sh = u;
         }
         __syncthreads();
@@ -151,6 +181,12 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, 
         const int i = e / nb, j = e - i * nb;
         G[(k0 + i) * ld + k0 + j] = (j >= i) ? T[i][j] : 0.0;
     }
+    if (tid == 0) {
+        st->min_pivot = min_piv;
+        st->min_diag = min_d;
+        st->max_diag = max_d;
+        st->fail = first_fail;
+    }
 }
 
 // Row panel of the Cholesky: G[k0:k0+nb, c] <- U_kk^{-T} G[k0:k0+nb, c] for
@@ -166,14 +202,15 @@ __global__ __launch_bounds__(64) void chol_panel_kernel(double* G, int64_t ld, i
     }
     __syncthreads();
     const int64_t c = k0 + nb + (int64_t)blockIdx.x * 64 + tid;
-    if (c >= d) return;
+    const bool ok = c < d;
+    for (int i = 0; i < nb; ++i) Y[i][tid] = ok ? G[(k0 + i) * ld + c] : 0.0;
+    if (!ok) return;
     for (int i = 0; i < nb; ++i) {
-        double v = G[(k0 + i) * ld + c];
+        double v = Y[i][tid];
         for (int l = 0; l < i; ++l) v = fma(-U[l][i], Y[l][tid], v);
-        v /= U[i][i];
-        Y[i][tid] = v;
-        G[(k0 + i) * ld + c] = v;
+        Y[i][tid] = v / U[i][i];
     }
+    for (int i = 0; i < nb; ++i) G[(k0 + i) * ld + c] = Y[i][tid];
 }
 
 // A[i, k0:k0+nb] <- A[i, k0:k0+nb] U_kk^{-1} (one thread per row).
@@ -188,15 +225,23 @@ __global__ __launch_bounds__(64) void trsm_rows_kernel(double* A, int64_t n, int
         Us[i][j] = U[(k0 + i) * ldu + k0 + j];
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 64 + tid;
-    if (i >= n) return;
-    double* row = A + i * lda + k0;
-    for (int j = 0; j < nb; ++j) {
-        double v = row[j];
-        for (int l = 0; l < j; ++l) v = fma(-Q[l][tid], Us[l][j], v);
-        v /= Us[j][j];
-        Q[j][tid] = v;
-        row[j] = v;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    for (int e = tid; e < 64 * nb; e += 64) {
+        const int rr = e / nb, j = e - rr * nb;
+        Q[j][rr] = (i0 + rr < n) ? A[(i0 + rr) * lda + k0 + j] : 0.0;
+    }
+    __syncthreads();
+    if (i0 + tid < n) {
+        for (int j = 0; j < nb; ++j) {
+            double v = Q[j][tid];
+            for (int l = 0; l < j; ++l) v = fma(-Q[l][tid], Us[l][j], v);
+            Q[j][tid] = v / Us[j][j];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * nb; e += 64) {
+        const int rr = e / nb, j = e - rr * nb;
+        if (i0 + rr < n) A[(i0 + rr) * lda + k0 + j] = Q[j][rr];
     }
 }
 
@@ -249,10 +294,20 @@ __global__ void status_reset_kernel(DenseStatus* st) {
 
 hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
-                    int64_t sbj, double beta, double* C, int64_t ldc, int upper) {
+                    int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
+                    int64_t work_elems) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    GemmArgs g{M, N, K, alpha, beta, A, sai, sal, B, sbl, sbj, C, ldc, upper};
-    dim3 grid((unsigned)ceil_div(N, GT), (unsigned)ceil_div(M, GT)), block(256);
+    const int64_t ti = ceil_div(M, GT), tj = ceil_div(N, GT);
+    const int64_t tiles = upper ? (ti * (ti + 1)) / 2 : ti * tj;
+    // split K until there are about 512 blocks, keeping >= 128 per chunk
+    int64_t nz = 1;
+    while (work && tiles * nz * 2 <= 512 && K / (nz * 2) >= 128 && (nz * 2) * M * N <= work_elems) nz *= 2;
+    const int64_t kchunk = round_up(ceil_div(K, nz), GK);
+    nz = ceil_div(K, kchunk);
+    if (nz < 1) nz = 1;
+    GemmArgs g{M, N, K, alpha, beta, A, sai, sal, B, sbl, sbj, C, ldc, upper,
+               kchunk, nz > 1 ? work : nullptr};
+    dim3 grid((unsigned)tj, (unsigned)ti, (unsigned)nz), block(256);
     if (a_f32 && b_f32)
         gemm_kernel<true, true><<<grid, block, 0, st>>>(g);
     else if (a_f32)
@@ -261,6 +316,10 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
         gemm_kernel<false, true><<<grid, block, 0, st>>>(g);
     else
         gemm_kernel<false, false><<<grid, block, 0, st>>>(g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nz == 1) return e;
+    splitk_reduce_kernel<<<(unsigned)ceil_div(M * N, 256), 256, 0, st>>>(work, (int)nz, M, N, alpha,
+                                                                         beta, C, ldc, upper);
     return hipGetLastError();
 }
 
@@ -276,7 +335,7 @@ hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, Dens
             if ((e = hipGetLastError()) != hipSuccess) return e;
             double* P = G + k0 * ld + k0 + nb;
             e = gemm_f64(st, rem, rem, nb, -1.0, P, 0, 1, ld, P, 0, ld, 1, 1.0,
-                         G + (k0 + nb) * ld + k0 + nb, ld, 1);
+                         G + (k0 + nb) * ld + k0 + nb, ld, 1, nullptr, 0);
             if (e != hipSuccess) return e;
         }
     }
@@ -285,12 +344,13 @@ hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, Dens
 }
 
 hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int64_t lda,
-                            const double* U, int64_t ldu) {
+                            const double* U, int64_t ldu, double* work, int64_t work_elems) {
     hipError_t e;
     for (int64_t k0 = 0; k0 < d; k0 += CB) {
         const int nb = (int)std::min<int64_t>(CB, d - k0);
         if (k0 > 0) {
-            e = gemm_f64(st, n, nb, k0, -1.0, A, 0, lda, 1, U + k0, 0, ldu, 1, 1.0, A + k0, lda, 0);
+            e = gemm_f64(st, n, nb, k0, -1.0, A, 0, lda, 1, U + k0, 0, ldu, 1, 1.0, A + k0, lda, 0,
+                         work, work_elems);
             if (e != hipSuccess) return e;
         }
         trsm_rows_kernel<<<(unsigned)ceil_div(n, 64), 64, 0, st>>>(A, n, lda, U, ldu, k0, nb);

@@ -22,7 +22,7 @@ namespace spcg {
 
 namespace {
 
-constexpr int A_COLS = 64;   // columns per phase-A block
+constexpr int A_COLS = 16;   // columns per phase-A block
 constexpr int B_ROWS = 4;    // rows of M per phase-B block (one per wave)
 
 struct PhaseAArgs {
@@ -39,30 +39,47 @@ struct PhaseAArgs {
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
-    __shared__ double sh_s[4][A_COLS];
-    __shared__ double sh_g[4][A_COLS];
+    // 16 columns x 16 partial lanes per block; each lane keeps 4 independent
+    // sums so that 4 loads are in flight, combined in a fixed order
+    __shared__ double sh_s[16][A_COLS + 1];
+    __shared__ double sh_g[16][A_COLS + 1];
     __shared__ double sh_r[256];
     __shared__ double sh_t[256];
     __shared__ int is_last;
     const DspaceState& S = a.S;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tx = threadIdx.x & (A_COLS - 1), ty = threadIdx.x / A_COLS;
     const int64_t col = (int64_t)blockIdx.x * A_COLS + tx;
     const bool want_s = a.variant != PA_START;
     const bool want_g = a.variant != PA_STEP;
-    double ss = 0.0, gg = 0.0;
+    double ss[4] = {0.0, 0.0, 0.0, 0.0}, gg[4] = {0.0, 0.0, 0.0, 0.0};
     if (col < S.d) {
-        for (int b = ty; b < a.nparts; b += 4) {
-            if (want_s) ss += a.part_s[(int64_t)b * a.dpad + col];
-            if (want_g) gg += a.part_g[(int64_t)b * a.dpad + col];
+        int b = ty;
+        for (; b + 48 < a.nparts; b += 64) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t off = (int64_t)(b + 16 * u) * a.dpad + col;
+                if (want_s) ss[u] += a.part_s[off];
+                if (want_g) gg[u] += a.part_g[off];
+            }
+        }
+        for (int u = 0; b < a.nparts; b += 16, ++u) {
+            const int64_t off = (int64_t)b * a.dpad + col;
+            if (want_s) ss[u] += a.part_s[off];
+            if (want_g) gg[u] += a.part_g[off];
         }
     }
-    sh_s[ty][tx] = ss;
-    sh_g[ty][tx] = gg;
+    sh_s[ty][tx] = (ss[0] + ss[1]) + (ss[2] + ss[3]);
+    sh_g[ty][tx] = (gg[0] + gg[1]) + (gg[2] + gg[3]);
     __syncthreads();
     double dot = 0.0;
     if (ty == 0 && col < S.d) {
-        const double s_col = (((sh_s[0][tx] + sh_s[1][tx]) + sh_s[2][tx]) + sh_s[3][tx]) * a.c2;
-        const double g_col = (((sh_g[0][tx] + sh_g[1][tx]) + sh_g[2][tx]) + sh_g[3][tx]) * a.c2;
+        double s_col = 0.0, g_col = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            s_col += sh_s[q][tx];
+            g_col += sh_g[q][tx];
+        }
+        s_col *= a.c2;
+        g_col *= a.c2;
         if (a.variant == PA_START) {
             S.g[col] = g_col;
         } else {
@@ -72,7 +89,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
         }
     }
     if (ty == 0) {
-        dot = group_sum<64>(dot);
+        dot = group_sum<A_COLS>(dot);
         if (tx == 0) S.blk[blockIdx.x] = dot;
     }
     __threadfence();
@@ -158,8 +175,15 @@ __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
     double gz = 0.0;
     if (!skip && i < S.d) {
         const double* row = S.Minv + i * S.d;
-        double acc = 0.0;
-        for (int64_t j = lane; j < S.d; j += 64) acc = fma(row[j], S.g[j], acc);
+        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t j0 = lane; j0 < S.d; j0 += 256) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t j = j0 + 64 * u;
+                if (j < S.d) acc4[u] = fma(row[j], S.g[j], acc4[u]);
+            }
+        }
+        double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         acc = group_sum<64>(acc);
         if (lane == 0) {
             S.z[i] = acc;

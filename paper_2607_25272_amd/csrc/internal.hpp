@@ -37,11 +37,13 @@ struct FwhtJob {
     int64_t ldbh;
     int narrow;               // 1: single-column FP64 transform (the response vector)
 };
-// Column-chunk width of the transform: every row width used by a job
-// (ldz, ldb, ldbh) must be equal and a multiple of it.
+// Widest column chunk of the transform (256-byte row segments): every row
+// width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.
 inline int fwht_chunk_cols(int in_dtype, int narrow) {
-    return narrow ? 1 : (in_dtype == DT_F64 ? 8 : 16);
+    return narrow ? 1 : (in_dtype == DT_F64 ? 32 : 64);
 }
+// Row padding of the stored sketch rows (multiple of every chunk width).
+inline int64_t sketch_ld(int64_t d, bool f64) { return round_up(d, f64 ? 32 : 64); }
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
 
 // --------------------------------------------------------------- product
@@ -116,14 +118,17 @@ struct DenseStatus {
 };
 // C = alpha op(A) op(B) + beta C; A(i,l) = A[i*sai + l*sal], B(l,j) = B[l*sbl + j*sbj]
 // upper = 1: only 64x64 tiles on or above the block diagonal are computed.
+// work (work_elems doubles, may be null) enables split-K for short-and-wide
+// products; the chunks are summed in a fixed order.
 hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
-                    int64_t sbj, double beta, double* C, int64_t ldc, int upper);
+                    int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
+                    int64_t work_elems);
 // In-place upper Cholesky G = U^T U (row-major d x d, ld); lower part zeroed.
 hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status);
 // In-place A <- A U^{-1} for A (n x d, lda) and upper-triangular U (d x d, ldu).
 hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int64_t lda,
-                            const double* U, int64_t ldu);
+                            const double* U, int64_t ldu, double* work, int64_t work_elems);
 hipError_t dense_fill_identity(hipStream_t st, double* A, int64_t d);
 hipError_t dense_convert(hipStream_t st, const void* src, int src_f32, int64_t rows, int64_t cols,
                          int64_t lds, double scale, double* dst, int64_t ldd);

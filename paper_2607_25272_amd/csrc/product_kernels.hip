@@ -31,20 +31,23 @@ namespace spcg {
 
 namespace {
 
-constexpr int NW = 4;        // waves per block
+constexpr int NW = 8;        // waves per block (one block per CU, 2 waves per SIMD)
 constexpr int DMAX_LDS = 4096;
 
 typedef float v2f __attribute__((ext_vector_type(2)));
 
 template <int BYTES>
 struct RawVec;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 template <>
 struct RawVec<16> {
-    typedef uint4 T;
+    typedef u32x4 T;
 };
 template <>
 struct RawVec<8> {
-    typedef uint2 T;
+    typedef u32x2 T;
 };
 template <>
 struct RawVec<4> {
@@ -86,10 +89,8 @@ struct Store<fp8_t> {
     static constexpr int VMAX = 16;
 };
 
-__device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
-    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
-}
-__device__ __forceinline__ uint32_t word_of(const uint2& v, int i) { return i == 0 ? v.x : v.y; }
+__device__ __forceinline__ uint32_t word_of(const u32x4& v, int i) { return v[i]; }
+__device__ __forceinline__ uint32_t word_of(const u32x2& v, int i) { return v[i]; }
 __device__ __forceinline__ uint32_t word_of(const uint32_t& v, int) { return v; }
 __device__ __forceinline__ uint32_t word_of(const uint16_t& v, int) { return v; }
 __device__ __forceinline__ uint32_t word_of(const uint8_t& v, int) { return v; }
@@ -209,29 +210,36 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
     const char* Abase = static_cast<const char*>(a.A);
     const int64_t row_bytes = a.lda * Store<TS>::BYTES;
 
-    for (int64_t base = r0 + (int64_t)wave * (U * RPW); base < r1; base += NW * U * RPW) {
-        Raw raw[U][NSLOT];
+    // Rolling prefetch: slot u of `raw` holds row (base + u * RPW) of the
+    // current sweep; right after a row is consumed its slot is refilled with
+    // the same row of the next sweep, so U rows stay in flight per wave while
+    // only one row is widened at a time.
+    const int64_t sweep = (int64_t)NW * U * RPW;
+    auto load_row = [&](int64_t row, Raw* dst) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t row = base + u * RPW + rs;
-#pragma unroll
-            for (int s = 0; s < NSLOT; ++s) {
-                const int vi = lir + s * LPR;
-                if (row < r1 && vi < a.nvec) {
-                    raw[u][s] = *reinterpret_cast<const Raw*>(Abase + row * row_bytes +
-                                                              (int64_t)vi * (VEC * Store<TS>::BYTES));
-                } else {
-                    raw[u][s] = Raw{};
-                }
+        for (int s = 0; s < NSLOT; ++s) {
+            const int vi = lir + s * LPR;
+            if (row < r1 && vi < a.nvec) {
+                dst[s] = __builtin_nontemporal_load(reinterpret_cast<const Raw*>(
+                    Abase + row * row_bytes + (int64_t)vi * (VEC * Store<TS>::BYTES)));
+            } else {
+                dst[s] = Raw{};
             }
         }
+    };
+    Raw raw[U][NSLOT];
+    const int64_t first = r0 + (int64_t)wave * (U * RPW) + rs;
+#pragma unroll
+    for (int u = 0; u < U; ++u) load_row(first + u * RPW, raw[u]);
+    for (int64_t base = first; base - rs < r1; base += sweep) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t row = base + u * RPW + rs;
+            const int64_t row = base + u * RPW;
             const bool valid = row < r1;
             CT v[NC];
 #pragma unroll
             for (int s = 0; s < NSLOT; ++s) Widen<TS, VEC, Raw>::run(raw[u][s], v + s * VEC);
+            load_row(row + sweep, raw[u]);
             CT dp = CT(0);
             double dx = 0.0;
 #pragma unroll
@@ -311,14 +319,27 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
     }
 }
 
+// rows in flight per wave: enough to keep ~64 KB of loads outstanding per
+// CU with 16 resident waves, without spilling (the SG mode holds both
+// products' operands and accumulators)
+template <int NC, int MODE>
+constexpr int unroll_rows() {
+    return MODE == PM_S ? (NC <= 16 ? 4 : 2) : (NC <= 8 ? 4 : 2);
+}
+
 template <typename TS, int VEC, int LPR, int NSLOT>
 hipError_t launch_shape(hipStream_t st, const ProdArgs& a, int mode, int nblocks) {
-    constexpr int U = NSLOT <= 2 ? 4 : (NSLOT <= 4 ? 2 : 1);
     dim3 grid(nblocks), block(64 * NW);
     switch (mode) {
-        case PM_S: product_kernel<TS, VEC, LPR, NSLOT, PM_S, U><<<grid, block, 0, st>>>(a); break;
-        case PM_G: product_kernel<TS, VEC, LPR, NSLOT, PM_G, U><<<grid, block, 0, st>>>(a); break;
-        default: product_kernel<TS, VEC, LPR, NSLOT, PM_SG, U><<<grid, block, 0, st>>>(a); break;
+        case PM_S:
+            product_kernel<TS, VEC, LPR, NSLOT, PM_S, unroll_rows<NSLOT * VEC, PM_S>()><<<grid, block, 0, st>>>(a);
+            break;
+        case PM_G:
+            product_kernel<TS, VEC, LPR, NSLOT, PM_G, unroll_rows<NSLOT * VEC, PM_G>()><<<grid, block, 0, st>>>(a);
+            break;
+        default:
+            product_kernel<TS, VEC, LPR, NSLOT, PM_SG, unroll_rows<NSLOT * VEC, PM_SG>()><<<grid, block, 0, st>>>(a);
+            break;
     }
     return hipGetLastError();
 }
@@ -351,7 +372,7 @@ hipError_t launch_type(hipStream_t st, const ProdArgs& a, int mode, int nblocks,
 
 }  // namespace
 
-int64_t product_max_blocks(int num_cu) { return (int64_t)(num_cu > 0 ? num_cu : 256) * 4; }
+int64_t product_max_blocks(int num_cu) { return (int64_t)(num_cu > 0 ? num_cu : 256); }
 
 int64_t product_max_d(int dtype) { return dtype == DT_F64 ? 2048 : 4096; }
 
@@ -373,9 +394,8 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
     int nslot = 1;
     while (nslot < ns) nslot <<= 1;
     if (nslot > 16 || (int64_t)nslot * vec * lpr > DMAX_LDS) return hipErrorInvalidValue;
-    const int U = nslot <= 2 ? 4 : (nslot <= 4 ? 2 : 1);
-    const int64_t rows_per_sweep = (int64_t)NW * U * (64 / lpr);
-    int64_t nb = ceil_div(j.m, rows_per_sweep * 4);
+    const int64_t rows_per_sweep = (int64_t)NW * 4 * (64 / lpr);
+    int64_t nb = ceil_div(j.m, rows_per_sweep * 2);
     nb = std::max<int64_t>(1, std::min<int64_t>(nb, product_max_blocks(j.num_cu)));
     int64_t rpb = ceil_div(j.m, nb);
     nb = ceil_div(j.m, rpb);

@@ -17,8 +17,7 @@ namespace spcg {
 
 namespace {
 
-constexpr int NB_MAX = 11;       // bits per pass: 2^11 rows x 64 B = 128 KB of LDS
-constexpr int FWHT_THREADS = 1024;
+constexpr int NB_MAX = 11;       // bits per transform pass
 
 __global__ void tables_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int64_t r,
                               int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat) {
@@ -52,33 +51,90 @@ __global__ void export_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int6
     }
 }
 
-template <typename TIN>
-struct InLoad;
+// Widening loads of the stored input: VL consecutive elements of one row.
+template <typename TIN, typename TZ, int VL>
+struct InVec;
+template <int VL>
+struct InVec<double, double, VL> {
+    __device__ static void scalar(const void* x, int64_t idx, const float*, int64_t, double* o) {
+        o[0] = static_cast<const double*>(x)[idx];
+    }
+    __device__ static void vec(const void* x, int64_t idx, const float*, int64_t, double* o) {
+        const double2 v = *reinterpret_cast<const double2*>(static_cast<const double*>(x) + idx);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <int VL>
+struct InVec<float, float, VL> {
+    __device__ static void scalar(const void* x, int64_t idx, const float*, int64_t, float* o) {
+        o[0] = static_cast<const float*>(x)[idx];
+    }
+    __device__ static void vec(const void* x, int64_t idx, const float*, int64_t, float* o) {
+        const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(x) + idx);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+template <int VL>
+struct InVec<bf16_t, float, VL> {
+    __device__ static void scalar(const void* x, int64_t idx, const float*, int64_t, float* o) {
+        o[0] = bf16_bits_to_f32(static_cast<const uint16_t*>(x)[idx]);
+    }
+    __device__ static void vec(const void* x, int64_t idx, const float*, int64_t, float* o) {
+        const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(x) + idx);
+        o[0] = __uint_as_float(v.x << 16);
+        o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16);
+        o[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+typedef float fwht_v2f __attribute__((ext_vector_type(2)));
+template <int VL>
+struct InVec<fp8_t, float, VL> {
+    __device__ static void scalar(const void* x, int64_t idx, const float* sc, int64_t col, float* o) {
+        const uint32_t v = static_cast<const uint8_t*>(x)[idx];
+        o[0] = __builtin_amdgcn_cvt_f32_fp8((int)v, 0) * sc[col];
+    }
+    __device__ static void vec(const void* x, int64_t idx, const float* sc, int64_t col, float* o) {
+        const int w = (int)*reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(x) + idx);
+        const fwht_v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+        const fwht_v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+        o[0] = lo.x * sc[col];
+        o[1] = lo.y * sc[col + 1];
+        o[2] = hi.x * sc[col + 2];
+        o[3] = hi.y * sc[col + 3];
+    }
+};
+
+template <typename TZ>
+struct ZVec;
 template <>
-struct InLoad<double> {
-    __device__ static double get(const void* x, int64_t idx, const float*, int64_t) {
-        return static_cast<const double*>(x)[idx];
+struct ZVec<float> {
+    static constexpr int VL = 4;
+    __device__ static void ld(const float* p, float* o) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+    __device__ static void st(float* p, const float* o) {
+        *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
     }
 };
 template <>
-struct InLoad<float> {
-    __device__ static float get(const void* x, int64_t idx, const float*, int64_t) {
-        return static_cast<const float*>(x)[idx];
+struct ZVec<double> {
+    static constexpr int VL = 2;
+    __device__ static void ld(const double* p, double* o) {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
     }
-};
-template <>
-struct InLoad<bf16_t> {
-    __device__ static float get(const void* x, int64_t idx, const float*, int64_t) {
-        return bf16_bits_to_f32(static_cast<const uint16_t*>(x)[idx]);
-    }
-};
-template <>
-struct InLoad<fp8_t> {
-    __device__ static float get(const void* x, int64_t idx, const float* scale, int64_t col) {
-        uint32_t v = static_cast<const uint8_t*>(x)[idx];
-        // hardware OCP e4m3 -> f32 conversion of the low byte
-        float f = __builtin_amdgcn_cvt_f32_fp8((int)v, 0);
-        return f * scale[col];
+    __device__ static void st(double* p, const double* o) {
+        *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
     }
 };
 
@@ -87,6 +143,7 @@ struct PassArgs {
     int64_t ldx;
     const float* col_scale;
     int64_t N, d;
+    int xvec;          // X rows allow aligned VL-element loads
     const void* zin;
     void* zout;
     int64_t ldz;
@@ -97,17 +154,32 @@ struct PassArgs {
     int64_t ldb;
     void* Bh;
     int64_t ldbh;
-    int lo, nb;
+    int lo, nb, q;
     int64_t nchunks, ntiles;
 };
 
 // One block = one tile of 2^nb rows x CW columns.
-template <typename TIN, typename TZ, int CW, bool FIRST, bool LAST>
-__global__ __launch_bounds__(FWHT_THREADS) void fwht_pass_kernel(PassArgs a) {
-    __shared__ TZ tile[(1 << NB_MAX) * CW];
+//
+// Lane layout: LPR = CW / VL lanes cover one tile row with VL-element
+// (16-byte) vectors; each thread holds R = 2^q tile rows of its VL columns
+// in registers: the rows that differ only in a q-bit window of the row
+// index.  The bits of the pass are processed in groups of at most q bits,
+// low group first; inside a group the butterflies run in registers in
+// ascending bit order, and between groups the tile goes once through LDS
+// (one vector element at a time) to re-slice it along the next group's
+// bits.  For the last, narrower group the window is widened downwards with
+// already-finished bits so that every thread always holds R rows.
+template <typename TIN, typename TZ, int CW, bool FIRST, bool LAST, int QMAX>
+__global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassArgs a) {
+    constexpr int VL = CW == 1 ? 1 : ZVec<TZ>::VL;
+    constexpr int LPR = CW / VL;
+    constexpr int LPRP = LPR == 1 ? 1 : LPR + 1;   // padded LDS row (bank spreading)
+    constexpr int RMAX = 1 << QMAX;
+    extern __shared__ __align__(16) unsigned char fwht_lds[];
+    TZ* lds = reinterpret_cast<TZ*>(fwht_lds);
     // Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
     // contiguous range of tiles so that the column chunks of one row group
-    // (which share cache lines) meet in the same L2.
+    // (which share DRAM pages) are fetched by the same L2 close in time.
     int64_t bid = blockIdx.x, nblk = gridDim.x, tid;
     if ((nblk & 7) == 0) {
         tid = (bid & 7) * (nblk >> 3) + (bid >> 3);
@@ -116,73 +188,185 @@ __global__ __launch_bounds__(FWHT_THREADS) void fwht_pass_kernel(PassArgs a) {
     }
     const int64_t o = tid / a.nchunks;
     const int64_t cc = tid - o * a.nchunks;
-    const int nb = a.nb, lo = a.lo;
-    const int64_t rows = 1ll << nb;
+    const int nb = a.nb, lo = a.lo, q = a.q;
+    const int R = 1 << q;
     const int64_t olo = o & ((1ll << lo) - 1);
     const int64_t ohi = o >> lo;
-    const int64_t col0 = cc * CW;
-    const int64_t nelem = rows * CW;
+    const int lr = threadIdx.x % LPR;
+    const int bidx = threadIdx.x / LPR;
+    const int64_t col0 = cc * CW + lr * VL;
 
-    // load
-    for (int64_t e = threadIdx.x; e < nelem; e += FWHT_THREADS) {
-        int64_t j = e / CW;
-        int c = (int)(e - j * CW);
-        int64_t k = (ohi << (lo + nb)) | (j << lo) | olo;
-        int64_t col = col0 + c;
-        TZ v = TZ(0);
-        if (FIRST) {
-            int32_t ps = a.perm_sign[k];
-            int64_t src = (int64_t)(ps & 0x7fffffff);
-            if (src < a.N && col < a.d) {
-                v = (TZ)InLoad<TIN>::get(a.x, src * a.ldx + col, a.col_scale, col);
-                if (ps < 0) v = -v;
+    auto tile_row = [&](int s0, int t) -> int {
+        const int base = ((bidx >> s0) << (s0 + q)) | (bidx & ((1 << s0) - 1));
+        return base | (t << s0);
+    };
+    auto global_row = [&](int j) -> int64_t { return (ohi << (lo + nb)) | ((int64_t)j << lo) | olo; };
+
+    TZ v[RMAX][VL];
+    // ---- load (window = bits [0, q))
+    if (FIRST) {
+        int32_t ps[RMAX];
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t)
+            if (t < R) ps[t] = a.perm_sign[global_row(tile_row(0, t))];
+        const bool full = a.xvec && col0 + VL <= a.d;
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+            if (t < R) {
+                const int64_t src = (int64_t)(ps[t] & 0x7fffffff);
+#pragma unroll
+                for (int e = 0; e < VL; ++e) v[t][e] = TZ(0);
+                if (src < a.N) {
+                    if (full) {
+                        InVec<TIN, TZ, VL>::vec(a.x, src * a.ldx + col0, a.col_scale, col0, v[t]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VL; ++e)
+                            if (col0 + e < a.d)
+                                InVec<TIN, TZ, VL>::scalar(a.x, src * a.ldx + col0 + e, a.col_scale,
+                                                           col0 + e, &v[t][e]);
+                    }
+                    if (ps[t] < 0) {
+#pragma unroll
+                        for (int e = 0; e < VL; ++e) v[t][e] = -v[t][e];
+                    }
+                }
             }
-        } else {
-            v = static_cast<const TZ*>(a.zin)[k * a.ldz + col];
         }
-        tile[e] = v;
-    }
-    __syncthreads();
-    // stages lo .. lo+nb-1 (local bit t)
-    const int64_t npairs = (rows >> 1) * CW;
-    for (int t = 0; t < nb; ++t) {
-        const int64_t h = 1ll << t;
-        for (int64_t e = threadIdx.x; e < npairs; e += FWHT_THREADS) {
-            int64_t q = e / CW;
-            int c = (int)(e - q * CW);
-            int64_t j = ((q >> t) << (t + 1)) | (q & (h - 1));
-            TZ u = tile[j * CW + c];
-            TZ w = tile[(j + h) * CW + c];
-            tile[j * CW + c] = u + w;
-            tile[(j + h) * CW + c] = u - w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < RMAX; ++t) {
+            if (t < R) {
+                const TZ* p = static_cast<const TZ*>(a.zin) + global_row(tile_row(0, t)) * a.ldz + col0;
+                if constexpr (VL == 1) {
+                    v[t][0] = *p;
+                } else {
+                    ZVec<TZ>::ld(p, v[t]);
+                }
+            }
         }
-        __syncthreads();
     }
-    // store
-    for (int64_t e = threadIdx.x; e < nelem; e += FWHT_THREADS) {
-        int64_t j = e / CW;
-        int c = (int)(e - j * CW);
-        int64_t k = (ohi << (lo + nb)) | (j << lo) | olo;
-        int64_t col = col0 + c;
-        TZ v = tile[e];
-        if (LAST) {
-            if (a.inv_slot) {
-                int32_t t = a.inv_slot[k];
-                if (t >= 0 && col < a.ldb) static_cast<TZ*>(a.B)[(int64_t)t * a.ldb + col] = v;
+    int done = 0, s0 = 0;
+    while (true) {
+        const int w = min(q, nb - done);   // bits of this group
+        const int e0 = q - w;              // finished bits below it in the window
+        // butterflies on register-row bits [e0, e0 + w), ascending
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            if (b >= e0 && b < e0 + w && (1 << b) < R) {
+#pragma unroll
+                for (int t = 0; t < RMAX; ++t) {
+                    if (t < R && !(t & (1 << b))) {
+#pragma unroll
+                        for (int e = 0; e < VL; ++e) {
+                            const TZ x0 = v[t][e], x1 = v[t | (1 << b)][e];
+                            v[t][e] = x0 + x1;
+                            v[t | (1 << b)][e] = x0 - x1;
+                        }
+                    }
+                }
             }
-            if (a.inv_hat) {
-                int32_t t = a.inv_hat[k];
-                if (t >= 0 && col < a.ldbh) static_cast<TZ*>(a.Bh)[(int64_t)t * a.ldbh + col] = v;
+        }
+        done += w;
+        if (done >= nb) break;
+        // re-slice through LDS for the next group, one vector element at a time
+        const int wn = min(q, nb - done);
+        const int s1 = done - (q - wn);
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+#pragma unroll
+            for (int t = 0; t < RMAX; ++t)
+                if (t < R) lds[tile_row(s0, t) * LPRP + lr] = v[t][e];
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < RMAX; ++t)
+                if (t < R) v[t][e] = lds[tile_row(s1, t) * LPRP + lr];
+            __syncthreads();
+        }
+        s0 = s1;
+    }
+    // ---- store
+#pragma unroll
+    for (int t = 0; t < RMAX; ++t) {
+        if (t < R) {
+            const int64_t k = global_row(tile_row(s0, t));
+            if (LAST) {
+                if (a.inv_slot) {
+                    const int32_t sl = a.inv_slot[k];
+                    if (sl >= 0) {
+                        TZ* p = static_cast<TZ*>(a.B) + (int64_t)sl * a.ldb + col0;
+                        if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
+                    }
+                }
+                if (a.inv_hat) {
+                    const int32_t sl = a.inv_hat[k];
+                    if (sl >= 0) {
+                        TZ* p = static_cast<TZ*>(a.Bh) + (int64_t)sl * a.ldbh + col0;
+                        if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
+                    }
+                }
+            } else {
+                TZ* p = static_cast<TZ*>(a.zout) + k * a.ldz + col0;
+                if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
             }
-        } else {
-            static_cast<TZ*>(a.zout)[k * a.ldz + col] = v;
         }
     }
 }
 
+// Threads per block and register window for a pass of nb bits.
+template <typename TZ, int CW>
+inline int pass_q(int nb) {
+    constexpr int VL = CW == 1 ? 1 : ZVec<TZ>::VL;
+    int q = nb < 4 ? nb : 4;
+    while (((int64_t)(CW / VL) << (nb - q)) > 1024) ++q;
+    return q;
+}
+
+template <typename TIN, typename TZ, int CW, bool FIRST, bool LAST, int QMAX>
+hipError_t launch_pass_q(hipStream_t st, const PassArgs& a) {
+    constexpr int VL = CW == 1 ? 1 : ZVec<TZ>::VL;
+    constexpr int LPR = CW / VL;
+    constexpr int LPRP = LPR == 1 ? 1 : LPR + 1;
+    const size_t lds = (size_t)(1 << a.nb) * LPRP * sizeof(TZ);
+    auto fn = fwht_pass_kernel<TIN, TZ, CW, FIRST, LAST, QMAX>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int threads = (int)(((int64_t)LPR << a.nb) >> a.q);
+    if (threads > (QMAX == 5 ? 512 : 1024)) return hipErrorInvalidValue;
+    fn<<<dim3((unsigned)a.ntiles), dim3(threads), lds, st>>>(a);
+    return hipGetLastError();
+}
+
+// register window: exactly q = QMAX bits for passes of >= 4 bits, the whole
+// pass for the tiny ones
+template <typename TIN, typename TZ, int CW, bool FIRST, bool LAST>
+hipError_t launch_pass(hipStream_t st, const PassArgs& a) {
+    if (a.q == 5) return launch_pass_q<TIN, TZ, CW, FIRST, LAST, 5>(st, a);
+    if (a.q == 4) return launch_pass_q<TIN, TZ, CW, FIRST, LAST, 4>(st, a);
+    if (a.q <= 3 && a.q == a.nb) return launch_pass_q<TIN, TZ, CW, FIRST, LAST, 3>(st, a);
+    return hipErrorInvalidValue;
+}
+
 template <typename TIN, typename TZ, int CW>
+hipError_t launch_any(hipStream_t st, const PassArgs& a, bool first, bool last) {
+    if (first && last) return launch_pass<TIN, TZ, CW, true, true>(st, a);
+    if (first) return launch_pass<TIN, TZ, CW, true, false>(st, a);
+    if (last) return launch_pass<TIN, TZ, CW, false, true>(st, a);
+    return launch_pass<TIN, TZ, CW, false, false>(st, a);
+}
+
+// Passes of at most NB_MAX bits; each pass uses 256-byte row segments, or
+// 128-byte ones for 11-bit passes (whose 256-byte tile would not fit).
+template <typename TIN, typename TZ>
 hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     const int L = job.L;
+    constexpr int E = sizeof(TZ);
+    constexpr int CW_WIDE = 256 / E, CW_NARROW = 128 / E;
     const int passes = (L + NB_MAX - 1) / NB_MAX;
     PassArgs a{};
     a.x = job.x;
@@ -198,26 +382,56 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     a.ldb = job.ldb;
     a.Bh = job.Bh;
     a.ldbh = job.ldbh;
-    a.nchunks = job.ldz / CW;
+    constexpr int VL = ZVec<TZ>::VL;
+    a.xvec = (job.ldx % VL == 0) && ((uintptr_t)job.x % (VL * sizeof(TIN)) == 0);
     int lo = 0;
     for (int pi = 0; pi < passes; ++pi) {
-        int nb = L / passes + (pi < L % passes ? 1 : 0);
+        const int nb = L / passes + (pi < L % passes ? 1 : 0);
+        const bool wide = nb <= 10;
+        const int cw = wide ? CW_WIDE : CW_NARROW;
         a.lo = lo;
         a.nb = nb;
+        a.q = wide ? pass_q<TZ, CW_WIDE>(nb) : pass_q<TZ, CW_NARROW>(nb);
+        if (a.q > 5) return hipErrorInvalidValue;
+        a.nchunks = job.ldz / cw;
         a.ntiles = (1ll << (L - nb)) * a.nchunks;
         a.zin = job.zbuf;
         a.zout = job.zbuf;
-        bool first = pi == 0, last = pi == passes - 1;
-        dim3 grid((unsigned)a.ntiles), block(FWHT_THREADS);
-        if (first && last)
-            fwht_pass_kernel<TIN, TZ, CW, true, true><<<grid, block, 0, st>>>(a);
-        else if (first)
-            fwht_pass_kernel<TIN, TZ, CW, true, false><<<grid, block, 0, st>>>(a);
-        else if (last)
-            fwht_pass_kernel<TIN, TZ, CW, false, true><<<grid, block, 0, st>>>(a);
-        else
-            fwht_pass_kernel<TIN, TZ, CW, false, false><<<grid, block, 0, st>>>(a);
-        hipError_t e = hipGetLastError();
+        const bool first = pi == 0, last = pi == passes - 1;
+        const hipError_t e = wide ? launch_any<TIN, TZ, CW_WIDE>(st, a, first, last)
+                                  : launch_any<TIN, TZ, CW_NARROW>(st, a, first, last);
+        if (e != hipSuccess) return e;
+        lo += nb;
+    }
+    return hipSuccess;
+}
+
+// Single-column FP64 transform (the response vector): 16 rows per thread.
+hipError_t run_passes_narrow(hipStream_t st, const FwhtJob& job) {
+    const int L = job.L;
+    const int passes = (L + NB_MAX - 1) / NB_MAX;
+    PassArgs a{};
+    a.x = job.x;
+    a.ldx = job.ldx;
+    a.N = job.N;
+    a.d = job.d;
+    a.ldz = job.ldz;
+    a.perm_sign = job.perm_sign;
+    a.inv_slot = job.inv_slot;
+    a.B = job.B;
+    a.ldb = job.ldb;
+    a.xvec = 0;
+    a.nchunks = 1;
+    int lo = 0;
+    for (int pi = 0; pi < passes; ++pi) {
+        const int nb = L / passes + (pi < L % passes ? 1 : 0);
+        a.lo = lo;
+        a.nb = nb;
+        a.q = pass_q<double, 1>(nb);
+        a.ntiles = 1ll << (L - nb);
+        a.zin = job.zbuf;
+        a.zout = job.zbuf;
+        const hipError_t e = launch_any<double, double, 1>(st, a, pi == 0, pi == passes - 1);
         if (e != hipSuccess) return e;
         lo += nb;
     }
@@ -246,6 +460,17 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
     return hipGetLastError();
 }
 
+template <typename TIN, typename TZ>
+hipError_t run_chunked(hipStream_t st, const FwhtJob& job, int seg_bytes) {
+    constexpr int E = sizeof(TZ);
+    switch (seg_bytes) {
+        case 64: return run_passes<TIN, TZ, 64 / E>(st, job);
+        case 128: return run_passes<TIN, TZ, 128 / E>(st, job);
+        case 256: return run_passes<TIN, TZ, 256 / E>(st, job);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {
     const int cw = fwht_chunk_cols(job.in_dtype, job.narrow);
     if (job.ldz % cw != 0 || (job.B && job.ldb != job.ldz) || (job.Bh && job.ldbh != job.ldz) ||
@@ -253,13 +478,13 @@ hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {
         return hipErrorInvalidValue;
     if (job.narrow) {
         if (job.in_dtype != DT_F64 || job.d != 1) return hipErrorInvalidValue;
-        return run_passes<double, double, 1>(st, job);
+        return run_passes_narrow(st, job);
     }
     switch (job.in_dtype) {
-        case DT_F64: return run_passes<double, double, 8>(st, job);
-        case DT_F32: return run_passes<float, float, 16>(st, job);
-        case DT_BF16: return run_passes<bf16_t, float, 16>(st, job);
-        case DT_FP8: return run_passes<fp8_t, float, 16>(st, job);
+        case DT_F64: return run_passes<double, double>(st, job);
+        case DT_F32: return run_passes<float, float>(st, job);
+        case DT_BF16: return run_passes<bf16_t, float>(st, job);
+        case DT_FP8: return run_passes<fp8_t, float>(st, job);
         default: return hipErrorInvalidValue;
     }
 }

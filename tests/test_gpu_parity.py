@@ -108,6 +108,35 @@ def test_sketch_rows_f64_bit_exact(S, ctx, N, d):
     assert np.array_equal(A0.cpu().numpy(), B[: sk.sizes[0]])
 
 
+def test_sketch_rows_f64_eleven_bit_passes(S, ctx):
+    # N' = 2^22: two 11-bit passes with 128-byte row segments; still bit-exact
+    N, d = (1 << 21) + 5, 3
+    _log("sketch f64 N'=2^22")
+    p = _problem(N, d, seed=99)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=7, m0=1 << 16, m_max=1 << 17, r=64)
+    B, BY, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 7, sk.sizes[-1], 64)
+    Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    Hg, _, _ = sk.view_tensor(-1)
+    assert sk.info.L == 22
+    assert np.array_equal(Ag.cpu().numpy(), B)
+    assert np.array_equal(bg.cpu().numpy(), BY)
+    assert np.array_equal(Hg.cpu().numpy(), Bh)
+
+
+def test_sketch_tiny_and_multi_rhs(S, ctx):
+    # N' = 8 (one 3-bit pass) and a three-column response
+    X = torch.arange(10, dtype=torch.float64, device=DEV).reshape(5, 2) - 3.0
+    Y = torch.arange(15, dtype=torch.float64, device=DEV).reshape(5, 3) * 0.5
+    sk = S.spcg_sketch(ctx, X, Y, seed=2, m0=3, r=4)
+    B, BY, Bh, _ = nested_srht(X.cpu().numpy(), Y.cpu().numpy(), 2, sk.sizes[-1], 4)
+    Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    Hg, _, _ = sk.view_tensor(-1)
+    assert sk.info.L == 3
+    assert np.array_equal(Ag.cpu().numpy(), B)
+    assert np.array_equal(bg.cpu().numpy(), BY)
+    assert np.array_equal(Hg.cpu().numpy(), Bh)
+
+
 @pytest.mark.parametrize("storage,N,d,tol", [("f32", 9000, 37, 2e-6), ("bf16", 6000, 40, 2e-6),
                                              ("fp8", 5000, 48, 2e-6)])
 def test_sketch_rows_reduced_precision(S, ctx, storage, N, d, tol):
