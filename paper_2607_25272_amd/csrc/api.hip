@@ -68,7 +68,7 @@ struct spcg_ctx {
     int64_t dvec_dpad = 0;
     // sketch and preconditioner workspaces used by spcg_solve
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
-    DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w;
+    DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w, dense_wd, dense_tmp;
     int64_t dense_w_elems = 0;
     // events for timing
     hipEvent_t ev_phase[8] = {};
@@ -265,19 +265,23 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
 int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, DenseStatus* host) {
     hipStream_t st = ctx->stream;
     HIP_TRY(ctx, dense_status_reset(st, dev_status));
-    HIP_TRY(ctx, cholesky_upper(st, G, d, d, dev_status));
+    HIP_TRY(ctx, cholesky_upper(st, G, d, d, dev_status, ctx->dense_wd.as<double>(), ctx->dense_tmp.as<double>(),
+                                ctx->dense_w.as<double>(), ctx->dense_w_elems));
     HIP_TRY(ctx, hipMemcpyAsync(host, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return SPCG_OK;
 }
 
-// split-K workspace of the dense kernels: 8 partial d x d (or r x 64) products
+// split-K workspace of the dense kernels (8 partial d x d or r x 64
+// products), the diagonal-block inverses (d x d) and a 64-column strip
 int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
     const int64_t elems = 8 * std::max<int64_t>(d * d, r * 64);
     if (ctx->dense_w_elems < elems) {
         HIP_TRY(ctx, ctx->dense_w.ensure((size_t)elems * 8));
         ctx->dense_w_elems = elems;
     }
+    HIP_TRY(ctx, ctx->dense_wd.ensure((size_t)d * d * 8));
+    HIP_TRY(ctx, ctx->dense_tmp.ensure((size_t)std::max(r, d) * 64 * 8));
     return SPCG_OK;
 }
 
@@ -292,7 +296,9 @@ int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
     HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
     double* W = ctx->dense_a.as<double>();
     HIP_TRY(ctx, dense_fill_identity(st, W, d));
-    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d, wk, we));
+    HIP_TRY(ctx, trtri_diag_blocks(st, pc->pR, d, d, ctx->dense_wd.as<double>()));
+    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d, ctx->dense_wd.as<double>(),
+                                  ctx->dense_tmp.as<double>(), wk, we));
     HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0, wk, we));
     return SPCG_OK;
 }
@@ -360,14 +366,16 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
     if ((rc = chol_checked(ctx, R1, d, dst, &hs)) != SPCG_OK) return rc;
     if (hs.fail) return fail(ctx, SPCG_E_RANK, "Cholesky of the (shifted) sketched Gram failed");
     HIP_TRY(ctx, dense_convert(st, sk->pBh, bf32, r, d, ld, std::sqrt(inv_r), Q, d));
-    HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R1, d, wk, we));
+    HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R1, d, ctx->dense_wd.as<double>(), ctx->dense_tmp.as<double>(),
+                                  wk, we));
     // second pass
     HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R2, d, 1, wk, we));
     if ((rc = chol_checked(ctx, R2, d, dst, &hs)) != SPCG_OK) return rc;
     if (hs.fail || hs.min_pivot < 1e-12)
         return fail(ctx, SPCG_E_RANK, "S_hat X is numerically rank deficient (pivot %.3g)", hs.min_pivot);
     if (passes == 3) {
-        HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R2, d, wk, we));
+        HIP_TRY(ctx, trsm_right_upper(st, Q, r, d, d, R2, d, ctx->dense_wd.as<double>(),
+                                      ctx->dense_tmp.as<double>(), wk, we));
         HIP_TRY(ctx, gemm_f64(st, d, d, r, 1.0, Q, 0, 1, d, Q, 0, d, 1, 0.0, R, d, 1, wk, we));
         if ((rc = chol_checked(ctx, R, d, dst, &hs)) != SPCG_OK) return rc;
         if (hs.fail || hs.min_pivot < 1e-12)

@@ -133,12 +133,24 @@ __global__ void splitk_reduce_kernel(const double* part, int nz, int64_t M, int6
     *cp = beta == 0.0 ? v : fma(beta, *cp, v);
 }
 
-// Unblocked upper Cholesky of the nb x nb diagonal block at (k0, k0).
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, int64_t k0, int nb,
-                                                         DenseStatus* st) {
-    __shared__ double T[CB][CB + 1];
-    __shared__ double piv_sh;
+// Upper Cholesky of the nb x nb diagonal block at (k0, k0) of G, in place
+// (strict lower part zeroed).
+// 256 threads in a 16 x 16 grid; each keeps a 4 x 4 patch of the block in
+// registers; per step only the pivot row goes through LDS.
+__global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, int64_t k0, int nb,
+                                                        DenseStatus* st) {
+    __shared__ double rowj[CB];
+    __shared__ double piv_u;
     const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    double a[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            a[r][c] = (i < nb && j < nb && j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
+        }
     double min_piv = 0.0, min_d = 0.0, max_d = 0.0;
     int first_fail = 0;
     if (tid == 0) {
@@ -147,40 +159,66 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, 
         max_d = st->max_diag;
         first_fail = st->fail;
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e / nb, j = e - i * nb;
-        T[i][j] = (j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
-    }
-    __syncthreads();
     for (int j = 0; j < nb; ++j) {
+        const int jr = j & 3, jb = j >> 2;
+        // pivot owner: diagonal element (j, j)
+        if (ty == jb && tx == jb) {
+            double piv = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (r == jr && c == jr) piv = a[r][c];
+            piv_u = piv;
+        }
+        __syncthreads();
+        double u = piv_u;
+        if (!(u > 0.0) || !__builtin_isfinite(u)) u = 1.0;
+        u = sqrt(u);
+        const double ru = 1.0 / u;
         if (tid == 0) {
-            double piv = T[j][j];
-            min_piv = piv < min_piv ? piv : min_piv;
-            if (!(piv > 0.0) || !__builtin_isfinite(piv)) {
-                if (first_fail == 0) first_fail = (int)(k0 + j) + 1;
-                piv = 1.0;
-            }
-            const double u = sqrt(piv);
-            T[j][j] = u;
+            const double p = piv_u;
+            min_piv = p < min_piv ? p : min_piv;
+            if ((!(p > 0.0) || !__builtin_isfinite(p)) && first_fail == 0) first_fail = (int)(k0 + j) + 1;
             min_d = u < min_d ? u : min_d;
             max_d = u > max_d ? u : max_d;
-            piv_sh = u;
+        }
+        // owners of row j scale it (U[j][l] = a[j][l] / u, U[j][j] = u) and publish it
+        if (ty == jb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r != jr) continue;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int l = tx * 4 + c;
+                    if (l == j) a[r][c] = u;
+                    else if (l > j) a[r][c] *= ru;
+                    rowj[l] = l >= j ? a[r][c] : 0.0;
+                }
+            }
         }
         __syncthreads();
-        const double u = piv_sh;
-        for (int l = j + 1 + tid; l < nb; l += 256) T[j][l] /= u;
-        __syncthreads();
-        const int rem = nb - j - 1;
-        for (int e = tid; e < rem * rem; e += 256) {
-            const int i = j + 1 + e / rem, l = j + 1 + e % rem;
-            if (l >= i) T[i][l] = fma(-T[j][i], T[j][l], T[i][l]);
+        // trailing update of rows i > j: a[i][l] -= U[j][i] U[j][l] (l >= i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = ty * 4 + r;
+            if (i > j && i < nb) {
+                const double uji = rowj[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int l = tx * 4 + c;
+                    if (l >= i && l < nb) a[r][c] = fma(-uji, rowj[l], a[r][c]);
+                }
+            }
         }
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e / nb, j = e - i * nb;
-        G[(k0 + i) * ld + k0 + j] = (j >= i) ? T[i][j] : 0.0;
-    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            if (i < nb && j < nb) G[(k0 + i) * ld + k0 + j] = (j >= i) ? a[r][c] : 0.0;
+        }
     if (tid == 0) {
         st->min_pivot = min_piv;
         st->min_diag = min_d;
@@ -189,60 +227,77 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* G, int64_t ld, 
     }
 }
 
-// Row panel of the Cholesky: G[k0:k0+nb, c] <- U_kk^{-T} G[k0:k0+nb, c] for
-// every column c >= k0 + nb (one thread per column).
-__global__ __launch_bounds__(64) void chol_panel_kernel(double* G, int64_t ld, int64_t k0, int nb,
-                                                        int64_t d) {
-    __shared__ double U[CB][CB + 1];
-    __shared__ double Y[CB][64];
+// Inverses of CB x CB diagonal blocks of an upper-triangular U, starting at
+// block `first` (one block of 256 threads per diagonal block).  A partial
+// last block is padded with the identity.  Recursive doubling in LDS:
+// invert the eight 8 x 8 diagonal blocks by back substitution, then for
+// s = 8, 16, 32 combine neighbouring s x s inverses with
+// W12 = -W11 U12 W22.
+__global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* U, int64_t d, int64_t ld, double* W,
+                                                           int64_t first) {
+    __shared__ double T[CB][CB + 1];
+    __shared__ double Wl[CB][CB + 1];
+    __shared__ double Tmp[CB][CB + 1];
     const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 64) {
-        const int i = e / nb, j = e - i * nb;
-        U[i][j] = G[(k0 + i) * ld + k0 + j];
+    const int64_t k0 = (first + (int64_t)blockIdx.x) * CB;
+    const int nb = (int)min((int64_t)CB, d - k0);
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        double v;
+        if (i < nb && j < nb) v = (j >= i) ? U[(k0 + i) * ld + k0 + j] : 0.0;
+        else v = (i == j) ? 1.0 : 0.0;
+        T[i][j] = v;
+        Wl[i][j] = 0.0;
     }
     __syncthreads();
-    const int64_t c = k0 + nb + (int64_t)blockIdx.x * 64 + tid;
-    const bool ok = c < d;
-    for (int i = 0; i < nb; ++i) Y[i][tid] = ok ? G[(k0 + i) * ld + c] : 0.0;
-    if (!ok) return;
-    for (int i = 0; i < nb; ++i) {
-        double v = Y[i][tid];
-        for (int l = 0; l < i; ++l) v = fma(-U[l][i], Y[l][tid], v);
-        Y[i][tid] = v / U[i][i];
+    if (tid < CB) {   // 8 x 8 diagonal blocks: thread = (block, column)
+        const int b0 = (tid >> 3) * 8, c = tid & 7;
+        double w[8];
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int l = i + 1; l < 8; ++l) acc = fma(-T[b0 + i][b0 + l], w[l], acc);
+            w[i] = (i <= c) ? acc / T[b0 + i][b0 + i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Wl[b0 + i][b0 + c] = w[i];
     }
-    for (int i = 0; i < nb; ++i) G[(k0 + i) * ld + c] = Y[i][tid];
+    __syncthreads();
+    for (int sz = 8; sz < CB; sz *= 2) {
+        const int pairs = CB / (2 * sz);
+        const int outs = pairs * sz * sz;
+        // Tmp = U12 W22
+        for (int e = tid; e < outs; e += 256) {
+            const int p = e / (sz * sz), rem = e % (sz * sz), i = rem / sz, j = rem % sz;
+            const int s0 = p * 2 * sz, s1 = s0 + sz;
+            double acc = 0.0;
+            for (int l = 0; l <= j; ++l) acc = fma(T[s0 + i][s1 + l], Wl[s1 + l][s1 + j], acc);
+            Tmp[s0 + i][s1 + j] = acc;
+        }
+        __syncthreads();
+        // W12 = -W11 Tmp
+        for (int e = tid; e < outs; e += 256) {
+            const int p = e / (sz * sz), rem = e % (sz * sz), i = rem / sz, j = rem % sz;
+            const int s0 = p * 2 * sz, s1 = s0 + sz;
+            double acc = 0.0;
+            for (int l = i; l < sz; ++l) acc = fma(Wl[s0 + i][s0 + l], Tmp[s0 + l][s1 + j], acc);
+            Wl[s0 + i][s1 + j] = -acc;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        if (i < nb && j < nb) W[(k0 + i) * ld + k0 + j] = Wl[i][j];
+    }
 }
 
-// A[i, k0:k0+nb] <- A[i, k0:k0+nb] U_kk^{-1} (one thread per row).
-__global__ __launch_bounds__(64) void trsm_rows_kernel(double* A, int64_t n, int64_t lda,
-                                                       const double* U, int64_t ldu, int64_t k0,
-                                                       int nb) {
-    __shared__ double Us[CB][CB + 1];
-    __shared__ double Q[CB][64];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 64) {
-        const int i = e / nb, j = e - i * nb;
-        Us[i][j] = U[(k0 + i) * ldu + k0 + j];
-    }
-    __syncthreads();
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    for (int e = tid; e < 64 * nb; e += 64) {
-        const int rr = e / nb, j = e - rr * nb;
-        Q[j][rr] = (i0 + rr < n) ? A[(i0 + rr) * lda + k0 + j] : 0.0;
-    }
-    __syncthreads();
-    if (i0 + tid < n) {
-        for (int j = 0; j < nb; ++j) {
-            double v = Q[j][tid];
-            for (int l = 0; l < j; ++l) v = fma(-Q[l][tid], Us[l][j], v);
-            Q[j][tid] = v / Us[j][j];
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * nb; e += 64) {
-        const int rr = e / nb, j = e - rr * nb;
-        if (i0 + rr < n) A[(i0 + rr) * lda + k0 + j] = Q[j][rr];
-    }
+__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
+                              int64_t cols) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t i = e / cols, j = e - i * cols;
+    dst[i * ldd + j] = src[i * lds + j];
 }
 
 __global__ void zero_lower_kernel(double* G, int64_t d, int64_t ld) {
@@ -323,19 +378,32 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
     return hipGetLastError();
 }
 
-hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status) {
+hipError_t copy2d(hipStream_t st, const double* src, int64_t lds, double* dst, int64_t ldd,
+                  int64_t rows, int64_t cols) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    copy2d_kernel<<<(unsigned)ceil_div(rows * cols, 256), 256, 0, st>>>(src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status,
+                          double* W, double* panel, double* work, int64_t work_elems) {
     hipError_t e;
     for (int64_t k0 = 0; k0 < d; k0 += CB) {
         const int nb = (int)std::min<int64_t>(CB, d - k0);
-        potrf_diag_kernel<<<1, 256, 0, st>>>(G, ld, k0, nb, status);
+        potrf_blk_kernel<<<1, 256, 0, st>>>(G, ld, k0, nb, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int64_t rem = d - k0 - nb;
+        trtri_blocks_kernel<<<1, 256, 0, st>>>(G, d, ld, W, k0 / CB);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t k1 = k0 + nb, rem = d - k1;
         if (rem > 0) {
-            chol_panel_kernel<<<(unsigned)ceil_div(rem, 64), 64, 0, st>>>(G, ld, k0, nb, d);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            double* P = G + k0 * ld + k0 + nb;
-            e = gemm_f64(st, rem, rem, nb, -1.0, P, 0, 1, ld, P, 0, ld, 1, 1.0,
-                         G + (k0 + nb) * ld + k0 + nb, ld, 1, nullptr, 0);
+            // row panel: U[k, k1:] = U_kk^{-T} G[k, k1:]  (panel buffer nb x rem)
+            e = gemm_f64(st, nb, rem, nb, 1.0, W + k0 * ld + k0, 0, 1, ld, G + k0 * ld + k1, 0, ld, 1,
+                         0.0, panel, rem, 0, nullptr, 0);
+            if (e != hipSuccess) return e;
+            if ((e = copy2d(st, panel, rem, G + k0 * ld + k1, ld, nb, rem)) != hipSuccess) return e;
+            // trailing update G[k1:, k1:] -= P^T P (upper tiles)
+            e = gemm_f64(st, rem, rem, nb, -1.0, panel, 0, 1, rem, panel, 0, rem, 1, 1.0,
+                         G + k1 * ld + k1, ld, 1, work, work_elems);
             if (e != hipSuccess) return e;
         }
     }
@@ -343,8 +411,14 @@ hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, Dens
     return hipGetLastError();
 }
 
+hipError_t trtri_diag_blocks(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W) {
+    trtri_blocks_kernel<<<(unsigned)ceil_div(d, CB), 256, 0, st>>>(U, d, ld, W, 0);
+    return hipGetLastError();
+}
+
 hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int64_t lda,
-                            const double* U, int64_t ldu, double* work, int64_t work_elems) {
+                            const double* U, int64_t ldu, const double* W, double* tmp, double* work,
+                            int64_t work_elems) {
     hipError_t e;
     for (int64_t k0 = 0; k0 < d; k0 += CB) {
         const int nb = (int)std::min<int64_t>(CB, d - k0);
@@ -353,8 +427,11 @@ hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int
                          work, work_elems);
             if (e != hipSuccess) return e;
         }
-        trsm_rows_kernel<<<(unsigned)ceil_div(n, 64), 64, 0, st>>>(A, n, lda, U, ldu, k0, nb);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // A[:, k] <- A[:, k] U_kk^{-1}
+        e = gemm_f64(st, n, nb, nb, 1.0, A + k0, 0, lda, 1, W + k0 * ldu + k0, 0, ldu, 1, 0.0, tmp, nb, 0,
+                     nullptr, 0);
+        if (e != hipSuccess) return e;
+        if ((e = copy2d(st, tmp, nb, A + k0, lda, n, nb)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

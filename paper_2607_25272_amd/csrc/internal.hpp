@@ -124,11 +124,18 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
                     int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
                     int64_t work_elems);
-// In-place upper Cholesky G = U^T U (row-major d x d, ld); lower part zeroed.
-hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status);
-// In-place A <- A U^{-1} for A (n x d, lda) and upper-triangular U (d x d, ldu).
+// In-place upper Cholesky G = U^T U (row-major d x d, ld); lower part
+// zeroed; the inverses of the 64 x 64 diagonal blocks of U go to the same
+// positions of W (d x d, ld).  panel: 64 x d scratch.
+hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status,
+                          double* W, double* panel, double* work, int64_t work_elems);
+// Inverses of the 64 x 64 diagonal blocks of an upper-triangular U into W.
+hipError_t trtri_diag_blocks(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W);
+// In-place A <- A U^{-1} for A (n x d, lda), upper-triangular U (d x d,
+// ldu) whose diagonal-block inverses are in W (same layout); tmp: n x 64.
 hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int64_t lda,
-                            const double* U, int64_t ldu, double* work, int64_t work_elems);
+                            const double* U, int64_t ldu, const double* W, double* tmp, double* work,
+                            int64_t work_elems);
 hipError_t dense_fill_identity(hipStream_t st, double* A, int64_t d);
 hipError_t dense_convert(hipStream_t st, const void* src, int src_f32, int64_t rows, int64_t cols,
                          int64_t lds, double scale, double* dst, int64_t ldd);
