@@ -232,12 +232,25 @@ typedef struct spcg_solve_stats {
 } spcg_solve_stats;
 
 /* beta (DEVICE, d x k row-major FP64) <- Algorithm 1 (or full-data PCG)
- * for (X, Y).  X: N x d any element type; Y: N x k SPCG_F64.  Stage II
+ * for (X, Y).  X: N x d any element type; Y: N x k SPCG_F64 (k > 1 takes
+ * the batched form with one problem, see spcg_solve_batched).  Stage II
  * stops when sqrt(g^T H^-1 g) <= tol ||X beta|| or at T total iterations.
  * Workspaces are cached in ctx and reused by later solves of the same or
  * smaller size. */
 int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
                double* beta, spcg_solve_stats* stats);
+
+/* Batched / multi-right-hand-side form.  Solves nprob independent problems
+ * (X[p], Y[p]) with the same options: every PCG step of all problems is one
+ * product launch over a queue of (problem, row range) tasks on the matrix
+ * cores plus one d-space launch (one block per problem), and Stage II stops
+ * per problem.  Requirements: X[p] SPCG_F32 or SPCG_BF16 (all the same),
+ * d <= 512, 1 <= k <= 16 right-hand sides (Y[p] is N x k SPCG_F64), beta[p]
+ * DEVICE d x k row-major FP64.  Products accumulate in FP32.  stats may be
+ * NULL or an array of nprob entries.  Returns the worst code over the
+ * problems (W_NOT_CONVERGED if any problem missed tol within T). */
+int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y,
+                       const spcg_solve_opts* opts, double* const* beta, spcg_solve_stats* stats);
 
 /* Default option values (all zero fields mean "default"). */
 void spcg_solve_opts_default(spcg_solve_opts* opts);

@@ -17,7 +17,8 @@ from ._lib import (SPCG_BF16, SPCG_E_BREAKDOWN, SPCG_E_DTYPE, SPCG_E_HIP, SPCG_E
                    SPCG_METHOD_FULL_PCG, SPCG_METHOD_SPCG, SPCG_OK, SPCG_W_NOT_CONVERGED)
 
 __all__ = ["Context", "SpcgError", "spcg_sketch", "spcg_precond_build", "spcg_precond_from_r",
-           "spcg_pcg_stage", "spcg_solve", "spcg_sketch_tables_host", "mat", "load"]
+           "spcg_pcg_stage", "spcg_solve", "spcg_solve_batched", "spcg_sketch_tables_host", "mat",
+           "load"]
 
 _DTYPES = {
     torch.float64: SPCG_F64,
@@ -240,11 +241,15 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
 
 
 def spcg_solve(ctx, X, Y, beta=None, col_scale=None, **kw):
-    """Algorithm 1 (or full-data PCG with method='pcg'); returns (beta, stats)."""
+    """Algorithm 1 (or full-data PCG with method='pcg'); returns (beta, stats).
+
+    Y may have k > 1 columns (beta is then d x k)."""
     o, keep = solve_opts(**kw)
     Xm, Ym = mat(X, col_scale), mat(Y)
     if beta is None:
-        beta = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
+        k = Y.shape[1] if Y.dim() == 2 else 1
+        shape = (X.shape[1],) if k == 1 else (X.shape[1], k)
+        beta = torch.empty(shape, dtype=torch.float64, device=X.device)
     st = L.SolveStats()
     rc = ctx.check(ctx.lib.spcg_solve(ctx.h, ctypes.byref(Xm), ctypes.byref(Ym), ctypes.byref(o),
                                       ctypes.c_void_p(beta.data_ptr()), ctypes.byref(st)))
@@ -252,6 +257,28 @@ def spcg_solve(ctx, X, Y, beta=None, col_scale=None, **kw):
     stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
     stats["rc"] = rc
     return beta, stats
+
+
+def spcg_solve_batched(ctx, Xs, Ys, betas=None, **kw):
+    """Batched / multi-RHS form: independent problems (Xs[p], Ys[p]) solved
+    together; returns (betas, stats_list) with betas[p] of shape d x k."""
+    n = len(Xs)
+    o, keep = solve_opts(**kw)
+    xm = (L.SpcgMat * n)(*[mat(x) for x in Xs])
+    ym = (L.SpcgMat * n)(*[mat(y) for y in Ys])
+    if betas is None:
+        betas = [torch.empty(x.shape[1], y.shape[1], dtype=torch.float64, device=x.device)
+                 for x, y in zip(Xs, Ys)]
+    ptrs = (ctypes.c_void_p * n)(*[b.data_ptr() for b in betas])
+    st = (L.SolveStats * n)()
+    rc = ctx.check(ctx.lib.spcg_solve_batched(ctx.h, n, xm, ym, ctypes.byref(o), ptrs, st))
+    del keep
+    stats = []
+    for i in range(n):
+        d = {f: getattr(st[i], f) for f, _ in L.SolveStats._fields_}
+        d["rc"] = rc
+        stats.append(d)
+    return betas, stats
 
 
 def spcg_sketch_tables_host(seed, L_bits, m, r):

@@ -570,6 +570,269 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// --------------------------------------------------- batched / multi-RHS
+
+struct BatchWork {
+    std::vector<spcg_sketch_t*> sk;
+    std::vector<spcg_precond_t*> pc;
+    DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal;
+    ~BatchWork() {
+        for (auto* p : sk) delete p;
+        for (auto* p : pc) delete p;
+    }
+};
+
+constexpr int MR_VECS = 6;   // X G Z P S Gt
+
+int build_tasks(const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks, std::vector<MrhsProblem>& out,
+                int64_t rows_per_task) {
+    tasks.clear();
+    out = hp;
+    for (size_t p = 0; p < hp.size(); ++p) {
+        out[p].t0 = (int)tasks.size();
+        if (hp[p].active) {
+            for (int64_t r = 0; r < hp[p].m; r += rows_per_task) {
+                MrhsTask t{};
+                t.prob = (int)p;
+                t.r0 = r;
+                t.r1 = std::min<int64_t>(hp[p].m, r + rows_per_task);
+                tasks.push_back(t);
+            }
+        }
+        out[p].t1 = (int)tasks.size();
+    }
+    return (int)tasks.size();
+}
+
+int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, const std::vector<MrhsProblem>& hp,
+                 int64_t rows_per_task) {
+    std::vector<MrhsTask> tasks;
+    std::vector<MrhsProblem> probs;
+    const int nt = build_tasks(hp, tasks, probs, rows_per_task);
+    const size_t per_task = (size_t)mrhs_max_d() * mrhs_max_k();
+    HIP_TRY(ctx, W.tasks.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
+    HIP_TRY(ctx, W.probs.ensure(probs.size() * sizeof(MrhsProblem)));
+    HIP_TRY(ctx, W.part_s.ensure((size_t)std::max(nt, 1) * per_task * 4));
+    HIP_TRY(ctx, W.part_g.ensure((size_t)std::max(nt, 1) * per_task * 4));
+    HIP_TRY(ctx, W.part_scal.ensure((size_t)std::max(nt, 1) * 2 * mrhs_max_k() * 4));
+    hipStream_t st = ctx->stream;
+    if (nt)
+        HIP_TRY(ctx, hipMemcpyAsync(W.tasks.p, tasks.data(), tasks.size() * sizeof(MrhsTask), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(W.probs.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, run_mrhs_product(st, dtype, mode, W.tasks.as<MrhsTask>(), nt, W.probs.as<MrhsProblem>(),
+                                  W.part_s.as<float>(), W.part_g.as<float>(), W.part_scal.as<float>()));
+    HIP_TRY(ctx, run_mrhs_dspace(st, variant, W.probs.as<MrhsProblem>(), (int)probs.size(), W.part_s.as<float>(),
+                                 W.part_g.as<float>(), W.part_scal.as<float>()));
+    // the pageable task/problem arrays above go out of scope: finish the copies
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return SPCG_OK;
+}
+
+int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
+                  double* const* beta, spcg_solve_stats* stats) {
+    int rc;
+    if (nprob < 1 || !X || !Y || !beta || !opts) return fail(ctx, SPCG_E_INVALID_ARG, "bad batched arguments");
+    const int dtype = X[0].dtype;
+    if (dtype != SPCG_F32 && dtype != SPCG_BF16)
+        return fail(ctx, SPCG_E_DTYPE, "the batched form needs SPCG_F32 or SPCG_BF16 storage");
+    for (int p = 0; p < nprob; ++p) {
+        if ((rc = check_mat(ctx, &X[p], "X[p]")) != SPCG_OK) return rc;
+        if ((rc = check_mat(ctx, &Y[p], "Y[p]")) != SPCG_OK) return rc;
+        if (X[p].dtype != dtype) return fail(ctx, SPCG_E_DTYPE, "all X[p] must share one storage type");
+        if (Y[p].dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "Y[p] must be SPCG_F64");
+        if (Y[p].rows != X[p].rows) return fail(ctx, SPCG_E_SHAPE, "X[%d] and Y[%d] row counts differ", p, p);
+        if (X[p].cols > mrhs_max_d()) return fail(ctx, SPCG_E_SHAPE, "batched form: d <= %d", mrhs_max_d());
+        if (Y[p].cols > mrhs_max_k()) return fail(ctx, SPCG_E_SHAPE, "batched form: k <= %d", mrhs_max_k());
+        if (!beta[p]) return fail(ctx, SPCG_E_INVALID_ARG, "beta[%d] is NULL", p);
+    }
+    if (opts->method != SPCG_METHOD_SPCG && opts->method != SPCG_METHOD_FULL_PCG)
+        return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
+    const int a = opts->a > 0 ? opts->a : 3;
+    const int T = opts->T > 0 ? opts->T : 100;
+    const double tol = opts->tol > 0.0 ? opts->tol : 5e-7;
+    hipStream_t st = ctx->stream;
+    const bool timing = opts->time_phases != 0;
+    if (timing) {
+        if ((rc = ensure_events(ctx)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
+    }
+    BatchWork W;
+    W.sk.assign(nprob, nullptr);
+    W.pc.assign(nprob, nullptr);
+    spcg_sketch_opts so = opts->sketch;
+    so.hat_only = opts->method == SPCG_METHOD_FULL_PCG ? 1 : 0;
+    for (int p = 0; p < nprob; ++p) {
+        W.sk[p] = new (std::nothrow) spcg_sketch_t();
+        if (!W.sk[p]) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+        if ((rc = sketch_build(ctx, &X[p], &Y[p], &so, false, W.sk[p])) != SPCG_OK) return rc;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
+    for (int p = 0; p < nprob; ++p) {
+        W.pc[p] = new (std::nothrow) spcg_precond_t();
+        if (!W.pc[p]) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+        if ((rc = precond_build(ctx, W.sk[p], &opts->precond, false, W.pc[p])) != SPCG_OK) return rc;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
+    const int64_t ldv = mrhs_max_d();
+    const int kmax = mrhs_max_k();
+    HIP_TRY(ctx, W.vecs.ensure((size_t)nprob * MR_VECS * kmax * ldv * 8));
+    HIP_TRY(ctx, W.scal.ensure((size_t)nprob * kmax * sizeof(MrhsScalars)));
+    HIP_TRY(ctx, hipMemsetAsync(W.vecs.p, 0, (size_t)nprob * MR_VECS * kmax * ldv * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(W.scal.p, 0, (size_t)nprob * kmax * sizeof(MrhsScalars), st));
+    std::vector<MrhsProblem> hp(nprob);
+    int64_t total_rows = 0, maxK = 0;
+    for (int p = 0; p < nprob; ++p) {
+        MrhsProblem& q = hp[p];
+        std::memset(&q, 0, sizeof q);
+        double* base = W.vecs.as<double>() + (size_t)p * MR_VECS * kmax * ldv;
+        q.d = (int)X[p].cols;
+        q.k = (int)Y[p].cols;
+        q.ldv = ldv;
+        q.X = base;
+        q.G = base + 1 * kmax * ldv;
+        q.Z = base + 2 * kmax * ldv;
+        q.P = base + 3 * kmax * ldv;
+        q.S = base + 4 * kmax * ldv;
+        q.Gt = base + 5 * kmax * ldv;
+        q.Minv = W.pc[p]->pMinv;
+        q.sc = W.scal.as<MrhsScalars>() + (size_t)p * kmax;
+        total_rows += X[p].rows;
+        maxK = std::max<int64_t>(maxK, W.sk[p]->K);
+    }
+    // tasks: about 4 per CU over the full data, never fewer than 256 rows
+    const int64_t rows_per_task = std::max<int64_t>(256, round_up(ceil_div(total_rows, 4 * ctx->num_cu), 16));
+    std::vector<int> t1(nprob, 0), t2(nprob, 0), conv(nprob, 0);
+    // Stage I: stage i of every problem that has one
+    for (int64_t i = 0; i < maxK; ++i) {
+        int ai = a;
+        if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
+        bool any = false;
+        for (int p = 0; p < nprob; ++p) {
+            MrhsProblem& q = hp[p];
+            q.active = i < W.sk[p]->K && t1[p] + ai <= T;
+            if (!q.active) continue;
+            any = true;
+            spcg_mat A{}, b{};
+            double c2 = 1.0;
+            spcg_sketch_view(W.sk[p], (int)i, &A, &b, &c2);
+            q.A = A.data;
+            q.m = A.rows;
+            q.lda = A.ld;
+            q.b = static_cast<const double*>(b.data);
+            q.ldb = b.ld;
+            q.c2 = c2;
+        }
+        if (!any) continue;
+        // the sketch rows of FP32/BF16 input are FP32
+        if ((rc = batched_pass(ctx, W, DT_F32, PM_G, PA_START, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+            return rc;
+        for (int it = 0; it < ai; ++it)
+            if ((rc = batched_pass(ctx, W, DT_F32, PM_S, PA_STEP, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+                return rc;
+        for (int p = 0; p < nprob; ++p)
+            if (hp[p].active) t1[p] += ai;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[3], st));
+    // Stage II on the full data; every problem stops on its own test
+    for (int p = 0; p < nprob; ++p) {
+        MrhsProblem& q = hp[p];
+        q.active = 1;
+        q.A = X[p].data;
+        q.m = X[p].rows;
+        q.lda = X[p].ld;
+        q.b = static_cast<const double*>(Y[p].data);
+        q.ldb = Y[p].ld;
+        q.c2 = 1.0;
+    }
+    std::vector<MrhsScalars> hs((size_t)nprob * kmax);
+    // Divergence guard: the FP32 products have an accuracy floor; a problem
+    // whose stopping ratio climbs well above its best value (iterating past
+    // the floor) stops, keeping the best iterate seen.
+    std::vector<double> best(nprob, INFINITY);
+    DevBuf bestx;
+    HIP_TRY(ctx, bestx.ensure((size_t)nprob * kmax * ldv * 8));
+    auto check = [&](int* n_active) -> int {
+        HIP_TRY(ctx, hipMemcpy(hs.data(), W.scal.p, hs.size() * sizeof(MrhsScalars), hipMemcpyDeviceToHost));
+        int act = 0;
+        for (int p = 0; p < nprob; ++p) {
+            if (!hp[p].active) continue;
+            bool done = true;
+            double worst = 0.0;
+            for (int c = 0; c < hp[p].k; ++c) {
+                const MrhsScalars& s = hs[(size_t)p * kmax + c];
+                if (s.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown in problem %d", p);
+                const double ratio = s.exact ? 0.0 : std::sqrt(std::max(s.rho, 0.0)) /
+                                                         std::max(std::sqrt(std::max(s.ax2, 0.0)), 1e-300);
+                worst = std::max(worst, ratio);
+                done = done && ratio <= tol;
+            }
+            double* xp = W.vecs.as<double>() + (size_t)p * MR_VECS * kmax * ldv;
+            double* bp = bestx.as<double>() + (size_t)p * kmax * ldv;
+            const bool diverging = worst > 100.0 * best[p];
+            if (worst < best[p]) {
+                best[p] = worst;
+                HIP_TRY(ctx, hipMemcpyAsync(bp, xp, (size_t)kmax * ldv * 8, hipMemcpyDeviceToDevice, st));
+            }
+            if (done) {
+                conv[p] = 1;
+                hp[p].active = 0;
+            } else if (diverging || t1[p] + t2[p] >= T) {
+                hp[p].active = 0;
+                HIP_TRY(ctx, hipMemcpyAsync(xp, bp, (size_t)kmax * ldv * 8, hipMemcpyDeviceToDevice, st));
+            } else {
+                ++act;
+            }
+        }
+        *n_active = act;
+        return SPCG_OK;
+    };
+    int act = 0;
+    if ((rc = batched_pass(ctx, W, dtype, PM_G, PA_START, hp, rows_per_task)) != SPCG_OK) return rc;
+    if ((rc = check(&act)) != SPCG_OK) return rc;
+    while (act > 0) {
+        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, rows_per_task)) != SPCG_OK) return rc;
+        for (int p = 0; p < nprob; ++p)
+            if (hp[p].active) ++t2[p];
+        if ((rc = check(&act)) != SPCG_OK) return rc;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[4], st));
+    // beta[p] (d x k row-major) <- X (column by column)
+    for (int p = 0; p < nprob; ++p)
+        HIP_TRY(ctx, hipMemcpy2DAsync(beta[p], (size_t)hp[p].k * 8, hp[p].X, 8, 8, hp[p].d, hipMemcpyDeviceToDevice, st));
+    for (int p = 0; p < nprob; ++p)
+        for (int c = 1; c < hp[p].k; ++c)
+            HIP_TRY(ctx, hipMemcpy2DAsync(beta[p] + c, (size_t)hp[p].k * 8, hp[p].X + (size_t)c * ldv, 8, 8, hp[p].d,
+                                          hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    bool all = true;
+    for (int p = 0; p < nprob; ++p) {
+        all = all && conv[p];
+        if (stats) {
+            spcg_solve_stats& s = stats[p];
+            std::memset(&s, 0, sizeof s);
+            s.K = (int32_t)W.sk[p]->K;
+            s.T_stage1 = t1[p];
+            s.T_stage2 = t2[p];
+            s.converged = conv[p];
+            s.qr_passes = W.pc[p]->passes;
+            s.rho_final = hs[(size_t)p * kmax].rho;
+            s.ax_norm = std::sqrt(std::max(hs[(size_t)p * kmax].ax2, 0.0));
+            if (timing) {
+                s.t_sketch_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[1]);
+                s.t_precond_ms = elapsed_ms(ctx->ev_phase[1], ctx->ev_phase[2]);
+                s.t_stage1_ms = elapsed_ms(ctx->ev_phase[2], ctx->ev_phase[3]);
+                s.t_stage2_ms = elapsed_ms(ctx->ev_phase[3], ctx->ev_phase[4]);
+                s.t_total_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[4]);
+            }
+        }
+    }
+    if (!all) {
+        fail(ctx, SPCG_W_NOT_CONVERGED, "some problems did not meet tol=%g within T=%d", tol, T);
+        return SPCG_W_NOT_CONVERGED;
+    }
+    return SPCG_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -788,6 +1051,12 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     return SPCG_OK;
 }
 
+int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y,
+                       const spcg_solve_opts* opts, double* const* beta, spcg_solve_stats* stats) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    return batched_solve(ctx, nprob, X, Y, opts, beta, stats);
+}
+
 void spcg_solve_opts_default(spcg_solve_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
@@ -809,8 +1078,10 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if (!beta) return fail(ctx, SPCG_E_INVALID_ARG, "beta is NULL");
     if (Y->dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "Y must be SPCG_F64");
     if (Y->rows != X->rows) return fail(ctx, SPCG_E_SHAPE, "X and Y row counts differ");
-    if (Y->cols != 1)
-        return fail(ctx, SPCG_E_SHAPE, "multiple right-hand sides are not supported by this entry point");
+    if (Y->cols > 1) {
+        double* const b1[1] = {beta};
+        return batched_solve(ctx, 1, X, Y, opts, b1, stats);
+    }
     if (opts->method != SPCG_METHOD_SPCG && opts->method != SPCG_METHOD_FULL_PCG)
         return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
     if (opts->a < 0 || opts->T < 0 || opts->tol < 0.0 || opts->a_list_len < 0 ||

@@ -109,6 +109,47 @@ hipError_t run_scalars_reset(hipStream_t st, PcgScalars* sc);
 hipError_t run_fill(hipStream_t st, double* v, int64_t n, double value);
 hipError_t run_counters_reset(hipStream_t st, unsigned int* c, int n);
 
+// ------------------------------------------------- multi-RHS / batched
+// One independent least-squares problem of a batch (or one problem with
+// k right-hand sides).  d-space vectors are stored column by column:
+// v[c * ldv + j], c < 16.
+struct MrhsScalars {
+    double rho, rho0, alpha, pts, resid2, ax2;
+    int32_t exact, breakdown;
+};
+struct MrhsProblem {
+    const void* A;          // m x d row-major (FP32 or BF16), leading dim lda
+    int64_t m, lda;
+    int d, k;
+    const double* b;        // m x k row-major, leading dim ldb
+    int64_t ldb;
+    double c2;
+    int64_t ldv;            // stride between d-space columns
+    double* X;              // iterate
+    double* G;
+    double* Z;
+    double* P;
+    double* S;
+    double* Gt;
+    const double* Minv;     // d x d
+    MrhsScalars* sc;        // k entries
+    int t0, t1;             // tasks of this problem in the current launch
+    int active;             // 0: skip (converged or no stage)
+};
+struct MrhsTask {
+    int prob;
+    int pad;
+    int64_t r0, r1;
+};
+int mrhs_max_d();
+int mrhs_max_k();
+hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, const MrhsTask* tasks, int ntasks,
+                            const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal);
+// One block per problem: the whole d-space step of all k columns.
+// variant: PA_START (g, z, p, rho from the G partials), PA_STEP, PA_REFRESH.
+hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs, int nprob,
+                           const float* part_s, const float* part_g, const float* part_scal);
+
 // --------------------------------------------------------- dense FP64
 struct DenseStatus {
     int32_t fail;        // first failing pivot index + 1, 0 if none

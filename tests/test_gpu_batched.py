@@ -1,0 +1,102 @@
+"""GPU parity of the multi-RHS and batched forms (k independent PCGs per
+problem sharing the products; many problems per launch) against the FP64
+oracle: every column of every problem must reach its OLS estimator to a
+relative prediction error of 1e-6."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle.ols import ols_tsqr
+from oracle.spcg import rel_pred_error
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2607_25272_amd as spcg_mod
+    return spcg_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+def _check(p, beta):
+    Xd = p.x_f64().cpu().numpy()
+    bh = ols_tsqr(Xd, p.Y.cpu().numpy())
+    B = beta.cpu().numpy().reshape(p.d, -1)
+    for c in range(bh.shape[1]):
+        assert rel_pred_error(Xd, B[:, c], bh[:, c]) <= 1e-6, c
+
+
+@pytest.mark.parametrize("N,d,k,storage", [(1 << 16, 100, 5, "f32"), (50_000, 512, 16, "f32"),
+                                           (40_000, 37, 3, "bf16"), (30_000, 16, 16, "f32")])
+def test_multi_rhs_solve(S, ctx, N, d, k, storage):
+    print(f"multi-rhs N={N} d={d} k={k} {storage}", flush=True)
+    p = workloads.gauss_colscale(N, d, 1e3, 1.0, storage=storage, k=k, seed=N + d + k, device=DEV)
+    beta, st = S.spcg_solve(ctx, p.X, p.Y, seed=1)
+    assert st["converged"] and beta.shape == (d, k)
+    _check(p, beta)
+
+
+def test_multi_rhs_columns_match_single_rhs_solves(S, ctx):
+    # each column of a k-RHS solve is its own PCG: it agrees with the solve
+    # of that column alone (both within 1e-6 of the same OLS estimator)
+    p = workloads.gauss_colscale(1 << 15, 40, 1e2, 1.0, storage="f32", k=4, seed=3, device=DEV)
+    beta, _ = S.spcg_solve(ctx, p.X, p.Y, seed=2)
+    Xd = p.x_f64().cpu().numpy()
+    for c in range(4):
+        b1, _ = S.spcg_solve(ctx, p.X, p.Y[:, c:c + 1].contiguous(), seed=2)
+        assert rel_pred_error(Xd, beta[:, c].cpu().numpy(), b1.cpu().numpy()) < 2e-6
+
+
+def test_multi_rhs_tolerance_below_fp32_floor_does_not_diverge(S, ctx):
+    # Iterating past the accuracy floor of the FP32 products must neither
+    # freeze the refreshed gradient nor drift away from the solution.
+    p = workloads.gauss_colscale(1 << 15, 40, 1e2, 1.0, storage="f32", k=4, seed=3, device=DEV)
+    Xd = p.x_f64().cpu().numpy()
+    bh = ols_tsqr(Xd, p.Y.cpu().numpy())
+    for T in (60, 100):
+        beta, st = S.spcg_solve(ctx, p.X, p.Y, seed=2, tol=1e-13, T=T)
+        B = beta.cpu().numpy()
+        errs = [rel_pred_error(Xd, B[:, c], bh[:, c]) for c in range(4)]
+        print("T", T, "rc", st["rc"], "T2", st["T_stage2"], ["%.1e" % e for e in errs], flush=True)
+        assert max(errs) <= 1e-6
+
+
+def test_batched_uneven_problems(S, ctx):
+    probs = workloads.batched(n_prob=12, N_range=(20_000, 120_000), d_range=(32, 512),
+                              cond_range=(1e2, 1e5), k_range=(1, 16), device=DEV)
+    print("batched shapes", [(q.N, q.d, q.k) for q in probs], flush=True)
+    betas, stats = S.spcg_solve_batched(ctx, [q.X for q in probs], [q.Y for q in probs], seed=1)
+    for q, b, st in zip(probs, betas, stats):
+        assert st["converged"], (q.N, q.d, q.k, st)
+        _check(q, b)
+
+
+def test_batched_full_pcg_and_bf16(S, ctx):
+    probs = [workloads.gauss_colscale(N, d, 1e3, 1.0, storage="bf16", k=k, seed=N, device=DEV)
+             for N, d, k in ((30_000, 64, 2), (45_000, 128, 1), (25_000, 200, 7))]
+    for method in ("spcg", "pcg"):
+        betas, stats = S.spcg_solve_batched(ctx, [q.X for q in probs], [q.Y for q in probs],
+                                            method=method, seed=5)
+        for q, b, st in zip(probs, betas, stats):
+            assert st["converged"]
+            _check(q, b)
+
+
+def test_batched_argument_errors(S, ctx):
+    p = workloads.gauss_colscale(2000, 8, 10, 1.0, storage="f64", k=2, seed=1, device=DEV)
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve_batched(ctx, [p.X], [p.Y])
+    assert e.value.code == S.SPCG_E_DTYPE
+    q = workloads.gauss_colscale(2000, 600, 10, 1.0, storage="f32", k=1, seed=1, device=DEV)
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve_batched(ctx, [q.X], [q.Y])
+    assert e.value.code == S.SPCG_E_SHAPE
