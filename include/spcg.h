@@ -214,8 +214,32 @@ typedef struct spcg_solve_opts {
     int32_t a_list_len;
     int32_t time_phases;  /* 1: record phase times (adds stream syncs) */
     int32_t time_products;/* 1: time every full-data product launch with events */
-    int32_t reserved;
+    int32_t stage_stride; /* 1: every prefix m_1..m_K; 2: every other prefix, ending
+                             at m_K, so sketch sizes grow by 4 per stage (0: 1) */
+    int32_t schedule;     /* SPCG_SCHEDULE_PLAIN or SPCG_SCHEDULE_LEARNED */
+    const float* schedule_weights; /* learned: DEVICE array of SPCG_MLP_PARAMS floats */
+    int32_t schedule_margin;  /* learned: iterations taken off the predicted Stage II
+                                 count before the unchecked run (0: 1, < 0: none) */
+    int32_t record_features;  /* 1: also compute the schedule features under the
+                                 plain schedule (returned in the stats) */
 } spcg_solve_opts;
+
+/* Plain schedule: Algorithm 1 as written (a_i = a, every prefix, stopping
+ * test after every check_every Stage II iterations).
+ * Learned schedule: the network below is evaluated on the device twice.
+ * (1) After the preconditioner is built, on the pre-Stage-I features; the
+ *     arg-max of outputs 0..3 gives a (replacing opts.a and a_list) and of
+ *     outputs 4..5 the stage stride (replacing opts.stage_stride).  One
+ *     stream synchronisation reads the decision.
+ * (2) At the start of Stage II, on the Stage II features, read with the
+ *     scalars of the first stopping test; s_hat = 10 * output 6.  Stage II
+ *     then runs max(0, round(s_hat) - margin) iterations without host
+ *     synchronisation, applies the stopping test once, and, if it fails,
+ *     continues with the plain test (the fallback) up to the budget T.
+ * The result is always judged by the same stopping test as the plain
+ * schedule. */
+#define SPCG_SCHEDULE_PLAIN 0
+#define SPCG_SCHEDULE_LEARNED 1
 
 typedef struct spcg_solve_stats {
     int32_t K;              /* sketched stages run */
@@ -229,6 +253,17 @@ typedef struct spcg_solve_stats {
     double t_sketch_ms, t_precond_ms, t_stage1_ms, t_stage2_ms, t_total_ms;
     double product_ms_sum;      /* summed duration of the timed product launches */
     double product_bytes;       /* algorithmic bytes of one full-data product launch */
+    int32_t host_syncs;         /* stream synchronisations made inside the solve */
+    int32_t policy_a;           /* a used in Stage I (the last a_i for an a_list) */
+    int32_t policy_stride;      /* stage stride used */
+    int32_t unchecked_iters;    /* Stage II iterations run before the first test after the start */
+    int32_t fallback;           /* learned: the plain test had to continue after the unchecked run */
+    float s_pred;               /* learned: 10 * output 6 of the Stage II evaluation */
+    double rho_ii0, ax2_ii0, resid2_ii0; /* Stage II start: g^T H^-1 g, ||X b||^2, ||Y - X b||^2 */
+    float features_pre[8];      /* schedule features (learned, or record_features) */
+    float features_ii[8];
+    float out_pre[8];           /* network outputs (learned; entries 0..6) */
+    float out_ii[8];
 } spcg_solve_stats;
 
 /* beta (DEVICE, d x k row-major FP64) <- Algorithm 1 (or full-data PCG)
@@ -254,6 +289,53 @@ int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_m
 
 /* Default option values (all zero fields mean "default"). */
 void spcg_solve_opts_default(spcg_solve_opts* opts);
+
+/* ---- learned schedule network -------------------------------------------
+ * The paper fixes a_i = 3 and a doubling schedule (Sec. 4.1) and names the
+ * automatic choice of the schedule an open problem (Sec. 4.3).  This
+ * library learns it: a dense network F -> H -> H -> O with ReLU after the
+ * first two layers, all FP32.  Parameters are one flat array, in order
+ * W1 (H x F row-major), b1 (H), W2 (H x H), b2 (H), W3 (O x H), b3 (O).
+ * Outputs: 0..3 logits of a - 1, 4..5 logits of stride - 1, 6 the Stage II
+ * count divided by SPCG_MLP_S_SCALE.
+ *
+ * Features (FP32, computed on the device; every value scale-free):
+ *   f0 = log10 N - 5, f1 = log10 d - 2, f2 = log2(N / d) / 8 - 1,
+ *   f3 = log10(max|R_jj| / min|R_jj|) / 3 - 1 (3 if a diagonal entry is 0),
+ *   f4 = log10(max q / mean q) / 2 over q_j = ||x_j||^2 of the rows
+ *        floor((2t + 1) N / 512), t < 256 (every row if N < 256; 0 if all q are 0),
+ *   pre-Stage-I: f5 = f6 = f7 = 0;
+ *   Stage II start (rho = g^T H^-1 g, fit = ||X beta||^2, res = ||Y - X beta||^2):
+ *   f5 = clamp(log10(sqrt(rho) / (tol sqrt(fit))) / 3, -3, 3) (-3 if rho <= 0, 3 if fit <= 0),
+ *   f6 = clamp(log10(res / fit) / 6, -2, 2) (-2 if res <= 0, 2 if fit <= 0), f7 = 1.
+ *
+ * Training loss of n samples with labels a in 0..3, g in 0..1, s >= 0 and
+ * weights w_a, w_s:
+ *   (1/n) sum [ w_a (CE(out[0:4], a) + CE(out[4:6], g))
+ *               + w_s SPCG_MLP_LAMBDA (out[6] - s / SPCG_MLP_S_SCALE)^2 ]
+ * with CE the softmax cross-entropy. */
+#define SPCG_MLP_F 8
+#define SPCG_MLP_H 64
+#define SPCG_MLP_O 7
+#define SPCG_MLP_PARAMS (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H + \
+                         SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
+#define SPCG_MLP_S_SCALE 10.0
+#define SPCG_MLP_LAMBDA 0.5
+
+/* out (DEVICE, n x O FP32) <- network(W, feats (DEVICE, n x F FP32)). */
+int spcg_mlp_forward(spcg_ctx* ctx, const float* W, const float* feats, int64_t n, float* out);
+/* grad (DEVICE, SPCG_MLP_PARAMS FP32) <- gradient of the mean loss above;
+ * *loss (DEVICE, one FP32, may be NULL) <- the loss.  Labels and weights
+ * are DEVICE arrays of n entries; a is clamped to 0..3 and g taken mod 2.
+ * Sums run in a fixed order (identical bits on repeated calls). */
+int spcg_mlp_loss_grad(spcg_ctx* ctx, const float* W, const float* feats, const int32_t* a_label,
+                       const int32_t* g_label, const float* s_label, const float* w_a,
+                       const float* w_s, int64_t n, float* grad, float* loss);
+/* One Adam step (Kingma and Ba) on n DEVICE parameters: m <- b1 m + (1 - b1) g,
+ * v <- b2 v + (1 - b2) g^2, W <- W - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
+ * step = t >= 1. */
+int spcg_mlp_adam(spcg_ctx* ctx, float* W, const float* grad, float* m, float* v, int64_t n,
+                  int32_t step, float lr, float beta1, float beta2, float eps);
 
 #ifdef __cplusplus
 }

@@ -17,8 +17,8 @@ from ._lib import (SPCG_BF16, SPCG_E_BREAKDOWN, SPCG_E_DTYPE, SPCG_E_HIP, SPCG_E
                    SPCG_METHOD_FULL_PCG, SPCG_METHOD_SPCG, SPCG_OK, SPCG_W_NOT_CONVERGED)
 
 __all__ = ["Context", "SpcgError", "spcg_sketch", "spcg_precond_build", "spcg_precond_from_r",
-           "spcg_pcg_stage", "spcg_solve", "spcg_solve_batched", "spcg_sketch_tables_host", "mat",
-           "load"]
+           "spcg_pcg_stage", "spcg_solve", "spcg_solve_batched", "spcg_sketch_tables_host",
+           "spcg_mlp_forward", "spcg_mlp_loss_grad", "spcg_mlp_adam", "mat", "load"]
 
 _DTYPES = {
     torch.float64: SPCG_F64,
@@ -223,7 +223,12 @@ def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, 
 
 
 def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, growth=2,
-               qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None):
+               qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None,
+               stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
+               record_features=False):
+    """spcg_solve_opts from keyword arguments.  schedule='learned' needs
+    ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
+    ``schedule.load_weights``)."""
     o = L.SolveOpts()
     ctx_lib = load()
     ctx_lib.spcg_solve_opts_default(ctypes.byref(o))
@@ -232,6 +237,16 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every
     o.time_phases, o.time_products = int(time_phases), int(time_products)
+    o.stage_stride = stage_stride
+    o.schedule = L.SPCG_SCHEDULE_LEARNED if schedule in ("learned", L.SPCG_SCHEDULE_LEARNED) else L.SPCG_SCHEDULE_PLAIN
+    if schedule not in ("plain", "learned", 0, 1):
+        raise ValueError(f"unknown schedule {schedule!r}")
+    if weights is not None:
+        if weights.dtype != torch.float32 or not weights.is_cuda or weights.numel() != L.SPCG_MLP_PARAMS:
+            raise ValueError("weights must be a float32 device tensor of SPCG_MLP_PARAMS entries")
+        o.schedule_weights = weights.data_ptr()
+    o.schedule_margin = schedule_margin
+    o.record_features = int(record_features)
     keep = None
     if a_list is not None:
         keep = (ctypes.c_int32 * len(a_list))(*a_list)
@@ -254,9 +269,17 @@ def spcg_solve(ctx, X, Y, beta=None, col_scale=None, **kw):
     rc = ctx.check(ctx.lib.spcg_solve(ctx.h, ctypes.byref(Xm), ctypes.byref(Ym), ctypes.byref(o),
                                       ctypes.c_void_p(beta.data_ptr()), ctypes.byref(st)))
     del keep
-    stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_}
+    stats = _stats_dict(st)
     stats["rc"] = rc
     return beta, stats
+
+
+def _stats_dict(st):
+    out = {}
+    for f, _ in L.SolveStats._fields_:
+        v = getattr(st, f)
+        out[f] = list(v) if isinstance(v, ctypes.Array) else v
+    return out
 
 
 def spcg_solve_batched(ctx, Xs, Ys, betas=None, **kw):
@@ -275,7 +298,7 @@ def spcg_solve_batched(ctx, Xs, Ys, betas=None, **kw):
     del keep
     stats = []
     for i in range(n):
-        d = {f: getattr(st[i], f) for f, _ in L.SolveStats._fields_}
+        d = _stats_dict(st[i])
         d["rc"] = rc
         stats.append(d)
     return betas, stats
@@ -295,3 +318,55 @@ def spcg_sketch_tables_host(seed, L_bits, m, r):
         raise SpcgError(rc, "spcg_sketch_tables_host failed")
     return {"slot_rows": slot[:m], "hat_rows": hat[:r], "input_perm": perm,
             "sign_bits": sign[:np_ // 8]}
+
+
+# ------------------------------------------------------------ schedule network
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_f32(t, numel, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name}: expected a contiguous float32 device tensor of {numel} entries")
+
+
+def spcg_mlp_forward(ctx, W, feats, out=None):
+    """Network outputs (n x 7) for features (n x 8), both float32 on the device."""
+    n = feats.shape[0]
+    _check_f32(W, L.SPCG_MLP_PARAMS, "W")
+    _check_f32(feats, n * L.SPCG_MLP_F, "feats")
+    if out is None:
+        out = torch.empty(n, L.SPCG_MLP_O, dtype=torch.float32, device=feats.device)
+    _check_f32(out, n * L.SPCG_MLP_O, "out")
+    ctx.check(ctx.lib.spcg_mlp_forward(ctx.h, _ptr(W), _ptr(feats), n, _ptr(out)))
+    return out
+
+
+def spcg_mlp_loss_grad(ctx, W, feats, a_label, g_label, s_label, w_a, w_s, grad=None, loss=None):
+    """(grad, loss) of the mean schedule loss; every argument a device tensor
+    (labels int32, the rest float32)."""
+    n = feats.shape[0]
+    _check_f32(W, L.SPCG_MLP_PARAMS, "W")
+    _check_f32(feats, n * L.SPCG_MLP_F, "feats")
+    for t, name in ((s_label, "s_label"), (w_a, "w_a"), (w_s, "w_s")):
+        _check_f32(t, n, name)
+    for t, name in ((a_label, "a_label"), (g_label, "g_label")):
+        if t.dtype != torch.int32 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous int32 device tensor of {n} entries")
+    if grad is None:
+        grad = torch.empty(L.SPCG_MLP_PARAMS, dtype=torch.float32, device=W.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=W.device)
+    ctx.check(ctx.lib.spcg_mlp_loss_grad(ctx.h, _ptr(W), _ptr(feats), _ptr(a_label), _ptr(g_label),
+                                         _ptr(s_label), _ptr(w_a), _ptr(w_s), n, _ptr(grad), _ptr(loss)))
+    return grad, loss
+
+
+def spcg_mlp_adam(ctx, W, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on W (in place), moments m and v updated in place."""
+    n = W.numel()
+    for t, name in ((W, "W"), (grad, "grad"), (m, "m"), (v, "v")):
+        _check_f32(t, n, name)
+    ctx.check(ctx.lib.spcg_mlp_adam(ctx.h, _ptr(W), _ptr(grad), _ptr(m), _ptr(v), n, step, lr, beta1,
+                                    beta2, eps))

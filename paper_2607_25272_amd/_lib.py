@@ -23,6 +23,12 @@ SPCG_E_NOMEM = -7
 
 SPCG_F64, SPCG_F32, SPCG_BF16, SPCG_FP8E4M3 = 0, 1, 2, 3
 SPCG_METHOD_SPCG, SPCG_METHOD_FULL_PCG = 0, 1
+SPCG_SCHEDULE_PLAIN, SPCG_SCHEDULE_LEARNED = 0, 1
+SPCG_MLP_F, SPCG_MLP_H, SPCG_MLP_O = 8, 64, 7
+SPCG_MLP_PARAMS = (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H
+                   + SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
+SPCG_MLP_S_SCALE = 10.0
+SPCG_MLP_LAMBDA = 0.5
 
 c_i32, c_i64, c_u64, c_f64, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -62,7 +68,9 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("sketch", SketchOpts), ("precond", PrecondOpts), ("method", c_i32),
                 ("a", c_i32), ("T", c_i32), ("check_every", c_i32), ("tol", c_f64),
                 ("a_list", ctypes.POINTER(c_i32)), ("a_list_len", c_i32),
-                ("time_phases", c_i32), ("time_products", c_i32), ("reserved", c_i32)]
+                ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
+                ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
+                ("record_features", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -70,7 +78,12 @@ class SolveStats(ctypes.Structure):
                 ("qr_passes", c_i32), ("product_launches", c_i32), ("rho_final", c_f64),
                 ("ax_norm", c_f64), ("t_sketch_ms", c_f64), ("t_precond_ms", c_f64),
                 ("t_stage1_ms", c_f64), ("t_stage2_ms", c_f64), ("t_total_ms", c_f64),
-                ("product_ms_sum", c_f64), ("product_bytes", c_f64)]
+                ("product_ms_sum", c_f64), ("product_bytes", c_f64), ("host_syncs", c_i32),
+                ("policy_a", c_i32), ("policy_stride", c_i32), ("unchecked_iters", c_i32),
+                ("fallback", c_i32), ("s_pred", ctypes.c_float), ("rho_ii0", c_f64),
+                ("ax2_ii0", c_f64), ("resid2_ii0", c_f64), ("features_pre", ctypes.c_float * 8),
+                ("features_ii", ctypes.c_float * 8), ("out_pre", ctypes.c_float * 8),
+                ("out_ii", ctypes.c_float * 8)]
 
 
 P = ctypes.POINTER
@@ -96,6 +109,10 @@ SIGNATURES = [
     ("spcg_solve_batched", c_i32, [c_vp, ctypes.c_int, P(SpcgMat), P(SpcgMat), P(SolveOpts), P(c_vp),
                                    P(SolveStats)]),
     ("spcg_solve_opts_default", None, [P(SolveOpts)]),
+    ("spcg_mlp_forward", c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp]),
+    ("spcg_mlp_loss_grad", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]),
+    ("spcg_mlp_adam", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_float]),
 ]
 
 _lib = None

@@ -70,6 +70,9 @@ struct spcg_ctx {
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
     DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w, dense_wd, dense_tmp;
     int64_t dense_w_elems = 0;
+    // learned schedule: features and network outputs (4 x 8 floats), gradient partials
+    DevBuf sched, mlp_part;
+    int syncs = 0;   // stream synchronisations of the current solve
     // events for timing
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
@@ -269,6 +272,7 @@ int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, D
                                 ctx->dense_w.as<double>(), ctx->dense_w_elems));
     HIP_TRY(ctx, hipMemcpyAsync(host, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
+    ctx->syncs++;
     return SPCG_OK;
 }
 
@@ -432,6 +436,7 @@ int ensure_stage_ws(spcg_ctx* ctx, int64_t d, DspaceState* S, double* x, const d
 int read_scalars(spcg_ctx* ctx, const DspaceState& S, PcgScalars* out) {
     HIP_TRY(ctx, hipMemcpyAsync(out, S.sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->syncs++;
     return SPCG_OK;
 }
 
@@ -475,10 +480,28 @@ int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const Dspa
     return SPCG_OK;
 }
 
+// Work done at the start of a tested stage for the schedule network:
+// Stage II features (when fpre is set) and, with weights, the network's
+// prediction of the iteration count; both come back with the first test.
+struct StageHooks {
+    const float* fpre = nullptr;   // device: pre-Stage-I features
+    float* fii = nullptr;          // device: Stage II features (8)
+    const float* W = nullptr;      // device: network weights (learned schedule)
+    float* out = nullptr;          // device: network outputs (8)
+    int margin = 1;
+    // results
+    float host_fii[8] = {};
+    float host_out[8] = {};
+    double s_pred = 0.0;
+    int unchecked = 0;
+    bool fallback = false;
+    PcgScalars start{};
+};
+
 // PCG(A, b, c2, M, x, iters) with optional stopping test; x is device memory.
 int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const spcg_precond_t* pc,
               double* x, int iters, double tol, bool refresh, int check_every, StageRun* out,
-              ProductTimer* timer) {
+              ProductTimer* timer, StageHooks* hooks = nullptr) {
     int rc;
     DspaceState S{};
     if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
@@ -494,12 +517,30 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
     if (check_every < 1) check_every = 1;
     out->iters_done = 0;
     out->converged = false;
+    int unchecked = 0;
     if (testing) {
+        if (hooks && hooks->fpre) {
+            HIP_TRY(ctx, run_features_ii(st, hooks->fpre, S.sc, tol, hooks->fii));
+            HIP_TRY(ctx, hipMemcpyAsync(hooks->host_fii, hooks->fii, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
+            if (hooks->W) {
+                HIP_TRY(ctx, run_mlp_forward(st, hooks->W, hooks->fii, 1, hooks->out));
+                HIP_TRY(ctx,
+                        hipMemcpyAsync(hooks->host_out, hooks->out, MLP_O * sizeof(float), hipMemcpyDeviceToHost, st));
+            }
+        }
         if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
+        if (hooks) hooks->start = out->sc;
         if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown at stage start");
         if (stop_test(out->sc, tol)) {
             out->converged = true;
             return SPCG_OK;
+        }
+        if (hooks && hooks->W) {
+            hooks->s_pred = (double)hooks->host_out[6] * MLP_S_SCALE;
+            const double rs = std::isfinite(hooks->s_pred) ? std::round(hooks->s_pred) : 0.0;
+            const double k = std::min(std::max(rs - (double)hooks->margin, 0.0), (double)iters);
+            unchecked = (int)k;
+            hooks->unchecked = unchecked;
         }
     }
     const int pmode = refresh ? PM_SG : PM_S;
@@ -509,13 +550,15 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
                                  ctx->part_g.as<double>(), ctx->part_scal.as<double>(), np, dpad, c2));
         HIP_TRY(ctx, run_phase_b(st, S, 0));
         out->iters_done = it + 1;
-        if (testing && ((it + 1) % check_every == 0 || it + 1 == iters)) {
+        const int done = it + 1;
+        if (testing && done >= unchecked && ((done - unchecked) % check_every == 0 || done == iters)) {
             if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
             if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown: p^T s <= 0 or non-finite");
             if (stop_test(out->sc, tol)) {
                 out->converged = true;
                 return SPCG_OK;
             }
+            if (hooks && unchecked > 0 && done == unchecked) hooks->fallback = true;
         }
     }
     if (!testing) {
@@ -1054,6 +1097,8 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
 int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y,
                        const spcg_solve_opts* opts, double* const* beta, spcg_solve_stats* stats) {
     if (!ctx) return SPCG_E_INVALID_ARG;
+    if (opts && opts->schedule != SPCG_SCHEDULE_PLAIN)
+        return fail(ctx, SPCG_E_INVALID_ARG, "the batched form runs the plain schedule only");
     return batched_solve(ctx, nprob, X, Y, opts, beta, stats);
 }
 
@@ -1079,21 +1124,31 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if (Y->dtype != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "Y must be SPCG_F64");
     if (Y->rows != X->rows) return fail(ctx, SPCG_E_SHAPE, "X and Y row counts differ");
     if (Y->cols > 1) {
+        if (opts->schedule != SPCG_SCHEDULE_PLAIN)
+            return fail(ctx, SPCG_E_INVALID_ARG, "the learned schedule takes one right-hand side");
         double* const b1[1] = {beta};
         return batched_solve(ctx, 1, X, Y, opts, b1, stats);
     }
     if (opts->method != SPCG_METHOD_SPCG && opts->method != SPCG_METHOD_FULL_PCG)
         return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
     if (opts->a < 0 || opts->T < 0 || opts->tol < 0.0 || opts->a_list_len < 0 ||
-        (opts->a_list_len > 0 && !opts->a_list))
+        (opts->a_list_len > 0 && !opts->a_list) || opts->stage_stride < 0 || opts->stage_stride > 2)
         return fail(ctx, SPCG_E_INVALID_ARG, "bad solve options");
-    const int a = opts->a > 0 ? opts->a : 3;
+    const bool learned = opts->schedule == SPCG_SCHEDULE_LEARNED;
+    if (opts->schedule != SPCG_SCHEDULE_PLAIN && !learned)
+        return fail(ctx, SPCG_E_INVALID_ARG, "unknown schedule %d", opts->schedule);
+    if (learned && (!opts->schedule_weights || opts->method != SPCG_METHOD_SPCG))
+        return fail(ctx, SPCG_E_INVALID_ARG, "the learned schedule needs weights and method SPCG");
+    const bool features = learned || opts->record_features;
+    int a = opts->a > 0 ? opts->a : 3;
+    int stride = opts->stage_stride > 0 ? opts->stage_stride : 1;
     const int T = opts->T > 0 ? opts->T : 100;
     const double tol = opts->tol > 0.0 ? opts->tol : 5e-7;
     const bool timing = opts->time_phases != 0;
     if (timing || opts->time_products) {
         if ((rc = ensure_events(ctx)) != SPCG_OK) return rc;
     }
+    ctx->syncs = 0;
     hipStream_t st = ctx->stream;
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
     spcg_sketch_opts so = opts->sketch;
@@ -1103,22 +1158,46 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
     spcg_precond_t pc;
     if ((rc = precond_build(ctx, &sk, &opts->precond, true, &pc)) != SPCG_OK) return rc;
-    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
     const int64_t d = X->cols;
+    float* sched = nullptr;
+    float host_fpre[8] = {}, host_out_pre[8] = {};
+    if (features) {
+        HIP_TRY(ctx, ctx->sched.ensure(32 * sizeof(float)));
+        sched = ctx->sched.as<float>();
+        HIP_TRY(ctx, run_features_pre(st, X->data, X->dtype, X->rows, d, X->ld, X->col_scale, pc.pR, d, sched));
+        HIP_TRY(ctx, hipMemcpyAsync(host_fpre, sched, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    if (learned) {
+        // decision 1: Stage I iteration count and prefix stride
+        HIP_TRY(ctx, run_mlp_forward(st, opts->schedule_weights, sched, 1, sched + 16));
+        HIP_TRY(ctx, hipMemcpyAsync(host_out_pre, sched + 16, MLP_O * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        ctx->syncs++;
+        int ia = 0;
+        for (int i = 1; i < 4; ++i)
+            if (host_out_pre[i] > host_out_pre[ia]) ia = i;
+        a = ia + 1;
+        stride = host_out_pre[5] > host_out_pre[4] ? 2 : 1;
+    }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
     DspaceState S{};
     if ((rc = ensure_stage_ws(ctx, d, &S, beta, pc.pMinv)) != SPCG_OK) return rc;
     HIP_TRY(ctx, run_scalars_reset(st, S.sc));
     HIP_TRY(ctx, run_fill(st, beta, d, 0.0));
-    // Stage I
-    int t1 = 0;
-    for (int64_t i = 0; i < sk.K; ++i) {
+    // Stage I over the prefixes K-1, K-1-stride, ... in increasing order
+    std::vector<int64_t> stages;
+    for (int64_t i = sk.K - 1; i >= 0; i -= stride) stages.push_back(i);
+    std::reverse(stages.begin(), stages.end());
+    int t1 = 0, a_used = a;
+    for (size_t si = 0; si < stages.size(); ++si) {
         int ai = a;
-        if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
+        if (!learned && opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(si, opts->a_list_len - 1)];
         if (ai < 0) return fail(ctx, SPCG_E_INVALID_ARG, "negative a_i");
         if (t1 + ai > T) ai = std::max(0, T - t1);
+        a_used = ai;
         spcg_mat A{}, b{};
         double c2 = 1.0;
-        spcg_sketch_view(&sk, (int)i, &A, &b, &c2);
+        spcg_sketch_view(&sk, (int)stages[si], &A, &b, &c2);
         if ((rc = stage_run_nosync(ctx, &A, &b, c2, &pc, beta, ai)) != SPCG_OK) return rc;
         t1 += ai;
     }
@@ -1127,14 +1206,24 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     ProductTimer timer;
     timer.ctx = ctx;
     StageRun run;
+    StageHooks hooks;
+    if (features) {
+        hooks.fpre = sched;
+        hooks.fii = sched + 8;
+    }
+    if (learned) {
+        hooks.W = opts->schedule_weights;
+        hooks.out = sched + 24;
+        hooks.margin = opts->schedule_margin == 0 ? 1 : std::max(0, opts->schedule_margin);
+    }
     rc = stage_run(ctx, X, Y, 1.0, &pc, beta, std::max(0, T - t1), tol, true, opts->check_every, &run,
-                   opts->time_products ? &timer : nullptr);
+                   opts->time_products ? &timer : nullptr, &hooks);
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[4], st));
     if (rc != SPCG_OK && rc != SPCG_E_BREAKDOWN) return rc;
     const int rc_stage = rc;
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
-        stats->K = (int32_t)sk.K;
+        stats->K = (int32_t)stages.size();
         stats->T_stage1 = t1;
         stats->T_stage2 = run.iters_done;
         stats->converged = run.converged;
@@ -1143,7 +1232,24 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
         const int64_t es = dtype_bytes(X->dtype);
         stats->product_bytes = (double)X->rows * X->cols * es + (double)X->rows * 8.0;
-        if (timing || opts->time_products) HIP_TRY(ctx, hipStreamSynchronize(st));
+        stats->policy_a = a_used;
+        stats->policy_stride = stride;
+        stats->unchecked_iters = hooks.unchecked;
+        stats->fallback = hooks.fallback ? 1 : 0;
+        stats->s_pred = (float)hooks.s_pred;
+        stats->rho_ii0 = hooks.start.rho;
+        stats->ax2_ii0 = hooks.start.ax2;
+        stats->resid2_ii0 = hooks.start.resid2;
+        if (timing || opts->time_products) {
+            HIP_TRY(ctx, hipStreamSynchronize(st));
+        }
+        stats->host_syncs = ctx->syncs;
+        for (int i = 0; i < 8; ++i) {
+            stats->features_pre[i] = host_fpre[i];
+            stats->features_ii[i] = hooks.host_fii[i];
+            stats->out_pre[i] = host_out_pre[i];
+            stats->out_ii[i] = hooks.host_out[i];
+        }
         if (timing) {
             stats->t_sketch_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[1]);
             stats->t_precond_ms = elapsed_ms(ctx->ev_phase[1], ctx->ev_phase[2]);
@@ -1163,6 +1269,40 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         fail(ctx, SPCG_W_NOT_CONVERGED, "Stage II did not meet tol=%g within T=%d", tol, T);
         return SPCG_W_NOT_CONVERGED;
     }
+    return SPCG_OK;
+}
+
+// ---------------------------------------------------- schedule network
+
+int spcg_mlp_forward(spcg_ctx* ctx, const float* W, const float* feats, int64_t n, float* out) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!W || !feats || !out))) return fail(ctx, SPCG_E_INVALID_ARG, "bad network arguments");
+    HIP_TRY(ctx, run_mlp_forward(ctx->stream, W, feats, n, out));
+    return SPCG_OK;
+}
+
+int spcg_mlp_loss_grad(spcg_ctx* ctx, const float* W, const float* feats, const int32_t* a_label,
+                       const int32_t* g_label, const float* s_label, const float* w_a, const float* w_s, int64_t n,
+                       float* grad, float* loss) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    if (n < 0 || !W || !grad || (n > 0 && (!feats || !a_label || !g_label || !s_label || !w_a || !w_s)))
+        return fail(ctx, SPCG_E_INVALID_ARG, "bad network arguments");
+    const int nb = mlp_grad_blocks(n);
+    HIP_TRY(ctx, ctx->mlp_part.ensure((size_t)nb * (MLP_PARAMS + 1) * sizeof(float)));
+    HIP_TRY(ctx, run_mlp_loss_grad(ctx->stream, W, feats, n, a_label, g_label, s_label, w_a, w_s,
+                                   ctx->mlp_part.as<float>(), grad, loss));
+    return SPCG_OK;
+}
+
+int spcg_mlp_adam(spcg_ctx* ctx, float* W, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                  float lr, float beta1, float beta2, float eps) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    if (n < 0 || step < 1 || (n > 0 && (!W || !grad || !m || !v)) || !(beta1 >= 0.f && beta1 < 1.f) ||
+        !(beta2 >= 0.f && beta2 < 1.f))
+        return fail(ctx, SPCG_E_INVALID_ARG, "bad Adam arguments");
+    const double c1 = 1.0 - std::pow((double)beta1, (double)step);
+    const double c2 = 1.0 - std::pow((double)beta2, (double)step);
+    HIP_TRY(ctx, run_adam(ctx->stream, W, grad, m, v, n, lr, beta1, beta2, eps, (float)c1, (float)c2));
     return SPCG_OK;
 }
 

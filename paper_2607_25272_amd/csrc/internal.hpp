@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "common.hpp"
+#include "spcg.h"
 
 namespace spcg {
 
@@ -182,5 +183,24 @@ hipError_t dense_convert(hipStream_t st, const void* src, int src_f32, int64_t r
                          int64_t lds, double scale, double* dst, int64_t ldd);
 hipError_t dense_add_trace_shift(hipStream_t st, double* G, int64_t d, double factor);
 hipError_t dense_status_reset(hipStream_t st, DenseStatus* status);
+
+// ------------------------------------------------------ learned schedule
+constexpr int MLP_F = SPCG_MLP_F, MLP_H = SPCG_MLP_H, MLP_O = SPCG_MLP_O;
+constexpr int MLP_PARAMS = SPCG_MLP_PARAMS;
+constexpr double MLP_S_SCALE = SPCG_MLP_S_SCALE;
+constexpr double MLP_LAMBDA = SPCG_MLP_LAMBDA;
+constexpr int MLP_SAMPLE_ROWS = 256;
+// Partial-gradient blocks used for n samples (each holds MLP_PARAMS + 1 floats).
+int mlp_grad_blocks(int64_t n);
+hipError_t run_mlp_forward(hipStream_t st, const float* W, const float* feats, int64_t n, float* out);
+hipError_t run_mlp_loss_grad(hipStream_t st, const float* W, const float* feats, int64_t n, const int32_t* la,
+                             const int32_t* lg, const float* ls, const float* wa, const float* ws, float* partial,
+                             float* grad, float* loss);
+// One Adam step; c1 = 1 - b1^t and c2 = 1 - b2^t are the bias corrections.
+hipError_t run_adam(hipStream_t st, float* W, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                    float b2, float eps, float c1, float c2);
+hipError_t run_features_pre(hipStream_t st, const void* X, int dtype, int64_t N, int64_t d, int64_t ld,
+                            const float* col_scale, const double* R, int64_t ldr, float* f);
+hipError_t run_features_ii(hipStream_t st, const float* fpre, const PcgScalars* sc, double tol, float* f);
 
 }  // namespace spcg

@@ -27,7 +27,7 @@ def lib():
     return spcg.load()
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_boundary_entry_points():
     names = _declared_functions()
     for required in ("spcg_sketch", "spcg_precond_build", "spcg_pcg_stage", "spcg_solve"):
         assert required in names
@@ -78,3 +78,42 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     lib.spcg_solve_opts_default(ctypes.byref(o))
     assert (o.a, o.T, o.sketch.seed, o.sketch.growth) == (3, 100, 1, 2)
     assert abs(o.tol - 5e-7) < 1e-20
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler
+    gives the header's structs."""
+    import subprocess
+
+    from paper_2607_25272_amd import _lib
+    structs = {"spcg_mat": _lib.SpcgMat, "spcg_sketch_opts": _lib.SketchOpts,
+               "spcg_sketch_info": _lib.SketchInfo, "spcg_precond_opts": _lib.PrecondOpts,
+               "spcg_stage_opts": _lib.StageOpts, "spcg_stage_stats": _lib.StageStats,
+               "spcg_solve_opts": _lib.SolveOpts, "spcg_solve_stats": _lib.SolveStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spcg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_schedule_constants_match_the_oracle():
+    from oracle import mlp
+    from paper_2607_25272_amd import _lib
+    assert (_lib.SPCG_MLP_F, _lib.SPCG_MLP_H, _lib.SPCG_MLP_O) == (mlp.F, mlp.H, mlp.O)
+    assert _lib.SPCG_MLP_PARAMS == mlp.n_params()
+    assert _lib.SPCG_MLP_S_SCALE == mlp.S_SCALE and _lib.SPCG_MLP_LAMBDA == mlp.LAMBDA

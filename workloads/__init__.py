@@ -191,6 +191,29 @@ def batched(n_prob=256, N_range=(50_000, 500_000), d_range=(32, 512), cond_range
     return probs
 
 
+def schedule_training_problem(i, device="cpu", seed=BASE_SEED + 4, storage="f32"):
+    """Problem ``i`` of the schedule network's training distribution:
+    N log-uniform in [1e4, 1e6], d log-uniform in [16, 512], condition
+    log-uniform in [1e1, 1e6], noise sigma log-uniform in [1e-3, 1], rows
+    Gaussian with column scales or Student-t (3 d.o.f.) times a correlation
+    factor, with equal probability."""
+    g = generator("cpu", seed * 100003 + i)
+    u = torch.rand(5, generator=g, dtype=torch.float64).tolist()
+    N = int(round(10 ** (4 + 2 * u[0])))
+    d = int(round(2 ** (4 + 5 * u[1])))
+    cond = 10 ** (1 + 5 * u[2])
+    sigma = 10 ** (-3 + 3 * u[4])
+    pseed = seed * 1000 + i
+    if u[3] < 0.5:
+        p = gauss_colscale(N, d, cond, sigma, storage=storage, seed=pseed, device=device,
+                           name=f"train_{i}")
+    else:
+        p = t3_corr(N, d, cond, sigma, storage=storage, seed=pseed, device=device)
+        p.name = f"train_{i}"
+    p.meta.update({"rows": "gauss" if u[3] < 0.5 else "t3", "sigma": sigma, "index": i})
+    return p
+
+
 CONFIGS = {
     0: dict(kind="haar_svd", N=20000, d=50, cond=1e3, sigma=0.1, storage="f64"),
     1: dict(kind="gauss_colscale", N=1_000_000, d=500, cond=1e4, sigma=1.0, storage="f32"),
