@@ -1084,7 +1084,7 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
         stats->rho0 = run.sc.rho0;
         stats->rho = run.sc.rho;
         stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
-        stats->resid_norm2 = run.sc.resid2;
+        stats->resid_norm2 = run.sc.resid2_0;
     }
     if (rc != SPCG_OK) return rc;
     if (opts->tol > 0.0 && !run.converged) {

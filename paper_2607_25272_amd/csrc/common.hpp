@@ -51,6 +51,44 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// ---- full-wave sums through DPP (no LDS round trips) ----------------------
+// Sum over the 64 lanes, returned uniformly: row_shr 1, 2, 4, 8 leave each
+// 16-lane row's total in its lane 15 (lanes shifted in from outside the
+// row read 0), row_bcast 15 / 31 fold the rows into lane 63, and readlane
+// broadcasts it.  The order of the additions is fixed.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, true);
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += __uint_as_float(dpp_u32<0x111>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x112>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x114>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x118>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x142, 0xa>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_u32<0x143, 0xc>(__float_as_uint(v)));
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
+}
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp_u32<CTRL, ROWMASK>((uint32_t)u);
+    const uint32_t hi = dpp_u32<CTRL, ROWMASK>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0x111>(v);
+    v += dpp_f64<0x112>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    v += dpp_f64<0x142, 0xa>(v);
+    v += dpp_f64<0x143, 0xc>(v);
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

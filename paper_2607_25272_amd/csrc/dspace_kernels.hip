@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
         }
         do_step = 0;
         if (a.variant == PA_START) {
+            sc->resid2_0 = sh_r[0] * a.c2;
             sc->exact = 0;
         } else {
             double pts = 0.0;
@@ -253,6 +254,7 @@ __global__ void scalars_reset_kernel(PcgScalars* sc) {
     sc->resid2 = 0.0;
     sc->ax2 = 0.0;
     sc->rho0 = 0.0;
+    sc->resid2_0 = 0.0;
     sc->exact = 0;
     sc->breakdown = 0;
     sc->iters = 0;

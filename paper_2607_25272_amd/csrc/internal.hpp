@@ -80,6 +80,7 @@ struct PcgScalars {
     double resid2;    // c2 ||b - A x||^2 from the last G/SG pass
     double ax2;       // c2 ||A x||^2 from the last G/SG pass
     double rho0;
+    double resid2_0;  // c2 ||b - A x||^2 at the stage start
     int32_t exact;    // rho reached exactly zero in this stage
     int32_t breakdown;// sticky: p^T s <= 0 or non-finite
     int32_t iters;

@@ -194,11 +194,14 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
         for (int e = 0; e < VEC; ++e) {
             const int i = s * VEC + e;
             const int col = (lir + s * LPR) * VEC + e;
+            // unconditional (clamped) loads: issued together, one wait
+            const int cc = min(col, d - 1);
             const bool ok = col < d;
-            double sc = 1.0;
-            if (FP8 && ok) sc = (double)a.col_scale[col];
-            preg[i] = (DO_S && ok) ? (CT)(a.p[col] * sc) : CT(0);
-            xreg[i] = (DO_G && ok) ? a.x[col] * sc : 0.0;
+            const double sc = FP8 ? (double)a.col_scale[cc] : 1.0;
+            const double pv = DO_S ? a.p[cc] * sc : 0.0;
+            const double xv = DO_G ? a.x[cc] * sc : 0.0;
+            preg[i] = ok ? (CT)pv : CT(0);
+            xreg[i] = ok ? xv : 0.0;
             sacc[i] = CT(0);
             gacc[i] = 0.0;
         }
@@ -247,10 +250,12 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
                 if (DO_S) dp = fma(v[i], preg[i], dp);
                 if (DO_G) dx = fma((double)v[i], xreg[i], dx);
             }
-            if (DO_S) dp = group_sum<LPR>(dp);
+            if constexpr (DO_S) {
+                if constexpr (LPR == 64) dp = wave_sum(dp); else dp = group_sum<LPR>(dp);
+            }
             double w = 0.0;
             if (DO_G) {
-                dx = group_sum<LPR>(dx);
+                if constexpr (LPR == 64) dx = wave_sum(dx); else dx = group_sum<LPR>(dx);
                 const double bb = valid ? a.b[row * a.ldbv] : 0.0;
                 w = valid ? bb - dx : 0.0;
                 if (lir == 0 && valid) {
@@ -319,6 +324,234 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
     }
 }
 
+// ---- LDS-staged variant for rows of more than 32 vectors ------------------
+//
+// Rows stream through a ring of RING LDS tiles that direct global->LDS
+// loads (global_load_lds_dword / _dwordx4) fill; a tile holds NW rows, one
+// per wave.  While a wave works on tile t, the loads of tiles t+1 .. t+RING-1
+// are in flight without occupying registers, so about (RING-1) * NW rows per
+// CU are outstanding whatever the row width (registers only hold the
+// column accumulators).  Every wave issues the same loads per tile (rows
+// past the block's range and vectors past the row are clamped to valid
+// addresses and ignored), so an explicit vmcnt wait covers exactly the
+// loads of the tile about to be read, and the s_barrier that follows makes
+// the whole tile visible and frees the slot refilled next.  Each ring slot
+// is a separate LDS object, so the compiler's own waits for the loads into
+// one slot do not hold back reads of another.  In G/SG mode the FP64 b of
+// each row rides along as a 4-byte-per-lane load.
+constexpr int RING = 4;
+constexpr int vmcnt_imm(int n) { return (n & 0xf) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8); }
+
+template <int DMAB>
+__device__ __forceinline__ void lds_load(const void* src, void* lds) {
+    void* g = const_cast<void*>(src);
+    auto* l = (__attribute__((address_space(3))) void*)(lds);
+    if constexpr (DMAB == 16) {
+        __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+    } else {
+        static_assert(DMAB == 4, "4- or 16-byte loads");
+        __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+    }
+}
+
+template <typename TS, int DMAB, int NSLOT, int MODE>
+__global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
+    typedef typename Store<TS>::CT CT;
+    typedef typename RawVec<DMAB>::T Raw;
+    constexpr int VEC = DMAB / Store<TS>::BYTES;
+    constexpr bool DO_S = MODE != PM_G;
+    constexpr bool DO_G = MODE != PM_S;
+    constexpr bool FP8 = std::is_same<TS, fp8_t>::value;
+    constexpr int NC = NSLOT * VEC;
+    constexpr int DCOLS = NC * 64;
+    constexpr int RW = NSLOT * 64 * DMAB;            // staged bytes of one row
+    constexpr int NOPS = NSLOT + (DO_G ? 1 : 0);    // loads per wave per tile
+    // one slot: NW staged rows, then (G/SG) 256 bytes per wave for b
+    constexpr int SLOT = NW * RW + (DO_G ? NW * 256 : 0);
+    static_assert(DCOLS * 8 <= NW * RW, "reduction buffers alias the ring");
+    static_assert((RING - 2) * NOPS < 64, "vmcnt range");
+    __shared__ __align__(16) unsigned char t0[SLOT];
+    __shared__ __align__(16) unsigned char t1[SLOT];
+    __shared__ __align__(16) unsigned char t2[SLOT];
+    __shared__ __align__(16) unsigned char t3[SLOT];
+    __shared__ double red_scal[2 * NW];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int d = a.d;
+    CT preg[NC];
+    double xreg[NC];
+    CT sacc[NC];
+    double gacc[NC];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int i = s * VEC + e;
+            const int col = (lane + s * 64) * VEC + e;
+            const int cc = min(col, d - 1);
+            const bool ok = col < d;
+            const double sc = FP8 ? (double)a.col_scale[cc] : 1.0;
+            const double pv = DO_S ? a.p[cc] * sc : 0.0;
+            const double xv = DO_G ? a.x[cc] * sc : 0.0;
+            preg[i] = ok ? (CT)pv : CT(0);
+            xreg[i] = ok ? xv : 0.0;
+            sacc[i] = CT(0);
+            gacc[i] = 0.0;
+        }
+    }
+    double r2 = 0.0, ax2 = 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
+    const int64_t r1 = min(a.m, r0 + a.rpb);
+    const int64_t rlast = r1 - 1;   // >= 0: a.m >= 1 and r1 = a.m for blocks past the end
+    const int64_t ntile = r1 > r0 ? (r1 - r0 + NW - 1) / NW : 0;
+    const char* Abase = static_cast<const char*>(a.A);
+    const int64_t row_bytes = a.lda * Store<TS>::BYTES;
+    const int64_t vlast = a.nvec - 1;
+
+    auto issue = [&](int64_t tile, unsigned char* T) {
+        const int64_t row = min(r0 + tile * NW + wave, rlast);
+        const char* src = Abase + row * row_bytes;
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const int64_t vi = min<int64_t>(s * 64 + lane, vlast);
+            lds_load<DMAB>(src + vi * DMAB, T + wave * RW + s * 64 * DMAB);
+        }
+        if constexpr (DO_G) {
+            lds_load<4>(reinterpret_cast<const char*>(a.b + row * a.ldbv) + 4 * (lane & 1), T + NW * RW + wave * 256);
+        }
+    };
+    auto consume = [&](int64_t tile, const unsigned char* T) {
+        const int64_t row = r0 + tile * NW + wave;
+        if (row >= r1) return;
+        CT v[NC];
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+            const Raw raw = *reinterpret_cast<const Raw*>(T + wave * RW + (s * 64 + lane) * DMAB);
+            Widen<TS, VEC, Raw>::run(raw, v + s * VEC);
+        }
+        CT dp = CT(0);
+        double dx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            if (DO_S) dp = fma(v[i], preg[i], dp);
+            if (DO_G) dx = fma((double)v[i], xreg[i], dx);
+        }
+        if (DO_S) dp = wave_sum(dp);
+        double w = 0.0;
+        if constexpr (DO_G) {
+            dx = wave_sum(dx);
+            const double bb = *reinterpret_cast<const double*>(T + NW * RW + wave * 256);
+            w = bb - dx;
+            if (lane == 0) {
+                r2 = fma(w, w, r2);
+                ax2 = fma(dx, dx, ax2);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            if (DO_S) sacc[i] = fma(dp, v[i], sacc[i]);
+            if (DO_G) gacc[i] = fma(w, (double)v[i], gacc[i]);
+        }
+    };
+
+    issue(0, t0);
+    issue(1, t1);
+    issue(2, t2);
+#define SPCG_RING_STEP(CUR, NXT, OFF)                           \
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm((RING - 2) * NOPS)); \
+    __builtin_amdgcn_s_barrier();                             \
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);                  \
+    issue(t + (OFF) + RING - 1, NXT);                         \
+    consume(t + (OFF), CUR);
+    for (int64_t t = 0; t < ntile; t += RING) {
+        SPCG_RING_STEP(t0, t3, 0)
+        SPCG_RING_STEP(t1, t0, 1)
+        SPCG_RING_STEP(t2, t1, 2)
+        SPCG_RING_STEP(t3, t2, 3)
+    }
+#undef SPCG_RING_STEP
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // cross-lane, then fixed wave order into LDS (the ring is free now)
+    double* red_s = reinterpret_cast<double*>(t0);
+    double* red_g = reinterpret_cast<double*>(t1);
+    for (int wv = 0; wv < NW; ++wv) {
+        if (wave == wv) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int col = (lane + s * 64) * VEC + e;
+                    if (col < d) {
+                        const int i = s * VEC + e;
+                        if (DO_S) red_s[col] = (wv == 0 ? 0.0 : red_s[col]) + (double)sacc[i];
+                        if (DO_G) red_g[col] = (wv == 0 ? 0.0 : red_g[col]) + gacc[i];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (DO_G) {
+        if (lane == 0) {
+            red_scal[2 * wave] = r2;
+            red_scal[2 * wave + 1] = ax2;
+        }
+    }
+    __syncthreads();
+    const int64_t prow = (int64_t)blockIdx.x * a.dpad;
+    for (int col = threadIdx.x; col < d; col += 64 * NW) {
+        const double sc = FP8 ? (double)a.col_scale[col] : 1.0;
+        if (DO_S) a.part_s[prow + col] = red_s[col] * sc;
+        if (DO_G) a.part_g[prow + col] = red_g[col] * sc;
+    }
+    if (DO_G && threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int wv = 0; wv < NW; ++wv) {
+            s0 += red_scal[2 * wv];
+            s1 += red_scal[2 * wv + 1];
+        }
+        a.part_scal[2 * blockIdx.x] = s0;
+        a.part_scal[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+template <typename TS, int DMAB, int NSLOT>
+hipError_t launch_ring(hipStream_t st, const ProdArgs& a, int mode, int nblocks) {
+    dim3 grid(nblocks), block(64 * NW);
+    switch (mode) {
+        case PM_S: product_ring_kernel<TS, DMAB, NSLOT, PM_S><<<grid, block, 0, st>>>(a); break;
+        case PM_G: product_ring_kernel<TS, DMAB, NSLOT, PM_G><<<grid, block, 0, st>>>(a); break;
+        default: product_ring_kernel<TS, DMAB, NSLOT, PM_SG><<<grid, block, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+// Ring shapes: 16-byte loads (VEC = 16 / element size) or 4-byte loads, at
+// most 16 columns per lane (d <= 1024 with 16-byte loads).
+template <typename TS>
+hipError_t launch_ring_type(hipStream_t st, const ProdArgs& a, int mode, int nblocks, int dmab, int nslot) {
+    constexpr int B = Store<TS>::BYTES;
+    if (dmab == 16) {
+        if (nslot == 1) return launch_ring<TS, 16, 1>(st, a, mode, nblocks);
+        if constexpr (16 / B * 2 <= 16) {
+            if (nslot == 2) return launch_ring<TS, 16, 2>(st, a, mode, nblocks);
+        }
+        if constexpr (16 / B * 4 <= 16) {
+            if (nslot == 4) return launch_ring<TS, 16, 4>(st, a, mode, nblocks);
+        }
+    }
+    if constexpr (B <= 4) {
+        if (dmab == 4) {
+            if (nslot == 1) return launch_ring<TS, 4, 1>(st, a, mode, nblocks);
+            if (nslot == 2) return launch_ring<TS, 4, 2>(st, a, mode, nblocks);
+            if (nslot == 4) return launch_ring<TS, 4, 4>(st, a, mode, nblocks);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 // rows in flight per wave: enough to keep ~64 KB of loads outstanding per
 // CU with 16 resident waves, without spilling (the SG mode holds both
 // products' operands and accumulators)
@@ -381,6 +614,48 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
     const int bytes = dtype_bytes(j.dtype);
     if (bytes == 0 || j.d < 1 || j.m < 0) return hipErrorInvalidValue;
     if (j.m == 0) return hipSuccess;
+    // LDS-staged kernel for rows of more than 32 load vectors
+    for (int dmab : {16, 4}) {
+        if (dmab < bytes) continue;
+        const int rv = dmab / bytes;
+        const int64_t nv = ceil_div(j.d, rv);
+        const bool ok = (j.lda * bytes) % dmab == 0 && (uintptr_t)j.A % dmab == 0 && nv * rv <= j.dmem &&
+                        (j.mode == PM_S || j.ldbv >= 1);
+        if (!ok) continue;
+        if (nv <= 32 || nv > 256) break;
+        int ns = 1;
+        while (ns * 64 < nv) ns <<= 1;
+        if (ns * rv > 16) break;
+        int64_t nb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(j.m, NW * 4), product_max_blocks(j.num_cu)));
+        const int64_t rpb = ceil_div(j.m, nb);
+        nb = ceil_div(j.m, rpb);
+        ProdArgs a{};
+        a.A = j.A;
+        a.m = j.m;
+        a.lda = j.lda;
+        a.rpb = rpb;
+        a.d = (int)j.d;
+        a.nvec = (int)nv;
+        a.col_scale = j.col_scale;
+        a.b = j.b;
+        a.ldbv = j.ldbv;
+        a.x = j.x;
+        a.p = j.p;
+        a.part_s = j.part_s;
+        a.part_g = j.part_g;
+        a.part_scal = j.part_scal;
+        a.dpad = j.dpad;
+        hipError_t e;
+        switch (j.dtype) {
+            case DT_F64: e = launch_ring_type<double>(st, a, j.mode, (int)nb, dmab, ns); break;
+            case DT_F32: e = launch_ring_type<float>(st, a, j.mode, (int)nb, dmab, ns); break;
+            case DT_BF16: e = launch_ring_type<bf16_t>(st, a, j.mode, (int)nb, dmab, ns); break;
+            case DT_FP8: e = launch_ring_type<fp8_t>(st, a, j.mode, (int)nb, dmab, ns); break;
+            default: e = hipErrorInvalidValue;
+        }
+        if (e == hipSuccess) *nblocks_out = (int)nb;
+        return e;
+    }
     int vec = 16 / bytes;
     int64_t nvec = ceil_div(j.d, vec);
     const bool aligned = (j.lda % vec == 0) && ((uintptr_t)j.A % 16 == 0) && (nvec * vec <= j.dmem);
