@@ -282,8 +282,12 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
  * per problem.  Requirements: X[p] SPCG_F32 or SPCG_BF16 (all the same),
  * d <= 512, 1 <= k <= 16 right-hand sides (Y[p] is N x k SPCG_F64), beta[p]
  * DEVICE d x k row-major FP64.  Products accumulate in FP32.  stats may be
- * NULL or an array of nprob entries.  Returns the worst code over the
- * problems (W_NOT_CONVERGED if any problem missed tol within T). */
+ * NULL or an array of nprob entries.  With opts.time_products, stats[0]
+ * holds the launches timed (the full-data product passes of Stage II), their
+ * summed duration and, in product_bytes, their summed algorithmic bytes
+ * (sum over the active problems of m (d elem + 8 k) per launch).  Returns the
+ * worst code over the problems (W_NOT_CONVERGED if any problem missed tol
+ * within T). */
 int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y,
                        const spcg_solve_opts* opts, double* const* beta, spcg_solve_stats* stats);
 

@@ -648,7 +648,7 @@ int build_tasks(const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks
 }
 
 int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, const std::vector<MrhsProblem>& hp,
-                 int64_t rows_per_task) {
+                 int64_t rows_per_task, ProductTimer* timer = nullptr) {
     std::vector<MrhsTask> tasks;
     std::vector<MrhsProblem> probs;
     const int nt = build_tasks(hp, tasks, probs, rows_per_task);
@@ -662,8 +662,14 @@ int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, 
     if (nt)
         HIP_TRY(ctx, hipMemcpyAsync(W.tasks.p, tasks.data(), tasks.size() * sizeof(MrhsTask), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(W.probs.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
+    const bool timed = timer && timer->used < MAX_TIMED;
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], st));
     HIP_TRY(ctx, run_mrhs_product(st, dtype, mode, W.tasks.as<MrhsTask>(), nt, W.probs.as<MrhsProblem>(),
                                   W.part_s.as<float>(), W.part_g.as<float>(), W.part_scal.as<float>()));
+    if (timed) {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used + 1], st));
+        timer->used++;
+    }
     HIP_TRY(ctx, run_mrhs_dspace(st, variant, W.probs.as<MrhsProblem>(), (int)probs.size(), W.part_s.as<float>(),
                                  W.part_g.as<float>(), W.part_scal.as<float>()));
     // the pageable task/problem arrays above go out of scope: finish the copies
@@ -695,10 +701,14 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     const double tol = opts->tol > 0.0 ? opts->tol : 5e-7;
     hipStream_t st = ctx->stream;
     const bool timing = opts->time_phases != 0;
-    if (timing) {
+    if (timing || opts->time_products) {
         if ((rc = ensure_events(ctx)) != SPCG_OK) return rc;
-        HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
     }
+    if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
+    ProductTimer timer;
+    timer.ctx = ctx;
+    double timed_bytes = 0.0;
+    const int64_t es = dtype_bytes(dtype);
     BatchWork W;
     W.sk.assign(nprob, nullptr);
     W.pc.assign(nprob, nullptr);
@@ -833,7 +843,12 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     if ((rc = batched_pass(ctx, W, dtype, PM_G, PA_START, hp, rows_per_task)) != SPCG_OK) return rc;
     if ((rc = check(&act)) != SPCG_OK) return rc;
     while (act > 0) {
-        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, rows_per_task)) != SPCG_OK) return rc;
+        ProductTimer* tp = opts->time_products ? &timer : nullptr;
+        if (tp && timer.used < MAX_TIMED) {
+            for (int p = 0; p < nprob; ++p)
+                if (hp[p].active) timed_bytes += (double)hp[p].m * (hp[p].d * es + hp[p].k * 8);
+        }
+        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, rows_per_task, tp)) != SPCG_OK) return rc;
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) ++t2[p];
         if ((rc = check(&act)) != SPCG_OK) return rc;
@@ -847,12 +862,19 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             HIP_TRY(ctx, hipMemcpy2DAsync(beta[p] + c, (size_t)hp[p].k * 8, hp[p].X + (size_t)c * ldv, 8, 8, hp[p].d,
                                           hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
+    double prod_ms = 0.0;
+    for (int i = 0; i < timer.used; ++i) prod_ms += elapsed_ms(ctx->ev_prod[2 * i], ctx->ev_prod[2 * i + 1]);
     bool all = true;
     for (int p = 0; p < nprob; ++p) {
         all = all && conv[p];
         if (stats) {
             spcg_solve_stats& s = stats[p];
             std::memset(&s, 0, sizeof s);
+            if (p == 0 && opts->time_products) {
+                s.product_launches = timer.used;
+                s.product_ms_sum = prod_ms;
+                s.product_bytes = timed_bytes;
+            }
             s.K = (int32_t)W.sk[p]->K;
             s.T_stage1 = t1[p];
             s.T_stage2 = t2[p];
