@@ -48,6 +48,11 @@ WORKLOADS = {
                        "m_K=N/2, r=6d, a_i=3, FP64, N=2^17..2^22"),
 }
 METRIC = "time-to-OLS-accuracy (s) and PCG-product HBM GB/s, SPCG vs full PCG, 1 GPU"
+# HBM bytes per launch of the full-data SG product from rocprofv3 PMC runs
+# (2.0 x FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy; the summary and
+# commands are in profiles/hbm_traffic_sg_product_and_transform.txt).  Valid
+# for the product kernel as profiled; workloads not profiled report null.
+SG_TRAFFIC_BYTES = {"cfg1": 2.0104e9, "cfg2": 8.0366e9}
 
 
 def log(msg):
@@ -169,6 +174,7 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
     n_launch = sum(r["prod_n"] for r in res.values())
     avg_ms = sum(r["prod_ms"] for r in res.values()) / max(n_launch, 1)
     rf = roofline(avg_ms, n_launch, bpl, "product_ring_kernel (SG mode, full data)")
+    rf["traffic"] = SG_TRAFFIC_BYTES.get(args.workload)
     cpu = None
     if not args.no_cpu_baseline:
         n_s = min(args.cpu_sample, N // 2)
@@ -298,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--skip-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -310,6 +318,14 @@ def main():
     import workloads
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     if args.workload == "batched":
         out = bench_batched(args, spcg, workloads, torch, dev)
     elif args.workload == "paper":
