@@ -69,7 +69,8 @@ typedef struct spcg_precond_s spcg_precond_t;
 typedef struct spcg_mat {
     const void* data;
     int32_t dtype;
-    int32_t reserved;
+    int32_t reserved;   /* callers set 0; spcg_sketch_view sets 1: the row padding
+                           up to ld holds zeros and may be read */
     int64_t rows;
     int64_t cols;
     int64_t ld;
@@ -100,13 +101,22 @@ typedef struct spcg_sketch_opts {
     int64_t r;        /* rows of S_hat, the preconditioner sketch (0: 6 d) */
     int32_t growth;   /* m_{i+1} / m_i (0: 2) */
     int32_t hat_only; /* 1: build only S_hat X (what full-data PCG needs); K = 0 */
+    int32_t stage_dtype; /* element type of the stored stage rows B: 0 selects
+                            SPCG_F64 for F64 input, SPCG_BF16 for BF16/FP8 input
+                            and SPCG_F32 for F32 input; SPCG_F32 or SPCG_BF16
+                            may be forced for non-F64 input.  The transform and
+                            the preconditioner rows S_hat X stay FP32 (FP64 for
+                            F64 input); BF16 rows are rounded to nearest even. */
+    int32_t transform_segment; /* tuning: 0 = library default; 64, 128 or 256 caps the
+                                  bytes of each row segment a transform tile holds
+                                  (narrower tiles fit more blocks per CU) */
 } spcg_sketch_opts;
 
 /* Shape of a built sketch. */
 typedef struct spcg_sketch_info {
     int64_t N, Np, d, k, r, K;
     int32_t L;              /* Np = 2^L, the padded row count */
-    int32_t sketch_dtype;   /* SPCG_F64 for F64 input, SPCG_F32 otherwise */
+    int32_t sketch_dtype;   /* element type of the stage rows B (see stage_dtype) */
     int64_t ld;             /* leading dimension of the stored sketch rows */
     int64_t m[64];          /* m_1 .. m_K */
 } spcg_sketch_info;

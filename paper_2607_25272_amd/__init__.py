@@ -106,8 +106,8 @@ class Sketch:
     def view_tensor(self, stage):
         """Copies of the stored (unscaled) sketch rows of a stage as tensors."""
         A, b, c2 = self.view(stage)
-        dt = torch.float64 if A.dtype == SPCG_F64 else torch.float32
-        es = 8 if A.dtype == SPCG_F64 else 4
+        dt = {SPCG_F64: torch.float64, SPCG_F32: torch.float32, SPCG_BF16: torch.bfloat16}[A.dtype]
+        es = {SPCG_F64: 8, SPCG_F32: 4, SPCG_BF16: 2}[A.dtype]
         Ah = _tensor_from_ptr(A.data, (A.rows, A.ld), dt, es, self.ctx.device)[:, :A.cols]
         bh = None
         if b.data:
@@ -179,8 +179,9 @@ class Precond:
 
 
 def spcg_sketch(ctx, X, Y=None, seed=1, m0=0, m_max=0, r=0, growth=2, hat_only=False,
-                col_scale=None):
-    o = L.SketchOpts(seed=seed, m0=m0, m_max=m_max, r=r, growth=growth, hat_only=int(hat_only))
+                col_scale=None, stage_dtype=0, transform_segment=0):
+    o = L.SketchOpts(seed=seed, m0=m0, m_max=m_max, r=r, growth=growth, hat_only=int(hat_only),
+                     stage_dtype=stage_dtype, transform_segment=transform_segment)
     Xm = mat(X, col_scale)
     Ym = mat(Y) if Y is not None else None
     h = ctypes.c_void_p()
@@ -225,7 +226,7 @@ def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, 
 def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, growth=2,
                qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None,
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
-               record_features=False):
+               record_features=False, stage_dtype=0, transform_segment=0):
     """spcg_solve_opts from keyword arguments.  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
     ``schedule.load_weights``)."""
@@ -233,6 +234,8 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     ctx_lib = load()
     ctx_lib.spcg_solve_opts_default(ctypes.byref(o))
     o.sketch.seed, o.sketch.m0, o.sketch.m_max, o.sketch.r, o.sketch.growth = seed, m0, m_max, r, growth
+    o.sketch.stage_dtype = stage_dtype
+    o.sketch.transform_segment = transform_segment
     o.precond.qr_passes = qr_passes
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every

@@ -41,7 +41,7 @@ class SpcgMat(ctypes.Structure):
 
 class SketchOpts(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("m0", c_i64), ("m_max", c_i64), ("r", c_i64),
-                ("growth", c_i32), ("hat_only", c_i32)]
+                ("growth", c_i32), ("hat_only", c_i32), ("stage_dtype", c_i32), ("transform_segment", c_i32)]
 
 
 class SketchInfo(ctypes.Structure):

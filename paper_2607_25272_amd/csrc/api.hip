@@ -83,7 +83,8 @@ struct spcg_sketch_s {
     spcg_ctx* ctx = nullptr;
     int64_t N = 0, Np = 0, d = 0, k = 0, r = 0, K = 0, ld = 0, ldy = 0;
     int L = 0;
-    int dtype = DT_F32;
+    int dtype = DT_F32;    // transform and S_hat rows
+    int bdtype = DT_F32;   // stage rows B
     uint64_t seed = 0;
     int64_t m[64] = {};
     bool owns = true;
@@ -187,6 +188,17 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     sk->seed = o ? o->seed : 0;
     sk->dtype = X->dtype == SPCG_F64 ? DT_F64 : DT_F32;
     sk->ld = sketch_ld(d, sk->dtype == DT_F64);
+    const int want = o ? o->stage_dtype : 0;
+    if (sk->dtype == DT_F64) {
+        if (want != 0 && want != SPCG_F64) return fail(ctx, SPCG_E_DTYPE, "FP64 input keeps FP64 stage rows");
+        sk->bdtype = DT_F64;
+    } else if (want == 0) {
+        sk->bdtype = (X->dtype == SPCG_BF16 || X->dtype == SPCG_FP8E4M3) ? DT_BF16 : DT_F32;
+    } else if (want == SPCG_F32 || want == SPCG_BF16) {
+        sk->bdtype = want == SPCG_F32 ? DT_F32 : DT_BF16;
+    } else {
+        return fail(ctx, SPCG_E_DTYPE, "stage_dtype must be 0, SPCG_F32 or SPCG_BF16");
+    }
     sk->K = 0;
     if (!hat_only) {
         if (m0 <= d) return fail(ctx, SPCG_E_SHAPE, "need m_1 > d (m_1=%lld)", (long long)m0);
@@ -206,7 +218,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     DevBuf& bBY = borrow ? ctx->wsBY : sk->BY;
     DevBuf& bBh = borrow ? ctx->wsBh : sk->Bh;
     if (mK) {
-        HIP_TRY(ctx, bB.ensure((size_t)mK * sk->ld * es));
+        HIP_TRY(ctx, bB.ensure((size_t)mK * sk->ld * dtype_bytes(sk->bdtype)));
         HIP_TRY(ctx, bBY.ensure((size_t)mK * sk->ldy * 8));
     }
     HIP_TRY(ctx, bBh.ensure((size_t)r * sk->ld * es));
@@ -240,6 +252,10 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     jx.ldb = sk->ld;
     jx.Bh = sk->pBh;
     jx.ldbh = sk->ld;
+    jx.b_bf16 = sk->bdtype == DT_BF16;
+    jx.seg_bytes = o ? o->transform_segment : 0;
+    if (jx.seg_bytes != 0 && jx.seg_bytes != 64 && jx.seg_bytes != 128 && jx.seg_bytes != 256)
+        return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128 or 256");
     jx.narrow = 0;
     HIP_TRY(ctx, run_fwht(st, jx));
     if (mK) {
@@ -458,7 +474,7 @@ int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const Dspa
     j.m = A->rows;
     j.d = A->cols;
     j.lda = A->ld;
-    j.dmem = A->cols;
+    j.dmem = A->reserved == 1 ? A->ld : A->cols;
     j.col_scale = A->col_scale;
     j.b = b ? static_cast<const double*>(b->data) : nullptr;
     j.ldbv = b ? b->ld : 0;
@@ -627,13 +643,25 @@ struct BatchWork {
 
 constexpr int MR_VECS = 6;   // X G Z P S Gt
 
-int build_tasks(const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks, std::vector<MrhsProblem>& out,
-                int64_t rows_per_task) {
+// Tasks grouped by row-width class (one product launch per class); the
+// tasks of a problem are contiguous, [t0, t1).  Returns the task count or a
+// negative class error.
+int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks,
+                std::vector<MrhsProblem>& out, int64_t rows_per_task, int* seg) {
     tasks.clear();
     out = hp;
+    std::vector<int> cls(hp.size(), -1);
     for (size_t p = 0; p < hp.size(); ++p) {
-        out[p].t0 = (int)tasks.size();
-        if (hp[p].active) {
+        out[p].t0 = out[p].t1 = 0;
+        if (!hp[p].active) continue;
+        cls[p] = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
+        if (cls[p] < 0) return -1;
+    }
+    for (int c = 0; c < MR_NCLASS; ++c) {
+        seg[c] = (int)tasks.size();
+        for (size_t p = 0; p < hp.size(); ++p) {
+            if (cls[p] != c) continue;
+            out[p].t0 = (int)tasks.size();
             for (int64_t r = 0; r < hp[p].m; r += rows_per_task) {
                 MrhsTask t{};
                 t.prob = (int)p;
@@ -641,9 +669,10 @@ int build_tasks(const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks
                 t.r1 = std::min<int64_t>(hp[p].m, r + rows_per_task);
                 tasks.push_back(t);
             }
+            out[p].t1 = (int)tasks.size();
         }
-        out[p].t1 = (int)tasks.size();
     }
+    seg[MR_NCLASS] = (int)tasks.size();
     return (int)tasks.size();
 }
 
@@ -651,7 +680,9 @@ int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, 
                  int64_t rows_per_task, ProductTimer* timer = nullptr) {
     std::vector<MrhsTask> tasks;
     std::vector<MrhsProblem> probs;
-    const int nt = build_tasks(hp, tasks, probs, rows_per_task);
+    int seg[MR_NCLASS + 1];
+    const int nt = build_tasks(dtype, hp, tasks, probs, rows_per_task, seg);
+    if (nt < 0) return fail(ctx, SPCG_E_SHAPE, "a batched matrix has an unsupported row layout");
     const size_t per_task = (size_t)mrhs_max_d() * mrhs_max_k();
     HIP_TRY(ctx, W.tasks.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
     HIP_TRY(ctx, W.probs.ensure(probs.size() * sizeof(MrhsProblem)));
@@ -664,8 +695,13 @@ int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, 
     HIP_TRY(ctx, hipMemcpyAsync(W.probs.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
     const bool timed = timer && timer->used < MAX_TIMED;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], st));
-    HIP_TRY(ctx, run_mrhs_product(st, dtype, mode, W.tasks.as<MrhsTask>(), nt, W.probs.as<MrhsProblem>(),
-                                  W.part_s.as<float>(), W.part_g.as<float>(), W.part_scal.as<float>()));
+    for (int c = 0; c < MR_NCLASS; ++c) {
+        const int n = seg[c + 1] - seg[c];
+        if (n > 0)
+            HIP_TRY(ctx, run_mrhs_product(st, dtype, mode, c, W.tasks.as<MrhsTask>(), seg[c], n,
+                                          W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
+                                          W.part_scal.as<float>()));
+    }
     if (timed) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used + 1], st));
         timer->used++;
@@ -771,16 +807,18 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             q.A = A.data;
             q.m = A.rows;
             q.lda = A.ld;
+            q.dmem = A.ld;   // sketch rows are zero-padded to ld
             q.b = static_cast<const double*>(b.data);
             q.ldb = b.ld;
             q.c2 = c2;
         }
         if (!any) continue;
-        // the sketch rows of FP32/BF16 input are FP32
-        if ((rc = batched_pass(ctx, W, DT_F32, PM_G, PA_START, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+        // stage rows: every problem's sketch has the same element type
+        const int sdt = W.sk[0]->bdtype;
+        if ((rc = batched_pass(ctx, W, sdt, PM_G, PA_START, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
             return rc;
         for (int it = 0; it < ai; ++it)
-            if ((rc = batched_pass(ctx, W, DT_F32, PM_S, PA_STEP, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+            if ((rc = batched_pass(ctx, W, sdt, PM_S, PA_STEP, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
                 return rc;
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) t1[p] += ai;
@@ -793,6 +831,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         q.A = X[p].data;
         q.m = X[p].rows;
         q.lda = X[p].ld;
+        q.dmem = X[p].cols;
         q.b = static_cast<const double*>(Y[p].data);
         q.ldb = Y[p].ld;
         q.c2 = 1.0;
@@ -963,7 +1002,7 @@ int spcg_sketch_get_info(const spcg_sketch_t* sk, spcg_sketch_info* info) {
     info->r = sk->r;
     info->K = sk->K;
     info->L = sk->L;
-    info->sketch_dtype = sk->dtype;
+    info->sketch_dtype = sk->bdtype;
     info->ld = sk->ld;
     for (int64_t i = 0; i < sk->K; ++i) info->m[i] = sk->m[i];
     return SPCG_OK;
@@ -974,8 +1013,8 @@ int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* 
     if (stage < -1 || stage >= sk->K) return SPCG_E_INVALID_ARG;
     const int64_t rows = stage < 0 ? sk->r : sk->m[stage];
     A->data = stage < 0 ? sk->pBh : sk->pB;
-    A->dtype = sk->dtype;
-    A->reserved = 0;
+    A->dtype = stage < 0 ? sk->dtype : sk->bdtype;
+    A->reserved = 1;   // zero-padded rows: columns up to ld may be read
     A->rows = rows;
     A->cols = sk->d;
     A->ld = sk->ld;

@@ -37,6 +37,8 @@ struct FwhtJob {
     void* Bh;                 // r x ldbh of TZ (rows pi_hat(t)), or null
     int64_t ldbh;
     int narrow;               // 1: single-column FP64 transform (the response vector)
+    int b_bf16;               // 1: store the B rows as BF16 (round to nearest even)
+    int seg_bytes;            // 0: default column segment; 64 / 128 / 256: at most this
 };
 // Widest column chunk of the transform (256-byte row segments): every row
 // width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.
@@ -122,6 +124,7 @@ struct MrhsScalars {
 struct MrhsProblem {
     const void* A;          // m x d row-major (FP32 or BF16), leading dim lda
     int64_t m, lda;
+    int64_t dmem;           // columns readable in every row (>= d)
     int d, k;
     const double* b;        // m x k row-major, leading dim ldb
     int64_t ldb;
@@ -145,8 +148,16 @@ struct MrhsTask {
 };
 int mrhs_max_d();
 int mrhs_max_k();
-hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, const MrhsTask* tasks, int ntasks,
-                            const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal);
+// Row-width classes of the product launches: load width (16 or 4 bytes) x
+// loads per row (a power of two); MR_CLASS_GENERIC reads element by element
+// (any row stride).
+enum MrhsClass : int { MR_CLASS_16x1 = 0, MR_CLASS_16x2, MR_CLASS_4x1, MR_CLASS_4x2, MR_CLASS_4x4, MR_CLASS_4x8,
+                       MR_CLASS_GENERIC, MR_NCLASS };
+int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d);
+// One launch over tasks[task0 .. task0 + ntasks), all of class cls; task t
+// writes partial block t.
+hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, const MrhsTask* tasks, int task0,
+                            int ntasks, const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal);
 // One block per problem: the whole d-space step of all k columns.
 // variant: PA_START (g, z, p, rho from the G partials), PA_STEP, PA_REFRESH.
 hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs, int nprob,

@@ -11,14 +11,21 @@
 //   B operand: lane l holds B[l / 16][l % 16]
 //   result   : lane l, register v holds C[4 (l / 16) + v][l % 16].
 //
-// Work is a list of tasks (problem, first row, last row); one launch covers
-// every task of a batch of independent problems.  A task's block stages
-// 16-row tiles of its problem's A in LDS (widened to FP32); the 4 waves
-// split the first GEMM along d and combine their 16 x 16 partials through
-// LDS; each wave then owns a quarter of the d / 16 output tiles of the
-// second GEMM, with the accumulators in registers.  The task writes one
-// FP32 partial d x 16 block per output; the per-problem d-space kernel sums
-// the partials of its tasks in a fixed order.
+// Work is a list of tasks (problem, first row, last row); one launch per
+// row-width class covers every task of that class in a batch of
+// independent problems.  A task's block streams 16-row tiles of its A
+// through a ring of LDS slots filled by direct global->LDS loads (the same
+// scheme as the single-RHS product: equal load counts per wave and tile,
+// explicit vmcnt waits, bare barriers, one LDS object per slot), so the
+// next tiles are in flight while the matrix cores work on the current one.
+// The constant B operands of the first GEMM (P and x split hi + lo) stay in
+// registers for the whole task: wave w owns the K steps w, w + 8, ...; the
+// 8 waves' 16 x 16 partials of W are combined through LDS, and each wave
+// then owns every 8th 16-column output tile of the second GEMM, with the
+// accumulators in registers.  The residual is formed in FP64 as
+// (b - A x_hi) - A x_lo.  The task writes one FP32 partial d x 16 block per
+// output; the per-problem d-space kernel sums the partials of its tasks in
+// a fixed order.
 #include <type_traits>
 
 #include "common.hpp"
@@ -30,11 +37,249 @@ namespace {
 
 constexpr int MT = 16;          // rows per tile (MFMA M)
 constexpr int KP = 16;          // right-hand sides per MFMA (N)
-constexpr int MR_DMAX = 512;    // columns supported by the staged path
-constexpr int MR_WAVES = 4;
-constexpr int AT_LD = MR_DMAX + 4;
+constexpr int MR_DMAX = 512;    // columns supported
+constexpr int MRW = 8;          // waves per block
+constexpr int MR_RING = 3;      // LDS slots
+constexpr int KJ = (MR_DMAX / 4 + MRW - 1) / MRW;   // first-GEMM K steps per wave
+constexpr int MAXT = MR_DMAX / 16 / MRW;            // second-GEMM tiles per wave
 
 typedef float mv4f __attribute__((ext_vector_type(4)));
+
+constexpr int mr_vmcnt_imm(int n) { return (n & 0xf) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8); }
+// wait for LDS (lgkm) only: vmcnt and expcnt at their maxima
+constexpr int MR_LGKM0 = 0xf | (3 << 14) | (0x7 << 4);
+
+template <int DMAB>
+__device__ __forceinline__ void mr_lds_load(const void* src, void* lds) {
+    void* g = const_cast<void*>(src);
+    auto* l = (__attribute__((address_space(3))) void*)(lds);
+    if constexpr (DMAB == 16) {
+        __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+    } else {
+        static_assert(DMAB == 4, "4- or 16-byte loads");
+        __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+    }
+}
+
+template <typename TS>
+__device__ __forceinline__ float lds_elem(const unsigned char* row, int col);
+template <>
+__device__ __forceinline__ float lds_elem<float>(const unsigned char* row, int col) {
+    return reinterpret_cast<const float*>(row)[col];
+}
+template <>
+__device__ __forceinline__ float lds_elem<bf16_t>(const unsigned char* row, int col) {
+    return bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(row)[col]);
+}
+
+template <typename TS, int MODE, int DMAB, int NIR>
+__global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* __restrict__ tasks, int task0,
+                                                                const MrhsProblem* __restrict__ probs,
+                                                                float* part_s, float* part_g, float* part_scal) {
+    constexpr bool DO_S = MODE != PM_G;
+    constexpr bool DO_G = MODE != PM_S;
+    constexpr int ES = std::is_same<TS, float>::value ? 4 : 2;
+    constexpr int RB = NIR * 64 * DMAB;              // staged bytes per row
+    constexpr int PITCH = RB + 16;                   // 16-byte pad: row starts hit different banks
+    constexpr int YB = DO_G ? 256 : 0;               // staged b bytes per row (k FP64 values)
+    constexpr int SLOT = MT * PITCH + MT * YB;
+    constexpr int AJOBS = MT * NIR;                  // A loads per tile
+    constexpr int OPS = AJOBS / MRW + (DO_G ? MT / MRW : 0);   // loads per wave per tile
+    static_assert(AJOBS % MRW == 0 && MT % MRW == 0, "even split of the loads");
+    static_assert((MR_RING - 2) * OPS < 64, "vmcnt range");
+    __shared__ __align__(16) unsigned char sl0[SLOT];
+    __shared__ __align__(16) unsigned char sl1[SLOT];
+    __shared__ __align__(16) unsigned char sl2[SLOT];
+    __shared__ float Wp[DO_S ? MRW : 1][MT][KP + 1];
+    __shared__ float Wg[DO_G ? MRW : 1][MT][KP + 1];
+    __shared__ float Wl[DO_G ? MRW : 1][MT][KP + 1];
+    __shared__ float nrm[2][4][KP];
+
+    const MrhsTask task = tasks[blockIdx.x];
+    const int64_t gtask = (int64_t)task0 + blockIdx.x;
+    const MrhsProblem pb = probs[task.prob];
+    const int d = pb.d, k = pb.k;
+    const int dt = (d + 15) / 16;          // 16-column tiles of d
+    const int d4 = (d + 3) / 4;            // K steps of the first GEMM
+    // wave index as a wave-uniform (scalar) value: row offsets stay in SGPRs
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int li = lane & 15, lg = lane >> 4;
+    const int nvec = (d * ES + DMAB - 1) / DMAB;    // load vectors holding the row's data
+    const char* Abase = static_cast<const char*>(pb.A);
+    const int64_t rowb = pb.lda * ES;
+    const int64_t rlast = task.r1 - 1;
+
+    // constant B operands of the first GEMM: P and x = hi + lo (~48 bits),
+    // zero outside d x k.  A x = A x_hi + A x_lo: the high product only
+    // changes when x_hi does, so steps far below FP32 resolution of x still
+    // move the residual through the low product.
+    float bp[KJ], bh[KJ], bl[KJ];
+#pragma unroll
+    for (int j = 0; j < KJ; ++j) {
+        const int s = wave + MRW * j;
+        const int row = 4 * s + lg;
+        const bool ok = row < d && li < k;
+        const int rr = ok ? row : 0, cc = ok ? li : 0;
+        const double pv = DO_S ? pb.P[(int64_t)cc * pb.ldv + rr] : 0.0;
+        const double xv = DO_G ? pb.X[(int64_t)cc * pb.ldv + rr] : 0.0;
+        bp[j] = ok ? (float)pv : 0.f;
+        const float hi = ok ? (float)xv : 0.f;
+        bh[j] = hi;
+        bl[j] = ok ? (float)(xv - (double)hi) : 0.f;
+    }
+    mv4f accS[MAXT], accG[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        accS[t] = mv4f{0.f, 0.f, 0.f, 0.f};
+        accG[t] = mv4f{0.f, 0.f, 0.f, 0.f};
+    }
+    float r2 = 0.f, ax2 = 0.f;   // wave 0, per lane: column li, rows of its group
+    const int64_t ntile = (task.r1 - task.r0 + MT - 1) / MT;
+
+    auto issue = [&](int64_t tl, unsigned char* T) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < AJOBS / MRW; ++q) {
+            const int job = wave + MRW * q;
+            const int r = job / NIR, c = job % NIR;
+            const int64_t grow = min(task.r0 + tl * MT + r, rlast);
+            const int vi = min(c * 64 + lane, nvec - 1);
+            mr_lds_load<DMAB>(Abase + grow * rowb + (int64_t)vi * DMAB, T + r * PITCH + c * 64 * DMAB);
+            // keep each address computation next to its load (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (DO_G) {
+#pragma unroll
+            for (int q = 0; q < MT / MRW; ++q) {
+                const int r = wave + MRW * q;
+                const int64_t grow = min(task.r0 + tl * MT + r, rlast);
+                const int w = min(lane, 2 * k - 1);
+                mr_lds_load<4>(reinterpret_cast<const char*>(pb.b + grow * pb.ldb) + 4 * w,
+                               T + MT * PITCH + r * 256);
+            }
+        }
+    };
+    auto consume = [&](int64_t tl, const unsigned char* T) __attribute__((always_inline)) {
+        // first GEMM: this wave's K steps of W = A_t [P | x_hi | x_lo]
+        mv4f ws = mv4f{0.f, 0.f, 0.f, 0.f}, wg = mv4f{0.f, 0.f, 0.f, 0.f}, wl = mv4f{0.f, 0.f, 0.f, 0.f};
+        const unsigned char* arow = T + li * PITCH;
+#pragma unroll
+        for (int j = 0; j < KJ; ++j) {
+            const int s = wave + MRW * j;
+            if (s < d4) {
+                const float av = lds_elem<TS>(arow, 4 * s + lg);
+                if (DO_S) ws = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[j], ws, 0, 0, 0);
+                if (DO_G) {
+                    wg = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bh[j], wg, 0, 0, 0);
+                    wl = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bl[j], wl, 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (DO_S) Wp[wave][4 * lg + v][li] = ws[v];
+            if (DO_G) {
+                Wg[wave][4 * lg + v][li] = wg[v];
+                Wl[wave][4 * lg + v][li] = wl[v];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(MR_LGKM0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // B operands of the second GEMM: W[4 s + lg][li] summed over waves
+        float wb[4], gb[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int rr = 4 * s + lg;
+            const bool ok = task.r0 + tl * MT + rr < task.r1 && li < k;
+            float t0 = 0.f, t1 = 0.f, tlo = 0.f;
+#pragma unroll
+            for (int w = 0; w < MRW; ++w) {
+                if (DO_S) t0 += Wp[w][rr][li];
+                if (DO_G) {
+                    t1 += Wg[w][rr][li];
+                    tlo += Wl[w][rr][li];
+                }
+            }
+            wb[s] = ok ? t0 : 0.f;
+            gb[s] = 0.f;
+            if constexpr (DO_G) {
+                const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[ok ? li : 0];
+                const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
+                gb[s] = (float)res;
+                if (wave == 0 && ok) {
+                    r2 = fmaf((float)res, (float)res, r2);
+                    ax2 = fmaf(t1, t1, ax2);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // bound the partial loads in flight
+        }
+        // second GEMM: S[:, tile mt] += A_t^T W
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            const int mt = wave + MRW * t;
+            if (mt < dt) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float av = lds_elem<TS>(T + (4 * s + lg) * PITCH, 16 * mt + li);
+                    if (DO_S) accS[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wb[s], accS[t], 0, 0, 0);
+                    if (DO_G) accG[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gb[s], accG[t], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    issue(0, sl0);
+    issue(1, sl1);
+    // every step runs (rows past the task contribute zeros), so the slot of
+    // each read is known at compile time
+#define SPCG_MR_STEP(CUR, NXT, OFF)                                  \
+    __builtin_amdgcn_s_waitcnt(mr_vmcnt_imm((MR_RING - 2) * OPS));   \
+    __builtin_amdgcn_s_barrier();                                    \
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);                         \
+    issue(t + (OFF) + MR_RING - 1, NXT);                             \
+    consume(t + (OFF), CUR);
+    for (int64_t t = 0; t < ntile; t += MR_RING) {
+        SPCG_MR_STEP(sl0, sl2, 0)
+        SPCG_MR_STEP(sl1, sl0, 1)
+        SPCG_MR_STEP(sl2, sl1, 2)
+    }
+#undef SPCG_MR_STEP
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // partial outputs: part[task][col][c] (c < 16)
+    const int64_t base = gtask * MR_DMAX * KP;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+        const int mt = wave + MRW * t;
+        if (mt < dt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = 16 * mt + 4 * lg + v;
+                if (DO_S) part_s[base + (int64_t)col * KP + li] = accS[t][v];
+                if (DO_G) part_g[base + (int64_t)col * KP + li] = accG[t][v];
+            }
+        }
+    }
+    if (DO_G) {
+        // reduce the per-lane norms of wave 0 over its 4 lane groups
+        if (wave == 0) {
+            nrm[0][lg][li] = r2;
+            nrm[1][lg][li] = ax2;
+        }
+        __syncthreads();
+        if (threadIdx.x < KP) {
+            const int c = threadIdx.x;
+            part_scal[gtask * 2 * KP + c] = ((nrm[0][0][c] + nrm[0][1][c]) + nrm[0][2][c]) + nrm[0][3][c];
+            part_scal[gtask * 2 * KP + KP + c] = ((nrm[1][0][c] + nrm[1][1][c]) + nrm[1][2][c]) + nrm[1][3][c];
+        }
+    }
+}
+
+// ---- register-staged fallback for row layouts the load-to-LDS path cannot
+// read (rows whose byte stride is not a multiple of 4): 16-row tiles are
+// widened element by element into LDS, one tile at a time.
+constexpr int MRG_WAVES = 4;
+constexpr int MRG_LD = MR_DMAX + 4;
 
 template <typename TS>
 __device__ __forceinline__ float widen1(const void* A, int64_t idx);
@@ -48,21 +293,22 @@ __device__ __forceinline__ float widen1<bf16_t>(const void* A, int64_t idx) {
 }
 
 template <typename TS, int MODE>
-__global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsTask* __restrict__ tasks,
+__global__ __launch_bounds__(64 * MRG_WAVES) void mrhs_product_reg_kernel(const MrhsTask* __restrict__ tasks, int task0,
                                                                      const MrhsProblem* __restrict__ probs,
                                                                      float* part_s, float* part_g,
                                                                      float* part_scal) {
     constexpr bool DO_S = MODE != PM_G;
     constexpr bool DO_G = MODE != PM_S;
-    __shared__ float At[MT][AT_LD];
+    __shared__ float At[MT][MRG_LD];
     __shared__ float Ps[DO_S ? MR_DMAX : 1][KP];
     __shared__ float Xs[DO_G ? MR_DMAX : 1][KP];    // x rounded to FP32
     __shared__ float Xl[DO_G ? MR_DMAX : 1][KP];    // x - Xs, the low part
-    __shared__ float Wp[MR_WAVES][MT][KP + 1];
-    __shared__ float Wgp[DO_G ? MR_WAVES : 1][MT][KP + 1];
-    __shared__ float Wlp[DO_G ? MR_WAVES : 1][MT][KP + 1];
+    __shared__ float Wp[MRG_WAVES][MT][KP + 1];
+    __shared__ float Wgp[DO_G ? MRG_WAVES : 1][MT][KP + 1];
+    __shared__ float Wlp[DO_G ? MRG_WAVES : 1][MT][KP + 1];
 
     const MrhsTask task = tasks[blockIdx.x];
+    const int64_t gtask = (int64_t)task0 + blockIdx.x;
     const MrhsProblem pb = probs[task.prob];
     const int d = pb.d, k = pb.k;
     const int dt = (d + 15) / 16;          // 16-column tiles of d
@@ -75,7 +321,7 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
     // does, so steps far below FP32 resolution of x still move the residual
     // (through the low product) and the refreshed gradient keeps seeing
     // them.
-    for (int e = threadIdx.x; e < MR_DMAX * KP; e += 64 * MR_WAVES) {
+    for (int e = threadIdx.x; e < MR_DMAX * KP; e += 64 * MRG_WAVES) {
         const int j = e / KP, c = e % KP;
         const bool ok = j < d && c < k;
         if (DO_S) Ps[j][c] = ok ? (float)pb.P[(int64_t)c * pb.ldv + j] : 0.f;
@@ -87,7 +333,7 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
         }
     }
     // this wave's output tiles of the second GEMM: mt = wave, wave + 4, ...
-    constexpr int MAXT = MR_DMAX / 16 / MR_WAVES;
+    constexpr int MAXT = MR_DMAX / 16 / MRG_WAVES;
     mv4f accS[MAXT], accG[MAXT];
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
@@ -96,12 +342,12 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
     }
     float r2 = 0.f, ax2 = 0.f;   // per lane: column li, rows of its groups
     // first-GEMM K range of this wave
-    const int kq = (d4 + MR_WAVES - 1) / MR_WAVES;
+    const int kq = (d4 + MRG_WAVES - 1) / MRG_WAVES;
     const int ks0 = wave * kq, ks1 = min(d4, ks0 + kq);
 
     for (int64_t row0 = task.r0; row0 < task.r1; row0 += MT) {
         __syncthreads();   // previous tile fully consumed
-        for (int e = threadIdx.x; e < MT * MR_DMAX; e += 64 * MR_WAVES) {
+        for (int e = threadIdx.x; e < MT * MR_DMAX; e += 64 * MRG_WAVES) {
             const int rr = e / MR_DMAX, j = e % MR_DMAX;
             const int64_t row = row0 + rr;
             At[rr][j] = (row < task.r1 && j < d) ? widen1<TS>(pb.A, row * pb.lda + j) : 0.f;
@@ -133,7 +379,7 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
             const int rr = 4 * s + lg;
             float t0 = 0.f, t1 = 0.f, tl = 0.f;
 #pragma unroll
-            for (int w = 0; w < MR_WAVES; ++w) {
+            for (int w = 0; w < MRG_WAVES; ++w) {
                 t0 += Wp[w][rr][li];
                 if (DO_G) {
                     t1 += Wgp[w][rr][li];
@@ -156,7 +402,7 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
         // second GEMM: S[:, tile mt] += A_t^T W
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-            const int mt = wave + MR_WAVES * t;
+            const int mt = wave + MRG_WAVES * t;
             if (mt < dt) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -168,10 +414,10 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
         }
     }
     // partial outputs: part[task][col][c] (c < 16)
-    const int64_t base = (int64_t)blockIdx.x * MR_DMAX * KP;
+    const int64_t base = gtask * MR_DMAX * KP;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
-        const int mt = wave + MR_WAVES * t;
+        const int mt = wave + MRG_WAVES * t;
         if (mt < dt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -191,11 +437,48 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
         __syncthreads();
         if (threadIdx.x < KP) {
             const int c = threadIdx.x;
-            part_scal[(int64_t)blockIdx.x * 2 * KP + c] = ((nrm[0][0][c] + nrm[0][1][c]) + nrm[0][2][c]) + nrm[0][3][c];
-            part_scal[(int64_t)blockIdx.x * 2 * KP + KP + c] =
+            part_scal[gtask * 2 * KP + c] = ((nrm[0][0][c] + nrm[0][1][c]) + nrm[0][2][c]) + nrm[0][3][c];
+            part_scal[gtask * 2 * KP + KP + c] =
                 ((nrm[1][0][c] + nrm[1][1][c]) + nrm[1][2][c]) + nrm[1][3][c];
         }
     }
+}
+
+
+template <typename TS, int DMAB, int NIR>
+hipError_t mr_launch(hipStream_t st, int mode, const MrhsTask* tasks, int task0, int ntasks, const MrhsProblem* probs,
+                     float* ps, float* pg, float* pscal) {
+    dim3 grid(ntasks), block(64 * MRW);
+    switch (mode) {
+        case PM_S: mrhs_product_kernel<TS, PM_S, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+        case PM_G: mrhs_product_kernel<TS, PM_G, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+        default: mrhs_product_kernel<TS, PM_SG, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t mr_launch_class(hipStream_t st, int mode, int cls, const MrhsTask* tasks, int task0, int ntasks,
+                           const MrhsProblem* probs, float* ps, float* pg, float* pscal) {
+    switch (cls) {
+        case MR_CLASS_16x1: return mr_launch<TS, 16, 1>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_16x2: return mr_launch<TS, 16, 2>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x1: return mr_launch<TS, 4, 1>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x2: return mr_launch<TS, 4, 2>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x4: return mr_launch<TS, 4, 4>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x8: return mr_launch<TS, 4, 8>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        default: break;
+    }
+    if (cls == MR_CLASS_GENERIC) {
+        dim3 grid(ntasks), block(64 * MRG_WAVES);
+        switch (mode) {
+            case PM_S: mrhs_product_reg_kernel<TS, PM_S><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+            case PM_G: mrhs_product_reg_kernel<TS, PM_G><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+            default: mrhs_product_reg_kernel<TS, PM_SG><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+        }
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -203,25 +486,34 @@ __global__ __launch_bounds__(64 * MR_WAVES) void mrhs_product_kernel(const MrhsT
 int mrhs_max_d() { return MR_DMAX; }
 int mrhs_max_k() { return KP; }
 
-hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, const MrhsTask* tasks, int ntasks,
-                            const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal) {
+int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d) {
+    const int es = dtype == DT_F32 ? 4 : 2;
+    for (int dmab : {16, 4}) {
+        const int64_t nv = ((int64_t)d * es + dmab - 1) / dmab;
+        const bool ok = (lda * es) % dmab == 0 && (uintptr_t)A % dmab == 0 && nv * dmab <= dmem * es;
+        if (!ok) continue;
+        const int64_t ni = (nv + 63) / 64;
+        if (dmab == 16) {
+            if (ni <= 1) return MR_CLASS_16x1;
+            if (ni <= 2) return MR_CLASS_16x2;
+            continue;
+        }
+        if (ni <= 1) return MR_CLASS_4x1;
+        if (ni <= 2) return MR_CLASS_4x2;
+        if (ni <= 4) return MR_CLASS_4x4;
+        if (ni <= 8) return MR_CLASS_4x8;
+    }
+    return MR_CLASS_GENERIC;
+}
+
+hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, const MrhsTask* tasks, int task0,
+                            int ntasks, const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal) {
     if (ntasks <= 0) return hipSuccess;
-    dim3 grid(ntasks), block(64 * MR_WAVES);
-#define SPCG_MR_LAUNCH(TS)                                                                                    \
-    switch (mode) {                                                                                           \
-        case PM_S: mrhs_product_kernel<TS, PM_S><<<grid, block, 0, st>>>(tasks, probs, part_s, part_g, part_scal); break; \
-        case PM_G: mrhs_product_kernel<TS, PM_G><<<grid, block, 0, st>>>(tasks, probs, part_s, part_g, part_scal); break; \
-        default: mrhs_product_kernel<TS, PM_SG><<<grid, block, 0, st>>>(tasks, probs, part_s, part_g, part_scal); break; \
-    }
-    if (dtype == DT_F32) {
-        SPCG_MR_LAUNCH(float)
-    } else if (dtype == DT_BF16) {
-        SPCG_MR_LAUNCH(bf16_t)
-    } else {
-        return hipErrorInvalidValue;
-    }
-#undef SPCG_MR_LAUNCH
-    return hipGetLastError();
+    if (dtype == DT_F32)
+        return mr_launch_class<float>(st, mode, cls, tasks + task0, task0, ntasks, probs, part_s, part_g, part_scal);
+    if (dtype == DT_BF16)
+        return mr_launch_class<bf16_t>(st, mode, cls, tasks + task0, task0, ntasks, probs, part_s, part_g, part_scal);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace spcg

@@ -376,7 +376,8 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
     __shared__ __align__(16) unsigned char t3[SLOT];
     __shared__ double red_scal[2 * NW];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // wave index as a wave-uniform (scalar) value: row offsets stay in SGPRs
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int d = a.d;
     CT preg[NC];
     double xreg[NC];

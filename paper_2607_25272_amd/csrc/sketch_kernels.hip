@@ -9,6 +9,8 @@
 // loads tiles of 2^nb rows (stride 2^lo) x CW columns into LDS and runs its
 // stages in order, so every element goes through the same additions in the
 // same order as a stage-by-stage transform.
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "rng.hpp"
@@ -109,6 +111,17 @@ struct InVec<fp8_t, float, VL> {
     }
 };
 
+// Four floats rounded to nearest even bfloat16, one 8-byte store.
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void bf16_store4(uint16_t* p, const float* o) {
+    const uint32_t w0 = f32_to_bf16_rne(o[0]) | (f32_to_bf16_rne(o[1]) << 16);
+    const uint32_t w1 = f32_to_bf16_rne(o[2]) | (f32_to_bf16_rne(o[3]) << 16);
+    *reinterpret_cast<uint2*>(p) = make_uint2(w0, w1);
+}
+
 template <typename TZ>
 struct ZVec;
 template <>
@@ -154,6 +167,7 @@ struct PassArgs {
     int64_t ldb;
     void* Bh;
     int64_t ldbh;
+    int b_bf16;        // store B rows as BF16
     int lo, nb, q;
     int64_t nchunks, ntiles;
 };
@@ -294,8 +308,17 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
                 if (a.inv_slot) {
                     const int32_t sl = a.inv_slot[k];
                     if (sl >= 0) {
-                        TZ* p = static_cast<TZ*>(a.B) + (int64_t)sl * a.ldb + col0;
-                        if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
+                        bool done_bf16 = false;
+                        if constexpr (std::is_same<TZ, float>::value && VL == 4) {
+                            if (a.b_bf16) {
+                                bf16_store4(static_cast<uint16_t*>(a.B) + (int64_t)sl * a.ldb + col0, v[t]);
+                                done_bf16 = true;
+                            }
+                        }
+                        if (!done_bf16) {
+                            TZ* p = static_cast<TZ*>(a.B) + (int64_t)sl * a.ldb + col0;
+                            if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
+                        }
                     }
                 }
                 if (a.inv_hat) {
@@ -366,7 +389,7 @@ template <typename TIN, typename TZ>
 hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     const int L = job.L;
     constexpr int E = sizeof(TZ);
-    constexpr int CW_WIDE = 256 / E, CW_NARROW = 128 / E;
+    constexpr int CW_WIDE = 256 / E, CW_NARROW = 128 / E, CW_TINY = 64 / E;
     const int passes = (L + NB_MAX - 1) / NB_MAX;
     PassArgs a{};
     a.x = job.x;
@@ -382,24 +405,31 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     a.ldb = job.ldb;
     a.Bh = job.Bh;
     a.ldbh = job.ldbh;
+    a.b_bf16 = job.b_bf16;
     constexpr int VL = ZVec<TZ>::VL;
     a.xvec = (job.ldx % VL == 0) && ((uintptr_t)job.x % (VL * sizeof(TIN)) == 0);
     int lo = 0;
     for (int pi = 0; pi < passes; ++pi) {
         const int nb = L / passes + (pi < L % passes ? 1 : 0);
-        const bool wide = nb <= 10;
-        const int cw = wide ? CW_WIDE : CW_NARROW;
+        // column segment per tile row: the widest whose tile fits the
+        // registers (256 B up to 10-bit passes, 128 B for 11 bits), unless
+        // the job asks for a narrower one (smaller blocks, more per CU)
+        int seg = nb <= 10 ? 256 : 128;
+        if (job.seg_bytes > 0 && job.seg_bytes < seg) seg = job.seg_bytes;
+        const int cw = seg / E;
         a.lo = lo;
         a.nb = nb;
-        a.q = wide ? pass_q<TZ, CW_WIDE>(nb) : pass_q<TZ, CW_NARROW>(nb);
+        a.q = cw == CW_WIDE ? pass_q<TZ, CW_WIDE>(nb) : cw == CW_NARROW ? pass_q<TZ, CW_NARROW>(nb)
+                                                                     : pass_q<TZ, CW_TINY>(nb);
         if (a.q > 5) return hipErrorInvalidValue;
         a.nchunks = job.ldz / cw;
         a.ntiles = (1ll << (L - nb)) * a.nchunks;
         a.zin = job.zbuf;
         a.zout = job.zbuf;
         const bool first = pi == 0, last = pi == passes - 1;
-        const hipError_t e = wide ? launch_any<TIN, TZ, CW_WIDE>(st, a, first, last)
-                                  : launch_any<TIN, TZ, CW_NARROW>(st, a, first, last);
+        const hipError_t e = cw == CW_WIDE     ? launch_any<TIN, TZ, CW_WIDE>(st, a, first, last)
+                             : cw == CW_NARROW ? launch_any<TIN, TZ, CW_NARROW>(st, a, first, last)
+                                               : launch_any<TIN, TZ, CW_TINY>(st, a, first, last);
         if (e != hipSuccess) return e;
         lo += nb;
     }

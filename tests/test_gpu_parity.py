@@ -137,21 +137,34 @@ def test_sketch_tiny_and_multi_rhs(S, ctx):
     assert np.array_equal(Hg.cpu().numpy(), Bh)
 
 
-@pytest.mark.parametrize("storage,N,d,tol", [("f32", 9000, 37, 2e-6), ("bf16", 6000, 40, 2e-6),
-                                             ("fp8", 5000, 48, 2e-6)])
-def test_sketch_rows_reduced_precision(S, ctx, storage, N, d, tol):
+@pytest.mark.parametrize("storage,N,d,stage_dtype", [("f32", 9000, 37, 0), ("bf16", 6000, 40, 0),
+                                                     ("fp8", 5000, 48, 0), ("bf16", 6000, 40, 1),
+                                                     ("f32", 7000, 40, 2)])
+def test_sketch_rows_reduced_precision(S, ctx, storage, N, d, stage_dtype):
     # FP32 transform of exactly-widened stored values vs the FP64 oracle on
-    # the same stored values; error bounded by L * u32 * row-norm scale
-    _log(f"sketch {storage} N={N} d={d}")
+    # the same stored values; error bounded by L * u32 * row-norm scale, plus
+    # the 2^-9 relative rounding of BF16 stage rows (the default for BF16 and
+    # FP8 input; stage_dtype 1 forces FP32 rows, 2 forces BF16)
+    _log(f"sketch {storage} N={N} d={d} stage_dtype={stage_dtype}")
+    tol = 2e-6
     p = _problem(N, d, storage=storage, seed=3)
-    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=5, col_scale=p.col_scale)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=5, col_scale=p.col_scale, stage_dtype=stage_dtype)
+    bf16_rows = stage_dtype == S.SPCG_BF16 or (stage_dtype == 0 and storage != "f32")
+    assert sk.info.sketch_dtype == (S.SPCG_BF16 if bf16_rows else S.SPCG_F32)
     Xd = p.x_f64().cpu().numpy()
     B, BY, Bh, info = nested_srht(Xd, p.Y.cpu().numpy(), 5, sk.sizes[-1], sk.info.r)
     Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
     Hg, _, _ = sk.view_tensor(-1)
+    assert Ag.dtype == (torch.bfloat16 if bf16_rows else torch.float32) and Hg.dtype == torch.float32
     scale = np.sqrt(info["Np"]) * np.abs(Xd).max(axis=0)   # |Z| <= sqrt(N') * column max
-    err = np.abs(Ag.cpu().numpy().astype(np.float64) - B) / scale
-    assert err.max() < tol * info["L"]
+    Af = Ag.float().cpu().numpy().astype(np.float64)
+    err = np.abs(Af - B) / scale
+    assert err.max() < tol * info["L"] + (2.0 ** -8 if bf16_rows else 0.0)
+    if bf16_rows:
+        # rounding is to nearest: within half a BF16 ulp of the exact row plus the transform error
+        rel = np.abs(Af - B) / np.maximum(np.abs(B), 1e-300)
+        big = np.abs(B) > 0.05 * scale
+        assert rel[big].max() < 2.0 ** -8 + 1e-3
     errh = np.abs(Hg.cpu().numpy().astype(np.float64) - Bh) / scale
     assert errh.max() < tol * info["L"]
     assert np.array_equal(bg.cpu().numpy(), BY)   # Y is always FP64
