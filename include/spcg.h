@@ -297,7 +297,8 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
  * summed duration and, in product_bytes, their summed algorithmic bytes
  * (sum over the active problems of m (d elem + 8 k) per launch).  Returns the
  * worst code over the problems (W_NOT_CONVERGED if any problem missed tol
- * within T). */
+ * within T).  The per-problem sketches, preconditioners and buffers stay in
+ * ctx for reuse by later batched calls and are freed by spcg_ctx_destroy. */
 int spcg_solve_batched(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y,
                        const spcg_solve_opts* opts, double* const* beta, spcg_solve_stats* stats);
 

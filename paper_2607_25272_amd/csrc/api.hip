@@ -56,6 +56,10 @@ constexpr int MAX_TIMED = 256;
 
 }  // namespace
 
+namespace {
+struct BatchWork;
+}
+
 struct spcg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -73,6 +77,9 @@ struct spcg_ctx {
     // learned schedule: features and network outputs (4 x 8 floats), gradient partials
     DevBuf sched, mlp_part;
     int syncs = 0;   // stream synchronisations of the current solve
+    // batched solves: per-problem sketches, preconditioners and buffers,
+    // kept for reuse by later calls (allocation is slow next to a solve)
+    BatchWork* batch = nullptr;
     // events for timing
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
@@ -200,6 +207,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
         return fail(ctx, SPCG_E_DTYPE, "stage_dtype must be 0, SPCG_F32 or SPCG_BF16");
     }
     sk->K = 0;
+    sk->k = 0;
     if (!hat_only) {
         if (m0 <= d) return fail(ctx, SPCG_E_SHAPE, "need m_1 > d (m_1=%lld)", (long long)m0);
         const int64_t limit = (o && o->m_max > 0) ? std::min<int64_t>(o->m_max, N - 1) : N - 1;
@@ -634,7 +642,7 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 struct BatchWork {
     std::vector<spcg_sketch_t*> sk;
     std::vector<spcg_precond_t*> pc;
-    DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal;
+    DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal, bestx;
     ~BatchWork() {
         for (auto* p : sk) delete p;
         for (auto* p : pc) delete p;
@@ -647,18 +655,23 @@ constexpr int MR_VECS = 6;   // X G Z P S Gt
 // tasks of a problem are contiguous, [t0, t1).  Returns the task count or a
 // negative class error.
 int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks,
-                std::vector<MrhsProblem>& out, int64_t rows_per_task, int* seg) {
+                std::vector<MrhsProblem>& out, int64_t target_tasks, int* seg) {
     tasks.clear();
     out = hp;
     std::vector<int> cls(hp.size(), -1);
+    int64_t class_rows[MR_NCLASS] = {};
     for (size_t p = 0; p < hp.size(); ++p) {
         out[p].t0 = out[p].t1 = 0;
         if (!hp[p].active) continue;
         cls[p] = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
         if (cls[p] < 0) return -1;
+        class_rows[cls[p]] += hp[p].m;
     }
     for (int c = 0; c < MR_NCLASS; ++c) {
         seg[c] = (int)tasks.size();
+        // each class is its own launch: split its rows into about
+        // target_tasks tasks so that every launch fills the device
+        const int64_t rows_per_task = std::max<int64_t>(256, round_up(ceil_div(class_rows[c], target_tasks), 16));
         for (size_t p = 0; p < hp.size(); ++p) {
             if (cls[p] != c) continue;
             out[p].t0 = (int)tasks.size();
@@ -677,11 +690,11 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
 }
 
 int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, const std::vector<MrhsProblem>& hp,
-                 int64_t rows_per_task, ProductTimer* timer = nullptr) {
+                 int64_t target_tasks, ProductTimer* timer = nullptr) {
     std::vector<MrhsTask> tasks;
     std::vector<MrhsProblem> probs;
     int seg[MR_NCLASS + 1];
-    const int nt = build_tasks(dtype, hp, tasks, probs, rows_per_task, seg);
+    const int nt = build_tasks(dtype, hp, tasks, probs, target_tasks, seg);
     if (nt < 0) return fail(ctx, SPCG_E_SHAPE, "a batched matrix has an unsupported row layout");
     const size_t per_task = (size_t)mrhs_max_d() * mrhs_max_k();
     HIP_TRY(ctx, W.tasks.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
@@ -745,20 +758,21 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     timer.ctx = ctx;
     double timed_bytes = 0.0;
     const int64_t es = dtype_bytes(dtype);
-    BatchWork W;
-    W.sk.assign(nprob, nullptr);
-    W.pc.assign(nprob, nullptr);
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    BatchWork& W = *ctx->batch;
+    while ((int)W.sk.size() < nprob) {
+        W.sk.push_back(new (std::nothrow) spcg_sketch_t());
+        W.pc.push_back(new (std::nothrow) spcg_precond_t());
+        if (!W.sk.back() || !W.pc.back()) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    }
     spcg_sketch_opts so = opts->sketch;
     so.hat_only = opts->method == SPCG_METHOD_FULL_PCG ? 1 : 0;
     for (int p = 0; p < nprob; ++p) {
-        W.sk[p] = new (std::nothrow) spcg_sketch_t();
-        if (!W.sk[p]) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
         if ((rc = sketch_build(ctx, &X[p], &Y[p], &so, false, W.sk[p])) != SPCG_OK) return rc;
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
     for (int p = 0; p < nprob; ++p) {
-        W.pc[p] = new (std::nothrow) spcg_precond_t();
-        if (!W.pc[p]) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
         if ((rc = precond_build(ctx, W.sk[p], &opts->precond, false, W.pc[p])) != SPCG_OK) return rc;
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
@@ -769,7 +783,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     HIP_TRY(ctx, hipMemsetAsync(W.vecs.p, 0, (size_t)nprob * MR_VECS * kmax * ldv * 8, st));
     HIP_TRY(ctx, hipMemsetAsync(W.scal.p, 0, (size_t)nprob * kmax * sizeof(MrhsScalars), st));
     std::vector<MrhsProblem> hp(nprob);
-    int64_t total_rows = 0, maxK = 0;
+    int64_t maxK = 0;
     for (int p = 0; p < nprob; ++p) {
         MrhsProblem& q = hp[p];
         std::memset(&q, 0, sizeof q);
@@ -785,11 +799,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         q.Gt = base + 5 * kmax * ldv;
         q.Minv = W.pc[p]->pMinv;
         q.sc = W.scal.as<MrhsScalars>() + (size_t)p * kmax;
-        total_rows += X[p].rows;
         maxK = std::max<int64_t>(maxK, W.sk[p]->K);
     }
-    // tasks: about 4 per CU over the full data, never fewer than 256 rows
-    const int64_t rows_per_task = std::max<int64_t>(256, round_up(ceil_div(total_rows, 4 * ctx->num_cu), 16));
+    // tasks per launch: about 4 per CU, never fewer than 256 rows each
+    const int64_t target_tasks = 4 * (int64_t)ctx->num_cu;
     std::vector<int> t1(nprob, 0), t2(nprob, 0), conv(nprob, 0);
     // Stage I: stage i of every problem that has one
     for (int64_t i = 0; i < maxK; ++i) {
@@ -815,10 +828,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         if (!any) continue;
         // stage rows: every problem's sketch has the same element type
         const int sdt = W.sk[0]->bdtype;
-        if ((rc = batched_pass(ctx, W, sdt, PM_G, PA_START, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+        if ((rc = batched_pass(ctx, W, sdt, PM_G, PA_START, hp, target_tasks)) != SPCG_OK)
             return rc;
         for (int it = 0; it < ai; ++it)
-            if ((rc = batched_pass(ctx, W, sdt, PM_S, PA_STEP, hp, std::max<int64_t>(256, rows_per_task / 4))) != SPCG_OK)
+            if ((rc = batched_pass(ctx, W, sdt, PM_S, PA_STEP, hp, target_tasks)) != SPCG_OK)
                 return rc;
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) t1[p] += ai;
@@ -841,7 +854,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // whose stopping ratio climbs well above its best value (iterating past
     // the floor) stops, keeping the best iterate seen.
     std::vector<double> best(nprob, INFINITY);
-    DevBuf bestx;
+    DevBuf& bestx = W.bestx;
     HIP_TRY(ctx, bestx.ensure((size_t)nprob * kmax * ldv * 8));
     auto check = [&](int* n_active) -> int {
         HIP_TRY(ctx, hipMemcpy(hs.data(), W.scal.p, hs.size() * sizeof(MrhsScalars), hipMemcpyDeviceToHost));
@@ -879,7 +892,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         return SPCG_OK;
     };
     int act = 0;
-    if ((rc = batched_pass(ctx, W, dtype, PM_G, PA_START, hp, rows_per_task)) != SPCG_OK) return rc;
+    if ((rc = batched_pass(ctx, W, dtype, PM_G, PA_START, hp, target_tasks)) != SPCG_OK) return rc;
     if ((rc = check(&act)) != SPCG_OK) return rc;
     while (act > 0) {
         ProductTimer* tp = opts->time_products ? &timer : nullptr;
@@ -887,7 +900,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             for (int p = 0; p < nprob; ++p)
                 if (hp[p].active) timed_bytes += (double)hp[p].m * (hp[p].d * es + hp[p].k * 8);
         }
-        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, rows_per_task, tp)) != SPCG_OK) return rc;
+        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, target_tasks, tp)) != SPCG_OK) return rc;
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) ++t2[p];
         if ((rc = check(&act)) != SPCG_OK) return rc;
@@ -971,6 +984,7 @@ int spcg_ctx_destroy(spcg_ctx* ctx) {
         for (auto& e : ctx->ev_phase) (void)hipEventDestroy(e);
         for (auto& e : ctx->ev_prod) (void)hipEventDestroy(e);
     }
+    delete ctx->batch;
     delete ctx;
     return SPCG_OK;
 }

@@ -136,13 +136,24 @@ __global__ void splitk_reduce_kernel(const double* part, int nz, int64_t M, int6
 // Upper Cholesky of the nb x nb diagonal block at (k0, k0) of G, in place
 // (strict lower part zeroed).
 // 256 threads in a 16 x 16 grid; each keeps a 4 x 4 patch of the block in
-// registers; per step only the pivot row goes through LDS.
+// registers.  Step j needs only the scaled pivot row j: the 16 threads of a
+// patch row share one wave, so the wave that owns row j + 1 reads its pivot
+// with a lane broadcast as soon as step j has updated it, scales the row
+// and publishes it through LDS (double-buffered).  One barrier per step.
+__device__ __forceinline__ double bcast_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, int64_t k0, int nb,
                                                         DenseStatus* st) {
-    __shared__ double rowj[CB];
-    __shared__ double piv_u;
+    __shared__ double rows[2][CB];
+    __shared__ double pivs[CB];
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double a[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -151,39 +162,20 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, i
             const int i = ty * 4 + r, j = tx * 4 + c;
             a[r][c] = (i < nb && j < nb && j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
         }
-    double min_piv = 0.0, min_d = 0.0, max_d = 0.0;
-    int first_fail = 0;
-    if (tid == 0) {
-        min_piv = st->min_pivot;
-        min_d = st->min_diag;
-        max_d = st->max_diag;
-        first_fail = st->fail;
-    }
-    for (int j = 0; j < nb; ++j) {
+    // scale row j (held by patch row j / 4, i.e. wave j / 16) and publish it
+    auto publish = [&](int j) __attribute__((always_inline)) {
         const int jr = j & 3, jb = j >> 2;
-        // pivot owner: diagonal element (j, j)
-        if (ty == jb && tx == jb) {
-            double piv = 0.0;
+        if (wave != (jb >> 2)) return;
+        double dg = a[0][0];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (r == jr && c == jr) piv = a[r][c];
-            piv_u = piv;
-        }
-        __syncthreads();
-        double u = piv_u;
+        for (int r = 1; r < 4; ++r)
+            if (r == jr) dg = a[r][r];
+        // the pivot (j, j) sits in patch (jb, jb): lane 16 (jb mod 4) + jb
+        const double piv = bcast_lane(dg, (jb & 3) * 16 + jb);
+        double u = piv;
         if (!(u > 0.0) || !__builtin_isfinite(u)) u = 1.0;
         u = sqrt(u);
         const double ru = 1.0 / u;
-        if (tid == 0) {
-            const double p = piv_u;
-            min_piv = p < min_piv ? p : min_piv;
-            if ((!(p > 0.0) || !__builtin_isfinite(p)) && first_fail == 0) first_fail = (int)(k0 + j) + 1;
-            min_d = u < min_d ? u : min_d;
-            max_d = u > max_d ? u : max_d;
-        }
-        // owners of row j scale it (U[j][l] = a[j][l] / u, U[j][j] = u) and publish it
         if (ty == jb) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -193,24 +185,30 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, i
                     const int l = tx * 4 + c;
                     if (l == j) a[r][c] = u;
                     else if (l > j) a[r][c] *= ru;
-                    rowj[l] = l >= j ? a[r][c] : 0.0;
+                    rows[j & 1][l] = l >= j ? a[r][c] : 0.0;
                 }
             }
+            if (tx == jb) pivs[j] = piv;
         }
-        __syncthreads();
+    };
+    publish(0);
+    for (int j = 0; j < nb; ++j) {
+        __syncthreads();   // row j published; row j - 1's buffer no longer read
+        const double* rj = rows[j & 1];
         // trailing update of rows i > j: a[i][l] -= U[j][i] U[j][l] (l >= i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = ty * 4 + r;
             if (i > j && i < nb) {
-                const double uji = rowj[i];
+                const double uji = rj[i];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int l = tx * 4 + c;
-                    if (l >= i && l < nb) a[r][c] = fma(-uji, rowj[l], a[r][c]);
+                    if (l >= i && l < nb) a[r][c] = fma(-uji, rj[l], a[r][c]);
                 }
             }
         }
+        if (j + 1 < nb) publish(j + 1);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -219,7 +217,19 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, i
             const int i = ty * 4 + r, j = tx * 4 + c;
             if (i < nb && j < nb) G[(k0 + i) * ld + k0 + j] = (j >= i) ? a[r][c] : 0.0;
         }
+    __syncthreads();
     if (tid == 0) {
+        double min_piv = st->min_pivot, min_d = st->min_diag, max_d = st->max_diag;
+        int first_fail = st->fail;
+        for (int j = 0; j < nb; ++j) {
+            const double p = pivs[j];
+            const bool bad = !(p > 0.0) || !__builtin_isfinite(p);
+            const double u = bad ? 1.0 : sqrt(p);
+            min_piv = p < min_piv ? p : min_piv;
+            if (bad && first_fail == 0) first_fail = (int)(k0 + j) + 1;
+            min_d = u < min_d ? u : min_d;
+            max_d = u > max_d ? u : max_d;
+        }
         st->min_pivot = min_piv;
         st->min_diag = min_d;
         st->max_diag = max_d;

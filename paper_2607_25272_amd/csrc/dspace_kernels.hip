@@ -39,12 +39,14 @@ struct PhaseAArgs {
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
-    // 16 columns x 16 partial lanes per block; each lane keeps 4 independent
-    // sums so that 4 loads are in flight, combined in a fixed order
+    // 16 columns x 16 partial lanes per block; lane ty sums partials
+    // ty + 16 v into four running sums (v mod 4), combined in a fixed order.
+    // All loads of the first 256 partials are issued before any is used.
     __shared__ double sh_s[16][A_COLS + 1];
     __shared__ double sh_g[16][A_COLS + 1];
     __shared__ double sh_r[256];
     __shared__ double sh_t[256];
+    __shared__ double sh_b[256];
     __shared__ int is_last;
     const DspaceState& S = a.S;
     const int tx = threadIdx.x & (A_COLS - 1), ty = threadIdx.x / A_COLS;
@@ -52,17 +54,23 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
     const bool want_s = a.variant != PA_START;
     const bool want_g = a.variant != PA_STEP;
     double ss[4] = {0.0, 0.0, 0.0, 0.0}, gg[4] = {0.0, 0.0, 0.0, 0.0};
+    double pc = 0.0;
     if (col < S.d) {
-        int b = ty;
-        for (; b + 48 < a.nparts; b += 64) {
+        if (want_s) pc = S.p[col];
+        double vs[16], vg[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t off = (int64_t)(b + 16 * u) * a.dpad + col;
-                if (want_s) ss[u] += a.part_s[off];
-                if (want_g) gg[u] += a.part_g[off];
-            }
+        for (int v = 0; v < 16; ++v) {
+            const int b = ty + 16 * v;
+            const int64_t off = (int64_t)b * a.dpad + col;
+            vs[v] = (want_s && b < a.nparts) ? a.part_s[off] : 0.0;
+            vg[v] = (want_g && b < a.nparts) ? a.part_g[off] : 0.0;
         }
-        for (int u = 0; b < a.nparts; b += 16, ++u) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            ss[v & 3] += vs[v];
+            gg[v & 3] += vg[v];
+        }
+        for (int b = ty + 256, u = 0; b < a.nparts; b += 16, u = (u + 1) & 3) {
             const int64_t off = (int64_t)b * a.dpad + col;
             if (want_s) ss[u] += a.part_s[off];
             if (want_g) gg[u] += a.part_g[off];
@@ -84,7 +92,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
             S.g[col] = g_col;
         } else {
             S.s[col] = s_col;
-            dot = S.p[col] * s_col;
+            dot = pc * s_col;
             if (a.variant == PA_REFRESH) S.gt[col] = g_col;
         }
     }
@@ -102,17 +110,23 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
     if (!is_last) return;
     __threadfence();
 
-    // ---- last block: scalars and the x / g update
+    // ---- last block: scalars and the x / g update.  The block partials of
+    // p^T s, the norm partials and the vectors of the update are all
+    // requested together.
     PcgScalars* sc = S.sc;
+    const unsigned nblk = gridDim.x;
+    double t0 = 0.0, t1 = 0.0;
     if (want_g) {
-        double t0 = 0.0, t1 = 0.0;
         for (int b = threadIdx.x; b < a.nparts; b += 256) {
             t0 += a.part_scal[2 * b];
             t1 += a.part_scal[2 * b + 1];
         }
-        sh_r[threadIdx.x] = t0;
-        sh_t[threadIdx.x] = t1;
-        __syncthreads();
+    }
+    if (threadIdx.x < nblk) sh_b[threadIdx.x] = S.blk[threadIdx.x];
+    sh_r[threadIdx.x] = t0;
+    sh_t[threadIdx.x] = t1;
+    __syncthreads();
+    if (want_g) {
         for (int w = 128; w > 0; w >>= 1) {
             if (threadIdx.x < w) {
                 sh_r[threadIdx.x] += sh_r[threadIdx.x + w];
@@ -134,7 +148,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
             sc->exact = 0;
         } else {
             double pts = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) pts += S.blk[b];
+            for (unsigned b = 0; b < nblk; ++b) pts += b < 256 ? sh_b[b] : S.blk[b];
             sc->pts = pts;
             const double rho = sc->rho;
             if (sc->breakdown || sc->exact) {
@@ -170,26 +184,34 @@ __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
     __shared__ double red[256];
     __shared__ int is_last;
     PcgScalars* sc = S.sc;
-    const bool skip = sc->breakdown || (!init && sc->exact);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * B_ROWS + wave;
-    double gz = 0.0;
-    if (!skip && i < S.d) {
+    // the row loads do not wait for the guard flags: a skipped iteration
+    // computes and discards
+    double acc = 0.0, gi = 0.0;
+    if (i < S.d) {
         const double* row = S.Minv + i * S.d;
         double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t j0 = lane; j0 < S.d; j0 += 256) {
+        for (int64_t j0 = lane; j0 < S.d; j0 += 512) {
+            double mv[8], gv[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int64_t j = j0 + 64 * u;
-                if (j < S.d) acc4[u] = fma(row[j], S.g[j], acc4[u]);
+                mv[u] = j < S.d ? row[j] : 0.0;
+                gv[u] = j < S.d ? S.g[j] : 0.0;
             }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc4[u & 3] = fma(mv[u], gv[u], acc4[u & 3]);
         }
-        double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+        acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         acc = group_sum<64>(acc);
-        if (lane == 0) {
-            S.z[i] = acc;
-            gz = S.g[i] * acc;
-        }
+        gi = S.g[i];
+    }
+    const bool skip = sc->breakdown || (!init && sc->exact);
+    double gz = 0.0;
+    if (!skip && i < S.d && lane == 0) {
+        S.z[i] = acc;
+        gz = gi * acc;
     }
     if (lane == 0) sh[wave] = gz;
     __syncthreads();
