@@ -18,6 +18,8 @@ Method for Linear Statistical Models"):
 * ``fwht``     - unnormalised Walsh-Hadamard transform (the H of the SRHT, Sec. 2.1).
 * ``sketch``   - nested SRHT: (Z_X, Z_Y) = (HDPX, HDPY) once, prefix row sets
                  for S_i and an independent row set for S-hat (Sec. 2.2).
+* ``countsketch`` - nested CountSketch of the SPCG-CS variant (Sec. 4.3):
+                 bucket map, signs, folding of nested sizes, independent S-hat.
 * ``linalg``   - Householder QR and triangular solves (preconditioner
                  "applied through a QR factorization", Sec. 4).
 * ``pcg``      - PCG(A, b, H-hat, beta_init, a) in normal-equation form (Sec. 2.2).

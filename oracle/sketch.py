@@ -42,12 +42,14 @@ def padded_bits(N):
     return L, 1 << L
 
 
-def sign_vector(seed, L, rows=None):
-    """+-1 entries of D for rows k (default: all 2^L rows), as float64."""
+def sign_vector(seed, L, rows=None, stream=STREAM_SIGN):
+    """+-1 entries of D for rows k (default: all 2^L rows), as float64.
+    ``stream`` selects an independent sign sequence (the CountSketch of the
+    preconditioner draws its own)."""
     k = np.arange(1 << L, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
     blk = k >> np.uint64(8)
     bit = k & np.uint64(255)
-    w = philox4x64(blk, 0, 0, 0, np.uint64(seed), np.uint64(STREAM_SIGN))
+    w = philox4x64(blk, 0, 0, 0, np.uint64(seed), np.uint64(stream))
     words = np.stack(w)  # (4, n)
     word = words[(bit >> np.uint64(6)).astype(np.int64), np.arange(k.size)]
     b = (word >> (bit & np.uint64(63))) & np.uint64(1)

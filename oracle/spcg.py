@@ -14,10 +14,14 @@ Readings (where the paper leaves a choice open):
 * r = 6d rows for S_hat, a_i = 3 (Sec. 4.1), beta_0 = 0, total budget T = 100;
 * Stage II stops when sqrt(rho) <= tol * ||X x|| (see ``pcg``) or when the
   total iteration count reaches T; tol defaults to 5e-7 so that the relative
-  prediction error ||X(x - beta_hat)|| / ||X beta_hat|| lands below 1e-6.
+  prediction error ||X(x - beta_hat)|| / ||X beta_hat|| lands below 1e-6;
+* ``sketch="cs"`` is SPCG-CS (Sec. 4.3): the nested CountSketch of
+  ``countsketch`` replaces the SRHT for both the stage sketches and S-hat;
+  its rows need no scaling (c^2 = 1, H-hat = (S-hat X)^T (S-hat X)).
 """
 import numpy as np
 
+from .countsketch import countsketch, nested_countsketch
 from .linalg import householder_qr
 from .pcg import pcg
 from .sketch import nested_srht, padded_bits
@@ -34,14 +38,33 @@ def schedule(N, d, m0=None, m_max=None, growth=2):
     return sizes
 
 
-def precond_from_sketch(B_hat):
-    """R with R^T R = B_hat^T B_hat / r (Householder QR of S_hat X)."""
+def precond_from_sketch(B_hat, scaled=True):
+    """R with R^T R = B_hat^T B_hat / r (Householder QR of S_hat X); with
+    ``scaled=False`` (CountSketch rows) R^T R = B_hat^T B_hat."""
     r = B_hat.shape[0]
-    return householder_qr(np.asarray(B_hat, dtype=np.float64) / np.sqrt(r))
+    B_hat = np.asarray(B_hat, dtype=np.float64)
+    return householder_qr(B_hat / np.sqrt(r) if scaled else B_hat)
+
+
+def _stage_problems(X, Y, seed, sizes, r, sketch):
+    """[(A_i, b_i (m_i x k), c2_i)] for the stages and R from S-hat."""
+    Y2 = Y if Y.ndim == 2 else Y[:, None]
+    if sketch == "cs":
+        stages, B_hat = nested_countsketch(X, Y2, seed, sizes, r)
+        probs = [(A, b, 1.0) for A, b in stages]
+        R = precond_from_sketch(B_hat, scaled=False)
+        L, Np = padded_bits(X.shape[0])
+        return probs, R, {"L": L, "Np": Np}
+    if sketch != "srht":
+        raise ValueError("sketch must be 'srht' or 'cs'")
+    mK = sizes[-1] if sizes else 1
+    B, BY, B_hat, sk = nested_srht(X, Y2, seed, mK, r)
+    probs = [(B[:m], BY[:m], 1.0 / m) for m in sizes]
+    return probs, precond_from_sketch(B_hat), sk
 
 
 def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
-         growth=2, history=False):
+         growth=2, history=False, sketch="srht"):
     """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k)."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
@@ -49,19 +72,16 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
     r = 6 * d if r is None else int(r)
     sizes = schedule(N, d, m0, m_max, growth)
     a_list = [a] * len(sizes) if np.isscalar(a) else list(a)
-    mK = sizes[-1] if sizes else 1
-    B, BY, B_hat, sk = nested_srht(X, Y, seed, mK, r)
-    R = precond_from_sketch(B_hat)
+    probs, R, sk = _stage_problems(X, Y, seed, sizes, r, sketch)
     multi = Y.ndim == 2
     Ys = Y if multi else Y[:, None]
-    BYs = BY if multi else BY[:, None]
     betas, infos = [], []
     for c in range(Ys.shape[1]):
         x = np.zeros(d)
         stage_x = []
         t = 0
-        for m, ai in zip(sizes, a_list):
-            x, _ = pcg(B[:m], BYs[:m, c], 1.0 / m, R, x, ai)
+        for (A, b, c2), ai in zip(probs, a_list):
+            x, _ = pcg(A, b[:, c], c2, R, x, ai)
             t += ai
             stage_x.append(x.copy())
         x, inf2 = pcg(X, Ys[:, c], 1.0, R, x, max(T - t, 0), tol=tol, history=history)
@@ -73,14 +93,17 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
     return beta, info
 
 
-def full_pcg(X, Y, seed, r=None, tol=5e-7, T=100):
+def full_pcg(X, Y, seed, r=None, tol=5e-7, T=100, sketch="srht"):
     """Full-data PCG from beta_0 = 0 with the same S_hat preconditioner."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     N, d = X.shape
     r = 6 * d if r is None else int(r)
-    _, _, B_hat, _ = nested_srht(X, Y, seed, 1, r)
-    R = precond_from_sketch(B_hat)
+    if sketch == "cs":
+        R = precond_from_sketch(countsketch(X, seed, r, hat=True), scaled=False)
+    else:
+        _, _, B_hat, _ = nested_srht(X, Y, seed, 1, r)
+        R = precond_from_sketch(B_hat)
     multi = Y.ndim == 2
     Ys = Y if multi else Y[:, None]
     betas, infos = [], []
