@@ -110,7 +110,21 @@ typedef struct spcg_sketch_opts {
     int32_t transform_segment; /* tuning: 0 = library default; 64, 128 or 256 caps the
                                   bytes of each row segment a transform tile holds
                                   (narrower tiles fit more blocks per CU) */
+    int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
+    int32_t reserved; /* set to 0 */
 } spcg_sketch_opts;
+
+/* Sketch operators.  SRHT: Sec. 2.1 / 2.2, the method's default.  COUNT:
+ * the CountSketch of the SPCG-CS variant (Sec. 4.3).  With N' = 2^L as for
+ * the SRHT, row k goes to bucket q(k) mod m with sign s(k), where q is a
+ * keyed Feistel bijection of [0, N') (Philox stream 5) and s is D's sign
+ * (stream 1); bucket b of S M is the sum of s(k) M[k] over its rows, so
+ * every bucket holds floor(N'/m) or ceil(N'/m) padded rows and no scaling is
+ * applied (E[S^T S] = I).  Stage i has m_i buckets (m_i divides m_{i+1}:
+ * S_i M is S_{i+1} M with buckets b + t m_i added).  S_hat draws its own
+ * bijection (stream 6) and signs (stream 7) and has r buckets. */
+#define SPCG_SKETCH_SRHT 0
+#define SPCG_SKETCH_COUNT 1
 
 /* Shape of a built sketch. */
 typedef struct spcg_sketch_info {
@@ -119,6 +133,8 @@ typedef struct spcg_sketch_info {
     int32_t sketch_dtype;   /* element type of the stage rows B (see stage_dtype) */
     int64_t ld;             /* leading dimension of the stored sketch rows */
     int64_t m[64];          /* m_1 .. m_K */
+    int32_t kind;           /* SPCG_SKETCH_SRHT or SPCG_SKETCH_COUNT */
+    int32_t reserved;
 } spcg_sketch_info;
 
 /* Nested SRHT of (X, Y).  With N' = 2^ceil(log2 N) and X, Y zero-padded to
@@ -126,6 +142,10 @@ typedef struct spcg_sketch_info {
  * Walsh-Hadamard matrix, D random signs, P a random permutation) and keeps
  * the rows pi(0..m_K) (nested prefixes: S_i X = rows 0..m_i, scaled by
  * 1/sqrt(m_i)) and pi_hat(0..r) (S_hat X, scaled by 1/sqrt(r)).
+ * With opts.kind = SPCG_SKETCH_COUNT the nested CountSketch above is built
+ * instead: one stored block of m_i rows per stage (bucket sums in a fixed
+ * order, reading every row of X once per sketch) and r bucket rows of S_hat;
+ * k <= 64.
  * X: N x d, any element type.  Y: N x k, SPCG_F64, k >= 1.
  * Errors: SHAPE if N <= d, m_1 <= d, r < d or r > N', k < 1, or Y.rows != N.
  * The handle owns the sketch rows; release with spcg_sketch_free. */
@@ -135,14 +155,16 @@ int spcg_sketch_get_info(const spcg_sketch_t* sk, spcg_sketch_info* info);
 /* Stage view: A = rows 0..m_i of the stored sketch of X (unscaled),
  * b = the same rows of the sketch of Y, *c2 = 1 / m_i, so that
  * c2 A^T A = (S_i X)^T (S_i X).  stage in [0, K); stage = -1 returns the
- * preconditioner sketch rows (b->data = NULL, *c2 = 1 / r).  Views borrow
- * the sketch's memory. */
+ * preconditioner sketch rows (b->data = NULL, *c2 = 1 / r).  For a
+ * CountSketch, A is stage i's block of m_i bucket rows and *c2 = 1 (also
+ * for stage -1).  Views borrow the sketch's memory. */
 int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* b, double* c2);
 /* Copies the sketch randomness to HOST arrays for reproducibility checks
  * (any pointer may be NULL): slot_rows[t] = pi(t) for t < m_K,
  * hat_rows[t] = pi_hat(t) for t < r, input_perm[k] = p(k) for k < N'
  * (W[k] = sign(k) * X[p(k)]), sign_bits[k/8] bit (k%8) set when D_kk = -1.
- * Synchronises the stream. */
+ * SRHT sketches only (INVALID_ARG for a CountSketch).  Synchronises the
+ * stream. */
 int spcg_sketch_export(spcg_ctx* ctx, const spcg_sketch_t* sk, int32_t* slot_rows,
                        int32_t* hat_rows, int32_t* input_perm, uint8_t* sign_bits);
 void spcg_sketch_free(spcg_sketch_t* sk);

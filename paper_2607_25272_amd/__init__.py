@@ -178,10 +178,18 @@ class Precond:
             pass
 
 
+def _sketch_kind(kind):
+    if kind in ("srht", L.SPCG_SKETCH_SRHT):
+        return L.SPCG_SKETCH_SRHT
+    if kind in ("cs", "count", L.SPCG_SKETCH_COUNT):
+        return L.SPCG_SKETCH_COUNT
+    raise ValueError(f"unknown sketch kind {kind!r}")
+
+
 def spcg_sketch(ctx, X, Y=None, seed=1, m0=0, m_max=0, r=0, growth=2, hat_only=False,
-                col_scale=None, stage_dtype=0, transform_segment=0):
+                col_scale=None, stage_dtype=0, transform_segment=0, kind="srht"):
     o = L.SketchOpts(seed=seed, m0=m0, m_max=m_max, r=r, growth=growth, hat_only=int(hat_only),
-                     stage_dtype=stage_dtype, transform_segment=transform_segment)
+                     stage_dtype=stage_dtype, transform_segment=transform_segment, kind=_sketch_kind(kind))
     Xm = mat(X, col_scale)
     Ym = mat(Y) if Y is not None else None
     h = ctypes.c_void_p()
@@ -226,8 +234,9 @@ def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, 
 def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, growth=2,
                qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None,
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
-               record_features=False, stage_dtype=0, transform_segment=0):
-    """spcg_solve_opts from keyword arguments.  schedule='learned' needs
+               record_features=False, stage_dtype=0, transform_segment=0, sketch="srht"):
+    """spcg_solve_opts from keyword arguments (``sketch``: "srht" or "cs",
+    the CountSketch of SPCG-CS).  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
     ``schedule.load_weights``)."""
     o = L.SolveOpts()
@@ -236,6 +245,7 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.sketch.seed, o.sketch.m0, o.sketch.m_max, o.sketch.r, o.sketch.growth = seed, m0, m_max, r, growth
     o.sketch.stage_dtype = stage_dtype
     o.sketch.transform_segment = transform_segment
+    o.sketch.kind = _sketch_kind(sketch)
     o.precond.qr_passes = qr_passes
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every

@@ -24,6 +24,7 @@ SPCG_E_NOMEM = -7
 SPCG_F64, SPCG_F32, SPCG_BF16, SPCG_FP8E4M3 = 0, 1, 2, 3
 SPCG_METHOD_SPCG, SPCG_METHOD_FULL_PCG = 0, 1
 SPCG_SCHEDULE_PLAIN, SPCG_SCHEDULE_LEARNED = 0, 1
+SPCG_SKETCH_SRHT, SPCG_SKETCH_COUNT = 0, 1
 SPCG_MLP_F, SPCG_MLP_H, SPCG_MLP_O = 8, 64, 7
 SPCG_MLP_PARAMS = (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H
                    + SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
@@ -41,13 +42,14 @@ class SpcgMat(ctypes.Structure):
 
 class SketchOpts(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("m0", c_i64), ("m_max", c_i64), ("r", c_i64),
-                ("growth", c_i32), ("hat_only", c_i32), ("stage_dtype", c_i32), ("transform_segment", c_i32)]
+                ("growth", c_i32), ("hat_only", c_i32), ("stage_dtype", c_i32), ("transform_segment", c_i32),
+                ("kind", c_i32), ("reserved", c_i32)]
 
 
 class SketchInfo(ctypes.Structure):
     _fields_ = [("N", c_i64), ("Np", c_i64), ("d", c_i64), ("k", c_i64), ("r", c_i64),
                 ("K", c_i64), ("L", c_i32), ("sketch_dtype", c_i32), ("ld", c_i64),
-                ("m", c_i64 * 64)]
+                ("m", c_i64 * 64), ("kind", c_i32), ("reserved", c_i32)]
 
 
 class PrecondOpts(ctypes.Structure):

@@ -94,6 +94,9 @@ struct spcg_sketch_s {
     int bdtype = DT_F32;   // stage rows B
     uint64_t seed = 0;
     int64_t m[64] = {};
+    int kind = SPCG_SKETCH_SRHT;
+    int64_t off[64] = {};      // CountSketch: first row of stage i in B / BY
+    double hat_c2 = 0.0;       // weight of the S_hat rows: 1/r (SRHT) or 1 (CountSketch)
     bool owns = true;
     DevBuf B, BY, Bh;          // owned storage (when owns)
     void* pB = nullptr;        // active pointers (owned or ctx workspace)
@@ -162,6 +165,81 @@ int ensure_events(spcg_ctx* ctx) {
 
 // ------------------------------------------------------------------ sketch
 
+// Nested CountSketch (SPCG-CS): tables, the finest stage by a gather over
+// its buckets, the coarser stages by folding, and S_hat by its own gather.
+int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_sketch_t* sk, DevBuf& bB,
+                      DevBuf& bBY, DevBuf& bBh) {
+    const int64_t K = sk->K, ld = sk->ld, ldy = sk->ldy, Np = sk->Np;
+    if (K && sk->k > 64) return fail(ctx, SPCG_E_SHAPE, "the CountSketch takes at most 64 right-hand sides");
+    int64_t tot = 0;
+    for (int64_t i = 0; i < K; ++i) {
+        if (i > 0 && sk->m[i] % sk->m[i - 1] != 0)
+            return fail(ctx, SPCG_E_SHAPE, "nested CountSketch sizes must divide each other");
+        sk->off[i] = tot;
+        tot += sk->m[i];
+    }
+    const size_t rowb = (size_t)ld * dtype_bytes(sk->bdtype);
+    if (tot) {
+        HIP_TRY(ctx, bB.ensure((size_t)tot * rowb));
+        HIP_TRY(ctx, bBY.ensure((size_t)tot * ldy * 8));
+    }
+    HIP_TRY(ctx, bBh.ensure((size_t)sk->r * ld * dtype_bytes(sk->dtype)));
+    sk->pB = tot ? bB.p : nullptr;
+    sk->pBY = tot ? bBY.as<double>() : nullptr;
+    sk->pBh = bBh.p;
+    HIP_TRY(ctx, ctx->tables.ensure((size_t)2 * Np * sizeof(int32_t)));
+    int32_t* tbl = ctx->tables.as<int32_t>();
+    int32_t* tbl_hat = tbl + Np;
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, launch_cs_tables(st, sk->seed, sk->L, K ? tbl : nullptr, tbl_hat));
+    CsJob j{};
+    j.x = X->data;
+    j.in_dtype = X->dtype;
+    j.N = sk->N;
+    j.d = sk->d;
+    j.ldx = X->ld;
+    j.col_scale = X->col_scale;
+    j.Np = Np;
+    j.ld = ld;
+    if (K) {
+        const bool f64 = sk->dtype == DT_F64;
+        const bool direct = sk->bdtype == sk->dtype;   // stage rows kept in the sum type
+        const int64_t mK = sk->m[K - 1];
+        char* Bb = static_cast<char*>(sk->pB);
+        void* work = nullptr;
+        if (!direct) {
+            HIP_TRY(ctx, ctx->zbuf.ensure((size_t)mK * ld * 4));
+            work = ctx->zbuf.p;
+        }
+        CsJob s = j;
+        s.y = static_cast<const double*>(Y->data);
+        s.ldy_in = Y->ld;
+        s.k = sk->k;
+        s.tbl = tbl;
+        s.nbk = mK;
+        s.out = Bb + (size_t)sk->off[K - 1] * rowb;
+        s.out_dtype = sk->bdtype;
+        s.work = work;
+        s.outy = sk->pBY + (size_t)sk->off[K - 1] * ldy;
+        s.ldoy = ldy;
+        HIP_TRY(ctx, run_cs_gather(st, s));
+        for (int64_t i = K - 2; i >= 0; --i) {
+            const int g = (int)(sk->m[i + 1] / sk->m[i]);
+            const void* src = direct ? static_cast<const void*>(Bb + (size_t)sk->off[i + 1] * rowb) : work;
+            HIP_TRY(ctx, run_cs_fold(st, f64, src, direct ? nullptr : work, Bb + (size_t)sk->off[i] * rowb,
+                                     sk->bdtype, ld, sk->m[i], g, sk->pBY + (size_t)sk->off[i + 1] * ldy,
+                                     sk->pBY + (size_t)sk->off[i] * ldy, ldy, sk->k));
+        }
+    }
+    CsJob h = j;
+    h.tbl = tbl_hat;
+    h.nbk = sk->r;
+    h.out = sk->pBh;
+    h.out_dtype = sk->dtype;
+    HIP_TRY(ctx, run_cs_gather(st, h));
+    return SPCG_OK;
+}
+
 int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_sketch_opts* o,
                  bool borrow, spcg_sketch_t* sk) {
     int rc;
@@ -225,6 +303,12 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     DevBuf& bB = borrow ? ctx->wsB : sk->B;
     DevBuf& bBY = borrow ? ctx->wsBY : sk->BY;
     DevBuf& bBh = borrow ? ctx->wsBh : sk->Bh;
+    const int kind = o ? o->kind : SPCG_SKETCH_SRHT;
+    if (kind != SPCG_SKETCH_SRHT && kind != SPCG_SKETCH_COUNT)
+        return fail(ctx, SPCG_E_INVALID_ARG, "sketch kind must be SPCG_SKETCH_SRHT or SPCG_SKETCH_COUNT");
+    sk->kind = kind;
+    sk->hat_c2 = kind == SPCG_SKETCH_COUNT ? 1.0 : 1.0 / (double)r;
+    if (kind == SPCG_SKETCH_COUNT) return countsketch_build(ctx, X, Y, sk, bB, bBY, bBh);
     if (mK) {
         HIP_TRY(ctx, bB.ensure((size_t)mK * sk->ld * dtype_bytes(sk->bdtype)));
         HIP_TRY(ctx, bBY.ensure((size_t)mK * sk->ldy * 8));
@@ -356,7 +440,7 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
     DenseStatus* dst = ctx->dense_status.as<DenseStatus>();
     DenseStatus hs{};
     double* R = pc->pR;
-    const double inv_r = 1.0 / (double)r;
+    const double inv_r = sk->hat_c2;   // S_hat X = sqrt(hat_c2) * (stored rows)
     if ((rc = ensure_dense_work(ctx, d, r)) != SPCG_OK) return rc;
     double* wk = ctx->dense_w.as<double>();
     const int64_t we = ctx->dense_w_elems;
@@ -1019,6 +1103,7 @@ int spcg_sketch_get_info(const spcg_sketch_t* sk, spcg_sketch_info* info) {
     info->sketch_dtype = sk->bdtype;
     info->ld = sk->ld;
     for (int64_t i = 0; i < sk->K; ++i) info->m[i] = sk->m[i];
+    info->kind = sk->kind;
     return SPCG_OK;
 }
 
@@ -1026,7 +1111,9 @@ int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* 
     if (!sk || !A) return SPCG_E_INVALID_ARG;
     if (stage < -1 || stage >= sk->K) return SPCG_E_INVALID_ARG;
     const int64_t rows = stage < 0 ? sk->r : sk->m[stage];
-    A->data = stage < 0 ? sk->pBh : sk->pB;
+    const bool cs = sk->kind == SPCG_SKETCH_COUNT;
+    const int64_t row0 = (cs && stage >= 0) ? sk->off[stage] : 0;
+    A->data = stage < 0 ? sk->pBh : static_cast<char*>(sk->pB) + (size_t)row0 * sk->ld * dtype_bytes(sk->bdtype);
     A->dtype = stage < 0 ? sk->dtype : sk->bdtype;
     A->reserved = 1;   // zero-padded rows: columns up to ld may be read
     A->rows = rows;
@@ -1034,7 +1121,7 @@ int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* 
     A->ld = sk->ld;
     A->col_scale = nullptr;
     if (b) {
-        b->data = stage < 0 ? nullptr : sk->pBY;
+        b->data = stage < 0 ? nullptr : sk->pBY + (size_t)row0 * sk->ldy;
         b->dtype = SPCG_F64;
         b->reserved = 0;
         b->rows = stage < 0 ? 0 : rows;
@@ -1042,13 +1129,14 @@ int spcg_sketch_view(const spcg_sketch_t* sk, int stage, spcg_mat* A, spcg_mat* 
         b->ld = sk->ldy;
         b->col_scale = nullptr;
     }
-    if (c2) *c2 = 1.0 / (double)rows;
+    if (c2) *c2 = stage < 0 ? sk->hat_c2 : (cs ? 1.0 : 1.0 / (double)rows);
     return SPCG_OK;
 }
 
 int spcg_sketch_export(spcg_ctx* ctx, const spcg_sketch_t* sk, int32_t* slot_rows, int32_t* hat_rows,
                        int32_t* input_perm, uint8_t* sign_bits) {
     if (!ctx || !sk) return SPCG_E_INVALID_ARG;
+    if (sk->kind != SPCG_SKETCH_SRHT) return fail(ctx, SPCG_E_INVALID_ARG, "export covers SRHT sketches only");
     const int64_t mK = sk->K ? sk->m[sk->K - 1] : 0;
     const size_t n_slot = (size_t)mK, n_hat = (size_t)sk->r, n_perm = (size_t)sk->Np,
                  n_sign = (size_t)(sk->Np / 8 > 0 ? sk->Np / 8 : 1);

@@ -1,0 +1,277 @@
+// Nested CountSketch (the SPCG-CS variant of Sec. 4.3) on gfx950.
+//
+// A CountSketch with m buckets adds every row k of the data, times a random
+// sign s(k), into bucket h(k): (S M)[b] = sum_{h(k) = b} s(k) M[k] (a sparse
+// operator, Sec. 2.1; O(Nd) work, the remark after Theorem 3.4).  Buckets
+// come from a keyed bijection q of the padded rows [0, N'): h(k) = q(k) mod m,
+// so each bucket receives floor(N'/m) or ceil(N'/m) rows and nested sizes
+// m_i | m_{i+1} give S_i M by folding S_{i+1} M (buckets b + t m_i added).
+//
+// The gather kernel inverts the map: a table lists, for every slot y, the
+// row k with q(k) = y and its sign, and bucket b sums the rows of slots
+// b, b + m, b + 2m, ... in that order (fixed order, no atomics).  One wave
+// handles one (bucket, 256-column window) pair and keeps up to four whole
+// row segments in flight; the rows are random, but each segment is 1 KB
+// (FP32) or more of contiguous memory.  Every row of X is read exactly once
+// per sketch.
+#include <type_traits>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace spcg {
+
+namespace {
+
+constexpr int CS_WAVES = 4;     // waves per block
+constexpr int CS_WIN = 256;     // columns per wave task (4 per lane)
+constexpr int CS_MU = 4;        // member rows in flight per wave
+
+__global__ void cs_tables_kernel(uint64_t seed, int L, int64_t np, int32_t* tbl, int32_t* tbl_hat) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= np) return;
+    if (tbl) {
+        const uint64_t k = feistel_inv((uint64_t)y, L, seed, STREAM_CS);
+        tbl[y] = (int32_t)((uint32_t)k | (sign_bit(seed, k) << 31));
+    }
+    if (tbl_hat) {
+        const uint64_t k = feistel_inv((uint64_t)y, L, seed, STREAM_CS_HAT);
+        tbl_hat[y] = (int32_t)((uint32_t)k | (sign_bit_stream(seed, k, STREAM_CS_HAT_SIGN) << 31));
+    }
+}
+
+// Four consecutive elements of row `row` from column c, widened; zeros
+// beyond d.
+template <typename TIN, typename TZ>
+struct Load4;
+template <>
+struct Load4<double, double> {
+    __device__ static void run(const void* x, int64_t row, int64_t ldx, int64_t c, int64_t d, bool vec, const float*,
+                               double* o) {
+        const double* p = static_cast<const double*>(x) + row * ldx + c;
+        if (vec && c + 4 <= d) {
+            const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+            o[0] = a.x;
+            o[1] = a.y;
+            o[2] = b.x;
+            o[3] = b.y;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = c + e < d ? p[e] : 0.0;
+        }
+    }
+};
+template <>
+struct Load4<float, float> {
+    __device__ static void run(const void* x, int64_t row, int64_t ldx, int64_t c, int64_t d, bool vec, const float*,
+                               float* o) {
+        const float* p = static_cast<const float*>(x) + row * ldx + c;
+        if (vec && c + 4 <= d) {
+            const float4 a = *reinterpret_cast<const float4*>(p);
+            o[0] = a.x;
+            o[1] = a.y;
+            o[2] = a.z;
+            o[3] = a.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = c + e < d ? p[e] : 0.f;
+        }
+    }
+};
+template <>
+struct Load4<bf16_t, float> {
+    __device__ static void run(const void* x, int64_t row, int64_t ldx, int64_t c, int64_t d, bool vec, const float*,
+                               float* o) {
+        const uint16_t* p = static_cast<const uint16_t*>(x) + row * ldx + c;
+        if (vec && c + 4 <= d) {
+            const uint2 a = *reinterpret_cast<const uint2*>(p);
+            o[0] = __uint_as_float(a.x << 16);
+            o[1] = __uint_as_float(a.x & 0xffff0000u);
+            o[2] = __uint_as_float(a.y << 16);
+            o[3] = __uint_as_float(a.y & 0xffff0000u);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = c + e < d ? bf16_bits_to_f32(p[e]) : 0.f;
+        }
+    }
+};
+template <>
+struct Load4<fp8_t, float> {
+    __device__ static void run(const void* x, int64_t row, int64_t ldx, int64_t c, int64_t d, bool vec,
+                               const float* sc, float* o) {
+        const uint8_t* p = static_cast<const uint8_t*>(x) + row * ldx + c;
+        if (vec && c + 4 <= d) {
+            const uint32_t a = *reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = fp8e4m3_bits_to_f32((a >> (8 * e)) & 0xffu) * sc[c + e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = c + e < d ? fp8e4m3_bits_to_f32(p[e]) * sc[c + e] : 0.f;
+        }
+    }
+};
+
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <typename TZ>
+__device__ __forceinline__ void store4(void* out, int out_dtype, int64_t idx, const TZ* v) {
+    if constexpr (std::is_same<TZ, double>::value) {
+        double2* p = reinterpret_cast<double2*>(static_cast<double*>(out) + idx);
+        p[0] = make_double2(v[0], v[1]);
+        p[1] = make_double2(v[2], v[3]);
+    } else {
+        if (out_dtype == DT_BF16) {
+            const uint32_t w0 = f32_to_bf16_rne(v[0]) | (f32_to_bf16_rne(v[1]) << 16);
+            const uint32_t w1 = f32_to_bf16_rne(v[2]) | (f32_to_bf16_rne(v[3]) << 16);
+            *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + idx) = make_uint2(w0, w1);
+        } else {
+            *reinterpret_cast<float4*>(static_cast<float*>(out) + idx) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+struct GatherArgs {
+    CsJob j;
+    int nwin;      // 256-column windows per row (ld / 256 rounded up)
+    int xvec;      // rows allow aligned 4-element loads
+};
+
+template <typename TIN, typename TZ>
+__global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) {
+    const CsJob& j = a.j;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nwaves = (int64_t)gridDim.x * CS_WAVES;
+    const int64_t ntask = j.nbk * a.nwin;
+    const bool vec = a.xvec != 0;
+    for (int64_t task = wave0; task < ntask; task += nwaves) {
+        const int64_t b = task / a.nwin;
+        const int w = (int)(task - b * a.nwin);
+        const int64_t c = (int64_t)w * CS_WIN + 4 * lane;
+        const bool do_y = j.outy && w == 0;
+        TZ acc[4] = {TZ(0), TZ(0), TZ(0), TZ(0)};
+        double yacc = 0.0;
+        for (int64_t y0 = b; y0 < j.Np; y0 += CS_MU * j.nbk) {
+            int32_t e[CS_MU];
+#pragma unroll
+            for (int u = 0; u < CS_MU; ++u) {
+                const int64_t yv = y0 + (int64_t)u * j.nbk;
+                e[u] = yv < j.Np ? j.tbl[yv] : 0x7fffffff;   // past the end: no row
+            }
+            TZ v[CS_MU][4];
+            double yv_[CS_MU];
+#pragma unroll
+            for (int u = 0; u < CS_MU; ++u) {
+                const int64_t k = e[u] & 0x7fffffff;
+                yv_[u] = 0.0;
+                if (k < j.N) {
+                    Load4<TIN, TZ>::run(j.x, k, j.ldx, c, j.d, vec, j.col_scale, v[u]);
+                    if (do_y && lane < j.k) yv_[u] = j.y[k * j.ldy_in + lane];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[u][q] = TZ(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CS_MU; ++u) {
+                const bool neg = e[u] < 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += neg ? -v[u][q] : v[u][q];
+                yacc += neg ? -yv_[u] : yv_[u];
+            }
+        }
+        if (c < j.ld) {
+            store4<TZ>(j.out, j.out_dtype, b * j.ld + c, acc);
+            if (j.work) store4<TZ>(j.work, std::is_same<TZ, double>::value ? DT_F64 : DT_F32, b * j.ld + c, acc);
+        }
+        if (do_y && lane < j.ldoy) j.outy[b * j.ldoy + lane] = lane < j.k ? yacc : 0.0;
+    }
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(256) void cs_fold_kernel(const TZ* src, TZ* work, void* dst, int out_dtype, int64_t ld,
+                                                      int64_t mc, int g) {
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;   // first of 4 columns
+    if (e >= mc * ld) return;
+    const int64_t b = e / ld, c = e - b * ld;
+    TZ v[4] = {TZ(0), TZ(0), TZ(0), TZ(0)};
+    for (int t = 0; t < g; ++t) {
+        const TZ* p = src + (b + (int64_t)t * mc) * ld + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += p[q];
+    }
+    if (work) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) work[b * ld + c + q] = v[q];
+    }
+    store4<TZ>(dst, out_dtype, b * ld + c, v);
+}
+
+__global__ __launch_bounds__(256) void cs_fold_y_kernel(const double* src, double* dst, int64_t ldy, int64_t mc, int g) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mc * ldy) return;
+    const int64_t b = e / ldy, c = e - b * ldy;
+    double v = 0.0;
+    for (int t = 0; t < g; ++t) v += src[(b + (int64_t)t * mc) * ldy + c];
+    dst[e] = v;
+}
+
+template <typename TIN, typename TZ>
+hipError_t gather_launch(hipStream_t st, const GatherArgs& a) {
+    const int64_t ntask = a.j.nbk * a.nwin;
+    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES), 65536);
+    cs_gather_kernel<TIN, TZ><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat) {
+    const int64_t np = 1ll << L;
+    cs_tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, tbl, tbl_hat);
+    return hipGetLastError();
+}
+
+hipError_t run_cs_gather(hipStream_t st, const CsJob& j) {
+    const bool f64 = j.in_dtype == DT_F64;
+    if (j.nbk <= 0 || j.ld < j.d || j.ld % 4 != 0 || j.Np >= (1ll << 31) || j.N > j.Np) return hipErrorInvalidValue;
+    if (f64 != (j.out_dtype == DT_F64)) return hipErrorInvalidValue;
+    if (j.outy && (j.k < 1 || j.k > 64 || j.ldoy < j.k || j.ldoy > 64)) return hipErrorInvalidValue;
+    GatherArgs a{};
+    a.j = j;
+    a.nwin = (int)ceil_div(j.ld, CS_WIN);
+    const int es = dtype_bytes(j.in_dtype);
+    a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
+    switch (j.in_dtype) {
+        case DT_F64: return gather_launch<double, double>(st, a);
+        case DT_F32: return gather_launch<float, float>(st, a);
+        case DT_BF16: return gather_launch<bf16_t, float>(st, a);
+        case DT_FP8: return gather_launch<fp8_t, float>(st, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t run_cs_fold(hipStream_t st, bool f64, const void* src, void* work, void* dst, int out_dtype, int64_t ld,
+                       int64_t mc, int g, const double* ysrc, double* ydst, int64_t ldy, int64_t k) {
+    if (mc <= 0 || g < 1 || ld % 4 != 0) return hipErrorInvalidValue;
+    const int64_t n4 = mc * ld / 4;
+    const unsigned blocks = (unsigned)ceil_div(n4, 256);
+    if (f64) {
+        cs_fold_kernel<double><<<blocks, 256, 0, st>>>(static_cast<const double*>(src), static_cast<double*>(work),
+                                                       dst, out_dtype, ld, mc, g);
+    } else {
+        cs_fold_kernel<float><<<blocks, 256, 0, st>>>(static_cast<const float*>(src), static_cast<float*>(work), dst,
+                                                      out_dtype, ld, mc, g);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !ysrc) return e;
+    (void)k;
+    cs_fold_y_kernel<<<(unsigned)ceil_div(mc * ldy, 256), 256, 0, st>>>(ysrc, ydst, ldy, mc, g);
+    return hipGetLastError();
+}
+
+}  // namespace spcg

@@ -9,6 +9,7 @@
 // which maps onto GPU-friendly pieces: a tiled GEMM, a blocked right-looking
 // Cholesky and a blocked triangular solve.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "common.hpp"
@@ -136,10 +137,14 @@ __global__ void splitk_reduce_kernel(const double* part, int nz, int64_t M, int6
 // Upper Cholesky of the nb x nb diagonal block at (k0, k0) of G, in place
 // (strict lower part zeroed).
 // 256 threads in a 16 x 16 grid; each keeps a 4 x 4 patch of the block in
-// registers.  Step j needs only the scaled pivot row j: the 16 threads of a
-// patch row share one wave, so the wave that owns row j + 1 reads its pivot
-// with a lane broadcast as soon as step j has updated it, scales the row
-// and publishes it through LDS (double-buffered).  One barrier per step.
+// registers.  Step j needs only w = row j of U right of the diagonal
+// (w[l] = U[j][l] for l > j, 0 otherwise): every patch then takes
+// a[i][l] -= w[i] w[l] without conditions (rows i <= j see w[i] = 0; the
+// strict lower part collects values that are never used).  The 16 threads
+// of a patch row share one wave, so the wave that owns row j + 1 reads its
+// pivot with a lane broadcast right after its own update, scales the row
+// and publishes w through LDS (double-buffered): one barrier per step.  The
+// step loop is unrolled by 4 so that the row inside a patch is static.
 __device__ __forceinline__ double bcast_lane(double v, int lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
@@ -149,7 +154,7 @@ __device__ __forceinline__ double bcast_lane(double v, int lane) {
 
 __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, int64_t k0, int nb,
                                                         DenseStatus* st) {
-    __shared__ double rows[2][CB];
+    __shared__ __align__(16) double rows[2][CB];
     __shared__ double pivs[CB];
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
@@ -162,53 +167,67 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, i
             const int i = ty * 4 + r, j = tx * 4 + c;
             a[r][c] = (i < nb && j < nb && j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
         }
-    // scale row j (held by patch row j / 4, i.e. wave j / 16) and publish it
-    auto publish = [&](int j) __attribute__((always_inline)) {
-        const int jr = j & 3, jb = j >> 2;
+    // row j = 4 jb + JR: scale it in place and publish w (wave jb / 4 only)
+    auto publish = [&](int jb, auto jr_c) __attribute__((always_inline)) {
+        constexpr int JR = decltype(jr_c)::value;
+        const int j = 4 * jb + JR;
         if (wave != (jb >> 2)) return;
-        double dg = a[0][0];
-#pragma unroll
-        for (int r = 1; r < 4; ++r)
-            if (r == jr) dg = a[r][r];
-        // the pivot (j, j) sits in patch (jb, jb): lane 16 (jb mod 4) + jb
-        const double piv = bcast_lane(dg, (jb & 3) * 16 + jb);
-        double u = piv;
-        if (!(u > 0.0) || !__builtin_isfinite(u)) u = 1.0;
-        u = sqrt(u);
+        // the pivot (j, j) sits in patch (jb, jb) at (JR, JR): lane 16 (jb mod 4) + jb
+        const double piv = bcast_lane(a[JR][JR], (jb & 3) * 16 + jb);
+        const bool bad = !(piv > 0.0) || !__builtin_isfinite(piv);
+        const double u = bad ? 1.0 : sqrt(piv);
         const double ru = 1.0 / u;
         if (ty == jb) {
+            double w[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (r != jr) continue;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int l = tx * 4 + c;
-                    if (l == j) a[r][c] = u;
-                    else if (l > j) a[r][c] *= ru;
-                    rows[j & 1][l] = l >= j ? a[r][c] : 0.0;
-                }
+            for (int c = 0; c < 4; ++c) {
+                const bool right = tx > jb || (tx == jb && c > JR);
+                const bool diag = tx == jb && c == JR;
+                const double v = a[JR][c] * ru;
+                a[JR][c] = diag ? u : (right ? v : a[JR][c]);
+                w[c] = right ? v : 0.0;
             }
+            *reinterpret_cast<double2*>(&rows[j & 1][tx * 4]) = make_double2(w[0], w[1]);
+            *reinterpret_cast<double2*>(&rows[j & 1][tx * 4 + 2]) = make_double2(w[2], w[3]);
             if (tx == jb) pivs[j] = piv;
         }
     };
-    publish(0);
-    for (int j = 0; j < nb; ++j) {
-        __syncthreads();   // row j published; row j - 1's buffer no longer read
-        const double* rj = rows[j & 1];
-        // trailing update of rows i > j: a[i][l] -= U[j][i] U[j][l] (l >= i)
+    auto update = [&](int j) __attribute__((always_inline)) {
+        const double* w = rows[j & 1];
+        const double2 wi0 = *reinterpret_cast<const double2*>(&w[ty * 4]);
+        const double2 wi1 = *reinterpret_cast<const double2*>(&w[ty * 4 + 2]);
+        const double2 wl0 = *reinterpret_cast<const double2*>(&w[tx * 4]);
+        const double2 wl1 = *reinterpret_cast<const double2*>(&w[tx * 4 + 2]);
+        const double wi[4] = {wi0.x, wi0.y, wi1.x, wi1.y};
+        const double wl[4] = {wl0.x, wl0.y, wl1.x, wl1.y};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ty * 4 + r;
-            if (i > j && i < nb) {
-                const double uji = rj[i];
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int l = tx * 4 + c;
-                    if (l >= i && l < nb) a[r][c] = fma(-uji, rj[l], a[r][c]);
-                }
-            }
-        }
-        if (j + 1 < nb) publish(j + 1);
+            for (int c = 0; c < 4; ++c) a[r][c] = fma(-wi[r], wl[c], a[r][c]);
+    };
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
+    using C3 = std::integral_constant<int, 3>;
+    publish(0, C0{});
+    for (int jb = 0; 4 * jb < nb; ++jb) {
+        const int j = 4 * jb;
+        __syncthreads();
+        update(j);
+        if (j + 1 >= nb) break;
+        publish(jb, C1{});
+        __syncthreads();
+        update(j + 1);
+        if (j + 2 >= nb) break;
+        publish(jb, C2{});
+        __syncthreads();
+        update(j + 2);
+        if (j + 3 >= nb) break;
+        publish(jb, C3{});
+        __syncthreads();
+        update(j + 3);
+        if (j + 4 >= nb) break;
+        publish(jb + 1, C0{});
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)

@@ -49,6 +49,36 @@ inline int fwht_chunk_cols(int in_dtype, int narrow) {
 inline int64_t sketch_ld(int64_t d, bool f64) { return round_up(d, f64 ? 32 : 64); }
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
 
+// ----------------------------------------------------------- CountSketch
+// Bucket tables for a padded size Np = 2^L: entry y holds the row k with
+// q(k) = y (q the bucket bijection) and its sign in bit 31.  Bucket b of an
+// m-bucket sketch gathers the entries y = b, b + m, b + 2m, ... < Np.
+hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat);
+
+struct CsJob {
+    const void* x;            // N x d input rows, element type in_dtype, leading dim ldx
+    int in_dtype;             // DT_*; sums are FP64 for DT_F64 input, FP32 otherwise
+    int64_t N, d, ldx;
+    const float* col_scale;   // FP8 only
+    const double* y;          // N x k FP64 responses (may be null)
+    int64_t ldy_in, k;
+    const int32_t* tbl;       // bucket table (see launch_cs_tables)
+    int64_t Np, nbk;          // padded rows; buckets
+    void* out;                // nbk x ld rows (element type out_dtype), zero beyond d
+    int out_dtype;            // DT_F64, DT_F32 or DT_BF16
+    void* work;               // optional nbk x ld copy in the sum type, or null
+    int64_t ld;
+    double* outy;             // nbk x ldoy sketched responses, or null
+    int64_t ldoy;
+};
+hipError_t run_cs_gather(hipStream_t st, const CsJob& job);
+// Folding to a coarser nested sketch: dst[b] = sum_{t < g} src[b + t mc]
+// (ascending t) for b < mc.  src and work hold rows in the sum type (FP64 for
+// f64, else FP32; work may equal src); dst takes out_dtype.  Also the
+// sketched responses (FP64) when ysrc is set.
+hipError_t run_cs_fold(hipStream_t st, bool f64, const void* src, void* work, void* dst, int out_dtype, int64_t ld,
+                       int64_t mc, int g, const double* ysrc, double* ydst, int64_t ldy, int64_t k);
+
 // --------------------------------------------------------------- product
 enum ProdMode : int { PM_S = 0, PM_G = 1, PM_SG = 2 };
 

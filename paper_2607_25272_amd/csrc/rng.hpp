@@ -27,7 +27,17 @@
 
 namespace spcg {
 
-enum : uint64_t { STREAM_SIGN = 1, STREAM_P = 2, STREAM_PI = 3, STREAM_PIHAT = 4 };
+enum : uint64_t {
+    STREAM_SIGN = 1,
+    STREAM_P = 2,
+    STREAM_PI = 3,
+    STREAM_PIHAT = 4,
+    // CountSketch: bucket bijection of the stage sketches, and the
+    // preconditioner sketch's own bijection and signs
+    STREAM_CS = 5,
+    STREAM_CS_HAT = 6,
+    STREAM_CS_HAT_SIGN = 7
+};
 constexpr int FEISTEL_ROUNDS = 6;
 
 SPCG_HD inline void mul_hilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
@@ -73,12 +83,15 @@ SPCG_HD inline Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint
     return out;
 }
 
-// 1 when D_kk = -1.
-SPCG_HD inline uint32_t sign_bit(uint64_t seed, uint64_t k) {
-    Philox4 w = philox4x64_10(k >> 8, 0, 0, 0, seed, STREAM_SIGN);
+// 1 when the sign of row k in the given stream is -1 (D_kk for STREAM_SIGN).
+SPCG_HD inline uint32_t sign_bit_stream(uint64_t seed, uint64_t k, uint64_t stream) {
+    Philox4 w = philox4x64_10(k >> 8, 0, 0, 0, seed, stream);
     uint32_t b = (uint32_t)(k & 255);
     return (uint32_t)((w.v[b >> 6] >> (b & 63)) & 1ull);
 }
+
+// 1 when D_kk = -1.
+SPCG_HD inline uint32_t sign_bit(uint64_t seed, uint64_t k) { return sign_bit_stream(seed, k, STREAM_SIGN); }
 
 SPCG_HD inline uint64_t feistel_round(uint64_t half, int rnd, int L, uint64_t seed, uint64_t stream) {
     return philox4x64_10(half, (uint64_t)rnd, (uint64_t)L, 0, seed, stream).v[0];
