@@ -6,10 +6,12 @@ test) of a synthetic least-squares problem already resident in HBM.
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
-                    [--workload cfg1|cfg2|cfg2fp8|batched|learned|paper]
+                    [--workload cfg1|cfg2|cfg2fp8|cfg1cs|cfg2cs|batched|learned|paper]
 
 cfg1 (default)  N=1e6, d=500, FP32 storage
 cfg2 / cfg2fp8  N=4e6, d=1000, BF16 / FP8-e4m3 storage (precision form)
+cfg1cs / cfg2cs the same problems solved by SPCG-CS (CountSketch sketches,
+                Sec. 4.3); SPCG-SRHT and full PCG are timed beside it
 batched         256 independent problems, N in [5e4, 5e5], d in [32, 512],
                 1..16 right-hand sides, FP32 (batched / multi-RHS form)
 learned         N=2e6, d=256, 1% of rows scaled by 100: plain vs learned schedule
@@ -39,6 +41,12 @@ WORKLOADS = {
     "cfg2fp8": dict(cfg=2, storage="fp8",
                     desc="X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; "
                          "N=4000000, d=1000; sigma=0.5; X stored FP8 e4m3 with per-column scales"),
+    "cfg1cs": dict(cfg=1, storage="f32", sketch="cs", base="cfg1",
+                   desc="X = G diag(s), G Gaussian, s log-spaced 1..1e4; N=1000000, d=500; sigma=1; "
+                        "X stored FP32; SPCG-CS (nested CountSketch)"),
+    "cfg2cs": dict(cfg=2, storage="bf16", sketch="cs", base="cfg2",
+                   desc="X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; "
+                        "N=4000000, d=1000; sigma=0.5; X stored BF16; SPCG-CS (nested CountSketch)"),
     "learned": dict(cfg=4, storage="f32",
                     desc="X = G diag(s), s log-spaced 1..1e4, a seeded 1% of rows scaled by 100; "
                          "N=2000000, d=256; sigma=1; X stored FP32; plain vs learned schedule"),
@@ -138,6 +146,9 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
     beta = torch.zeros(d, dtype=torch.float64, device=dev)
     W = None
     methods = ["spcg", "pcg"]
+    sketch = wl.get("sketch", "srht")
+    if sketch == "cs":
+        methods = ["spcg", "spcg_srht", "pcg"]
     if args.workload == "learned":
         from paper_2607_25272_amd import schedule
         W = schedule.load_weights(dev)
@@ -145,7 +156,8 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
 
     def make(method):
         def solve(time_products=False, time_phases=False):
-            kw = dict(time_products=time_products, time_phases=time_phases, seed=1, col_scale=p.col_scale)
+            kw = dict(time_products=time_products, time_phases=time_phases, seed=1, col_scale=p.col_scale,
+                      sketch="srht" if method == "spcg_srht" else sketch)
             if method == "learned":
                 kw.update(schedule="learned", weights=W)
             _, st = spcg.spcg_solve(ctx, p.X, p.Y, beta=beta, method="pcg" if method == "pcg" else "spcg",
@@ -174,7 +186,8 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
     n_launch = sum(r["prod_n"] for r in res.values())
     avg_ms = sum(r["prod_ms"] for r in res.values()) / max(n_launch, 1)
     rf = roofline(avg_ms, n_launch, bpl, "product_ring_kernel (SG mode, full data)")
-    rf["traffic"] = SG_TRAFFIC_BYTES.get(args.workload)
+    # the same product kernel streams the same X for the CountSketch variants
+    rf["traffic"] = SG_TRAFFIC_BYTES.get(wl.get("base", args.workload))
     cpu = None
     if not args.no_cpu_baseline:
         n_s = min(args.cpu_sample, N // 2)
@@ -190,7 +203,8 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": wl["desc"], "tol": 5e-7, "a_i": sp["stats"]["policy_a"], "r": 6 * d,
                    "m_1": 4 * d, "stage_stride": sp["stats"]["policy_stride"], "K": sp["stats"]["K"],
-                   "T_stage1": sp["stats"]["T_stage1"], "T_stage2": sp["stats"]["T_stage2"]},
+                   "T_stage1": sp["stats"]["T_stage1"], "T_stage2": sp["stats"]["T_stage2"],
+                   "sketch": "CountSketch (SPCG-CS)" if sketch == "cs" else "SRHT"},
         "full_pcg_s": pc["s"], "full_pcg_iters": pc["stats"]["T_stage2"],
         "speedup_vs_full_pcg": pc["s"] / sp["s"],
         "rel_pred_error_vs_ols": {m: res[m]["rel"] for m in res},
@@ -200,6 +214,9 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
         "host_syncs": {m: res[m]["stats"]["host_syncs"] for m in res},
         "roofline": rf, "cpu_baseline": cpu,
     }
+    if sketch == "cs":
+        out["spcg_srht_s"] = res["spcg_srht"]["s"]
+        out["cs_speedup_vs_srht"] = res["spcg_srht"]["s"] / sp["s"]
     if args.workload == "learned":
         out["plain_schedule_s"] = res["spcg"]["s"]
         out["learned_gain_vs_plain"] = res["spcg"]["s"] / sp["s"]

@@ -254,6 +254,13 @@ typedef struct spcg_solve_opts {
                                  count before the unchecked run (0: 1, < 0: none) */
     int32_t record_features;  /* 1: also compute the schedule features under the
                                  plain schedule (returned in the stats) */
+    int32_t batch_direct;     /* batched form: 1 launches every pass directly; 0 (default)
+                                 captures each Stage I stage, and the Stage II product and
+                                 d-space launches of each active set, in hipGraphs */
+    int32_t batch_tasks_per_cu; /* batched form, full-data passes: tasks per CU of each
+                                   row-width class launch; 0 (default) autotunes it once per
+                                   context and storage type, timing one product pass with
+                                   2, 4 and 8 (results are discarded) */
 } spcg_solve_opts;
 
 /* Plain schedule: Algorithm 1 as written (a_i = a, every prefix, stopping
@@ -296,6 +303,8 @@ typedef struct spcg_solve_stats {
     float features_ii[8];
     float out_pre[8];           /* network outputs (learned; entries 0..6) */
     float out_ii[8];
+    int32_t batch_tasks_per_cu; /* batched form: task granularity used in Stage II */
+    int32_t batch_graphs;       /* batched form: executable graphs launched */
 } spcg_solve_stats;
 
 /* beta (DEVICE, d x k row-major FP64) <- Algorithm 1 (or full-data PCG)

@@ -234,7 +234,8 @@ def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, 
 def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, growth=2,
                qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None,
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
-               record_features=False, stage_dtype=0, transform_segment=0, sketch="srht"):
+               record_features=False, stage_dtype=0, transform_segment=0, sketch="srht",
+               batch_direct=False, batch_tasks_per_cu=0):
     """spcg_solve_opts from keyword arguments (``sketch``: "srht" or "cs",
     the CountSketch of SPCG-CS).  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
@@ -246,6 +247,8 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.sketch.stage_dtype = stage_dtype
     o.sketch.transform_segment = transform_segment
     o.sketch.kind = _sketch_kind(sketch)
+    o.batch_direct = int(batch_direct)
+    o.batch_tasks_per_cu = batch_tasks_per_cu
     o.precond.qr_passes = qr_passes
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every

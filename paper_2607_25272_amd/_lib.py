@@ -72,7 +72,7 @@ class SolveOpts(ctypes.Structure):
                 ("a_list", ctypes.POINTER(c_i32)), ("a_list_len", c_i32),
                 ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
                 ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
-                ("record_features", c_i32)]
+                ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -85,7 +85,7 @@ class SolveStats(ctypes.Structure):
                 ("fallback", c_i32), ("s_pred", ctypes.c_float), ("rho_ii0", c_f64),
                 ("ax2_ii0", c_f64), ("resid2_ii0", c_f64), ("features_pre", ctypes.c_float * 8),
                 ("features_ii", ctypes.c_float * 8), ("out_pre", ctypes.c_float * 8),
-                ("out_ii", ctypes.c_float * 8)]
+                ("out_ii", ctypes.c_float * 8), ("batch_tasks_per_cu", c_i32), ("batch_graphs", c_i32)]
 
 
 P = ctypes.POINTER

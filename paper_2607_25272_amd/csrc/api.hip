@@ -727,11 +727,35 @@ struct BatchWork {
     std::vector<spcg_sketch_t*> sk;
     std::vector<spcg_precond_t*> pc;
     DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal, bestx;
+    // one stream per row-width class (the class launches of a pass run
+    // concurrently), a private stream for graph capture, fork/join events
+    hipStream_t cls[MR_NCLASS] = {};
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr, join[MR_NCLASS] = {}, tune[2] = {};
+    int tasks_per_cu[4] = {};   // autotuned task granularity per storage type (0: not yet)
     ~BatchWork() {
         for (auto* p : sk) delete p;
         for (auto* p : pc) delete p;
+        for (auto& q : cls)
+            if (q) (void)hipStreamDestroy(q);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto& e : join)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : tune)
+            if (e) (void)hipEventDestroy(e);
     }
 };
+
+int batch_streams(spcg_ctx* ctx, BatchWork& W) {
+    if (W.cap) return SPCG_OK;
+    for (auto& q : W.cls) HIP_TRY(ctx, hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&W.fork, hipEventDisableTiming));
+    for (auto& e : W.join) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : W.tune) HIP_TRY(ctx, hipEventCreate(&e));
+    return SPCG_OK;
+}
 
 constexpr int MR_VECS = 6;   // X G Z P S Gt
 
@@ -773,13 +797,25 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
     return (int)tasks.size();
 }
 
-int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, const std::vector<MrhsProblem>& hp,
-                 int64_t target_tasks, ProductTimer* timer = nullptr) {
+// The task list of one active set, uploaded once and reused by every pass
+// over that set (stream synchronisations before the buffers may grow and
+// after the upload: the host arrays are pageable).
+struct BatchPlan {
+    int nt = 0;
+    int nprob = 0;
+    int seg[MR_NCLASS + 1] = {};
+};
+
+int batched_setup(spcg_ctx* ctx, BatchWork& W, int dtype, const std::vector<MrhsProblem>& hp, int64_t target_tasks,
+                  BatchPlan& plan) {
+    // earlier passes (or graphs) may still read the buffers that grow below
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<MrhsTask> tasks;
     std::vector<MrhsProblem> probs;
-    int seg[MR_NCLASS + 1];
-    const int nt = build_tasks(dtype, hp, tasks, probs, target_tasks, seg);
+    const int nt = build_tasks(dtype, hp, tasks, probs, target_tasks, plan.seg);
     if (nt < 0) return fail(ctx, SPCG_E_SHAPE, "a batched matrix has an unsupported row layout");
+    plan.nt = nt;
+    plan.nprob = (int)probs.size();
     const size_t per_task = (size_t)mrhs_max_d() * mrhs_max_k();
     HIP_TRY(ctx, W.tasks.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
     HIP_TRY(ctx, W.probs.ensure(probs.size() * sizeof(MrhsProblem)));
@@ -790,24 +826,90 @@ int batched_pass(spcg_ctx* ctx, BatchWork& W, int dtype, int mode, int variant, 
     if (nt)
         HIP_TRY(ctx, hipMemcpyAsync(W.tasks.p, tasks.data(), tasks.size() * sizeof(MrhsTask), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(W.probs.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
-    const bool timed = timer && timer->used < MAX_TIMED;
-    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], st));
-    for (int c = 0; c < MR_NCLASS; ++c) {
-        const int n = seg[c + 1] - seg[c];
-        if (n > 0)
-            HIP_TRY(ctx, run_mrhs_product(st, dtype, mode, c, W.tasks.as<MrhsTask>(), seg[c], n,
-                                          W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
-                                          W.part_scal.as<float>()));
-    }
-    if (timed) {
-        HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used + 1], st));
-        timer->used++;
-    }
-    HIP_TRY(ctx, run_mrhs_dspace(st, variant, W.probs.as<MrhsProblem>(), (int)probs.size(), W.part_s.as<float>(),
-                                 W.part_g.as<float>(), W.part_scal.as<float>()));
-    // the pageable task/problem arrays above go out of scope: finish the copies
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return SPCG_OK;
+}
+
+// The product launches of one pass on stream st: each row-width class on
+// its own stream (the classes write disjoint task partials), joined back
+// into st.  Launches only: safe to capture.
+int batched_products(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int dtype, int mode, const BatchPlan& plan) {
+    int used = 0;
+    for (int c = 0; c < MR_NCLASS; ++c) used += plan.seg[c + 1] > plan.seg[c];
+    if (used > 1) HIP_TRY(ctx, hipEventRecord(W.fork, st));
+    for (int c = 0; c < MR_NCLASS; ++c) {
+        const int n = plan.seg[c + 1] - plan.seg[c];
+        if (n <= 0) continue;
+        hipStream_t sc = st;
+        if (used > 1) {
+            sc = W.cls[c];
+            HIP_TRY(ctx, hipStreamWaitEvent(sc, W.fork, 0));
+        }
+        HIP_TRY(ctx, run_mrhs_product(sc, dtype, mode, c, W.tasks.as<MrhsTask>(), plan.seg[c], n,
+                                      W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
+                                      W.part_scal.as<float>()));
+        if (used > 1) {
+            HIP_TRY(ctx, hipEventRecord(W.join[c], sc));
+            HIP_TRY(ctx, hipStreamWaitEvent(st, W.join[c], 0));
+        }
+    }
+    return SPCG_OK;
+}
+
+int batched_dspace(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int variant, const BatchPlan& plan) {
+    HIP_TRY(ctx, run_mrhs_dspace(st, variant, W.probs.as<MrhsProblem>(), plan.nprob, W.part_s.as<float>(),
+                                 W.part_g.as<float>(), W.part_scal.as<float>()));
+    return SPCG_OK;
+}
+
+// Captures the launches of body(stream) into an executable graph, recorded
+// on the private capture stream (the library stream may be the null stream,
+// which cannot be captured).  *exec stays null when capture is unavailable;
+// the caller then launches directly.
+template <class F>
+int capture_graph(spcg_ctx* ctx, BatchWork& W, F&& body, hipGraphExec_t* exec) {
+    *exec = nullptr;
+    if (hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return SPCG_OK;
+    }
+    const int rc = body(W.cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(W.cap, &g);
+    if (rc != SPCG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return SPCG_OK;
+    }
+    const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        *exec = nullptr;
+    }
+    return SPCG_OK;
+}
+
+// Runs body once: as a captured graph launched on the library stream when
+// graphs are on (the graph is kept in *keep for destruction after the
+// solve), else directly on the library stream.
+template <class F>
+int run_captured(spcg_ctx* ctx, BatchWork& W, bool graphs, F&& body, std::vector<hipGraphExec_t>& keep) {
+    if (graphs) {
+        hipGraphExec_t ex = nullptr;
+        int rc;
+        if ((rc = capture_graph(ctx, W, body, &ex)) != SPCG_OK) return rc;
+        if (ex) {
+            keep.push_back(ex);
+            HIP_TRY(ctx, hipGraphLaunch(ex, ctx->stream));
+            return SPCG_OK;
+        }
+    }
+    return body(ctx->stream);
 }
 
 int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
@@ -885,10 +987,23 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         q.sc = W.scal.as<MrhsScalars>() + (size_t)p * kmax;
         maxK = std::max<int64_t>(maxK, W.sk[p]->K);
     }
-    // tasks per launch: about 4 per CU, never fewer than 256 rows each
+    // tasks per launch in Stage I: about 4 per CU, never fewer than 256 rows each
     const int64_t target_tasks = 4 * (int64_t)ctx->num_cu;
+    const bool graphs_on = opts->batch_direct == 0;
+    if ((rc = batch_streams(ctx, W)) != SPCG_OK) return rc;
+    // executable graphs of this solve, destroyed once the stream is idle
+    struct GraphList {
+        hipStream_t st;
+        std::vector<hipGraphExec_t> g;
+        ~GraphList() {
+            if (!g.empty()) (void)hipStreamSynchronize(st);
+            for (auto e : g) (void)hipGraphExecDestroy(e);
+        }
+    } graphs{st, {}};
+    int graphs_launched = 0;
     std::vector<int> t1(nprob, 0), t2(nprob, 0), conv(nprob, 0);
-    // Stage I: stage i of every problem that has one
+    // Stage I: stage i of every problem that has one; its G pass and a_i S
+    // passes form one graph
     for (int64_t i = 0; i < maxK; ++i) {
         int ai = a;
         if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
@@ -912,11 +1027,21 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         if (!any) continue;
         // stage rows: every problem's sketch has the same element type
         const int sdt = W.sk[0]->bdtype;
-        if ((rc = batched_pass(ctx, W, sdt, PM_G, PA_START, hp, target_tasks)) != SPCG_OK)
-            return rc;
-        for (int it = 0; it < ai; ++it)
-            if ((rc = batched_pass(ctx, W, sdt, PM_S, PA_STEP, hp, target_tasks)) != SPCG_OK)
-                return rc;
+        BatchPlan plan;
+        if ((rc = batched_setup(ctx, W, sdt, hp, target_tasks, plan)) != SPCG_OK) return rc;
+        auto stage = [&](hipStream_t s) -> int {
+            int r;
+            if ((r = batched_products(ctx, W, s, sdt, PM_G, plan)) != SPCG_OK) return r;
+            if ((r = batched_dspace(ctx, W, s, PA_START, plan)) != SPCG_OK) return r;
+            for (int it = 0; it < ai; ++it) {
+                if ((r = batched_products(ctx, W, s, sdt, PM_S, plan)) != SPCG_OK) return r;
+                if ((r = batched_dspace(ctx, W, s, PA_STEP, plan)) != SPCG_OK) return r;
+            }
+            return SPCG_OK;
+        };
+        const size_t before = graphs.g.size();
+        if ((rc = run_captured(ctx, W, graphs_on, stage, graphs.g)) != SPCG_OK) return rc;
+        graphs_launched += (int)(graphs.g.size() - before);
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) t1[p] += ai;
     }
@@ -933,6 +1058,29 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         q.ldb = Y[p].ld;
         q.c2 = 1.0;
     }
+    // task granularity of the full-data passes: fixed, cached, or tuned now
+    // by timing one product pass per candidate (the partials are discarded:
+    // the d-space step is not run, so the iterates are unaffected)
+    int tpc = opts->batch_tasks_per_cu > 0 ? opts->batch_tasks_per_cu : W.tasks_per_cu[dtype & 3];
+    if (tpc <= 0) {
+        double best_ms = INFINITY;
+        for (int cand : {2, 4, 8}) {
+            BatchPlan tp;
+            if ((rc = batched_setup(ctx, W, dtype, hp, (int64_t)cand * ctx->num_cu, tp)) != SPCG_OK) return rc;
+            if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp)) != SPCG_OK) return rc;   // warm-up
+            HIP_TRY(ctx, hipEventRecord(W.tune[0], st));
+            if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp)) != SPCG_OK) return rc;
+            HIP_TRY(ctx, hipEventRecord(W.tune[1], st));
+            HIP_TRY(ctx, hipEventSynchronize(W.tune[1]));
+            const double ms = elapsed_ms(W.tune[0], W.tune[1]);
+            if (ms < best_ms) {
+                best_ms = ms;
+                tpc = cand;
+            }
+        }
+        W.tasks_per_cu[dtype & 3] = tpc;
+    }
+    const int64_t full_tasks = (int64_t)tpc * ctx->num_cu;
     std::vector<MrhsScalars> hs((size_t)nprob * kmax);
     // Divergence guard: the FP32 products have an accuracy floor; a problem
     // whose stopping ratio climbs well above its best value (iterating past
@@ -940,8 +1088,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     std::vector<double> best(nprob, INFINITY);
     DevBuf& bestx = W.bestx;
     HIP_TRY(ctx, bestx.ensure((size_t)nprob * kmax * ldv * 8));
+    bool set_changed = true;
     auto check = [&](int* n_active) -> int {
-        HIP_TRY(ctx, hipMemcpy(hs.data(), W.scal.p, hs.size() * sizeof(MrhsScalars), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpyAsync(hs.data(), W.scal.p, hs.size() * sizeof(MrhsScalars), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
         int act = 0;
         for (int p = 0; p < nprob; ++p) {
             if (!hp[p].active) continue;
@@ -965,8 +1115,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             if (done) {
                 conv[p] = 1;
                 hp[p].active = 0;
+                set_changed = true;
             } else if (diverging || t1[p] + t2[p] >= T) {
                 hp[p].active = 0;
+                set_changed = true;
                 HIP_TRY(ctx, hipMemcpyAsync(xp, bp, (size_t)kmax * ldv * 8, hipMemcpyDeviceToDevice, st));
             } else {
                 ++act;
@@ -976,15 +1128,54 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         return SPCG_OK;
     };
     int act = 0;
-    if ((rc = batched_pass(ctx, W, dtype, PM_G, PA_START, hp, target_tasks)) != SPCG_OK) return rc;
+    BatchPlan plan;
+    if ((rc = batched_setup(ctx, W, dtype, hp, full_tasks, plan)) != SPCG_OK) return rc;
+    set_changed = false;
+    if ((rc = batched_products(ctx, W, st, dtype, PM_G, plan)) != SPCG_OK) return rc;
+    if ((rc = batched_dspace(ctx, W, st, PA_START, plan)) != SPCG_OK) return rc;
     if ((rc = check(&act)) != SPCG_OK) return rc;
+    // one graph for the product launches and one for the d-space launch of
+    // each active set, replayed every iteration (events around the product
+    // graph time the products alone)
+    hipGraphExec_t gprod = nullptr, gds = nullptr;
     while (act > 0) {
-        ProductTimer* tp = opts->time_products ? &timer : nullptr;
-        if (tp && timer.used < MAX_TIMED) {
+        if (set_changed) {
+            if ((rc = batched_setup(ctx, W, dtype, hp, full_tasks, plan)) != SPCG_OK) return rc;
+            set_changed = false;
+            gprod = gds = nullptr;
+            if (graphs_on) {
+                if ((rc = capture_graph(ctx, W, [&](hipStream_t s) { return batched_products(ctx, W, s, dtype, PM_SG, plan); },
+                                        &gprod)) != SPCG_OK)
+                    return rc;
+                if (gprod) graphs.g.push_back(gprod);
+                if ((rc = capture_graph(ctx, W, [&](hipStream_t s) { return batched_dspace(ctx, W, s, PA_REFRESH, plan); },
+                                        &gds)) != SPCG_OK)
+                    return rc;
+                if (gds) graphs.g.push_back(gds);
+            }
+        }
+        const bool timed = opts->time_products && timer.used < MAX_TIMED;
+        if (timed) {
             for (int p = 0; p < nprob; ++p)
                 if (hp[p].active) timed_bytes += (double)hp[p].m * (hp[p].d * es + hp[p].k * 8);
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer.used], st));
         }
-        if ((rc = batched_pass(ctx, W, dtype, PM_SG, PA_REFRESH, hp, target_tasks, tp)) != SPCG_OK) return rc;
+        if (gprod) {
+            HIP_TRY(ctx, hipGraphLaunch(gprod, st));
+            ++graphs_launched;
+        } else if ((rc = batched_products(ctx, W, st, dtype, PM_SG, plan)) != SPCG_OK) {
+            return rc;
+        }
+        if (timed) {
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer.used + 1], st));
+            timer.used++;
+        }
+        if (gds) {
+            HIP_TRY(ctx, hipGraphLaunch(gds, st));
+            ++graphs_launched;
+        } else if ((rc = batched_dspace(ctx, W, st, PA_REFRESH, plan)) != SPCG_OK) {
+            return rc;
+        }
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) ++t2[p];
         if ((rc = check(&act)) != SPCG_OK) return rc;
@@ -1016,6 +1207,8 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             s.T_stage2 = t2[p];
             s.converged = conv[p];
             s.qr_passes = W.pc[p]->passes;
+            s.batch_tasks_per_cu = tpc;
+            s.batch_graphs = graphs_launched;
             s.rho_final = hs[(size_t)p * kmax].rho;
             s.ax_norm = std::sqrt(std::max(hs[(size_t)p * kmax].ax2, 0.0));
             if (timing) {

@@ -40,8 +40,6 @@ constexpr int KP = 16;          // right-hand sides per MFMA (N)
 constexpr int MR_DMAX = 512;    // columns supported
 constexpr int MRW = 8;          // waves per block
 constexpr int MR_RING = 3;      // LDS slots
-constexpr int KJ = (MR_DMAX / 4 + MRW - 1) / MRW;   // first-GEMM K steps per wave
-constexpr int MAXT = MR_DMAX / 16 / MRW;            // second-GEMM tiles per wave
 
 typedef float mv4f __attribute__((ext_vector_type(4)));
 
@@ -86,6 +84,10 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     constexpr int AJOBS = MT * NIR;                  // A loads per tile
     constexpr int OPS = AJOBS / MRW + (DO_G ? MT / MRW : 0);   // loads per wave per tile
     static_assert(AJOBS % MRW == 0 && MT % MRW == 0, "even split of the loads");
+    // widest row of the class: the register arrays below are sized for it
+    constexpr int DCLS = NIR * 64 * DMAB / ES < MR_DMAX ? NIR * 64 * DMAB / ES : MR_DMAX;
+    constexpr int KJ = (DCLS / 4 + MRW - 1) / MRW;      // first-GEMM K steps per wave
+    constexpr int MAXT = (DCLS / 16 + MRW - 1) / MRW;   // second-GEMM output tiles per wave
     static_assert((MR_RING - 2) * OPS < 64, "vmcnt range");
     __shared__ __align__(16) unsigned char sl0[SLOT];
     __shared__ __align__(16) unsigned char sl1[SLOT];
@@ -93,7 +95,9 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     __shared__ float Wp[DO_S ? MRW : 1][MT][KP + 1];
     __shared__ float Wg[DO_G ? MRW : 1][MT][KP + 1];
     __shared__ float Wl[DO_G ? MRW : 1][MT][KP + 1];
-    __shared__ float nrm[2][4][KP];
+    __shared__ float Wfs[DO_S ? MT : 1][KP + 1];   // B operands of the second GEMM
+    __shared__ float Wfg[DO_G ? MT : 1][KP + 1];
+    __shared__ float nrm[2][MRW][32];
 
     const MrhsTask task = tasks[blockIdx.x];
     const int64_t gtask = (int64_t)task0 + blockIdx.x;
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         accS[t] = mv4f{0.f, 0.f, 0.f, 0.f};
         accG[t] = mv4f{0.f, 0.f, 0.f, 0.f};
     }
-    float r2 = 0.f, ax2 = 0.f;   // wave 0, per lane: column li, rows of its group
+    float r2 = 0.f, ax2 = 0.f;   // per lane l < 32: column l mod 16, rows 2 wave + l / 16
     const int64_t ntile = (task.r1 - task.r0 + MT - 1) / MT;
 
     auto issue = [&](int64_t tl, unsigned char* T) __attribute__((always_inline)) {
@@ -185,33 +189,40 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         __builtin_amdgcn_s_waitcnt(MR_LGKM0);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // B operands of the second GEMM: W[4 s + lg][li] summed over waves
-        float wb[4], gb[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int rr = 4 * s + lg;
-            const bool ok = task.r0 + tl * MT + rr < task.r1 && li < k;
+        // reduce-scatter: wave w sums the 8 partials of rows 2w, 2w + 1 (lane
+        // l < 32: row 2w + l / 16, column l mod 16) in a fixed order, forms
+        // the residual there once, and publishes the second GEMM's B operands
+        if (lane < 32) {
+            const int rr = 2 * wave + (lane >> 4), cc = lane & 15;
+            const bool ok = task.r0 + tl * MT + rr < task.r1 && cc < k;
             float t0 = 0.f, t1 = 0.f, tlo = 0.f;
 #pragma unroll
             for (int w = 0; w < MRW; ++w) {
-                if (DO_S) t0 += Wp[w][rr][li];
+                if (DO_S) t0 += Wp[w][rr][cc];
                 if (DO_G) {
-                    t1 += Wg[w][rr][li];
-                    tlo += Wl[w][rr][li];
+                    t1 += Wg[w][rr][cc];
+                    tlo += Wl[w][rr][cc];
                 }
             }
-            wb[s] = ok ? t0 : 0.f;
-            gb[s] = 0.f;
+            if (DO_S) Wfs[rr][cc] = ok ? t0 : 0.f;
             if constexpr (DO_G) {
-                const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[ok ? li : 0];
+                const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[ok ? cc : 0];
                 const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
-                gb[s] = (float)res;
-                if (wave == 0 && ok) {
+                Wfg[rr][cc] = (float)res;
+                if (ok) {
                     r2 = fmaf((float)res, (float)res, r2);
                     ax2 = fmaf(t1, t1, ax2);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);   // bound the partial loads in flight
+        }
+        __builtin_amdgcn_s_waitcnt(MR_LGKM0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        float wb[4], gb[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            wb[s] = DO_S ? Wfs[4 * s + lg][li] : 0.f;
+            gb[s] = DO_G ? Wfg[4 * s + lg][li] : 0.f;
         }
         // second GEMM: S[:, tile mt] += A_t^T W
 #pragma unroll
@@ -261,16 +272,22 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         }
     }
     if (DO_G) {
-        // reduce the per-lane norms of wave 0 over its 4 lane groups
-        if (wave == 0) {
-            nrm[0][lg][li] = r2;
-            nrm[1][lg][li] = ax2;
+        // per-column norms: the 8 waves' two row lanes, in a fixed order
+        if (lane < 32) {
+            nrm[0][wave][lane] = r2;
+            nrm[1][wave][lane] = ax2;
         }
         __syncthreads();
         if (threadIdx.x < KP) {
             const int c = threadIdx.x;
-            part_scal[gtask * 2 * KP + c] = ((nrm[0][0][c] + nrm[0][1][c]) + nrm[0][2][c]) + nrm[0][3][c];
-            part_scal[gtask * 2 * KP + KP + c] = ((nrm[1][0][c] + nrm[1][1][c]) + nrm[1][2][c]) + nrm[1][3][c];
+            float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+            for (int w = 0; w < MRW; ++w) {
+                a0 += nrm[0][w][c] + nrm[0][w][c + 16];
+                a1 += nrm[1][w][c] + nrm[1][w][c + 16];
+            }
+            part_scal[gtask * 2 * KP + c] = a0;
+            part_scal[gtask * 2 * KP + KP + c] = a1;
         }
     }
 }

@@ -100,3 +100,52 @@ def test_batched_argument_errors(S, ctx):
     with pytest.raises(S.SpcgError) as e:
         S.spcg_solve_batched(ctx, [q.X], [q.Y])
     assert e.value.code == S.SPCG_E_SHAPE
+
+
+def _uneven(n=10, seed=11):
+    return workloads.batched(n_prob=n, N_range=(20_000, 90_000), d_range=(32, 512),
+                             cond_range=(1e2, 1e5), k_range=(1, 16), seed=seed, device=DEV)
+
+
+def test_batched_graphs_replay_matches_direct_launches(S, ctx):
+    # The captured graphs hold exactly the direct launches: with the same
+    # task granularity, one Stage I graph per stage and the Stage II product
+    # and d-space graphs (replayed once per iteration, with the host's
+    # stopping test and copies between replays) give identical bits, solve
+    # after solve.
+    probs = _uneven()
+    Xs, Ys = [q.X for q in probs], [q.Y for q in probs]
+    ref, st_d = S.spcg_solve_batched(ctx, Xs, Ys, seed=3, batch_direct=True, batch_tasks_per_cu=4)
+    assert st_d[0]["batch_graphs"] == 0
+    for rep in range(2):
+        got, st_g = S.spcg_solve_batched(ctx, Xs, Ys, seed=3, batch_tasks_per_cu=4)
+        assert st_g[0]["batch_graphs"] > 0 and st_g[0]["batch_tasks_per_cu"] == 4
+        for q, a, b, s1, s2 in zip(probs, ref, got, st_d, st_g):
+            assert s1["T_stage2"] == s2["T_stage2"]
+            assert torch.equal(a, b), (rep, q.N, q.d, q.k)
+    for q, b, st in zip(probs, got, st_g):
+        assert st["converged"]
+        _check(q, b)
+
+
+def test_batched_autotuned_granularity(S, ctx):
+    # The tuner picks 2, 4 or 8 tasks per CU once per context and storage
+    # type; its timing passes leave the iterates untouched, so the tuned
+    # solve equals a solve run with that granularity fixed.
+    probs = _uneven(n=6, seed=12)
+    Xs, Ys = [q.X for q in probs], [q.Y for q in probs]
+    c2 = S.Context(0)
+    try:
+        got, st = S.spcg_solve_batched(c2, Xs, Ys, seed=4)
+        tpc = st[0]["batch_tasks_per_cu"]
+        assert tpc in (2, 4, 8)
+        fixed, st_f = S.spcg_solve_batched(c2, Xs, Ys, seed=4, batch_tasks_per_cu=tpc)
+        again, st_a = S.spcg_solve_batched(c2, Xs, Ys, seed=4)
+        assert st_a[0]["batch_tasks_per_cu"] == tpc
+        for a, b, c in zip(got, fixed, again):
+            assert torch.equal(a, b) and torch.equal(a, c)
+        for q, b, s in zip(probs, got, st):
+            assert s["converged"]
+            _check(q, b)
+    finally:
+        c2.close()
