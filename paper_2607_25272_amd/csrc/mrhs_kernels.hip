@@ -19,10 +19,13 @@
 // explicit vmcnt waits, bare barriers, one LDS object per slot), so the
 // next tiles are in flight while the matrix cores work on the current one.
 // The constant B operands of the first GEMM (P and x split hi + lo) stay in
-// registers for the whole task: wave w owns the K steps w, w + 8, ...; the
-// 8 waves' 16 x 16 partials of W are combined through LDS, and each wave
-// then owns every 8th 16-column output tile of the second GEMM, with the
-// accumulators in registers.  The residual is formed in FP64 as
+// registers for the whole task: wave w owns the 16-column K groups w, w + 8,
+// ..., with the K order inside a group permuted so that each lane's four A
+// values are one LDS read.  The 8 waves' 16 x 16 partials of W are combined
+// through LDS (each wave sums two rows and forms their residual once), and
+// each wave then owns every 8th 16-column output tile of the second GEMM,
+// whose K (row) order is permuted to make its LDS reads conflict-free, with
+// the accumulators in registers.  The residual is formed in FP64 as
 // (b - A x_hi) - A x_lo.  The task writes one FP32 partial d x 16 block per
 // output; the per-problem d-space kernel sums the partials of its tasks in
 // a fixed order.
@@ -70,6 +73,27 @@ __device__ __forceinline__ float lds_elem<bf16_t>(const unsigned char* row, int 
     return bf16_bits_to_f32(reinterpret_cast<const uint16_t*>(row)[col]);
 }
 
+// Four consecutive elements of an LDS row (16-byte aligned for FP32, 8 for
+// BF16), widened: one LDS read.
+template <typename TS>
+__device__ __forceinline__ void lds_elem4(const unsigned char* row, int col, float* o);
+template <>
+__device__ __forceinline__ void lds_elem4<float>(const unsigned char* row, int col, float* o) {
+    const float4 v = *reinterpret_cast<const float4*>(row + 4 * col);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void lds_elem4<bf16_t>(const unsigned char* row, int col, float* o) {
+    const uint2 v = *reinterpret_cast<const uint2*>(row + 2 * col);
+    o[0] = __uint_as_float(v.x << 16);
+    o[1] = __uint_as_float(v.x & 0xffff0000u);
+    o[2] = __uint_as_float(v.y << 16);
+    o[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+
 template <typename TS, int MODE, int DMAB, int NIR>
 __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* __restrict__ tasks, int task0,
                                                                 const MrhsProblem* __restrict__ probs,
@@ -86,17 +110,24 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     static_assert(AJOBS % MRW == 0 && MT % MRW == 0, "even split of the loads");
     // widest row of the class: the register arrays below are sized for it
     constexpr int DCLS = NIR * 64 * DMAB / ES < MR_DMAX ? NIR * 64 * DMAB / ES : MR_DMAX;
-    constexpr int KJ = (DCLS / 4 + MRW - 1) / MRW;      // first-GEMM K steps per wave
+    constexpr int KG = (DCLS / 16 + MRW - 1) / MRW;     // 16-column K groups per wave (first GEMM)
     constexpr int MAXT = (DCLS / 16 + MRW - 1) / MRW;   // second-GEMM output tiles per wave
     static_assert((MR_RING - 2) * OPS < 64, "vmcnt range");
     __shared__ __align__(16) unsigned char sl0[SLOT];
     __shared__ __align__(16) unsigned char sl1[SLOT];
     __shared__ __align__(16) unsigned char sl2[SLOT];
-    __shared__ float Wp[DO_S ? MRW : 1][MT][KP + 1];
-    __shared__ float Wg[DO_G ? MRW : 1][MT][KP + 1];
-    __shared__ float Wl[DO_G ? MRW : 1][MT][KP + 1];
-    __shared__ float Wfs[DO_S ? MT : 1][KP + 1];   // B operands of the second GEMM
-    __shared__ float Wfg[DO_G ? MT : 1][KP + 1];
+    // Column packing: the first GEMM's B operand is [P | x_hi | x_lo] (the
+    // matrices this mode needs, k columns each) laid side by side over
+    // NS1 = ceil(NM1 k / 16) 16-column slabs, and the second GEMM's is
+    // [W_p | g] over NS2 = ceil(NM2 k / 16) slabs, so small k runs fewer
+    // MFMAs.  Packed column q is matrix q / k, right-hand side q mod k.
+    constexpr int NM1 = (DO_S ? 1 : 0) + (DO_G ? 2 : 0);
+    constexpr int NM2 = (DO_S ? 1 : 0) + (DO_G ? 1 : 0);
+    // per-wave partials of W per slab; row pitch 20 keeps the MFMA-layout
+    // stores (rows 4 lg + v, column li) conflict-free
+    __shared__ float W1[NM1][MRW][MT][KP + 4];
+    // the second GEMM's packed B operand (pitch 36: its reads are conflict-free)
+    __shared__ float W2[MT][2 * KP + 4];
     __shared__ float nrm[2][MRW][32];
 
     const MrhsTask task = tasks[blockIdx.x];
@@ -104,7 +135,7 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     const MrhsProblem pb = probs[task.prob];
     const int d = pb.d, k = pb.k;
     const int dt = (d + 15) / 16;          // 16-column tiles of d
-    const int d4 = (d + 3) / 4;            // K steps of the first GEMM
+    const int ns1 = (NM1 * k + 15) / 16, ns2 = (NM2 * k + 15) / 16;
     // wave index as a wave-uniform (scalar) value: row offsets stay in SGPRs
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int li = lane & 15, lg = lane >> 4;
@@ -112,30 +143,47 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     const char* Abase = static_cast<const char*>(pb.A);
     const int64_t rowb = pb.lda * ES;
     const int64_t rlast = task.r1 - 1;
+    for (int e = threadIdx.x; e < MT * (2 * KP + 4); e += 64 * MRW) (&W2[0][0])[e] = 0.f;
 
     // constant B operands of the first GEMM: P and x = hi + lo (~48 bits),
     // zero outside d x k.  A x = A x_hi + A x_lo: the high product only
     // changes when x_hi does, so steps far below FP32 resolution of x still
     // move the residual through the low product.
-    float bp[KJ], bh[KJ], bl[KJ];
+    // The K order inside each 16-column group q is permuted: at step u lane
+    // group lg takes column 16 q + 4 lg + u, so a lane's four A values of a
+    // group are contiguous (one LDS read) and the B constants follow.
+    float b1[NM1][KG][4];
 #pragma unroll
-    for (int j = 0; j < KJ; ++j) {
-        const int s = wave + MRW * j;
-        const int row = 4 * s + lg;
-        const bool ok = row < d && li < k;
-        const int rr = ok ? row : 0, cc = ok ? li : 0;
-        const double pv = DO_S ? pb.P[(int64_t)cc * pb.ldv + rr] : 0.0;
-        const double xv = DO_G ? pb.X[(int64_t)cc * pb.ldv + rr] : 0.0;
-        bp[j] = ok ? (float)pv : 0.f;
-        const float hi = ok ? (float)xv : 0.f;
-        bh[j] = hi;
-        bl[j] = ok ? (float)(xv - (double)hi) : 0.f;
+    for (int sl = 0; sl < NM1; ++sl) {
+        const int qc = 16 * sl + li;           // packed column of this lane
+        const int mi = qc / k, c = qc - mi * k;
+        // matrix mi: P (when DO_S) first, then x_hi, then x_lo
+        const int src = DO_S ? mi : mi + 1;    // 0 P, 1 x_hi, 2 x_lo
+        // one load per value, no branch; the vectors live in global memory
+        typedef const __attribute__((address_space(1))) double gdouble;
+        gdouble* base = (gdouble*)(src == 0 ? pb.P : pb.X);
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            const int q = wave + MRW * g;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = 16 * q + 4 * lg + u;
+                const bool ok = row < d && mi < NM1;
+                const double xv = base[(int64_t)(ok ? c : 0) * pb.ldv + (ok ? row : 0)];
+                const float hi = (float)xv, lo = (float)(xv - (double)hi);
+                // a 0/1 weight rather than a select keeps the load unconditional
+                // (all loads of the slab in flight at once; the values are finite)
+                b1[sl][g][u] = (src == 2 ? lo : hi) * (ok ? 1.f : 0.f);
+            }
+        }
+        // bound the loads in flight (registers) to one slab
+        __builtin_amdgcn_sched_barrier(0);
     }
-    mv4f accS[MAXT], accG[MAXT];
+    mv4f acc[2][MAXT];
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
-        accS[t] = mv4f{0.f, 0.f, 0.f, 0.f};
-        accG[t] = mv4f{0.f, 0.f, 0.f, 0.f};
+        acc[0][t] = mv4f{0.f, 0.f, 0.f, 0.f};
+        acc[1][t] = mv4f{0.f, 0.f, 0.f, 0.f};
     }
     float r2 = 0.f, ax2 = 0.f;   // per lane l < 32: column l mod 16, rows 2 wave + l / 16
     const int64_t ntile = (task.r1 - task.r0 + MT - 1) / MT;
@@ -163,79 +211,114 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         }
     };
     auto consume = [&](int64_t tl, const unsigned char* T) __attribute__((always_inline)) {
-        // first GEMM: this wave's K steps of W = A_t [P | x_hi | x_lo]
-        mv4f ws = mv4f{0.f, 0.f, 0.f, 0.f}, wg = mv4f{0.f, 0.f, 0.f, 0.f}, wl = mv4f{0.f, 0.f, 0.f, 0.f};
-        const unsigned char* arow = T + li * PITCH;
+        // first GEMM: this wave's K groups of W = A_t [P | x_hi | x_lo] (packed)
+        mv4f w1[NM1];
 #pragma unroll
-        for (int j = 0; j < KJ; ++j) {
-            const int s = wave + MRW * j;
-            if (s < d4) {
-                const float av = lds_elem<TS>(arow, 4 * s + lg);
-                if (DO_S) ws = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bp[j], ws, 0, 0, 0);
-                if (DO_G) {
-                    wg = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bh[j], wg, 0, 0, 0);
-                    wl = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bl[j], wl, 0, 0, 0);
+        for (int sl = 0; sl < NM1; ++sl) w1[sl] = mv4f{0.f, 0.f, 0.f, 0.f};
+        const unsigned char* arow = T + li * PITCH;
+        // the slab count is uniform per task: one loop body per count, so
+        // the MFMA chains carry no per-instruction conditions
+        auto gemm1 = [&](auto ns_c) __attribute__((always_inline)) {
+            constexpr int NS = decltype(ns_c)::value;
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                const int q = wave + MRW * g;
+                if (q < dt) {
+                    float a4[4];
+                    lds_elem4<TS>(arow, 16 * q + 4 * lg, a4);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                        for (int sl = 0; sl < NS; ++sl)
+                            w1[sl] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[u], b1[sl][g][u], w1[sl], 0, 0, 0);
+                    }
                 }
             }
+        };
+        if constexpr (NM1 >= 3) {
+            if (ns1 >= 3) gemm1(std::integral_constant<int, 3>{});
+            else if (ns1 == 2) gemm1(std::integral_constant<int, 2>{});
+            else gemm1(std::integral_constant<int, 1>{});
+        } else if constexpr (NM1 == 2) {
+            if (ns1 == 2) gemm1(std::integral_constant<int, 2>{});
+            else gemm1(std::integral_constant<int, 1>{});
+        } else {
+            gemm1(std::integral_constant<int, 1>{});
         }
+        // unused slabs store their zeros
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            if (DO_S) Wp[wave][4 * lg + v][li] = ws[v];
-            if (DO_G) {
-                Wg[wave][4 * lg + v][li] = wg[v];
-                Wl[wave][4 * lg + v][li] = wl[v];
-            }
+#pragma unroll
+            for (int sl = 0; sl < NM1; ++sl) W1[sl][wave][4 * lg + v][li] = w1[sl][v];
         }
         __builtin_amdgcn_s_waitcnt(MR_LGKM0);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         // reduce-scatter: wave w sums the 8 partials of rows 2w, 2w + 1 (lane
-        // l < 32: row 2w + l / 16, column l mod 16) in a fixed order, forms
-        // the residual there once, and publishes the second GEMM's B operands
+        // l < 32: row 2w + l / 16, right-hand side l mod 16) in a fixed
+        // order, forms the residual there once, and publishes the second
+        // GEMM's packed B operand
         if (lane < 32) {
             const int rr = 2 * wave + (lane >> 4), cc = lane & 15;
-            const bool ok = task.r0 + tl * MT + rr < task.r1 && cc < k;
-            float t0 = 0.f, t1 = 0.f, tlo = 0.f;
+            if (cc < k) {
+                const bool ok = task.r0 + tl * MT + rr < task.r1;
+                if constexpr (DO_S) {
+                    float t0 = 0.f;
 #pragma unroll
-            for (int w = 0; w < MRW; ++w) {
-                if (DO_S) t0 += Wp[w][rr][cc];
-                if (DO_G) {
-                    t1 += Wg[w][rr][cc];
-                    tlo += Wl[w][rr][cc];
+                    for (int w = 0; w < MRW; ++w) t0 += W1[0][w][rr][cc];
+                    W2[rr][cc] = ok ? t0 : 0.f;
                 }
-            }
-            if (DO_S) Wfs[rr][cc] = ok ? t0 : 0.f;
-            if constexpr (DO_G) {
-                const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[ok ? cc : 0];
-                const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
-                Wfg[rr][cc] = (float)res;
-                if (ok) {
-                    r2 = fmaf((float)res, (float)res, r2);
-                    ax2 = fmaf(t1, t1, ax2);
+                if constexpr (DO_G) {
+                    const int qh = (DO_S ? k : 0) + cc, ql = qh + k;
+                    float t1 = 0.f, tlo = 0.f;
+#pragma unroll
+                    for (int w = 0; w < MRW; ++w) {
+                        t1 += W1[qh >> 4][w][rr][qh & 15];
+                        tlo += W1[ql >> 4][w][rr][ql & 15];
+                    }
+                    const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[cc];
+                    const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
+                    W2[rr][(DO_S ? k : 0) + cc] = (float)res;
+                    if (ok) {
+                        r2 = fmaf((float)res, (float)res, r2);
+                        ax2 = fmaf(t1, t1, ax2);
+                    }
                 }
             }
         }
         __builtin_amdgcn_s_waitcnt(MR_LGKM0);
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        float wb[4], gb[4];
+        // second GEMM with the rows of the tile permuted: at step u lane group
+        // lg takes row 4 lg + u (conflict-free LDS reads of A_t^T)
+        float b2[2][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            wb[s] = DO_S ? Wfs[4 * s + lg][li] : 0.f;
-            gb[s] = DO_G ? Wfg[4 * s + lg][li] : 0.f;
+        for (int u = 0; u < 4; ++u) {
+            b2[0][u] = W2[4 * lg + u][li];
+            b2[1][u] = NM2 > 1 ? W2[4 * lg + u][16 + li] : 0.f;
         }
-        // second GEMM: S[:, tile mt] += A_t^T W
+        // second GEMM: [S | G][:, tile mt] += A_t^T [W_p | g]
+        auto gemm2 = [&](auto ns_c) __attribute__((always_inline)) {
+            constexpr int NS = decltype(ns_c)::value;
 #pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
-            const int mt = wave + MRW * t;
-            if (mt < dt) {
+            for (int t = 0; t < MAXT; ++t) {
+                const int mt = wave + MRW * t;
+                if (mt < dt) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float av = lds_elem<TS>(T + (4 * s + lg) * PITCH, 16 * mt + li);
-                    if (DO_S) accS[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wb[s], accS[t], 0, 0, 0);
-                    if (DO_G) accG[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gb[s], accG[t], 0, 0, 0);
+                    for (int u = 0; u < 4; ++u) {
+                        const float av = lds_elem<TS>(T + (4 * lg + u) * PITCH, 16 * mt + li);
+#pragma unroll
+                        for (int sl = 0; sl < NS; ++sl)
+                            acc[sl][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b2[sl][u], acc[sl][t], 0, 0, 0);
+                    }
                 }
             }
+        };
+        if constexpr (NM2 > 1) {
+            if (ns2 > 1) gemm2(std::integral_constant<int, 2>{});
+            else gemm2(std::integral_constant<int, 1>{});
+        } else {
+            gemm2(std::integral_constant<int, 1>{});
         }
     };
 
@@ -257,17 +340,23 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
 #undef SPCG_MR_STEP
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // partial outputs: part[task][col][c] (c < 16)
+    // partial outputs: part[task][col][c] (c < 16), unpacked from the slabs
     const int64_t base = gtask * MR_DMAX * KP;
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-        const int mt = wave + MRW * t;
-        if (mt < dt) {
+    for (int sl = 0; sl < 2; ++sl) {
+        const int q2 = 16 * sl + li;
+        const int mi = q2 / k, c = q2 - mi * k;
+        if (mi >= NM2) continue;
+        float* out = (DO_S && mi == 0) ? part_s : part_g;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int col = 16 * mt + 4 * lg + v;
-                if (DO_S) part_s[base + (int64_t)col * KP + li] = accS[t][v];
-                if (DO_G) part_g[base + (int64_t)col * KP + li] = accG[t][v];
+        for (int t = 0; t < MAXT; ++t) {
+            const int mt = wave + MRW * t;
+            if (mt < dt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int col = 16 * mt + 4 * lg + v;
+                    out[base + (int64_t)col * KP + c] = acc[sl][t][v];
+                }
             }
         }
     }
