@@ -60,7 +60,7 @@ METRIC = "time-to-OLS-accuracy (s) and PCG-product HBM GB/s, SPCG vs full PCG, 1
 # (2.0 x FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy; the summary and
 # commands are in profiles/hbm_traffic_sg_product_and_transform.txt).  Valid
 # for the product kernel as profiled; workloads not profiled report null.
-SG_TRAFFIC_BYTES = {"cfg1": 2.0104e9, "cfg2": 8.0366e9}
+SG_TRAFFIC_BYTES = {"cfg1": 2.0103e9, "cfg2": 8.0366e9}
 
 
 def log(msg):

@@ -204,27 +204,39 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
     if (K) {
         const bool f64 = sk->dtype == DT_F64;
         const bool direct = sk->bdtype == sk->dtype;   // stage rows kept in the sum type
-        const int64_t mK = sk->m[K - 1];
+        // the finest stage and up to 3 coarser ones come from one gather
+        // (growth 2; one coarser for growth 4); the rest by folding
+        const int g = K > 1 ? (int)(sk->m[1] / sk->m[0]) : 2;
+        int J = 0;
+        if (K > 1 && g == 2) J = (int)std::min<int64_t>(3, K - 1);
+        if (K > 1 && g == 4) J = 1;
+        const int64_t lowest = K - 1 - J;   // coarsest stage written by the gather
         char* Bb = static_cast<char*>(sk->pB);
         void* work = nullptr;
-        if (!direct) {
-            HIP_TRY(ctx, ctx->zbuf.ensure((size_t)mK * ld * 4));
+        if (!direct && lowest > 0) {
+            HIP_TRY(ctx, ctx->zbuf.ensure((size_t)sk->m[lowest] * ld * 4));
             work = ctx->zbuf.p;
         }
-        CsJob s = j;
-        s.y = static_cast<const double*>(Y->data);
-        s.ldy_in = Y->ld;
-        s.k = sk->k;
-        s.tbl = tbl;
-        s.nbk = mK;
-        s.out = Bb + (size_t)sk->off[K - 1] * rowb;
-        s.out_dtype = sk->bdtype;
-        s.work = work;
-        s.outy = sk->pBY + (size_t)sk->off[K - 1] * ldy;
-        s.ldoy = ldy;
-        HIP_TRY(ctx, run_cs_gather(st, s));
-        for (int64_t i = K - 2; i >= 0; --i) {
-            const int g = (int)(sk->m[i + 1] / sk->m[i]);
+        CsTreeJob t{};
+        t.base = j;
+        t.base.y = static_cast<const double*>(Y->data);
+        t.base.ldy_in = Y->ld;
+        t.base.k = sk->k;
+        t.base.tbl = tbl;
+        t.base.nbk = sk->m[K - 1];
+        t.base.out_dtype = sk->bdtype;
+        t.base.ldoy = ldy;
+        t.growth = g;
+        t.levels = J;
+        for (int l = 0; l <= J; ++l) {
+            const int64_t i = K - 1 - l;
+            t.out[l] = Bb + (size_t)sk->off[i] * rowb;
+            t.outy[l] = sk->pBY + (size_t)sk->off[i] * ldy;
+            t.m[l] = sk->m[i];
+        }
+        t.work = work;
+        HIP_TRY(ctx, run_cs_gather_tree(st, t));
+        for (int64_t i = lowest - 1; i >= 0; --i) {
             const void* src = direct ? static_cast<const void*>(Bb + (size_t)sk->off[i + 1] * rowb) : work;
             HIP_TRY(ctx, run_cs_fold(st, f64, src, direct ? nullptr : work, Bb + (size_t)sk->off[i] * rowb,
                                      sk->bdtype, ld, sk->m[i], g, sk->pBY + (size_t)sk->off[i + 1] * ldy,

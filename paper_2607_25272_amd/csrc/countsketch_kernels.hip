@@ -220,6 +220,116 @@ __global__ __launch_bounds__(256) void cs_fold_y_kernel(const double* src, doubl
     dst[e] = v;
 }
 
+
+struct TreeArgs {
+    CsJob j;                 // j.nbk: finest bucket count
+    int nwin, xvec;
+    void* out[4];
+    double* outy[4];
+    int64_t m[4];
+    void* work;
+};
+
+constexpr int ipow(int g, int j) { return j == 0 ? 1 : g * ipow(g, j - 1); }
+
+template <typename TIN, typename TZ, int G, int J>
+__global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs a) {
+    constexpr int NF = ipow(G, J);   // finest buckets per coarse bucket
+    const CsJob& j = a.j;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nwaves = (int64_t)gridDim.x * CS_WAVES;
+    const int64_t mc = a.m[J];
+    const int64_t ntask = mc * a.nwin;
+    const bool vec = a.xvec != 0;
+    for (int64_t task = wave0; task < ntask; task += nwaves) {
+        const int64_t c = task / a.nwin;
+        const int w = (int)(task - c * a.nwin);
+        const int64_t col = (int64_t)w * CS_WIN + 4 * lane;
+        const bool do_y = j.outy && w == 0;
+        TZ acc[NF][4];
+        double yacc[NF];
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[t][q] = TZ(0);
+            yacc[t] = 0.0;
+            // finest bucket c + t mc: its slots in ascending order
+            for (int64_t y0 = c + t * mc; y0 < j.Np; y0 += CS_MU * j.nbk) {
+                int32_t e[CS_MU];
+#pragma unroll
+                for (int u = 0; u < CS_MU; ++u) {
+                    const int64_t yv = y0 + (int64_t)u * j.nbk;
+                    e[u] = yv < j.Np ? j.tbl[yv] : 0x7fffffff;
+                }
+                TZ v[CS_MU][4];
+                double yv_[CS_MU];
+#pragma unroll
+                for (int u = 0; u < CS_MU; ++u) {
+                    const int64_t k = e[u] & 0x7fffffff;
+                    yv_[u] = 0.0;
+                    if (k < j.N) {
+                        Load4<TIN, TZ>::run(j.x, k, j.ldx, col, j.d, vec, j.col_scale, v[u]);
+                        if (do_y && lane < j.k) yv_[u] = j.y[k * j.ldy_in + lane];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[u][q] = TZ(0);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CS_MU; ++u) {
+                    const bool neg = e[u] < 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[t][q] += neg ? -v[u][q] : v[u][q];
+                    yacc[t] += neg ? -yv_[u] : yv_[u];
+                }
+            }
+            if (col < j.ld) store4<TZ>(a.out[0], j.out_dtype, (c + t * mc) * j.ld + col, acc[t]);
+            if (do_y && lane < j.ldoy) a.outy[0][(c + t * mc) * j.ldoy + lane] = lane < j.k ? yacc[t] : 0.0;
+        }
+        // coarser levels: bucket s of level l adds buckets s + r G^(J-l) of
+        // level l - 1 in ascending r (the folding order)
+#pragma unroll
+        for (int l = 1; l <= J; ++l) {
+            const int nb = ipow(G, J - l);
+#pragma unroll
+            for (int s2 = 0; s2 < NF; ++s2) {
+                if (s2 >= nb) continue;
+#pragma unroll
+                for (int r = 1; r < G; ++r) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[s2][q] += acc[s2 + r * nb][q];
+                    yacc[s2] += yacc[s2 + r * nb];
+                }
+                if (col < j.ld) store4<TZ>(a.out[l], j.out_dtype, (c + s2 * mc) * j.ld + col, acc[s2]);
+                if (do_y && lane < j.ldoy) a.outy[l][(c + s2 * mc) * j.ldoy + lane] = lane < j.k ? yacc[s2] : 0.0;
+            }
+        }
+        if (a.work && col < j.ld)
+            store4<TZ>(a.work, std::is_same<TZ, double>::value ? DT_F64 : DT_F32, c * j.ld + col, acc[0]);
+    }
+}
+
+template <typename TIN, typename TZ, int G, int J>
+hipError_t tree_launch(hipStream_t st, const TreeArgs& a) {
+    const int64_t ntask = a.m[J] * a.nwin;
+    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES), 65536);
+    cs_gather_tree_kernel<TIN, TZ, G, J><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename TIN, typename TZ>
+hipError_t tree_dispatch(hipStream_t st, const TreeArgs& a, int g, int levels) {
+    if (levels == 0) return tree_launch<TIN, TZ, 2, 0>(st, a);
+    if (g == 2) {
+        if (levels == 1) return tree_launch<TIN, TZ, 2, 1>(st, a);
+        if (levels == 2) return tree_launch<TIN, TZ, 2, 2>(st, a);
+        if (levels == 3) return tree_launch<TIN, TZ, 2, 3>(st, a);
+    }
+    if (g == 4 && levels == 1) return tree_launch<TIN, TZ, 4, 1>(st, a);
+    return hipErrorInvalidValue;
+}
+
 template <typename TIN, typename TZ>
 hipError_t gather_launch(hipStream_t st, const GatherArgs& a) {
     const int64_t ntask = a.j.nbk * a.nwin;
@@ -251,6 +361,38 @@ hipError_t run_cs_gather(hipStream_t st, const CsJob& j) {
         case DT_F32: return gather_launch<float, float>(st, a);
         case DT_BF16: return gather_launch<bf16_t, float>(st, a);
         case DT_FP8: return gather_launch<fp8_t, float>(st, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& t) {
+    const CsJob& j = t.base;
+    const bool f64 = j.in_dtype == DT_F64;
+    if (t.levels < 0 || t.levels > 3 || j.nbk != t.m[0] || j.ld < j.d || j.ld % 4 != 0 || j.Np >= (1ll << 31) ||
+        j.N > j.Np)
+        return hipErrorInvalidValue;
+    for (int l = 1; l <= t.levels; ++l)
+        if (t.m[l] <= 0 || t.m[l - 1] != t.m[l] * t.growth) return hipErrorInvalidValue;
+    if (f64 != (j.out_dtype == DT_F64)) return hipErrorInvalidValue;
+    if (j.outy && (j.k < 1 || j.k > 64 || j.ldoy < j.k || j.ldoy > 64)) return hipErrorInvalidValue;
+    TreeArgs a{};
+    a.j = j;
+    a.j.outy = nullptr;
+    a.nwin = (int)ceil_div(j.ld, CS_WIN);
+    const int es = dtype_bytes(j.in_dtype);
+    a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
+    for (int l = 0; l <= t.levels; ++l) {
+        a.out[l] = t.out[l];
+        a.outy[l] = t.outy[l];
+        a.m[l] = t.m[l];
+    }
+    a.j.outy = t.outy[0];
+    a.work = t.work;
+    switch (j.in_dtype) {
+        case DT_F64: return tree_dispatch<double, double>(st, a, t.growth, t.levels);
+        case DT_F32: return tree_dispatch<float, float>(st, a, t.growth, t.levels);
+        case DT_BF16: return tree_dispatch<bf16_t, float>(st, a, t.growth, t.levels);
+        case DT_FP8: return tree_dispatch<fp8_t, float>(st, a, t.growth, t.levels);
         default: return hipErrorInvalidValue;
     }
 }

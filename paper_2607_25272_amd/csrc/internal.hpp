@@ -72,6 +72,21 @@ struct CsJob {
     int64_t ldoy;
 };
 hipError_t run_cs_gather(hipStream_t st, const CsJob& job);
+// The finest stage and up to 3 coarser ones in one gather: a wave takes a
+// bucket c of the coarsest produced level (m[levels] buckets) and its
+// growth^levels finest buckets c + t m[levels], and adds them level by
+// level in the folding order (bit-identical to gathering the finest stage
+// and folding).  base.nbk = m[0]; out[l] / outy[l] take level l (0 finest);
+// work (optional) the coarsest produced level in the sum type.
+struct CsTreeJob {
+    CsJob base;
+    int growth, levels;
+    void* out[4];
+    double* outy[4];
+    int64_t m[4];
+    void* work;
+};
+hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& job);
 // Folding to a coarser nested sketch: dst[b] = sum_{t < g} src[b + t mc]
 // (ascending t) for b < mc.  src and work hold rows in the sum type (FP64 for
 // f64, else FP32; work may equal src); dst takes out_dtype.  Also the
