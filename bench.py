@@ -6,7 +6,7 @@ test) of a synthetic least-squares problem already resident in HBM.
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
-                    [--workload cfg1|cfg2|cfg2fp8|cfg1cs|cfg2cs|batched|learned|paper]
+                    [--workload cfg1|cfg2|cfg2fp8|cfg1cs|cfg2cs|batched|learned|paper|tuned]
 
 cfg1 (default)  N=1e6, d=500, FP32 storage
 cfg2 / cfg2fp8  N=4e6, d=1000, BF16 / FP8-e4m3 storage (precision form)
@@ -17,6 +17,8 @@ batched         256 independent problems, N in [5e4, 5e5], d in [32, 512],
 learned         N=2e6, d=256, 1% of rows scaled by 100: plain vs learned schedule
 paper           the Sec. 4 / Table 1 setting (d=64, sigma^2=1e-8, m_1=8d,
                 m_K=N/2, FP64), N=2^17..2^22: iteration counts and GPU times
+tuned           the Sec. 4.3 setting (N=2^22, d=64, kappa=1e8): paper schedule,
+                tuned sizes, theory-driven a_i, CountSketch, full PCG
 """
 import argparse
 import json
@@ -54,6 +56,9 @@ WORKLOADS = {
                          "kappa log-uniform in [1e2, 1e5], k ~ U{1..16} right-hand sides; sigma=1; FP32"),
     "paper": dict(desc="Sec. 4 setting: X = G D, d=64, kappa in {1e4, 1e8}, sigma^2=1e-8, m_1=8d, "
                        "m_K=N/2, r=6d, a_i=3, FP64, N=2^17..2^22"),
+    "tuned": dict(desc="Sec. 4.3 setting: X = G D, N=2^22, d=64, kappa=1e8, sigma^2=1e-8, FP64; SPCG (m_1=8d "
+                       "doubling to N/2, a_i=3), the tuned schedule (2^10..2^16 then 2^20, a_i=4), theory-driven "
+                       "a_i (Theorems 3.3/3.4, omega=0.5), SPCG-CS, and full PCG"),
 }
 METRIC = "time-to-OLS-accuracy (s) and PCG-product HBM GB/s, SPCG vs full PCG, 1 GPU"
 # HBM bytes per launch of the full-data SG product from rocprofv3 PMC runs
@@ -312,6 +317,51 @@ def bench_paper(args, spcg, workloads, torch, dev):
     }
 
 
+def bench_tuned(args, spcg, workloads, torch, dev):
+    """Sec. 4.3 refinements on the GPU: schedules and CountSketch at N=2^22."""
+    N, d = 1 << 22, 64
+    p = workloads.paper_table1(N, 1e8, device=dev)
+    ctx = spcg.Context(0)
+    beta = torch.zeros(d, dtype=torch.float64, device=dev)
+    tuned = [2 ** k for k in range(10, 17)] + [2 ** 20]
+    variants = {
+        "spcg": dict(m0=8 * d, m_max=N // 2),
+        "spcg_tuned": dict(m_list=tuned, a=4),
+        "spcg_theory": dict(m0=8 * d, m_max=N // 2, a_rule="theory", omega=0.5),
+        "spcg_cs": dict(m0=8 * d, m_max=N // 2, sketch="cs"),
+        "spcg_cs_tuned": dict(m_list=tuned, a=4, sketch="cs"),
+        "pcg": dict(method="pcg"),
+    }
+    res = {}
+    for name, kw in variants.items():
+        kw = dict(kw, beta=beta, seed=1)
+        for _ in range(args.warmup):
+            spcg.spcg_solve(ctx, p.X, p.Y, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            _, st = spcg.spcg_solve(ctx, p.X, p.Y, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        _, ph = spcg.spcg_solve(ctx, p.X, p.Y, time_phases=True, **kw)
+        rel = pred_error_vs_ols(p, beta) if not args.skip_check else None
+        res[name] = {"s": statistics.median(ts), "K": st["K"], "T_stage1": st["T_stage1"],
+                     "T_stage2": st["T_stage2"], "rel": rel,
+                     "phases_ms": {k: round(ph[k], 3) for k in ("t_sketch_ms", "t_precond_ms", "t_stage1_ms",
+                                                               "t_stage2_ms")}}
+        log(f"{name}: {res[name]['s'] * 1e3:.2f} ms, K={st['K']} T1={st['T_stage1']} T2={st['T_stage2']} rel={rel}")
+    ctx.close()
+    sp = res["spcg"]
+    return {
+        "metric": METRIC, "value": sp["s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sp["s"] * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["tuned"]["desc"], "value_is": "median SPCG time (paper schedule)"},
+        "variants": res, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +397,8 @@ def main():
         out = bench_batched(args, spcg, workloads, torch, dev)
     elif args.workload == "paper":
         out = bench_paper(args, spcg, workloads, torch, dev)
+    elif args.workload == "tuned":
+        out = bench_tuned(args, spcg, workloads, torch, dev)
     else:
         out = bench_single(args, WORKLOADS[args.workload], spcg, workloads, torch, dev)
     print(json.dumps(out), flush=True)

@@ -112,6 +112,12 @@ typedef struct spcg_sketch_opts {
                                   (narrower tiles fit more blocks per CU) */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
     int32_t reserved; /* set to 0 */
+    const int64_t* m_list; /* optional HOST array of the stage sizes m_1 < ... < m_K (replaces
+                              m0 / growth / m_max), e.g. the tuned schedule of Sec. 4.3:
+                              2^10 ... 2^16, then 2^20.  d < m_1, m_K < N, K <= 64; for a
+                              CountSketch each size must divide the next. */
+    int32_t m_list_len;
+    int32_t reserved2; /* set to 0 */
 } spcg_sketch_opts;
 
 /* Sketch operators.  SRHT: Sec. 2.1 / 2.2, the method's default.  COUNT:
@@ -261,7 +267,19 @@ typedef struct spcg_solve_opts {
                                    row-width class launch; 0 (default) autotunes it once per
                                    context and storage type, timing one product pass with
                                    2, 4 and 8 (results are discarded) */
+    int32_t a_rule;           /* SPCG_A_FIXED (a / a_list) or SPCG_A_THEORY (below) */
+    int32_t reserved3;
+    double omega;             /* SPCG_A_THEORY: the stagewise accuracy factor (0: 0.5) */
 } spcg_solve_opts;
+
+/* a_i rules.  THEORY takes the stage iteration counts from Theorems 3.3
+ * and 3.4 for the stage sizes actually run (after stage_stride): with
+ * r_{i-1,i} = sqrt((m_i - d) / (m_{i-1} - d)),
+ *   a_i = ceil(ln{[(1 + omega) r_{i-1,i} + 1] / omega} / ln 4)   (i >= 2),
+ *   a_1 = ceil(alpha), alpha the same expression with r_{1,2} (the bound
+ *         Theorem 3.4 gives for every stage; r = 1 when K = 1). */
+#define SPCG_A_FIXED 0
+#define SPCG_A_THEORY 1
 
 /* Plain schedule: Algorithm 1 as written (a_i = a, every prefix, stopping
  * test after every check_every Stage II iterations).

@@ -25,6 +25,7 @@ from .countsketch import countsketch, nested_countsketch
 from .linalg import householder_qr
 from .pcg import pcg
 from .sketch import nested_srht, padded_bits
+from .theory import theory_schedule
 
 
 def schedule(N, d, m0=None, m_max=None, growth=2):
@@ -64,14 +65,20 @@ def _stage_problems(X, Y, seed, sizes, r, sketch):
 
 
 def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
-         growth=2, history=False, sketch="srht"):
-    """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k)."""
+         growth=2, history=False, sketch="srht", sizes=None):
+    """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k).
+    ``sizes`` gives the stage sizes explicitly (e.g. the tuned schedule of
+    Sec. 4.3); ``a`` may be a number, a per-stage list, or ("theory", omega)
+    for the counts of Theorems 3.3 / 3.4 (``theory.theory_schedule``)."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     N, d = X.shape
     r = 6 * d if r is None else int(r)
-    sizes = schedule(N, d, m0, m_max, growth)
-    a_list = [a] * len(sizes) if np.isscalar(a) else list(a)
+    sizes = schedule(N, d, m0, m_max, growth) if sizes is None else [int(m) for m in sizes]
+    if isinstance(a, tuple) and a and a[0] == "theory":
+        a_list = theory_schedule(sizes, d, a[1])
+    else:
+        a_list = [a] * len(sizes) if np.isscalar(a) else list(a)
     probs, R, sk = _stage_problems(X, Y, seed, sizes, r, sketch)
     multi = Y.ndim == 2
     Ys = Y if multi else Y[:, None]
@@ -87,7 +94,7 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
         x, inf2 = pcg(X, Ys[:, c], 1.0, R, x, max(T - t, 0), tol=tol, history=history)
         betas.append(x)
         infos.append({"stage_x": stage_x, "stage2": inf2, "T_stage1": t,
-                      "T": t + inf2["iters"]})
+                      "T": t + inf2["iters"], "a_list": a_list})
     beta = np.stack(betas, axis=1) if multi else betas[0]
     info = {"sizes": sizes, "R": R, "per_rhs": infos, "L": sk["L"], "Np": sk["Np"]}
     return beta, info

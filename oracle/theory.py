@@ -33,6 +33,24 @@ def alpha_bound(m1, m2, d, omega):
     return math.log((1.0 + (1.0 + omega) * rbar) / omega) / math.log(4.0)
 
 
+def theory_schedule(sizes, d, omega=0.5):
+    """Stage iteration counts from Theorems 3.3 and 3.4 (the theory-driven
+    schedule): a_i = ceil of the Theorem 3.3 bound for i >= 2, and a_1 =
+    ceil(alpha), the bound Theorem 3.4 gives for every stage (with r = 1 when
+    there is one stage)."""
+    sizes = list(sizes)
+    out = []
+    for i in range(len(sizes)):
+        if len(sizes) < 2:
+            val = math.log((2.0 + omega) / omega) / math.log(4.0)
+        elif i == 0:
+            val = alpha_bound(sizes[0], sizes[1], d, omega)
+        else:
+            val = iteration_lower_bound(sizes[i - 1], sizes[i], d, omega)
+        out.append(max(1, math.ceil(val - 1e-12)))
+    return out
+
+
 def first_stage_iterations(q1, omega):
     """Smallest unrounded a_1 with theta^{a_1} q_1 <= omega:
     a_1 = ln(q_1 / omega) / ln 4   (proof of Theorem 3.4)."""

@@ -186,10 +186,21 @@ def _sketch_kind(kind):
     raise ValueError(f"unknown sketch kind {kind!r}")
 
 
+def _sizes(m_list):
+    if not m_list:
+        return None, 0
+    arr = (ctypes.c_int64 * len(m_list))(*[int(m) for m in m_list])
+    return arr, len(m_list)
+
+
 def spcg_sketch(ctx, X, Y=None, seed=1, m0=0, m_max=0, r=0, growth=2, hat_only=False,
-                col_scale=None, stage_dtype=0, transform_segment=0, kind="srht"):
+                col_scale=None, stage_dtype=0, transform_segment=0, kind="srht", m_list=None):
+    sizes, n_sizes = _sizes(m_list)
     o = L.SketchOpts(seed=seed, m0=m0, m_max=m_max, r=r, growth=growth, hat_only=int(hat_only),
                      stage_dtype=stage_dtype, transform_segment=transform_segment, kind=_sketch_kind(kind))
+    if sizes is not None:
+        o.m_list = ctypes.cast(sizes, ctypes.POINTER(ctypes.c_int64))
+        o.m_list_len = n_sizes
     Xm = mat(X, col_scale)
     Ym = mat(Y) if Y is not None else None
     h = ctypes.c_void_p()
@@ -235,7 +246,7 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
                qr_passes=0, check_every=1, time_phases=False, time_products=False, a_list=None,
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
                record_features=False, stage_dtype=0, transform_segment=0, sketch="srht",
-               batch_direct=False, batch_tasks_per_cu=0):
+               batch_direct=False, batch_tasks_per_cu=0, m_list=None, a_rule="fixed", omega=0.0):
     """spcg_solve_opts from keyword arguments (``sketch``: "srht" or "cs",
     the CountSketch of SPCG-CS).  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
@@ -249,6 +260,14 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.sketch.kind = _sketch_kind(sketch)
     o.batch_direct = int(batch_direct)
     o.batch_tasks_per_cu = batch_tasks_per_cu
+    sizes, n_sizes = _sizes(m_list)
+    if sizes is not None:
+        o.sketch.m_list = ctypes.cast(sizes, ctypes.POINTER(ctypes.c_int64))
+        o.sketch.m_list_len = n_sizes
+    if a_rule not in ("fixed", "theory", L.SPCG_A_FIXED, L.SPCG_A_THEORY):
+        raise ValueError(f"unknown a_rule {a_rule!r}")
+    o.a_rule = L.SPCG_A_THEORY if a_rule in ("theory", L.SPCG_A_THEORY) else L.SPCG_A_FIXED
+    o.omega = omega
     o.precond.qr_passes = qr_passes
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every
@@ -263,10 +282,11 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
         o.schedule_weights = weights.data_ptr()
     o.schedule_margin = schedule_margin
     o.record_features = int(record_features)
-    keep = None
+    keep = [sizes]   # host arrays the options point to, alive until the call returns
     if a_list is not None:
-        keep = (ctypes.c_int32 * len(a_list))(*a_list)
-        o.a_list = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+        arr = (ctypes.c_int32 * len(a_list))(*a_list)
+        keep.append(arr)
+        o.a_list = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
         o.a_list_len = len(a_list)
     return o, keep
 

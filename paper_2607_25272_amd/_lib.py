@@ -25,6 +25,7 @@ SPCG_F64, SPCG_F32, SPCG_BF16, SPCG_FP8E4M3 = 0, 1, 2, 3
 SPCG_METHOD_SPCG, SPCG_METHOD_FULL_PCG = 0, 1
 SPCG_SCHEDULE_PLAIN, SPCG_SCHEDULE_LEARNED = 0, 1
 SPCG_SKETCH_SRHT, SPCG_SKETCH_COUNT = 0, 1
+SPCG_A_FIXED, SPCG_A_THEORY = 0, 1
 SPCG_MLP_F, SPCG_MLP_H, SPCG_MLP_O = 8, 64, 7
 SPCG_MLP_PARAMS = (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H
                    + SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
@@ -43,7 +44,8 @@ class SpcgMat(ctypes.Structure):
 class SketchOpts(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("m0", c_i64), ("m_max", c_i64), ("r", c_i64),
                 ("growth", c_i32), ("hat_only", c_i32), ("stage_dtype", c_i32), ("transform_segment", c_i32),
-                ("kind", c_i32), ("reserved", c_i32)]
+                ("kind", c_i32), ("reserved", c_i32), ("m_list", ctypes.POINTER(c_i64)),
+                ("m_list_len", c_i32), ("reserved2", c_i32)]
 
 
 class SketchInfo(ctypes.Structure):
@@ -72,7 +74,8 @@ class SolveOpts(ctypes.Structure):
                 ("a_list", ctypes.POINTER(c_i32)), ("a_list_len", c_i32),
                 ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
                 ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
-                ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32)]
+                ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32),
+                ("a_rule", c_i32), ("reserved3", c_i32), ("omega", c_f64)]
 
 
 class SolveStats(ctypes.Structure):

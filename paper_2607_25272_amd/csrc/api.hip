@@ -205,10 +205,12 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
         const bool f64 = sk->dtype == DT_F64;
         const bool direct = sk->bdtype == sk->dtype;   // stage rows kept in the sum type
         // the finest stage and up to 3 coarser ones come from one gather
-        // (growth 2; one coarser for growth 4); the rest by folding
-        const int g = K > 1 ? (int)(sk->m[1] / sk->m[0]) : 2;
+        // (while the sizes halve; one coarser at a ratio of 4); the rest by
+        // folding with each step's own ratio
+        const int g = K > 1 ? (int)(sk->m[K - 1] / sk->m[K - 2]) : 2;
         int J = 0;
-        if (K > 1 && g == 2) J = (int)std::min<int64_t>(3, K - 1);
+        if (K > 1 && g == 2)
+            while (J < 3 && J < K - 1 && sk->m[K - 1 - J] == 2 * sk->m[K - 2 - J]) ++J;
         if (K > 1 && g == 4) J = 1;
         const int64_t lowest = K - 1 - J;   // coarsest stage written by the gather
         char* Bb = static_cast<char*>(sk->pB);
@@ -238,8 +240,9 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
         HIP_TRY(ctx, run_cs_gather_tree(st, t));
         for (int64_t i = lowest - 1; i >= 0; --i) {
             const void* src = direct ? static_cast<const void*>(Bb + (size_t)sk->off[i + 1] * rowb) : work;
+            const int gi = (int)(sk->m[i + 1] / sk->m[i]);
             HIP_TRY(ctx, run_cs_fold(st, f64, src, direct ? nullptr : work, Bb + (size_t)sk->off[i] * rowb,
-                                     sk->bdtype, ld, sk->m[i], g, sk->pBY + (size_t)sk->off[i + 1] * ldy,
+                                     sk->bdtype, ld, sk->m[i], gi, sk->pBY + (size_t)sk->off[i + 1] * ldy,
                                      sk->pBY + (size_t)sk->off[i] * ldy, ldy, sk->k));
         }
     }
@@ -298,7 +301,17 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     }
     sk->K = 0;
     sk->k = 0;
-    if (!hat_only) {
+    if (!hat_only && o && o->m_list_len > 0) {
+        if (!o->m_list) return fail(ctx, SPCG_E_INVALID_ARG, "m_list is NULL");
+        if (o->m_list_len > 64) return fail(ctx, SPCG_E_SHAPE, "more than 64 stages");
+        for (int i = 0; i < o->m_list_len; ++i) {
+            const int64_t m = o->m_list[i];
+            if (m <= d || m >= N || (i > 0 && m <= o->m_list[i - 1]))
+                return fail(ctx, SPCG_E_SHAPE, "m_list must increase strictly within (d, N)");
+            sk->m[sk->K++] = m;
+        }
+        sk->k = Y->cols;
+    } else if (!hat_only) {
         if (m0 <= d) return fail(ctx, SPCG_E_SHAPE, "need m_1 > d (m_1=%lld)", (long long)m0);
         const int64_t limit = (o && o->m_max > 0) ? std::min<int64_t>(o->m_max, N - 1) : N - 1;
         for (int64_t m = m0; m <= limit; m *= growth) {
@@ -727,6 +740,18 @@ int check_stage_args(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const 
     return SPCG_OK;
 }
 
+// a_i of Theorems 3.3 / 3.4 for the stage sizes m[0..n) actually run.
+std::vector<int> theory_a(const int64_t* m, int n, int64_t d, double omega) {
+    std::vector<int> a(n, 1);
+    auto bound = [&](double r) { return std::log(((1.0 + omega) * r + 1.0) / omega) / std::log(4.0); };
+    auto ratio = [&](int64_t mp, int64_t mc) { return std::sqrt((double)(mc - d) / (double)(mp - d)); };
+    for (int i = 0; i < n; ++i) {
+        const double r = n < 2 ? 1.0 : (i == 0 ? ratio(m[0], m[1]) : ratio(m[i - 1], m[i]));
+        a[i] = std::max(1, (int)std::ceil(bound(r) - 1e-12));
+    }
+    return a;
+}
+
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
@@ -931,6 +956,8 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     const int dtype = X[0].dtype;
     if (dtype != SPCG_F32 && dtype != SPCG_BF16)
         return fail(ctx, SPCG_E_DTYPE, "the batched form needs SPCG_F32 or SPCG_BF16 storage");
+    if (opts->a_rule != SPCG_A_FIXED)
+        return fail(ctx, SPCG_E_INVALID_ARG, "the batched form takes a fixed a / a_list");
     for (int p = 0; p < nprob; ++p) {
         if ((rc = check_mat(ctx, &X[p], "X[p]")) != SPCG_OK) return rc;
         if ((rc = check_mat(ctx, &Y[p], "Y[p]")) != SPCG_OK) return rc;
@@ -1500,7 +1527,8 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if (opts->method != SPCG_METHOD_SPCG && opts->method != SPCG_METHOD_FULL_PCG)
         return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
     if (opts->a < 0 || opts->T < 0 || opts->tol < 0.0 || opts->a_list_len < 0 ||
-        (opts->a_list_len > 0 && !opts->a_list) || opts->stage_stride < 0 || opts->stage_stride > 2)
+        (opts->a_list_len > 0 && !opts->a_list) || opts->stage_stride < 0 || opts->stage_stride > 2 ||
+        (opts->a_rule != SPCG_A_FIXED && opts->a_rule != SPCG_A_THEORY) || opts->omega < 0.0 || opts->omega >= 1.0)
         return fail(ctx, SPCG_E_INVALID_ARG, "bad solve options");
     const bool learned = opts->schedule == SPCG_SCHEDULE_LEARNED;
     if (opts->schedule != SPCG_SCHEDULE_PLAIN && !learned)
@@ -1556,10 +1584,17 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     std::vector<int64_t> stages;
     for (int64_t i = sk.K - 1; i >= 0; i -= stride) stages.push_back(i);
     std::reverse(stages.begin(), stages.end());
+    std::vector<int> a_th;
+    if (!learned && opts->a_rule == SPCG_A_THEORY) {
+        std::vector<int64_t> ms;
+        for (int64_t i : stages) ms.push_back(sk.m[i]);
+        a_th = theory_a(ms.data(), (int)ms.size(), d, opts->omega > 0.0 ? opts->omega : 0.5);
+    }
     int t1 = 0, a_used = a;
     for (size_t si = 0; si < stages.size(); ++si) {
         int ai = a;
         if (!learned && opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(si, opts->a_list_len - 1)];
+        if (!a_th.empty()) ai = a_th[si];
         if (ai < 0) return fail(ctx, SPCG_E_INVALID_ARG, "negative a_i");
         if (t1 + ai > T) ai = std::max(0, T - t1);
         a_used = ai;

@@ -84,3 +84,44 @@ def test_complexity_and_flops():
     assert t["stage1"] == pytest.approx(4 * a * N * d)
     assert pcg_flops(1000, 10) == (4 * 1000 + 13) * 10 + 200
     assert prediction_efficiency(1000, 10, 505) == pytest.approx(2.0)
+
+
+def test_theory_schedule_follows_theorems_3_3_and_3_4():
+    # doubling from m_1 = 4d: r_{1,2}^2 = 2 + d/(m_1 - d) (remark after
+    # Theorem 3.3), the bounds decrease with i, and a_1 = ceil(alpha)
+    from oracle.theory import alpha_bound, theory_schedule
+    d, omega = 50, 0.5
+    sizes = [4 * d * 2 ** i for i in range(7)]
+    a = theory_schedule(sizes, d, omega)
+    r12 = math.sqrt(2 + d / (sizes[0] - d))
+    assert a[0] == math.ceil(math.log((1 + (1 + omega) * r12) / omega) / math.log(4))
+    assert a[0] == math.ceil(alpha_bound(sizes[0], sizes[1], d, omega))
+    for i in range(1, 7):
+        r = math.sqrt((sizes[i] - d) / (sizes[i - 1] - d))
+        assert a[i] == math.ceil(math.log(((1 + omega) * r + 1) / omega) / math.log(4))
+    assert all(x >= y for x, y in zip(a, a[1:]))
+    # omega -> smaller demands more iterations; a single stage uses r = 1
+    assert sum(theory_schedule(sizes, d, 0.05)) > sum(a)
+    assert theory_schedule([1000], d, 0.5) == [math.ceil(math.log(2.5 / 0.5) / math.log(4))]
+    # the tuned sizes of Sec. 4.3: the jump 2^16 -> 2^20 (r ~ 4) asks for more
+    # iterations than a doubling step before rounding, and never fewer after
+    tuned = [2 ** k for k in range(10, 17)] + [2 ** 20]
+    at = theory_schedule(tuned, 64, 0.5)
+    assert iteration_lower_bound(tuned[-2], tuned[-1], 64, 0.5) > iteration_lower_bound(tuned[-3], tuned[-2], 64, 0.5)
+    assert at[-1] >= at[-2]
+
+
+def test_oracle_spcg_with_size_list_and_theory_counts():
+    from oracle.spcg import spcg, rel_pred_error
+    from oracle.ols import ols_householder
+    from oracle.theory import theory_schedule
+    rng = np.random.default_rng(9)
+    N, d = 1 << 14, 16
+    X = rng.standard_normal((N, d)) * np.logspace(0, 2, d)
+    Y = X @ rng.standard_normal(d) + 0.01 * rng.standard_normal(N)
+    sizes = [2 ** k for k in range(7, 12)] + [2 ** 13]
+    b, info = spcg(X, Y, 1, sizes=sizes, a=("theory", 0.5))
+    assert info["sizes"] == sizes
+    assert info["per_rhs"][0]["a_list"] == theory_schedule(sizes, d, 0.5)
+    assert info["per_rhs"][0]["T_stage1"] == sum(theory_schedule(sizes, d, 0.5))
+    assert rel_pred_error(X, b, ols_householder(X, Y)) < 1e-6
