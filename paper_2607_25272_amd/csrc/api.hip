@@ -190,6 +190,10 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
     HIP_TRY(ctx, ctx->tables.ensure((size_t)2 * Np * sizeof(int32_t)));
     int32_t* tbl = ctx->tables.as<int32_t>();
     int32_t* tbl_hat = tbl + Np;
+    // scratch (grown before any launch below uses it): the FP32 working copy
+    // of the stage folds and the segment partials of S_hat
+    const size_t seg_bytes = (size_t)64 * sk->r * ld * dtype_bytes(sk->dtype);
+    HIP_TRY(ctx, ctx->zbuf.ensure(std::max(seg_bytes, K ? (size_t)sk->m[K - 1] * ld * 4 : (size_t)0)));
     hipStream_t st = ctx->stream;
     HIP_TRY(ctx, launch_cs_tables(st, sk->seed, sk->L, K ? tbl : nullptr, tbl_hat));
     CsJob j{};
@@ -215,10 +219,7 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
         const int64_t lowest = K - 1 - J;   // coarsest stage written by the gather
         char* Bb = static_cast<char*>(sk->pB);
         void* work = nullptr;
-        if (!direct && lowest > 0) {
-            HIP_TRY(ctx, ctx->zbuf.ensure((size_t)sk->m[lowest] * ld * 4));
-            work = ctx->zbuf.p;
-        }
+        if (!direct && lowest > 0) work = ctx->zbuf.p;   // m[lowest] x ld FP32, sized above
         CsTreeJob t{};
         t.base = j;
         t.base.y = static_cast<const double*>(Y->data);
@@ -251,6 +252,10 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
     h.nbk = sk->r;
     h.out = sk->pBh;
     h.out_dtype = sk->dtype;
+    // segment partials of the few S_hat buckets (at most 64 per bucket; the
+    // buffer was sized before the first launch)
+    h.scratch = ctx->zbuf.p;
+    h.scratch_bytes = seg_bytes;
     HIP_TRY(ctx, run_cs_gather(st, h));
     return SPCG_OK;
 }

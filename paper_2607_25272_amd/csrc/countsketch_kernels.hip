@@ -9,11 +9,11 @@
 //
 // The gather kernel inverts the map: a table lists, for every slot y, the
 // row k with q(k) = y and its sign, and bucket b sums the rows of slots
-// b, b + m, b + 2m, ... in that order (fixed order, no atomics).  One wave
-// handles one (bucket, 256-column window) pair and keeps up to four whole
-// row segments in flight; the rows are random, but each segment is 1 KB
-// (FP32) or more of contiguous memory.  Every row of X is read exactly once
-// per sketch.
+// b, b + m, b + 2m, ... in that order (fixed order, no atomics).  A group
+// of 16, 32 or 64 lanes (the narrowest that covers the row, 4 columns per
+// lane) handles one (bucket, window) pair and keeps up to four row segments
+// in flight; the rows are random, but each segment is contiguous (1 KB for a
+// 256-column FP32 window).  Every row of X is read exactly once per sketch.
 #include <type_traits>
 
 #include "common.hpp"
@@ -25,7 +25,6 @@ namespace spcg {
 namespace {
 
 constexpr int CS_WAVES = 4;     // waves per block
-constexpr int CS_WIN = 256;     // columns per wave task (4 per lane)
 constexpr int CS_MU = 4;        // member rows in flight per wave
 
 __global__ void cs_tables_kernel(uint64_t seed, int L, int64_t np, int32_t* tbl, int32_t* tbl_hat) {
@@ -136,30 +135,40 @@ __device__ __forceinline__ void store4(void* out, int out_dtype, int64_t idx, co
 
 struct GatherArgs {
     CsJob j;
-    int nwin;      // 256-column windows per row (ld / 256 rounded up)
+    int nwin;      // column windows per row
     int xvec;      // rows allow aligned 4-element loads
+    int nseg;      // segments per bucket (slots t = seg, seg + nseg, ...)
+    void* seg_out; // nseg > 1: partial sums [seg][bucket][ld] in the sum type
 };
 
-template <typename TIN, typename TZ>
+// LPB lanes take one (bucket, 4 LPB-column window) pair, so a wave holds
+// 64 / LPB buckets at once when the rows are short.
+template <typename TIN, typename TZ, int LPB>
 __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) {
+    constexpr int NG = 64 / LPB;
     const CsJob& j = a.j;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, gi = lane / LPB, sl = lane % LPB;
     const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t nwaves = (int64_t)gridDim.x * CS_WAVES;
-    const int64_t ntask = j.nbk * a.nwin;
+    const int64_t ntask = j.nbk * a.nwin * a.nseg;
+    const int64_t step = (int64_t)a.nseg * j.nbk;    // between a segment's slots
     const bool vec = a.xvec != 0;
-    for (int64_t task = wave0; task < ntask; task += nwaves) {
-        const int64_t b = task / a.nwin;
-        const int w = (int)(task - b * a.nwin);
-        const int64_t c = (int64_t)w * CS_WIN + 4 * lane;
+    for (int64_t t0 = wave0 * NG; t0 < ntask; t0 += nwaves * NG) {
+        const int64_t task = t0 + gi;
+        if (task >= ntask) continue;
+        const int64_t rest = task / a.nseg;
+        const int sg = (int)(task - rest * a.nseg);
+        const int64_t b = rest / a.nwin;
+        const int w = (int)(rest - b * a.nwin);
+        const int64_t c = (int64_t)w * 4 * LPB + 4 * sl;
         const bool do_y = j.outy && w == 0;
         TZ acc[4] = {TZ(0), TZ(0), TZ(0), TZ(0)};
         double yacc = 0.0;
-        for (int64_t y0 = b; y0 < j.Np; y0 += CS_MU * j.nbk) {
+        for (int64_t y0 = b + sg * j.nbk; y0 < j.Np; y0 += CS_MU * step) {
             int32_t e[CS_MU];
 #pragma unroll
             for (int u = 0; u < CS_MU; ++u) {
-                const int64_t yv = y0 + (int64_t)u * j.nbk;
+                const int64_t yv = y0 + (int64_t)u * step;
                 e[u] = yv < j.Np ? j.tbl[yv] : 0x7fffffff;   // past the end: no row
             }
             TZ v[CS_MU][4];
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) 
                 yv_[u] = 0.0;
                 if (k < j.N) {
                     Load4<TIN, TZ>::run(j.x, k, j.ldx, c, j.d, vec, j.col_scale, v[u]);
-                    if (do_y && lane < j.k) yv_[u] = j.y[k * j.ldy_in + lane];
+                    if (do_y && sl < j.k) yv_[u] = j.y[k * j.ldy_in + sl];
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) v[u][q] = TZ(0);
@@ -184,12 +193,32 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) 
                 yacc += neg ? -yv_[u] : yv_[u];
             }
         }
+        constexpr int SUM_DT = std::is_same<TZ, double>::value ? DT_F64 : DT_F32;
         if (c < j.ld) {
-            store4<TZ>(j.out, j.out_dtype, b * j.ld + c, acc);
-            if (j.work) store4<TZ>(j.work, std::is_same<TZ, double>::value ? DT_F64 : DT_F32, b * j.ld + c, acc);
+            if (a.nseg > 1) {
+                store4<TZ>(a.seg_out, SUM_DT, ((int64_t)sg * j.nbk + b) * j.ld + c, acc);
+            } else {
+                store4<TZ>(j.out, j.out_dtype, b * j.ld + c, acc);
+                if (j.work) store4<TZ>(j.work, SUM_DT, b * j.ld + c, acc);
+            }
         }
-        if (do_y && lane < j.ldoy) j.outy[b * j.ldoy + lane] = lane < j.k ? yacc : 0.0;
+        if (do_y && sl < j.ldoy) j.outy[b * j.ldoy + sl] = sl < j.k ? yacc : 0.0;
     }
+}
+
+// Bucket rows from segment partials: sum over segments in ascending order.
+template <typename TZ>
+__global__ __launch_bounds__(256) void cs_seg_reduce_kernel(const TZ* part, int nseg, int64_t nbk, int64_t ld, void* out,
+                                                            int out_dtype) {
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (e >= nbk * ld) return;
+    TZ v[4] = {TZ(0), TZ(0), TZ(0), TZ(0)};
+    for (int sg = 0; sg < nseg; ++sg) {
+        const TZ* p = part + (int64_t)sg * nbk * ld + e;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += p[q];
+    }
+    store4<TZ>(out, out_dtype, e, v);
 }
 
 template <typename TZ>
@@ -232,20 +261,23 @@ struct TreeArgs {
 
 constexpr int ipow(int g, int j) { return j == 0 ? 1 : g * ipow(g, j - 1); }
 
-template <typename TIN, typename TZ, int G, int J>
+template <typename TIN, typename TZ, int G, int J, int LPB>
 __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs a) {
     constexpr int NF = ipow(G, J);   // finest buckets per coarse bucket
+    constexpr int NG = 64 / LPB;     // coarse buckets per wave (short rows)
     const CsJob& j = a.j;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, gi = lane / LPB, sl = lane % LPB;
     const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t nwaves = (int64_t)gridDim.x * CS_WAVES;
     const int64_t mc = a.m[J];
     const int64_t ntask = mc * a.nwin;
     const bool vec = a.xvec != 0;
-    for (int64_t task = wave0; task < ntask; task += nwaves) {
+    for (int64_t t0 = wave0 * NG; t0 < ntask; t0 += nwaves * NG) {
+        const int64_t task = t0 + gi;
+        if (task >= ntask) continue;
         const int64_t c = task / a.nwin;
         const int w = (int)(task - c * a.nwin);
-        const int64_t col = (int64_t)w * CS_WIN + 4 * lane;
+        const int64_t col = (int64_t)w * 4 * LPB + 4 * sl;
         const bool do_y = j.outy && w == 0;
         TZ acc[NF][4];
         double yacc[NF];
@@ -270,7 +302,7 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs 
                     yv_[u] = 0.0;
                     if (k < j.N) {
                         Load4<TIN, TZ>::run(j.x, k, j.ldx, col, j.d, vec, j.col_scale, v[u]);
-                        if (do_y && lane < j.k) yv_[u] = j.y[k * j.ldy_in + lane];
+                        if (do_y && sl < j.k) yv_[u] = j.y[k * j.ldy_in + sl];
                     } else {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) v[u][q] = TZ(0);
@@ -285,7 +317,7 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs 
                 }
             }
             if (col < j.ld) store4<TZ>(a.out[0], j.out_dtype, (c + t * mc) * j.ld + col, acc[t]);
-            if (do_y && lane < j.ldoy) a.outy[0][(c + t * mc) * j.ldoy + lane] = lane < j.k ? yacc[t] : 0.0;
+            if (do_y && sl < j.ldoy) a.outy[0][(c + t * mc) * j.ldoy + sl] = sl < j.k ? yacc[t] : 0.0;
         }
         // coarser levels: bucket s of level l adds buckets s + r G^(J-l) of
         // level l - 1 in ascending r (the folding order)
@@ -302,7 +334,7 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs 
                     yacc[s2] += yacc[s2 + r * nb];
                 }
                 if (col < j.ld) store4<TZ>(a.out[l], j.out_dtype, (c + s2 * mc) * j.ld + col, acc[s2]);
-                if (do_y && lane < j.ldoy) a.outy[l][(c + s2 * mc) * j.ldoy + lane] = lane < j.k ? yacc[s2] : 0.0;
+                if (do_y && sl < j.ldoy) a.outy[l][(c + s2 * mc) * j.ldoy + sl] = sl < j.k ? yacc[s2] : 0.0;
             }
         }
         if (a.work && col < j.ld)
@@ -310,32 +342,54 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs 
     }
 }
 
-template <typename TIN, typename TZ, int G, int J>
+template <typename TIN, typename TZ, int G, int J, int LPB>
 hipError_t tree_launch(hipStream_t st, const TreeArgs& a) {
     const int64_t ntask = a.m[J] * a.nwin;
-    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES), 65536);
-    cs_gather_tree_kernel<TIN, TZ, G, J><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES * (64 / LPB)), 65536);
+    cs_gather_tree_kernel<TIN, TZ, G, J, LPB><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
     return hipGetLastError();
 }
 
-template <typename TIN, typename TZ>
-hipError_t tree_dispatch(hipStream_t st, const TreeArgs& a, int g, int levels) {
-    if (levels == 0) return tree_launch<TIN, TZ, 2, 0>(st, a);
+template <typename TIN, typename TZ, int LPB>
+hipError_t tree_dispatch_l(hipStream_t st, const TreeArgs& a, int g, int levels) {
+    if (levels == 0) return tree_launch<TIN, TZ, 2, 0, LPB>(st, a);
     if (g == 2) {
-        if (levels == 1) return tree_launch<TIN, TZ, 2, 1>(st, a);
-        if (levels == 2) return tree_launch<TIN, TZ, 2, 2>(st, a);
-        if (levels == 3) return tree_launch<TIN, TZ, 2, 3>(st, a);
+        if (levels == 1) return tree_launch<TIN, TZ, 2, 1, LPB>(st, a);
+        if (levels == 2) return tree_launch<TIN, TZ, 2, 2, LPB>(st, a);
+        if (levels == 3) return tree_launch<TIN, TZ, 2, 3, LPB>(st, a);
     }
-    if (g == 4 && levels == 1) return tree_launch<TIN, TZ, 4, 1>(st, a);
+    if (g == 4 && levels == 1) return tree_launch<TIN, TZ, 4, 1, LPB>(st, a);
     return hipErrorInvalidValue;
 }
 
 template <typename TIN, typename TZ>
-hipError_t gather_launch(hipStream_t st, const GatherArgs& a) {
-    const int64_t ntask = a.j.nbk * a.nwin;
-    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES), 65536);
-    cs_gather_kernel<TIN, TZ><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+hipError_t tree_dispatch(hipStream_t st, const TreeArgs& a, int g, int levels, int lpb) {
+    if (lpb == 16) return tree_dispatch_l<TIN, TZ, 16>(st, a, g, levels);
+    if (lpb == 32) return tree_dispatch_l<TIN, TZ, 32>(st, a, g, levels);
+    return tree_dispatch_l<TIN, TZ, 64>(st, a, g, levels);
+}
+
+template <typename TIN, typename TZ, int LPB>
+hipError_t gather_launch_l(hipStream_t st, const GatherArgs& a) {
+    const int64_t ntask = a.j.nbk * a.nwin * a.nseg;
+    const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES * (64 / LPB)), 65536);
+    cs_gather_kernel<TIN, TZ, LPB><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
     return hipGetLastError();
+}
+
+template <typename TIN, typename TZ>
+hipError_t gather_launch(hipStream_t st, const GatherArgs& a, int lpb) {
+    if (lpb == 16) return gather_launch_l<TIN, TZ, 16>(st, a);
+    if (lpb == 32) return gather_launch_l<TIN, TZ, 32>(st, a);
+    return gather_launch_l<TIN, TZ, 64>(st, a);
+}
+
+// Lanes per (bucket, window): the narrowest power of two >= 16 that covers
+// the row with 4 columns per lane (and the responses, one per lane).
+int lanes_per_bucket(int64_t ld, int64_t k) {
+    int lpb = 16;
+    while (lpb < 64 && (4 * lpb < ld || lpb < k)) lpb *= 2;
+    return lpb;
 }
 
 }  // namespace
@@ -353,16 +407,40 @@ hipError_t run_cs_gather(hipStream_t st, const CsJob& j) {
     if (j.outy && (j.k < 1 || j.k > 64 || j.ldoy < j.k || j.ldoy > 64)) return hipErrorInvalidValue;
     GatherArgs a{};
     a.j = j;
-    a.nwin = (int)ceil_div(j.ld, CS_WIN);
+    const int lpb = lanes_per_bucket(j.ld, j.outy ? std::max<int64_t>(j.k, j.ldoy) : 1);
+    a.nwin = (int)ceil_div(j.ld, 4 * lpb);
+    // few, long buckets (the preconditioner sketch at small d): split each
+    // bucket's slots over segments so that enough lane groups stream rows
+    a.nseg = 1;
+    const int64_t groups = j.nbk * a.nwin, members = ceil_div(j.Np, j.nbk);
+    const size_t sum_es = (j.in_dtype == DT_F64) ? 8 : 4;
+    if (!j.outy && !j.work && j.scratch && groups < 16384 && members > 64) {
+        int64_t ns = std::min<int64_t>(ceil_div(16384, groups), members / 16);
+        ns = std::min<int64_t>(ns, (int64_t)(j.scratch_bytes / ((size_t)j.nbk * j.ld * sum_es)));
+        if (ns > 1) {
+            a.nseg = (int)ns;
+            a.seg_out = j.scratch;
+        }
+    }
     const int es = dtype_bytes(j.in_dtype);
     a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
+    hipError_t e;
     switch (j.in_dtype) {
-        case DT_F64: return gather_launch<double, double>(st, a);
-        case DT_F32: return gather_launch<float, float>(st, a);
-        case DT_BF16: return gather_launch<bf16_t, float>(st, a);
-        case DT_FP8: return gather_launch<fp8_t, float>(st, a);
+        case DT_F64: e = gather_launch<double, double>(st, a, lpb); break;
+        case DT_F32: e = gather_launch<float, float>(st, a, lpb); break;
+        case DT_BF16: e = gather_launch<bf16_t, float>(st, a, lpb); break;
+        case DT_FP8: e = gather_launch<fp8_t, float>(st, a, lpb); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess || a.nseg == 1) return e;
+    const unsigned blocks = (unsigned)ceil_div(j.nbk * j.ld / 4, 256);
+    if (f64)
+        cs_seg_reduce_kernel<double><<<blocks, 256, 0, st>>>(static_cast<const double*>(a.seg_out), a.nseg, j.nbk,
+                                                             j.ld, j.out, j.out_dtype);
+    else
+        cs_seg_reduce_kernel<float><<<blocks, 256, 0, st>>>(static_cast<const float*>(a.seg_out), a.nseg, j.nbk, j.ld,
+                                                            j.out, j.out_dtype);
+    return hipGetLastError();
 }
 
 hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& t) {
@@ -378,7 +456,8 @@ hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& t) {
     TreeArgs a{};
     a.j = j;
     a.j.outy = nullptr;
-    a.nwin = (int)ceil_div(j.ld, CS_WIN);
+    const int lpb = lanes_per_bucket(j.ld, t.outy[0] ? std::max<int64_t>(j.k, j.ldoy) : 1);
+    a.nwin = (int)ceil_div(j.ld, 4 * lpb);
     const int es = dtype_bytes(j.in_dtype);
     a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
     for (int l = 0; l <= t.levels; ++l) {
@@ -389,10 +468,10 @@ hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& t) {
     a.j.outy = t.outy[0];
     a.work = t.work;
     switch (j.in_dtype) {
-        case DT_F64: return tree_dispatch<double, double>(st, a, t.growth, t.levels);
-        case DT_F32: return tree_dispatch<float, float>(st, a, t.growth, t.levels);
-        case DT_BF16: return tree_dispatch<bf16_t, float>(st, a, t.growth, t.levels);
-        case DT_FP8: return tree_dispatch<fp8_t, float>(st, a, t.growth, t.levels);
+        case DT_F64: return tree_dispatch<double, double>(st, a, t.growth, t.levels, lpb);
+        case DT_F32: return tree_dispatch<float, float>(st, a, t.growth, t.levels, lpb);
+        case DT_BF16: return tree_dispatch<bf16_t, float>(st, a, t.growth, t.levels, lpb);
+        case DT_FP8: return tree_dispatch<fp8_t, float>(st, a, t.growth, t.levels, lpb);
         default: return hipErrorInvalidValue;
     }
 }

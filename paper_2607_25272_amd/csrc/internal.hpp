@@ -70,6 +70,8 @@ struct CsJob {
     int64_t ld;
     double* outy;             // nbk x ldoy sketched responses, or null
     int64_t ldoy;
+    void* scratch;            // optional: lets few, long buckets be split into
+    size_t scratch_bytes;     // segments (partial sums, reduced in segment order)
 };
 hipError_t run_cs_gather(hipStream_t st, const CsJob& job);
 // The finest stage and up to 3 coarser ones in one gather: a wave takes a
