@@ -26,20 +26,26 @@ import numpy as np
 from .linalg import precond_apply
 
 
-def pcg(A, b, c2, R, x0, iters, tol=None, history=False):
+def pcg(A, b, c2, R, x0, iters, tol=None, history=False, g0=None):
     """Returns (x, info).
 
     iters: maximum number of iterations (the stage's a_i, or the remaining
     budget in Stage II).  tol: None -> run exactly ``iters`` iterations.
-    info: {"iters": done, "rho": [...], "converged": bool, "xs": [...]}.
+    g0: the starting gradient c2 A^T (b - A x0) when the caller already has
+    it (nested-gradient reuse); computed here otherwise.
+    info: {"iters": done, "rho": [...], "converged": bool, "xs": [...],
+    "g": the final recurrence gradient}.
     A exact zero rho means the current x solves the system; no further
     iteration is taken (avoids 0/0).
     """
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
-    resid = b - A @ x
-    g = c2 * (A.T @ resid)
+    if g0 is None:
+        resid = b - A @ x
+        g = c2 * (A.T @ resid)
+    else:
+        g = np.array(g0, dtype=np.float64, copy=True)
     ax_norm = np.linalg.norm(A @ x) * np.sqrt(c2) if tol is not None else None
     z = precond_apply(R, g)
     p = z.copy()
@@ -51,7 +57,7 @@ def pcg(A, b, c2, R, x0, iters, tol=None, history=False):
         return tol is not None and np.sqrt(max(rho_, 0.0)) <= tol * axn
 
     if _stop(rho, ax_norm):
-        info.update(iters=0, converged=True)
+        info.update(iters=0, converged=True, g=g)
         return x, info
     while done < iters:
         if rho == 0.0:
@@ -79,4 +85,5 @@ def pcg(A, b, c2, R, x0, iters, tol=None, history=False):
             info["converged"] = True
             break
     info["iters"] = done
+    info["g"] = g
     return x, info

@@ -65,11 +65,16 @@ def _stage_problems(X, Y, seed, sizes, r, sketch):
 
 
 def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
-         growth=2, history=False, sketch="srht", sizes=None):
+         growth=2, history=False, sketch="srht", sizes=None, nested_gradient=False):
     """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k).
     ``sizes`` gives the stage sizes explicitly (e.g. the tuned schedule of
     Sec. 4.3); ``a`` may be a number, a per-stage list, or ("theory", omega)
-    for the counts of Theorems 3.3 / 3.4 (``theory.theory_schedule``)."""
+    for the counts of Theorems 3.3 / 3.4 (``theory.theory_schedule``).
+
+    ``nested_gradient`` (SRHT only): the sketches are nested prefixes
+    (Sec. 2.2), so with c2_i = 1/m_i the stage-(i+1) starting gradient is
+    (m_i/m_{i+1}) g_i(x) + c2_{i+1} dA^T (db - dA x) over the new rows
+    dA = rows m_i..m_{i+1} only, g_i the previous stage's final gradient."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     N, d = X.shape
@@ -87,8 +92,16 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
         x = np.zeros(d)
         stage_x = []
         t = 0
+        g_prev, m_prev = None, 0
         for (A, b, c2), ai in zip(probs, a_list):
-            x, _ = pcg(A, b[:, c], c2, R, x, ai)
+            g0 = None
+            if nested_gradient and g_prev is not None:
+                if sketch != "srht":
+                    raise ValueError("nested-gradient reuse needs nested prefixes (the SRHT)")
+                dA, db = A[m_prev:], b[m_prev:, c]
+                g0 = (m_prev / A.shape[0]) * g_prev + c2 * (dA.T @ (db - dA @ x))
+            x, inf1 = pcg(A, b[:, c], c2, R, x, ai, g0=g0)
+            g_prev, m_prev = inf1["g"], A.shape[0]
             t += ai
             stage_x.append(x.copy())
         x, inf2 = pcg(X, Ys[:, c], 1.0, R, x, max(T - t, 0), tol=tol, history=history)

@@ -127,3 +127,36 @@ def test_spcg_prediction_error_reaches_ols_level():
         bT, _ = spcg(X, Y, seed=s + 1, m0=8 * 16, tol=1e-12)
         ratios.append(np.linalg.norm(X @ (bT - beta)) ** 2 / np.linalg.norm(X @ (bh - beta)) ** 2)
     assert max(ratios) < 1.01
+
+
+def test_nested_gradient_reuse_equals_direct_gradient():
+    # Nested prefixes (Sec. 2.2): with c2 = 1/m the stage-start gradient of
+    # the larger prefix is the rescaled gradient of the smaller one plus the
+    # new rows' term, for any x
+    from oracle.pcg import pcg
+    from oracle.spcg import precond_from_sketch, spcg, rel_pred_error
+    from oracle.sketch import nested_srht
+    from oracle.ols import ols_householder
+    rng = np.random.default_rng(11)
+    N, d = 4096, 12
+    X = rng.standard_normal((N, d)) * np.logspace(0, 2, d)
+    Y = X @ rng.standard_normal(d) + 0.1 * rng.standard_normal(N)
+    B, BY, Bh, _ = nested_srht(X, Y, 3, 1024, 72)
+    R = precond_from_sketch(Bh)
+    x = rng.standard_normal(d)
+    m1, m2 = 256, 512
+    g1 = (B[:m1].T @ (BY[:m1] - B[:m1] @ x)) / m1
+    direct = (B[:m2].T @ (BY[:m2] - B[:m2] @ x)) / m2
+    nested = (m1 / m2) * g1 + (B[m1:m2].T @ (BY[m1:m2] - B[m1:m2] @ x)) / m2
+    np.testing.assert_allclose(nested, direct, rtol=1e-12, atol=1e-12 * np.abs(direct).max())
+    # the PCG's final recurrence gradient equals the true gradient at its iterate
+    xe, info = pcg(B[:m1], BY[:m1], 1.0 / m1, R, np.zeros(d), 3)
+    true_g = (B[:m1].T @ (BY[:m1] - B[:m1] @ xe)) / m1
+    np.testing.assert_allclose(info["g"], true_g, rtol=1e-9, atol=1e-9 * np.abs(true_g).max())
+    # and SPCG with reuse reaches the OLS estimator with the same stage counts
+    b1, i1 = spcg(X, Y, 3, nested_gradient=True)
+    b0, i0 = spcg(X, Y, 3)
+    bh = ols_householder(X, Y)
+    assert rel_pred_error(X, b1, bh) < 1e-6
+    assert i1["per_rhs"][0]["T_stage1"] == i0["per_rhs"][0]["T_stage1"]
+    assert abs(i1["per_rhs"][0]["stage2"]["iters"] - i0["per_rhs"][0]["stage2"]["iters"]) <= 1
