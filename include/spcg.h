@@ -268,7 +268,13 @@ typedef struct spcg_solve_opts {
                                    context and storage type, timing one product pass with
                                    2, 4 and 8 (results are discarded) */
     int32_t a_rule;           /* SPCG_A_FIXED (a / a_list) or SPCG_A_THEORY (below) */
-    int32_t reserved3;
+    int32_t nested_gradient;  /* 1: SRHT stages after the first start from the previous
+                                 stage's gradient: g = (m_prev / m_i) g_prev
+                                 + (1/m_i) dA^T (db - dA x) over the new prefix rows only
+                                 (the sketches are nested prefixes, Sec. 2.2), so each
+                                 stage-start pass reads m_i - m_prev rows instead of m_i.
+                                 Ignored for a CountSketch (its stages are not prefixes).
+                                 spcg_solve_opts_default sets 1. */
     double omega;             /* SPCG_A_THEORY: the stagewise accuracy factor (0: 0.5) */
 } spcg_solve_opts;
 

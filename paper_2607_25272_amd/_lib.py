@@ -75,7 +75,7 @@ class SolveOpts(ctypes.Structure):
                 ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
                 ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
                 ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32),
-                ("a_rule", c_i32), ("reserved3", c_i32), ("omega", c_f64)]
+                ("a_rule", c_i32), ("nested_gradient", c_i32), ("omega", c_f64)]
 
 
 class SolveStats(ctypes.Structure):

@@ -707,17 +707,31 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
     return SPCG_OK;
 }
 
+// m_prev > 0: the previous stage ran on the first m_prev rows of this
+// prefix view (nested sketches) and left its final gradient in the state;
+// the starting gradient then needs a G pass over the new rows only.
 int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
-                     const spcg_precond_t* pc, double* x, int iters) {
+                     const spcg_precond_t* pc, double* x, int iters, int64_t m_prev = 0) {
     int rc;
     DspaceState S{};
     if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
     hipStream_t st = ctx->stream;
     const int64_t dpad = round_up(A->cols, 64);
     int np = 0;
-    if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
-    HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
-                             np, dpad, c2));
+    if (m_prev > 0 && m_prev < A->rows) {
+        spcg_mat dA = *A, db = *b;
+        dA.data = static_cast<const char*>(A->data) + (size_t)m_prev * A->ld * dtype_bytes(A->dtype);
+        dA.rows = A->rows - m_prev;
+        db.data = static_cast<const double*>(b->data) + (size_t)m_prev * b->ld;
+        db.rows = dA.rows;
+        if ((rc = product_pass(ctx, &dA, &db, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, run_phase_a(st, S, PA_START_NESTED, nullptr, ctx->part_g.as<double>(),
+                                 ctx->part_scal.as<double>(), np, dpad, c2, (double)m_prev / (double)A->rows));
+    } else {
+        if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
+                                 np, dpad, c2));
+    }
     HIP_TRY(ctx, run_phase_b(st, S, 1));
     for (int it = 0; it < iters; ++it) {
         if ((rc = product_pass(ctx, A, b, S, PM_S, &np, nullptr)) != SPCG_OK) return rc;
@@ -1512,6 +1526,7 @@ void spcg_solve_opts_default(spcg_solve_opts* o) {
     o->T = 100;
     o->check_every = 1;
     o->tol = 5e-7;
+    o->nested_gradient = 1;
 }
 
 int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_solve_opts* opts,
@@ -1606,7 +1621,10 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         spcg_mat A{}, b{};
         double c2 = 1.0;
         spcg_sketch_view(&sk, (int)stages[si], &A, &b, &c2);
-        if ((rc = stage_run_nosync(ctx, &A, &b, c2, &pc, beta, ai)) != SPCG_OK) return rc;
+        // nested prefixes: reuse the previous stage's gradient (SRHT only)
+        const int64_t m_prev = (opts->nested_gradient && si > 0 && sk.kind == SPCG_SKETCH_SRHT)
+                                   ? sk.m[stages[si - 1]] : 0;
+        if ((rc = stage_run_nosync(ctx, &A, &b, c2, &pc, beta, ai, m_prev)) != SPCG_OK) return rc;
         t1 += ai;
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[3], st));

@@ -33,6 +33,7 @@ struct PhaseAArgs {
     int nparts;
     int64_t dpad;
     double c2;
+    double g_scale;   // PA_START_NESTED: weight of the previous gradient
     int variant;
 };
 
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
     const DspaceState& S = a.S;
     const int tx = threadIdx.x & (A_COLS - 1), ty = threadIdx.x / A_COLS;
     const int64_t col = (int64_t)blockIdx.x * A_COLS + tx;
-    const bool want_s = a.variant != PA_START;
+    const bool start = a.variant == PA_START || a.variant == PA_START_NESTED;
+    const bool want_s = !start;
     const bool want_g = a.variant != PA_STEP;
     double ss[4] = {0.0, 0.0, 0.0, 0.0}, gg[4] = {0.0, 0.0, 0.0, 0.0};
     double pc = 0.0;
@@ -90,6 +92,8 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
         g_col *= a.c2;
         if (a.variant == PA_START) {
             S.g[col] = g_col;
+        } else if (a.variant == PA_START_NESTED) {
+            S.g[col] = fma(a.g_scale, S.g[col], g_col);
         } else {
             S.s[col] = s_col;
             dot = pc * s_col;
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
             sc->ax2 = sh_t[0] * a.c2;
         }
         do_step = 0;
-        if (a.variant == PA_START) {
+        if (start) {
             sc->resid2_0 = sh_r[0] * a.c2;
             sc->exact = 0;
         } else {
@@ -312,8 +316,9 @@ hipError_t run_counters_reset(hipStream_t st, unsigned int* c, int n) {
 
 hipError_t run_phase_a(hipStream_t st, const DspaceState& S, int variant, const double* part_s,
                        const double* part_g, const double* part_scal, int nparts, int64_t dpad,
-                       double c2) {
+                       double c2, double g_scale) {
     PhaseAArgs a;
+    a.g_scale = g_scale;
     a.S = S;
     a.part_s = part_s;
     a.part_g = part_g;

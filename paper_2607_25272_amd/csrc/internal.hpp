@@ -150,10 +150,13 @@ struct DspaceState {
     int64_t d;
 };
 // phase A: reduce the product partials; start / step / refresh variants
-enum PhaseA : int { PA_START = 0, PA_STEP = 1, PA_REFRESH = 2 };
+// PA_START_NESTED: g = g_scale * g + c2 * (reduced partials), the starting
+// gradient of a larger nested prefix from the previous stage's gradient and
+// a G pass over the new rows only.
+enum PhaseA : int { PA_START = 0, PA_STEP = 1, PA_REFRESH = 2, PA_START_NESTED = 3 };
 hipError_t run_phase_a(hipStream_t st, const DspaceState& S, int variant, const double* part_s,
                        const double* part_g, const double* part_scal, int nparts, int64_t dpad,
-                       double c2);
+                       double c2, double g_scale = 0.0);
 // phase B: z = H^-1 g, rho' = g^T z, p update (init or CG step)
 hipError_t run_phase_b(hipStream_t st, const DspaceState& S, int init);
 hipError_t run_scalars_reset(hipStream_t st, PcgScalars* sc);

@@ -80,3 +80,26 @@ def test_schedule_option_errors(S, ctx, prob):
     with pytest.raises(S.SpcgError) as e:   # multi-RHS runs the batched form: fixed a only
         S.spcg_solve(ctx, q.X, q.Y, a_rule="theory")
     assert e.value.code == S.SPCG_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_nested_gradient_reuse(S, ctx, storage):
+    # stage starts from the previous stage's gradient plus a
+    # G pass over the new prefix rows; same stage structure, same accuracy
+    print(f"nested gradient {storage}", flush=True)
+    p = workloads.gauss_colscale(1 << 17, 96, 1e4, 1.0, storage=storage, seed=41, device=DEV)
+    Xd = p.x_f64().cpu().numpy()
+    Yd = p.Y.cpu().numpy()[:, 0]
+    bh = ols_householder(Xd, Yd)
+    b0, s0 = S.spcg_solve(ctx, p.X, p.Y, seed=5)
+    b1, s1 = S.spcg_solve(ctx, p.X, p.Y, seed=5, nested_gradient=True)
+    assert s1["converged"] and s1["K"] == s0["K"] and s1["T_stage1"] == s0["T_stage1"]
+    assert abs(s1["T_stage2"] - s0["T_stage2"]) <= 1
+    assert rel_pred_error(Xd, b1.cpu().numpy(), bh) <= 1e-6
+    if storage == "f64":
+        _, info = spcg(Xd, Yd, 5, nested_gradient=True)
+        assert abs(s1["T_stage2"] - info["per_rhs"][0]["stage2"]["iters"]) <= 1
+    # a CountSketch ignores the option (its stages are folds, not prefixes)
+    c0, _ = S.spcg_solve(ctx, p.X, p.Y, seed=5, sketch="cs")
+    c1, _ = S.spcg_solve(ctx, p.X, p.Y, seed=5, sketch="cs", nested_gradient=True)
+    assert torch.equal(c0, c1)
