@@ -379,6 +379,8 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     if (jx.seg_bytes != 0 && jx.seg_bytes != 64 && jx.seg_bytes != 128 && jx.seg_bytes != 256)
         return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128 or 256");
     jx.narrow = 0;
+    jx.stream = 1;
+    jx.num_cu = ctx->num_cu;
     HIP_TRY(ctx, run_fwht(st, jx));
     if (mK) {
         FwhtJob jy{};

@@ -39,6 +39,10 @@ struct FwhtJob {
     int narrow;               // 1: single-column FP64 transform (the response vector)
     int b_bf16;               // 1: store the B rows as BF16 (round to nearest even)
     int seg_bytes;            // 0: default column segment; 64 / 128 / 256: at most this
+                              // (one tile per block)
+    int stream;               // 1: 10- and 11-bit FP32-precision passes use the streaming
+                              // kernel (persistent blocks, next tile prefetched)
+    int num_cu;               // compute units (grid of the streaming kernel)
 };
 // Widest column chunk of the transform (256-byte row segments): every row
 // width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.

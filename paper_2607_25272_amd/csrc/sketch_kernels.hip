@@ -336,6 +336,296 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
     }
 }
 
+// Streaming form of a pass at FP32 working precision (FP32, BF16 and FP8
+// input).  A persistent block of 512 threads walks a fixed share of the
+// tiles; the next tile streams from HBM into an LDS staging buffer through
+// direct global->LDS loads while the current one goes through its
+// butterflies, LDS exchanges and stores, so every CU keeps reads and writes
+// in flight while it computes.  Tiles are 2^NB rows x CW columns with 16 rows
+// per thread: CW = 32 gives NB = 10, CW = 16 gives NB = 11.  The butterflies
+// run in the same order as in fwht_pass_kernel (stages in ascending bit
+// order, each (a, b) -> (a + b, a - b)), so both kernels give bit-identical
+// results.
+//
+// Per tile j: barrier (the staged tile j is complete in every wave); each
+// thread reads its rows from the staging buffer; barrier (staging free);
+// the loads of tile j + 1 into the staging buffer (and, first pass, the
+// permutation entries of the tiles after it) are issued; butterflies and
+// LDS re-slicing run; then one vmcnt(0) wait -- by then the staged loads,
+// issued a whole tile of work earlier, have landed -- and the stores of
+// tile j, which drain during the next tile.
+//
+// Staging layout: row-major, ROWB bytes per tile row, with the row index
+// XOR-swizzled in its low bits by bits 4.. (so the 16-row groups that one
+// wave reads at a time fall into different LDS banks).  A direct load
+// writes 16 bytes per lane at consecutive LDS addresses, so each lane picks
+// the (row, 16-byte piece) that lands at its address.  Exchange buffer: one
+// FP32 element per (row, lane), rows swizzled the same way.
+constexpr int STREAM_THREADS = 512;
+constexpr int stream_vmcnt0() { return (0x7 << 4) | (0xf << 8); }   // s_waitcnt vmcnt(0)
+
+__device__ __forceinline__ void stream_lds_load16(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds(const_cast<void*>(src), (__attribute__((address_space(3))) void*)(lds),
+                                     16, 0, 0);
+}
+
+template <typename TI>
+struct StageRead;   // 4 consecutive staged elements of one row -> FP32
+template <>
+struct StageRead<float> {
+    __device__ static void rd(const unsigned char* p, const float*, int64_t, float* o) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+template <>
+struct StageRead<bf16_t> {
+    __device__ static void rd(const unsigned char* p, const float*, int64_t, float* o) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        o[0] = __uint_as_float(v.x << 16);
+        o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16);
+        o[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+template <>
+struct StageRead<fp8_t> {
+    __device__ static void rd(const unsigned char* p, const float* sc, int64_t col, float* o) {
+        const int w = (int)*reinterpret_cast<const uint32_t*>(p);
+        const fwht_v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+        const fwht_v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+        o[0] = lo.x * sc[col];
+        o[1] = lo.y * sc[col + 1];
+        o[2] = hi.x * sc[col + 2];
+        o[3] = hi.y * sc[col + 3];
+    }
+};
+
+template <typename TIN, int CW, bool FIRST, bool LAST>
+__global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a) {
+    constexpr int VL = 4, Q = 4, R = 16, THREADS = STREAM_THREADS;
+    constexpr int LPR = CW / VL;
+    constexpr int ROWS = THREADS * R / LPR;
+    constexpr int NB = ROWS == 1024 ? 10 : 11;
+    constexpr int NG = (NB + Q - 1) / Q;        // register groups of the pass
+    typedef typename std::conditional<FIRST, TIN, float>::type TI;   // staged element
+    constexpr int IB = (int)sizeof(TI);
+    constexpr int ROWB = CW * IB;               // staged bytes per tile row
+    constexpr int STG = ROWS * ROWB;
+    constexpr int NI = STG / (THREADS * 16);    // direct loads per thread per tile
+    constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;   // staging row swizzle
+    constexpr int XM = 64 / LPR - 1;                       // exchange row swizzle
+    static_assert(ROWS == (1 << NB) && !(FIRST && LAST), "stream tile shape");
+    static_assert(ROWB >= 16 && NI >= 1 && NI * THREADS * 16 == STG && SM < 16 && XM < 16, "staging");
+    // two separate LDS objects: the compiler then knows that exchange
+    // traffic does not touch the buffer the direct loads are filling
+    __shared__ __align__(16) unsigned char stg[STG];
+    __shared__ __align__(16) float exb[ROWS * LPR];
+
+    // This block's tiles are first + j * stride, j < count.  Blocks are
+    // dispatched round-robin over the 8 XCDs; XCD x takes the x-th eighth of
+    // the tiles, so the column chunks of one row group (which share DRAM
+    // pages) are fetched through the same L2 close in time.
+    const int64_t T = a.ntiles;
+    const int64_t G = gridDim.x;
+    int64_t first, stride, count;
+    if ((G & 7) == 0 && (T & 7) == 0) {
+        const int64_t per = T >> 3, M = G >> 3, m = blockIdx.x >> 3;
+        first = (int64_t)(blockIdx.x & 7) * per + m;
+        stride = M;
+        count = m < per ? (per - m + M - 1) / M : 0;
+    } else {
+        first = blockIdx.x;
+        stride = G;
+        count = (int64_t)blockIdx.x < T ? (T - blockIdx.x + G - 1) / G : 0;
+    }
+    if (count == 0) return;   // uniform over the block
+
+    const int lo = a.lo;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lr = threadIdx.x % LPR;
+    const int bidx = threadIdx.x / LPR;
+    // bx: this thread's row-group index (bidx), passed in so that the loop
+    // can hand over a copy the compiler may not hoist: LDS addresses are then
+    // recomputed per tile instead of occupying registers for the whole loop
+    auto tile_row = [](int bx, int s0, int t) -> int {
+        const int base = ((bx >> s0) << (s0 + Q)) | (bx & ((1 << s0) - 1));
+        return base | (t << s0);
+    };
+    auto srow = [](int row) -> int { return row ^ ((row >> 4) & SM); };   // an involution
+    auto xrow = [](int row) -> int { return row ^ ((row >> 4) & XM); };
+    struct Tile {
+        int64_t rowbase;   // global row of tile row 0
+        int64_t cbase;     // first column of the tile
+    };
+    auto tile_of = [&](int64_t j) -> Tile {
+        const int64_t tix = first + j * stride;
+        const int64_t o = tix / a.nchunks;
+        const int64_t cc = tix - o * a.nchunks;
+        const int64_t olo = o & ((1ll << lo) - 1);
+        const int64_t ohi = o >> lo;
+        return Tile{(ohi << (lo + NB)) | olo, cc * CW};
+    };
+    auto grow = [&](const Tile& tl, int r) -> int64_t { return tl.rowbase | ((int64_t)r << lo); };
+    // tile row and 16-byte piece that direct load i of this lane fetches
+    auto dma_slot = [&](int i, int& row, int& piece) {
+        const int P = ((wave * NI + i) * 64 + lane) * 16;
+        row = srow(P / ROWB);
+        piece = (P % ROWB) / 16;
+    };
+
+    int32_t dp[NI];   // first pass: permutation entries of the rows this lane stages next
+    int32_t cp[R];    // first pass: permutation entries of this thread's rows
+    auto load_dperm = [&](int64_t j) __attribute__((always_inline)) {
+        const Tile tl = tile_of(j);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            int row, piece;
+            dma_slot(i, row, piece);
+            dp[i] = a.perm_sign[grow(tl, row)];
+        }
+    };
+    auto load_cperm = [&](int64_t j) __attribute__((always_inline)) {
+        const Tile tl = tile_of(j);
+#pragma unroll
+        for (int t = 0; t < R; ++t) cp[t] = a.perm_sign[grow(tl, tile_row(bidx, 0, t))];
+    };
+    auto issue_stage = [&](int64_t j) __attribute__((always_inline)) {
+        const Tile tl = tile_of(j);
+        unsigned char* dst = stg + wave * NI * 1024;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            int row, piece;
+            dma_slot(i, row, piece);
+            const int64_t col = tl.cbase + piece * (16 / IB);
+            const unsigned char* src;
+            if constexpr (FIRST) {
+                // rows past N and pieces past d read row 0 instead; the
+                // reader zeroes them
+                const int64_t sr = (int64_t)(dp[i] & 0x7fffffff);
+                const bool ok = sr < a.N && col < a.d;
+                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+            } else {
+                src = static_cast<const unsigned char*>(a.zin) + (grow(tl, row) * a.ldz + col) * 4;
+            }
+            stream_lds_load16(src, dst + i * 1024);
+        }
+    };
+
+    float v[R][VL];
+    int32_t sl[R], sh[R];
+    // prologue: stage tile 0
+    if constexpr (FIRST) {
+        load_dperm(0);
+        load_cperm(0);
+    }
+    issue_stage(0);
+    if constexpr (FIRST) {
+        if (count > 1) load_dperm(1);
+    }
+    __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+
+    for (int64_t j = 0; j < count; ++j) {
+        const Tile tl = tile_of(j);
+        int bx = bidx, lx = lr;
+        asm volatile("" : "+v"(bx), "+v"(lx));
+        __syncthreads();   // every wave has waited for its part of tile j
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int row = tile_row(bx, 0, t);
+            const int64_t col0 = tl.cbase + lr * VL;
+            float x[VL];
+            StageRead<TI>::rd(stg + srow(row) * ROWB + lx * VL * IB, a.col_scale, col0, x);
+            if constexpr (FIRST) {
+                const bool valid = (int64_t)(cp[t] & 0x7fffffff) < a.N;
+#pragma unroll
+                for (int e = 0; e < VL; ++e) {
+                    float y = col0 + e < a.d ? x[e] : 0.f;
+                    if (cp[t] < 0) y = -y;
+                    v[t][e] = valid ? y : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VL; ++e) v[t][e] = x[e];
+            }
+        }
+        __syncthreads();   // staging buffer free
+        if (j + 1 < count) issue_stage(j + 1);
+        if constexpr (FIRST) {
+            if (j + 1 < count) load_cperm(j + 1);
+            if (j + 2 < count) load_dperm(j + 2);
+        }
+        if constexpr (LAST) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int64_t k = grow(tl, tile_row(bidx, NB - Q, t));
+                sl[t] = a.inv_slot ? a.inv_slot[k] : -1;
+                sh[t] = a.inv_hat ? a.inv_hat[k] : -1;
+            }
+        }
+        int done = 0, s0 = 0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            const int w = NB - done < Q ? NB - done : Q;
+            const int e0 = Q - w;
+#pragma unroll
+            for (int b = 0; b < Q; ++b) {
+                if (b >= e0 && b < e0 + w) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        if (!(t & (1 << b))) {
+#pragma unroll
+                            for (int e = 0; e < VL; ++e) {
+                                const float x0 = v[t][e], x1 = v[t | (1 << b)][e];
+                                v[t][e] = x0 + x1;
+                                v[t | (1 << b)][e] = x0 - x1;
+                            }
+                        }
+                    }
+                }
+            }
+            done += w;
+            if (gi + 1 < NG) {
+                const int wn = NB - done < Q ? NB - done : Q;
+                const int s1 = done - (Q - wn);
+#pragma unroll
+                for (int e = 0; e < VL; ++e) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) exb[xrow(tile_row(bx, s0, t)) * LPR + lx] = v[t][e];
+                    __syncthreads();
+#pragma unroll
+                    for (int t = 0; t < R; ++t) v[t][e] = exb[xrow(tile_row(bx, s1, t)) * LPR + lx];
+                    __syncthreads();
+                }
+                s0 = s1;
+            }
+        }
+        // the staged loads of tile j + 1 (and the table loads) are complete
+        // after this wait; the stores below drain during the next tile
+        __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        const int64_t col0 = tl.cbase + lr * VL;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if constexpr (LAST) {
+                if (sl[t] >= 0) {
+                    if (a.b_bf16) {
+                        bf16_store4(static_cast<uint16_t*>(a.B) + (int64_t)sl[t] * a.ldb + col0, v[t]);
+                    } else {
+                        ZVec<float>::st(static_cast<float*>(a.B) + (int64_t)sl[t] * a.ldb + col0, v[t]);
+                    }
+                }
+                if (sh[t] >= 0) ZVec<float>::st(static_cast<float*>(a.Bh) + (int64_t)sh[t] * a.ldbh + col0, v[t]);
+            } else {
+                ZVec<float>::st(static_cast<float*>(a.zout) + grow(tl, tile_row(bidx, NB - Q, t)) * a.ldz + col0, v[t]);
+            }
+        }
+    }
+}
+
 // Threads per block and register window for a pass of nb bits.
 template <typename TZ, int CW>
 inline int pass_q(int nb) {
@@ -383,8 +673,26 @@ hipError_t launch_any(hipStream_t st, const PassArgs& a, bool first, bool last) 
     return launch_pass<TIN, TZ, CW, false, false>(st, a);
 }
 
+template <typename TIN, int CW, bool FIRST, bool LAST>
+hipError_t launch_stream_one(hipStream_t st, const PassArgs& a, int64_t grid) {
+    auto fn = fwht_stream_kernel<TIN, CW, FIRST, LAST>;
+    fn<<<dim3((unsigned)grid), dim3(STREAM_THREADS), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename TIN, int CW>
+hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last) {
+    if (first && last) return hipErrorInvalidValue;
+    if (first) return launch_stream_one<TIN, CW, true, false>(st, a, grid);
+    if (last) return launch_stream_one<TIN, CW, false, true>(st, a, grid);
+    return launch_stream_one<TIN, CW, false, false>(st, a, grid);
+}
+
 // Passes of at most NB_MAX bits; each pass uses 256-byte row segments, or
 // 128-byte ones for 11-bit passes (whose 256-byte tile would not fit).
+// 10-bit passes at FP32 working precision of a multi-pass transform (and
+// 11-bit ones for FP32 input) use the streaming kernel unless the job asks
+// for one tile per block.
 template <typename TIN, typename TZ>
 hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     const int L = job.L;
@@ -411,6 +719,30 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     int lo = 0;
     for (int pi = 0; pi < passes; ++pi) {
         const int nb = L / passes + (pi < L % passes ? 1 : 0);
+        const bool first = pi == 0, last = pi == passes - 1;
+        if constexpr (std::is_same<TZ, float>::value) {
+            // 11-bit passes need 64-byte rows (CW = 16): measured faster than
+            // one tile per block for FP32 input only
+            const int scw = nb == 10 ? 32 : (nb == 11 && std::is_same<TIN, float>::value) ? 16 : 0;
+            // the first pass stages rows of X with 16-byte direct loads
+            const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
+            if (job.stream && job.num_cu > 0 && scw && passes >= 2 && job.seg_bytes == 0 &&
+                job.ldz % scw == 0 && (!first || xdma)) {
+                a.lo = lo;
+                a.nb = nb;
+                a.q = 4;
+                a.nchunks = job.ldz / scw;
+                a.ntiles = (1ll << (L - nb)) * a.nchunks;
+                a.zin = job.zbuf;
+                a.zout = job.zbuf;
+                const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
+                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
+                                               : launch_stream<TIN, 16>(st, a, grid, first, last);
+                if (e != hipSuccess) return e;
+                lo += nb;
+                continue;
+            }
+        }
         // column segment per tile row: the widest whose tile fits the
         // registers (256 B up to 10-bit passes, 128 B for 11 bits), unless
         // the job asks for a narrower one (smaller blocks, more per CU)
@@ -426,7 +758,6 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
         a.ntiles = (1ll << (L - nb)) * a.nchunks;
         a.zin = job.zbuf;
         a.zout = job.zbuf;
-        const bool first = pi == 0, last = pi == passes - 1;
         const hipError_t e = cw == CW_WIDE     ? launch_any<TIN, TZ, CW_WIDE>(st, a, first, last)
                              : cw == CW_NARROW ? launch_any<TIN, TZ, CW_NARROW>(st, a, first, last)
                                                : launch_any<TIN, TZ, CW_TINY>(st, a, first, last);
@@ -488,17 +819,6 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
     export_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(seed, L, np, mK, r, slot_rows,
                                                               hat_rows, input_perm, sign_bits);
     return hipGetLastError();
-}
-
-template <typename TIN, typename TZ>
-hipError_t run_chunked(hipStream_t st, const FwhtJob& job, int seg_bytes) {
-    constexpr int E = sizeof(TZ);
-    switch (seg_bytes) {
-        case 64: return run_passes<TIN, TZ, 64 / E>(st, job);
-        case 128: return run_passes<TIN, TZ, 128 / E>(st, job);
-        case 256: return run_passes<TIN, TZ, 256 / E>(st, job);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {

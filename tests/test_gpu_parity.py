@@ -170,6 +170,50 @@ def test_sketch_rows_reduced_precision(S, ctx, storage, N, d, stage_dtype):
     assert np.array_equal(bg.cpu().numpy(), BY)   # Y is always FP64
 
 
+def _raw_rows(sk, stage):
+    A, _, _ = sk.view_tensor(stage)
+    A = A.contiguous()
+    return A.view(torch.int16 if A.dtype == torch.bfloat16 else torch.int32).cpu().numpy()
+
+
+@pytest.mark.parametrize("storage,N,d", [("f32", 600_001, 40), ("f32", 600_001, 37),
+                                         ("bf16", 700_000, 24), ("fp8", 700_000, 48),
+                                         ("f32", 1_100_000, 12)])
+def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
+    # N' = 2^20 (two 10-bit passes) or 2^21 (FP32: two 11-bit passes): the
+    # default transform streams tiles through LDS in persistent blocks;
+    # transform_segment = 256 forces one tile per block.  Same butterflies in
+    # the same order -> identical bits (d = 37: rows whose 16-byte pieces
+    # straddle d, first pass on the tiled kernel)
+    _log(f"sketch streaming {storage} N={N} d={d}")
+    p = _problem(N, d, storage=storage, seed=N % 89)
+    rows = []
+    for seg in (0, 256):
+        sk = S.spcg_sketch(ctx, p.X, p.Y, seed=5, col_scale=p.col_scale, transform_segment=seg)
+        rows.append((_raw_rows(sk, len(sk.sizes) - 1), _raw_rows(sk, -1), sk.info.L))
+    assert rows[0][2] == (20 if N < (1 << 20) else 21)
+    assert np.array_equal(rows[0][0], rows[1][0])
+    assert np.array_equal(rows[0][1], rows[1][1])
+
+
+def test_sketch_streaming_transform_against_oracle(S, ctx):
+    # the streaming path at N' = 2^20 against the FP64 oracle on the same
+    # stored values (tolerance as for the tiled FP32 transform)
+    N, d = 600_001, 16
+    _log("sketch streaming vs oracle N'=2^20")
+    p = _problem(N, d, storage="f32", seed=21)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=9, m0=1 << 14, m_max=1 << 16, r=256)
+    Xd = p.x_f64().cpu().numpy()
+    B, BY, Bh, info = nested_srht(Xd, p.Y.cpu().numpy(), 9, sk.sizes[-1], 256)
+    assert info["L"] == 20
+    Ag, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    Hg, _, _ = sk.view_tensor(-1)
+    scale = np.sqrt(info["Np"]) * np.abs(Xd).max(axis=0)
+    assert (np.abs(Ag.cpu().numpy().astype(np.float64) - B) / scale).max() < 2e-6 * info["L"]
+    assert (np.abs(Hg.cpu().numpy().astype(np.float64) - Bh) / scale).max() < 2e-6 * info["L"]
+    assert np.array_equal(bg.cpu().numpy(), BY)
+
+
 # ------------------------------------------------------- preconditioner
 
 @pytest.mark.parametrize("passes", [0, 1, 2, 3])
