@@ -439,10 +439,8 @@ int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
     const int64_t we = ctx->dense_w_elems;
     HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
     double* W = ctx->dense_a.as<double>();
-    HIP_TRY(ctx, dense_fill_identity(st, W, d));
-    HIP_TRY(ctx, trtri_diag_blocks(st, pc->pR, d, d, ctx->dense_wd.as<double>()));
-    HIP_TRY(ctx, trsm_right_upper(st, W, d, d, d, pc->pR, d, ctx->dense_wd.as<double>(),
-                                  ctx->dense_tmp.as<double>(), wk, we));
+    // W = R^{-1} (the split-K workspace, >= d^2 doubles, serves as scratch)
+    HIP_TRY(ctx, tri_inverse_upper(st, pc->pR, d, d, W, wk));
     HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0, wk, we));
     return SPCG_OK;
 }

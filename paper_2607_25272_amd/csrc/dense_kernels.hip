@@ -152,21 +152,13 @@ __device__ __forceinline__ double bcast_lane(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, int64_t k0, int nb,
-                                                        DenseStatus* st) {
-    __shared__ __align__(16) double rows[2][CB];
-    __shared__ double pivs[CB];
+// a: this thread's 4 x 4 patch (rows 4 ty + r, columns 4 tx + c) of the
+// nb x nb block; only the upper part (diagonal included) is read.  On
+// return the upper part holds U; pivs[0..nb) the pivots.
+__device__ __forceinline__ void potrf_patch(double (&a)[4][4], int nb, double (*rows)[CB], double* pivs) {
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    double a[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = ty * 4 + r, j = tx * 4 + c;
-            a[r][c] = (i < nb && j < nb && j >= i) ? G[(k0 + i) * ld + k0 + j] : 0.0;
-        }
     // row j = 4 jb + JR: scale it in place and publish w (wave jb / 4 only)
     auto publish = [&](int jb, auto jr_c) __attribute__((always_inline)) {
         constexpr int JR = decltype(jr_c)::value;
@@ -229,55 +221,36 @@ __global__ __launch_bounds__(256) void potrf_blk_kernel(double* G, int64_t ld, i
         if (j + 4 >= nb) break;
         publish(jb + 1, C0{});
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = ty * 4 + r, j = tx * 4 + c;
-            if (i < nb && j < nb) G[(k0 + i) * ld + k0 + j] = (j >= i) ? a[r][c] : 0.0;
-        }
-    __syncthreads();
-    if (tid == 0) {
-        double min_piv = st->min_pivot, min_d = st->min_diag, max_d = st->max_diag;
-        int first_fail = st->fail;
-        for (int j = 0; j < nb; ++j) {
-            const double p = pivs[j];
-            const bool bad = !(p > 0.0) || !__builtin_isfinite(p);
-            const double u = bad ? 1.0 : sqrt(p);
-            min_piv = p < min_piv ? p : min_piv;
-            if (bad && first_fail == 0) first_fail = (int)(k0 + j) + 1;
-            min_d = u < min_d ? u : min_d;
-            max_d = u > max_d ? u : max_d;
-        }
-        st->min_pivot = min_piv;
-        st->min_diag = min_d;
-        st->max_diag = max_d;
-        st->fail = first_fail;
-    }
+    __syncthreads();   // pivs complete
 }
 
-// Inverses of CB x CB diagonal blocks of an upper-triangular U, starting at
-// block `first` (one block of 256 threads per diagonal block).  A partial
-// last block is padded with the identity.  Recursive doubling in LDS:
-// invert the eight 8 x 8 diagonal blocks by back substitution, then for
-// s = 8, 16, 32 combine neighbouring s x s inverses with
-// W12 = -W11 U12 W22.
-__global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* U, int64_t d, int64_t ld, double* W,
-                                                           int64_t first) {
-    __shared__ double T[CB][CB + 1];
-    __shared__ double Wl[CB][CB + 1];
-    __shared__ double Tmp[CB][CB + 1];
-    const int tid = threadIdx.x;
-    const int64_t k0 = (first + (int64_t)blockIdx.x) * CB;
-    const int nb = (int)min((int64_t)CB, d - k0);
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e >> 6, j = e & 63;
-        double v;
-        if (i < nb && j < nb) v = (j >= i) ? U[(k0 + i) * ld + k0 + j] : 0.0;
-        else v = (i == j) ? 1.0 : 0.0;
-        T[i][j] = v;
-        Wl[i][j] = 0.0;
+// running pivot statistics of the factorization (one thread)
+__device__ __forceinline__ void potrf_status(const double* pivs, int nb, int64_t k0, DenseStatus* st) {
+    double min_piv = st->min_pivot, min_d = st->min_diag, max_d = st->max_diag;
+    int first_fail = st->fail;
+    for (int j = 0; j < nb; ++j) {
+        const double p = pivs[j];
+        const bool bad = !(p > 0.0) || !__builtin_isfinite(p);
+        const double u = bad ? 1.0 : sqrt(p);
+        min_piv = p < min_piv ? p : min_piv;
+        if (bad && first_fail == 0) first_fail = (int)(k0 + j) + 1;
+        min_d = u < min_d ? u : min_d;
+        max_d = u > max_d ? u : max_d;
     }
+    st->min_pivot = min_piv;
+    st->min_diag = min_d;
+    st->max_diag = max_d;
+    st->fail = first_fail;
+}
+
+// Inverse of the upper-triangular CB x CB block in T (identity past the
+// used size) into Wl, by recursive doubling in LDS: invert the eight 8 x 8
+// diagonal blocks by back substitution, then for s = 8, 16, 32 combine
+// neighbouring s x s inverses with W12 = -W11 U12 W22.  Tmp is scratch.
+// Expects T complete (caller synchronizes); Wl is complete on return.
+__device__ __forceinline__ void trtri_lds(double (*T)[CB + 1], double (*Wl)[CB + 1], double (*Tmp)[CB + 1]) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < CB * CB; e += 256) Wl[e >> 6][e & 63] = 0.0;
     __syncthreads();
     if (tid < CB) {   // 8 x 8 diagonal blocks: thread = (block, column)
         const int b0 = (tid >> 3) * 8, c = tid & 7;
@@ -315,10 +288,213 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* U, int6
         }
         __syncthreads();
     }
+}
+
+// Inverses of CB x CB diagonal blocks of an upper-triangular U, starting at
+// block `first` (one block of 256 threads per diagonal block).  A partial
+// last block is padded with the identity.
+__global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* U, int64_t d, int64_t ld, double* W,
+                                                           int64_t first) {
+    __shared__ double T[CB][CB + 1];
+    __shared__ double Wl[CB][CB + 1];
+    __shared__ double Tmp[CB][CB + 1];
+    const int tid = threadIdx.x;
+    const int64_t k0 = (first + (int64_t)blockIdx.x) * CB;
+    const int nb = (int)min((int64_t)CB, d - k0);
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        double v;
+        if (i < nb && j < nb) v = (j >= i) ? U[(k0 + i) * ld + k0 + j] : 0.0;
+        else v = (i == j) ? 1.0 : 0.0;
+        T[i][j] = v;
+    }
+    __syncthreads();
+    trtri_lds(T, Wl, Tmp);
     for (int e = tid; e < CB * CB; e += 256) {
         const int i = e >> 6, j = e & 63;
         if (i < nb && j < nb) W[(k0 + i) * ld + k0 + j] = Wl[i][j];
     }
+}
+
+// ---- fused blocked Cholesky (upper, G = U^T U) ------------------------------
+//
+// chol_first_kernel factors the first diagonal block; then one
+// chol_step_kernel per panel k (rows k0 .. k0 + CB) does, for every tile
+// pair ti <= tj of the trailing part (one block each):
+//   P_i = W_kk^T G[k, ti],  P_j = W_kk^T G[k, tj]   (columns of U_k,trailing)
+//   G[ti, tj] -= P_i^T P_j
+// with W_kk = U_kk^{-1}.  The diagonal-pair blocks keep their P_j as U's row
+// panel, stored transposed in the (otherwise unused) strict lower triangle
+// so that no block overwrites rows another block still reads; the block of
+// the first trailing diagonal tile then factors it in place (potrf on its
+// register patch, which has exactly the update's layout) and inverts it:
+// U and W of panel k + 1.  chol_finish_kernel moves the row panels to the
+// upper triangle and clears the lower one.  Per panel: one launch instead
+// of a factor, an inverse, a panel product, a copy and a trailing update.
+__device__ __forceinline__ void store_factor_and_inverse(double (&a)[4][4], int nb, double* G, int64_t ld,
+                                                         int64_t k0, double* Wd, double (*T)[CB + 1],
+                                                         double (*Wl)[CB + 1], double (*Tmp)[CB + 1],
+                                                         double (*rows)[CB], double* pivs, DenseStatus* st) {
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    potrf_patch(a, nb, rows, pivs);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            const double u = (j >= i) ? a[r][c] : 0.0;
+            if (i < nb && j < nb) G[(k0 + i) * ld + k0 + j] = u;
+            T[i][j] = (i < nb && j < nb) ? u : (i == j ? 1.0 : 0.0);
+        }
+    if (tid == 0) potrf_status(pivs, nb, k0, st);
+    __syncthreads();
+    trtri_lds(T, Wl, Tmp);
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        if (i < nb && j < nb) Wd[(k0 + i) * ld + k0 + j] = Wl[i][j];
+    }
+}
+
+__global__ __launch_bounds__(256) void chol_first_kernel(double* G, int64_t d, int64_t ld, double* Wd,
+                                                         DenseStatus* st) {
+    __shared__ double T[CB][CB + 1];
+    __shared__ double Wl[CB][CB + 1];
+    __shared__ double Tmp[CB][CB + 1];
+    __shared__ __align__(16) double rows[2][CB];
+    __shared__ double pivs[CB];
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int nb = (int)min((int64_t)CB, d);
+    double a[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            a[r][c] = (i < nb && j < nb && j >= i) ? G[i * ld + j] : 0.0;
+        }
+    store_factor_and_inverse(a, nb, G, ld, 0, Wd, T, Wl, Tmp, rows, pivs, st);
+}
+
+__global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, int64_t ld, int64_t k0, double* Wd,
+                                                        DenseStatus* st) {
+    __shared__ double S0[CB][CB + 1];   // W_kk; then T of the next factor
+    __shared__ double S1[CB][CB + 1];   // G[k, ti] -> P_i; then the inverse
+    __shared__ double S2[CB][CB + 1];   // G[k, tj] -> P_j; then scratch
+    __shared__ __align__(16) double rows[2][CB];
+    __shared__ double pivs[CB];
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const int64_t k1 = k0 + CB;
+    const int64_t nt = (d - k1 + CB - 1) / CB;
+    // block -> (ti, tj), ti <= tj, row by row over the upper triangle
+    int64_t b = blockIdx.x, ti = 0;
+    while (b >= nt - ti) {
+        b -= nt - ti;
+        ++ti;
+    }
+    const int64_t tj = ti + b;
+    const bool diag = ti == tj;
+    const int64_t i0 = k1 + ti * CB, j0 = k1 + tj * CB;
+    const int ni = (int)min((int64_t)CB, d - i0), nj = (int)min((int64_t)CB, d - j0);
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        S0[r][c] = c >= r ? Wd[(k0 + r) * ld + k0 + c] : 0.0;
+        S1[r][c] = c < ni ? G[(k0 + r) * ld + i0 + c] : 0.0;
+        if (!diag) S2[r][c] = c < nj ? G[(k0 + r) * ld + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    // P = W_kk^T A: P[r][c] = sum_{l <= r} W[l][r] A[l][c]
+    double pi[4][4], pj[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            pi[r][c] = 0.0;
+            pj[r][c] = 0.0;
+        }
+    for (int l = 0; l < CB; ++l) {
+        double wv[4], av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wv[r] = S0[l][ty * 4 + r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            av[c] = S1[l][tx * 4 + c];
+            bv[c] = diag ? 0.0 : S2[l][tx * 4 + c];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                pi[r][c] = fma(wv[r], av[c], pi[r][c]);
+                pj[r][c] = fma(wv[r], bv[c], pj[r][c]);
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            S1[ty * 4 + r][tx * 4 + c] = pi[r][c];
+            if (!diag) S2[ty * 4 + r][tx * 4 + c] = pj[r][c];
+        }
+    // the diagonal-pair blocks keep U's row panel (transposed, lower triangle)
+    if (diag) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int pr = ty * 4 + r, pc = tx * 4 + c;
+                if (pc < nj) G[(j0 + pc) * ld + k0 + pr] = pi[r][c];
+            }
+    }
+    __syncthreads();
+    // trailing update of this tile: G[ti, tj] -= P_i^T P_j
+    const double (*Pj)[CB + 1] = diag ? S1 : S2;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            acc[r][c] = (i < ni && j < nj) ? G[(i0 + i) * ld + j0 + j] : 0.0;
+        }
+    for (int l = 0; l < CB; ++l) {
+        double pv[4], qv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pv[r] = S1[l][ty * 4 + r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qv[c] = Pj[l][tx * 4 + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(-pv[r], qv[c], acc[r][c]);
+    }
+    if (ti == 0 && tj == 0) {
+        // the next diagonal block: factor and invert it
+        __syncthreads();   // S0..S2 are reused below
+        store_factor_and_inverse(acc, ni, G, ld, k1, Wd, S0, S1, S2, rows, pivs, st);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            if (i < ni && j < nj) G[(i0 + i) * ld + j0 + j] = acc[r][c];
+        }
+}
+
+// upper triangle <- the row panels kept in the lower triangle; lower <- 0
+__global__ void chol_finish_kernel(double* G, int64_t d, int64_t ld) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d * d) return;
+    const int64_t i = e / d, j = e - i * d;
+    if (j <= i) return;
+    // (i, j) upper, (j, i) its mirror
+    if (i / CB != j / CB) G[i * ld + j] = G[j * ld + i];
+    G[j * ld + i] = 0.0;
 }
 
 __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows,
@@ -327,13 +503,6 @@ __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64
     if (e >= rows * cols) return;
     const int64_t i = e / cols, j = e - i * cols;
     dst[i * ldd + j] = src[i * lds + j];
-}
-
-__global__ void zero_lower_kernel(double* G, int64_t d, int64_t ld) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d * d) return;
-    const int64_t i = e / d, j = e - i * d;
-    if (j < i) G[i * ld + j] = 0.0;
 }
 
 __global__ void identity_kernel(double* A, int64_t d) {
@@ -415,28 +584,16 @@ hipError_t copy2d(hipStream_t st, const double* src, int64_t lds, double* dst, i
 }
 
 hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status,
-                          double* W, double* panel, double* work, int64_t work_elems) {
+                          double* W, double*, double*, int64_t) {
     hipError_t e;
-    for (int64_t k0 = 0; k0 < d; k0 += CB) {
-        const int nb = (int)std::min<int64_t>(CB, d - k0);
-        potrf_blk_kernel<<<1, 256, 0, st>>>(G, ld, k0, nb, status);
+    chol_first_kernel<<<1, 256, 0, st>>>(G, d, ld, W, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int64_t k0 = 0; k0 + CB < d; k0 += CB) {
+        const int64_t nt = ceil_div(d - k0 - CB, CB);
+        chol_step_kernel<<<(unsigned)(nt * (nt + 1) / 2), 256, 0, st>>>(G, d, ld, k0, W, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        trtri_blocks_kernel<<<1, 256, 0, st>>>(G, d, ld, W, k0 / CB);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int64_t k1 = k0 + nb, rem = d - k1;
-        if (rem > 0) {
-            // row panel: U[k, k1:] = U_kk^{-T} G[k, k1:]  (panel buffer nb x rem)
-            e = gemm_f64(st, nb, rem, nb, 1.0, W + k0 * ld + k0, 0, 1, ld, G + k0 * ld + k1, 0, ld, 1,
-                         0.0, panel, rem, 0, nullptr, 0);
-            if (e != hipSuccess) return e;
-            if ((e = copy2d(st, panel, rem, G + k0 * ld + k1, ld, nb, rem)) != hipSuccess) return e;
-            // trailing update G[k1:, k1:] -= P^T P (upper tiles)
-            e = gemm_f64(st, rem, rem, nb, -1.0, panel, 0, 1, rem, panel, 0, rem, 1, 1.0,
-                         G + k1 * ld + k1, ld, 1, work, work_elems);
-            if (e != hipSuccess) return e;
-        }
     }
-    zero_lower_kernel<<<(unsigned)ceil_div(d * d, 256), 256, 0, st>>>(G, d, ld);
+    chol_finish_kernel<<<(unsigned)ceil_div(d * d, 256), 256, 0, st>>>(G, d, ld);
     return hipGetLastError();
 }
 
@@ -461,6 +618,27 @@ hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int
                      nullptr, 0);
         if (e != hipSuccess) return e;
         if ((e = copy2d(st, tmp, nb, A + k0, lda, n, nb)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp) {
+    hipError_t e;
+    if ((e = dense_fill_identity(st, W, d)) != hipSuccess) return e;
+    if ((e = trtri_diag_blocks(st, U, d, ld, W)) != hipSuccess) return e;
+    // recursive doubling over block columns: [W11 W12; 0 W22] with
+    // W12 = -W11 (U12 W22), neighbouring s-blocks per level, s = CB, 2 CB, ...
+    for (int64_t s = CB; s < d; s *= 2) {
+        for (int64_t a = 0; a + s < d; a += 2 * s) {
+            const int64_t s2 = std::min<int64_t>(s, d - a - s);
+            const int64_t b = a + s;
+            e = gemm_f64(st, s, s2, s2, 1.0, U + a * ld + b, 0, ld, 1, W + b * ld + b, 0, ld, 1, 0.0, tmp, s2, 0,
+                         nullptr, 0);
+            if (e != hipSuccess) return e;
+            e = gemm_f64(st, s, s2, s, -1.0, W + a * ld + a, 0, ld, 1, tmp, 0, s2, 1, 0.0, W + a * ld + b, ld, 0,
+                         nullptr, 0);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

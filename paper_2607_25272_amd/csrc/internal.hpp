@@ -232,11 +232,16 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
                     int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
                     int64_t work_elems);
-// In-place upper Cholesky G = U^T U (row-major d x d, ld); lower part
-// zeroed; the inverses of the 64 x 64 diagonal blocks of U go to the same
-// positions of W (d x d, ld).  panel: 64 x d scratch.
+// In-place upper Cholesky G = U^T U (row-major d x d, ld; the upper part
+// of G is read); lower part zeroed; the inverses of the 64 x 64 diagonal
+// blocks of U go to the same positions of W (d x d, ld).  One fused launch
+// per 64-row panel.  The remaining arguments are unused.
 hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status,
                           double* W, double* panel, double* work, int64_t work_elems);
+// W = U^{-1} (d x d, ld) for upper-triangular U: diagonal-block inverses,
+// then block recursive doubling W12 = -W11 U12 W22 over 64, 128, ...
+// column blocks.  tmp: d * d / 4 doubles.
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp);
 // Inverses of the 64 x 64 diagonal blocks of an upper-triangular U into W.
 hipError_t trtri_diag_blocks(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W);
 // In-place A <- A U^{-1} for A (n x d, lda), upper-triangular U (d x d,
