@@ -425,7 +425,7 @@ int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
         ctx->dense_w_elems = elems;
     }
     HIP_TRY(ctx, ctx->dense_wd.ensure((size_t)d * d * 8));
-    HIP_TRY(ctx, ctx->dense_tmp.ensure((size_t)std::max(r, d) * 64 * 8));
+    HIP_TRY(ctx, ctx->dense_tmp.ensure((size_t)std::max(std::max(r, d) * 64, d * d / 4 + 64) * 8));
     return SPCG_OK;
 }
 
@@ -439,8 +439,7 @@ int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
     const int64_t we = ctx->dense_w_elems;
     HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
     double* W = ctx->dense_a.as<double>();
-    // W = R^{-1} (the split-K workspace, >= d^2 doubles, serves as scratch)
-    HIP_TRY(ctx, tri_inverse_upper(st, pc->pR, d, d, W, wk));
+    HIP_TRY(ctx, tri_inverse_upper(st, pc->pR, d, d, W, ctx->dense_tmp.as<double>(), wk, we));
     HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0, wk, we));
     return SPCG_OK;
 }

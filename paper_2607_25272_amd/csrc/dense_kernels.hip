@@ -43,45 +43,51 @@ __device__ __forceinline__ double ld_elem(const void* p, int64_t idx) {
     return static_cast<const double*>(p)[idx];
 }
 
-template <bool AF32, bool BF32>
+// TT x TT output tile per block of 256 threads (16 x 16, each a P x P
+// patch, P = TT / 16); K in steps of GK through LDS.  TT = 64 for large
+// products; TT = 32 gives 4x the blocks for the small ones, whose time is
+// set by how many CUs they occupy.
+template <bool AF32, bool BF32, int TT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    constexpr int P = TT / 16;
+    constexpr int NL = TT * GK / 256;   // loads per thread per operand and k step
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     if (g.upper && ti > tj) return;
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
+    __shared__ double As[GK][TT + 1];
+    __shared__ double Bs[GK][TT + 1];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
-    const int64_t i0 = ti * GT, j0 = tj * GT;
-    double acc[4][4];
+    const int64_t i0 = ti * TT, j0 = tj * TT;
+    double acc[P][P];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < P; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+        for (int c = 0; c < P; ++c) acc[r][c] = 0.0;
     const bool a_icontig = g.sai == 1;
     const bool b_jcontig = g.sbj == 1;
     const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
     for (int64_t l0 = kbeg; l0 < kend; l0 += GK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NL; ++q) {
             const int e = tid + q * 256;
             int i, l;
             if (a_icontig) {
-                i = e & 63;
-                l = e >> 6;
+                i = e % TT;
+                l = e / TT;
             } else {
-                l = e & 15;
-                i = e >> 4;
+                l = e % GK;
+                i = e / GK;
             }
             const int64_t gi = i0 + i, gl = l0 + l;
             As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
             int j;
             if (b_jcontig) {
-                j = e & 63;
-                l = e >> 6;
+                j = e % TT;
+                l = e / TT;
             } else {
-                l = e & 15;
-                j = e >> 4;
+                l = e % GK;
+                j = e / GK;
             }
             const int64_t gj = j0 + j, gl2 = l0 + l;
             Bs[l][j] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
@@ -89,25 +95,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         __syncthreads();
 #pragma unroll
         for (int l = 0; l < GK; ++l) {
-            double av[4], bv[4];
+            double av[P], bv[P];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) av[r] = As[l][ty * 4 + r];
+            for (int r = 0; r < P; ++r) av[r] = As[l][ty * P + r];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) bv[c] = Bs[l][tx * 4 + c];
+            for (int c = 0; c < P; ++c) bv[c] = Bs[l][tx * P + c];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < P; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+                for (int c = 0; c < P; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + ty * 4 + r;
+    for (int r = 0; r < P; ++r) {
+        const int64_t gi = i0 + ty * P + r;
         if (gi >= g.M) continue;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t gj = j0 + tx * 4 + c;
+        for (int c = 0; c < P; ++c) {
+            const int64_t gj = j0 + tx * P + c;
             if (gj >= g.N) continue;
             if (g.part) {
                 g.part[((int64_t)blockIdx.z * g.M + gi) * g.N + gj] = acc[r][c];
@@ -545,12 +551,33 @@ __global__ void status_reset_kernel(DenseStatus* st) {
 
 }  // namespace
 
+namespace {
+template <int TT>
+hipError_t gemm_launch(hipStream_t st, const GemmArgs& g, int a_f32, int b_f32, dim3 grid) {
+    const dim3 block(256);
+    if (a_f32 && b_f32)
+        gemm_kernel<true, true, TT><<<grid, block, 0, st>>>(g);
+    else if (a_f32)
+        gemm_kernel<true, false, TT><<<grid, block, 0, st>>>(g);
+    else if (b_f32)
+        gemm_kernel<false, true, TT><<<grid, block, 0, st>>>(g);
+    else
+        gemm_kernel<false, false, TT><<<grid, block, 0, st>>>(g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const void* A,
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
                     int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
                     int64_t work_elems) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const int64_t ti = ceil_div(M, GT), tj = ceil_div(N, GT);
+    // products with few 64 x 64 tiles (not the upper-tile Gram) use 32 x 32
+    // tiles: their time is set by how many CUs they occupy
+    const bool small = !upper && ceil_div(M, GT) * ceil_div(N, GT) < 64;
+    const int64_t tt = small ? 32 : GT;
+    const int64_t ti = ceil_div(M, tt), tj = ceil_div(N, tt);
     const int64_t tiles = upper ? (ti * (ti + 1)) / 2 : ti * tj;
     // split K until there are about 512 blocks, keeping >= 128 per chunk
     int64_t nz = 1;
@@ -560,16 +587,8 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
     if (nz < 1) nz = 1;
     GemmArgs g{M, N, K, alpha, beta, A, sai, sal, B, sbl, sbj, C, ldc, upper,
                kchunk, nz > 1 ? work : nullptr};
-    dim3 grid((unsigned)tj, (unsigned)ti, (unsigned)nz), block(256);
-    if (a_f32 && b_f32)
-        gemm_kernel<true, true><<<grid, block, 0, st>>>(g);
-    else if (a_f32)
-        gemm_kernel<true, false><<<grid, block, 0, st>>>(g);
-    else if (b_f32)
-        gemm_kernel<false, true><<<grid, block, 0, st>>>(g);
-    else
-        gemm_kernel<false, false><<<grid, block, 0, st>>>(g);
-    hipError_t e = hipGetLastError();
+    const dim3 grid((unsigned)tj, (unsigned)ti, (unsigned)nz);
+    hipError_t e = small ? gemm_launch<32>(st, g, a_f32, b_f32, grid) : gemm_launch<GT>(st, g, a_f32, b_f32, grid);
     if (e != hipSuccess || nz == 1) return e;
     splitk_reduce_kernel<<<(unsigned)ceil_div(M * N, 256), 256, 0, st>>>(work, (int)nz, M, N, alpha,
                                                                          beta, C, ldc, upper);
@@ -622,7 +641,8 @@ hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int
     return hipSuccess;
 }
 
-hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp) {
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp,
+                             double* work, int64_t work_elems) {
     hipError_t e;
     if ((e = dense_fill_identity(st, W, d)) != hipSuccess) return e;
     if ((e = trtri_diag_blocks(st, U, d, ld, W)) != hipSuccess) return e;
@@ -633,10 +653,10 @@ hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t
             const int64_t s2 = std::min<int64_t>(s, d - a - s);
             const int64_t b = a + s;
             e = gemm_f64(st, s, s2, s2, 1.0, U + a * ld + b, 0, ld, 1, W + b * ld + b, 0, ld, 1, 0.0, tmp, s2, 0,
-                         nullptr, 0);
+                         work, work_elems);
             if (e != hipSuccess) return e;
             e = gemm_f64(st, s, s2, s, -1.0, W + a * ld + a, 0, ld, 1, tmp, 0, s2, 1, 0.0, W + a * ld + b, ld, 0,
-                         nullptr, 0);
+                         work, work_elems);
             if (e != hipSuccess) return e;
         }
     }

@@ -240,8 +240,10 @@ hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, Dens
                           double* W, double* panel, double* work, int64_t work_elems);
 // W = U^{-1} (d x d, ld) for upper-triangular U: diagonal-block inverses,
 // then block recursive doubling W12 = -W11 U12 W22 over 64, 128, ...
-// column blocks.  tmp: d * d / 4 doubles.
-hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp);
+// column blocks.  tmp: d * d / 4 doubles; work: split-K workspace (as for
+// gemm_f64, may be null).
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp,
+                             double* work, int64_t work_elems);
 // Inverses of the 64 x 64 diagonal blocks of an upper-triangular U into W.
 hipError_t trtri_diag_blocks(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W);
 // In-place A <- A U^{-1} for A (n x d, lda), upper-triangular U (d x d,
