@@ -127,17 +127,19 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
         }
     }
     if (threadIdx.x < nblk) sh_b[threadIdx.x] = S.blk[threadIdx.x];
-    sh_r[threadIdx.x] = t0;
-    sh_t[threadIdx.x] = t1;
-    __syncthreads();
+    // norm partials: DPP sums per wave, then the four waves in order (one
+    // barrier instead of a shared-memory tree)
     if (want_g) {
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                sh_r[threadIdx.x] += sh_r[threadIdx.x + w];
-                sh_t[threadIdx.x] += sh_t[threadIdx.x + w];
-            }
-            __syncthreads();
+        const double wr = wave_sum(t0), wt = wave_sum(t1);
+        if ((threadIdx.x & 63) == 0) {
+            sh_r[threadIdx.x >> 6] = wr;
+            sh_t[threadIdx.x >> 6] = wt;
         }
+    }
+    __syncthreads();
+    if (want_g && threadIdx.x == 0) {
+        sh_r[0] = (sh_r[0] + sh_r[1]) + (sh_r[2] + sh_r[3]);
+        sh_t[0] = (sh_t[0] + sh_t[1]) + (sh_t[2] + sh_t[3]);
     }
     __shared__ double alpha_sh;
     __shared__ int do_step;
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
             for (int u = 0; u < 8; ++u) acc4[u & 3] = fma(mv[u], gv[u], acc4[u & 3]);
         }
         acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-        acc = group_sum<64>(acc);
+        acc = wave_sum(acc);
         gi = S.g[i];
     }
     const bool skip = sc->breakdown || (!init && sc->exact);
@@ -233,19 +235,17 @@ __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    // fixed-order reduction of the block partials
+    // fixed-order reduction of the block partials: DPP sums per wave, then
+    // the four waves in order
     double t = 0.0;
     for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) t += S.blk[b];
-    red[threadIdx.x] = t;
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
     __shared__ double gamma_sh;
     __shared__ int mode;  // 0 skip, 1 p = z, 2 p = z + gamma p
     if (threadIdx.x == 0) {
-        const double rho_new = red[0];
+        const double rho_new = (red[0] + red[1]) + (red[2] + red[3]);
         mode = 0;
         if (!skip) {
             if (!finite(rho_new)) {
