@@ -235,6 +235,27 @@ def test_precond_qr_matches_householder(S, ctx, passes):
     assert rel < bound, (rel, bound)
 
 
+@pytest.mark.parametrize("d", [64, 65, 130, 200])
+def test_precond_blocked_cholesky_panels(S, ctx, d):
+    # one fused launch per 64-row panel: d = 64 (the first block only), 65
+    # (one step, 1-wide trailing tile), 130 and 200 (several steps, partial
+    # last tiles) against Householder R of the same sketch rows
+    N, cond = 30000, 1e3
+    _log(f"precond blocked Cholesky d={d}")
+    p = _problem(N, d, cond=cond, seed=d)
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=3)
+    _, _, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 3, sk.sizes[-1], sk.info.r)
+    R_or = precond_from_sketch(Bh)
+    pc = S.spcg_precond_build(ctx, sk, qr_passes=1)
+    R, used = pc.export()
+    assert used == 1
+    assert np.all(np.diag(R) > 0) and np.array_equal(np.tril(R, -1), np.zeros_like(R))
+    kappa = np.linalg.cond(R_or)
+    bound = 50 * d * kappa ** 2 * 2.0 ** -53
+    rel = np.linalg.norm(R - R_or) / np.linalg.norm(R_or)
+    assert rel < bound, (rel, bound)
+
+
 def test_precond_ill_conditioned_falls_back_to_three_passes(S, ctx):
     N, d = 1 << 14, 16
     _log("precond kappa=1e8")
@@ -295,8 +316,13 @@ def test_pcg_stage_matches_oracle(S, ctx, storage, rtol):
     assert rel_pred_error(Xd, beta.cpu().numpy(), bh) < 1e-6
 
 
-def test_pcg_stage_exact_preconditioner_one_step(S, ctx):
-    N, d = 5000, 20
+@pytest.mark.parametrize("d", [20, 64, 65, 130, 200])
+def test_pcg_stage_exact_preconditioner_one_step(S, ctx, d):
+    # M = R^{-1} R^{-T} from the exact R: one PCG step reaches the OLS
+    # solution.  d = 65, 130, 200 exercise partial 64-column blocks in the
+    # recursive-doubling inverse (two and three levels)
+    N = 5000
+    _log(f"exact preconditioner d={d}")
     p = _problem(N, d, seed=12)
     Xd = p.x_f64().cpu().numpy()
     R = householder_qr(Xd)
