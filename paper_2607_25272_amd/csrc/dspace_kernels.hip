@@ -23,7 +23,8 @@ namespace spcg {
 namespace {
 
 constexpr int A_COLS = 16;   // columns per phase-A block
-constexpr int B_ROWS = 4;    // rows of M per phase-B block (one per wave)
+constexpr int B_ROWS = 4;    // rows of M per phase-B wave and sweep
+constexpr int B_GRID = 32;   // at most this many phase-B blocks (few device-scope hand-offs)
 
 struct PhaseAArgs {
     DspaceState S;
@@ -38,6 +39,26 @@ struct PhaseAArgs {
 };
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Hand-off to the last block: every wave waits for its own global stores,
+// the block barrier orders them before thread 0, and thread 0 alone
+// releases at device scope and counts the block.  A device-scope fence
+// costs tens of nanoseconds and fences of different blocks serialize, so
+// one fence per block (not one per wave) and few blocks keep the hand-off
+// short.  Returns true in the last block, after its acquire.
+__device__ __forceinline__ bool last_block_arrive(unsigned int* counter, int* is_last) {
+    __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xf << 8));   // vmcnt(0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        *is_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!*is_last) return false;
+    __threadfence();
+    return true;
+}
 
 __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
     // 16 columns x 16 partial lanes per block; lane ty sums partials
@@ -104,15 +125,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
         dot = group_sum<A_COLS>(dot);
         if (tx == 0) S.blk[blockIdx.x] = dot;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(&S.counters[0], 1u);
-        is_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    if (!last_block_arrive(&S.counters[0], &is_last)) return;
 
     // ---- last block: scalars and the x / g update.  The block partials of
     // p^T s, the norm partials and the vectors of the update are all
@@ -186,55 +199,57 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
 }
 
 __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
-    __shared__ double sh[B_ROWS];
-    __shared__ double red[256];
+    __shared__ double sh[4];
+    __shared__ double red[4];
     __shared__ int is_last;
     PcgScalars* sc = S.sc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * B_ROWS + wave;
-    // the row loads do not wait for the guard flags: a skipped iteration
-    // computes and discards
-    double acc = 0.0, gi = 0.0;
-    if (i < S.d) {
-        const double* row = S.Minv + i * S.d;
-        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+    // wave w of block b takes rows b*4 + w + k * stride, k = 0..B_ROWS-1 per
+    // sweep (stride = 4 * gridDim.x); the row loads of a sweep are all
+    // issued before any is used, and they do not wait for the guard flags
+    // (a skipped iteration computes and discards)
+    const bool skip = sc->breakdown || (!init && sc->exact);
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    double gz = 0.0;
+    for (int64_t i0 = (int64_t)blockIdx.x * 4 + wave; i0 < S.d; i0 += B_ROWS * stride) {
+        double acc4[B_ROWS][2];
+#pragma unroll
+        for (int k = 0; k < B_ROWS; ++k) acc4[k][0] = acc4[k][1] = 0.0;
         for (int64_t j0 = lane; j0 < S.d; j0 += 512) {
-            double mv[8], gv[8];
+            double gv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int64_t j = j0 + 64 * u;
-                mv[u] = j < S.d ? row[j] : 0.0;
                 gv[u] = j < S.d ? S.g[j] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc4[u & 3] = fma(mv[u], gv[u], acc4[u & 3]);
+            for (int k = 0; k < B_ROWS; ++k) {
+                const int64_t i = i0 + k * stride;
+                const double* row = S.Minv + min(i, S.d - 1) * S.d;
+                double mv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t j = j0 + 64 * u;
+                    mv[u] = (i < S.d && j < S.d) ? row[j] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc4[k][u & 1] = fma(mv[u], gv[u], acc4[k][u & 1]);
+            }
         }
-        acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-        acc = wave_sum(acc);
-        gi = S.g[i];
-    }
-    const bool skip = sc->breakdown || (!init && sc->exact);
-    double gz = 0.0;
-    if (!skip && i < S.d && lane == 0) {
-        S.z[i] = acc;
-        gz = gi * acc;
+#pragma unroll
+        for (int k = 0; k < B_ROWS; ++k) {
+            const int64_t i = i0 + k * stride;
+            const double acc = wave_sum(acc4[k][0] + acc4[k][1]);
+            if (!skip && i < S.d && lane == 0) {
+                S.z[i] = acc;
+                gz += S.g[i] * acc;
+            }
+        }
     }
     if (lane == 0) sh[wave] = gz;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < B_ROWS; ++w) t += sh[w];
-        S.blk[blockIdx.x] = t;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(&S.counters[1], 1u);
-        is_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    if (threadIdx.x == 0) S.blk[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    if (!last_block_arrive(&S.counters[1], &is_last)) return;
     // fixed-order reduction of the block partials: DPP sums per wave, then
     // the four waves in order
     double t = 0.0;
@@ -333,7 +348,7 @@ hipError_t run_phase_a(hipStream_t st, const DspaceState& S, int variant, const 
 }
 
 hipError_t run_phase_b(hipStream_t st, const DspaceState& S, int init) {
-    const int64_t grid = ceil_div(S.d, B_ROWS);
+    const int64_t grid = std::min<int64_t>(ceil_div(S.d, 4 * B_ROWS), B_GRID);
     phase_b_kernel<<<(unsigned)grid, 256, 0, st>>>(S, init);
     return hipGetLastError();
 }
