@@ -429,8 +429,10 @@ int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
     return SPCG_OK;
 }
 
-// R -> (R, M = R^{-1} R^{-T})
-int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
+// R -> (R, M = R^{-1} R^{-T}); diag_inv: the inverses of R's 64 x 64
+// diagonal blocks when the Cholesky that produced R left them (d x d, or
+// null)
+int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc, const double* diag_inv = nullptr) {
     const int64_t d = pc->d;
     hipStream_t st = ctx->stream;
     int rc;
@@ -439,7 +441,7 @@ int precond_finish(spcg_ctx* ctx, spcg_precond_t* pc) {
     const int64_t we = ctx->dense_w_elems;
     HIP_TRY(ctx, ctx->dense_a.ensure((size_t)d * d * 8));
     double* W = ctx->dense_a.as<double>();
-    HIP_TRY(ctx, tri_inverse_upper(st, pc->pR, d, d, W, ctx->dense_tmp.as<double>(), wk, we));
+    HIP_TRY(ctx, tri_inverse_upper(st, pc->pR, d, d, W, diag_inv, ctx->dense_tmp.as<double>(), wk, we));
     HIP_TRY(ctx, gemm_f64(st, d, d, d, 1.0, W, 0, d, 1, W, 0, 1, d, 0.0, pc->pMinv, d, 0, wk, we));
     return SPCG_OK;
 }
@@ -484,7 +486,7 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
         const double ratio = ok ? hs.max_diag / hs.min_diag : INFINITY;
         if (ok && (mode == 1 || ratio <= 1e5)) {
             pc->passes = 1;
-            return precond_finish(ctx, pc);
+            return precond_finish(ctx, pc, ctx->dense_wd.as<double>());
         }
         if (mode == 1)
             return fail(ctx, SPCG_E_RANK, "Cholesky of the sketched Gram failed at pivot %d", hs.fail);

@@ -511,6 +511,14 @@ __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64
     dst[i * ldd + j] = src[i * lds + j];
 }
 
+// W = the 64 x 64 diagonal blocks of D, zeros elsewhere
+__global__ void blockdiag_copy_kernel(const double* D, int64_t d, int64_t ld, double* W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d * d) return;
+    const int64_t i = e / d, j = e - i * d;
+    W[i * ld + j] = (i / CB == j / CB) ? D[i * ld + j] : 0.0;
+}
+
 __global__ void identity_kernel(double* A, int64_t d) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= d * d) return;
@@ -641,11 +649,16 @@ hipError_t trsm_right_upper(hipStream_t st, double* A, int64_t n, int64_t d, int
     return hipSuccess;
 }
 
-hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp,
-                             double* work, int64_t work_elems) {
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W,
+                             const double* diag_inv, double* tmp, double* work, int64_t work_elems) {
     hipError_t e;
-    if ((e = dense_fill_identity(st, W, d)) != hipSuccess) return e;
-    if ((e = trtri_diag_blocks(st, U, d, ld, W)) != hipSuccess) return e;
+    if (diag_inv) {
+        blockdiag_copy_kernel<<<(unsigned)ceil_div(d * d, 256), 256, 0, st>>>(diag_inv, d, ld, W);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        if ((e = dense_fill_identity(st, W, d)) != hipSuccess) return e;
+        if ((e = trtri_diag_blocks(st, U, d, ld, W)) != hipSuccess) return e;
+    }
     // recursive doubling over block columns: [W11 W12; 0 W22] with
     // W12 = -W11 (U12 W22), neighbouring s-blocks per level, s = CB, 2 CB, ...
     for (int64_t s = CB; s < d; s *= 2) {

@@ -238,12 +238,13 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
 // per 64-row panel.  The remaining arguments are unused.
 hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, DenseStatus* status,
                           double* W, double* panel, double* work, int64_t work_elems);
-// W = U^{-1} (d x d, ld) for upper-triangular U: diagonal-block inverses,
-// then block recursive doubling W12 = -W11 U12 W22 over 64, 128, ...
-// column blocks.  tmp: d * d / 4 doubles; work: split-K workspace (as for
+// W = U^{-1} (d x d, ld) for upper-triangular U: diagonal-block inverses
+// (taken from diag_inv, same layout, when given; computed otherwise), then
+// block recursive doubling W12 = -W11 U12 W22 over 64, 128, ... column
+// blocks.  tmp: d * d / 4 doubles; work: split-K workspace (as for
 // gemm_f64, may be null).
-hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W, double* tmp,
-                             double* work, int64_t work_elems);
+hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W,
+                             const double* diag_inv, double* tmp, double* work, int64_t work_elems);
 // Inverses of the 64 x 64 diagonal blocks of an upper-triangular U into W.
 hipError_t trtri_diag_blocks(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W);
 // In-place A <- A U^{-1} for A (n x d, lda), upper-triangular U (d x d,
