@@ -126,6 +126,99 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
 }
 
+// The same tiling (64 x 64 output per block, K in steps of GK through LDS)
+// with the products on the FP64 matrix cores: each of the 4 waves owns a
+// 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  Per 16 x 16 x 4
+// step a lane feeds A[i][k] with i = lane mod 16, k = lane / 16 and B[k][j]
+// with j = lane mod 16, k = lane / 16, and holds D[lane / 16 + 4 v][lane mod
+// 16] in register v (rows interleaved, unlike the FP32 16x16x4 form; checked
+// on the device).  Per K step a wave reads 4 doubles per lane from
+// LDS for 16 instructions (1024 FMA each), against 8 reads per 16 FMA of the
+// register-tiled kernel.
+typedef double gemm_v4d __attribute__((ext_vector_type(4)));
+
+template <bool AF32, bool BF32>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
+    const int64_t ti = blockIdx.y, tj = blockIdx.x;
+    if (g.upper && ti > tj) return;
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t i0 = ti * GT, j0 = tj * GT;
+    gemm_v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = gemm_v4d{0.0, 0.0, 0.0, 0.0};
+    const bool a_icontig = g.sai == 1;
+    const bool b_jcontig = g.sbj == 1;
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = min(g.K, kbeg + g.kchunk);
+    for (int64_t l0 = kbeg; l0 < kend; l0 += GK) {
+#pragma unroll
+        for (int q = 0; q < GT * GK / 256; ++q) {
+            const int e = tid + q * 256;
+            int i, l;
+            if (a_icontig) {
+                i = e % GT;
+                l = e / GT;
+            } else {
+                l = e % GK;
+                i = e / GK;
+            }
+            const int64_t gi = i0 + i, gl = l0 + l;
+            As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
+            int j;
+            if (b_jcontig) {
+                j = e % GT;
+                l = e / GT;
+            } else {
+                l = e % GK;
+                j = e / GK;
+            }
+            const int64_t gj = j0 + j, gl2 = l0 + l;
+            Bs[l][j] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GK / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                av[t] = As[kk][wr * 32 + t * 16 + (lane & 15)];
+                bv[t] = Bs[kk][wc * 32 + t * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
+                const int64_t gj = j0 + wc * 32 + b * 16 + (lane & 15);
+                if (gi >= g.M || gj >= g.N) continue;
+                const double r = acc[a][b][v];
+                if (g.part) {
+                    g.part[((int64_t)blockIdx.z * g.M + gi) * g.N + gj] = r;
+                    continue;
+                }
+                double* cp = g.C + gi * g.ldc + gj;
+                const double val = g.alpha * r;
+                *cp = g.beta == 0.0 ? val : fma(g.beta, *cp, val);
+            }
+}
+
 // C = alpha * sum_z part[z] + beta * C (fixed order over z)
 __global__ void splitk_reduce_kernel(const double* part, int nz, int64_t M, int64_t N, double alpha,
                                      double beta, double* C, int64_t ldc, int upper) {
@@ -563,6 +656,17 @@ namespace {
 template <int TT>
 hipError_t gemm_launch(hipStream_t st, const GemmArgs& g, int a_f32, int b_f32, dim3 grid) {
     const dim3 block(256);
+    if constexpr (TT == GT) {
+        if (a_f32 && b_f32)
+            gemm_mfma_kernel<true, true><<<grid, block, 0, st>>>(g);
+        else if (a_f32)
+            gemm_mfma_kernel<true, false><<<grid, block, 0, st>>>(g);
+        else if (b_f32)
+            gemm_mfma_kernel<false, true><<<grid, block, 0, st>>>(g);
+        else
+            gemm_mfma_kernel<false, false><<<grid, block, 0, st>>>(g);
+        return hipGetLastError();
+    }
     if (a_f32 && b_f32)
         gemm_kernel<true, true, TT><<<grid, block, 0, st>>>(g);
     else if (a_f32)
