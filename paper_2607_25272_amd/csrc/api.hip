@@ -80,6 +80,10 @@ struct spcg_ctx {
     // batched solves: per-problem sketches, preconditioners and buffers,
     // kept for reuse by later calls (allocation is slow next to a solve)
     BatchWork* batch = nullptr;
+    // the transform's output-slot tables are built on a side stream beside
+    // its first pass (created on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_side_fork = nullptr, ev_side_join = nullptr;
     // events for timing
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
@@ -356,7 +360,19 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     const size_t zy = (size_t)Np * sk->ldy * 8;
     HIP_TRY(ctx, ctx->zbuf.ensure(std::max(zx, zy)));
     hipStream_t st = ctx->stream;
-    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, mK ? inv_slot : nullptr, inv_hat));
+    // the permutation first; the output-slot tables (only the last pass
+    // needs them) on the side stream, overlapping the first pass's memory
+    // traffic with their Feistel arithmetic
+    if (!ctx->side) {
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_fork, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_join, hipEventDisableTiming));
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
+    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, nullptr, nullptr));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_side_fork, 0));
+    HIP_TRY(ctx, launch_sketch_tables(ctx->side, sk->seed, L, mK, r, nullptr, mK ? inv_slot : nullptr, inv_hat));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_side_join, ctx->side));
     FwhtJob jx{};
     jx.x = X->data;
     jx.in_dtype = X->dtype;
@@ -381,6 +397,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     jx.narrow = 0;
     jx.stream = 1;
     jx.num_cu = ctx->num_cu;
+    jx.wait_before_last = ctx->ev_side_join;
     HIP_TRY(ctx, run_fwht(st, jx));
     if (mK) {
         FwhtJob jy{};
@@ -1321,6 +1338,12 @@ int spcg_ctx_destroy(spcg_ctx* ctx) {
         for (auto& e : ctx->ev_prod) (void)hipEventDestroy(e);
     }
     delete ctx->batch;
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_side_fork) (void)hipEventDestroy(ctx->ev_side_fork);
+    if (ctx->ev_side_join) (void)hipEventDestroy(ctx->ev_side_join);
     delete ctx;
     return SPCG_OK;
 }

@@ -10,7 +10,8 @@
 namespace spcg {
 
 // ---------------------------------------------------------------- sketch
-// Per-row randomness tables for a padded size Np = 2^L:
+// Per-row randomness tables for a padded size Np = 2^L (each output may be
+// null and is then skipped):
 //   perm_sign[k] = p(k) | (sign_bit(k) << 31)
 //   inv_slot[k]  = pi^{-1}(k)     if < mK, else -1
 //   inv_hat[k]   = pi_hat^{-1}(k) if < r,  else -1
@@ -43,6 +44,9 @@ struct FwhtJob {
     int stream;               // 1: 10- and 11-bit FP32-precision passes use the streaming
                               // kernel (persistent blocks, next tile prefetched)
     int num_cu;               // compute units (grid of the streaming kernel)
+    hipEvent_t wait_before_last;  // if set: the last pass waits for it (the
+                                  // output-slot tables are built beside the
+                                  // first pass)
 };
 // Widest column chunk of the transform (256-byte row segments): every row
 // width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.

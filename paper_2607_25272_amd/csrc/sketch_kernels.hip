@@ -26,9 +26,11 @@ __global__ void tables_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int6
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
     uint64_t uk = (uint64_t)k;
-    uint32_t pk = (uint32_t)feistel_fwd(uk, L, seed, STREAM_P);
-    uint32_t sb = sign_bit(seed, uk);
-    perm_sign[k] = (int32_t)(pk | (sb << 31));
+    if (perm_sign) {
+        uint32_t pk = (uint32_t)feistel_fwd(uk, L, seed, STREAM_P);
+        uint32_t sb = sign_bit(seed, uk);
+        perm_sign[k] = (int32_t)(pk | (sb << 31));
+    }
     if (inv_slot) {
         int64_t t = (int64_t)feistel_inv(uk, L, seed, STREAM_PI);
         inv_slot[k] = t < mK ? (int32_t)t : -1;
@@ -720,6 +722,10 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     for (int pi = 0; pi < passes; ++pi) {
         const int nb = L / passes + (pi < L % passes ? 1 : 0);
         const bool first = pi == 0, last = pi == passes - 1;
+        if (last && job.wait_before_last) {
+            const hipError_t e = hipStreamWaitEvent(st, job.wait_before_last, 0);
+            if (e != hipSuccess) return e;
+        }
         if constexpr (std::is_same<TZ, float>::value) {
             // 11-bit passes need 64-byte rows (CW = 16): measured faster than
             // one tile per block for FP32 input only
