@@ -80,6 +80,9 @@ struct spcg_ctx {
     // batched solves: per-problem sketches, preconditioners and buffers,
     // kept for reuse by later calls (allocation is slow next to a solve)
     BatchWork* batch = nullptr;
+    // pinned copy of the Cholesky pivot status and its event
+    DenseStatus* host_status = nullptr;
+    hipEvent_t ev_status = nullptr;
     // the transform's output-slot tables are built on a side stream beside
     // its first pass (created on first use)
     hipStream_t side = nullptr;
@@ -422,15 +425,34 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
 
 // --------------------------------------------------------- preconditioner
 
-int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, DenseStatus* host) {
+// Cholesky of G with its pivot status copied to pinned host memory behind
+// it; the caller waits for the copy with chol_status_wait (and may queue
+// more work first).
+int chol_enqueue(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status) {
     hipStream_t st = ctx->stream;
+    if (!ctx->host_status) {
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->host_status, sizeof(DenseStatus), hipHostMallocDefault));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_status, hipEventDisableTiming));
+    }
     HIP_TRY(ctx, dense_status_reset(st, dev_status));
     HIP_TRY(ctx, cholesky_upper(st, G, d, d, dev_status, ctx->dense_wd.as<double>(), ctx->dense_tmp.as<double>(),
                                 ctx->dense_w.as<double>(), ctx->dense_w_elems));
-    HIP_TRY(ctx, hipMemcpyAsync(host, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-    ctx->syncs++;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_status, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_status, st));
     return SPCG_OK;
+}
+
+int chol_status_wait(spcg_ctx* ctx, DenseStatus* host) {
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev_status));
+    ctx->syncs++;
+    *host = *ctx->host_status;
+    return SPCG_OK;
+}
+
+int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, DenseStatus* host) {
+    int rc;
+    if ((rc = chol_enqueue(ctx, G, d, dev_status)) != SPCG_OK) return rc;
+    return chol_status_wait(ctx, host);
 }
 
 // split-K workspace of the dense kernels (8 partial d x d or r x 64
@@ -498,12 +520,17 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
     };
     if (mode == 0 || mode == 1) {
         HIP_TRY(ctx, gram_hat(R));
-        if ((rc = chol_checked(ctx, R, d, dst, &hs)) != SPCG_OK) return rc;
+        // M is formed right behind the factor while the host waits for the
+        // pivot status (no idle gap); a failed or badly scaled factor is
+        // redone below, which overwrites R and M
+        if ((rc = chol_enqueue(ctx, R, d, dst)) != SPCG_OK) return rc;
+        if ((rc = precond_finish(ctx, pc, ctx->dense_wd.as<double>())) != SPCG_OK) return rc;
+        if ((rc = chol_status_wait(ctx, &hs)) != SPCG_OK) return rc;
         const bool ok = hs.fail == 0 && hs.min_diag > 0.0;
         const double ratio = ok ? hs.max_diag / hs.min_diag : INFINITY;
         if (ok && (mode == 1 || ratio <= 1e5)) {
             pc->passes = 1;
-            return precond_finish(ctx, pc, ctx->dense_wd.as<double>());
+            return SPCG_OK;
         }
         if (mode == 1)
             return fail(ctx, SPCG_E_RANK, "Cholesky of the sketched Gram failed at pivot %d", hs.fail);
@@ -1342,6 +1369,8 @@ int spcg_ctx_destroy(spcg_ctx* ctx) {
         (void)hipStreamSynchronize(ctx->side);
         (void)hipStreamDestroy(ctx->side);
     }
+    if (ctx->host_status) (void)hipHostFree(ctx->host_status);
+    if (ctx->ev_status) (void)hipEventDestroy(ctx->ev_status);
     if (ctx->ev_side_fork) (void)hipEventDestroy(ctx->ev_side_fork);
     if (ctx->ev_side_join) (void)hipEventDestroy(ctx->ev_side_join);
     delete ctx;
