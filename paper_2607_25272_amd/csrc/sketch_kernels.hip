@@ -172,6 +172,11 @@ struct PassArgs {
     int b_bf16;        // store B rows as BF16
     int lo, nb, q;
     int64_t nchunks, ntiles;
+    // chunk-major Z of a two-pass streaming transform (zt_hibits > 0): the
+    // element (k, col) sits at ((chunk << lobits | k_lo) << hibits | k_hi) * CW
+    // + col mod CW with k = k_hi 2^lobits + k_lo, so that a last-pass tile
+    // (fixed k_lo and chunk) is one contiguous block
+    int zt_lobits, zt_hibits;
 };
 
 // One block = one tile of 2^nb rows x CW columns.
@@ -473,6 +478,12 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
         return Tile{(ohi << (lo + NB)) | olo, cc * CW};
     };
     auto grow = [&](const Tile& tl, int r) -> int64_t { return tl.rowbase | ((int64_t)r << lo); };
+    // element offset of Z(k, col)
+    auto zoff = [&](int64_t k, int64_t col) -> int64_t {
+        if (a.zt_hibits == 0) return k * a.ldz + col;
+        const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
+        return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
+    };
     // tile row and 16-byte piece that direct load i of this lane fetches
     auto dma_slot = [&](int i, int& row, int& piece) {
         const int P = ((wave * NI + i) * 64 + lane) * 16;
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
                 const bool ok = sr < a.N && col < a.d;
                 src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
             } else {
-                src = static_cast<const unsigned char*>(a.zin) + (grow(tl, row) * a.ldz + col) * 4;
+                src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, row), col) * 4;
             }
             stream_lds_load16(src, dst + i * 1024);
         }
@@ -622,7 +633,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
                 }
                 if (sh[t] >= 0) ZVec<float>::st(static_cast<float*>(a.Bh) + (int64_t)sh[t] * a.ldbh + col0, v[t]);
             } else {
-                ZVec<float>::st(static_cast<float*>(a.zout) + grow(tl, tile_row(bidx, NB - Q, t)) * a.ldz + col0, v[t]);
+                ZVec<float>::st(static_cast<float*>(a.zout) + zoff(grow(tl, tile_row(bidx, NB - Q, t)), col0), v[t]);
             }
         }
     }
@@ -718,22 +729,35 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     a.b_bf16 = job.b_bf16;
     constexpr int VL = ZVec<TZ>::VL;
     a.xvec = (job.ldx % VL == 0) && ((uintptr_t)job.x % (VL * sizeof(TIN)) == 0);
+    // the first pass stages rows of X with 16-byte direct loads
+    const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
+    // column width of the streaming kernel for a pass (0: one tile per block).
+    // 11-bit passes need 64-byte rows (CW = 16): measured faster than one
+    // tile per block for FP32 input only
+    auto stream_cw = [&](int nb, bool first) -> int {
+        if (!std::is_same<TZ, float>::value) return 0;
+        const int scw = nb == 10 ? 32 : (nb == 11 && std::is_same<TIN, float>::value) ? 16 : 0;
+        if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes != 0 || job.ldz % scw != 0 ||
+            (first && !xdma))
+            return 0;
+        return scw;
+    };
+    const int nb0 = L / passes + (0 < L % passes ? 1 : 0);
+    const int cw0 = stream_cw(nb0, true), cw1 = passes == 2 ? stream_cw(L - nb0, false) : 0;
+    const bool ztrans = passes == 2 && cw0 && cw0 == cw1;
     int lo = 0;
     for (int pi = 0; pi < passes; ++pi) {
         const int nb = L / passes + (pi < L % passes ? 1 : 0);
         const bool first = pi == 0, last = pi == passes - 1;
+        a.zt_lobits = ztrans ? nb0 : 0;
+        a.zt_hibits = ztrans ? L - nb0 : 0;
         if (last && job.wait_before_last) {
             const hipError_t e = hipStreamWaitEvent(st, job.wait_before_last, 0);
             if (e != hipSuccess) return e;
         }
         if constexpr (std::is_same<TZ, float>::value) {
-            // 11-bit passes need 64-byte rows (CW = 16): measured faster than
-            // one tile per block for FP32 input only
-            const int scw = nb == 10 ? 32 : (nb == 11 && std::is_same<TIN, float>::value) ? 16 : 0;
-            // the first pass stages rows of X with 16-byte direct loads
-            const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
-            if (job.stream && job.num_cu > 0 && scw && passes >= 2 && job.seg_bytes == 0 &&
-                job.ldz % scw == 0 && (!first || xdma)) {
+            const int scw = stream_cw(nb, first);
+            if (scw) {
                 a.lo = lo;
                 a.nb = nb;
                 a.q = 4;
