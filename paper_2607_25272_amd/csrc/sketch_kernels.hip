@@ -222,6 +222,13 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
         return base | (t << s0);
     };
     auto global_row = [&](int j) -> int64_t { return (ohi << (lo + nb)) | ((int64_t)j << lo) | olo; };
+    // element offset of Z(k, col) (row-major, or chunk-major as described
+    // at PassArgs)
+    auto zoff = [&](int64_t k, int64_t col) -> int64_t {
+        if (a.zt_hibits == 0) return k * a.ldz + col;
+        const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
+        return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
+    };
 
     TZ v[RMAX][VL];
     // ---- load (window = bits [0, q))
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
 #pragma unroll
         for (int t = 0; t < RMAX; ++t) {
             if (t < R) {
-                const TZ* p = static_cast<const TZ*>(a.zin) + global_row(tile_row(0, t)) * a.ldz + col0;
+                const TZ* p = static_cast<const TZ*>(a.zin) + zoff(global_row(tile_row(0, t)), col0);
                 if constexpr (VL == 1) {
                     v[t][0] = *p;
                 } else {
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
                     }
                 }
             } else {
-                TZ* p = static_cast<TZ*>(a.zout) + k * a.ldz + col0;
+                TZ* p = static_cast<TZ*>(a.zout) + zoff(k, col0);
                 if constexpr (VL == 1) *p = v[t][0]; else ZVec<TZ>::st(p, v[t]);
             }
         }
@@ -742,9 +749,22 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             return 0;
         return scw;
     };
+    // column width of the one-tile-per-block kernel: the widest segment
+    // whose tile fits the registers (256 B up to 10-bit passes, 128 B for 11
+    // bits), unless the job asks for a narrower one
+    auto tiled_cw = [&](int nb) -> int {
+        int seg = nb <= 10 ? 256 : 128;
+        if (job.seg_bytes > 0 && job.seg_bytes < seg) seg = job.seg_bytes;
+        return seg / E;
+    };
+    auto pass_cw = [&](int nb, bool first) -> int {
+        const int scw = stream_cw(nb, first);
+        return scw ? scw : tiled_cw(nb);
+    };
+    // two passes with one column width keep Z chunk-major (last-pass tiles
+    // then read contiguous blocks)
     const int nb0 = L / passes + (0 < L % passes ? 1 : 0);
-    const int cw0 = stream_cw(nb0, true), cw1 = passes == 2 ? stream_cw(L - nb0, false) : 0;
-    const bool ztrans = passes == 2 && cw0 && cw0 == cw1;
+    const bool ztrans = passes == 2 && pass_cw(nb0, true) == pass_cw(L - nb0, false);
     int lo = 0;
     for (int pi = 0; pi < passes; ++pi) {
         const int nb = L / passes + (pi < L % passes ? 1 : 0);
@@ -773,12 +793,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 continue;
             }
         }
-        // column segment per tile row: the widest whose tile fits the
-        // registers (256 B up to 10-bit passes, 128 B for 11 bits), unless
-        // the job asks for a narrower one (smaller blocks, more per CU)
-        int seg = nb <= 10 ? 256 : 128;
-        if (job.seg_bytes > 0 && job.seg_bytes < seg) seg = job.seg_bytes;
-        const int cw = seg / E;
+        const int cw = tiled_cw(nb);
         a.lo = lo;
         a.nb = nb;
         a.q = cw == CW_WIDE ? pass_q<TZ, CW_WIDE>(nb) : cw == CW_NARROW ? pass_q<TZ, CW_NARROW>(nb)
