@@ -107,12 +107,11 @@ typedef struct spcg_sketch_opts {
                             may be forced for non-F64 input.  The transform and
                             the preconditioner rows S_hat X stay FP32 (FP64 for
                             F64 input); BF16 rows are rounded to nearest even. */
-    int32_t transform_segment; /* tuning: 0 = library default (10-bit passes, and 11-bit
-                                  ones for F32 input, stream 128- or 64-byte row
-                                  segments through LDS in persistent blocks); 64, 128
-                                  or 256 selects one tile per block with at most that
-                                  many bytes per row segment.  Results are bit-identical
-                                  either way. */
+    int32_t transform_segment; /* tuning: 0 = library default (10-bit passes stream
+                                  128-byte row segments through LDS in persistent
+                                  blocks); 64, 128 or 256 selects one tile per block
+                                  with at most that many bytes per row segment.
+                                  Results are bit-identical either way. */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
     int32_t reserved; /* set to 0 */
     const int64_t* m_list; /* optional HOST array of the stage sizes m_1 < ... < m_K (replaces

@@ -356,7 +356,8 @@ __global__ __launch_bounds__(QMAX == 5 ? 512 : 1024) void fwht_pass_kernel(PassA
 // direct global->LDS loads while the current one goes through its
 // butterflies, LDS exchanges and stores, so every CU keeps reads and writes
 // in flight while it computes.  Tiles are 2^NB rows x CW columns with 16 rows
-// per thread: CW = 32 gives NB = 10, CW = 16 gives NB = 11.  The butterflies
+// per thread: CW = 32 gives NB = 10 (the shape the library launches; CW = 16
+// would give NB = 11).  The butterflies
 // run in the same order as in fwht_pass_kernel (stages in ascending bit
 // order, each (a, b) -> (a + b, a - b)), so both kernels give bit-identical
 // results.
@@ -710,9 +711,8 @@ hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool f
 
 // Passes of at most NB_MAX bits; each pass uses 256-byte row segments, or
 // 128-byte ones for 11-bit passes (whose 256-byte tile would not fit).
-// 10-bit passes at FP32 working precision of a multi-pass transform (and
-// 11-bit ones for FP32 input) use the streaming kernel unless the job asks
-// for one tile per block.
+// 10-bit passes at FP32 working precision of a multi-pass transform use the
+// streaming kernel unless the job asks for one tile per block.
 template <typename TIN, typename TZ>
 hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     const int L = job.L;
@@ -739,11 +739,12 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     // the first pass stages rows of X with 16-byte direct loads
     const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
     // column width of the streaming kernel for a pass (0: one tile per block).
-    // 11-bit passes need 64-byte rows (CW = 16): measured faster than one
-    // tile per block for FP32 input only
+    // 11-bit passes would need 64-byte rows (CW = 16); with chunk-major Z the
+    // tiled kernel's 128-byte rows measured faster there (2.71 against
+    // 2.88 ms at N = 2e6, d = 256), so only 10-bit passes stream
     auto stream_cw = [&](int nb, bool first) -> int {
         if (!std::is_same<TZ, float>::value) return 0;
-        const int scw = nb == 10 ? 32 : (nb == 11 && std::is_same<TIN, float>::value) ? 16 : 0;
+        const int scw = nb == 10 ? 32 : 0;
         if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes != 0 || job.ldz % scw != 0 ||
             (first && !xdma))
             return 0;
@@ -786,8 +787,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
-                                               : launch_stream<TIN, 16>(st, a, grid, first, last);
+                const hipError_t e = launch_stream<TIN, 32>(st, a, grid, first, last);
                 if (e != hipSuccess) return e;
                 lo += nb;
                 continue;

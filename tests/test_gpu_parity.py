@@ -180,11 +180,12 @@ def _raw_rows(sk, stage):
                                          ("bf16", 700_000, 24), ("fp8", 700_000, 48),
                                          ("f32", 1_100_000, 12)])
 def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
-    # N' = 2^20 (two 10-bit passes) or 2^21 (FP32: two 11-bit passes): the
-    # default transform streams tiles through LDS in persistent blocks;
-    # transform_segment = 256 forces one tile per block.  Same butterflies in
-    # the same order -> identical bits (d = 37: rows whose 16-byte pieces
-    # straddle d, first pass on the tiled kernel)
+    # N' = 2^20 (two 10-bit passes): the default transform streams tiles
+    # through LDS in persistent blocks; transform_segment = 256 forces one
+    # tile per block.  Same butterflies in the same order -> identical bits
+    # (d = 37: rows whose 16-byte pieces straddle d, first pass on the tiled
+    # kernel and Z row-major; N' = 2^21: two tiled 11-bit passes with
+    # chunk-major Z in both runs)
     _log(f"sketch streaming {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 89)
     rows = []
