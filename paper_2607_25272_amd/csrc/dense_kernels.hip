@@ -141,6 +141,7 @@ template <bool AF32, bool BF32>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     if (g.upper && ti > tj) return;
+    constexpr int NL = GT * GK / 256;   // elements per thread per operand and k step
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
     const int tid = threadIdx.x;
@@ -156,32 +157,37 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     const bool b_jcontig = g.sbj == 1;
     const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
+    // the (row or column, k) slots this thread loads for either operand
+    int ai[NL], al[NL], bj[NL], bl[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int e = tid + q * 256;
+        ai[q] = a_icontig ? e % GT : e / GK;
+        al[q] = a_icontig ? e / GT : e % GK;
+        bj[q] = b_jcontig ? e % GT : e / GK;
+        bl[q] = b_jcontig ? e / GT : e % GK;
+    }
+    double ra[NL], rb[NL];
+    auto fetch = [&](int64_t l0) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int64_t gi = i0 + ai[q], gl = l0 + al[q];
+            ra[q] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
+            const int64_t gj = j0 + bj[q], gl2 = l0 + bl[q];
+            rb[q] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+        }
+    };
+    // software pipeline: the loads of k step l0 + GK are in flight while
+    // step l0 runs on the matrix cores
+    if (kbeg < kend) fetch(kbeg);
     for (int64_t l0 = kbeg; l0 < kend; l0 += GK) {
 #pragma unroll
-        for (int q = 0; q < GT * GK / 256; ++q) {
-            const int e = tid + q * 256;
-            int i, l;
-            if (a_icontig) {
-                i = e % GT;
-                l = e / GT;
-            } else {
-                l = e % GK;
-                i = e / GK;
-            }
-            const int64_t gi = i0 + i, gl = l0 + l;
-            As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
-            int j;
-            if (b_jcontig) {
-                j = e % GT;
-                l = e / GT;
-            } else {
-                l = e % GK;
-                j = e / GK;
-            }
-            const int64_t gj = j0 + j, gl2 = l0 + l;
-            Bs[l][j] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+        for (int q = 0; q < NL; ++q) {
+            As[al[q]][ai[q]] = ra[q];
+            Bs[bl[q]][bj[q]] = rb[q];
         }
         __syncthreads();
+        if (l0 + GK < kend) fetch(l0 + GK);
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
