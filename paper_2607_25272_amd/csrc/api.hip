@@ -428,7 +428,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
 // Cholesky of G with its pivot status copied to pinned host memory behind
 // it; the caller waits for the copy with chol_status_wait (and may queue
 // more work first).
-int chol_enqueue(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status) {
+int chol_enqueue(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, DenseStatus* host_dst = nullptr) {
     hipStream_t st = ctx->stream;
     if (!ctx->host_status) {
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->host_status, sizeof(DenseStatus), hipHostMallocDefault));
@@ -437,7 +437,8 @@ int chol_enqueue(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status) {
     HIP_TRY(ctx, dense_status_reset(st, dev_status));
     HIP_TRY(ctx, cholesky_upper(st, G, d, d, dev_status, ctx->dense_wd.as<double>(), ctx->dense_tmp.as<double>(),
                                 ctx->dense_w.as<double>(), ctx->dense_w_elems));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_status, dev_status, sizeof(DenseStatus), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(host_dst ? host_dst : ctx->host_status, dev_status, sizeof(DenseStatus),
+                                hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_status, st));
     return SPCG_OK;
 }
@@ -497,8 +498,21 @@ int precond_alloc(spcg_ctx* ctx, spcg_precond_t* pc, int64_t d, bool borrow) {
     return SPCG_OK;
 }
 
+// a one-pass factor is kept when the Cholesky succeeded and (mode 0) its
+// diagonal spans at most five decades
+bool precond_status_ok(const DenseStatus& hs, int mode) {
+    const bool ok = hs.fail == 0 && hs.min_diag > 0.0;
+    const double ratio = ok ? hs.max_diag / hs.min_diag : INFINITY;
+    return ok && (mode == 1 || ratio <= 1e5);
+}
+
+// deferred (pinned host memory, modes 0 and 1 only): queue the one-pass
+// factor and M, copy the pivot status to *deferred behind them and return
+// without waiting; the caller checks it with precond_status_ok once the
+// stream has passed the copy and builds again (without deferral) when it
+// fails.
 int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opts* o, bool borrow,
-                  spcg_precond_t* pc) {
+                  spcg_precond_t* pc, DenseStatus* deferred = nullptr) {
     int rc;
     const int64_t d = sk->d, r = sk->r, ld = sk->ld;
     const int mode = o ? o->qr_passes : 0;
@@ -523,12 +537,14 @@ int precond_build(spcg_ctx* ctx, const spcg_sketch_t* sk, const spcg_precond_opt
         // M is formed right behind the factor while the host waits for the
         // pivot status (no idle gap); a failed or badly scaled factor is
         // redone below, which overwrites R and M
-        if ((rc = chol_enqueue(ctx, R, d, dst)) != SPCG_OK) return rc;
+        if ((rc = chol_enqueue(ctx, R, d, dst, deferred)) != SPCG_OK) return rc;
         if ((rc = precond_finish(ctx, pc, ctx->dense_wd.as<double>())) != SPCG_OK) return rc;
+        if (deferred) {
+            pc->passes = 1;
+            return SPCG_OK;
+        }
         if ((rc = chol_status_wait(ctx, &hs)) != SPCG_OK) return rc;
-        const bool ok = hs.fail == 0 && hs.min_diag > 0.0;
-        const double ratio = ok ? hs.max_diag / hs.min_diag : INFINITY;
-        if (ok && (mode == 1 || ratio <= 1e5)) {
+        if (precond_status_ok(hs, mode)) {
             pc->passes = 1;
             return SPCG_OK;
         }
@@ -834,9 +850,27 @@ struct BatchWork {
     hipStream_t cap = nullptr;
     hipEvent_t fork = nullptr, join[MR_NCLASS] = {}, tune[2] = {};
     int tasks_per_cu[4] = {};   // autotuned task granularity per storage type (0: not yet)
+    // per-problem setup (sketch, preconditioner) is spread over NLANE lanes,
+    // each a context of its own (stream and workspaces), so the small
+    // transforms and the latency-bound factor chains of different problems
+    // overlap; one pinned pivot status per problem
+    static constexpr int NLANE = 8;
+    spcg_ctx* lane[NLANE] = {};
+    hipEvent_t lane_join[NLANE] = {};
+    DenseStatus* hstat = nullptr;
+    size_t hstat_n = 0;
     ~BatchWork() {
         for (auto* p : sk) delete p;
         for (auto* p : pc) delete p;
+        for (auto* c : lane) {
+            if (!c) continue;
+            hipStream_t q = c->stream;
+            (void)spcg_ctx_destroy(c);
+            (void)hipStreamDestroy(q);
+        }
+        for (auto& e : lane_join)
+            if (e) (void)hipEventDestroy(e);
+        if (hstat) (void)hipHostFree(hstat);
         for (auto& q : cls)
             if (q) (void)hipStreamDestroy(q);
         if (cap) (void)hipStreamDestroy(cap);
@@ -847,6 +881,41 @@ struct BatchWork {
             if (e) (void)hipEventDestroy(e);
     }
 };
+
+int batch_lanes(spcg_ctx* ctx, BatchWork& W) {
+    if (W.lane[0]) return SPCG_OK;
+    for (int i = 0; i < BatchWork::NLANE; ++i) {
+        hipStream_t q = nullptr;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        const int rc = spcg_ctx_create(ctx->device, q, &W.lane[i]);
+        if (rc != SPCG_OK) {
+            (void)hipStreamDestroy(q);
+            W.lane[i] = nullptr;
+            return fail(ctx, rc, "lane context creation failed");
+        }
+        HIP_TRY(ctx, hipEventCreateWithFlags(&W.lane_join[i], hipEventDisableTiming));
+    }
+    return SPCG_OK;
+}
+
+// lane streams wait for what is queued on st / st waits for the lanes
+int lanes_fork(spcg_ctx* ctx, BatchWork& W, hipStream_t st) {
+    HIP_TRY(ctx, hipEventRecord(W.fork, st));
+    for (auto* c : W.lane) HIP_TRY(ctx, hipStreamWaitEvent(c->stream, W.fork, 0));
+    return SPCG_OK;
+}
+int lanes_join(spcg_ctx* ctx, BatchWork& W, hipStream_t st) {
+    for (int i = 0; i < BatchWork::NLANE; ++i) {
+        HIP_TRY(ctx, hipEventRecord(W.lane_join[i], W.lane[i]->stream));
+        HIP_TRY(ctx, hipStreamWaitEvent(st, W.lane_join[i], 0));
+    }
+    return SPCG_OK;
+}
+// a lane's error becomes the caller's
+int lane_fail(spcg_ctx* ctx, spcg_ctx* lane, int rc) {
+    ctx->err = lane->err;
+    return rc;
+}
 
 int batch_streams(spcg_ctx* ctx, BatchWork& W) {
     if (W.cap) return SPCG_OK;
@@ -1057,12 +1126,43 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     }
     spcg_sketch_opts so = opts->sketch;
     so.hat_only = opts->method == SPCG_METHOD_FULL_PCG ? 1 : 0;
+    // sketches and one-pass preconditioners of the problems on the lanes
+    // (problem p on lane p mod NLANE), each phase joined back into st
+    if ((rc = batch_streams(ctx, W)) != SPCG_OK) return rc;
+    if ((rc = batch_lanes(ctx, W)) != SPCG_OK) return rc;
+    if ((rc = lanes_fork(ctx, W, st)) != SPCG_OK) return rc;
     for (int p = 0; p < nprob; ++p) {
-        if ((rc = sketch_build(ctx, &X[p], &Y[p], &so, false, W.sk[p])) != SPCG_OK) return rc;
+        spcg_ctx* ln = W.lane[p % BatchWork::NLANE];
+        if ((rc = sketch_build(ln, &X[p], &Y[p], &so, false, W.sk[p])) != SPCG_OK) return lane_fail(ctx, ln, rc);
     }
+    if ((rc = lanes_join(ctx, W, st)) != SPCG_OK) return rc;
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
+    const int qmode = opts->precond.qr_passes;
+    const bool defer = qmode == 0 || qmode == 1;
+    if (defer && W.hstat_n < (size_t)nprob) {
+        if (W.hstat) HIP_TRY(ctx, hipHostFree(W.hstat));
+        W.hstat = nullptr;
+        W.hstat_n = 0;
+        HIP_TRY(ctx, hipHostMalloc((void**)&W.hstat, (size_t)nprob * sizeof(DenseStatus), hipHostMallocDefault));
+        W.hstat_n = (size_t)nprob;
+    }
+    if ((rc = lanes_fork(ctx, W, st)) != SPCG_OK) return rc;
     for (int p = 0; p < nprob; ++p) {
-        if ((rc = precond_build(ctx, W.sk[p], &opts->precond, false, W.pc[p])) != SPCG_OK) return rc;
+        spcg_ctx* ln = W.lane[p % BatchWork::NLANE];
+        if ((rc = precond_build(ln, W.sk[p], &opts->precond, false, W.pc[p], defer ? &W.hstat[p] : nullptr)) !=
+            SPCG_OK)
+            return lane_fail(ctx, ln, rc);
+    }
+    if ((rc = lanes_join(ctx, W, st)) != SPCG_OK) return rc;
+    if (defer) {
+        // the pivot statuses: a factor that failed or is badly scaled is
+        // built again here, with the fallback of a single solve
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        ctx->syncs++;
+        for (int p = 0; p < nprob; ++p) {
+            if (precond_status_ok(W.hstat[p], qmode)) continue;
+            if ((rc = precond_build(ctx, W.sk[p], &opts->precond, false, W.pc[p])) != SPCG_OK) return rc;
+        }
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
     const int64_t ldv = mrhs_max_d();
