@@ -80,6 +80,23 @@ def test_batched_uneven_problems(S, ctx):
         _check(q, b)
 
 
+def test_batched_preconditioner_fallback_per_problem(S, ctx):
+    # the one-pass factors of a batch are queued on several lanes and their
+    # pivot statuses checked together; a badly scaled factor (column scales
+    # spanning 1e6 > 1e5) is rebuilt with shifted CholeskyQR3 for that
+    # problem alone, the others keep one pass
+    probs = [workloads.gauss_colscale(N, d, cond, 1.0, storage="f32", k=k, seed=N + d, device=DEV)
+             for N, d, cond, k in ((30_000, 48, 1e2, 2), (40_000, 64, 1e6, 1), (25_000, 96, 1e3, 3),
+                                   (35_000, 40, 1e2, 1), (20_000, 80, 1e3, 2), (28_000, 56, 1e2, 1),
+                                   (33_000, 72, 1e3, 1), (22_000, 24, 1e2, 2), (26_000, 32, 1e6, 2))]
+    betas, stats = S.spcg_solve_batched(ctx, [q.X for q in probs], [q.Y for q in probs], seed=3)
+    for q, b, st in zip(probs, betas, stats):
+        print("problem", q.N, q.d, "qr_passes", st["qr_passes"], flush=True)
+        assert st["qr_passes"] == (3 if q.N in (40_000, 26_000) else 1)
+        assert st["converged"], st
+        _check(q, b)
+
+
 def test_batched_full_pcg_and_bf16(S, ctx):
     probs = [workloads.gauss_colscale(N, d, 1e3, 1.0, storage="bf16", k=k, seed=N, device=DEV)
              for N, d, k in ((30_000, 64, 2), (45_000, 128, 1), (25_000, 200, 7))]
