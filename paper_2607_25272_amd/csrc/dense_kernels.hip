@@ -329,23 +329,68 @@ __device__ __forceinline__ void potrf_patch(double (&a)[4][4], int nb, double (*
     __syncthreads();   // pivs complete
 }
 
-// running pivot statistics of the factorization (one thread)
+// running pivot statistics of the factorization: one wave, lane j takes
+// pivot j (nb <= 64); a NaN pivot never lowers the minimum, and the first
+// failure is the smallest failing index
 __device__ __forceinline__ void potrf_status(const double* pivs, int nb, int64_t k0, DenseStatus* st) {
-    double min_piv = st->min_pivot, min_d = st->min_diag, max_d = st->max_diag;
-    int first_fail = st->fail;
-    for (int j = 0; j < nb; ++j) {
-        const double p = pivs[j];
-        const bool bad = !(p > 0.0) || !__builtin_isfinite(p);
-        const double u = bad ? 1.0 : sqrt(p);
-        min_piv = p < min_piv ? p : min_piv;
-        if (bad && first_fail == 0) first_fail = (int)(k0 + j) + 1;
-        min_d = u < min_d ? u : min_d;
-        max_d = u > max_d ? u : max_d;
+    const int j = threadIdx.x & 63;
+    const bool in = j < nb;
+    const double p = in ? pivs[j] : 1.0;
+    const bool bad = in && (!(p > 0.0) || !__builtin_isfinite(p));
+    const double u = bad ? 1.0 : sqrt(p);
+    const double inf = __builtin_huge_val();
+    double mp = (in && p == p) ? p : inf;
+    double mn = in ? u : inf, mx = in ? u : -inf;
+    int ff = bad ? j : 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double a = __shfl_xor(mp, o), b = __shfl_xor(mn, o), c = __shfl_xor(mx, o);
+        const int f = __shfl_xor(ff, o);
+        mp = a < mp ? a : mp;
+        mn = b < mn ? b : mn;
+        mx = c > mx ? c : mx;
+        ff = f < ff ? f : ff;
     }
-    st->min_pivot = min_piv;
-    st->min_diag = min_d;
-    st->max_diag = max_d;
-    st->fail = first_fail;
+    if (j == 0) {
+        if (mp < st->min_pivot) st->min_pivot = mp;
+        if (mn < st->min_diag) st->min_diag = mn;
+        if (mx > st->max_diag) st->max_diag = mx;
+        if (st->fail == 0 && ff < 64) st->fail = (int)(k0 + ff) + 1;
+    }
+}
+
+// One doubling round of trtri_lds: for each pair of neighbouring SZ x SZ
+// diagonal blocks, W12 = -W11 (U12 W22).  W is upper triangular with its
+// strict lower part zero, so the products run over the full SZ range: the
+// extra terms are exact zeros added after (first product) or before (second)
+// the triangular ones, and the fixed trip count lets the LDS loads batch.
+template <int SZ>
+__device__ __forceinline__ void trtri_round(double (*T)[CB + 1], double (*Wl)[CB + 1], double (*Tmp)[CB + 1]) {
+    constexpr int OUTS = (CB / (2 * SZ)) * SZ * SZ;
+    static_assert(OUTS % 256 == 0, "whole rounds per thread");
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e0 = 0; e0 < OUTS; e0 += 256) {
+        const int e = e0 + tid;
+        const int p = e / (SZ * SZ), rem = e % (SZ * SZ), i = rem / SZ, j = rem % SZ;
+        const int s0 = p * 2 * SZ, s1 = s0 + SZ;
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < SZ; ++l) acc = fma(T[s0 + i][s1 + l], Wl[s1 + l][s1 + j], acc);
+        Tmp[s0 + i][s1 + j] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e0 = 0; e0 < OUTS; e0 += 256) {
+        const int e = e0 + tid;
+        const int p = e / (SZ * SZ), rem = e % (SZ * SZ), i = rem / SZ, j = rem % SZ;
+        const int s0 = p * 2 * SZ, s1 = s0 + SZ;
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < SZ; ++l) acc = fma(Wl[s0 + i][s0 + l], Tmp[s0 + l][s1 + j], acc);
+        Wl[s0 + i][s1 + j] = -acc;
+    }
+    __syncthreads();
 }
 
 // Inverse of the upper-triangular CB x CB block in T (identity past the
@@ -354,6 +399,7 @@ __device__ __forceinline__ void potrf_status(const double* pivs, int nb, int64_t
 // neighbouring s x s inverses with W12 = -W11 U12 W22.  Tmp is scratch.
 // Expects T complete (caller synchronizes); Wl is complete on return.
 __device__ __forceinline__ void trtri_lds(double (*T)[CB + 1], double (*Wl)[CB + 1], double (*Tmp)[CB + 1]) {
+    static_assert(CB == 64, "three doubling rounds");
     const int tid = threadIdx.x;
     for (int e = tid; e < CB * CB; e += 256) Wl[e >> 6][e & 63] = 0.0;
     __syncthreads();
@@ -371,28 +417,9 @@ __device__ __forceinline__ void trtri_lds(double (*T)[CB + 1], double (*Wl)[CB +
         for (int i = 0; i < 8; ++i) Wl[b0 + i][b0 + c] = w[i];
     }
     __syncthreads();
-    for (int sz = 8; sz < CB; sz *= 2) {
-        const int pairs = CB / (2 * sz);
-        const int outs = pairs * sz * sz;
-        // Tmp = U12 W22
-        for (int e = tid; e < outs; e += 256) {
-            const int p = e / (sz * sz), rem = e % (sz * sz), i = rem / sz, j = rem % sz;
-            const int s0 = p * 2 * sz, s1 = s0 + sz;
-            double acc = 0.0;
-            for (int l = 0; l <= j; ++l) acc = fma(T[s0 + i][s1 + l], Wl[s1 + l][s1 + j], acc);
-            Tmp[s0 + i][s1 + j] = acc;
-        }
-        __syncthreads();
-        // W12 = -W11 Tmp
-        for (int e = tid; e < outs; e += 256) {
-            const int p = e / (sz * sz), rem = e % (sz * sz), i = rem / sz, j = rem % sz;
-            const int s0 = p * 2 * sz, s1 = s0 + sz;
-            double acc = 0.0;
-            for (int l = i; l < sz; ++l) acc = fma(Wl[s0 + i][s0 + l], Tmp[s0 + l][s1 + j], acc);
-            Wl[s0 + i][s1 + j] = -acc;
-        }
-        __syncthreads();
-    }
+    trtri_round<8>(T, Wl, Tmp);
+    trtri_round<16>(T, Wl, Tmp);
+    trtri_round<32>(T, Wl, Tmp);
 }
 
 // Inverses of CB x CB diagonal blocks of an upper-triangular U, starting at
@@ -452,7 +479,7 @@ __device__ __forceinline__ void store_factor_and_inverse(double (&a)[4][4], int 
             if (i < nb && j < nb) G[(k0 + i) * ld + k0 + j] = u;
             T[i][j] = (i < nb && j < nb) ? u : (i == j ? 1.0 : 0.0);
         }
-    if (tid == 0) potrf_status(pivs, nb, k0, st);
+    if (tid < 64) potrf_status(pivs, nb, k0, st);   // wave 0
     __syncthreads();
     trtri_lds(T, Wl, Tmp);
     for (int e = tid; e < CB * CB; e += 256) {
