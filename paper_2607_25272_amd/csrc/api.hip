@@ -457,7 +457,8 @@ int chol_checked(spcg_ctx* ctx, double* G, int64_t d, DenseStatus* dev_status, D
 }
 
 // split-K workspace of the dense kernels (8 partial d x d or r x 64
-// products), the diagonal-block inverses (d x d) and a 64-column strip
+// products), the diagonal-block inverses (d x d) and a d x d (at least
+// 64-column) scratch
 int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
     const int64_t elems = 8 * std::max<int64_t>(d * d, r * 64);
     if (ctx->dense_w_elems < elems) {
@@ -465,7 +466,7 @@ int ensure_dense_work(spcg_ctx* ctx, int64_t d, int64_t r) {
         ctx->dense_w_elems = elems;
     }
     HIP_TRY(ctx, ctx->dense_wd.ensure((size_t)d * d * 8));
-    HIP_TRY(ctx, ctx->dense_tmp.ensure((size_t)std::max(std::max(r, d) * 64, d * d / 4 + 64) * 8));
+    HIP_TRY(ctx, ctx->dense_tmp.ensure((size_t)std::max(std::max(r, d) * 64, d * d + 64) * 8));
     return SPCG_OK;
 }
 

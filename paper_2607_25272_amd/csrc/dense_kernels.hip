@@ -35,6 +35,11 @@ struct GemmArgs {
     int upper;
     int64_t kchunk;     // K range per blockIdx.z
     double* part;       // split-K: [gridDim.z][M][N] partial products (or null)
+    // batched products (bsc != 0): blockIdx.z selects entry z, whose A, B and
+    // C start bsa, bsb and bsc elements after entry 0's; no split-K.  The
+    // last entry may be narrower: N = n_last, K = k_last where those are > 0
+    int64_t bsa, bsb, bsc;
+    int64_t n_last, k_last;
 };
 
 template <bool F32>
@@ -65,8 +70,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         for (int c = 0; c < P; ++c) acc[r][c] = 0.0;
     const bool a_icontig = g.sai == 1;
     const bool b_jcontig = g.sbj == 1;
-    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
-    const int64_t kend = min(g.K, kbeg + g.kchunk);
+    const bool batched = g.bsc != 0;
+    const int64_t oa = batched ? (int64_t)blockIdx.z * g.bsa : 0;
+    const int64_t ob = batched ? (int64_t)blockIdx.z * g.bsb : 0;
+    const bool lastz = batched && blockIdx.z + 1 == gridDim.z;
+    const int64_t gN = lastz && g.n_last > 0 ? g.n_last : g.N;
+    const int64_t gK = lastz && g.k_last > 0 ? g.k_last : g.K;
+    const int64_t kbeg = batched ? 0 : (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = batched ? gK : min(g.K, kbeg + g.kchunk);
     for (int64_t l0 = kbeg; l0 < kend; l0 += GK) {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
@@ -80,7 +91,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 i = e / GK;
             }
             const int64_t gi = i0 + i, gl = l0 + l;
-            As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
+            As[l][i] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, oa + gi * g.sai + gl * g.sal) : 0.0;
             int j;
             if (b_jcontig) {
                 j = e % TT;
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 j = e / GK;
             }
             const int64_t gj = j0 + j, gl2 = l0 + l;
-            Bs[l][j] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+            Bs[l][j] = (gj < gN && gl2 < kend) ? ld_elem<BF32>(g.B, ob + gl2 * g.sbl + gj * g.sbj) : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -114,12 +125,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int c = 0; c < P; ++c) {
             const int64_t gj = j0 + tx * P + c;
-            if (gj >= g.N) continue;
+            if (gj >= gN) continue;
             if (g.part) {
                 g.part[((int64_t)blockIdx.z * g.M + gi) * g.N + gj] = acc[r][c];
                 continue;
             }
-            double* cp = g.C + gi * g.ldc + gj;
+            double* cp = g.C + (batched ? (int64_t)blockIdx.z * g.bsc : 0) + gi * g.ldc + gj;
             const double v = g.alpha * acc[r][c];
             *cp = g.beta == 0.0 ? v : fma(g.beta, *cp, v);
         }
@@ -155,8 +166,14 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
         for (int b = 0; b < 2; ++b) acc[a][b] = gemm_v4d{0.0, 0.0, 0.0, 0.0};
     const bool a_icontig = g.sai == 1;
     const bool b_jcontig = g.sbj == 1;
-    const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
-    const int64_t kend = min(g.K, kbeg + g.kchunk);
+    const bool batched = g.bsc != 0;
+    const int64_t oa = batched ? (int64_t)blockIdx.z * g.bsa : 0;
+    const int64_t ob = batched ? (int64_t)blockIdx.z * g.bsb : 0;
+    const bool lastz = batched && blockIdx.z + 1 == gridDim.z;
+    const int64_t gN = lastz && g.n_last > 0 ? g.n_last : g.N;
+    const int64_t gK = lastz && g.k_last > 0 ? g.k_last : g.K;
+    const int64_t kbeg = batched ? 0 : (int64_t)blockIdx.z * g.kchunk;
+    const int64_t kend = batched ? gK : min(g.K, kbeg + g.kchunk);
     // the (row or column, k) slots this thread loads for either operand
     int ai[NL], al[NL], bj[NL], bl[NL];
 #pragma unroll
@@ -172,9 +189,9 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int64_t gi = i0 + ai[q], gl = l0 + al[q];
-            ra[q] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, gi * g.sai + gl * g.sal) : 0.0;
+            ra[q] = (gi < g.M && gl < kend) ? ld_elem<AF32>(g.A, oa + gi * g.sai + gl * g.sal) : 0.0;
             const int64_t gj = j0 + bj[q], gl2 = l0 + bl[q];
-            rb[q] = (gj < g.N && gl2 < kend) ? ld_elem<BF32>(g.B, gl2 * g.sbl + gj * g.sbj) : 0.0;
+            rb[q] = (gj < gN && gl2 < kend) ? ld_elem<BF32>(g.B, ob + gl2 * g.sbl + gj * g.sbj) : 0.0;
         }
     };
     // software pipeline: the loads of k step l0 + GK are in flight while
@@ -213,13 +230,13 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int64_t gi = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * v;
                 const int64_t gj = j0 + wc * 32 + b * 16 + (lane & 15);
-                if (gi >= g.M || gj >= g.N) continue;
+                if (gi >= g.M || gj >= gN) continue;
                 const double r = acc[a][b][v];
                 if (g.part) {
                     g.part[((int64_t)blockIdx.z * g.M + gi) * g.N + gj] = r;
                     continue;
                 }
-                double* cp = g.C + gi * g.ldc + gj;
+                double* cp = g.C + (batched ? (int64_t)blockIdx.z * g.bsc : 0) + gi * g.ldc + gj;
                 const double val = g.alpha * r;
                 *cp = g.beta == 0.0 ? val : fma(g.beta, *cp, val);
             }
@@ -743,6 +760,28 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
     return hipGetLastError();
 }
 
+// `batch` FP64 products of one shape (the last may have N = n_last and
+// K = k_last, where those are > 0), entry z at A + z bsa, B + z bsb and
+// C + z bsc (row-major strides as for gemm_f64); one launch, no split-K.
+// A single entry goes through gemm_f64 (which may split K into work).
+hipError_t gemm_f64_batched(hipStream_t st, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
+                            const double* A, int64_t sai, int64_t sal, int64_t bsa, const double* B,
+                            int64_t sbl, int64_t sbj, int64_t bsb, double beta, double* C, int64_t ldc,
+                            int64_t bsc, int64_t n_last, int64_t k_last, double* work, int64_t work_elems) {
+    if (M <= 0 || N <= 0 || batch <= 0 || n_last < 0 || n_last > N || k_last < 0 || k_last > K)
+        return M <= 0 || N <= 0 || batch <= 0 ? hipSuccess : hipErrorInvalidValue;
+    if (batch == 1)
+        return gemm_f64(st, M, n_last > 0 ? n_last : N, k_last > 0 ? k_last : K, alpha, A, 0, sai, sal, B, 0, sbl,
+                        sbj, beta, C, ldc, 0, work, work_elems);
+    if (bsc == 0 || batch > 65535) return hipErrorInvalidValue;
+    const bool small = ceil_div(M, GT) * ceil_div(N, GT) * batch < 64;
+    const int64_t tt = small ? 32 : GT;
+    GemmArgs g{M, N, K, alpha, beta, A, sai, sal, B, sbl, sbj, C, ldc, 0, round_up(K, GK), nullptr,
+               bsa, bsb, bsc, n_last, k_last};
+    const dim3 grid((unsigned)ceil_div(N, tt), (unsigned)ceil_div(M, tt), (unsigned)batch);
+    return small ? gemm_launch<32>(st, g, 0, 0, grid) : gemm_launch<GT>(st, g, 0, 0, grid);
+}
+
 hipError_t copy2d(hipStream_t st, const double* src, int64_t lds, double* dst, int64_t ldd,
                   int64_t rows, int64_t cols) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
@@ -801,17 +840,21 @@ hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t
     }
     // recursive doubling over block columns: [W11 W12; 0 W22] with
     // W12 = -W11 (U12 W22), neighbouring s-blocks per level, s = CB, 2 CB, ...
+    // All pairs of a level (pair p at columns 2 p s; the last one may be
+    // narrower, min(s, d - 2 p s - s)) go in one batched launch per product,
+    // each with its own s x s slice of tmp: ceil((d - s) / 2s) s^2 < d^2
+    // elements.
     for (int64_t s = CB; s < d; s *= 2) {
-        for (int64_t a = 0; a + s < d; a += 2 * s) {
-            const int64_t s2 = std::min<int64_t>(s, d - a - s);
-            const int64_t b = a + s;
-            e = gemm_f64(st, s, s2, s2, 1.0, U + a * ld + b, 0, ld, 1, W + b * ld + b, 0, ld, 1, 0.0, tmp, s2, 0,
-                         work, work_elems);
-            if (e != hipSuccess) return e;
-            e = gemm_f64(st, s, s2, s, -1.0, W + a * ld + a, 0, ld, 1, tmp, 0, s2, 1, 0.0, W + a * ld + b, ld, 0,
-                         work, work_elems);
-            if (e != hipSuccess) return e;
-        }
+        const int64_t pairs = ceil_div(d - s, 2 * s);
+        const int64_t s2 = std::min<int64_t>(s, d - (pairs - 1) * 2 * s - s);   // last pair's width, in (0, s]
+        const int64_t nl = s2 < s ? s2 : 0;
+        const int64_t step = 2 * s * (ld + 1);   // from pair p to pair p + 1 along the diagonal
+        e = gemm_f64_batched(st, pairs, s, s, s, 1.0, U + s, ld, 1, step, W + s * ld + s, ld, 1, step, 0.0, tmp, s,
+                             s * s, nl, nl, work, work_elems);
+        if (e != hipSuccess) return e;
+        e = gemm_f64_batched(st, pairs, s, s, s, -1.0, W, ld, 1, step, tmp, s, 1, s * s, 0.0, W + s, ld, step, nl,
+                             0, work, work_elems);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

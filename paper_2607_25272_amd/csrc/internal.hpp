@@ -236,6 +236,13 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
                     int a_f32, int64_t sai, int64_t sal, const void* B, int b_f32, int64_t sbl,
                     int64_t sbj, double beta, double* C, int64_t ldc, int upper, double* work,
                     int64_t work_elems);
+// `batch` FP64 products of one shape in one launch: entry z reads A + z bsa
+// and B + z bsb and writes C + z bsc (bsc != 0); the last entry has N = n_last
+// and K = k_last where those are > 0.  No split-K unless batch = 1.
+hipError_t gemm_f64_batched(hipStream_t st, int64_t batch, int64_t M, int64_t N, int64_t K, double alpha,
+                            const double* A, int64_t sai, int64_t sal, int64_t bsa, const double* B,
+                            int64_t sbl, int64_t sbj, int64_t bsb, double beta, double* C, int64_t ldc,
+                            int64_t bsc, int64_t n_last, int64_t k_last, double* work, int64_t work_elems);
 // In-place upper Cholesky G = U^T U (row-major d x d, ld; the upper part
 // of G is read); lower part zeroed; the inverses of the 64 x 64 diagonal
 // blocks of U go to the same positions of W (d x d, ld).  One fused launch
@@ -245,8 +252,8 @@ hipError_t cholesky_upper(hipStream_t st, double* G, int64_t d, int64_t ld, Dens
 // W = U^{-1} (d x d, ld) for upper-triangular U: diagonal-block inverses
 // (taken from diag_inv, same layout, when given; computed otherwise), then
 // block recursive doubling W12 = -W11 U12 W22 over 64, 128, ... column
-// blocks.  tmp: d * d / 4 doubles; work: split-K workspace (as for
-// gemm_f64, may be null).
+// blocks, all pairs of a level in one batched launch per product.  tmp: d * d
+// doubles; work: split-K workspace (as for gemm_f64, may be null).
 hipError_t tri_inverse_upper(hipStream_t st, const double* U, int64_t d, int64_t ld, double* W,
                              const double* diag_inv, double* tmp, double* work, int64_t work_elems);
 // Inverses of the 64 x 64 diagonal blocks of an upper-triangular U into W.
