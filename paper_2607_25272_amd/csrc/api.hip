@@ -194,15 +194,17 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
     sk->pB = tot ? bB.p : nullptr;
     sk->pBY = tot ? bBY.as<double>() : nullptr;
     sk->pBh = bBh.p;
-    HIP_TRY(ctx, ctx->tables.ensure((size_t)2 * Np * sizeof(int32_t)));
+    // bucket tables, then the round tables of their two bijections
+    HIP_TRY(ctx, ctx->tables.ensure(((size_t)2 * Np + 2 * (size_t)feistel_table_size(sk->L)) * sizeof(int32_t)));
     int32_t* tbl = ctx->tables.as<int32_t>();
     int32_t* tbl_hat = tbl + Np;
+    uint32_t* rt = reinterpret_cast<uint32_t*>(tbl + 2 * Np);
     // scratch (grown before any launch below uses it): the FP32 working copy
     // of the stage folds and the segment partials of S_hat
     const size_t seg_bytes = (size_t)64 * sk->r * ld * dtype_bytes(sk->dtype);
     HIP_TRY(ctx, ctx->zbuf.ensure(std::max(seg_bytes, K ? (size_t)sk->m[K - 1] * ld * 4 : (size_t)0)));
     hipStream_t st = ctx->stream;
-    HIP_TRY(ctx, launch_cs_tables(st, sk->seed, sk->L, K ? tbl : nullptr, tbl_hat));
+    HIP_TRY(ctx, launch_cs_tables(st, sk->seed, sk->L, K ? tbl : nullptr, tbl_hat, rt));
     CsJob j{};
     j.x = X->data;
     j.in_dtype = X->dtype;
@@ -355,26 +357,29 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     sk->pBY = mK ? bBY.as<double>() : nullptr;
     sk->pBh = bBh.p;
     // randomness tables and transform scratch (always context workspace)
-    HIP_TRY(ctx, ctx->tables.ensure((size_t)3 * Np * sizeof(int32_t)));
+    // randomness tables, then the round tables of the three Feistel streams
+    HIP_TRY(ctx, ctx->tables.ensure(((size_t)3 * Np + 3 * (size_t)feistel_table_size(L)) * sizeof(int32_t)));
     int32_t* perm_sign = ctx->tables.as<int32_t>();
     int32_t* inv_slot = perm_sign + Np;
     int32_t* inv_hat = perm_sign + 2 * Np;
+    uint32_t* rt = reinterpret_cast<uint32_t*>(perm_sign + 3 * Np);
     const size_t zx = (size_t)Np * sk->ld * es;
     const size_t zy = (size_t)Np * sk->ldy * 8;
     HIP_TRY(ctx, ctx->zbuf.ensure(std::max(zx, zy)));
     hipStream_t st = ctx->stream;
-    // the permutation first; the output-slot tables (only the last pass
-    // needs them) on the side stream, overlapping the first pass's memory
-    // traffic with their Feistel arithmetic
+    // the round tables of the three Feistel streams (one launch) and the
+    // permutation first; the output-slot tables (only the last pass needs
+    // them) on the side stream, beside the first pass
     if (!ctx->side) {
         HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_fork, hipEventDisableTiming));
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_join, hipEventDisableTiming));
     }
+    HIP_TRY(ctx, launch_sketch_round_tables(st, sk->seed, L, rt));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
-    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, nullptr, nullptr));
+    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, nullptr, nullptr, rt));
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_side_fork, 0));
-    HIP_TRY(ctx, launch_sketch_tables(ctx->side, sk->seed, L, mK, r, nullptr, mK ? inv_slot : nullptr, inv_hat));
+    HIP_TRY(ctx, launch_sketch_tables(ctx->side, sk->seed, L, mK, r, nullptr, mK ? inv_slot : nullptr, inv_hat, rt));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_join, ctx->side));
     FwhtJob jx{};
     jx.x = X->data;

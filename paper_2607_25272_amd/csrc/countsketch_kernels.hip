@@ -27,15 +27,16 @@ namespace {
 constexpr int CS_WAVES = 4;     // waves per block
 constexpr int CS_MU = 4;        // member rows in flight per wave
 
-__global__ void cs_tables_kernel(uint64_t seed, int L, int64_t np, int32_t* tbl, int32_t* tbl_hat) {
+__global__ void cs_tables_kernel(uint64_t seed, int L, int64_t np, int32_t* tbl, int32_t* tbl_hat,
+                                 const uint32_t* rt, const uint32_t* rt_hat) {
     const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= np) return;
     if (tbl) {
-        const uint64_t k = feistel_inv((uint64_t)y, L, seed, STREAM_CS);
+        const uint64_t k = feistel_inv_tab((uint32_t)y, L, rt);
         tbl[y] = (int32_t)((uint32_t)k | (sign_bit(seed, k) << 31));
     }
     if (tbl_hat) {
-        const uint64_t k = feistel_inv((uint64_t)y, L, seed, STREAM_CS_HAT);
+        const uint64_t k = feistel_inv_tab((uint32_t)y, L, rt_hat);
         tbl_hat[y] = (int32_t)((uint32_t)k | (sign_bit_stream(seed, k, STREAM_CS_HAT_SIGN) << 31));
     }
 }
@@ -394,9 +395,13 @@ int lanes_per_bucket(int64_t ld, int64_t k) {
 
 }  // namespace
 
-hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat) {
-    const int64_t np = 1ll << L;
-    cs_tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, tbl, tbl_hat);
+hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat, uint32_t* rt) {
+    if (L < 1 || L > 30 || !rt) return hipErrorInvalidValue;
+    const int64_t np = 1ll << L, ts = feistel_table_size(L);
+    const uint64_t streams[2] = {STREAM_CS, STREAM_CS_HAT};
+    const hipError_t e = launch_feistel_tables(st, seed, L, 2, streams, rt);
+    if (e != hipSuccess) return e;
+    cs_tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, tbl, tbl_hat, rt, rt + ts);
     return hipGetLastError();
 }
 

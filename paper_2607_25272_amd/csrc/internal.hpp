@@ -15,8 +15,16 @@ namespace spcg {
 //   perm_sign[k] = p(k) | (sign_bit(k) << 31)
 //   inv_slot[k]  = pi^{-1}(k)     if < mK, else -1
 //   inv_hat[k]   = pi_hat^{-1}(k) if < r,  else -1
+// rt: the round tables of the p, pi and pi_hat streams (written by
+// launch_sketch_round_tables before).  1 <= L <= 30.
 hipError_t launch_sketch_tables(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
-                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat);
+                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt);
+// Round tables of the p, pi and pi_hat streams: 3 feistel_table_size(L)
+// words, one launch.
+hipError_t launch_sketch_round_tables(hipStream_t st, uint64_t seed, int L, uint32_t* rt);
+// Round tables of n <= 3 Feistel streams, table i at rt + i
+// feistel_table_size(L); one launch.
+hipError_t launch_feistel_tables(hipStream_t st, uint64_t seed, int L, int n, const uint64_t* streams, uint32_t* rt);
 // Forward maps for export (device arrays, any may be null).
 hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
                                 int32_t* slot_rows, int32_t* hat_rows, int32_t* input_perm,
@@ -61,7 +69,9 @@ hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
 // Bucket tables for a padded size Np = 2^L: entry y holds the row k with
 // q(k) = y (q the bucket bijection) and its sign in bit 31.  Bucket b of an
 // m-bucket sketch gathers the entries y = b, b + m, b + 2m, ... < Np.
-hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat);
+// rt: workspace of 2 feistel_table_size(L) words (round tables of the two
+// bucket bijections).
+hipError_t launch_cs_tables(hipStream_t st, uint64_t seed, int L, int32_t* tbl, int32_t* tbl_hat, uint32_t* rt);
 
 struct CsJob {
     const void* x;            // N x d input rows, element type in_dtype, leading dim ldx

@@ -136,4 +136,44 @@ SPCG_HD inline uint64_t feistel_inv(uint64_t y, int L, uint64_t seed, uint64_t s
     return (l << b) | r;
 }
 
+// Table form of the same network.  Round j only ever sees one half of the
+// word, a value below 2^ceil(L/2), so its round function can be tabulated:
+// entry (j, h) = F_j(h) masked to round j's output width (ceil(L/2) bits for
+// even j, floor(L/2) for odd j; the mask both directions apply).  With the
+// table, pi and pi^{-1} cost six lookups instead of six Philox calls.
+SPCG_HD inline int64_t feistel_table_size(int L) { return (int64_t)FEISTEL_ROUNDS << ((L + 1) / 2); }
+
+SPCG_HD inline uint32_t feistel_table_entry(int64_t e, int L, uint64_t seed, uint64_t stream) {
+    const int a = (L + 1) / 2, b = L - a;
+    const int j = (int)(e >> a);
+    const uint64_t h = (uint64_t)e & low_mask(a);
+    return (uint32_t)(feistel_round(h, j, L, seed, stream) & low_mask((j & 1) ? b : a));
+}
+
+// pi(x) on [0, 2^L), L <= 30, from the stream's round table
+SPCG_HD inline uint32_t feistel_fwd_tab(uint32_t x, int L, const uint32_t* rt) {
+    const int a = (L + 1) / 2, b = L - a;
+    uint32_t l = x >> b, r = x & (uint32_t)low_mask(b);
+#pragma unroll
+    for (int j = 0; j < FEISTEL_ROUNDS; ++j) {
+        const uint32_t nr = l ^ rt[((int64_t)j << a) + r];
+        l = r;
+        r = nr;
+    }
+    return (l << b) | r;
+}
+
+// pi^{-1}(y) on [0, 2^L), L <= 30, from the stream's round table
+SPCG_HD inline uint32_t feistel_inv_tab(uint32_t y, int L, const uint32_t* rt) {
+    const int a = (L + 1) / 2, b = L - a;
+    uint32_t l = y >> b, r = y & (uint32_t)low_mask(b);
+#pragma unroll
+    for (int j = FEISTEL_ROUNDS - 1; j >= 0; --j) {
+        const uint32_t pl = r ^ rt[((int64_t)j << a) + l];
+        r = l;
+        l = pl;
+    }
+    return (l << b) | r;
+}
+
 }  // namespace spcg

@@ -21,22 +21,47 @@ namespace {
 
 constexpr int NB_MAX = 11;       // bits per transform pass
 
-__global__ void tables_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int64_t r,
-                              int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np) return;
-    uint64_t uk = (uint64_t)k;
+// Round-function tables of n <= 3 Feistel streams (see feistel_table_entry),
+// table i at rt + i feistel_table_size(L).
+__global__ void feistel_table_kernel(uint64_t seed, int L, int n, uint64_t s0, uint64_t s1, uint64_t s2,
+                                     uint32_t* rt) {
+    const int64_t ts = feistel_table_size(L);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * ts) return;
+    const int i = (int)(e / ts);
+    const uint64_t stream = i == 0 ? s0 : (i == 1 ? s1 : s2);
+    rt[e] = feistel_table_entry(e - i * ts, L, seed, stream);
+}
+
+// 256 threads per block: the block's rows k share k >> 8, so one Philox call
+// of the sign stream (thread 0, through LDS) gives all their signs.
+__global__ __launch_bounds__(256) void tables_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int64_t r,
+                                                     int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat,
+                                                     const uint32_t* rt_p, const uint32_t* rt_pi,
+                                                     const uint32_t* rt_pihat) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in = k < np;
     if (perm_sign) {
-        uint32_t pk = (uint32_t)feistel_fwd(uk, L, seed, STREAM_P);
-        uint32_t sb = sign_bit(seed, uk);
-        perm_sign[k] = (int32_t)(pk | (sb << 31));
+        __shared__ uint64_t sw[4];
+        if (threadIdx.x == 0) {
+            const Philox4 w = philox4x64_10((uint64_t)blockIdx.x, 0, 0, 0, seed, STREAM_SIGN);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sw[i] = w.v[i];
+        }
+        __syncthreads();
+        if (in) {
+            const uint32_t b = (uint32_t)(k & 255);
+            const uint32_t sb = (uint32_t)((sw[b >> 6] >> (b & 63)) & 1ull);
+            perm_sign[k] = (int32_t)(feistel_fwd_tab((uint32_t)k, L, rt_p) | (sb << 31));
+        }
     }
+    if (!in) return;
     if (inv_slot) {
-        int64_t t = (int64_t)feistel_inv(uk, L, seed, STREAM_PI);
+        const int64_t t = feistel_inv_tab((uint32_t)k, L, rt_pi);
         inv_slot[k] = t < mK ? (int32_t)t : -1;
     }
     if (inv_hat) {
-        int64_t t = (int64_t)feistel_inv(uk, L, seed, STREAM_PIHAT);
+        const int64_t t = feistel_inv_tab((uint32_t)k, L, rt_pihat);
         inv_hat[k] = t < r ? (int32_t)t : -1;
     }
 }
@@ -846,11 +871,25 @@ hipError_t run_passes_narrow(hipStream_t st, const FwhtJob& job) {
 
 }  // namespace
 
+hipError_t launch_feistel_tables(hipStream_t st, uint64_t seed, int L, int n, const uint64_t* streams, uint32_t* rt) {
+    if (L < 1 || L > 30 || n < 1 || n > 3) return hipErrorInvalidValue;
+    const int64_t total = n * feistel_table_size(L);
+    feistel_table_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, st>>>(seed, L, n, streams[0], n > 1 ? streams[1] : 0,
+                                                                         n > 2 ? streams[2] : 0, rt);
+    return hipGetLastError();
+}
+
+hipError_t launch_sketch_round_tables(hipStream_t st, uint64_t seed, int L, uint32_t* rt) {
+    const uint64_t streams[3] = {STREAM_P, STREAM_PI, STREAM_PIHAT};
+    return launch_feistel_tables(st, seed, L, 3, streams, rt);
+}
+
 hipError_t launch_sketch_tables(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
-                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat) {
-    int64_t np = 1ll << L;
-    tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, mK, r, perm_sign,
-                                                                inv_slot, inv_hat);
+                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt) {
+    if (L < 1 || L > 30 || !rt) return hipErrorInvalidValue;
+    const int64_t np = 1ll << L, ts = feistel_table_size(L);
+    tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, mK, r, perm_sign, inv_slot, inv_hat,
+                                                                rt, rt + ts, rt + 2 * ts);
     return hipGetLastError();
 }
 
