@@ -317,11 +317,14 @@ def test_pcg_stage_matches_oracle(S, ctx, storage, rtol):
     assert rel_pred_error(Xd, beta.cpu().numpy(), bh) < 1e-6
 
 
-@pytest.mark.parametrize("d", [20, 64, 65, 130, 200])
+@pytest.mark.parametrize("d", [20, 64, 65, 130, 200, 321, 450])
 def test_pcg_stage_exact_preconditioner_one_step(S, ctx, d):
     # M = R^{-1} R^{-T} from the exact R: one PCG step reaches the OLS
     # solution.  d = 65, 130, 200 exercise partial 64-column blocks in the
-    # recursive-doubling inverse (two and three levels)
+    # recursive-doubling inverse (two and three levels); the pairs of a
+    # level share one batched launch, whose last pair is narrower at
+    # d = 200 (8 columns at s = 64), 321 (1 column) and 450 (2 and 66
+    # columns at s = 64 and 128)
     N = 5000
     _log(f"exact preconditioner d={d}")
     p = _problem(N, d, seed=12)
