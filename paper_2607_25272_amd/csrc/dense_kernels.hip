@@ -289,8 +289,16 @@ __device__ __forceinline__ void potrf_patch(double (&a)[4][4], int nb, double (*
         // the pivot (j, j) sits in patch (jb, jb) at (JR, JR): lane 16 (jb mod 4) + jb
         const double piv = bcast_lane(a[JR][JR], (jb & 3) * 16 + jb);
         const bool bad = !(piv > 0.0) || !__builtin_isfinite(piv);
-        const double u = bad ? 1.0 : sqrt(piv);
-        const double ru = 1.0 / u;
+        // 1 / sqrt(piv) from the hardware estimate and two Newton steps,
+        // then sqrt(piv) = piv / sqrt(piv) with one Newton correction: a
+        // shorter dependent chain than a square root and a division
+        const double p1 = bad ? 1.0 : piv;
+        double y = __builtin_amdgcn_rsq(p1);
+        y = fma(0.5 * y, fma(-p1 * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-p1 * y, y, 1.0), y);
+        double u = p1 * y;
+        u = fma(fma(-u, u, p1), 0.5 * y, u);
+        const double ru = y;
         if (ty == jb) {
             double w[4];
 #pragma unroll
@@ -410,11 +418,51 @@ __device__ __forceinline__ void trtri_round(double (*T)[CB + 1], double (*Wl)[CB
     __syncthreads();
 }
 
+// The same round on the FP64 matrix cores, for SZ = 16 (two pairs) and 32
+// (one pair): each product has at most four 16 x 16 output tiles, one per
+// wave.  Per step of 4 in K, lane l feeds A[l mod 16][l / 16] and
+// B[l / 16][l mod 16] and holds D[l / 16 + 4 v][l mod 16] in register v.
+template <int SZ>
+__device__ __forceinline__ void trtri_round_mfma(double (*T)[CB + 1], double (*Wl)[CB + 1],
+                                                 double (*Tmp)[CB + 1]) {
+    constexpr int TS = SZ / 16;                   // tiles per side of a pair's block
+    constexpr int TILES = (CB / (2 * SZ)) * TS * TS;
+    static_assert(SZ % 16 == 0 && TILES <= 4, "one tile per wave");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int li = lane & 15, lk = lane >> 4;
+    const bool active = wave < TILES;             // uniform over the wave
+    const int pr = wave / (TS * TS), t = wave % (TS * TS);
+    const int ti = (t / TS) * 16, tj = (t % TS) * 16;
+    const int s0 = pr * 2 * SZ, s1 = s0 + SZ;
+    if (active) {   // Tmp = U12 W22
+        gemm_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < SZ; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[s0 + ti + li][s1 + k0 + lk], Wl[s1 + k0 + lk][s1 + tj + li],
+                                                       acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tmp[s0 + ti + lk + 4 * v][s1 + tj + li] = acc[v];
+    }
+    __syncthreads();
+    if (active) {   // W12 = -W11 Tmp
+        gemm_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k0 = 0; k0 < SZ; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[s0 + ti + li][s0 + k0 + lk], Tmp[s0 + k0 + lk][s1 + tj + li],
+                                                       acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Wl[s0 + ti + lk + 4 * v][s1 + tj + li] = -acc[v];
+    }
+    __syncthreads();
+}
+
 // Inverse of the upper-triangular CB x CB block in T (identity past the
 // used size) into Wl, by recursive doubling in LDS: invert the eight 8 x 8
 // diagonal blocks by back substitution, then for s = 8, 16, 32 combine
-// neighbouring s x s inverses with W12 = -W11 U12 W22.  Tmp is scratch.
-// Expects T complete (caller synchronizes); Wl is complete on return.
+// neighbouring s x s inverses with W12 = -W11 U12 W22 (s = 16, 32 on the
+// matrix cores).  Tmp is scratch.  Expects T complete (caller synchronizes);
+// Wl is complete on return.
 __device__ __forceinline__ void trtri_lds(double (*T)[CB + 1], double (*Wl)[CB + 1], double (*Tmp)[CB + 1]) {
     static_assert(CB == 64, "three doubling rounds");
     const int tid = threadIdx.x;
@@ -435,8 +483,8 @@ __device__ __forceinline__ void trtri_lds(double (*T)[CB + 1], double (*Wl)[CB +
     }
     __syncthreads();
     trtri_round<8>(T, Wl, Tmp);
-    trtri_round<16>(T, Wl, Tmp);
-    trtri_round<32>(T, Wl, Tmp);
+    trtri_round_mfma<16>(T, Wl, Tmp);
+    trtri_round_mfma<32>(T, Wl, Tmp);
 }
 
 // Inverses of CB x CB diagonal blocks of an upper-triangular U, starting at
