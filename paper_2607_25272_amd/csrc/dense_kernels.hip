@@ -498,12 +498,20 @@ __global__ __launch_bounds__(256) void trtri_blocks_kernel(const double* U, int6
     const int tid = threadIdx.x;
     const int64_t k0 = (first + (int64_t)blockIdx.x) * CB;
     const int nb = (int)min((int64_t)CB, d - k0);
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e >> 6, j = e & 63;
-        double v;
-        if (i < nb && j < nb) v = (j >= i) ? U[(k0 + i) * ld + k0 + j] : 0.0;
-        else v = (i == j) ? 1.0 : 0.0;
-        T[i][j] = v;
+    {
+        constexpr int NQ = CB * CB / 256;
+        double v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {   // all loads in flight first
+            const int e = tid + q * 256, i = e >> 6, j = e & 63;
+            if (i < nb && j < nb) v[q] = (j >= i) ? U[(k0 + i) * ld + k0 + j] : 0.0;
+            else v[q] = (i == j) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * 256;
+            T[e >> 6][e & 63] = v[q];
+        }
     }
     __syncthreads();
     trtri_lds(T, Wl, Tmp);
@@ -595,11 +603,25 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
     const bool diag = ti == tj;
     const int64_t i0 = k1 + ti * CB, j0 = k1 + tj * CB;
     const int ni = (int)min((int64_t)CB, d - i0), nj = (int)min((int64_t)CB, d - j0);
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        S0[r][c] = c >= r ? Wd[(k0 + r) * ld + k0 + c] : 0.0;
-        S1[r][c] = c < ni ? G[(k0 + r) * ld + i0 + c] : 0.0;
-        if (!diag) S2[r][c] = c < nj ? G[(k0 + r) * ld + j0 + c] : 0.0;
+    // every global load is issued before the first LDS store (a rolled
+    // load-store loop would wait for each load in turn)
+    {
+        constexpr int NQ = CB * CB / 256;
+        double l0[NQ], l1[NQ], l2[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * 256, r = e >> 6, c = e & 63;
+            l0[q] = c >= r ? Wd[(k0 + r) * ld + k0 + c] : 0.0;
+            l1[q] = c < ni ? G[(k0 + r) * ld + i0 + c] : 0.0;
+            l2[q] = (!diag && c < nj) ? G[(k0 + r) * ld + j0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * 256, r = e >> 6, c = e & 63;
+            S0[r][c] = l0[q];
+            S1[r][c] = l1[q];
+            if (!diag) S2[r][c] = l2[q];
+        }
     }
     __syncthreads();
     // P = W_kk^T A: P[r][c] = sum_{l <= r} W[l][r] A[l][c]
@@ -611,6 +633,7 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
             pi[r][c] = 0.0;
             pj[r][c] = 0.0;
         }
+#pragma unroll 8
     for (int l = 0; l < CB; ++l) {
         double wv[4], av[4], bv[4];
 #pragma unroll
@@ -657,6 +680,7 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
             const int i = ty * 4 + r, j = tx * 4 + c;
             acc[r][c] = (i < ni && j < nj) ? G[(i0 + i) * ld + j0 + j] : 0.0;
         }
+#pragma unroll 8
     for (int l = 0; l < CB; ++l) {
         double pv[4], qv[4];
 #pragma unroll
