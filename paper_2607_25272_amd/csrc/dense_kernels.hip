@@ -604,7 +604,17 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
     const int64_t i0 = k1 + ti * CB, j0 = k1 + tj * CB;
     const int ni = (int)min((int64_t)CB, d - i0), nj = (int)min((int64_t)CB, d - j0);
     // every global load is issued before the first LDS store (a rolled
-    // load-store loop would wait for each load in turn)
+    // load-store loop would wait for each load in turn), the trailing tile
+    // G[ti, tj] included: no block of this step writes it (the kept row
+    // panels go to panel k's columns)
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ty * 4 + r, j = tx * 4 + c;
+            acc[r][c] = (i < ni && j < nj) ? G[(i0 + i) * ld + j0 + j] : 0.0;
+        }
     {
         constexpr int NQ = CB * CB / 256;
         double l0[NQ], l1[NQ], l2[NQ];
@@ -633,24 +643,32 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
             pi[r][c] = 0.0;
             pj[r][c] = 0.0;
         }
+    // diagonal pairs (ti = tj, the critical block among them) form P_i only
+    auto panel = [&](auto both_c) __attribute__((always_inline)) {
+        constexpr bool BOTH = decltype(both_c)::value;
 #pragma unroll 8
-    for (int l = 0; l < CB; ++l) {
-        double wv[4], av[4], bv[4];
+        for (int l = 0; l < CB; ++l) {
+            double wv[4], av[4], bv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) wv[r] = S0[l][ty * 4 + r];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            av[c] = S1[l][tx * 4 + c];
-            bv[c] = diag ? 0.0 : S2[l][tx * 4 + c];
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r) wv[r] = S0[l][ty * 4 + r];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                pi[r][c] = fma(wv[r], av[c], pi[r][c]);
-                pj[r][c] = fma(wv[r], bv[c], pj[r][c]);
+                av[c] = S1[l][tx * 4 + c];
+                bv[c] = BOTH ? S2[l][tx * 4 + c] : 0.0;
             }
-    }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    pi[r][c] = fma(wv[r], av[c], pi[r][c]);
+                    if constexpr (BOTH) pj[r][c] = fma(wv[r], bv[c], pj[r][c]);
+                }
+        }
+    };
+    if (diag)
+        panel(std::false_type{});
+    else
+        panel(std::true_type{});
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -672,14 +690,6 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* G, int64_t d, in
     __syncthreads();
     // trailing update of this tile: G[ti, tj] -= P_i^T P_j
     const double (*Pj)[CB + 1] = diag ? S1 : S2;
-    double acc[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = ty * 4 + r, j = tx * 4 + c;
-            acc[r][c] = (i < ni && j < nj) ? G[(i0 + i) * ld + j0 + j] : 0.0;
-        }
 #pragma unroll 8
     for (int l = 0; l < CB; ++l) {
         double pv[4], qv[4];
