@@ -637,8 +637,10 @@ __device__ void colwise_dot(const double* a, const double* b, int64_t ldv, int d
                             double (*red)[KP + 1]) {
     const int c = threadIdx.x % KP, q = threadIdx.x / KP;   // 16 lanes per column
     double t = 0.0;
-    if (c < k)
+    if (c < k) {
+#pragma unroll 8
         for (int j = q; j < d; j += DS_THREADS / KP) t = fma(a[(int64_t)c * ldv + j], b[(int64_t)c * ldv + j], t);
+    }
     red[q][c] = t;
     __syncthreads();
     if (threadIdx.x < KP) {
@@ -662,24 +664,45 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
     const int d = pb.d, k = pb.k;
     const int64_t ldv = pb.ldv;
     const bool want_s = variant != PA_START, want_g = variant != PA_STEP;
-    // 1. reduce the task partials (fixed task order)
-    for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
-        const int j = e / KP, c = e % KP;
-        if (c >= k) continue;
-        double ss = 0.0, gg = 0.0;
-        for (int t = pb.t0; t < pb.t1; ++t) {
-            const int64_t off = (int64_t)t * MR_DMAX * KP + (int64_t)j * KP + c;
-            if (want_s) ss += (double)part_s[off];
-            if (want_g) gg += (double)part_g[off];
-        }
-        if (variant == PA_START) pb.G[c * ldv + j] = gg * pb.c2;
-        else {
-            pb.S[c * ldv + j] = ss * pb.c2;
-            if (variant == PA_REFRESH) pb.Gt[c * ldv + j] = gg * pb.c2;
+    // 1. reduce the task partials, each element in task order.  The task
+    //    loop is outside: per task, EQ elements per thread have their loads
+    //    in flight together (element-by-element it would wait out one load
+    //    latency per task and element).
+    {
+        constexpr int EQ = 16;
+        const int ne = d * KP;
+        for (int e0 = threadIdx.x; e0 < ne; e0 += EQ * DS_THREADS) {
+            double ss[EQ], gg[EQ];
+#pragma unroll
+            for (int q = 0; q < EQ; ++q) ss[q] = gg[q] = 0.0;
+            for (int t = pb.t0; t < pb.t1; ++t) {
+                const int64_t base = (int64_t)t * MR_DMAX * KP;   // element e = j KP + c of task t
+#pragma unroll
+                for (int q = 0; q < EQ; ++q) {
+                    const int e = e0 + q * DS_THREADS;
+                    if (e < ne && e % KP < k) {
+                        if (want_s) ss[q] += (double)part_s[base + e];
+                        if (want_g) gg[q] += (double)part_g[base + e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < EQ; ++q) {
+                const int e = e0 + q * DS_THREADS;
+                if (e >= ne) continue;
+                const int j = e / KP, c = e % KP;
+                if (c >= k) continue;
+                if (variant == PA_START) pb.G[c * ldv + j] = gg[q] * pb.c2;
+                else {
+                    pb.S[c * ldv + j] = ss[q] * pb.c2;
+                    if (variant == PA_REFRESH) pb.Gt[c * ldv + j] = gg[q] * pb.c2;
+                }
+            }
         }
     }
     if (want_g && threadIdx.x < KP) {
         double r2 = 0.0, ax2 = 0.0;
+#pragma unroll 8
         for (int t = pb.t0; t < pb.t1; ++t) {
             r2 += (double)part_scal[(int64_t)t * 2 * KP + threadIdx.x];
             ax2 += (double)part_scal[(int64_t)t * 2 * KP + KP + threadIdx.x];
@@ -718,6 +741,7 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
             step_sh[c] = doit;
         }
         __syncthreads();
+#pragma unroll 8
         for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
             const int j = e / KP, c = e % KP;
             if (c >= k || !step_sh[c]) continue;
@@ -731,21 +755,48 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
         pb.sc[threadIdx.x].exact = 0;
     }
     __syncthreads();
-    // 3. z = M g for every column (thread per row of M)
-    for (int i = threadIdx.x; i < d; i += DS_THREADS) {
-        double acc[KP];
+    // 3. z = M g for every column, thread per row i, j in order.  M = W W^T
+    //    is symmetric, so row i is read as column i: the lanes of a wave take
+    //    consecutive i and each load of M is one contiguous row segment.  The
+    //    k values of g at each j come from an LDS copy (loads unrolled so that
+    //    they are in flight together).
+    {
+        __shared__ double gs[MR_DMAX][KP];
+#pragma unroll 8
+        for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
+            const int j = e / KP, c = e % KP;
+            gs[j][c] = c < k ? pb.G[c * ldv + j] : 0.0;
+        }
+        __syncthreads();
+        // a thread's two rows (d <= 2 DS_THREADS) advance together, j
+        // unrolled by 8: each block streams its own d x d M from HBM, so
+        // what bounds it is how many loads are in flight
+        static_assert(MR_DMAX <= 2 * DS_THREADS, "two rows per thread");
+        const int i0 = threadIdx.x, i1 = threadIdx.x + DS_THREADS;
+        const bool h0 = i0 < d, h1 = i1 < d;
+        double a0[KP], a1[KP];
 #pragma unroll
-        for (int c = 0; c < KP; ++c) acc[c] = 0.0;
-        const double* row = pb.Minv + (int64_t)i * d;
+        for (int c = 0; c < KP; ++c) a0[c] = a1[c] = 0.0;
+#pragma unroll 8
         for (int j = 0; j < d; ++j) {
-            const double m = row[j];
+            const double* mj = pb.Minv + (int64_t)j * d;
+            const double m0 = h0 ? mj[i0] : 0.0;
+            const double m1 = h1 ? mj[i1] : 0.0;
+            // every column, without branches (g is zero past k): straight-line
+            // code lets the loads of later j issue before these FMAs
 #pragma unroll
-            for (int c = 0; c < KP; ++c)
-                if (c < k) acc[c] = fma(m, pb.G[c * ldv + j], acc[c]);
+            for (int c = 0; c < KP; ++c) {
+                const double g = gs[j][c];
+                a0[c] = fma(m0, g, a0[c]);
+                a1[c] = fma(m1, g, a1[c]);
+            }
         }
 #pragma unroll
         for (int c = 0; c < KP; ++c)
-            if (c < k) pb.Z[c * ldv + i] = acc[c];
+            if (c < k) {
+                if (h0) pb.Z[c * ldv + i0] = a0[c];
+                if (h1) pb.Z[c * ldv + i1] = a1[c];
+            }
     }
     __syncthreads();
     // 4. rho' = g^T z; p = z (start) or z + (rho'/rho) p
@@ -778,6 +829,7 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
         step_sh[c] = mode;
     }
     __syncthreads();
+#pragma unroll 8
     for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
         const int j = e / KP, c = e % KP;
         if (c >= k || step_sh[c] == 0) continue;
