@@ -824,11 +824,11 @@ hipError_t gemm_f64(hipStream_t st, int64_t M, int64_t N, int64_t K, double alph
     const int64_t ti = ceil_div(M, tt), tj = ceil_div(N, tt);
     const int64_t tiles = upper ? (ti * (ti + 1)) / 2 : ti * tj;
     // split K until there are about 512 blocks (2048 for the matrix-core
-    // tiles, several per CU, so that their k loops overlap), keeping >= 128
-    // (64 for the matrix-core tiles) per chunk
+    // tiles, several per CU, so that their k loops overlap), keeping >= 64
+    // per chunk
     const int64_t target = small ? 512 : 2048;
     int64_t nz = 1;
-    while (work && tiles * nz * 2 <= target && K / (nz * 2) >= (small ? 128 : 64) && (nz * 2) * M * N <= work_elems) nz *= 2;
+    while (work && tiles * nz * 2 <= target && K / (nz * 2) >= 64 && (nz * 2) * M * N <= work_elems) nz *= 2;
     const int64_t kchunk = round_up(ceil_div(K, nz), GK);
     nz = ceil_div(K, kchunk);
     if (nz < 1) nz = 1;
