@@ -87,6 +87,10 @@ struct spcg_ctx {
     // its first pass (created on first use)
     hipStream_t side = nullptr;
     hipEvent_t ev_side_fork = nullptr, ev_side_join = nullptr;
+    // a solve runs the response transform on the side stream too, beside
+    // the preconditioner; y_pending until the library stream waits for it
+    hipEvent_t ev_y = nullptr;
+    bool y_pending = false;
     // events for timing
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
@@ -269,9 +273,26 @@ int countsketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, spcg_
     return SPCG_OK;
 }
 
+// Order the library stream after a response transform left on the side
+// stream (host = true: wait on the host, before buffers it uses may be
+// reallocated).
+int y_join(spcg_ctx* ctx, bool host) {
+    if (!ctx->y_pending) return SPCG_OK;
+    if (host)
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev_y));
+    else
+        HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_y, 0));
+    ctx->y_pending = false;
+    return SPCG_OK;
+}
+
+// defer_y: run the response transform on the side stream and leave it
+// pending (the caller joins with y_join before reading the sketched
+// responses).
 int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_sketch_opts* o,
-                 bool borrow, spcg_sketch_t* sk) {
+                 bool borrow, spcg_sketch_t* sk, bool defer_y = false) {
     int rc;
+    if ((rc = y_join(ctx, true)) != SPCG_OK) return rc;
     if ((rc = check_mat(ctx, X, "X")) != SPCG_OK) return rc;
     const bool hat_only = o && o->hat_only;
     if (!hat_only) {
@@ -374,6 +395,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
         HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_fork, hipEventDisableTiming));
         HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_side_join, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->ev_y, hipEventDisableTiming));
     }
     HIP_TRY(ctx, launch_sketch_round_tables(st, sk->seed, L, rt));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
@@ -423,7 +445,15 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
         jy.B = sk->pBY;
         jy.ldb = sk->ldy;
         jy.narrow = sk->k == 1;
-        HIP_TRY(ctx, run_fwht(st, jy));
+        if (defer_y) {
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
+            HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_side_fork, 0));
+            HIP_TRY(ctx, run_fwht(ctx->side, jy));
+            HIP_TRY(ctx, hipEventRecord(ctx->ev_y, ctx->side));
+            ctx->y_pending = true;
+        } else {
+            HIP_TRY(ctx, run_fwht(st, jy));
+        }
     }
     return SPCG_OK;
 }
@@ -1479,6 +1509,7 @@ int spcg_ctx_destroy(spcg_ctx* ctx) {
     if (ctx->ev_status) (void)hipEventDestroy(ctx->ev_status);
     if (ctx->ev_side_fork) (void)hipEventDestroy(ctx->ev_side_fork);
     if (ctx->ev_side_join) (void)hipEventDestroy(ctx->ev_side_join);
+    if (ctx->ev_y) (void)hipEventDestroy(ctx->ev_y);
     delete ctx;
     return SPCG_OK;
 }
@@ -1729,10 +1760,13 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     spcg_sketch_opts so = opts->sketch;
     so.hat_only = opts->method == SPCG_METHOD_FULL_PCG ? 1 : 0;
     spcg_sketch_t sk;
-    if ((rc = sketch_build(ctx, X, Y, &so, true, &sk)) != SPCG_OK) return rc;
+    // the response transform runs beside the preconditioner (which needs
+    // only S_hat X); the stages wait for it below
+    if ((rc = sketch_build(ctx, X, Y, &so, true, &sk, true)) != SPCG_OK) return rc;
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
     spcg_precond_t pc;
     if ((rc = precond_build(ctx, &sk, &opts->precond, true, &pc)) != SPCG_OK) return rc;
+    if ((rc = y_join(ctx, false)) != SPCG_OK) return rc;
     const int64_t d = X->cols;
     float* sched = nullptr;
     float host_fpre[8] = {}, host_out_pre[8] = {};
