@@ -449,7 +449,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     constexpr int VL = 4, Q = 4, R = 16, THREADS = STREAM_THREADS;
     constexpr int LPR = CW / VL;
     constexpr int ROWS = THREADS * R / LPR;
-    constexpr int NB = ROWS == 1024 ? 10 : 11;
+    constexpr int NB = __builtin_ctz(ROWS);      // bits of the pass: 9 or 10 (11 would fit too)
     constexpr int NG = (NB + Q - 1) / Q;        // register groups of the pass
     typedef typename std::conditional<FIRST, TIN, float>::type TI;   // staged element
     constexpr int IB = (int)sizeof(TI);
@@ -766,10 +766,12 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     // column width of the streaming kernel for a pass (0: one tile per block).
     // 11-bit passes would need 64-byte rows (CW = 16); with chunk-major Z the
     // tiled kernel's 128-byte rows measured faster there (2.71 against
-    // 2.88 ms at N = 2e6, d = 256), so only 10-bit passes stream
+    // 2.88 ms at N = 2e6, d = 256), so only passes of 9 and 10 bits stream
     auto stream_cw = [&](int nb, bool first) -> int {
         if (!std::is_same<TZ, float>::value) return 0;
-        const int scw = nb == 10 ? 32 : 0;
+        // 1024 x 128 B or 512 x 256 B tiles (128 KB each); 256 x 512 B tiles
+        // for 8 bits would spill registers in the first pass
+        const int scw = nb == 10 ? 32 : nb == 9 ? 64 : 0;
         if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes != 0 || job.ldz % scw != 0 ||
             (first && !xdma))
             return 0;
@@ -812,7 +814,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = launch_stream<TIN, 32>(st, a, grid, first, last);
+                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
+                                               : launch_stream<TIN, 64>(st, a, grid, first, last);
                 if (e != hipSuccess) return e;
                 lo += nb;
                 continue;

@@ -197,6 +197,26 @@ def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
     assert np.array_equal(rows[0][1], rows[1][1])
 
 
+@pytest.mark.parametrize("storage,N,d,L", [("f32", 200_001, 40, 18), ("f32", 300_001, 37, 19),
+                                           ("bf16", 150_000, 24, 18), ("fp8", 250_001, 48, 18),
+                                           ("f32", 100_001, 70, 17)])
+def test_sketch_streaming_nine_bit_passes_match_tiled(S, ctx, storage, N, d, L):
+    # 9-bit passes stream 512-row x 256-byte tiles: N' = 2^18 (9 + 9 bits,
+    # chunk-major Z), 2^19 (10 + 9: two tile widths, Z row-major; d = 37
+    # keeps the first pass on the tiled kernel) and 2^17 (9 + 8: the 8-bit
+    # pass stays tiled).  Same butterflies in the same order -> identical
+    # bits to one tile per block.
+    _log(f"sketch streaming 9-bit {storage} N={N} d={d}")
+    p = _problem(N, d, storage=storage, seed=N % 83)
+    rows = []
+    for seg in (0, 256):
+        sk = S.spcg_sketch(ctx, p.X, p.Y, seed=6, col_scale=p.col_scale, transform_segment=seg)
+        rows.append((_raw_rows(sk, len(sk.sizes) - 1), _raw_rows(sk, -1), sk.info.L))
+    assert rows[0][2] == L
+    assert np.array_equal(rows[0][0], rows[1][0])
+    assert np.array_equal(rows[0][1], rows[1][1])
+
+
 def test_sketch_streaming_transform_against_oracle(S, ctx):
     # the streaming path at N' = 2^20 against the FP64 oracle on the same
     # stored values (tolerance as for the tiled FP32 transform)
