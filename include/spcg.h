@@ -107,9 +107,10 @@ typedef struct spcg_sketch_opts {
                             may be forced for non-F64 input.  The transform and
                             the preconditioner rows S_hat X stay FP32 (FP64 for
                             F64 input); BF16 rows are rounded to nearest even. */
-    int32_t transform_segment; /* tuning: 0 = library default (10-bit passes stream
-                                  128-byte row segments through LDS in persistent
-                                  blocks); 64, 128 or 256 selects one tile per block
+    int32_t transform_segment; /* tuning: 0 = library default (10- and 9-bit passes
+                                  stream 128- or 256-byte row segments through LDS
+                                  in persistent blocks); 64, 128 or 256 selects one
+                                  tile per block
                                   with at most that many bytes per row segment.
                                   Results are bit-identical either way. */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
