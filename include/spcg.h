@@ -110,9 +110,9 @@ typedef struct spcg_sketch_opts {
     int32_t transform_segment; /* tuning: 0 = library default (10- and 9-bit passes
                                   stream 128- or 256-byte row segments through LDS
                                   in persistent blocks); 64, 128 or 256 selects one
-                                  tile per block
-                                  with at most that many bytes per row segment.
-                                  Results are bit-identical either way. */
+                                  tile per block with at most that many bytes per
+                                  row segment.  Results are bit-identical either
+                                  way. */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
     int32_t reserved; /* set to 0 */
     const int64_t* m_list; /* optional HOST array of the stage sizes m_1 < ... < m_K (replaces
