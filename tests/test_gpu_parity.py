@@ -304,6 +304,33 @@ def test_precond_rank_deficient_is_reported(S, ctx):
     assert e.value.code == S.SPCG_E_RANK
 
 
+
+def test_solve_after_failed_solve_on_same_context(S, ctx):
+    # A solve that fails in the preconditioner leaves the response transform
+    # of its sketch (run beside the preconditioner on the side stream) in
+    # flight.  The next solve on the context (a larger problem, so the
+    # transform scratch grows) waits for it first and gives the same bits as
+    # the same solve on a fresh context.
+    _log("solve after a failed solve")
+    bad = _problem(50_000, 12, seed=10, storage="f64")
+    Xb = bad.X.clone()
+    Xb[:, 5] = Xb[:, 3]
+    with pytest.raises(S.SpcgError) as e:
+        S.spcg_solve(ctx, Xb, bad.Y, seed=2, qr_passes=3)
+    assert e.value.code == S.SPCG_E_RANK
+    good = _problem(300_000, 40, cond=1e3, sigma=1.0, storage="f32", seed=11)
+    b1, st1 = S.spcg_solve(ctx, good.X, good.Y, seed=2)
+    c2 = S.Context(0)
+    try:
+        b2, _ = S.spcg_solve(c2, good.X, good.Y, seed=2)
+    finally:
+        c2.close()
+    assert st1["converged"]
+    assert torch.equal(b1, b2)
+    Xd = good.x_f64().cpu().numpy()
+    bh = ols_tsqr(Xd, good.Y.cpu().numpy()[:, 0])
+    assert rel_pred_error(Xd, b1.cpu().numpy(), bh) <= 1e-6
+
 # ------------------------------------------------------------ PCG stage
 
 @pytest.mark.parametrize("storage,rtol", [("f64", 1e-9), ("f32", 2e-3)])
