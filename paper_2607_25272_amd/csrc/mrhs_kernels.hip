@@ -628,7 +628,7 @@ namespace spcg {
 
 namespace {
 
-constexpr int DS_THREADS = 256;
+constexpr int DS_THREADS = 512;
 
 __device__ __forceinline__ bool dfinite(double v) { return __builtin_isfinite(v); }
 
@@ -768,35 +768,26 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
             gs[j][c] = c < k ? pb.G[c * ldv + j] : 0.0;
         }
         __syncthreads();
-        // a thread's two rows (d <= 2 DS_THREADS) advance together, j
-        // unrolled by 8: each block streams its own d x d M from HBM, so
-        // what bounds it is how many loads are in flight
-        static_assert(MR_DMAX <= 2 * DS_THREADS, "two rows per thread");
-        const int i0 = threadIdx.x, i1 = threadIdx.x + DS_THREADS;
-        const bool h0 = i0 < d, h1 = i1 < d;
-        double a0[KP], a1[KP];
+        // one row per thread (d <= DS_THREADS), j unrolled by 4: each block
+        // streams its own d x d M from HBM, so what bounds it is how many
+        // loads are in flight
+        static_assert(MR_DMAX <= DS_THREADS, "one row per thread");
+        const int i0 = threadIdx.x;
+        const bool h0 = i0 < d;
+        double a0[KP];
 #pragma unroll
-        for (int c = 0; c < KP; ++c) a0[c] = a1[c] = 0.0;
-#pragma unroll 8
+        for (int c = 0; c < KP; ++c) a0[c] = 0.0;
+#pragma unroll 4
         for (int j = 0; j < d; ++j) {
-            const double* mj = pb.Minv + (int64_t)j * d;
-            const double m0 = h0 ? mj[i0] : 0.0;
-            const double m1 = h1 ? mj[i1] : 0.0;
+            const double m0 = h0 ? pb.Minv[(int64_t)j * d + i0] : 0.0;
             // every column, without branches (g is zero past k): straight-line
             // code lets the loads of later j issue before these FMAs
 #pragma unroll
-            for (int c = 0; c < KP; ++c) {
-                const double g = gs[j][c];
-                a0[c] = fma(m0, g, a0[c]);
-                a1[c] = fma(m1, g, a1[c]);
-            }
+            for (int c = 0; c < KP; ++c) a0[c] = fma(m0, gs[j][c], a0[c]);
         }
 #pragma unroll
         for (int c = 0; c < KP; ++c)
-            if (c < k) {
-                if (h0) pb.Z[c * ldv + i0] = a0[c];
-                if (h1) pb.Z[c * ldv + i1] = a1[c];
-            }
+            if (c < k && h0) pb.Z[c * ldv + i0] = a0[c];
     }
     __syncthreads();
     // 4. rho' = g^T z; p = z (start) or z + (rho'/rho) p
