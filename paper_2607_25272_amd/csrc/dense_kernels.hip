@@ -149,7 +149,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 typedef double gemm_v4d __attribute__((ext_vector_type(4)));
 
 template <bool AF32, bool BF32>
-__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
+// (at least 4 waves per SIMD: 3 blocks per CU left the k-step load latency exposed)
+__global__ __launch_bounds__(256, 4) void gemm_mfma_kernel(GemmArgs g) {
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     if (g.upper && ti > tj) return;
     constexpr int NL = GT * GK / 256;   // elements per thread per operand and k step
