@@ -125,3 +125,100 @@ def test_oracle_spcg_with_size_list_and_theory_counts():
     assert info["per_rhs"][0]["a_list"] == theory_schedule(sizes, d, 0.5)
     assert info["per_rhs"][0]["T_stage1"] == sum(theory_schedule(sizes, d, 0.5))
     assert rel_pred_error(X, b, ols_householder(X, Y)) < 1e-6
+
+
+def _theorem32_recursion(e0, a_list, deltas, s, delta_ols, theta=0.25):
+    """The error recursion behind Theorem 3.2, run step by step: the stage
+    bound e_i <= theta^{a_i} e_{i-1} + (1 + theta^{a_i}) delta_i (Theorem 3.1
+    with the warm start), then the full-data stage
+    e_T <= theta^s e_{T_dagger} + (1 + theta^s) delta_OLS (second-stage lemma
+    plus the triangle inequality), each taken with equality."""
+    e = e0
+    for a, dl in zip(a_list, deltas):
+        e = theta ** a * e + (1.0 + theta ** a) * dl
+    return theta ** s * e + (1.0 + theta ** s) * delta_ols
+
+
+def test_global_bound_ols_hand_values():
+    # theta = 1/4, T = 3, e0 = 8, s = 1, C = 3, delta_OLS = 2:
+    # 8/64 + [1 + (1/4)(1 + 5)] 2 = 0.125 + 5 = 5.125
+    from oracle.theory import global_bound_ols
+    assert global_bound_ols(0.25, 3, 8.0, 1, 3.0, 2.0) == pytest.approx(5.125, rel=1e-15)
+    # s = 0: [2 + 5C/3] delta_OLS;  C = 0 recovers (1 + theta^s) delta_OLS
+    assert global_bound_ols(0.25, 0, 0.0, 0, 3.0, 1.0) == pytest.approx(7.0, rel=1e-15)
+    assert global_bound_ols(0.25, 5, 0.0, 2, 0.0, 1.0) == pytest.approx(1.0625, rel=1e-15)
+
+
+def test_global_bound_ols_dominates_the_recursion():
+    # Theorem 3.2: with a_i >= 1 and delta_i <= C delta_OLS the recursion is
+    # bounded by eq. (global-ols) for any e0, schedule and s
+    from oracle.theory import global_bound_ols
+    rng = np.random.default_rng(32)
+    for _ in range(2000):
+        K = int(rng.integers(1, 14))
+        a = [int(x) for x in rng.integers(1, 6, K)]
+        s = int(rng.integers(0, 8))
+        C = float(rng.uniform(0.1, 20))
+        dols = float(rng.uniform(0.01, 3))
+        deltas = list(rng.uniform(0, C * dols, K))
+        e0 = float(rng.uniform(0, 1e3))
+        T = sum(a) + s
+        lhs = _theorem32_recursion(e0, a, deltas, s, dols)
+        assert lhs <= global_bound_ols(0.25, T, e0, s, C, dols) * (1 + 1e-12)
+
+
+def test_global_bound_ols_is_tight_for_unit_stages():
+    # a_i = 1 and delta_i = C delta_OLS make every step of the proof an
+    # equality except the geometric tail: the gap to eq. (global-ols) is
+    # C delta_OLS theta^s (1 + theta) theta^K / (1 - theta) and vanishes as K grows
+    from oracle.theory import global_bound_ols
+    C, dols, e0 = 2.0, 1.5, 10.0
+    for s in (0, 1, 3):
+        for K in (1, 4, 30):
+            T = K + s
+            lhs = _theorem32_recursion(e0, [1] * K, [C * dols] * K, s, dols)
+            gap = C * dols * 0.25 ** s * 1.25 * 0.25 ** K / 0.75
+            assert global_bound_ols(0.25, T, e0, s, C, dols) - lhs == pytest.approx(gap, rel=1e-9, abs=1e-13)
+
+
+def test_first_stage_iterations_hand_values():
+    # proof of Theorem 3.4: a_1 = ln(q_1 / omega) / ln 4 solves theta^{a_1} q_1 = omega
+    from oracle.theory import first_stage_iterations
+    assert first_stage_iterations(2.0, 0.5) == pytest.approx(1.0, rel=1e-15)
+    assert first_stage_iterations(8.0, 0.5) == pytest.approx(2.0, rel=1e-15)
+    assert first_stage_iterations(1.0, 1.0 / 64) == pytest.approx(3.0, rel=1e-15)
+    for q1, w in ((1.7, 0.3), (5.0, 0.05), (1.01, 0.9)):
+        a1 = first_stage_iterations(q1, w)
+        assert 0.25 ** a1 * q1 == pytest.approx(w, rel=1e-13)
+
+
+def test_first_stage_iterations_bracketed_as_theorem_3_4_states():
+    # 1 < q_1 < 1 + (1 + omega) r_bar implies ln(1/omega)/ln 4 < a_1 < alpha
+    from oracle.theory import alpha_bound, first_stage_iterations, stage_ratio
+    d = 64
+    for m1 in (512, 1024, 4096):
+        rbar = stage_ratio(m1, 2 * m1, d)
+        for w in (0.0625, 0.25, 0.5, 0.9):
+            lo = math.log(1.0 / w) / math.log(4.0)
+            hi = alpha_bound(m1, 2 * m1, d, w)
+            for q1 in np.linspace(1.0, 1.0 + (1.0 + w) * rbar, 12)[1:-1]:
+                a1 = first_stage_iterations(q1, w)
+                assert lo < a1 < hi
+
+
+def test_complexity_second_stage_term():
+    # proof of Theorem 3.4: T = ln(1/sigma)/ln 4 total iterations minus
+    # K ln(1/omega)/ln 4 in Stage I leaves ln(omega^K/sigma)/ln 4 full-data
+    # iterations of 4 N d FLOPs each.  omega = 1/2, sigma = 4^-10, K = 4:
+    # ln(2^16)/ln 4 = 8 iterations, i.e. 32 N d
+    N, d = 1 << 16, 8
+    t = complexity_terms(N, d, 0.5, 4.0 ** -10, 4, 128, 256)
+    assert t["stage2"] == pytest.approx(32 * N * d, rel=1e-12)
+    for K, w, sg in ((3, 0.3, 1e-6), (8, 0.7, 1e-9)):
+        t = complexity_terms(N, d, w, sg, K, 128, 256)
+        T = math.log(1 / sg) / math.log(4)
+        assert t["stage2"] / (4 * N * d) == pytest.approx(T - K * math.log(1 / w) / math.log(4), rel=1e-12)
+    # positive exactly when omega > sigma^(1/K)
+    sg, K = 1e-4, 4
+    assert complexity_terms(N, d, sg ** (1 / K) * 1.01, sg, K, 128, 256)["stage2"] > 0
+    assert complexity_terms(N, d, sg ** (1 / K) * 0.99, sg, K, 128, 256)["stage2"] < 0
