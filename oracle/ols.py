@@ -28,19 +28,36 @@ def ols_householder(X, Y):
     return beta if Y.ndim == 2 else beta[:, 0]
 
 
-def tsqr_r(blocks):
-    """R factor of the row-stacked blocks (each n_b x c, float64)."""
-    Rs = []
-    for blk in blocks:
-        blk = np.asarray(blk, dtype=np.float64)
-        if blk.shape[0] == 0:
-            continue
-        Rs.append(np.linalg.qr(blk, mode="r"))
+def _block_r(blk):
+    blk = np.asarray(blk, dtype=np.float64)
+    return None if blk.shape[0] == 0 else np.linalg.qr(blk, mode="r")
+
+
+def tsqr_r(blocks, workers=1):
+    """R factor of the row-stacked blocks (each n_b x c, float64).
+
+    The blocks are factored independently and their R factors stacked in
+    block order and factored again.  With ``workers`` > 1 the block
+    factorizations run concurrently on that many threads (one BLAS thread
+    each); the stacked order, and so the result, is unchanged."""
+    if workers <= 1:
+        Rs = [_block_r(b) for b in blocks]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        from threadpoolctl import threadpool_limits
+        Rs, pending = [], []
+        with threadpool_limits(1), ThreadPoolExecutor(max_workers=workers) as ex:
+            for b in blocks:
+                pending.append(ex.submit(_block_r, b))
+                if len(pending) >= 2 * workers:      # bound the blocks in flight
+                    Rs.append(pending.pop(0).result())
+            Rs.extend(f.result() for f in pending)
+    Rs = [R for R in Rs if R is not None]
     R = np.linalg.qr(np.concatenate(Rs, axis=0), mode="r")
     return R
 
 
-def ols_tsqr(X, Y, block=65536):
+def ols_tsqr(X, Y, block=65536, workers=1):
     """OLS via TSQR of [X | Y] over row blocks of ``block`` rows."""
     X = np.asarray(X)
     Y = np.asarray(Y)
@@ -52,7 +69,7 @@ def ols_tsqr(X, Y, block=65536):
             yield np.concatenate([np.asarray(X[i:i + block], dtype=np.float64),
                                   np.asarray(Y2[i:i + block], dtype=np.float64)], axis=1)
 
-    Ra = tsqr_r(blocks())
+    Ra = tsqr_r(blocks(), workers)
     return ols_from_r(Ra, d, Y.ndim == 2)
 
 

@@ -105,3 +105,39 @@ def nested_srht(X, Y, seed, m_K, r):
     pih = hat_slot_rows(seed, L, r)
     info = {"L": L, "Np": Np, "pi": pi, "pi_hat": pih}
     return ZX[pi], ZY[pi], ZX[pih], info
+
+
+class SrhtRowAccumulator:
+    """Selected rows of Z = H_un D P X-tilde, accumulated over row blocks of X.
+
+    Row i of Z is sum_k (-1)^{popcount(i & k)} sign(k) X-tilde[p(k)]
+    (Sec. 2.1 with the unnormalised Sylvester H_un, H_un[i, k] =
+    (-1)^{popcount(i & k)}).  Substituting n = p(k) lets X be read block by
+    block in its own row order: row n contributes with k = p^{-1}(n).
+    Padded rows are zero and contribute nothing."""
+
+    def __init__(self, rows, seed, L):
+        self.rows = np.asarray(rows, dtype=np.int64)
+        self.seed, self.L = seed, L
+        p = input_perm(seed, L)
+        self.pinv = np.empty_like(p)
+        self.pinv[p] = np.arange(p.size, dtype=np.int64)
+        self.value = None
+
+    def add(self, n0, Xb):
+        """Adds the contribution of the float64 rows n0 .. n0 + len(Xb) - 1."""
+        Xb = np.asarray(Xb, dtype=np.float64)
+        k = self.pinv[n0:n0 + Xb.shape[0]]
+        sg = sign_vector(self.seed, self.L, rows=k)
+        par = np.bitwise_count(self.rows[:, None] & k[None, :]) & 1
+        part = ((1.0 - 2.0 * par) * sg[None, :]) @ Xb
+        self.value = part if self.value is None else self.value + part
+
+
+def srht_rows_streamed(blocks, rows, seed, L):
+    """Rows ``rows`` of Z = H_un D P X-tilde from the blocks (n0, Xb) of X
+    (see SrhtRowAccumulator).  Returns len(rows) x c."""
+    acc = SrhtRowAccumulator(rows, seed, L)
+    for n0, Xb in blocks:
+        acc.add(n0, Xb)
+    return acc.value

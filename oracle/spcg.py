@@ -19,6 +19,8 @@ Readings (where the paper leaves a choice open):
   ``countsketch`` replaces the SRHT for both the stage sketches and S-hat;
   its rows need no scaling (c^2 = 1, H-hat = (S-hat X)^T (S-hat X)).
 """
+import time
+
 import numpy as np
 
 from .countsketch import countsketch, nested_countsketch
@@ -52,20 +54,23 @@ def _stage_problems(X, Y, seed, sizes, r, sketch):
     Y2 = Y if Y.ndim == 2 else Y[:, None]
     if sketch == "cs":
         stages, B_hat = nested_countsketch(X, Y2, seed, sizes, r)
+        t_sk = time.perf_counter()
         probs = [(A, b, 1.0) for A, b in stages]
         R = precond_from_sketch(B_hat, scaled=False)
         L, Np = padded_bits(X.shape[0])
-        return probs, R, {"L": L, "Np": Np}
+        return probs, R, {"L": L, "Np": Np}, t_sk
     if sketch != "srht":
         raise ValueError("sketch must be 'srht' or 'cs'")
     mK = sizes[-1] if sizes else 1
     B, BY, B_hat, sk = nested_srht(X, Y2, seed, mK, r)
+    t_sk = time.perf_counter()
     probs = [(B[:m], BY[:m], 1.0 / m) for m in sizes]
-    return probs, precond_from_sketch(B_hat), sk
+    return probs, precond_from_sketch(B_hat), sk, t_sk
 
 
 def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
-         growth=2, history=False, sketch="srht", sizes=None, nested_gradient=False):
+         growth=2, history=False, sketch="srht", sizes=None, nested_gradient=False,
+         timings=None):
     """Algorithm 1.  Returns (beta_T, info) for Y of shape (N,) or (N, k).
     ``sizes`` gives the stage sizes explicitly (e.g. the tuned schedule of
     Sec. 4.3); ``a`` may be a number, a per-stage list, or ("theory", omega)
@@ -74,7 +79,12 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
     ``nested_gradient`` (SRHT only): the sketches are nested prefixes
     (Sec. 2.2), so with c2_i = 1/m_i the stage-(i+1) starting gradient is
     (m_i/m_{i+1}) g_i(x) + c2_{i+1} dA^T (db - dA x) over the new rows
-    dA = rows m_i..m_{i+1} only, g_i the previous stage's final gradient."""
+    dA = rows m_i..m_{i+1} only, g_i the previous stage's final gradient.
+
+    ``timings`` (a dict, optional) receives the wall-clock seconds of the
+    sketch, the preconditioner, Stage I and Stage II (instrumentation only)."""
+    clock = time.perf_counter
+    t0 = clock()
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     N, d = X.shape
@@ -84,7 +94,8 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
         a_list = theory_schedule(sizes, d, a[1])
     else:
         a_list = [a] * len(sizes) if np.isscalar(a) else list(a)
-    probs, R, sk = _stage_problems(X, Y, seed, sizes, r, sketch)
+    probs, R, sk, t_sketch = _stage_problems(X, Y, seed, sizes, r, sketch)
+    t1 = t_pc = clock()
     multi = Y.ndim == 2
     Ys = Y if multi else Y[:, None]
     betas, infos = [], []
@@ -104,12 +115,21 @@ def spcg(X, Y, seed, m0=None, m_max=None, r=None, a=3, tol=5e-7, T=100,
             g_prev, m_prev = inf1["g"], A.shape[0]
             t += ai
             stage_x.append(x.copy())
+        t_s1 = clock()
         x, inf2 = pcg(X, Ys[:, c], 1.0, R, x, max(T - t, 0), tol=tol, history=history)
+        t_s2 = clock()
+        if timings is not None:
+            timings["stage1"] = timings.get("stage1", 0.0) + (t_s1 - t1)
+            timings["stage2"] = timings.get("stage2", 0.0) + (t_s2 - t_s1)
+            t1 = t_s2
         betas.append(x)
         infos.append({"stage_x": stage_x, "stage2": inf2, "T_stage1": t,
                       "T": t + inf2["iters"], "a_list": a_list})
     beta = np.stack(betas, axis=1) if multi else betas[0]
     info = {"sizes": sizes, "R": R, "per_rhs": infos, "L": sk["L"], "Np": sk["Np"]}
+    if timings is not None:
+        timings["sketch"] = t_sketch - t0
+        timings["precond"] = t_pc - t_sketch
     return beta, info
 
 

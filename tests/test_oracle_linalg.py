@@ -61,3 +61,21 @@ def test_ols_exact_on_hadamard_columns():
     Y = rng.integers(-100, 100, size=1 << L).astype(np.float64)
     exact = X.T @ Y / (1 << L)
     np.testing.assert_allclose(ols_householder(X, Y), exact, rtol=0, atol=1e-12)
+
+
+def test_tsqr_concurrent_blocks_equal_sequential():
+    # the block factorizations are independent: running them on threads
+    # leaves the stacked order and so the R factor unchanged, and beta
+    # agrees with LAPACK's least squares
+    from oracle.ols import ols_tsqr, tsqr_r
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((9000, 12)) * np.logspace(0, 3, 12)
+    Y = X @ rng.standard_normal(12) + 0.1 * rng.standard_normal(9000)
+    A = np.concatenate([X, Y[:, None]], axis=1)
+    blocks = [A[i:i + 1000] for i in range(0, 9000, 1000)]
+    R1 = tsqr_r(iter(blocks), workers=1)
+    R4 = tsqr_r(iter(blocks), workers=4)
+    assert np.array_equal(R1, R4)
+    b = ols_tsqr(X, Y, block=700, workers=3)
+    ref = np.linalg.lstsq(X, Y, rcond=None)[0]
+    assert np.linalg.norm(X @ (b - ref)) / np.linalg.norm(X @ ref) < 1e-12

@@ -99,3 +99,20 @@ def test_nested_prefix_views():
     assert np.array_equal(B, Z[info["pi"]])
     assert np.array_equal(Bh, Z[info["pi_hat"]])
     assert B.shape == (1024, d) and BY.shape == (1024,) and Bh.shape == (48, d)
+
+
+def test_streamed_srht_rows_equal_the_dense_transform():
+    # rows of Z = H_un D P X accumulated block by block in X's own row order
+    # equal the same rows of the full transform, exactly on integer data
+    # (ragged blocks, N not a power of two)
+    from oracle.sketch import padded_bits, srht_rows_streamed, transform
+    rng = np.random.default_rng(4)
+    N, c, seed = 3000, 5, 11
+    X = rng.integers(-8, 9, size=(N, c)).astype(np.float64)
+    L, Np = padded_bits(N)
+    Z = transform(X, seed)
+    rows = rng.choice(Np, 40, replace=False)
+    bounds = [0, 1, 700, 701, 2048, 2999, N]
+    blocks = ((a, X[a:b]) for a, b in zip(bounds, bounds[1:]))
+    got = srht_rows_streamed(blocks, rows, seed, L)
+    assert np.array_equal(got, Z[rows])
