@@ -231,8 +231,14 @@ typedef struct spcg_stage_stats {
 
 /* PCG on c2 A^T A x = c2 A^T b, x = beta (DEVICE, d x k row-major FP64: in =
  * warm start, out = iterate), preconditioned by pc.  A: m x d (any element
- * type), b: m x k SPCG_F64.  stats may be NULL.
- * Returns BREAKDOWN (beta holds the last good iterate) or
+ * type), b: m x k SPCG_F64, k >= 1: the k columns are k independent PCG
+ * solves that share A.  With k > 1, FP32 or BF16 rows, d <= 512 and
+ * k <= 16, every product pass reads A once for all columns on the matrix
+ * cores (FP32 accumulation, FP64 residuals and d-space work); otherwise the
+ * columns run one after another on the single-right-hand-side kernels.  A
+ * stopping test (tol > 0) passes when it passes for every column.  stats
+ * may be NULL; it reports column 0, with iters the largest count over the
+ * columns.  Returns BREAKDOWN (beta holds the last good iterate) or
  * W_NOT_CONVERGED when tol > 0 was not met within iters. */
 int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
                    const spcg_precond_t* pc, double* beta, const spcg_stage_opts* opts,
@@ -254,7 +260,11 @@ typedef struct spcg_solve_opts {
     const int32_t* a_list;/* optional HOST array of per-stage a_i (length a_list_len) */
     int32_t a_list_len;
     int32_t time_phases;  /* 1: record phase times (adds stream syncs) */
-    int32_t time_products;/* 1: time every full-data product launch with events */
+    int32_t time_products;/* 1: time every full-data product launch with events;
+                             2: time every launch of the kernel classes SPCG_KT_*
+                             (SRHT sketch passes over X, every product pass and
+                             the d-space phases) into the stats' kernel_* fields
+                             (events around each launch: an instrumented run) */
     int32_t stage_stride; /* 1: every prefix m_1..m_K; 2: every other prefix, ending
                              at m_K, so sketch sizes grow by 4 per stage (0: 1) */
     int32_t schedule;     /* SPCG_SCHEDULE_PLAIN or SPCG_SCHEDULE_LEARNED */
@@ -332,7 +342,27 @@ typedef struct spcg_solve_stats {
     float out_ii[8];
     int32_t batch_tasks_per_cu; /* batched form: task granularity used in Stage II */
     int32_t batch_graphs;       /* batched form: executable graphs launched */
+    /* time_products = 2 (single-problem solves): per kernel class, the
+     * summed duration in ms of the timed launches, their summed algorithmic
+     * bytes (the class comments below) and their number */
+    double kernel_ms[8];
+    double kernel_bytes[8];
+    int32_t kernel_launches[8];
 } spcg_solve_stats;
+
+/* Kernel classes of spcg_solve_stats.kernel_*.  Algorithmic bytes count
+ * the d used columns of each row (not the row padding) and elem = the
+ * element size of the matrix streamed. */
+#define SPCG_KT_TRANSFORM_FIRST 0 /* first SRHT pass over X: N d elem_X (read X) + N' d z (write Z),
+                                     z = 8 for FP64 input, else 4 */
+#define SPCG_KT_TRANSFORM_REST 1  /* later passes: N' d z (read Z) + N' d z (write Z), or, for the
+                                     last pass, m_K d elem_B (write B) + r d z (write S_hat X) */
+#define SPCG_KT_PROD_S 2          /* s = c2 A^T (A p): m d elem */
+#define SPCG_KT_PROD_G 3          /* stage-start gradient: m (d elem + 8) */
+#define SPCG_KT_PROD_SG 4         /* dual pass (s and the refreshed gradient): m (d elem + 8) */
+#define SPCG_KT_PHASE_A 5         /* d-space phase A (latency-bound: no bytes counted) */
+#define SPCG_KT_PHASE_B 6         /* d-space phase B (latency-bound: no bytes counted) */
+#define SPCG_KT_N 8
 
 /* beta (DEVICE, d x k row-major FP64) <- Algorithm 1 (or full-data PCG)
  * for (X, Y).  X: N x d any element type; Y: N x k SPCG_F64 (k > 1 takes

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(_HERE, "libspcg.so")
 
 SPCG_OK = 0
 SPCG_W_NOT_CONVERGED = 1
+SPCG_KT_TRANSFORM_FIRST, SPCG_KT_TRANSFORM_REST, SPCG_KT_PROD_S, SPCG_KT_PROD_G = 0, 1, 2, 3
+SPCG_KT_PROD_SG, SPCG_KT_PHASE_A, SPCG_KT_PHASE_B, SPCG_KT_N = 4, 5, 6, 8
 SPCG_E_INVALID_ARG = -1
 SPCG_E_SHAPE = -2
 SPCG_E_DTYPE = -3
@@ -88,7 +90,8 @@ class SolveStats(ctypes.Structure):
                 ("fallback", c_i32), ("s_pred", ctypes.c_float), ("rho_ii0", c_f64),
                 ("ax2_ii0", c_f64), ("resid2_ii0", c_f64), ("features_pre", ctypes.c_float * 8),
                 ("features_ii", ctypes.c_float * 8), ("out_pre", ctypes.c_float * 8),
-                ("out_ii", ctypes.c_float * 8), ("batch_tasks_per_cu", c_i32), ("batch_graphs", c_i32)]
+                ("out_ii", ctypes.c_float * 8), ("batch_tasks_per_cu", c_i32), ("batch_graphs", c_i32),
+                ("kernel_ms", c_f64 * 8), ("kernel_bytes", c_f64 * 8), ("kernel_launches", c_i32 * 8)]
 
 
 P = ctypes.POINTER

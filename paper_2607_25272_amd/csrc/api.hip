@@ -58,6 +58,21 @@ constexpr int MAX_TIMED = 256;
 
 namespace {
 struct BatchWork;
+
+// Per-kernel-class timing of an instrumented solve (time_products = 2):
+// one start/end event pair per timed launch, recorded on the library stream.
+constexpr int KT_MAX = 2048;
+struct KTimer {
+    hipEvent_t ev[2 * KT_MAX] = {};
+    int cls[KT_MAX] = {};
+    double bytes[KT_MAX] = {};
+    int used = 0;
+    bool ready = false;
+    ~KTimer() {
+        if (ready)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+};
 }
 
 struct spcg_ctx {
@@ -70,6 +85,7 @@ struct spcg_ctx {
     DevBuf dvec;      // g z p s gt (5 * dpad) + blk (1024)
     DevBuf scal;      // PcgScalars + counters
     int64_t dvec_dpad = 0;
+    DevBuf colx;      // one column of beta (column-by-column multi-RHS stages)
     // sketch and preconditioner workspaces used by spcg_solve
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
     DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w, dense_wd, dense_tmp;
@@ -95,6 +111,8 @@ struct spcg_ctx {
     hipEvent_t ev_phase[8] = {};
     hipEvent_t ev_prod[2 * MAX_TIMED] = {};
     bool events_ready = false;
+    KTimer* kt = nullptr;   // created on the first instrumented solve
+    bool kt_on = false;     // launches are being timed by class
 };
 
 struct spcg_sketch_s {
@@ -172,6 +190,50 @@ int ensure_events(spcg_ctx* ctx) {
     for (auto& e : ctx->ev_prod) HIP_TRY(ctx, hipEventCreate(&e));
     ctx->events_ready = true;
     return SPCG_OK;
+}
+
+// A timed launch of class cls with `bytes` algorithmic bytes: *idx is its
+// record (start event already on the library stream unless `reserve`), or
+// -1 when launches are not being timed or the records are used up.
+int kt_begin(spcg_ctx* ctx, int cls, double bytes, int* idx, bool reserve = false) {
+    *idx = -1;
+    if (!ctx->kt_on || !ctx->kt || ctx->kt->used >= KT_MAX) return SPCG_OK;
+    KTimer& t = *ctx->kt;
+    const int i = t.used++;
+    t.cls[i] = cls;
+    t.bytes[i] = bytes;
+    if (!reserve) HIP_TRY(ctx, hipEventRecord(t.ev[2 * i], ctx->stream));
+    *idx = i;
+    return SPCG_OK;
+}
+int kt_end(spcg_ctx* ctx, int idx) {
+    if (idx >= 0) HIP_TRY(ctx, hipEventRecord(ctx->kt->ev[2 * idx + 1], ctx->stream));
+    return SPCG_OK;
+}
+int kt_start(spcg_ctx* ctx) {
+    if (!ctx->kt) ctx->kt = new (std::nothrow) KTimer();
+    if (!ctx->kt) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    if (!ctx->kt->ready) {
+        for (auto& e : ctx->kt->ev) HIP_TRY(ctx, hipEventCreate(&e));
+        ctx->kt->ready = true;
+    }
+    ctx->kt->used = 0;
+    ctx->kt_on = true;
+    return SPCG_OK;
+}
+// d-space phases, timed by class when an instrumented solve runs
+int phase_a(spcg_ctx* ctx, const DspaceState& S, int variant, const double* part_s, const double* part_g,
+            const double* part_scal, int nparts, int64_t dpad, double c2, double g_scale = 0.0) {
+    int rc, i;
+    if ((rc = kt_begin(ctx, SPCG_KT_PHASE_A, 0.0, &i)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_phase_a(ctx->stream, S, variant, part_s, part_g, part_scal, nparts, dpad, c2, g_scale));
+    return kt_end(ctx, i);
+}
+int phase_b(spcg_ctx* ctx, const DspaceState& S, int init) {
+    int rc, i;
+    if ((rc = kt_begin(ctx, SPCG_KT_PHASE_B, 0.0, &i)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_phase_b(ctx->stream, S, init));
+    return kt_end(ctx, i);
 }
 
 // ------------------------------------------------------------------ sketch
@@ -428,6 +490,24 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     jx.stream = 1;
     jx.num_cu = ctx->num_cu;
     jx.wait_before_last = ctx->ev_side_join;
+    if (ctx->kt_on) {
+        // algorithmic bytes of each pass (used columns only)
+        const int np = fwht_passes(L);
+        const double eX = (double)dtype_bytes(X->dtype), eB = (double)dtype_bytes(sk->bdtype);
+        const double zrow = (double)d * (double)es, outb = (double)mK * d * eB + (double)r * d * (double)es;
+        for (int pi = 0; pi < np && pi < 3; ++pi) {
+            const double in = pi == 0 ? (double)N * d * eX : (double)Np * zrow;
+            const double outp = pi == np - 1 ? outb : (double)Np * zrow;
+            int idx;
+            if ((rc = kt_begin(ctx, pi == 0 ? SPCG_KT_TRANSFORM_FIRST : SPCG_KT_TRANSFORM_REST, in + outp, &idx,
+                               true)) != SPCG_OK)
+                return rc;
+            if (idx >= 0) {
+                jx.pass_ev[2 * pi] = ctx->kt->ev[2 * idx];
+                jx.pass_ev[2 * pi + 1] = ctx->kt->ev[2 * idx + 1];
+            }
+        }
+    }
     HIP_TRY(ctx, run_fwht(st, jx));
     if (mK) {
         FwhtJob jy{};
@@ -637,7 +717,37 @@ struct StageRun {
     PcgScalars sc{};
 };
 
-int ensure_stage_ws(spcg_ctx* ctx, int64_t d, DspaceState* S, double* x, const double* Minv) {
+// Workspace of one PCG solve: the product partials (one row of dpad
+// doubles per product block) and the d-space state.  Filled from the
+// context's cached buffers (ensure_stage_ws) or from the static area of the
+// allocation-free entry point (static_stage_ws).
+struct StageWs {
+    DspaceState S{};
+    double* part_s = nullptr;
+    double* part_g = nullptr;
+    double* part_scal = nullptr;
+    int num_cu = 256;   // product launches use at most this many blocks
+};
+
+// d-vector block g z p s gt (5 dpad) + per-block scalars (1024), then the
+// PcgScalars record and its two last-block counters
+void stage_ws_layout(StageWs* W, double* v, int64_t stride, void* scal, double* x, const double* Minv,
+                     int64_t d) {
+    DspaceState& S = W->S;
+    S.x = x;
+    S.g = v;
+    S.z = v + stride;
+    S.p = v + 2 * stride;
+    S.s = v + 3 * stride;
+    S.gt = v + 4 * stride;
+    S.blk = v + 5 * stride;
+    S.sc = static_cast<PcgScalars*>(scal);
+    S.counters = reinterpret_cast<unsigned int*>(static_cast<char*>(scal) + sizeof(PcgScalars));
+    S.Minv = Minv;
+    S.d = d;
+}
+
+int ensure_stage_ws(spcg_ctx* ctx, int64_t d, StageWs* W, double* x, const double* Minv) {
     const int64_t dpad = round_up(d, 64);
     const size_t mb = (size_t)product_max_blocks(ctx->num_cu);
     HIP_TRY(ctx, ctx->part_s.ensure(mb * dpad * 8));
@@ -652,19 +762,11 @@ int ensure_stage_ws(spcg_ctx* ctx, int64_t d, DspaceState* S, double* x, const d
         HIP_TRY(ctx, run_counters_reset(ctx->stream,
                                         reinterpret_cast<unsigned int*>(ctx->scal.as<char>() + sizeof(PcgScalars)), 16));
     }
-    double* v = ctx->dvec.as<double>();
-    const int64_t stride = ctx->dvec_dpad;
-    S->x = x;
-    S->g = v;
-    S->z = v + stride;
-    S->p = v + 2 * stride;
-    S->s = v + 3 * stride;
-    S->gt = v + 4 * stride;
-    S->blk = v + 5 * stride;
-    S->sc = ctx->scal.as<PcgScalars>();
-    S->counters = reinterpret_cast<unsigned int*>(ctx->scal.as<char>() + sizeof(PcgScalars));
-    S->Minv = Minv;
-    S->d = d;
+    stage_ws_layout(W, ctx->dvec.as<double>(), ctx->dvec_dpad, ctx->scal.p, x, Minv, d);
+    W->part_s = ctx->part_s.as<double>();
+    W->part_g = ctx->part_g.as<double>();
+    W->part_scal = ctx->part_scal.as<double>();
+    W->num_cu = ctx->num_cu;
     return SPCG_OK;
 }
 
@@ -685,7 +787,7 @@ struct ProductTimer {
     int used = 0;
 };
 
-int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const DspaceState& S, int mode,
+int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const StageWs& W, int mode,
                  int* nparts, ProductTimer* timer) {
     ProdJob j{};
     j.A = A->data;
@@ -697,17 +799,24 @@ int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const Dspa
     j.col_scale = A->col_scale;
     j.b = b ? static_cast<const double*>(b->data) : nullptr;
     j.ldbv = b ? b->ld : 0;
-    j.x = S.x;
-    j.p = S.p;
+    j.x = W.S.x;
+    j.p = W.S.p;
     j.mode = mode;
-    j.part_s = ctx->part_s.as<double>();
-    j.part_g = ctx->part_g.as<double>();
-    j.part_scal = ctx->part_scal.as<double>();
+    j.part_s = W.part_s;
+    j.part_g = W.part_g;
+    j.part_scal = W.part_scal;
     j.dpad = round_up(A->cols, 64);
-    j.num_cu = ctx->num_cu;
+    j.num_cu = W.num_cu;
     const bool timed = timer && timer->used < MAX_TIMED;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], ctx->stream));
+    const double e = (double)dtype_bytes(A->dtype);
+    const double bytes = mode == PM_S ? (double)A->rows * A->cols * e : (double)A->rows * (A->cols * e + 8.0);
+    int rc, ki;
+    if ((rc = kt_begin(ctx, mode == PM_S ? SPCG_KT_PROD_S : mode == PM_G ? SPCG_KT_PROD_G : SPCG_KT_PROD_SG, bytes,
+                       &ki)) != SPCG_OK)
+        return rc;
     HIP_TRY(ctx, run_product(ctx->stream, j, nparts));
+    if ((rc = kt_end(ctx, ki)) != SPCG_OK) return rc;
     if (timed) {
         HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used + 1], ctx->stream));
         timer->used++;
@@ -733,21 +842,26 @@ struct StageHooks {
     PcgScalars start{};
 };
 
-// PCG(A, b, c2, M, x, iters) with optional stopping test; x is device memory.
+// PCG(A, b, c2, M, x, iters) with optional stopping test; x is device
+// memory.  W: a prepared workspace (the context's when null).
 int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const spcg_precond_t* pc,
               double* x, int iters, double tol, bool refresh, int check_every, StageRun* out,
-              ProductTimer* timer, StageHooks* hooks = nullptr) {
+              ProductTimer* timer, StageHooks* hooks = nullptr, const StageWs* W_in = nullptr) {
     int rc;
-    DspaceState S{};
-    if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
+    StageWs Wl;
+    if (!W_in) {
+        if ((rc = ensure_stage_ws(ctx, A->cols, &Wl, x, pc->pMinv)) != SPCG_OK) return rc;
+        W_in = &Wl;
+    }
+    const StageWs& W = *W_in;
+    const DspaceState& S = W.S;
     hipStream_t st = ctx->stream;
     const int64_t dpad = round_up(A->cols, 64);
     int np = 0;
     // stage start: g = c2 A^T (b - A x), z = M g, p = z, rho = g^T z
-    if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
-    HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
-                             np, dpad, c2));
-    HIP_TRY(ctx, run_phase_b(st, S, 1));
+    if ((rc = product_pass(ctx, A, b, W, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+    if ((rc = phase_a(ctx, S, PA_START, nullptr, W.part_g, W.part_scal, np, dpad, c2)) != SPCG_OK) return rc;
+    if ((rc = phase_b(ctx, S, 1)) != SPCG_OK) return rc;
     const bool testing = tol > 0.0;
     if (check_every < 1) check_every = 1;
     out->iters_done = 0;
@@ -780,10 +894,11 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
     }
     const int pmode = refresh ? PM_SG : PM_S;
     for (int it = 0; it < iters; ++it) {
-        if ((rc = product_pass(ctx, A, b, S, pmode, &np, timer)) != SPCG_OK) return rc;
-        HIP_TRY(ctx, run_phase_a(st, S, refresh ? PA_REFRESH : PA_STEP, ctx->part_s.as<double>(),
-                                 ctx->part_g.as<double>(), ctx->part_scal.as<double>(), np, dpad, c2));
-        HIP_TRY(ctx, run_phase_b(st, S, 0));
+        if ((rc = product_pass(ctx, A, b, W, pmode, &np, timer)) != SPCG_OK) return rc;
+        if ((rc = phase_a(ctx, S, refresh ? PA_REFRESH : PA_STEP, W.part_s, W.part_g, W.part_scal, np, dpad, c2)) !=
+            SPCG_OK)
+            return rc;
+        if ((rc = phase_b(ctx, S, 0)) != SPCG_OK) return rc;
         out->iters_done = it + 1;
         const int done = it + 1;
         if (testing && done >= unchecked && ((done - unchecked) % check_every == 0 || done == iters)) {
@@ -810,8 +925,9 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
 int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
                      const spcg_precond_t* pc, double* x, int iters, int64_t m_prev = 0) {
     int rc;
-    DspaceState S{};
-    if ((rc = ensure_stage_ws(ctx, A->cols, &S, x, pc->pMinv)) != SPCG_OK) return rc;
+    StageWs W;
+    if ((rc = ensure_stage_ws(ctx, A->cols, &W, x, pc->pMinv)) != SPCG_OK) return rc;
+    const DspaceState& S = W.S;
     hipStream_t st = ctx->stream;
     const int64_t dpad = round_up(A->cols, 64);
     int np = 0;
@@ -821,19 +937,19 @@ int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double
         dA.rows = A->rows - m_prev;
         db.data = static_cast<const double*>(b->data) + (size_t)m_prev * b->ld;
         db.rows = dA.rows;
-        if ((rc = product_pass(ctx, &dA, &db, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
-        HIP_TRY(ctx, run_phase_a(st, S, PA_START_NESTED, nullptr, ctx->part_g.as<double>(),
-                                 ctx->part_scal.as<double>(), np, dpad, c2, (double)m_prev / (double)A->rows));
+        if ((rc = product_pass(ctx, &dA, &db, W, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+        if ((rc = phase_a(ctx, S, PA_START_NESTED, nullptr, W.part_g, W.part_scal, np, dpad, c2,
+                          (double)m_prev / (double)A->rows)) != SPCG_OK)
+            return rc;
     } else {
-        if ((rc = product_pass(ctx, A, b, S, PM_G, &np, nullptr)) != SPCG_OK) return rc;
-        HIP_TRY(ctx, run_phase_a(st, S, PA_START, nullptr, ctx->part_g.as<double>(), ctx->part_scal.as<double>(),
-                                 np, dpad, c2));
+        if ((rc = product_pass(ctx, A, b, W, PM_G, &np, nullptr)) != SPCG_OK) return rc;
+        if ((rc = phase_a(ctx, S, PA_START, nullptr, W.part_g, W.part_scal, np, dpad, c2)) != SPCG_OK) return rc;
     }
-    HIP_TRY(ctx, run_phase_b(st, S, 1));
+    if ((rc = phase_b(ctx, S, 1)) != SPCG_OK) return rc;
     for (int it = 0; it < iters; ++it) {
-        if ((rc = product_pass(ctx, A, b, S, PM_S, &np, nullptr)) != SPCG_OK) return rc;
-        HIP_TRY(ctx, run_phase_a(st, S, PA_STEP, ctx->part_s.as<double>(), nullptr, nullptr, np, dpad, c2));
-        HIP_TRY(ctx, run_phase_b(st, S, 0));
+        if ((rc = product_pass(ctx, A, b, W, PM_S, &np, nullptr)) != SPCG_OK) return rc;
+        if ((rc = phase_a(ctx, S, PA_STEP, W.part_s, nullptr, nullptr, np, dpad, c2)) != SPCG_OK) return rc;
+        if ((rc = phase_b(ctx, S, 0)) != SPCG_OK) return rc;
     }
     return SPCG_OK;
 }
@@ -850,8 +966,7 @@ int check_stage_args(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const 
                                         (long long)b->rows, (long long)A->rows);
     if (A->cols != pc->d) return fail(ctx, SPCG_E_SHAPE, "A has %lld columns, preconditioner %lld",
                                       (long long)A->cols, (long long)pc->d);
-    if (b->cols != 1)
-        return fail(ctx, SPCG_E_SHAPE, "multiple right-hand sides are not supported by this entry point");
+    if (b->cols < 1) return fail(ctx, SPCG_E_SHAPE, "b needs at least one column");
     if (A->cols > product_max_d(A->dtype)) return fail(ctx, SPCG_E_SHAPE, "d too large");
     return SPCG_OK;
 }
@@ -1466,6 +1581,139 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     return SPCG_OK;
 }
 
+
+
+// ------------------------------------------- one PCG solve, k right-hand sides
+
+// The k columns of beta (d x k row-major) <-> the column-major d-space
+// vectors of a multi-RHS problem (column c at v + c ldv).
+int beta_to_cols(spcg_ctx* ctx, const double* beta, int64_t d, int64_t k, double* v, int64_t ldv) {
+    for (int64_t c = 0; c < k; ++c)
+        HIP_TRY(ctx, hipMemcpy2DAsync(v + c * ldv, 8, beta + c, (size_t)k * 8, 8, d, hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+    return SPCG_OK;
+}
+int cols_to_beta(spcg_ctx* ctx, const double* v, int64_t ldv, int64_t d, int64_t k, double* beta) {
+    for (int64_t c = 0; c < k; ++c)
+        HIP_TRY(ctx, hipMemcpy2DAsync(beta + c, (size_t)k * 8, v + c * ldv, 8, 8, d, hipMemcpyDeviceToDevice,
+                                      ctx->stream));
+    return SPCG_OK;
+}
+
+// True when the matrix-core multi-RHS product takes A (FP32 or BF16 rows of
+// a supported layout, d <= 512, k <= 16); other stages run column by column.
+bool mrhs_stage_ok(const spcg_mat* A, int64_t k) {
+    if (A->dtype != SPCG_F32 && A->dtype != SPCG_BF16) return false;
+    if (A->cols > mrhs_max_d() || k > mrhs_max_k()) return false;
+    const int64_t dmem = A->reserved == 1 ? A->ld : A->cols;
+    return mrhs_class(A->dtype, A->data, A->ld, dmem, (int)A->cols) >= 0;
+}
+
+// PCG(A, b, c2, M, beta, iters) for the k columns of b at once: every
+// product pass reads A once for all columns (MFMA tiles, FP32 accumulation,
+// FP64 residuals), the d-space step runs per column, and the stopping test
+// passes when every column passes.  sc0: column 0's scalars at the end;
+// resid0: c2 ||b - A beta||^2 of column 0 at the start.
+int mrhs_stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const spcg_precond_t* pc,
+                   double* beta, int iters, double tol, bool refresh, int check_every, StageRun* out,
+                   MrhsScalars* sc0, double* resid0) {
+    int rc;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(ctx, SPCG_E_NOMEM, "host allocation failed");
+    BatchWork& W = *ctx->batch;
+    if ((rc = batch_streams(ctx, W)) != SPCG_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const int64_t d = A->cols, k = b->cols;
+    const int64_t ldv = mrhs_max_d();
+    const int kmax = mrhs_max_k();
+    // the vectors may still be read by an earlier batched call's graphs
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    HIP_TRY(ctx, W.vecs.ensure((size_t)MR_VECS * kmax * ldv * 8));
+    HIP_TRY(ctx, W.scal.ensure((size_t)kmax * sizeof(MrhsScalars)));
+    HIP_TRY(ctx, hipMemsetAsync(W.vecs.p, 0, (size_t)MR_VECS * kmax * ldv * 8, st));
+    HIP_TRY(ctx, hipMemsetAsync(W.scal.p, 0, (size_t)kmax * sizeof(MrhsScalars), st));
+    std::vector<MrhsProblem> hp(1);
+    MrhsProblem& q = hp[0];
+    std::memset(&q, 0, sizeof q);
+    double* base = W.vecs.as<double>();
+    q.d = (int)d;
+    q.k = (int)k;
+    q.ldv = ldv;
+    q.X = base;
+    q.G = base + 1 * kmax * ldv;
+    q.Z = base + 2 * kmax * ldv;
+    q.P = base + 3 * kmax * ldv;
+    q.S = base + 4 * kmax * ldv;
+    q.Gt = base + 5 * kmax * ldv;
+    q.Minv = pc->pMinv;
+    q.sc = W.scal.as<MrhsScalars>();
+    q.A = A->data;
+    q.m = A->rows;
+    q.lda = A->ld;
+    q.dmem = A->reserved == 1 ? A->ld : A->cols;
+    q.b = static_cast<const double*>(b->data);
+    q.ldb = b->ld;
+    q.c2 = c2;
+    q.active = 1;
+    if ((rc = beta_to_cols(ctx, beta, d, k, q.X, ldv)) != SPCG_OK) return rc;
+    BatchPlan plan;
+    if ((rc = batched_setup(ctx, W, A->dtype, hp, 4 * (int64_t)ctx->num_cu, plan)) != SPCG_OK) return rc;
+    std::vector<MrhsScalars> hs(kmax);
+    auto read = [&]() -> int {
+        HIP_TRY(ctx, hipMemcpyAsync(hs.data(), W.scal.p, (size_t)k * sizeof(MrhsScalars), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        ctx->syncs++;
+        for (int64_t c = 0; c < k; ++c)
+            if (hs[c].breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown in column %lld", (long long)c);
+        return SPCG_OK;
+    };
+    auto all_pass = [&]() {
+        for (int64_t c = 0; c < k; ++c) {
+            const MrhsScalars& s = hs[c];
+            if (s.exact) continue;
+            if (!(std::sqrt(std::max(s.rho, 0.0)) <= tol * std::sqrt(std::max(s.ax2, 0.0)))) return false;
+        }
+        return true;
+    };
+    auto finish = [&](int code) -> int {
+        int r2;
+        if ((r2 = cols_to_beta(ctx, q.X, ldv, d, k, beta)) != SPCG_OK) return r2;
+        *sc0 = hs[0];
+        return code;
+    };
+    out->iters_done = 0;
+    out->converged = false;
+    if ((rc = batched_products(ctx, W, st, A->dtype, PM_G, plan)) != SPCG_OK) return rc;
+    if ((rc = batched_dspace(ctx, W, st, PA_START, plan)) != SPCG_OK) return rc;
+    if ((rc = read()) != SPCG_OK) return finish(rc);
+    *resid0 = hs[0].resid2;
+    const bool testing = tol > 0.0;
+    if (check_every < 1) check_every = 1;
+    if (testing && all_pass()) {
+        out->converged = true;
+        return finish(SPCG_OK);
+    }
+    const int pmode = refresh ? PM_SG : PM_S;
+    for (int it = 0; it < iters; ++it) {
+        if ((rc = batched_products(ctx, W, st, A->dtype, pmode, plan)) != SPCG_OK) return rc;
+        if ((rc = batched_dspace(ctx, W, st, refresh ? PA_REFRESH : PA_STEP, plan)) != SPCG_OK) return rc;
+        out->iters_done = it + 1;
+        if (testing && ((it + 1) % check_every == 0 || it + 1 == iters)) {
+            if ((rc = read()) != SPCG_OK) return finish(rc);
+            if (all_pass()) {
+                out->converged = true;
+                return finish(SPCG_OK);
+            }
+        }
+    }
+    if (!testing) {
+        if ((rc = read()) != SPCG_OK) return finish(rc);
+        bool ex = true;
+        for (int64_t c = 0; c < k; ++c) ex = ex && hs[c].exact;
+        out->converged = ex;
+    }
+    return finish(SPCG_OK);
+}
 }  // namespace
 
 // ================================================================== C ABI
@@ -1501,6 +1749,7 @@ int spcg_ctx_destroy(spcg_ctx* ctx) {
         for (auto& e : ctx->ev_prod) (void)hipEventDestroy(e);
     }
     delete ctx->batch;
+    delete ctx->kt;
     if (ctx->side) {
         (void)hipStreamSynchronize(ctx->side);
         (void)hipStreamDestroy(ctx->side);
@@ -1675,23 +1924,70 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     if ((rc = check_stage_args(ctx, A, b, pc, beta)) != SPCG_OK) return rc;
     if (!opts || opts->iters < 0 || opts->tol < 0.0 || !(c2 > 0.0))
         return fail(ctx, SPCG_E_INVALID_ARG, "bad stage options (iters >= 0, tol >= 0, c2 > 0)");
-    int64_t d = A->cols;
-    DspaceState S{};
-    if ((rc = ensure_stage_ws(ctx, d, &S, beta, pc->pMinv)) != SPCG_OK) return rc;
-    HIP_TRY(ctx, run_scalars_reset(ctx->stream, S.sc));
-    StageRun run;
+    const int64_t d = A->cols, k = b->cols;
     const bool refresh = opts->refresh_gradient || opts->tol > 0.0;
-    rc = stage_run(ctx, A, b, c2, pc, beta, opts->iters, opts->tol, refresh, opts->check_every, &run, nullptr);
+    StageRun run;
+    PcgScalars sc{};   // column 0 at the end
+    double resid0 = 0.0;
+    bool conv = true;
+    int iters_max = 0;
+    if (k == 1) {
+        StageWs W;
+        if ((rc = ensure_stage_ws(ctx, d, &W, beta, pc->pMinv)) != SPCG_OK) return rc;
+        HIP_TRY(ctx, run_scalars_reset(ctx->stream, W.S.sc));
+        rc = stage_run(ctx, A, b, c2, pc, beta, opts->iters, opts->tol, refresh, opts->check_every, &run, nullptr,
+                       nullptr, &W);
+        sc = run.sc;
+        resid0 = run.sc.resid2_0;
+        conv = run.converged;
+        iters_max = run.iters_done;
+    } else if (mrhs_stage_ok(A, k)) {
+        MrhsScalars m0{};
+        rc = mrhs_stage_run(ctx, A, b, c2, pc, beta, opts->iters, opts->tol, refresh, opts->check_every, &run, &m0,
+                            &resid0);
+        sc.rho0 = m0.rho0;
+        sc.rho = m0.rho;
+        sc.ax2 = m0.ax2;
+        conv = run.converged;
+        iters_max = run.iters_done;
+    } else {
+        // column by column on the single-RHS kernels (FP64 and FP8 rows,
+        // d > 512 or k > 16): one PCG per column, each from its warm start
+        HIP_TRY(ctx, ctx->colx.ensure((size_t)d * 8));
+        double* x = ctx->colx.as<double>();
+        StageWs W;
+        if ((rc = ensure_stage_ws(ctx, d, &W, x, pc->pMinv)) != SPCG_OK) return rc;
+        rc = SPCG_OK;
+        for (int64_t c = 0; c < k && rc == SPCG_OK; ++c) {
+            spcg_mat bc = *b;
+            bc.data = static_cast<const double*>(b->data) + c;
+            bc.cols = 1;
+            HIP_TRY(ctx, hipMemcpy2DAsync(x, 8, beta + c, (size_t)k * 8, 8, d, hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_TRY(ctx, run_scalars_reset(ctx->stream, W.S.sc));
+            StageRun rcol;
+            rc = stage_run(ctx, A, &bc, c2, pc, x, opts->iters, opts->tol, refresh, opts->check_every, &rcol,
+                           nullptr, nullptr, &W);
+            // the column's last good iterate is returned on breakdown too
+            HIP_TRY(ctx, hipMemcpy2DAsync(beta + c, (size_t)k * 8, x, 8, 8, d, hipMemcpyDeviceToDevice, ctx->stream));
+            if (c == 0) {
+                sc = rcol.sc;
+                resid0 = rcol.sc.resid2_0;
+            }
+            conv = conv && rcol.converged;
+            iters_max = std::max(iters_max, rcol.iters_done);
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
     if (stats) {
-        stats->iters = run.iters_done;
-        stats->converged = run.converged;
-        stats->rho0 = run.sc.rho0;
-        stats->rho = run.sc.rho;
-        stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
-        stats->resid_norm2 = run.sc.resid2_0;
+        stats->iters = iters_max;
+        stats->converged = conv;
+        stats->rho0 = sc.rho0;
+        stats->rho = sc.rho;
+        stats->ax_norm = std::sqrt(std::max(sc.ax2, 0.0));
+        stats->resid_norm2 = resid0;
     }
     if (rc != SPCG_OK) return rc;
-    if (opts->tol > 0.0 && !run.converged) {
+    if (opts->tol > 0.0 && !conv) {
         fail(ctx, SPCG_W_NOT_CONVERGED, "stopping test not met in %d iterations", opts->iters);
         return SPCG_W_NOT_CONVERGED;
     }
@@ -1754,6 +2050,14 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if (timing || opts->time_products) {
         if ((rc = ensure_events(ctx)) != SPCG_OK) return rc;
     }
+    // time_products = 2: every launch timed by kernel class (switched off
+    // again on every return)
+    const bool by_class = opts->time_products == 2;
+    struct KtOff {
+        spcg_ctx* c;
+        ~KtOff() { c->kt_on = false; }
+    } kt_off{ctx};
+    if (by_class && (rc = kt_start(ctx)) != SPCG_OK) return rc;
     ctx->syncs = 0;
     hipStream_t st = ctx->stream;
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[0], st));
@@ -1789,9 +2093,9 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         stride = host_out_pre[5] > host_out_pre[4] ? 2 : 1;
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
-    DspaceState S{};
-    if ((rc = ensure_stage_ws(ctx, d, &S, beta, pc.pMinv)) != SPCG_OK) return rc;
-    HIP_TRY(ctx, run_scalars_reset(st, S.sc));
+    StageWs SW;
+    if ((rc = ensure_stage_ws(ctx, d, &SW, beta, pc.pMinv)) != SPCG_OK) return rc;
+    HIP_TRY(ctx, run_scalars_reset(st, SW.S.sc));
     HIP_TRY(ctx, run_fill(st, beta, d, 0.0));
     // Stage I over the prefixes K-1, K-1-stride, ... in increasing order
     std::vector<int64_t> stages;
@@ -1836,7 +2140,7 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         hooks.margin = opts->schedule_margin == 0 ? 1 : std::max(0, opts->schedule_margin);
     }
     rc = stage_run(ctx, X, Y, 1.0, &pc, beta, std::max(0, T - t1), tol, true, opts->check_every, &run,
-                   opts->time_products ? &timer : nullptr, &hooks);
+                   opts->time_products == 1 ? &timer : nullptr, &hooks);
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[4], st));
     if (rc != SPCG_OK && rc != SPCG_E_BREAKDOWN) return rc;
     const int rc_stage = rc;
@@ -1876,11 +2180,23 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
             stats->t_stage2_ms = elapsed_ms(ctx->ev_phase[3], ctx->ev_phase[4]);
             stats->t_total_ms = elapsed_ms(ctx->ev_phase[0], ctx->ev_phase[4]);
         }
-        if (opts->time_products) {
+        if (opts->time_products == 1) {
             double sum = 0.0;
             for (int i = 0; i < timer.used; ++i) sum += elapsed_ms(ctx->ev_prod[2 * i], ctx->ev_prod[2 * i + 1]);
             stats->product_ms_sum = sum;
             stats->product_launches = timer.used;
+        }
+        if (by_class) {
+            const KTimer& t = *ctx->kt;
+            for (int i = 0; i < t.used; ++i) {
+                const int c = t.cls[i];
+                stats->kernel_ms[c] += elapsed_ms(t.ev[2 * i], t.ev[2 * i + 1]);
+                stats->kernel_bytes[c] += t.bytes[i];
+                stats->kernel_launches[c] += 1;
+            }
+            // the full-data dual passes, as time_products = 1 reports them
+            stats->product_ms_sum = stats->kernel_ms[SPCG_KT_PROD_SG];
+            stats->product_launches = stats->kernel_launches[SPCG_KT_PROD_SG];
         }
     }
     if (rc_stage == SPCG_E_BREAKDOWN) return rc_stage;

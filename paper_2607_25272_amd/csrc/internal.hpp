@@ -55,6 +55,8 @@ struct FwhtJob {
     hipEvent_t wait_before_last;  // if set: the last pass waits for it (the
                                   // output-slot tables are built beside the
                                   // first pass)
+    hipEvent_t pass_ev[6];        // optional timing events: pass i (< 3) is
+                                  // bracketed by pass_ev[2i] and pass_ev[2i+1]
 };
 // Widest column chunk of the transform (256-byte row segments): every row
 // width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.
@@ -64,6 +66,8 @@ inline int fwht_chunk_cols(int in_dtype, int narrow) {
 // Row padding of the stored sketch rows (multiple of every chunk width).
 inline int64_t sketch_ld(int64_t d, bool f64) { return round_up(d, f64 ? 32 : 64); }
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
+// Number of passes run_fwht makes over an N' = 2^L row transform.
+int fwht_passes(int L);
 
 // ----------------------------------------------------------- CountSketch
 // Bucket tables for a padded size Np = 2^L: entry y holds the row k with

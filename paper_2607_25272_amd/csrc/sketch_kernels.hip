@@ -803,6 +803,11 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             const hipError_t e = hipStreamWaitEvent(st, job.wait_before_last, 0);
             if (e != hipSuccess) return e;
         }
+        hipEvent_t ev0 = pi < 3 ? job.pass_ev[2 * pi] : nullptr, ev1 = pi < 3 ? job.pass_ev[2 * pi + 1] : nullptr;
+        if (ev0) {
+            const hipError_t e = hipEventRecord(ev0, st);
+            if (e != hipSuccess) return e;
+        }
         if constexpr (std::is_same<TZ, float>::value) {
             const int scw = stream_cw(nb, first);
             if (scw) {
@@ -817,6 +822,10 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
                                                : launch_stream<TIN, 64>(st, a, grid, first, last);
                 if (e != hipSuccess) return e;
+                if (ev1) {
+                    const hipError_t e1 = hipEventRecord(ev1, st);
+                    if (e1 != hipSuccess) return e1;
+                }
                 lo += nb;
                 continue;
             }
@@ -835,6 +844,10 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                              : cw == CW_NARROW ? launch_any<TIN, TZ, CW_NARROW>(st, a, first, last)
                                                : launch_any<TIN, TZ, CW_TINY>(st, a, first, last);
         if (e != hipSuccess) return e;
+        if (ev1) {
+            const hipError_t e1 = hipEventRecord(ev1, st);
+            if (e1 != hipSuccess) return e1;
+        }
         lo += nb;
     }
     return hipSuccess;
@@ -907,6 +920,8 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
                                                               hat_rows, input_perm, sign_bits);
     return hipGetLastError();
 }
+
+int fwht_passes(int L) { return (L + NB_MAX - 1) / NB_MAX; }
 
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {
     const int cw = fwht_chunk_cols(job.in_dtype, job.narrow);
