@@ -1,17 +1,24 @@
 """Benchmark: time-to-OLS-accuracy of SPCG vs full PCG on one MI355X.
 
-A step is one whole solve (nested SRHT sketch, FP64 QR preconditioner,
-Stage I sketched PCG stages, Stage II full-data PCG until the stopping
-test) of a synthetic least-squares problem already resident in HBM.
-Prints one JSON line.
+A step is one whole solve (nested sketch, FP64 QR preconditioner, Stage I
+sketched PCG stages, Stage II full-data PCG until the stopping test) of a
+synthetic least-squares problem already resident in HBM.  Prints one JSON
+line.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
-                    [--workload cfg1|cfg2|cfg2fp8|cfg1cs|cfg2cs|batched|learned|paper|tuned]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload NAME]
 
-cfg1 (default)  N=1e6, d=500, FP32 storage
-cfg2 / cfg2fp8  N=4e6, d=1000, BF16 / FP8-e4m3 storage (precision form)
-cfg1cs / cfg2cs the same problems solved by SPCG-CS (CountSketch sketches,
-                Sec. 4.3); SPCG-SRHT and full PCG are timed beside it
+cfg2 (default)  the headline workload: N=4e6, d=1000, X = T C (Student-t(3)
+                rows, correlation factor of condition 1e5), sigma=0.5.
+                value = SPCG (SRHT) with X stored FP32 (the unquantized
+                data); beside it full PCG, SPCG-CS (CountSketch, Sec. 4.3)
+                and full PCG with the CountSketch preconditioner, and the
+                precision form: the same solves with X stored BF16 and
+                FP8-e4m3 (per-column scales), each with its error against
+                the OLS estimator of the stored and of the unquantized data
+cfg2bf16 / cfg2fp8  one storage type of the same problem (SPCG vs full PCG)
+cfg1            N=1e6, d=500, FP32 storage
+cfg1cs / cfg2cs the same problems solved by SPCG-CS; SPCG-SRHT and full PCG
+                are timed beside it
 batched         256 independent problems, N in [5e4, 5e5], d in [32, 512],
                 1..16 right-hand sides, FP32 (batched / multi-RHS form)
 learned         N=2e6, d=256, 1% of rows scaled by 100: plain vs learned schedule
@@ -19,9 +26,16 @@ paper           the Sec. 4 / Table 1 setting (d=64, sigma^2=1e-8, m_1=8d,
                 m_K=N/2, FP64), N=2^17..2^22: iteration counts and GPU times
 tuned           the Sec. 4.3 setting (N=2^22, d=64, kappa=1e8): paper schedule,
                 tuned sizes, theory-driven a_i, CountSketch, full PCG
+
+Timing: W untimed warm-up solves, then K timed solves bracketed by device
+synchronisations, with no per-launch events in them (every method is timed
+the same way).  Per-kernel durations come from separate instrumented solves
+of the same workload (time_products = 2: HIP events on the library's stream
+around every launch), which also give the roofline figures.
 """
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -33,22 +47,22 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
+T3_DESC = ("X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; N=4000000, d=1000; "
+           "sigma=0.5")
 WORKLOADS = {
+    "cfg2": dict(cfg=2, storage="f32", headline=True,
+                 desc=T3_DESC + "; X stored FP32 (the unquantized data); precision form beside it: "
+                                "X stored BF16 and FP8 e4m3 with per-column scales"),
+    "cfg2bf16": dict(cfg=2, storage="bf16", desc=T3_DESC + "; X stored BF16"),
+    "cfg2fp8": dict(cfg=2, storage="fp8", desc=T3_DESC + "; X stored FP8 e4m3 with per-column scales"),
     "cfg1": dict(cfg=1, storage="f32",
                  desc="X = G diag(s), G Gaussian, s log-spaced 1..1e4; N=1000000, d=500; sigma=1; "
                       "X stored FP32"),
-    "cfg2": dict(cfg=2, storage="bf16",
-                 desc="X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; "
-                      "N=4000000, d=1000; sigma=0.5; X stored BF16"),
-    "cfg2fp8": dict(cfg=2, storage="fp8",
-                    desc="X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; "
-                         "N=4000000, d=1000; sigma=0.5; X stored FP8 e4m3 with per-column scales"),
-    "cfg1cs": dict(cfg=1, storage="f32", sketch="cs", base="cfg1",
+    "cfg1cs": dict(cfg=1, storage="f32", sketch="cs",
                    desc="X = G diag(s), G Gaussian, s log-spaced 1..1e4; N=1000000, d=500; sigma=1; "
                         "X stored FP32; SPCG-CS (nested CountSketch)"),
-    "cfg2cs": dict(cfg=2, storage="bf16", sketch="cs", base="cfg2",
-                   desc="X = T C, T Student-t(3), C = Q1 diag(s) Q2^T with s log-spaced 1..1e5; "
-                        "N=4000000, d=1000; sigma=0.5; X stored BF16; SPCG-CS (nested CountSketch)"),
+    "cfg2cs": dict(cfg=2, storage="bf16", sketch="cs",
+                   desc=T3_DESC + "; X stored BF16; SPCG-CS (nested CountSketch)"),
     "learned": dict(cfg=4, storage="f32",
                     desc="X = G diag(s), s log-spaced 1..1e4, a seeded 1% of rows scaled by 100; "
                          "N=2000000, d=256; sigma=1; X stored FP32; plain vs learned schedule"),
@@ -61,85 +75,277 @@ WORKLOADS = {
                        "a_i (Theorems 3.3/3.4, omega=0.5), SPCG-CS, and full PCG"),
 }
 METRIC = "time-to-OLS-accuracy (s) and PCG-product HBM GB/s, SPCG vs full PCG, 1 GPU"
-# HBM bytes per launch of the full-data SG product from rocprofv3 PMC runs
-# (2.0 x FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy; the summary and
-# commands are in profiles/hbm_traffic_sg_product_and_transform.txt).  Valid
-# for the product kernel as profiled; workloads not profiled report null.
-SG_TRAFFIC_BYTES = {"cfg1": 2.0103e9, "cfg2": 8.0366e9}
+DTYPE_NAME = {"f32": "f32", "bf16": "bf16", "fp8": "fp8e4m3", "f64": "f64"}
+
+# kernel classes of spcg_solve_stats.kernel_* (include/spcg.h SPCG_KT_*)
+KT_NAMES = ["transform_first_pass", "transform_last_pass", "product_S", "product_G", "product_SG",
+            "phase_A", "phase_B"]
+KT_KERNELS = ["fwht_pass_kernel / fwht_stream_kernel (first SRHT pass: gather X[p(k)], signs, first bits; "
+              "writes Z)",
+              "fwht_pass_kernel / fwht_stream_kernel (last SRHT pass: remaining bits, scatter to S_K X and "
+              "S_hat X)",
+              "product_ring_kernel (S mode: s = c2 A^T A p, Stage I)",
+              "product_ring_kernel (G mode: stage-start gradient)",
+              "product_ring_kernel (SG mode: s and the refreshed gradient, full data)",
+              "phase_a_kernel", "phase_b_kernel"]
+BYTE_CLASSES = range(5)
+# HBM bytes per launch from rocprofv3 PMC runs (2.0 x FETCH_SIZE + WRITE_SIZE,
+# calibrated on a 1 GiB copy) for a kernel class and workload, taken on the
+# kernel as it now stands; everything else reports null.
+PMC_TRAFFIC = {}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+class OlsError:
+    """||X (beta - beta_ols)|| / ||X beta|| for one stored matrix, without
+    forming beta_ols: with G = X^T X and g = X^T (Y - X beta),
+    X^T X (beta_ols - beta) = g, so ||X (beta - beta_ols)||^2 = g^T G^-1 g.
+    G is accumulated once in FP64 over row chunks (no library call sees more
+    than 2^31 elements) and factored by Cholesky; each beta then costs one
+    FP64 pass for g and ||X beta||.  A measurement estimate: the full-size
+    comparison against the oracle's TSQR is a test."""
+
+    def __init__(self, X, Y, col_scale=None, chunk=1 << 18):
+        import torch
+        self.X, self.Y, self.sc, self.chunk = X, Y, col_scale, chunk
+        d = X.shape[1]
+        G = torch.zeros(d, d, dtype=torch.float64, device=X.device)
+        for i in range(0, X.shape[0], chunk):
+            xb = self._rows(i)
+            G += xb.T @ xb
+            del xb
+        self.L = torch.linalg.cholesky(G)
+
+    def _rows(self, i):
+        import torch
+        xb = self.X[i:i + self.chunk].to(torch.float64)
+        return xb * self.sc.to(torch.float64) if self.sc is not None else xb
+
+    def __call__(self, beta):
+        import torch
+        d = self.X.shape[1]
+        k = self.Y.shape[1]
+        b = beta.reshape(d, k)
+        g = torch.zeros(d, k, dtype=torch.float64, device=beta.device)
+        fit2 = torch.zeros(k, dtype=torch.float64, device=beta.device)
+        for i in range(0, self.X.shape[0], self.chunk):
+            xb = self._rows(i)
+            f = xb @ b
+            g += xb.T @ (self.Y[i:i + self.chunk] - f)
+            fit2 += (f * f).sum(0)
+            del xb, f
+        z = torch.cholesky_solve(g, self.L)
+        err = torch.sqrt(torch.clamp((g * z).sum(0), min=0.0)) / torch.sqrt(torch.clamp(fit2, min=1e-300))
+        return float(err.max())
+
+
 def pred_error_vs_ols(p, beta, chunk=1 << 18):
-    """max over right-hand sides of ||X (beta - beta_ols)|| / ||X beta_ols||,
-    without forming beta_ols.
-
-    With g = X^T (Y - X beta) and G = X^T X, X^T X (beta_ols - beta) = g, so
-    ||X (beta - beta_ols)||^2 = g^T G^-1 g.  G, g and ||X beta|| are
-    accumulated in FP64 over row chunks (no library call sees more than
-    2^31 elements), then one Cholesky solve of the d x d system."""
-    import torch
-    d, k = p.d, p.k
-    G = torch.zeros(d, d, dtype=torch.float64, device=beta.device)
-    g = torch.zeros(d, k, dtype=torch.float64, device=beta.device)
-    fit2 = torch.zeros(k, dtype=torch.float64, device=beta.device)
-    b = beta.reshape(d, k)
-    for i in range(0, p.N, chunk):
-        xb = p.x_f64(slice(i, min(i + chunk, p.N)))
-        G += xb.T @ xb
-        f = xb @ b
-        g += xb.T @ (p.Y[i:i + chunk] - f)
-        fit2 += (f * f).sum(0)
-        del xb, f
-    L = torch.linalg.cholesky(G)
-    z = torch.cholesky_solve(g, L)
-    err = torch.sqrt(torch.clamp((g * z).sum(0), min=0.0)) / torch.sqrt(torch.clamp(fit2, min=1e-300))
-    return float(err.max())
+    return OlsError(p.X, p.Y, p.col_scale, chunk)(beta)
 
 
-def cpu_baseline(X, Y, n_sample):
-    """The FP64 NumPy oracle's SPCG on the first n_sample rows."""
-    from oracle.spcg import spcg
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
-    Xs = X.double().cpu().numpy()
-    Ys = Y[:n_sample, 0].cpu().numpy()
+        return None
+
+
+def cpu_baseline(Xs, Y, N, gpu_T2, seed=1):
+    """The FP64 NumPy oracle's SPCG (oracle.spcg.spcg, as it stands) on the
+    first n_s rows of the workload, timed by phase on this host, and the
+    phase-by-phase extrapolation of that time to the full N:
+    * sketch: the transform costs O(N' log2 N') per column;
+    * preconditioner: the QR of the r = 6d rows of S_hat X is the same work;
+    * Stage I: proportional to sum_i (a_i + 1) m_i (one gradient pass and a_i
+      iterations of two passes over m_i rows per stage);
+    * Stage II: proportional to N (2 + 3 T_II) (the oracle's starting
+      gradient takes two passes, each iteration three), with T_II the full
+      solve's Stage II count measured on the GPU (Algorithm 1 runs the same
+      iterations on either)."""
+    import numpy as np
+    from oracle.spcg import schedule, spcg
+    n_s, d = Xs.shape
+    Xs = Xs.double().cpu().numpy()
+    Ys = Y[:n_s, 0].cpu().numpy()
+    t = {}
     t0 = time.perf_counter()
-    spcg(Xs, Ys, seed=1)
-    return time.perf_counter() - t0, threads
+    _, info = spcg(Xs, Ys, seed=seed, timings=t)
+    total = time.perf_counter() - t0
+    sizes_s, sizes_f = info["sizes"], schedule(N, d)
+    T2_s = info["per_rhs"][0]["T"] - info["per_rhs"][0]["T_stage1"]
+    Ls, Lf = max(1, (n_s - 1).bit_length()), max(1, (N - 1).bit_length())
+    f_sketch = ((1 << Lf) * Lf) / ((1 << Ls) * Ls)
+    f_stage1 = sum(4 * m for m in sizes_f) / max(sum(4 * m for m in sizes_s), 1)
+    f_stage2 = (N * (2 + 3 * gpu_T2)) / (n_s * (2 + 3 * T2_s))
+    est = t["sketch"] * f_sketch + t["precond"] + t["stage1"] * f_stage1 + t["stage2"] * f_stage2
+    desc = (f"FP64 NumPy oracle SPCG on the first {n_s} rows (d={d}): K={len(sizes_s)}, T_II={T2_s}, "
+            f"{total:.2f} s (sketch {t['sketch']:.2f}, preconditioner {t['precond']:.2f}, Stage I "
+            f"{t['stage1']:.2f}, Stage II {t['stage2']:.2f} s); value extrapolated to N={N} (K={len(sizes_f)}, "
+            f"T_II={gpu_T2}) phase by phase: sketch x N'log2N' ({f_sketch:.1f}), preconditioner x 1, "
+            f"Stage I x sum (a_i+1) m_i ({f_stage1:.1f}), Stage II x N (2 + 3 T_II) ({f_stage2:.1f})")
+    return {"value": est, "unit": "s", "cores": blas_threads() or os.cpu_count(), "kind": "oracle",
+            "sample": desc, "sample_rows": n_s, "sample_s": total, "sample_phases_s": t,
+            "host_cpus": os.cpu_count(), "blas_threads": blas_threads()}
 
 
-def roofline(avg_ms, launches, bytes_per_launch, kernel):
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
-            "kernel": kernel, "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
-            "launches": launches}
+def roofline(kern, cls, workload):
+    """The roofline entry of kernel class cls from instrumented solves."""
+    k = kern[KT_NAMES[cls]]
+    traffic = PMC_TRAFFIC.get((KT_NAMES[cls], workload))
+    return {"bound": "hbm", "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": k["GBps"] / HBM_PEAK_GBPS if k["GBps"] else None, "traffic": traffic,
+            "kernel": KT_KERNELS[cls], "class": KT_NAMES[cls], "bytes_per_launch": k["bytes_per_launch"],
+            "avg_launch_ms": k["avg_ms"], "launches": k["launches"], "ms_per_solve": k["ms_per_solve"]}
 
 
-def timed_solves(solve, steps, warmup, label):
-    """Warm-up, then `steps` timed solves bracketed by device syncs; returns
-    (seconds per solve, product ms sum, product launches, last stats)."""
+def kernel_table(stats_list):
+    """Per kernel class over instrumented solves: launches and ms per solve,
+    average launch duration, algorithmic bytes per launch, achieved GB/s."""
+    n = len(stats_list)
+    out = {}
+    for c, name in enumerate(KT_NAMES):
+        ms = sum(s["kernel_ms"][c] for s in stats_list)
+        by = sum(s["kernel_bytes"][c] for s in stats_list)
+        nl = sum(s["kernel_launches"][c] for s in stats_list)
+        if nl == 0:
+            continue
+        out[name] = {"launches_per_solve": nl / n, "ms_per_solve": ms / n, "avg_ms": ms / nl,
+                     "bytes_per_launch": by / nl if c in BYTE_CLASSES else None,
+                     "GBps": (by / (ms * 1e-3) / 1e9) if (c in BYTE_CLASSES and ms > 0) else None,
+                     "launches": nl}
+        if out[name]["GBps"] is not None:
+            out[name]["frac"] = out[name]["GBps"] / HBM_PEAK_GBPS
+    return out
+
+
+def dominant_class(kern):
+    best, cls = -1.0, None
+    for c in BYTE_CLASSES:
+        k = kern.get(KT_NAMES[c])
+        if k and k["ms_per_solve"] > best:
+            best, cls = k["ms_per_solve"], c
+    return cls
+
+
+def measure(solve, steps, warmup, label, instrumented=2):
+    """W warm-up solves, K timed solves (device syncs around the loop, no
+    per-launch events), one solve with phase times, then `instrumented`
+    solves with every launch timed by kernel class."""
     import torch
     log(f"{label}: warmup {warmup}")
     for _ in range(warmup):
-        solve(time_products=False)
+        solve()
     torch.cuda.synchronize()
     log(f"{label}: timing {steps} solves")
-    prod_ms, prod_n, last = 0.0, 0, None
     t0 = time.perf_counter()
     for _ in range(steps):
-        last = solve(time_products=True)
-        st0 = last[0] if isinstance(last, list) else last
-        prod_ms += st0["product_ms_sum"]
-        prod_n += st0["product_launches"]
+        last = solve()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, prod_ms, prod_n, last
+    dt = (time.perf_counter() - t0) / steps
+    ph = solve(time_phases=True)
+    inst = [solve(time_products=2) for _ in range(instrumented)]
+    torch.cuda.synchronize()
+    kern = kernel_table(inst) if instrumented else {}
+    log(f"{label}: {dt * 1e3:.3f} ms/solve, K={last['K']} T1={last['T_stage1']} T2={last['T_stage2']} "
+        f"a={last['policy_a']} stride={last['policy_stride']} syncs={last['host_syncs']} "
+        f"phases sketch={ph['t_sketch_ms']:.3f} precond={ph['t_precond_ms']:.3f} "
+        f"stage1={ph['t_stage1_ms']:.3f} stage2={ph['t_stage2_ms']:.3f} ms")
+    for name, k in kern.items():
+        gb = f"{k['GBps']:.0f} GB/s" if k.get("GBps") else "-"
+        log(f"{label}:   {name}: {k['launches_per_solve']:.1f} launches, {k['ms_per_solve']:.3f} ms/solve, "
+            f"{k['avg_ms'] * 1e3:.1f} us avg, {gb}")
+    return {"s": dt, "stats": last, "phases": ph, "kernels": kern}
+
+
+def phases_dict(ph):
+    return {k: round(ph[k], 4) for k in ("t_sketch_ms", "t_precond_ms", "t_stage1_ms", "t_stage2_ms",
+                                          "t_total_ms")}
+
+
+def solver(spcg, ctx, X, Y, col_scale, beta, method, sketch, extra=None):
+    def solve(time_products=0, time_phases=False):
+        kw = dict(time_products=time_products, time_phases=time_phases, seed=1, col_scale=col_scale,
+                  sketch=sketch)
+        if extra:
+            kw.update(extra)
+        _, st = spcg.spcg_solve(ctx, X, Y, beta=beta, method=method, **kw)
+        return st
+    return solve
+
+
+def bench_headline(args, wl, spcg, workloads, torch, dev):
+    """N=4e6, d=1000: SPCG vs full PCG with both sketch kinds on the FP32
+    (unquantized) data, and the precision form in BF16 and FP8."""
+    log("generating cfg2 (FP32 = unquantized) and its BF16 / FP8 copies")
+    p = workloads.make_config(2, device=dev, storage="f32")
+    stores = {"f32": (p.X, None), "bf16": workloads.store(p.X, "bf16"), "fp8": workloads.store(p.X, "fp8")}
+    torch.cuda.synchronize()
+    N, d = p.N, p.d
+    ctx = spcg.Context(0)
+    beta = torch.zeros(d, dtype=torch.float64, device=dev)
+    log("FP64 Gram of the unquantized data")
+    err_unq = OlsError(p.X, p.Y)
+    runs = {}
+    plan = [("f32", "srht"), ("f32", "cs"), ("bf16", "srht"), ("fp8", "srht"), ("bf16", "cs"), ("fp8", "cs")]
+    for storage, sk in plan:
+        X, sc = stores[storage]
+        err_st = err_unq if storage == "f32" else OlsError(X, p.Y, sc)
+        for method in ("spcg", "pcg"):
+            name = f"{storage}_{sk}_{method}"
+            r = measure(solver(spcg, ctx, X, p.Y, sc, beta, method, sk), args.steps, args.warmup, name,
+                        instrumented=2 if storage == "f32" or method == "spcg" else 1)
+            if not args.skip_check:
+                r["rel"] = err_st(beta)
+                r["rel_unquantized"] = err_unq(beta) if storage != "f32" else r["rel"]
+                log(f"{name}: rel vs OLS of the stored data {r['rel']:.3e}, of the unquantized data "
+                    f"{r['rel_unquantized']:.3e}")
+            runs[name] = r
+        del err_st
+        torch.cuda.empty_cache()
+    head = runs["f32_srht_spcg"]
+    kern = head["kernels"]
+    dom = dominant_class(kern)
+    rf = roofline(kern, dom, "cfg2")
+    rf["workload"] = "SPCG (SRHT) step at N=4e6, d=1000, FP32"
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_s = min(args.cpu_sample or 32768, N // 2)
+        log(f"cpu baseline: oracle SPCG on {n_s} rows")
+        cpu = cpu_baseline(p.X[:n_s], p.Y, N, head["stats"]["T_stage2"])
+        log(f"cpu baseline: {cpu['sample']}")
+
+    def line(r):
+        st = r["stats"]
+        out = {"s": r["s"], "K": st["K"], "T_stage1": st["T_stage1"], "T_stage2": st["T_stage2"],
+               "host_syncs": st["host_syncs"], "phases_ms": phases_dict(r["phases"])}
+        if "rel" in r:
+            out["rel_vs_ols_stored"] = r["rel"]
+            out["rel_vs_ols_unquantized"] = r["rel_unquantized"]
+        return out
+
+    solves = {name: line(r) for name, r in runs.items()}
+    speedups = {f"{s}_{k}": runs[f"{s}_{k}_pcg"]["s"] / runs[f"{s}_{k}_spcg"]["s"] for s, k in plan}
+    kernels = {name: r["kernels"] for name, r in runs.items() if name.endswith("_spcg") or name.startswith("f32")}
+    out = {
+        "metric": METRIC, "value": head["s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["s"] * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["desc"], "N": N, "d": d, "tol": 5e-7, "a_i": head["stats"]["policy_a"],
+                   "r": 6 * d, "m_1": 4 * d, "K": head["stats"]["K"], "T_stage1": head["stats"]["T_stage1"],
+                   "T_stage2": head["stats"]["T_stage2"], "sketch": "SRHT", "value_is": "SPCG (SRHT), X FP32"},
+        "full_pcg_s": runs["f32_srht_pcg"]["s"], "full_pcg_iters": runs["f32_srht_pcg"]["stats"]["T_stage2"],
+        "speedup_vs_full_pcg": speedups["f32_srht"],
+        "rel_pred_error_vs_ols": {"spcg": head.get("rel"), "pcg": runs["f32_srht_pcg"].get("rel")},
+        "speedups_vs_full_pcg_same_sketch": speedups,
+        "solves": solves,
+        "roofline": rf, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    ctx.close()
+    return out
 
 
 def bench_single(args, wl, spcg, workloads, torch, dev):
@@ -149,63 +355,35 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
     N, d = p.N, p.d
     ctx = spcg.Context(0)
     beta = torch.zeros(d, dtype=torch.float64, device=dev)
-    W = None
-    methods = ["spcg", "pcg"]
     sketch = wl.get("sketch", "srht")
+    methods = [("spcg", "spcg", sketch, None), ("pcg", "pcg", sketch, None)]
     if sketch == "cs":
-        methods = ["spcg", "spcg_srht", "pcg"]
+        methods.insert(1, ("spcg_srht", "spcg", "srht", None))
+        methods.append(("pcg_srht", "pcg", "srht", None))
     if args.workload == "learned":
         from paper_2607_25272_amd import schedule
         W = schedule.load_weights(dev)
-        methods = ["learned", "spcg", "pcg"]
-
-    def make(method):
-        def solve(time_products=False, time_phases=False):
-            kw = dict(time_products=time_products, time_phases=time_phases, seed=1, col_scale=p.col_scale,
-                      sketch="srht" if method == "spcg_srht" else sketch)
-            if method == "learned":
-                kw.update(schedule="learned", weights=W)
-            _, st = spcg.spcg_solve(ctx, p.X, p.Y, beta=beta, method="pcg" if method == "pcg" else "spcg",
-                                    **kw)
-            return st
-        return solve
-
+        methods.insert(0, ("learned", "spcg", sketch, dict(schedule="learned", weights=W)))
+    err = None if args.skip_check else OlsError(p.X, p.Y, p.col_scale)
     res = {}
-    for method in methods:
-        solve = make(method)
-        dt, pms, pn, last = timed_solves(solve, args.steps, args.warmup, method)
-        ph = solve(time_phases=True)
-        torch.cuda.synchronize()
-        rel = None if args.skip_check else pred_error_vs_ols(p, beta)
-        torch.cuda.empty_cache()
-        res[method] = dict(s=dt, stats=last, phases=ph, prod_ms=pms, prod_n=pn, rel=rel)
-        log(f"{method}: {dt * 1e3:.3f} ms/solve, K={last['K']} T1={last['T_stage1']} T2={last['T_stage2']} "
-            f"a={last['policy_a']} stride={last['policy_stride']} syncs={last['host_syncs']} rel={rel} "
-            f"phases sketch={ph['t_sketch_ms']:.3f} precond={ph['t_precond_ms']:.3f} "
-            f"stage1={ph['t_stage1_ms']:.3f} stage2={ph['t_stage2_ms']:.3f} ms")
+    for name, method, sk, extra in methods:
+        r = measure(solver(spcg, ctx, p.X, p.Y, p.col_scale, beta, method, sk, extra), args.steps, args.warmup,
+                    name)
+        r["rel"] = err(beta) if err else None
+        res[name] = r
     head = "learned" if args.workload == "learned" else "spcg"
     sp, pc = res[head], res["pcg"]
-    # roofline of the full-data product (Stage II / full PCG dual pass): one
-    # read of X plus the FP64 response vector per launch
-    bpl = float(N) * d * p.X.element_size() + float(N) * 8.0
-    n_launch = sum(r["prod_n"] for r in res.values())
-    avg_ms = sum(r["prod_ms"] for r in res.values()) / max(n_launch, 1)
-    rf = roofline(avg_ms, n_launch, bpl, "product_ring_kernel (SG mode, full data)")
-    # the same product kernel streams the same X for the CountSketch variants
-    rf["traffic"] = SG_TRAFFIC_BYTES.get(wl.get("base", args.workload))
+    dom = dominant_class(sp["kernels"])
+    rf = roofline(sp["kernels"], dom, args.workload)
     cpu = None
     if not args.no_cpu_baseline:
-        n_s = min(args.cpu_sample, N // 2)
+        n_s = min(args.cpu_sample or 65536, N // 2)
         log(f"cpu baseline: oracle SPCG on {n_s} rows")
-        t_cpu, threads = cpu_baseline(p.x_f64(slice(0, n_s)), p.Y, n_s)
-        cpu = {"value": t_cpu * N / n_s, "unit": "s", "cores": threads, "kind": "oracle",
-               "sample": f"FP64 NumPy oracle SPCG on the first {n_s} rows (d={d}) of the same workload "
-                         f"took {t_cpu:.2f} s; value scaled linearly by N/{n_s}"}
-    dtype = {"f32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[wl["storage"]]
+        cpu = cpu_baseline(p.x_f64(slice(0, n_s)), p.Y, N, sp["stats"]["T_stage2"])
     out = {
         "metric": METRIC, "value": sp["s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sp["s"] * 1e3, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAME[wl["storage"]], "data": "synthetic",
         "config": {"workload": wl["desc"], "tol": 5e-7, "a_i": sp["stats"]["policy_a"], "r": 6 * d,
                    "m_1": 4 * d, "stage_stride": sp["stats"]["policy_stride"], "K": sp["stats"]["K"],
                    "T_stage1": sp["stats"]["T_stage1"], "T_stage2": sp["stats"]["T_stage2"],
@@ -213,20 +391,35 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
         "full_pcg_s": pc["s"], "full_pcg_iters": pc["stats"]["T_stage2"],
         "speedup_vs_full_pcg": pc["s"] / sp["s"],
         "rel_pred_error_vs_ols": {m: res[m]["rel"] for m in res},
-        "phases_ms": {m: {k: round(res[m]["phases"][k], 4) for k in
-                          ("t_sketch_ms", "t_precond_ms", "t_stage1_ms", "t_stage2_ms", "t_total_ms")}
-                      for m in res},
+        "phases_ms": {m: phases_dict(res[m]["phases"]) for m in res},
         "host_syncs": {m: res[m]["stats"]["host_syncs"] for m in res},
-        "roofline": rf, "cpu_baseline": cpu,
+        "roofline": rf, "kernels": {m: res[m]["kernels"] for m in res}, "cpu_baseline": cpu,
     }
     if sketch == "cs":
         out["spcg_srht_s"] = res["spcg_srht"]["s"]
+        out["pcg_srht_s"] = res["pcg_srht"]["s"]
         out["cs_speedup_vs_srht"] = res["spcg_srht"]["s"] / sp["s"]
     if args.workload == "learned":
         out["plain_schedule_s"] = res["spcg"]["s"]
         out["learned_gain_vs_plain"] = res["spcg"]["s"] / sp["s"]
     ctx.close()
     return out
+
+
+def timed_solves(solve, steps, warmup, label):
+    """Warm-up, then `steps` timed solves bracketed by device syncs (no
+    per-launch events); returns (seconds per solve, 0, 0, last stats)."""
+    import torch
+    log(f"{label}: warmup {warmup}")
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    log(f"{label}: timing {steps} solves")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        last = solve()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, 0.0, 0, last
 
 
 def bench_batched(args, spcg, workloads, torch, dev):
@@ -246,7 +439,9 @@ def bench_batched(args, spcg, workloads, torch, dev):
             return st
         dt, pms, pn, last = timed_solves(solve, args.steps, args.warmup, method)
         ph = solve(time_phases=True)[0]
+        last = solve(time_products=True)
         torch.cuda.synchronize()
+        pms, pn = last[0]["product_ms_sum"], last[0]["product_launches"]
         rel = None
         if not args.skip_check:
             rel = max(pred_error_vs_ols(q, b) for q, b in zip(probs, betas))
@@ -262,7 +457,11 @@ def bench_batched(args, spcg, workloads, torch, dev):
     launches_last = sp["stats"][0]["product_launches"] + pc["stats"][0]["product_launches"]
     bpl = (sp["bytes"] + pc["bytes"]) / max(launches_last, 1)
     avg_ms = (sp["prod_ms"] + pc["prod_ms"]) / max(sp["prod_n"] + pc["prod_n"], 1)
-    rf = roofline(avg_ms, sp["prod_n"] + pc["prod_n"], bpl, "mrhs_product_kernel (SG mode, full data, MFMA)")
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    rf = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+          "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
+          "kernel": "mrhs_product_kernel (SG mode, full data, MFMA)", "bytes_per_launch": bpl,
+          "avg_launch_ms": avg_ms, "launches": sp["prod_n"] + pc["prod_n"]}
     ctx.close()
     return {
         "metric": METRIC, "value": sp["s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -365,11 +564,14 @@ def bench_tuned(args, spcg, workloads, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="rows of the oracle's CPU sample (0: 32768 for d=1000 workloads, else 65536)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the whole problem (checks the CPU extrapolation; slow)")
     ap.add_argument("--skip-check", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one 1 GiB device-to-device copy (reference for the HBM byte counters)")
@@ -393,15 +595,39 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
+    wl = WORKLOADS[args.workload]
     if args.workload == "batched":
         out = bench_batched(args, spcg, workloads, torch, dev)
     elif args.workload == "paper":
         out = bench_paper(args, spcg, workloads, torch, dev)
     elif args.workload == "tuned":
         out = bench_tuned(args, spcg, workloads, torch, dev)
+    elif wl.get("headline"):
+        out = bench_headline(args, wl, spcg, workloads, torch, dev)
     else:
-        out = bench_single(args, WORKLOADS[args.workload], spcg, workloads, torch, dev)
+        out = bench_single(args, wl, spcg, workloads, torch, dev)
+    if args.cpu_full and args.workload not in ("batched", "paper", "tuned"):
+        out["cpu_full_check"] = cpu_full(args, wl, workloads, torch, dev, out)
     print(json.dumps(out), flush=True)
+
+
+def cpu_full(args, wl, workloads, torch, dev, out):
+    """The oracle on the whole problem, to check the extrapolated cpu_baseline."""
+    from oracle.spcg import spcg as oracle_spcg
+    p = workloads.make_config(wl["cfg"], device=dev, storage=wl["storage"])
+    X = p.x_f64().cpu().numpy()
+    Y = p.Y[:, 0].cpu().numpy()
+    del p
+    torch.cuda.empty_cache()
+    log(f"cpu full: oracle SPCG on all {X.shape[0]} rows")
+    t = {}
+    t0 = time.perf_counter()
+    _, info = oracle_spcg(X, Y, seed=1, timings=t)
+    total = time.perf_counter() - t0
+    est = out["cpu_baseline"]["value"] if out.get("cpu_baseline") else None
+    log(f"cpu full: {total:.1f} s (extrapolated {est})")
+    return {"s": total, "phases_s": t, "T": info["per_rhs"][0]["T"], "extrapolated_s": est,
+            "blas_threads": blas_threads(), "host_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":
