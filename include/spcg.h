@@ -244,6 +244,22 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
                    const spcg_precond_t* pc, double* beta, const spcg_stage_opts* opts,
                    spcg_stage_stats* stats);
 
+/* spcg_pcg_stage for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same PCG, kernels and results as spcg_pcg_stage with one
+ * right-hand side, but every workspace (product partials, d-space vectors,
+ * scalars and counters) lives in a static device array of about 4.3 MB that
+ * each device holds from the first context created on it until the process
+ * ends; the call itself allocates nothing.  Limits: k = 1 and d <= 1024
+ * (SHAPE otherwise); at most 256 product blocks.  All calls on one device
+ * share that array, so calls that overlap in time on one device (from any
+ * context or stream) race and must not be issued; each call clears the
+ * counters and the scalar record it needs before use.  Stopping tests still
+ * read the scalars back with one stream synchronisation each. */
+int spcg_pcg_stage_noalloc(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
+                           const spcg_precond_t* pc, double* beta, const spcg_stage_opts* opts,
+                           spcg_stage_stats* stats);
+
 /* ---- whole solve (Algorithm 1) ------------------------------------------ */
 
 #define SPCG_METHOD_SPCG 0      /* Algorithm 1 */

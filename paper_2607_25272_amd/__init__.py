@@ -17,7 +17,7 @@ from ._lib import (SPCG_BF16, SPCG_E_BREAKDOWN, SPCG_E_DTYPE, SPCG_E_HIP, SPCG_E
                    SPCG_METHOD_FULL_PCG, SPCG_METHOD_SPCG, SPCG_OK, SPCG_W_NOT_CONVERGED)
 
 __all__ = ["Context", "SpcgError", "spcg_sketch", "spcg_precond_build", "spcg_precond_from_r",
-           "spcg_pcg_stage", "spcg_solve", "spcg_solve_batched", "spcg_sketch_tables_host",
+           "spcg_pcg_stage", "spcg_pcg_stage_noalloc", "spcg_solve", "spcg_solve_batched", "spcg_sketch_tables_host",
            "spcg_mlp_forward", "spcg_mlp_loss_grad", "spcg_mlp_adam", "mat", "load"]
 
 _DTYPES = {
@@ -238,6 +238,20 @@ def spcg_pcg_stage(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False, 
     rc = ctx.check(ctx.lib.spcg_pcg_stage(ctx.h, ctypes.byref(Am), ctypes.byref(bm), c2, precond.h,
                                           ctypes.c_void_p(beta.data_ptr()), ctypes.byref(o),
                                           ctypes.byref(st)))
+    return {"iters": st.iters, "converged": bool(st.converged), "rho0": st.rho0, "rho": st.rho,
+            "ax_norm": st.ax_norm, "resid_norm2": st.resid_norm2, "rc": rc}
+
+
+def spcg_pcg_stage_noalloc(ctx, A, b, c2, precond, beta, iters, tol=0.0, refresh=False,
+                           check_every=1, col_scale=None):
+    """spcg_pcg_stage on the library's static scratch (k = 1, d <= 1024): the
+    call allocates no device memory."""
+    Am, bm = _as_mat(A, col_scale), _as_mat(b)
+    o = L.StageOpts(iters=iters, refresh_gradient=int(refresh), tol=tol, check_every=check_every)
+    st = L.StageStats()
+    rc = ctx.check(ctx.lib.spcg_pcg_stage_noalloc(ctx.h, ctypes.byref(Am), ctypes.byref(bm), c2,
+                                                  precond.h, ctypes.c_void_p(beta.data_ptr()),
+                                                  ctypes.byref(o), ctypes.byref(st)))
     return {"iters": st.iters, "converged": bool(st.converged), "rho0": st.rho0, "rho": st.rho,
             "ax_norm": st.ax_norm, "resid_norm2": st.resid_norm2, "rc": rc}
 

@@ -113,6 +113,8 @@ SIGNATURES = [
     ("spcg_precond_free", None, [c_vp]),
     ("spcg_pcg_stage", c_i32, [c_vp, P(SpcgMat), P(SpcgMat), c_f64, c_vp, c_vp, P(StageOpts),
                                P(StageStats)]),
+    ("spcg_pcg_stage_noalloc", c_i32, [c_vp, P(SpcgMat), P(SpcgMat), c_f64, c_vp, c_vp, P(StageOpts),
+                               P(StageStats)]),
     ("spcg_solve", c_i32, [c_vp, P(SpcgMat), P(SpcgMat), P(SolveOpts), c_vp, P(SolveStats)]),
     ("spcg_solve_batched", c_i32, [c_vp, ctypes.c_int, P(SpcgMat), P(SpcgMat), P(SolveOpts), P(c_vp),
                                    P(SolveStats)]),

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,6 +55,42 @@ struct DevBuf {
 
 constexpr int MAX_TIMED = 256;
 
+// Static scratch of spcg_pcg_stage_noalloc: product partials for at most
+// NA_BLOCKS blocks of NA_DMAX columns (s and g), the per-block scalars, the
+// d-space vectors and the PCG scalar record with its two counters.  Each
+// device holds its own copy for the life of the process; host code reaches
+// it only through the address that hipGetSymbolAddress returns on that
+// device (na_scratch_address), never through the symbol itself.
+constexpr int64_t NA_DMAX = 1024;
+constexpr int64_t NA_BLOCKS = 256;
+constexpr size_t NA_PART = (size_t)NA_BLOCKS * NA_DMAX;
+constexpr size_t NA_DVEC = 5 * (size_t)NA_DMAX + 1024;
+constexpr size_t NA_SCAL = 32;   // 256 bytes: PcgScalars and the counters
+constexpr size_t NA_DOUBLES = 2 * NA_PART + 2 * (size_t)NA_BLOCKS + NA_DVEC + NA_SCAL;
+__device__ __align__(256) double scratch[NA_DOUBLES];
+static_assert(sizeof(PcgScalars) + 2 * sizeof(unsigned int) <= NA_SCAL * sizeof(double), "scalar slot");
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+double* na_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of this device's scratch (the device must be current);
+// looked up once per device.
+hipError_t na_scratch_address(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= NA_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(na_mutex);
+    if (!na_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        na_ptr[device] = static_cast<double*>(p);
+    }
+    *out = na_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 namespace {
@@ -86,6 +123,9 @@ struct spcg_ctx {
     DevBuf scal;      // PcgScalars + counters
     int64_t dvec_dpad = 0;
     DevBuf colx;      // one column of beta (column-by-column multi-RHS stages)
+    // this device's copy of the allocation-free entry point's static scratch
+    // (device address from hipGetSymbolAddress at context creation)
+    double* na_scratch = nullptr;
     // sketch and preconditioner workspaces used by spcg_solve
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
     DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w, dense_wd, dense_tmp;
@@ -1735,6 +1775,11 @@ int spcg_ctx_create(int device, void* hip_stream, spcg_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
+    if (na_scratch_address(device, &c->na_scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SPCG_E_HIP;
+    }
 
     *out = c;
     return SPCG_OK;
@@ -1988,6 +2033,52 @@ int spcg_pcg_stage(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     }
     if (rc != SPCG_OK) return rc;
     if (opts->tol > 0.0 && !conv) {
+        fail(ctx, SPCG_W_NOT_CONVERGED, "stopping test not met in %d iterations", opts->iters);
+        return SPCG_W_NOT_CONVERGED;
+    }
+    return SPCG_OK;
+}
+
+int spcg_pcg_stage_noalloc(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
+                           const spcg_precond_t* pc, double* beta, const spcg_stage_opts* opts,
+                           spcg_stage_stats* stats) {
+    if (!ctx) return SPCG_E_INVALID_ARG;
+    int rc;
+    if ((rc = check_stage_args(ctx, A, b, pc, beta)) != SPCG_OK) return rc;
+    if (!opts || opts->iters < 0 || opts->tol < 0.0 || !(c2 > 0.0))
+        return fail(ctx, SPCG_E_INVALID_ARG, "bad stage options (iters >= 0, tol >= 0, c2 > 0)");
+    if (b->cols != 1) return fail(ctx, SPCG_E_SHAPE, "spcg_pcg_stage_noalloc takes one right-hand side");
+    if (A->cols > NA_DMAX)
+        return fail(ctx, SPCG_E_SHAPE, "spcg_pcg_stage_noalloc: d = %lld exceeds its static scratch (d <= %lld)",
+                    (long long)A->cols, (long long)NA_DMAX);
+    if (!ctx->na_scratch) return fail(ctx, SPCG_E_HIP, "static scratch address unavailable");
+    const int64_t d = A->cols;
+    // layout of the static scratch (see scratch above); every call reuses
+    // it, so the counters and the scalar record are cleared by kernels first
+    StageWs W;
+    double* base = ctx->na_scratch;
+    W.part_s = base;
+    W.part_g = base + NA_PART;
+    W.part_scal = base + 2 * NA_PART;
+    double* dv = W.part_scal + 2 * NA_BLOCKS;
+    stage_ws_layout(&W, dv, NA_DMAX, dv + NA_DVEC, beta, pc->pMinv, d);
+    W.num_cu = (int)std::min<int64_t>(ctx->num_cu, NA_BLOCKS);
+    HIP_TRY(ctx, run_counters_reset(ctx->stream, W.S.counters, 2));
+    HIP_TRY(ctx, run_scalars_reset(ctx->stream, W.S.sc));
+    StageRun run;
+    const bool refresh = opts->refresh_gradient || opts->tol > 0.0;
+    rc = stage_run(ctx, A, b, c2, pc, beta, opts->iters, opts->tol, refresh, opts->check_every, &run, nullptr,
+                   nullptr, &W);
+    if (stats) {
+        stats->iters = run.iters_done;
+        stats->converged = run.converged;
+        stats->rho0 = run.sc.rho0;
+        stats->rho = run.sc.rho;
+        stats->ax_norm = std::sqrt(std::max(run.sc.ax2, 0.0));
+        stats->resid_norm2 = run.sc.resid2_0;
+    }
+    if (rc != SPCG_OK) return rc;
+    if (opts->tol > 0.0 && !run.converged) {
         fail(ctx, SPCG_W_NOT_CONVERGED, "stopping test not met in %d iterations", opts->iters);
         return SPCG_W_NOT_CONVERGED;
     }
