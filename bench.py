@@ -313,7 +313,7 @@ def bench_headline(args, wl, spcg, workloads, torch, dev):
     rf["workload"] = "SPCG (SRHT) step at N=4e6, d=1000, FP32"
     cpu = None
     if not args.no_cpu_baseline:
-        n_s = min(args.cpu_sample or 32768, N // 2)
+        n_s = min(args.cpu_sample or 131072, N // 2)
         log(f"cpu baseline: oracle SPCG on {n_s} rows")
         cpu = cpu_baseline(p.X[:n_s], p.Y, N, head["stats"]["T_stage2"])
         log(f"cpu baseline: {cpu['sample']}")
@@ -569,7 +569,7 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="rows of the oracle's CPU sample (0: 32768 for d=1000 workloads, else 65536)")
+                    help="rows of the oracle's CPU sample (0: 131072 for the d=1000 headline, else 65536)")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle on the whole problem (checks the CPU extrapolation; slow)")
     ap.add_argument("--skip-check", action="store_true")
