@@ -17,7 +17,9 @@
  * Conventions shared by every call
  * --------------------------------
  * - Matrices are row-major: element (i, j) of an spcg_mat lives at
- *   data + (i * ld + j) * sizeof(element).  ld >= cols.
+ *   data + (i * ld + j) * sizeof(element).  ld >= cols.  The allocation
+ *   behind a matrix spans rows * ld elements: kernels may read (never
+ *   write) the row padding between cols and ld, whose contents are ignored.
  * - All data pointers (matrix data, beta, col_scale, R) are DEVICE
  *   pointers on the context's device unless a parameter says "host".
  * - The caller owns X, Y and beta; the library never writes X or Y.
@@ -109,10 +111,12 @@ typedef struct spcg_sketch_opts {
                             F64 input); BF16 rows are rounded to nearest even. */
     int32_t transform_segment; /* tuning: 0 = library default (10- and 9-bit passes
                                   stream 128- or 256-byte row segments through LDS
-                                  in persistent blocks); 64, 128 or 256 selects one
-                                  tile per block with at most that many bytes per
-                                  row segment.  Results are bit-identical either
-                                  way. */
+                                  in persistent blocks; the 11-bit passes of
+                                  N' = 2^21 and 2^22 transforms stage half-tiles
+                                  of 2048 rows x 128 bytes); 64, 128 or 256
+                                  selects one tile per block with at most that
+                                  many bytes per row segment.  Results are
+                                  bit-identical either way. */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
     int32_t reserved; /* set to 0 */
     const int64_t* m_list; /* optional HOST array of the stage sizes m_1 < ... < m_K (replaces

@@ -481,11 +481,22 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     sk->pBh = bBh.p;
     // randomness tables and transform scratch (always context workspace)
     // randomness tables, then the round tables of the three Feistel streams
-    HIP_TRY(ctx, ctx->tables.ensure(((size_t)3 * Np + 3 * (size_t)feistel_table_size(L)) * sizeof(int32_t)));
+    // the 11-bit half-tile-staged last pass also reads both output slots per
+    // row in tile order (pair table after the round tables)
+    const int seg = o ? o->transform_segment : 0;
+    if (seg != 0 && seg != 64 && seg != 128 && seg != 256 && seg != -64)
+        return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128 or 256");
+    const int split = fwht_split_tables(X->dtype == SPCG_F64 ? DT_F64 : DT_F32, L, sk->ld, seg);
+    const size_t tsz = (size_t)3 * Np + 3 * (size_t)feistel_table_size(L);
+    const size_t tpad = (size_t)round_up((int64_t)(tsz * sizeof(int32_t)), 16);
+    const size_t psz = (split & 2) ? (size_t)Np * sizeof(int2) : 0;
+    HIP_TRY(ctx, ctx->tables.ensure(tpad + psz + ((split & 1) ? (size_t)Np / 4 : 0)));
     int32_t* perm_sign = ctx->tables.as<int32_t>();
     int32_t* inv_slot = perm_sign + Np;
     int32_t* inv_hat = perm_sign + 2 * Np;
     uint32_t* rt = reinterpret_cast<uint32_t*>(perm_sign + 3 * Np);
+    int2* pair_t = (split & 2) ? reinterpret_cast<int2*>(ctx->tables.as<char>() + tpad) : nullptr;
+    uint32_t* row_masks = (split & 1) ? reinterpret_cast<uint32_t*>(ctx->tables.as<char>() + tpad + psz) : nullptr;
     const size_t zx = (size_t)Np * sk->ld * es;
     const size_t zy = (size_t)Np * sk->ldy * 8;
     HIP_TRY(ctx, ctx->zbuf.ensure(std::max(zx, zy)));
@@ -501,9 +512,11 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     }
     HIP_TRY(ctx, launch_sketch_round_tables(st, sk->seed, L, rt));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
-    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, nullptr, nullptr, rt));
+    HIP_TRY(ctx, launch_sketch_tables(st, sk->seed, L, mK, r, perm_sign, nullptr, nullptr, rt, nullptr, 0, row_masks,
+                                      N));
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_side_fork, 0));
-    HIP_TRY(ctx, launch_sketch_tables(ctx->side, sk->seed, L, mK, r, nullptr, mK ? inv_slot : nullptr, inv_hat, rt));
+    HIP_TRY(ctx, launch_sketch_tables(ctx->side, sk->seed, L, mK, r, nullptr, mK ? inv_slot : nullptr, inv_hat, rt,
+                                      pair_t, L / 2));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_join, ctx->side));
     FwhtJob jx{};
     jx.x = X->data;
@@ -523,13 +536,13 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     jx.Bh = sk->pBh;
     jx.ldbh = sk->ld;
     jx.b_bf16 = sk->bdtype == DT_BF16;
-    jx.seg_bytes = o ? o->transform_segment : 0;
-    if (jx.seg_bytes != 0 && jx.seg_bytes != 64 && jx.seg_bytes != 128 && jx.seg_bytes != 256)
-        return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128 or 256");
+    jx.seg_bytes = seg;
     jx.narrow = 0;
     jx.stream = 1;
     jx.num_cu = ctx->num_cu;
     jx.wait_before_last = ctx->ev_side_join;
+    jx.slot_pairs = pair_t;
+    jx.row_masks = row_masks;
     if (ctx->kt_on) {
         // algorithmic bytes of each pass (used columns only)
         const int np = fwht_passes(L);

@@ -17,8 +17,16 @@ namespace spcg {
 //   inv_hat[k]   = pi_hat^{-1}(k) if < r,  else -1
 // rt: the round tables of the p, pi and pi_hat streams (written by
 // launch_sketch_round_tables before).  1 <= L <= 30.
+// pair_t (optional, with inv_slot or inv_hat): both output slots of row k
+// at index (k mod 2^plo) 2^(L - plo) + k / 2^plo, so that a last transform
+// pass over bits [plo, L) finds the slots of one tile's rows contiguously.
+// row_masks (optional, with perm_sign; N = the unpadded row count): for each
+// group of 16 rows k = 16 g + t, bit t = sign bit of row k and bit 16 + t =
+// (p(k) < N), so that a first transform pass reads one word per 16 rows.
 hipError_t launch_sketch_tables(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
-                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt);
+                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt,
+                                int2* pair_t = nullptr, int plo = 0, uint32_t* row_masks = nullptr,
+                                int64_t N = 0);
 // Round tables of the p, pi and pi_hat streams: 3 feistel_table_size(L)
 // words, one launch.
 hipError_t launch_sketch_round_tables(hipStream_t st, uint64_t seed, int L, uint32_t* rt);
@@ -57,7 +65,17 @@ struct FwhtJob {
                                   // first pass)
     hipEvent_t pass_ev[6];        // optional timing events: pass i (< 3) is
                                   // bracketed by pass_ev[2i] and pass_ev[2i+1]
+    const uint32_t* row_masks;    // optional: launch_sketch_tables' row_masks (sign and
+                                  // validity of 16 rows per word) for the split first pass
+    const int2* slot_pairs;       // optional: (inv_slot, inv_hat) per row in the order of
+                                  // launch_sketch_tables' pair_t with plo = the last pass's
+                                  // first bit (lets 11-bit last passes stage them in LDS)
 };
+// Tables that the half-tile-staged 11-bit passes of an N' = 2^L transform
+// read (FP32 working precision, two passes, the first of 11 bits): bit 0
+// FwhtJob::row_masks (first pass), bit 1 FwhtJob::slot_pairs (an 11-bit
+// last pass, plo = 11).  0: run_fwht does not use that kernel.
+int fwht_split_tables(int in_dtype, int L, int64_t ldz, int seg_bytes);
 // Widest column chunk of the transform (256-byte row segments): every row
 // width used by a job (ldz, ldb, ldbh) must be equal and a multiple of it.
 inline int fwht_chunk_cols(int in_dtype, int narrow) {

@@ -38,7 +38,8 @@ __global__ void feistel_table_kernel(uint64_t seed, int L, int n, uint64_t s0, u
 __global__ __launch_bounds__(256) void tables_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int64_t r,
                                                      int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat,
                                                      const uint32_t* rt_p, const uint32_t* rt_pi,
-                                                     const uint32_t* rt_pihat) {
+                                                     const uint32_t* rt_pihat, int2* pair_t, int plo,
+                                                     uint32_t* row_masks, int64_t N) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool in = k < np;
     if (perm_sign) {
@@ -49,21 +50,36 @@ __global__ __launch_bounds__(256) void tables_kernel(uint64_t seed, int L, int64
             for (int i = 0; i < 4; ++i) sw[i] = w.v[i];
         }
         __syncthreads();
+        uint32_t sb = 0, pk = 0;
         if (in) {
             const uint32_t b = (uint32_t)(k & 255);
-            const uint32_t sb = (uint32_t)((sw[b >> 6] >> (b & 63)) & 1ull);
-            perm_sign[k] = (int32_t)(feistel_fwd_tab((uint32_t)k, L, rt_p) | (sb << 31));
+            sb = (uint32_t)((sw[b >> 6] >> (b & 63)) & 1ull);
+            pk = feistel_fwd_tab((uint32_t)k, L, rt_p);
+            perm_sign[k] = (int32_t)(pk | (sb << 31));
+        }
+        if (row_masks) {
+            // 16-row groups are 16-lane groups of the wave (np >= 16 rows)
+            const uint64_t sbits = __ballot(in && sb);
+            const uint64_t vbits = __ballot(in && (int64_t)pk < N);
+            const int g = (threadIdx.x & 63) >> 4;
+            if (in && (threadIdx.x & 15) == 0)
+                row_masks[k >> 4] = (uint32_t)((sbits >> (16 * g)) & 0xffffu) |
+                                    ((uint32_t)((vbits >> (16 * g)) & 0xffffu) << 16);
         }
     }
     if (!in) return;
+    int32_t s_slot = -1, s_hat = -1;
     if (inv_slot) {
         const int64_t t = feistel_inv_tab((uint32_t)k, L, rt_pi);
-        inv_slot[k] = t < mK ? (int32_t)t : -1;
+        s_slot = t < mK ? (int32_t)t : -1;
+        inv_slot[k] = s_slot;
     }
     if (inv_hat) {
         const int64_t t = feistel_inv_tab((uint32_t)k, L, rt_pihat);
-        inv_hat[k] = t < r ? (int32_t)t : -1;
+        s_hat = t < r ? (int32_t)t : -1;
+        inv_hat[k] = s_hat;
     }
+    if (pair_t) pair_t[((k & ((1ll << plo) - 1)) << (L - plo)) | (k >> plo)] = make_int2(s_slot, s_hat);
 }
 
 __global__ void export_kernel(uint64_t seed, int L, int64_t np, int64_t mK, int64_t r,
@@ -195,6 +211,8 @@ struct PassArgs {
     void* Bh;
     int64_t ldbh;
     int b_bf16;        // store B rows as BF16
+    const int2* slot_pairs;   // split last pass: (inv_slot, inv_hat) per row, tile-contiguous
+    const uint32_t* row_masks;   // split first pass: sign / validity bits of 16 rows per word
     int lo, nb, q;
     int64_t nchunks, ntiles;
     // chunk-major Z of a two-pass streaming transform (zt_hibits > 0): the
@@ -407,6 +425,10 @@ constexpr int stream_vmcnt0() { return (0x7 << 4) | (0xf << 8); }   // s_waitcnt
 __device__ __forceinline__ void stream_lds_load16(const void* src, void* lds) {
     __builtin_amdgcn_global_load_lds(const_cast<void*>(src), (__attribute__((address_space(3))) void*)(lds),
                                      16, 0, 0);
+}
+__device__ __forceinline__ void stream_lds_load4(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds(const_cast<void*>(src), (__attribute__((address_space(3))) void*)(lds),
+                                     4, 0, 0);
 }
 
 template <typename TI>
@@ -672,6 +694,379 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     }
 }
 
+// 11-bit pass at FP32 working precision in persistent 1024-thread blocks
+// (one per CU) with half-tile staging.  A tile is 2048 rows x 32 columns
+// (128-byte row segments, 256 KB); it sits in registers (16 rows x 4
+// columns per thread) while it is transformed, and LDS holds one half-tile
+// of staged input (128 KB for FP32 rows) and a 32 KB exchange buffer.
+//
+// Row bits of a tile and where they live.  At load, thread (wave w, lane l)
+// holds rows t | (l >> 3) << 4 | w << 7, t < 16 its register index, so
+// stages 0..3 run on register bits, stages 4..6 on lane bits 3..5 and
+// stages 7..10 on the wave index:
+//   stage 4 (lane bit 3): the partner's value from a DPP row rotation by 8,
+//            then fma(+-1, x, partner): x + p below, p - x above;
+//   stage 5 (lane bit 4): v_permlane16_swap of registers t and t + 8 gives
+//            both pairs' operands in place; their sum and difference are
+//            the two results, which swaps row bit 5 into register bit 3 and
+//            row bit 3 into lane bit 4;
+//   stage 6 (lane bit 5): the same with v_permlane32_swap on registers t and
+//            t + 4 (row bit 6 into register bit 2, row bit 2 into lane bit 5);
+// then one exchange through LDS (per column element, two 32 KB rounds by
+// row bit 2, which is lane bit 5 on both sides) brings row bits 7..10 into
+// the registers, and stages 7..10 run there.  Every stage is the butterfly
+// (a, b) -> (a + b, a - b) in ascending stage order, as in fwht_pass_kernel,
+// so the output is bit-identical to it.
+//
+// Per tile j:
+//   A  the first half (row bit 10 = 0, staged during tile j-1) goes to the
+//      registers of waves 0..7; the direct loads of the second half are
+//      issued into the freed staging buffer; waves 0..7 run stages 0..6;
+//   B  once the second half has landed, waves 8..15 take it and run stages
+//      0..6; the direct loads of the next tile's first half are issued;
+//   C  the exchange, stages 7..10, one vmcnt(0) wait (the next first half
+//      has landed), and the stores, which drain during the next A phase.
+constexpr int SPLIT_THREADS = 1024;
+
+template <typename TIN, bool FIRST, bool LAST, int DW>
+__global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
+    constexpr int CW = 32, VL = 4, R = 16, THREADS = SPLIT_THREADS;
+    constexpr int LPR = CW / VL;                 // 8 lanes per tile row
+    constexpr int NB = 11, HALF = 1 << (NB - 1);
+    typedef typename std::conditional<FIRST, TIN, float>::type TI;   // staged element
+    constexpr int IB = (int)sizeof(TI);
+    constexpr int ROWB = CW * IB;                // staged bytes per tile row
+    constexpr int STG = HALF * ROWB;             // one half-tile
+    constexpr int NI = STG / (THREADS * DW);     // direct loads of DW bytes per thread per half-tile
+    constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;
+    static_assert(NI >= 1 && NI * THREADS * DW == STG && !(FIRST && LAST) && (DW == 16 || (FIRST && DW == 4)),
+                  "split tile shape");
+    __shared__ __align__(16) unsigned char stg[STG];
+    __shared__ __align__(16) float exb[HALF * LPR];
+
+    const int64_t T = a.ntiles;
+    const int64_t G = gridDim.x;
+    int64_t first, stride, count;
+    if ((G & 7) == 0 && (T & 7) == 0) {
+        const int64_t per = T >> 3, M = G >> 3, m = blockIdx.x >> 3;
+        first = (int64_t)(blockIdx.x & 7) * per + m;
+        stride = M;
+        count = m < per ? (per - m + M - 1) / M : 0;
+    } else {
+        first = blockIdx.x;
+        stride = G;
+        count = (int64_t)blockIdx.x < T ? (T - blockIdx.x + G - 1) / G : 0;
+    }
+    if (count == 0) return;   // uniform over the block
+
+    const int lo = a.lo;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int myhalf = wave >> 3;
+    auto srow = [](int row) -> int { return row ^ ((row >> 4) & SM); };
+    struct Tile {
+        int64_t rowbase;
+        int64_t cbase;
+    };
+    // tile index = o * nchunks + cc, walked incrementally (uniform scalars)
+    auto tile_at = [&](int64_t o, int64_t cc) -> Tile {
+        const int64_t olo = o & ((1ll << lo) - 1);
+        const int64_t ohi = o >> lo;
+        return Tile{(ohi << (lo + NB)) | olo, cc * CW};
+    };
+    const int64_t nch = a.nchunks;
+    int64_t o_cur = first / nch, c_cur = first - (first / nch) * nch;
+    auto advance = [&](int64_t& o, int64_t& c) {
+        c += stride;
+        while (c >= nch) {
+            c -= nch;
+            ++o;
+        }
+    };
+    auto grow = [&](const Tile& tl, int r) -> int64_t { return tl.rowbase | ((int64_t)r << lo); };
+    auto zoff = [&](int64_t k, int64_t col) -> int64_t {
+        if (a.zt_hibits == 0) return k * a.ldz + col;
+        const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
+        return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
+    };
+    // tile row of register t at load (stage bits 0..3 in registers); lx is
+    // an opaque copy of the lane index (see the loop)
+    auto load_row = [&](int t, int lx) -> int { return t | ((lx >> 3) << 4) | (wave << 7); };
+    // tile row of register t after the exchange (stage bits 7..10 in registers)
+    auto final_row = [&](int t, int lx) -> int {
+        return (wave & 1) | ((wave >> 1) & 1) << 1 | (lx >> 5) << 2 | ((lx >> 4) & 1) << 3 | ((lx >> 3) & 1) << 4 |
+               ((wave >> 2) & 1) << 5 | ((wave >> 3) & 1) << 6 | t << 7;
+    };
+    // half-tile row and DW-byte piece that direct load i of this lane fetches
+    auto dma_slot = [&](int i, int lx, int& row, int& piece) {
+        const int P = ((wave * NI + i) * 64 + lx) * DW;
+        row = srow(P / ROWB);
+        piece = (P % ROWB) / DW;
+    };
+    // first pass: the direct loads of wave w fetch the half-tile rows
+    // [64 w, 64 w + 64); lane l loads the permutation entry of row 64 w + l
+    // and each load's row entry comes from its lane by a cross-lane permute
+    auto load_dperm = [&](const Tile& tl, int h, int lx) __attribute__((always_inline)) -> int32_t {
+        return a.perm_sign[(uint32_t)grow(tl, h * HALF + wave * 64 + lx)];
+    };
+    // first pass: sign (bit t) and validity (bit 16 + t) of this thread's 16
+    // consecutive rows, one word of the row-mask table
+    auto load_cmask = [&](const Tile& tl, int lx) __attribute__((always_inline)) -> uint32_t {
+        return a.row_masks[(uint32_t)grow(tl, load_row(0, lx)) >> 4];
+    };
+    auto issue_half = [&](const Tile& tl, int h, int32_t dp, int lx) __attribute__((always_inline)) {
+        unsigned char* dst = stg + wave * NI * 64 * DW;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            int row, piece;
+            dma_slot(i, lx, row, piece);
+            const int64_t col = tl.cbase + piece * (DW / IB);
+            const unsigned char* src;
+            if constexpr (FIRST) {
+                // rows past N and pieces past d read row 0; the reader zeroes them
+                const int32_t pe = __builtin_amdgcn_ds_bpermute((row - wave * 64) << 2, dp);
+                const int64_t sr = (int64_t)(pe & 0x7fffffff);
+                const bool ok = sr < a.N && col < a.d;
+                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+            } else {
+                src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, h * HALF + row), col) * 4;
+            }
+            if constexpr (DW == 16) stream_lds_load16(src, dst + i * 1024);
+            else stream_lds_load4(src, dst + i * 256);
+        }
+    };
+
+    float v[R][VL];
+    // this thread's rows of its half from the staging buffer
+    auto read_own = [&](const Tile& tl, uint32_t cm, int lx) __attribute__((always_inline)) {
+        const int64_t col0 = tl.cbase + (lx & 7) * VL;
+        const int base = (((wave & 7) << 3) | (lx >> 3)) << 4;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float x[VL];
+            StageRead<TI>::rd(stg + srow(base | t) * ROWB + (lx & 7) * VL * IB, a.col_scale, col0, x);
+            if constexpr (FIRST) {
+                const bool valid = (cm >> (16 + t)) & 1u;
+                const bool neg = (cm >> t) & 1u;
+#pragma unroll
+                for (int e = 0; e < VL; ++e) {
+                    float y = col0 + e < a.d ? x[e] : 0.f;
+                    if (neg) y = -y;
+                    v[t][e] = valid ? y : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VL; ++e) v[t][e] = x[e];
+            }
+        }
+    };
+    // stages on register bits [b0, b1), ascending
+    auto bfly = [&](int b0, int b1) __attribute__((always_inline)) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b >= b0 && b < b1) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    if (!(t & (1 << b))) {
+#pragma unroll
+                        for (int e = 0; e < VL; ++e) {
+                            const float x0 = v[t][e], x1 = v[t | (1 << b)][e];
+                            v[t][e] = x0 + x1;
+                            v[t | (1 << b)][e] = x0 - x1;
+                        }
+                    }
+                }
+            }
+        }
+    };
+    // stages 4..6 on the lane bits (see above)
+    auto lane_stages = [&](int lx) __attribute__((always_inline)) {
+        const float sg = (lx & 8) ? -1.f : 1.f;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const float p = __int_as_float(
+                    __builtin_amdgcn_update_dpp(0, __float_as_int(v[t][e]), 0x128, 0xf, 0xf, false));
+                v[t][e] = __builtin_fmaf(sg, v[t][e], p);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const auto w = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[t][e]),
+                                                                __float_as_uint(v[t + 8][e]), false, false);
+                const float xn = __uint_as_float(w[0]), yn = __uint_as_float(w[1]);
+                v[t][e] = xn + yn;
+                v[t + 8][e] = xn - yn;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (t & 4) continue;
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const auto w = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[t][e]),
+                                                                __float_as_uint(v[t + 4][e]), false, false);
+                const float xn = __uint_as_float(w[0]), yn = __uint_as_float(w[1]);
+                v[t][e] = xn + yn;
+                v[t + 4][e] = xn - yn;
+            }
+        }
+    };
+    // row bits 7..10 into the registers: per column element, two rounds by
+    // row bit 2 (lane bit 5 before and after); exchange index of a row:
+    // r3 | r4 << 1 | r0 << 2 | r1 << 3 | r5 << 4 | r6 << 5 | r7..r10 << 6
+    auto exchange = [&](int lx) __attribute__((always_inline)) {
+        const int lrx = lx & 7, x3 = (lx >> 3) & 1, x4 = (lx >> 4) & 1, x5 = lx >> 5;
+        const int wbase = ((x4 | x3 << 1 | wave << 6) << 3) + lrx;
+        const int rbase = ((x4 | x3 << 1 | wave << 2) << 3) + lrx;
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+#pragma unroll
+            for (int rho = 0; rho < 2; ++rho) {
+                const bool active = x5 == rho;
+                if (active) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        const int off = ((t & 1) << 2 | ((t >> 1) & 1) << 3 | ((t >> 3) & 1) << 4 | ((t >> 2) & 1) << 5) << 3;
+                        exb[wbase + off] = v[t][e];
+                    }
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) v[t][e] = exb[rbase + (t << 9)];
+                }
+                __syncthreads();
+            }
+        }
+    };
+
+    // completes every pending butterfly before this point (the scheduler
+    // would otherwise sink the last stages into the store loop and keep
+    // their partial sums live)
+    auto settle = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < VL; ++e)
+            asm volatile("" : "+v"(v[0][e]), "+v"(v[1][e]), "+v"(v[2][e]), "+v"(v[3][e]), "+v"(v[4][e]),
+                         "+v"(v[5][e]), "+v"(v[6][e]), "+v"(v[7][e]), "+v"(v[8][e]), "+v"(v[9][e]),
+                         "+v"(v[10][e]), "+v"(v[11][e]), "+v"(v[12][e]), "+v"(v[13][e]), "+v"(v[14][e]),
+                         "+v"(v[15][e]));
+    };
+
+    int32_t dpa = 0, dpb = 0;   // first pass: this lane's entry for the next first / second half-tile
+    uint32_t cm = 0;            // first pass: sign and validity of this thread's rows
+    {
+        const Tile t0 = tile_at(o_cur, c_cur);
+        if constexpr (FIRST) {
+            dpa = load_dperm(t0, 0, lane);
+            __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        }
+        issue_half(t0, 0, dpa, lane);
+        if constexpr (FIRST) {
+            cm = load_cmask(t0, lane);
+            dpb = load_dperm(t0, 1, lane);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+
+    for (int64_t j = 0; j < count; ++j) {
+        const Tile tl = tile_at(o_cur, c_cur);
+        int64_t o_nx = o_cur, c_nx = c_cur;
+        advance(o_nx, c_nx);
+        const Tile tn = tile_at(o_nx, c_nx);
+        // an opaque copy of the lane index, renewed per phase: lane-dependent
+        // addresses are recomputed where they are used instead of being
+        // hoisted out of the loop into registers
+        int lx = lane;
+        asm volatile("" : "+v"(lx));
+        // ---- A: first half
+        __syncthreads();   // every wave has waited for its loads of the first half
+        if (myhalf == 0) read_own(tl, cm, lx);
+        __syncthreads();   // staging free
+        asm volatile("" : "+v"(lx));
+        issue_half(tl, 1, dpb, lx);
+        if constexpr (FIRST) {
+            if (j + 1 < count) dpa = load_dperm(tn, 0, lx);
+        }
+        if (myhalf == 0) {
+            bfly(0, 4);
+            asm volatile("" : "+v"(lx));
+            lane_stages(lx);
+        }
+        __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        // ---- B: second half
+        __syncthreads();   // the second half is complete in every wave
+        asm volatile("" : "+v"(lx));
+        if (myhalf == 1) read_own(tl, cm, lx);
+        __syncthreads();   // staging free
+        asm volatile("" : "+v"(lx));
+        if (j + 1 < count) {
+            issue_half(tn, 0, dpa, lx);
+            if constexpr (FIRST) {
+                cm = load_cmask(tn, lx);
+                dpb = load_dperm(tn, 1, lx);
+            }
+        }
+        if (myhalf == 1) {
+            bfly(0, 4);
+            asm volatile("" : "+v"(lx));
+            lane_stages(lx);
+        }
+        // ---- C: stages 7..10 and the stores
+        asm volatile("" : "+v"(lx));
+        exchange(lx);
+        if constexpr (LAST) {
+            // the output slots of this tile's rows (contiguous in slot_pairs)
+            // into the free exchange buffer
+            asm volatile("" : "+v"(lx));
+            const int2* src = a.slot_pairs + ((tl.rowbase & ((1ll << lo) - 1)) << NB) + (wave * 64 + lx) * 2;
+            stream_lds_load16(src, reinterpret_cast<unsigned char*>(exb) + wave * 1024);
+        }
+        bfly(0, 4);
+        settle();
+        // the next first half (and the table loads) are complete after this
+        // wait; the stores below drain during the next tile
+        __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        if constexpr (LAST) __syncthreads();   // the slot pairs are visible
+        // one row at a time: the opaque lane copy keeps the compiler from
+        // computing all sixteen 64-bit store addresses up front
+        if constexpr (LAST) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                asm volatile("" : "+v"(lx));
+                const int2 pr = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+                const int64_t col0 = tl.cbase + (lx & 7) * VL;
+                if (pr.x >= 0) {
+                    if (a.b_bf16) {
+                        bf16_store4(static_cast<uint16_t*>(a.B) + (int64_t)pr.x * a.ldb + col0, v[t]);
+                    } else {
+                        ZVec<float>::st(static_cast<float*>(a.B) + (int64_t)pr.x * a.ldb + col0, v[t]);
+                    }
+                }
+                if (pr.y >= 0) ZVec<float>::st(static_cast<float*>(a.Bh) + (int64_t)pr.y * a.ldbh + col0, v[t]);
+            }
+        } else {
+            // Z offsets are linear in the register index (row step 128)
+            asm volatile("" : "+v"(lx));
+            const int64_t col0 = tl.cbase + (lx & 7) * VL;
+            const int64_t z0 = zoff(grow(tl, final_row(0, lx)), col0);
+            const int64_t zs = zoff(grow(tl, final_row(1, lx)), col0) - z0;
+            float* p = static_cast<float*>(a.zout) + z0;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                ZVec<float>::st(p, v[t]);
+                p += zs;
+                asm volatile("" : "+v"(p));
+            }
+        }
+        o_cur = o_nx;
+        c_cur = c_nx;
+    }
+}
+
 // Threads per block and register window for a pass of nb bits.
 template <typename TZ, int CW>
 inline int pass_q(int nb) {
@@ -726,6 +1121,25 @@ hipError_t launch_stream_one(hipStream_t st, const PassArgs& a, int64_t grid) {
     return hipGetLastError();
 }
 
+// dw4: the first pass stages rows of X with 4-byte direct loads (FP8 rows
+// whose length is not a multiple of 16 bytes)
+template <typename TIN>
+hipError_t launch_split(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
+    const dim3 g((unsigned)grid), b(SPLIT_THREADS);
+    if (first && last) return hipErrorInvalidValue;
+    if (first && dw4) {
+        if constexpr (std::is_same<TIN, fp8_t>::value) fwht_split_kernel<TIN, true, false, 4><<<g, b, 0, st>>>(a);
+        else return hipErrorInvalidValue;
+    } else if (first) {
+        fwht_split_kernel<TIN, true, false, 16><<<g, b, 0, st>>>(a);
+    } else if (last) {
+        fwht_split_kernel<TIN, false, true, 16><<<g, b, 0, st>>>(a);
+    } else {
+        fwht_split_kernel<TIN, false, false, 16><<<g, b, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
 template <typename TIN, int CW>
 hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last) {
     if (first && last) return hipErrorInvalidValue;
@@ -759,10 +1173,15 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     a.Bh = job.Bh;
     a.ldbh = job.ldbh;
     a.b_bf16 = job.b_bf16;
+    a.slot_pairs = job.slot_pairs;
+    a.row_masks = job.row_masks;
     constexpr int VL = ZVec<TZ>::VL;
     a.xvec = (job.ldx % VL == 0) && ((uintptr_t)job.x % (VL * sizeof(TIN)) == 0);
     // the first pass stages rows of X with 16-byte direct loads
     const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
+    // FP8 rows of a length that is a multiple of 4 bytes (4-byte direct loads)
+    const bool xdma4 = std::is_same<TIN, fp8_t>::value && (uintptr_t)job.x % 4 == 0 && job.ldx % 4 == 0;
+    const int split = fwht_split_tables(job.in_dtype, L, job.ldz, job.seg_bytes);
     // column width of the streaming kernel for a pass (0: one tile per block).
     // 11-bit passes would need 64-byte rows (CW = 16); with chunk-major Z the
     // tiled kernel's 128-byte rows measured faster there (2.71 against
@@ -770,9 +1189,10 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     auto stream_cw = [&](int nb, bool first) -> int {
         if (!std::is_same<TZ, float>::value) return 0;
         // 1024 x 128 B or 512 x 256 B tiles (128 KB each); 256 x 512 B tiles
-        // for 8 bits would spill registers in the first pass
-        const int scw = nb == 10 ? 32 : nb == 9 ? 64 : 0;
-        if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes != 0 || job.ldz % scw != 0 ||
+        // for 8 bits would spill registers in the first pass.  seg_bytes = -64
+        // also streams 11-bit passes in 2048 x 64 B tiles.
+        const int scw = nb == 10 ? 32 : nb == 9 ? 64 : (nb == 11 && job.seg_bytes == -64) ? 16 : 0;
+        if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes > 0 || job.ldz % scw != 0 ||
             (first && !xdma))
             return 0;
         return scw;
@@ -809,6 +1229,26 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             if (e != hipSuccess) return e;
         }
         if constexpr (std::is_same<TZ, float>::value) {
+            // 11-bit passes with half-tile staging (128-byte row segments)
+            if (nb == NB_MAX && job.stream && job.num_cu > 0 &&
+                (first ? (split & 1) && (xdma || xdma4) && job.row_masks : (split & 2) && job.slot_pairs)) {
+                a.lo = lo;
+                a.nb = nb;
+                a.q = 4;
+                a.nchunks = job.ldz / 32;
+                a.ntiles = (1ll << (L - nb)) * a.nchunks;
+                a.zin = job.zbuf;
+                a.zout = job.zbuf;
+                const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
+                const hipError_t e = launch_split<TIN>(st, a, grid, first, last, first && !xdma);
+                if (e != hipSuccess) return e;
+                if (ev1) {
+                    const hipError_t e1 = hipEventRecord(ev1, st);
+                    if (e1 != hipSuccess) return e1;
+                }
+                lo += nb;
+                continue;
+            }
             const int scw = stream_cw(nb, first);
             if (scw) {
                 a.lo = lo;
@@ -819,8 +1259,9 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
-                                               : launch_stream<TIN, 64>(st, a, grid, first, last);
+                const hipError_t e = scw == 32   ? launch_stream<TIN, 32>(st, a, grid, first, last)
+                                     : scw == 64 ? launch_stream<TIN, 64>(st, a, grid, first, last)
+                                                 : launch_stream<TIN, 16>(st, a, grid, first, last);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);
@@ -901,11 +1342,15 @@ hipError_t launch_sketch_round_tables(hipStream_t st, uint64_t seed, int L, uint
 }
 
 hipError_t launch_sketch_tables(hipStream_t st, uint64_t seed, int L, int64_t mK, int64_t r,
-                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt) {
+                                int32_t* perm_sign, int32_t* inv_slot, int32_t* inv_hat, const uint32_t* rt,
+                                int2* pair_t, int plo, uint32_t* row_masks, int64_t N) {
+    if (pair_t && (plo < 1 || plo >= L)) return hipErrorInvalidValue;
+    if (row_masks && (L < 4 || !perm_sign)) return hipErrorInvalidValue;
     if (L < 1 || L > 30 || !rt) return hipErrorInvalidValue;
     const int64_t np = 1ll << L, ts = feistel_table_size(L);
     tables_kernel<<<(unsigned)ceil_div(np, 256), 256, 0, st>>>(seed, L, np, mK, r, perm_sign, inv_slot, inv_hat,
-                                                                rt, rt + ts, rt + 2 * ts);
+                                                                rt, rt + ts, rt + 2 * ts, pair_t, plo, row_masks,
+                                                                N);
     return hipGetLastError();
 }
 
@@ -922,6 +1367,13 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
 }
 
 int fwht_passes(int L) { return (L + NB_MAX - 1) / NB_MAX; }
+
+int fwht_split_tables(int in_dtype, int L, int64_t ldz, int seg_bytes) {
+    if (in_dtype == DT_F64 || ldz % 32 != 0 || seg_bytes != 0) return 0;
+    if (L == 2 * NB_MAX) return 3;
+    if (L == 2 * NB_MAX - 1) return 1;
+    return 0;
+}
 
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {
     const int cw = fwht_chunk_cols(job.in_dtype, job.narrow);

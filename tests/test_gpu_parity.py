@@ -184,8 +184,8 @@ def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
     # through LDS in persistent blocks; transform_segment = 256 forces one
     # tile per block.  Same butterflies in the same order -> identical bits
     # (d = 37: rows whose 16-byte pieces straddle d, first pass on the tiled
-    # kernel and Z row-major; N' = 2^21: two tiled 11-bit passes with
-    # chunk-major Z in both runs)
+    # kernel and Z row-major; N' = 2^21: an 11-bit first pass, half-tile
+    # staged by default, with chunk-major Z in both runs)
     _log(f"sketch streaming {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 89)
     rows = []
@@ -213,6 +213,29 @@ def test_sketch_streaming_nine_bit_passes_match_tiled(S, ctx, storage, N, d, L):
         sk = S.spcg_sketch(ctx, p.X, p.Y, seed=6, col_scale=p.col_scale, transform_segment=seg)
         rows.append((_raw_rows(sk, len(sk.sizes) - 1), _raw_rows(sk, -1), sk.info.L))
     assert rows[0][2] == L
+    assert np.array_equal(rows[0][0], rows[1][0])
+    assert np.array_equal(rows[0][1], rows[1][1])
+
+
+@pytest.mark.parametrize("storage,N,d", [("f32", 2_200_001, 40), ("f32", 2_500_000, 37),
+                                         ("bf16", 2_300_000, 24), ("fp8", 2_150_000, 48),
+                                         ("fp8", 2_150_000, 44), ("fp8", 1_500_000, 44),
+                                         ("bf16", 1_200_000, 64)])
+def test_sketch_split_eleven_bit_passes_match_tiled(S, ctx, storage, N, d):
+    # 11-bit passes stage half-tiles of 2048 rows x 128 bytes: N' = 2^22
+    # (11 + 11 bits, both passes; d = 37: rows of X are not 16-byte aligned,
+    # so only the last pass) and N' = 2^21 (the 11-bit first pass, then a
+    # streamed 10-bit pass).  FP8 rows of 44 bytes are staged with 4-byte
+    # direct loads.  transform_segment = 256 runs one tile per block.  Same
+    # butterflies in the same order -> identical bits.
+    _log(f"sketch split 11-bit {storage} N={N} d={d}")
+    p = _problem(N, d, storage=storage, seed=N % 79)
+    rows = []
+    for seg in (0, 256):
+        sk = S.spcg_sketch(ctx, p.X, p.Y, seed=7, col_scale=p.col_scale, transform_segment=seg)
+        rows.append((_raw_rows(sk, len(sk.sizes) - 1), _raw_rows(sk, -1), sk.info.L))
+        del sk
+    assert rows[0][2] == (N - 1).bit_length()
     assert np.array_equal(rows[0][0], rows[1][0])
     assert np.array_equal(rows[0][1], rows[1][1])
 
