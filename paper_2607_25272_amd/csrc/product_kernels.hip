@@ -330,8 +330,10 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
 // loads (global_load_lds_dword / _dwordx4) fill; a tile holds NW rows, one
 // per wave.  While a wave works on tile t, the loads of tiles t+1 .. t+RING-1
 // are in flight without occupying registers, so about (RING-1) * NW rows per
-// CU are outstanding whatever the row width (registers only hold the
-// column accumulators).  Every wave issues the same loads per tile (rows
+// CU are outstanding (registers only hold the column accumulators).  The
+// ring is as deep as the LDS allows (ring_depth): 4 slots of 4 KB rows, 8
+// of 2 KB rows and 12 of 1 KB rows, so narrow rows (BF16, FP8) keep as
+// many bytes in flight as wide ones.  Every wave issues the same loads per tile (rows
 // past the block's range and vectors past the row are clamped to valid
 // addresses and ignored), so an explicit vmcnt wait covers exactly the
 // loads of the tile about to be read, and the s_barrier that follows makes
@@ -339,8 +341,20 @@ __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
 // is a separate LDS object, so the compiler's own waits for the loads into
 // one slot do not hold back reads of another.  In G/SG mode the FP64 b of
 // each row rides along as a 4-byte-per-lane load.
-constexpr int RING = 4;
+constexpr int RING_LDS = 150 * 1024;   // LDS bytes the ring may take
+constexpr int ring_depth(int slot) {
+    return slot * 12 <= RING_LDS ? 12 : slot * 8 <= RING_LDS ? 8 : slot * 6 <= RING_LDS ? 6 : 4;
+}
 constexpr int vmcnt_imm(int n) { return (n & 0xf) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8); }
+
+// f(std::integral_constant<int, I>) for I = B .. E-1, unrolled at compile time
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 template <int DMAB>
 __device__ __forceinline__ void lds_load(const void* src, void* lds) {
@@ -365,16 +379,47 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
     constexpr int NC = NSLOT * VEC;
     constexpr int DCOLS = NC * 64;
     constexpr int RW = NSLOT * 64 * DMAB;            // staged bytes of one row
-    constexpr int NOPS = NSLOT + (DO_G ? 1 : 0);    // loads per wave per tile
-    // one slot: NW staged rows, then (G/SG) 256 bytes per wave for b
-    constexpr int SLOT = NW * RW + (DO_G ? NW * 256 : 0);
+    // rows per wave and tile.  Two rows per wave (overlapping their
+    // dot-product and reduction chains) measured no faster for 1 KB FP8 or
+    // 2 KB BF16 rows of the SG mode: the VALU work per row (FP64 residual
+    // and gradient accumulation, 16 columns per lane) bounds them, not the
+    // per-row latency.
+    constexpr int RPW = 1;
+    constexpr int NOPS = RPW * (NSLOT + (DO_G ? 1 : 0));   // loads per wave per tile
+    // one slot: RPW x NW staged rows, then (G/SG) 256 bytes per row for b
+    constexpr int SLOT = RPW * NW * RW + (DO_G ? RPW * NW * 256 : 0);
+    constexpr int RING = ring_depth(SLOT);
     static_assert(DCOLS * 8 <= NW * RW, "reduction buffers alias the ring");
     static_assert((RING - 2) * NOPS < 64, "vmcnt range");
+    // one LDS object per slot (slots past RING are 16-byte placeholders)
     __shared__ __align__(16) unsigned char t0[SLOT];
     __shared__ __align__(16) unsigned char t1[SLOT];
     __shared__ __align__(16) unsigned char t2[SLOT];
     __shared__ __align__(16) unsigned char t3[SLOT];
+    __shared__ __align__(16) unsigned char t4[RING > 4 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t5[RING > 5 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t6[RING > 6 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t7[RING > 7 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t8[RING > 8 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t9[RING > 9 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t10[RING > 10 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char t11[RING > 11 ? SLOT : 16];
     __shared__ double red_scal[2 * NW];
+    auto slot = [&](auto kc) -> unsigned char* {
+        constexpr int k = decltype(kc)::value;
+        if constexpr (k == 0) return t0;
+        else if constexpr (k == 1) return t1;
+        else if constexpr (k == 2) return t2;
+        else if constexpr (k == 3) return t3;
+        else if constexpr (k == 4) return t4;
+        else if constexpr (k == 5) return t5;
+        else if constexpr (k == 6) return t6;
+        else if constexpr (k == 7) return t7;
+        else if constexpr (k == 8) return t8;
+        else if constexpr (k == 9) return t9;
+        else if constexpr (k == 10) return t10;
+        else return t11;
+    };
 
     // wave index as a wave-uniform (scalar) value: row offsets stay in SGPRs
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -404,73 +449,103 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
     const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = min(a.m, r0 + a.rpb);
     const int64_t rlast = r1 - 1;   // >= 0: a.m >= 1 and r1 = a.m for blocks past the end
-    const int64_t ntile = r1 > r0 ? (r1 - r0 + NW - 1) / NW : 0;
+    const int64_t ntile = r1 > r0 ? (r1 - r0 + NW * RPW - 1) / (NW * RPW) : 0;
     const char* Abase = static_cast<const char*>(a.A);
     const int64_t row_bytes = a.lda * Store<TS>::BYTES;
     const int64_t vlast = a.nvec - 1;
 
+    // row rr of this wave in tile `tile` (rows of a wave stay in order)
+    auto row_of = [&](int64_t tile, int rr) -> int64_t { return r0 + (tile * RPW + rr) * NW + wave; };
     auto issue = [&](int64_t tile, unsigned char* T) {
-        const int64_t row = min(r0 + tile * NW + wave, rlast);
-        const char* src = Abase + row * row_bytes;
 #pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-            const int64_t vi = min<int64_t>(s * 64 + lane, vlast);
-            lds_load<DMAB>(src + vi * DMAB, T + wave * RW + s * 64 * DMAB);
-        }
-        if constexpr (DO_G) {
-            lds_load<4>(reinterpret_cast<const char*>(a.b + row * a.ldbv) + 4 * (lane & 1), T + NW * RW + wave * 256);
+        for (int rr = 0; rr < RPW; ++rr) {
+            const int64_t row = min(row_of(tile, rr), rlast);
+            const char* src = Abase + row * row_bytes;
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const int64_t vi = min<int64_t>(s * 64 + lane, vlast);
+                lds_load<DMAB>(src + vi * DMAB, T + (rr * NW + wave) * RW + s * 64 * DMAB);
+            }
+            if constexpr (DO_G) {
+                lds_load<4>(reinterpret_cast<const char*>(a.b + row * a.ldbv) + 4 * (lane & 1),
+                            T + RPW * NW * RW + (rr * NW + wave) * 256);
+            }
         }
     };
     auto consume = [&](int64_t tile, const unsigned char* T) {
-        const int64_t row = r0 + tile * NW + wave;
-        if (row >= r1) return;
-        CT v[NC];
+        if (row_of(tile, 0) >= r1) return;
+        CT v[RPW][NC];
 #pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-            const Raw raw = *reinterpret_cast<const Raw*>(T + wave * RW + (s * 64 + lane) * DMAB);
-            Widen<TS, VEC, Raw>::run(raw, v + s * VEC);
+        for (int rr = 0; rr < RPW; ++rr) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const Raw raw = *reinterpret_cast<const Raw*>(T + (rr * NW + wave) * RW + (s * 64 + lane) * DMAB);
+                Widen<TS, VEC, Raw>::run(raw, v[rr] + s * VEC);
+            }
         }
-        CT dp = CT(0);
-        double dx = 0.0;
+        // two partial sums per dot product (even / odd columns of the lane)
+        CT dp[RPW][2];
+        double dx[RPW][2];
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            dp[rr][0] = dp[rr][1] = CT(0);
+            dx[rr][0] = dx[rr][1] = 0.0;
+        }
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            if (DO_S) dp = fma(v[i], preg[i], dp);
-            if (DO_G) dx = fma((double)v[i], xreg[i], dx);
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) {
+                if (DO_S) dp[rr][i & 1] = fma(v[rr][i], preg[i], dp[rr][i & 1]);
+                if (DO_G) dx[rr][i & 1] = fma((double)v[rr][i], xreg[i], dx[rr][i & 1]);
+            }
         }
-        if (DO_S) dp = wave_sum(dp);
-        double w = 0.0;
-        if constexpr (DO_G) {
-            dx = wave_sum(dx);
-            const double bb = *reinterpret_cast<const double*>(T + NW * RW + wave * 256);
-            w = bb - dx;
-            if (lane == 0) {
-                r2 = fma(w, w, r2);
-                ax2 = fma(dx, dx, ax2);
+        CT ps[RPW];
+        double w[RPW];
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr) {
+            // a row past the range (its loads were clamped to a valid row)
+            // contributes nothing
+            const bool live = row_of(tile, rr) < r1;
+            ps[rr] = CT(0);
+            w[rr] = 0.0;
+            if (DO_S) {
+                const CT t = wave_sum(dp[rr][0] + dp[rr][1]);
+                ps[rr] = live ? t : CT(0);
+            }
+            if constexpr (DO_G) {
+                const double ax = wave_sum(dx[rr][0] + dx[rr][1]);
+                const double bb = *reinterpret_cast<const double*>(T + RPW * NW * RW + (rr * NW + wave) * 256);
+                const double ww = bb - ax;
+                w[rr] = live ? ww : 0.0;
+                if (lane == 0 && live) {
+                    r2 = fma(ww, ww, r2);
+                    ax2 = fma(ax, ax, ax2);
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            if (DO_S) sacc[i] = fma(dp, v[i], sacc[i]);
-            if (DO_G) gacc[i] = fma(w, (double)v[i], gacc[i]);
+        for (int rr = 0; rr < RPW; ++rr) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (DO_S) sacc[i] = fma(ps[rr], v[rr][i], sacc[i]);
+                if (DO_G) gacc[i] = fma(w[rr], (double)v[rr][i], gacc[i]);
+            }
         }
     };
 
-    issue(0, t0);
-    issue(1, t1);
-    issue(2, t2);
-#define SPCG_RING_STEP(CUR, NXT, OFF)                           \
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm((RING - 2) * NOPS)); \
-    __builtin_amdgcn_s_barrier();                             \
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);                  \
-    issue(t + (OFF) + RING - 1, NXT);                         \
-    consume(t + (OFF), CUR);
+    static_for<0, RING - 1>([&](auto kc) { issue(decltype(kc)::value, slot(kc)); });
     for (int64_t t = 0; t < ntile; t += RING) {
-        SPCG_RING_STEP(t0, t3, 0)
-        SPCG_RING_STEP(t1, t0, 1)
-        SPCG_RING_STEP(t2, t1, 2)
-        SPCG_RING_STEP(t3, t2, 3)
+        // step k: wait for tile t + k (slot k), refill slot k - 1 (read
+        // at step k - 1, freed by this barrier) with tile t + k + RING - 1
+        static_for<0, RING>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm((RING - 2) * NOPS));
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            issue(t + k + RING - 1, slot(std::integral_constant<int, (k + RING - 1) % RING>{}));
+            consume(t + k, slot(kc));
+        });
     }
-#undef SPCG_RING_STEP
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
