@@ -277,6 +277,40 @@ def solver(spcg, ctx, X, Y, col_scale, beta, method, sketch, extra=None):
     return solve
 
 
+TUNED_SIZES = [1 << k for k in range(10, 17)] + [1 << 20]   # Sec. 4.3: 2^10 .. 2^16, then 2^20
+
+
+def learned_weights(dev):
+    """The shipped per-stage schedule network, or None if it is missing."""
+    from paper_2607_25272_amd import schedule
+    try:
+        return schedule.load_weights(dev)
+    except (OSError, ValueError) as e:
+        log(f"no learned schedule weights: {e}")
+        return None
+
+
+def solve_cost_fn(spcg, ctx, X, Y, sc, sketch):
+    """Bytes read by a solve's product passes (schedule.solve_cost) from its
+    stats; the stage sizes are those of the default sketch of (X, Y)."""
+    import torch
+    from paper_2607_25272_amd import schedule
+    sk = spcg.spcg_sketch(ctx, X, Y, seed=1, col_scale=sc, kind=sketch)
+    sizes = list(sk.sizes)
+    A, _, _ = sk.view(len(sizes) - 1)
+    e_b = {spcg.SPCG_F64: 8, spcg.SPCG_F32: 4, spcg.SPCG_BF16: 2}[A.dtype]
+    sk.free()
+    e_x = {torch.float64: 8, torch.float32: 4, torch.bfloat16: 2, torch.float8_e4m3fn: 1}[X.dtype]
+    N, d = X.shape
+
+    def cost(st, run_sizes=None):
+        sz = sizes if run_sizes is None else run_sizes
+        if st["stages_planned"] != len(sz):
+            return None
+        return schedule.solve_cost(st, sz, N, d, e_x, e_b, nested=sketch == "srht")
+    return cost
+
+
 def bench_headline(args, wl, spcg, workloads, torch, dev):
     """N=4e6, d=1000: SPCG vs full PCG with both sketch kinds on the FP32
     (unquantized) data, and the precision form in BF16 and FP8."""
@@ -291,13 +325,24 @@ def bench_headline(args, wl, spcg, workloads, torch, dev):
     err_unq = OlsError(p.X, p.Y)
     runs = {}
     plan = [("f32", "srht"), ("f32", "cs"), ("bf16", "srht"), ("fp8", "srht"), ("bf16", "cs"), ("fp8", "cs")]
+    W = learned_weights(dev)
+    # beside Algorithm 1 as written (a_i = 3, every prefix): the learned
+    # per-stage schedule and the Sec. 4.3 tuned sizes, with the SRHT
+    extra = {"learned": ("spcg", dict(schedule="learned", weights=W)) if W is not None else None,
+             "tuned": ("spcg", dict(m_list=TUNED_SIZES, a=4))}
+    costs = {}
     for storage, sk in plan:
         X, sc = stores[storage]
         err_st = err_unq if storage == "f32" else OlsError(X, p.Y, sc)
-        for method in ("spcg", "pcg"):
-            name = f"{storage}_{sk}_{method}"
-            r = measure(solver(spcg, ctx, X, p.Y, sc, beta, method, sk), args.steps, args.warmup, name,
+        cost = solve_cost_fn(spcg, ctx, X, p.Y, sc, sk)
+        methods = [("spcg", "spcg", None), ("pcg", "pcg", None)]
+        if sk == "srht":
+            methods += [(k, v[0], v[1]) for k, v in extra.items() if v is not None]
+        for mname, method, kw in methods:
+            name = f"{storage}_{sk}_{mname}"
+            r = measure(solver(spcg, ctx, X, p.Y, sc, beta, method, sk, kw), args.steps, args.warmup, name,
                         instrumented=2 if storage == "f32" or method == "spcg" else 1)
+            costs[name] = cost(r["stats"], TUNED_SIZES if mname == "tuned" else None)
             if not args.skip_check:
                 r["rel"] = err_st(beta)
                 r["rel_unquantized"] = err_unq(beta) if storage != "f32" else r["rel"]
@@ -328,6 +373,20 @@ def bench_headline(args, wl, spcg, workloads, torch, dev):
         return out
 
     solves = {name: line(r) for name, r in runs.items()}
+    for name in solves:
+        solves[name]["product_bytes_read"] = costs[name]
+    schedules = {}
+    for storage in ("f32", "bf16", "fp8"):
+        base = f"{storage}_srht_spcg"
+        for k in ("learned", "tuned"):
+            name = f"{storage}_srht_{k}"
+            if name in runs:
+                schedules[name] = {"time_plain_over_this": runs[base]["s"] / runs[name]["s"],
+                                   "bytes_plain_over_this": (costs[base] / costs[name]
+                                                             if costs[base] and costs[name] else None),
+                                   "stage_iters": runs[name]["stats"]["stage_iters"][
+                                       :runs[name]["stats"]["stages_planned"]],
+                                   "vs_full_pcg": runs[f"{storage}_srht_pcg"]["s"] / runs[name]["s"]}
     speedups = {f"{s}_{k}": runs[f"{s}_{k}_pcg"]["s"] / runs[f"{s}_{k}_spcg"]["s"] for s, k in plan}
     kernels = {name: r["kernels"] for name, r in runs.items() if name.endswith("_spcg") or name.startswith("f32")}
     out = {
@@ -341,6 +400,7 @@ def bench_headline(args, wl, spcg, workloads, torch, dev):
         "speedup_vs_full_pcg": speedups["f32_srht"],
         "rel_pred_error_vs_ols": {"spcg": head.get("rel"), "pcg": runs["f32_srht_pcg"].get("rel")},
         "speedups_vs_full_pcg_same_sketch": speedups,
+        "schedules_vs_plain": schedules,
         "solves": solves,
         "roofline": rf, "kernels": kernels, "cpu_baseline": cpu,
     }
@@ -400,8 +460,12 @@ def bench_single(args, wl, spcg, workloads, torch, dev):
         out["pcg_srht_s"] = res["pcg_srht"]["s"]
         out["cs_speedup_vs_srht"] = res["spcg_srht"]["s"] / sp["s"]
     if args.workload == "learned":
+        cost = solve_cost_fn(spcg, ctx, p.X, p.Y, p.col_scale, sketch)
+        cp, cl = cost(res["spcg"]["stats"]), cost(sp["stats"])
         out["plain_schedule_s"] = res["spcg"]["s"]
         out["learned_gain_vs_plain"] = res["spcg"]["s"] / sp["s"]
+        out["learned_bytes_plain_over_learned"] = cp / cl if cp and cl else None
+        out["learned_stage_iters"] = sp["stats"]["stage_iters"][:sp["stats"]["stages_planned"]]
     ctx.close()
     return out
 

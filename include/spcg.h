@@ -309,6 +309,10 @@ typedef struct spcg_solve_opts {
                                  Ignored for a CountSketch (its stages are not prefixes).
                                  spcg_solve_opts_default sets 1. */
     double omega;             /* SPCG_A_THEORY: the stagewise accuracy factor (0: 0.5) */
+    int32_t stage_limit;      /* plain schedule: run only the first stage_limit of the
+                                 planned stages (after stage_stride), Stage II next;
+                                 0: all.  A zero entry of a_list runs the stage's
+                                 start (its gradient) and no PCG iteration. */
 } spcg_solve_opts;
 
 /* a_i rules.  THEORY takes the stage iteration counts from Theorems 3.3
@@ -322,18 +326,23 @@ typedef struct spcg_solve_opts {
 
 /* Plain schedule: Algorithm 1 as written (a_i = a, every prefix, stopping
  * test after every check_every Stage II iterations).
- * Learned schedule: the network below is evaluated on the device twice.
- * (1) After the preconditioner is built, on the pre-Stage-I features; the
- *     arg-max of outputs 0..3 gives a (replacing opts.a and a_list) and of
- *     outputs 4..5 the stage stride (replacing opts.stage_stride).  One
- *     stream synchronisation reads the decision.
- * (2) At the start of Stage II, on the Stage II features, read with the
- *     scalars of the first stopping test; s_hat = 10 * output 6.  Stage II
- *     then runs max(0, round(s_hat) - margin) iterations without host
- *     synchronisation, applies the stopping test once, and, if it fails,
- *     continues with the plain test (the fallback) up to the budget T.
- * The result is always judged by the same stopping test as the plain
- * schedule. */
+ * Learned schedule: the network below decides on the device, per stage,
+ * with no stream synchronisation in Stage I.  The planned stages are every
+ * prefix m_0 < ... < m_{K-1} of the sketch (stage_stride, a, a_list and
+ * a_rule are ignored).  At the start of planned stage i (after its
+ * starting-gradient pass) the device computes the stage features, runs the
+ * network and takes a_i = arg-max of outputs 0..4 (PCG iterations of the
+ * stage, 0..4) and stop = arg-max of outputs 5..6; with stop = 1 the later
+ * stages are skipped entirely and Stage II follows.  The launches of every
+ * planned stage are queued up front; the kernels of a skipped start or
+ * iteration read the decision and return at once.  Stage I iterations are
+ * capped so that they total at most T - 1.  At the start of Stage II the
+ * network runs on the Stage II features, read with the scalars of the
+ * first stopping test; s_hat = 10 * output 7.  Stage II then runs
+ * max(0, round(s_hat) - margin) iterations without host synchronisation,
+ * applies the stopping test once, and, if it fails, continues with the
+ * plain test (the fallback) up to the budget T.  The result is always
+ * judged by the same stopping test as the plain schedule. */
 #define SPCG_SCHEDULE_PLAIN 0
 #define SPCG_SCHEDULE_LEARNED 1
 
@@ -350,16 +359,16 @@ typedef struct spcg_solve_stats {
     double product_ms_sum;      /* summed duration of the timed product launches */
     double product_bytes;       /* algorithmic bytes of one full-data product launch */
     int32_t host_syncs;         /* stream synchronisations made inside the solve */
-    int32_t policy_a;           /* a used in Stage I (the last a_i for an a_list) */
-    int32_t policy_stride;      /* stage stride used */
+    int32_t policy_a;           /* a of the last Stage I stage run */
+    int32_t policy_stride;      /* stage stride used (1 for the learned schedule) */
     int32_t unchecked_iters;    /* Stage II iterations run before the first test after the start */
     int32_t fallback;           /* learned: the plain test had to continue after the unchecked run */
     float s_pred;               /* learned: 10 * output 6 of the Stage II evaluation */
     double rho_ii0, ax2_ii0, resid2_ii0; /* Stage II start: g^T H^-1 g, ||X b||^2, ||Y - X b||^2 */
     float features_pre[8];      /* schedule features (learned, or record_features) */
     float features_ii[8];
-    float out_pre[8];           /* network outputs (learned; entries 0..6) */
-    float out_ii[8];
+    float out_pre[8];           /* unused (zero) */
+    float out_ii[8];            /* network outputs at the Stage II start (learned) */
     int32_t batch_tasks_per_cu; /* batched form: task granularity used in Stage II */
     int32_t batch_graphs;       /* batched form: executable graphs launched */
     /* time_products = 2 (single-problem solves): per kernel class, the
@@ -368,6 +377,13 @@ typedef struct spcg_solve_stats {
     double kernel_ms[8];
     double kernel_bytes[8];
     int32_t kernel_launches[8];
+    /* Stage I per planned stage i < stages_planned (<= 64): PCG iterations
+     * run (-1: stage not started), and for i < 16 the stage features and
+     * network outputs (learned; features also with record_features) */
+    int32_t stages_planned;
+    int32_t stage_iters[64];
+    float stage_features[16 * 8];
+    float stage_out[16 * 8];
 } spcg_solve_stats;
 
 /* Kernel classes of spcg_solve_stats.kernel_*.  Algorithmic bytes count
@@ -419,27 +435,39 @@ void spcg_solve_opts_default(spcg_solve_opts* opts);
  * library learns it: a dense network F -> H -> H -> O with ReLU after the
  * first two layers, all FP32.  Parameters are one flat array, in order
  * W1 (H x F row-major), b1 (H), W2 (H x H), b2 (H), W3 (O x H), b3 (O).
- * Outputs: 0..3 logits of a - 1, 4..5 logits of stride - 1, 6 the Stage II
- * count divided by SPCG_MLP_S_SCALE.
+ * Outputs: 0..4 logits of a_i (a stage's PCG iterations), 5..6 logits of
+ * stop (Stage I ends after this stage), 7 the Stage II count divided by
+ * SPCG_MLP_S_SCALE.
  *
  * Features (FP32, computed on the device; every value scale-free):
- *   f0 = log10 N - 5, f1 = log10 d - 2, f2 = log2(N / d) / 8 - 1,
+ *   base (before Stage I): f0 = log10 N - 5, f1 = log10 d - 2,
+ *   f2 = log2(N / d) / 8 - 1,
  *   f3 = log10(max|R_jj| / min|R_jj|) / 3 - 1 (3 if a diagonal entry is 0),
  *   f4 = log10(max q / mean q) / 2 over q_j = ||x_j||^2 of the rows
  *        floor((2t + 1) N / 512), t < 256 (every row if N < 256; 0 if all q are 0),
- *   pre-Stage-I: f5 = f6 = f7 = 0;
+ *   f5 = f6 = f7 = 0;
+ *   start of planned stage i of K (sizes m_0 < ... < m_{K-1}; res and fit
+ *   the residual and fit norms of the rows the starting-gradient pass
+ *   read: all m_i rows, or the new rows m_{i-1}..m_i of a nested start):
+ *   f2 = log2(m_i / d) / 8 - 1,
+ *   f5 = B_i / 4, B_i = ln{[1.5 r + 1] / 0.5} / ln 4 the Theorem 3.3 bound at
+ *        omega = 1/2, r = sqrt((m_i - d) / (m_{i-1} - d)) (i = 0: the pair
+ *        m_0, m_1; r = 1 if K = 1),
+ *   f6 = clamp(log10(res / fit) / 6, -2, 2) (-2 if res <= 0, 2 if fit <= 0),
+ *   f7 = i / K, the others as the base;
  *   Stage II start (rho = g^T H^-1 g, fit = ||X beta||^2, res = ||Y - X beta||^2):
  *   f5 = clamp(log10(sqrt(rho) / (tol sqrt(fit))) / 3, -3, 3) (-3 if rho <= 0, 3 if fit <= 0),
- *   f6 = clamp(log10(res / fit) / 6, -2, 2) (-2 if res <= 0, 2 if fit <= 0), f7 = 1.
+ *   f6 = clamp(log10(res / fit) / 6, -2, 2) (-2 if res <= 0, 2 if fit <= 0), f7 = 1,
+ *   the others as the base.
  *
- * Training loss of n samples with labels a in 0..3, g in 0..1, s >= 0 and
+ * Training loss of n samples with labels a in 0..4, g in 0..1, s >= 0 and
  * weights w_a, w_s:
- *   (1/n) sum [ w_a (CE(out[0:4], a) + CE(out[4:6], g))
- *               + w_s SPCG_MLP_LAMBDA (out[6] - s / SPCG_MLP_S_SCALE)^2 ]
+ *   (1/n) sum [ w_a (CE(out[0:5], a) + CE(out[5:7], g))
+ *               + w_s SPCG_MLP_LAMBDA (out[7] - s / SPCG_MLP_S_SCALE)^2 ]
  * with CE the softmax cross-entropy. */
 #define SPCG_MLP_F 8
 #define SPCG_MLP_H 64
-#define SPCG_MLP_O 7
+#define SPCG_MLP_O 8
 #define SPCG_MLP_PARAMS (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H + \
                          SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
 #define SPCG_MLP_S_SCALE 10.0
@@ -449,7 +477,7 @@ void spcg_solve_opts_default(spcg_solve_opts* opts);
 int spcg_mlp_forward(spcg_ctx* ctx, const float* W, const float* feats, int64_t n, float* out);
 /* grad (DEVICE, SPCG_MLP_PARAMS FP32) <- gradient of the mean loss above;
  * *loss (DEVICE, one FP32, may be NULL) <- the loss.  Labels and weights
- * are DEVICE arrays of n entries; a is clamped to 0..3 and g taken mod 2.
+ * are DEVICE arrays of n entries; a is clamped to 0..4 and g taken mod 2.
  * Sums run in a fixed order (identical bits on repeated calls). */
 int spcg_mlp_loss_grad(spcg_ctx* ctx, const float* W, const float* feats, const int32_t* a_label,
                        const int32_t* g_label, const float* s_label, const float* w_a,

@@ -261,7 +261,7 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
                record_features=False, stage_dtype=0, transform_segment=0, sketch="srht",
                batch_direct=False, batch_tasks_per_cu=0, m_list=None, a_rule="fixed", omega=0.0,
-               nested_gradient=True):
+               nested_gradient=True, stage_limit=0):
     """spcg_solve_opts from keyword arguments (``sketch``: "srht" or "cs",
     the CountSketch of SPCG-CS).  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
@@ -284,6 +284,7 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.a_rule = L.SPCG_A_THEORY if a_rule in ("theory", L.SPCG_A_THEORY) else L.SPCG_A_FIXED
     o.omega = omega
     o.nested_gradient = int(nested_gradient)
+    o.stage_limit = stage_limit
     o.precond.qr_passes = qr_passes
     o.method = SPCG_METHOD_FULL_PCG if method in ("pcg", "full_pcg", SPCG_METHOD_FULL_PCG) else SPCG_METHOD_SPCG
     o.a, o.T, o.tol, o.check_every = a, T, tol, check_every

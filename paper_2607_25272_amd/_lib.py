@@ -28,7 +28,7 @@ SPCG_METHOD_SPCG, SPCG_METHOD_FULL_PCG = 0, 1
 SPCG_SCHEDULE_PLAIN, SPCG_SCHEDULE_LEARNED = 0, 1
 SPCG_SKETCH_SRHT, SPCG_SKETCH_COUNT = 0, 1
 SPCG_A_FIXED, SPCG_A_THEORY = 0, 1
-SPCG_MLP_F, SPCG_MLP_H, SPCG_MLP_O = 8, 64, 7
+SPCG_MLP_F, SPCG_MLP_H, SPCG_MLP_O = 8, 64, 8
 SPCG_MLP_PARAMS = (SPCG_MLP_H * SPCG_MLP_F + SPCG_MLP_H + SPCG_MLP_H * SPCG_MLP_H + SPCG_MLP_H
                    + SPCG_MLP_O * SPCG_MLP_H + SPCG_MLP_O)
 SPCG_MLP_S_SCALE = 10.0
@@ -77,7 +77,7 @@ class SolveOpts(ctypes.Structure):
                 ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
                 ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
                 ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32),
-                ("a_rule", c_i32), ("nested_gradient", c_i32), ("omega", c_f64)]
+                ("a_rule", c_i32), ("nested_gradient", c_i32), ("omega", c_f64), ("stage_limit", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -91,7 +91,9 @@ class SolveStats(ctypes.Structure):
                 ("ax2_ii0", c_f64), ("resid2_ii0", c_f64), ("features_pre", ctypes.c_float * 8),
                 ("features_ii", ctypes.c_float * 8), ("out_pre", ctypes.c_float * 8),
                 ("out_ii", ctypes.c_float * 8), ("batch_tasks_per_cu", c_i32), ("batch_graphs", c_i32),
-                ("kernel_ms", c_f64 * 8), ("kernel_bytes", c_f64 * 8), ("kernel_launches", c_i32 * 8)]
+                ("kernel_ms", c_f64 * 8), ("kernel_bytes", c_f64 * 8), ("kernel_launches", c_i32 * 8),
+                ("stages_planned", c_i32), ("stage_iters", c_i32 * 64), ("stage_features", ctypes.c_float * 128),
+                ("stage_out", ctypes.c_float * 128)]
 
 
 P = ctypes.POINTER

@@ -860,6 +860,8 @@ int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const Stag
     j.part_scal = W.part_scal;
     j.dpad = round_up(A->cols, 64);
     j.num_cu = W.num_cu;
+    j.gate = W.S.gate;
+    j.gmin = W.S.gmin;
     const bool timed = timer && timer->used < MAX_TIMED;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev_prod[2 * timer->used], ctx->stream));
     const double e = (double)dtype_bytes(A->dtype);
@@ -879,13 +881,27 @@ int product_pass(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, const Stag
 
 // Work done at the start of a tested stage for the schedule network:
 // Stage II features (when fpre is set) and, with weights, the network's
-// prediction of the iteration count; both come back with the first test.
+// prediction of the iteration count; both come back with the first test,
+// as do the listed device-to-host copies.  With t1_host set, the stage's
+// iteration budget is capped at t_total - *t1_host once that copy is in.
 struct StageHooks {
     const float* fpre = nullptr;   // device: pre-Stage-I features
     float* fii = nullptr;          // device: Stage II features (8)
     const float* W = nullptr;      // device: network weights (learned schedule)
     float* out = nullptr;          // device: network outputs (8)
     int margin = 1;
+    struct Copy {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    Copy copies[4] = {};
+    int ncopy = 0;
+    void add_copy(void* dst, const void* src, size_t bytes) {
+        if (ncopy < 4 && bytes > 0) copies[ncopy++] = Copy{dst, src, bytes};
+    }
+    const int32_t* t1_host = nullptr;
+    int t_total = 0;
     // results
     float host_fii[8] = {};
     float host_out[8] = {};
@@ -921,6 +937,11 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
     out->converged = false;
     int unchecked = 0;
     if (testing) {
+        if (hooks) {
+            for (int i = 0; i < hooks->ncopy; ++i)
+                HIP_TRY(ctx, hipMemcpyAsync(hooks->copies[i].dst, hooks->copies[i].src, hooks->copies[i].bytes,
+                                            hipMemcpyDeviceToHost, st));
+        }
         if (hooks && hooks->fpre) {
             HIP_TRY(ctx, run_features_ii(st, hooks->fpre, S.sc, tol, hooks->fii));
             HIP_TRY(ctx, hipMemcpyAsync(hooks->host_fii, hooks->fii, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -932,13 +953,14 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
         }
         if ((rc = read_scalars(ctx, S, &out->sc)) != SPCG_OK) return rc;
         if (hooks) hooks->start = out->sc;
+        if (hooks && hooks->t1_host) iters = std::max(0, std::min(iters, hooks->t_total - *hooks->t1_host));
         if (out->sc.breakdown) return fail(ctx, SPCG_E_BREAKDOWN, "PCG breakdown at stage start");
         if (stop_test(out->sc, tol)) {
             out->converged = true;
             return SPCG_OK;
         }
         if (hooks && hooks->W) {
-            hooks->s_pred = (double)hooks->host_out[6] * MLP_S_SCALE;
+            hooks->s_pred = (double)hooks->host_out[MLP_NA + 2] * MLP_S_SCALE;
             const double rs = std::isfinite(hooks->s_pred) ? std::round(hooks->s_pred) : 0.0;
             const double k = std::min(std::max(rs - (double)hooks->margin, 0.0), (double)iters);
             unchecked = (int)k;
@@ -975,13 +997,15 @@ int stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, co
 // m_prev > 0: the previous stage ran on the first m_prev rows of this
 // prefix view (nested sketches) and left its final gradient in the state;
 // the starting gradient then needs a G pass over the new rows only.
-int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
-                     const spcg_precond_t* pc, double* x, int iters, int64_t m_prev = 0) {
+//
+// stage_start_nosync / stage_iter_nosync: the stage start (starting
+// gradient, z, p, rho) and one PCG iteration of a sketched stage, without
+// host synchronisation.  W may carry a launch gate (W.S.gate): every kernel
+// then returns at once unless the decision word is >= W.S.gmin.
+int stage_start_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const StageWs& W,
+                       int64_t m_prev) {
     int rc;
-    StageWs W;
-    if ((rc = ensure_stage_ws(ctx, A->cols, &W, x, pc->pMinv)) != SPCG_OK) return rc;
     const DspaceState& S = W.S;
-    hipStream_t st = ctx->stream;
     const int64_t dpad = round_up(A->cols, 64);
     int np = 0;
     if (m_prev > 0 && m_prev < A->rows) {
@@ -998,12 +1022,32 @@ int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double
         if ((rc = product_pass(ctx, A, b, W, PM_G, &np, nullptr)) != SPCG_OK) return rc;
         if ((rc = phase_a(ctx, S, PA_START, nullptr, W.part_g, W.part_scal, np, dpad, c2)) != SPCG_OK) return rc;
     }
-    if ((rc = phase_b(ctx, S, 1)) != SPCG_OK) return rc;
-    for (int it = 0; it < iters; ++it) {
-        if ((rc = product_pass(ctx, A, b, W, PM_S, &np, nullptr)) != SPCG_OK) return rc;
-        if ((rc = phase_a(ctx, S, PA_STEP, W.part_s, nullptr, nullptr, np, dpad, c2)) != SPCG_OK) return rc;
-        if ((rc = phase_b(ctx, S, 0)) != SPCG_OK) return rc;
-    }
+    return phase_b(ctx, S, 1);
+}
+
+int stage_iter_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2, const StageWs& W) {
+    int rc, np = 0;
+    const int64_t dpad = round_up(A->cols, 64);
+    if ((rc = product_pass(ctx, A, b, W, PM_S, &np, nullptr)) != SPCG_OK) return rc;
+    if ((rc = phase_a(ctx, W.S, PA_STEP, W.part_s, nullptr, nullptr, np, dpad, c2)) != SPCG_OK) return rc;
+    return phase_b(ctx, W.S, 0);
+}
+
+StageWs gated(const StageWs& W, const int32_t* gate, int gmin) {
+    StageWs G = W;
+    G.S.gate = gate;
+    G.S.gmin = gmin;
+    return G;
+}
+
+int stage_run_nosync(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c2,
+                     const spcg_precond_t* pc, double* x, int iters, int64_t m_prev = 0) {
+    int rc;
+    StageWs W;
+    if ((rc = ensure_stage_ws(ctx, A->cols, &W, x, pc->pMinv)) != SPCG_OK) return rc;
+    if ((rc = stage_start_nosync(ctx, A, b, c2, W, m_prev)) != SPCG_OK) return rc;
+    for (int it = 0; it < iters; ++it)
+        if ((rc = stage_iter_nosync(ctx, A, b, c2, W)) != SPCG_OK) return rc;
     return SPCG_OK;
 }
 
@@ -2138,7 +2182,8 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         return fail(ctx, SPCG_E_INVALID_ARG, "unknown method %d", opts->method);
     if (opts->a < 0 || opts->T < 0 || opts->tol < 0.0 || opts->a_list_len < 0 ||
         (opts->a_list_len > 0 && !opts->a_list) || opts->stage_stride < 0 || opts->stage_stride > 2 ||
-        (opts->a_rule != SPCG_A_FIXED && opts->a_rule != SPCG_A_THEORY) || opts->omega < 0.0 || opts->omega >= 1.0)
+        (opts->a_rule != SPCG_A_FIXED && opts->a_rule != SPCG_A_THEORY) || opts->omega < 0.0 || opts->omega >= 1.0 ||
+        opts->stage_limit < 0)
         return fail(ctx, SPCG_E_INVALID_ARG, "bad solve options");
     const bool learned = opts->schedule == SPCG_SCHEDULE_LEARNED;
     if (opts->schedule != SPCG_SCHEDULE_PLAIN && !learned)
@@ -2147,7 +2192,7 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         return fail(ctx, SPCG_E_INVALID_ARG, "the learned schedule needs weights and method SPCG");
     const bool features = learned || opts->record_features;
     int a = opts->a > 0 ? opts->a : 3;
-    int stride = opts->stage_stride > 0 ? opts->stage_stride : 1;
+    const int stride = learned ? 1 : (opts->stage_stride > 0 ? opts->stage_stride : 1);
     const int T = opts->T > 0 ? opts->T : 100;
     const double tol = opts->tol > 0.0 ? opts->tol : 5e-7;
     const bool timing = opts->time_phases != 0;
@@ -2176,56 +2221,95 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     if ((rc = precond_build(ctx, &sk, &opts->precond, true, &pc)) != SPCG_OK) return rc;
     if ((rc = y_join(ctx, false)) != SPCG_OK) return rc;
     const int64_t d = X->cols;
+    // planned stages: the prefixes K-1, K-1-stride, ... in increasing order
+    // (every prefix for the learned schedule); stage_limit keeps the first
+    std::vector<int64_t> stages;
+    for (int64_t i = sk.K - 1; i >= 0; i -= stride) stages.push_back(i);
+    std::reverse(stages.begin(), stages.end());
+    const int Kplan = (int)stages.size();
+    if (learned && Kplan > SCHED_KMAX)
+        return fail(ctx, SPCG_E_INVALID_ARG, "the learned schedule takes at most %d stages", SCHED_KMAX);
+    const int Krun = (!learned && opts->stage_limit > 0) ? std::min(Kplan, (int)opts->stage_limit) : Kplan;
+    // schedule scratch (floats): base features, Stage II features, Stage II
+    // outputs, then per planned stage its features and network outputs, then
+    // the decision words
+    constexpr int SF_BASE = 0, SF_II = 8, SF_OUT_II = 24, SF_STAGE = 32, SF_SOUT = SF_STAGE + 8 * SCHED_KMAX,
+                  SF_CTL = SF_SOUT + 8 * SCHED_KMAX;
     float* sched = nullptr;
-    float host_fpre[8] = {}, host_out_pre[8] = {};
+    int32_t* ctl = nullptr;
+    float host_fpre[8] = {};
     if (features) {
-        HIP_TRY(ctx, ctx->sched.ensure(32 * sizeof(float)));
+        HIP_TRY(ctx, ctx->sched.ensure((size_t)(SF_CTL + sched_ctl_words(SCHED_KMAX)) * sizeof(float)));
         sched = ctx->sched.as<float>();
-        HIP_TRY(ctx, run_features_pre(st, X->data, X->dtype, X->rows, d, X->ld, X->col_scale, pc.pR, d, sched));
-        HIP_TRY(ctx, hipMemcpyAsync(host_fpre, sched, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
+        ctl = reinterpret_cast<int32_t*>(sched + SF_CTL);
+        HIP_TRY(ctx, run_features_pre(st, X->data, X->dtype, X->rows, d, X->ld, X->col_scale, pc.pR, d,
+                                      sched + SF_BASE));
+        HIP_TRY(ctx, hipMemcpyAsync(host_fpre, sched + SF_BASE, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
     }
-    if (learned) {
-        // decision 1: Stage I iteration count and prefix stride
-        HIP_TRY(ctx, run_mlp_forward(st, opts->schedule_weights, sched, 1, sched + 16));
-        HIP_TRY(ctx, hipMemcpyAsync(host_out_pre, sched + 16, MLP_O * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIP_TRY(ctx, hipStreamSynchronize(st));
-        ctx->syncs++;
-        int ia = 0;
-        for (int i = 1; i < 4; ++i)
-            if (host_out_pre[i] > host_out_pre[ia]) ia = i;
-        a = ia + 1;
-        stride = host_out_pre[5] > host_out_pre[4] ? 2 : 1;
-    }
+    // stage features known on the host: size, Theorem 3.3 bound (omega =
+    // 1/2) over the planned sizes, position
+    auto stage_fixed = [&](int si, float* f2, float* f5, float* f7) {
+        const double m = (double)sk.m[stages[si]], dd = (double)d;
+        auto bound = [&](double mp, double mc) {
+            const double r = std::sqrt((mc - dd) / (mp - dd));
+            return std::log((1.5 * r + 1.0) / 0.5) / std::log(4.0);
+        };
+        double B;
+        if (Kplan == 1) B = std::log(5.0) / std::log(4.0);
+        else if (si == 0) B = bound((double)sk.m[stages[0]], (double)sk.m[stages[1]]);
+        else B = bound((double)sk.m[stages[si - 1]], m);
+        *f2 = (float)(std::log2(m / dd) / 8.0 - 1.0);
+        *f5 = (float)(B / 4.0);
+        *f7 = (float)((double)si / (double)Kplan);
+    };
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[2], st));
     StageWs SW;
     if ((rc = ensure_stage_ws(ctx, d, &SW, beta, pc.pMinv)) != SPCG_OK) return rc;
     HIP_TRY(ctx, run_scalars_reset(st, SW.S.sc));
     HIP_TRY(ctx, run_fill(st, beta, d, 0.0));
-    // Stage I over the prefixes K-1, K-1-stride, ... in increasing order
-    std::vector<int64_t> stages;
-    for (int64_t i = sk.K - 1; i >= 0; i -= stride) stages.push_back(i);
-    std::reverse(stages.begin(), stages.end());
     std::vector<int> a_th;
     if (!learned && opts->a_rule == SPCG_A_THEORY) {
         std::vector<int64_t> ms;
         for (int64_t i : stages) ms.push_back(sk.m[i]);
         a_th = theory_a(ms.data(), (int)ms.size(), d, opts->omega > 0.0 ? opts->omega : 0.5);
     }
+    if (learned) HIP_TRY(ctx, run_sched_init(st, ctl, Kplan));
+    std::vector<int> iters_run(Kplan, -1);
     int t1 = 0, a_used = a;
-    for (size_t si = 0; si < stages.size(); ++si) {
-        int ai = a;
-        if (!learned && opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(si, opts->a_list_len - 1)];
-        if (!a_th.empty()) ai = a_th[si];
-        if (ai < 0) return fail(ctx, SPCG_E_INVALID_ARG, "negative a_i");
-        if (t1 + ai > T) ai = std::max(0, T - t1);
-        a_used = ai;
+    for (int si = 0; si < Krun; ++si) {
         spcg_mat A{}, b{};
         double c2 = 1.0;
         spcg_sketch_view(&sk, (int)stages[si], &A, &b, &c2);
         // nested prefixes: reuse the previous stage's gradient (SRHT only)
         const int64_t m_prev = (opts->nested_gradient && si > 0 && sk.kind == SPCG_SKETCH_SRHT)
                                    ? sk.m[stages[si - 1]] : 0;
-        if ((rc = stage_run_nosync(ctx, &A, &b, c2, &pc, beta, ai, m_prev)) != SPCG_OK) return rc;
+        float f2 = 0.f, f5 = 0.f, f7 = 0.f;
+        if (features) stage_fixed(si, &f2, &f5, &f7);
+        float* frow = features ? sched + SF_STAGE + 8 * si : nullptr;
+        if (learned) {
+            // every launch of the stage is queued; the decision words switch
+            // off what the network does not choose
+            if ((rc = stage_start_nosync(ctx, &A, &b, c2, gated(SW, ctl + si, 1), m_prev)) != SPCG_OK) return rc;
+            float* orow = sched + SF_SOUT + 8 * si;
+            HIP_TRY(ctx, run_features_stage(st, sched + SF_BASE, SW.S.sc, f2, f5, f7, ctl + si, frow));
+            HIP_TRY(ctx, run_mlp_forward(st, opts->schedule_weights, frow, 1, orow));
+            HIP_TRY(ctx, run_sched_decide(st, orow, ctl, si, Kplan, T - 1));
+            for (int it = 0; it < MLP_NA - 1; ++it)
+                if ((rc = stage_iter_nosync(ctx, &A, &b, c2, gated(SW, ctl + Kplan + 1 + si, it + 1))) != SPCG_OK)
+                    return rc;
+            continue;
+        }
+        int ai = a;
+        if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(si, opts->a_list_len - 1)];
+        if (!a_th.empty()) ai = a_th[si];
+        if (ai < 0) return fail(ctx, SPCG_E_INVALID_ARG, "negative a_i");
+        if (t1 + ai > T) ai = std::max(0, T - t1);
+        a_used = ai;
+        if ((rc = stage_start_nosync(ctx, &A, &b, c2, SW, m_prev)) != SPCG_OK) return rc;
+        if (features) HIP_TRY(ctx, run_features_stage(st, sched + SF_BASE, SW.S.sc, f2, f5, f7, nullptr, frow));
+        for (int it = 0; it < ai; ++it)
+            if ((rc = stage_iter_nosync(ctx, &A, &b, c2, SW)) != SPCG_OK) return rc;
+        iters_run[si] = ai;
         t1 += ai;
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[3], st));
@@ -2234,23 +2318,44 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     timer.ctx = ctx;
     StageRun run;
     StageHooks hooks;
+    std::vector<int32_t> host_ctl(learned ? sched_ctl_words(Kplan) : 0);
+    std::vector<float> host_sf(features ? 8 * SCHED_FREC : 0), host_so(learned ? 8 * SCHED_FREC : 0);
+    const int nrec = std::min(Krun, SCHED_FREC);
     if (features) {
-        hooks.fpre = sched;
-        hooks.fii = sched + 8;
+        hooks.fpre = sched + SF_BASE;
+        hooks.fii = sched + SF_II;
+        if (nrec > 0) hooks.add_copy(host_sf.data(), sched + SF_STAGE, (size_t)nrec * 8 * sizeof(float));
     }
     if (learned) {
         hooks.W = opts->schedule_weights;
-        hooks.out = sched + 24;
+        hooks.out = sched + SF_OUT_II;
         hooks.margin = opts->schedule_margin == 0 ? 1 : std::max(0, opts->schedule_margin);
+        hooks.add_copy(host_so.data(), sched + SF_SOUT, (size_t)nrec * 8 * sizeof(float));
+        // the Stage I decisions come back with the first stopping test, which
+        // then caps Stage II at T minus the Stage I iterations
+        hooks.add_copy(host_ctl.data(), ctl, host_ctl.size() * sizeof(int32_t));
+        hooks.t1_host = &host_ctl[2 * Kplan + 1];
+        hooks.t_total = T;
     }
-    rc = stage_run(ctx, X, Y, 1.0, &pc, beta, std::max(0, T - t1), tol, true, opts->check_every, &run,
-                   opts->time_products == 1 ? &timer : nullptr, &hooks);
+    rc = stage_run(ctx, X, Y, 1.0, &pc, beta, learned ? T : std::max(0, T - t1), tol, true, opts->check_every,
+                   &run, opts->time_products == 1 ? &timer : nullptr, &hooks);
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[4], st));
     if (rc != SPCG_OK && rc != SPCG_E_BREAKDOWN) return rc;
     const int rc_stage = rc;
+    if (learned) {
+        // the copies ran before the first stopping test (stage_run always
+        // tests at the Stage II start)
+        t1 = host_ctl[2 * Kplan + 1];
+        for (int si = 0; si < Kplan; ++si) {
+            iters_run[si] = host_ctl[Kplan + 1 + si];
+            if (iters_run[si] >= 0) a_used = iters_run[si];
+        }
+    }
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
-        stats->K = (int32_t)stages.size();
+        int started = 0;
+        for (int v : iters_run) started += v >= 0 ? 1 : 0;
+        stats->K = started;
         stats->T_stage1 = t1;
         stats->T_stage2 = run.iters_done;
         stats->converged = run.converged;
@@ -2267,6 +2372,10 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         stats->rho_ii0 = hooks.start.rho;
         stats->ax2_ii0 = hooks.start.ax2;
         stats->resid2_ii0 = hooks.start.resid2;
+        stats->stages_planned = std::min(Kplan, SCHED_KMAX);
+        for (int si = 0; si < SCHED_KMAX; ++si) stats->stage_iters[si] = si < Kplan ? iters_run[si] : -1;
+        for (int i = 0; i < (int)host_sf.size() && i < 8 * nrec; ++i) stats->stage_features[i] = host_sf[i];
+        for (int i = 0; i < (int)host_so.size() && i < 8 * nrec; ++i) stats->stage_out[i] = host_so[i];
         if (timing || opts->time_products) {
             HIP_TRY(ctx, hipStreamSynchronize(st));
         }
@@ -2274,7 +2383,6 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         for (int i = 0; i < 8; ++i) {
             stats->features_pre[i] = host_fpre[i];
             stats->features_ii[i] = hooks.host_fii[i];
-            stats->out_pre[i] = host_out_pre[i];
             stats->out_ii[i] = hooks.host_out[i];
         }
         if (timing) {

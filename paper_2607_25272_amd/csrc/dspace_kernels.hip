@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void phase_a_kernel(PhaseAArgs a) {
     __shared__ double sh_b[256];
     __shared__ int is_last;
     const DspaceState& S = a.S;
+    if (S.gate && *S.gate < S.gmin) return;   // switched off on the device (uniform)
     const int tx = threadIdx.x & (A_COLS - 1), ty = threadIdx.x / A_COLS;
     const int64_t col = (int64_t)blockIdx.x * A_COLS + tx;
     const bool start = a.variant == PA_START || a.variant == PA_START_NESTED;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void phase_b_kernel(DspaceState S, int init) {
     __shared__ double sh[4];
     __shared__ double red[4];
     __shared__ int is_last;
+    if (S.gate && *S.gate < S.gmin) return;   // switched off on the device (uniform)
     PcgScalars* sc = S.sc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // wave w of block b takes rows b*4 + w + k * stride, k = 0..B_ROWS-1 per

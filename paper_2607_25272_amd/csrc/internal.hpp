@@ -155,6 +155,8 @@ struct ProdJob {
     double* part_scal;       // [nblocks][2]: sum (b - a.x)^2, sum (a.x)^2
     int64_t dpad;
     int num_cu;
+    const int32_t* gate = nullptr;   // optional: the launch does nothing unless *gate >= gmin
+    int32_t gmin = 0;
 };
 // Chooses the launch shape, returns the number of blocks (partials) used.
 hipError_t run_product(hipStream_t st, const ProdJob& job, int* nblocks_out);
@@ -188,6 +190,10 @@ struct DspaceState {
     PcgScalars* sc;
     const double* Minv;  // d x d
     int64_t d;
+    // optional launch gate: the phase kernels return at once unless
+    // *gate >= gmin (a decision written earlier on the same stream)
+    const int32_t* gate = nullptr;
+    int32_t gmin = 0;
 };
 // phase A: reduce the product partials; start / step / refresh variants
 // PA_START_NESTED: g = g_scale * g + c2 * (reduced partials), the starting
@@ -319,5 +325,24 @@ hipError_t run_adam(hipStream_t st, float* W, const float* g, float* m, float* v
 hipError_t run_features_pre(hipStream_t st, const void* X, int dtype, int64_t N, int64_t d, int64_t ld,
                             const float* col_scale, const double* R, int64_t ldr, float* f);
 hipError_t run_features_ii(hipStream_t st, const float* fpre, const PcgScalars* sc, double tol, float* f);
+
+// Per-stage decisions of the learned schedule.  Control words of K planned
+// stages (2 K + 2 int32): ctl[i] (i <= K) = 1 if stage i starts,
+// ctl[K + 1 + i] = PCG iterations of stage i (-1 before its decision or if
+// it never starts), ctl[2 K + 1] = Stage I iterations so far.
+constexpr int MLP_NA = 5;          // a_i choices 0..4 (outputs 0..4), stop (5..6), s_II (7)
+constexpr int SCHED_KMAX = 64;     // planned stages with recorded decisions
+constexpr int SCHED_FREC = 16;     // stages whose features / outputs are recorded
+__host__ __device__ inline int sched_ctl_words(int K) { return 2 * K + 2; }
+hipError_t run_sched_init(hipStream_t st, int32_t* ctl, int K);
+// Stage features: f = base with f2, f5, f7 replaced (host-computed from the
+// planned sizes) and f6 from the stage-start scalars; skipped unless
+// gate is null or *gate >= 1.
+hipError_t run_features_stage(hipStream_t st, const float* fbase, const PcgScalars* sc, float f2, float f5, float f7,
+                              const int32_t* gate, float* f);
+// Decision of stage s from the network outputs (skipped unless ctl[s] >= 1):
+// a = first arg-max of out[0..4], capped so that Stage I totals at most
+// t_cap; ctl[s + 1] = 1 unless out[6] > out[5] (stop).
+hipError_t run_sched_decide(hipStream_t st, const float* out, int32_t* ctl, int s, int K, int t_cap);
 
 }  // namespace spcg

@@ -164,10 +164,16 @@ struct ProdArgs {
     double* part_g;
     double* part_scal;
     int64_t dpad;
+    const int32_t* gate;   // optional: return at once unless *gate >= gmin
+    int32_t gmin;
 };
+
+// a launch switched off by a device-side decision (uniform over the grid)
+__device__ __forceinline__ bool gated_off(const ProdArgs& a) { return a.gate && *a.gate < a.gmin; }
 
 template <typename TS, int VEC, int LPR, int NSLOT, int MODE, int U>
 __global__ __launch_bounds__(64 * NW) void product_kernel(ProdArgs a) {
+    if (gated_off(a)) return;
     typedef typename Store<TS>::CT CT;
     typedef typename RawVec<VEC * Store<TS>::BYTES>::T Raw;
     constexpr bool DO_S = MODE != PM_G;
@@ -370,6 +376,7 @@ __device__ __forceinline__ void lds_load(const void* src, void* lds) {
 
 template <typename TS, int DMAB, int NSLOT, int MODE>
 __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
+    if (gated_off(a)) return;
     typedef typename Store<TS>::CT CT;
     typedef typename RawVec<DMAB>::T Raw;
     constexpr int VEC = DMAB / Store<TS>::BYTES;
@@ -721,6 +728,8 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
         a.part_g = j.part_g;
         a.part_scal = j.part_scal;
         a.dpad = j.dpad;
+        a.gate = j.gate;
+        a.gmin = j.gmin;
         hipError_t e;
         switch (j.dtype) {
             case DT_F64: e = launch_ring_type<double>(st, a, j.mode, (int)nb, dmab, ns); break;
@@ -766,6 +775,8 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
     a.part_g = j.part_g;
     a.part_scal = j.part_scal;
     a.dpad = j.dpad;
+    a.gate = j.gate;
+    a.gmin = j.gmin;
     hipError_t e;
     switch (j.dtype) {
         case DT_F64: e = launch_type<double>(st, a, j.mode, (int)nb, vec, lpr, nslot); break;

@@ -1,6 +1,7 @@
-// Learned schedule on gfx950: the features of a problem and a three-layer
-// FP32 network (forward, loss gradient, Adam) that maps them to the Stage I
-// iteration count, the prefix stride and the Stage II iteration count.
+// Learned schedule on gfx950: the features of a problem and of each
+// sketched stage, a three-layer FP32 network (forward, loss gradient, Adam)
+// that maps them to a stage's iteration count, whether Stage I stops after
+// it, and the Stage II iteration count, and the per-stage decision kernels.
 //
 // The network is tiny (5191 parameters), so the kernels keep all weights in
 // LDS and give each sample eight threads (eight hidden units each).  The
@@ -95,32 +96,37 @@ __global__ __launch_bounds__(NT) void mlp_kernel(const float* __restrict__ W, co
 #pragma unroll
                 for (int i = 0; i < O; ++i) o[i] = row[RDO + i];
                 if (valid) {
-                    const int a = min(max(la[smp], 0), 3), g = lg[smp] & 1;
+                    // outputs 0..NA-1: a_i logits, NA..NA+1: stop logits, NA+2: s_II
+                    constexpr int NA = MLP_NA;
+                    static_assert(NA + 3 == O, "output layout");
+                    const int a = min(max(la[smp], 0), NA - 1), g = lg[smp] & 1;
                     const float t = ls[smp] * (float)(1.0 / MLP_S_SCALE);
                     const float w1 = wa[smp], w2 = ws[smp];
-                    const float ma = fmaxf(fmaxf(o[0], o[1]), fmaxf(o[2], o[3]));
-                    float ea[4], sa = 0.f;
+                    float ma = o[0];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 1; i < NA; ++i) ma = fmaxf(ma, o[i]);
+                    float ea[NA], sa = 0.f;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i) {
                         ea[i] = expf(o[i] - ma);
                         sa += ea[i];
                     }
-                    const float mg = fmaxf(o[4], o[5]);
-                    const float eg0 = expf(o[4] - mg), eg1 = expf(o[5] - mg);
+                    const float mg = fmaxf(o[NA], o[NA + 1]);
+                    const float eg0 = expf(o[NA] - mg), eg1 = expf(o[NA + 1] - mg);
                     const float sg = eg0 + eg1;
                     float oa = 0.f;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) oa = i == a ? o[i] : oa;
-                    const float og = g == 0 ? o[4] : o[5];
+                    for (int i = 0; i < NA; ++i) oa = i == a ? o[i] : oa;
+                    const float og = g == 0 ? o[NA] : o[NA + 1];
                     const float ce = (ma + logf(sa) - oa) + (mg + logf(sg) - og);
-                    const float rr = o[6] - t;
+                    const float rr = o[NA + 2] - t;
                     l = w1 * ce + w2 * (float)MLP_LAMBDA * rr * rr;
                     const float ka = w1 * inv_n;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) row[RDO + i] = ka * (ea[i] / sa - (i == a ? 1.f : 0.f));
-                    row[RDO + 4] = ka * (eg0 / sg - (g == 0 ? 1.f : 0.f));
-                    row[RDO + 5] = ka * (eg1 / sg - (g == 1 ? 1.f : 0.f));
-                    row[RDO + 6] = w2 * (float)(2.0 * MLP_LAMBDA) * rr * inv_n;
+                    for (int i = 0; i < NA; ++i) row[RDO + i] = ka * (ea[i] / sa - (i == a ? 1.f : 0.f));
+                    row[RDO + NA] = ka * (eg0 / sg - (g == 0 ? 1.f : 0.f));
+                    row[RDO + NA + 1] = ka * (eg1 / sg - (g == 1 ? 1.f : 0.f));
+                    row[RDO + NA + 2] = w2 * (float)(2.0 * MLP_LAMBDA) * rr * inv_n;
                 } else {
 #pragma unroll
                     for (int i = 0; i < O; ++i) row[RDO + i] = 0.f;
@@ -324,7 +330,76 @@ __global__ void features_ii_kernel(const float* __restrict__ fpre, const PcgScal
     f[7] = 1.f;
 }
 
+// Features at the start of a sketched stage: the base features with the
+// stage size, the Theorem 3.3 bound and the position (host-computed), and
+// the residual-to-fit ratio of the rows the starting-gradient pass read.
+__global__ void features_stage_kernel(const float* __restrict__ fb, const PcgScalars* __restrict__ sc, float f2,
+                                      float f5, float f7, const int32_t* __restrict__ gate, float* __restrict__ f) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (gate && *gate < 1) return;
+    const double ax2 = sc->ax2, r2 = sc->resid2;
+    double f6;
+    if (!(r2 > 0.0)) {
+        f6 = -2.0;
+    } else if (!(ax2 > 0.0)) {
+        f6 = 2.0;
+    } else {
+        f6 = log10(r2 / ax2) / 6.0;
+    }
+    f[0] = fb[0];
+    f[1] = fb[1];
+    f[2] = f2;
+    f[3] = fb[3];
+    f[4] = fb[4];
+    f[5] = f5;
+    f[6] = (float)fmin(fmax(f6, -2.0), 2.0);
+    f[7] = f7;
+}
+
+__global__ void sched_init_kernel(int32_t* ctl, int K) {
+    for (int i = threadIdx.x; i < sched_ctl_words(K); i += blockDim.x) {
+        int v;
+        if (i <= K) v = i == 0 ? 1 : 0;           // start flags: stage 0 starts
+        else if (i <= 2 * K) v = -1;              // iterations: not decided
+        else v = 0;                               // Stage I iterations so far
+        ctl[i] = v;
+    }
+}
+
+__global__ void sched_decide_kernel(const float* __restrict__ out, int32_t* __restrict__ ctl, int s, int K,
+                                    int t_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (ctl[s] < 1) return;
+    int a = 0;
+    for (int i = 1; i < MLP_NA; ++i)
+        if (out[i] > out[a]) a = i;
+    const int used = ctl[2 * K + 1];
+    a = max(0, min(a, t_cap - used));
+    const bool stop = out[MLP_NA + 1] > out[MLP_NA];
+    ctl[K + 1 + s] = a;
+    ctl[2 * K + 1] = used + a;
+    ctl[s + 1] = stop ? 0 : 1;   // ctl[K] is a sentinel
+}
+
 }  // namespace
+
+hipError_t run_sched_init(hipStream_t st, int32_t* ctl, int K) {
+    if (K < 1) return hipErrorInvalidValue;
+    sched_init_kernel<<<1, 128, 0, st>>>(ctl, K);
+    return hipGetLastError();
+}
+
+hipError_t run_features_stage(hipStream_t st, const float* fbase, const PcgScalars* sc, float f2, float f5, float f7,
+                              const int32_t* gate, float* f) {
+    features_stage_kernel<<<1, 64, 0, st>>>(fbase, sc, f2, f5, f7, gate, f);
+    return hipGetLastError();
+}
+
+hipError_t run_sched_decide(hipStream_t st, const float* out, int32_t* ctl, int s, int K, int t_cap) {
+    if (s < 0 || s >= K) return hipErrorInvalidValue;
+    sched_decide_kernel<<<1, 64, 0, st>>>(out, ctl, s, K, t_cap);
+    return hipGetLastError();
+}
 
 int mlp_grad_blocks(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, CH), 1), MAX_GRAD_BLOCKS); }
 

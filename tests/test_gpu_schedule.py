@@ -4,12 +4,17 @@
   HIP kernels, FP32) against the FP64 oracle in ``oracle/mlp.py`` to about
   1e-5 relative, and a short training run against the oracle's trajectory.
 * The schedule features computed on the device against the oracle's
-  definition on the same inputs.
-* The solve follows the network's decisions exactly (crafted weights), stays
-  within 1e-6 of the OLS estimator, and with the decisions fixed gives the
-  same bits as the plain schedule with those settings.
-* The trained weights shipped with the package beat the plain schedule on
-  the evaluation workload (N = 2e6, d = 256, 1% of rows scaled by 100).
+  definition on the same inputs: the base and Stage II features, and the
+  per-stage features along the oracle's own Stage I trajectory.
+* The solve follows the network's per-stage decisions exactly (crafted
+  weights; random weights checked stage by stage against the oracle's
+  forward pass on the recorded features), stays within 1e-6 of the OLS
+  estimator, makes no stream synchronisation in Stage I, and with the
+  decisions fixed gives the same bits as the plain schedule with those
+  settings.
+* The trained weights shipped with the package read fewer bytes in their
+  product passes than the plain schedule on the evaluation workload
+  (N = 2e6, d = 256, 1% of rows scaled by 100) at equal accuracy.
 """
 import os
 import statistics
@@ -22,7 +27,8 @@ import torch
 import workloads
 from oracle import mlp
 from oracle.ols import ols_tsqr
-from oracle.spcg import rel_pred_error
+from oracle.sketch import nested_srht
+from oracle.spcg import rel_pred_error, spcg
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -50,7 +56,7 @@ def _rand_params(seed, scale=1.0):
 def _batch(seed, n):
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n, mlp.F)).astype(np.float32)
-    a = rng.integers(0, 4, n).astype(np.int32)
+    a = rng.integers(0, mlp.NA, n).astype(np.int32)
     g = rng.integers(0, 2, n).astype(np.int32)
     s = rng.integers(0, 30, n).astype(np.float32)
     wa = (rng.random(n) < 0.3).astype(np.float32)
@@ -166,6 +172,33 @@ def test_features_match_oracle(S, ctx, N, d, storage):
     pc.free()
 
 
+def test_stage_features_match_oracle_trajectory(S, ctx):
+    # cfg0 in FP64: the GPU's Stage I iterates equal the oracle's to 1e-9,
+    # so the stage-start residual-to-fit ratios (rows of the nested start
+    # pass) agree as well; every stage's features against features_stage
+    p = workloads.make_config(0, device=DEV)
+    Xd = p.x_f64().cpu().numpy()
+    Yd = p.Y.cpu().numpy()[:, 0]
+    N, d = Xd.shape
+    beta, st = S.spcg_solve(ctx, p.X, p.Y, seed=1, record_features=True)
+    assert st["converged"]
+    _, info = spcg(Xd, Yd, 1, a=3, nested_gradient=True)
+    sizes = info["sizes"]
+    K = len(sizes)
+    assert st["stages_planned"] == K and list(st["stage_iters"][:K]) == [3] * K
+    B, BY, _, _ = nested_srht(Xd, Yd, 1, sizes[-1], 6 * d)
+    f_pre = np.array(st["features_pre"], dtype=np.float64)
+    stage_x = info["per_rhs"][0]["stage_x"]
+    for s_ in range(min(K, 16)):
+        lo = sizes[s_ - 1] if s_ > 0 else 0
+        x = stage_x[s_ - 1] if s_ > 0 else np.zeros(d)
+        fit = B[lo:sizes[s_]] @ x
+        res = BY[lo:sizes[s_]] - fit
+        f_ref = mlp.features_stage(f_pre, sizes, s_, d, float(res @ res), float(fit @ fit))
+        f_gpu = np.array(st["stage_features"][8 * s_:8 * s_ + 8], dtype=np.float64)
+        assert np.abs(f_gpu - f_ref).max() <= 1e-5, (s_, f_gpu, f_ref)
+
+
 def _crafted(b3):
     th = np.zeros(mlp.n_params(), np.float32)
     th[-mlp.O:] = b3
@@ -179,37 +212,79 @@ def prob0():
     return p, Xd, ols_tsqr(Xd, p.Y.cpu().numpy())[:, 0]
 
 
-@pytest.mark.parametrize("b3,a,stride,unchecked", [
-    ([0, 0, 5, 0, 0, 3, 0.74], 3, 2, 6),
-    ([4, 0, 0, 0, 2, 0, 0.0], 1, 1, 0),
-    ([0, 1, 0, 0, 0, 0, 3.0], 2, 1, 29),
-    ([0, 0, 0, 9, 0, 1, -1.0], 4, 2, 0),
+# crafted networks: zero weights, so every stage sees outputs = b3
+@pytest.mark.parametrize("b3,a,stop,unchecked", [
+    ([0, 0, 0, 5, 0, 3, 0, 0.0], 3, 0, 0),      # the plain schedule
+    ([0, 0, 7, 0, 0, 0, 4, 0.0], 2, 1, 0),      # a_1 = 2, then Stage II
+    ([9, 0, 0, 0, 0, 2, 0, 0.74], 0, 0, 6),     # starts only, 6 unchecked Stage II iterations
+    ([0, 0, 0, 0, 3, 0, 1, 0.3], 4, 1, 2),
 ])
-def test_learned_solve_follows_the_network(S, ctx, prob0, b3, a, stride, unchecked):
+def test_learned_solve_follows_the_network(S, ctx, prob0, b3, a, stop, unchecked):
     p, Xd, bh = prob0
     W = _crafted(b3)
     beta, st = S.spcg_solve(ctx, p.X, p.Y, seed=3, schedule="learned", weights=W)
-    print("learned", b3, {k: st[k] for k in ("policy_a", "policy_stride", "K", "T_stage1", "T_stage2",
-                                             "unchecked_iters", "fallback", "host_syncs", "s_pred")},
-          flush=True)
-    assert st["converged"] and st["policy_a"] == a and st["policy_stride"] == stride
-    assert st["unchecked_iters"] == mlp.unchecked_iters(b3[6], 1, 100 - st["T_stage1"])
-    assert st["unchecked_iters"] == unchecked
-    assert abs(st["s_pred"] - b3[6] * 10) < 1e-4
+    K = st["stages_planned"]
+    its = list(st["stage_iters"][:K])
+    print("learned", b3, its, {k: st[k] for k in ("K", "T_stage1", "T_stage2", "unchecked_iters", "fallback",
+                                                  "host_syncs", "s_pred")}, flush=True)
+    n = 1 if stop else K
+    assert its == [a] * n + [-1] * (K - n)
+    assert st["converged"] and st["K"] == n and st["T_stage1"] == a * n
+    assert st["unchecked_iters"] == mlp.unchecked_iters(b3[7], 1, 100 - st["T_stage1"]) == unchecked
+    assert abs(st["s_pred"] - b3[7] * 10) < 1e-4
     assert rel_pred_error(Xd, beta.cpu().numpy(), bh) <= 1e-6
-    # with the same (a, stride) the plain schedule runs the same kernels
-    _, st_all = S.spcg_solve(ctx, p.X, p.Y, seed=3, record_features=True)
-    K_all = st_all["K"]
-    assert st["K"] == (K_all + stride - 1) // stride
-    plain, stp = S.spcg_solve(ctx, p.X, p.Y, seed=3, a=a, stage_stride=stride)
+    # the recorded outputs are the network's, for every started stage
+    assert np.allclose(np.array(st["stage_out"][:8 * n]).reshape(n, 8), np.array(b3, np.float32)[None, :])
+    # with the same decisions the plain schedule runs the same kernels (the
+    # switched-off launches change nothing) and the same host syncs
+    plain, stp = S.spcg_solve(ctx, p.X, p.Y, seed=3, a_list=[a] * n, stage_limit=n if stop else 0)
+    assert list(stp["stage_iters"][:K]) == its
     if unchecked == 0:
         assert torch.equal(plain, beta)
         assert st["T_stage2"] == stp["T_stage2"] and not st["fallback"]
-        assert st["host_syncs"] == stp["host_syncs"] + 1
+        assert st["host_syncs"] == stp["host_syncs"]
     else:
         # the first test comes after `unchecked` iterations: never earlier
         assert st["T_stage2"] >= unchecked
         assert st["fallback"] == int(stp["T_stage2"] > unchecked)
+
+
+def test_learned_stage_one_respects_the_budget(S, ctx, prob0):
+    # a = 4 at every stage with T = 7: Stage I takes T - 1 = 6 iterations
+    # (4, then 2, then 0 per stage) and Stage II is left one
+    p = prob0[0]
+    W = _crafted([0, 0, 0, 0, 5, 1, 0, 0.0])
+    _, st = S.spcg_solve(ctx, p.X, p.Y, seed=3, schedule="learned", weights=W, T=7)
+    K = st["stages_planned"]
+    assert list(st["stage_iters"][:K]) == [4, 2] + [0] * (K - 2)
+    assert st["T_stage1"] == 6 and st["T_stage2"] <= 1
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_decisions_match_oracle_forward(S, ctx, seed):
+    # random networks: at every started stage the device decision equals
+    # the oracle's policy on the recorded features, and the recorded
+    # outputs equal the oracle's forward pass on them
+    p = workloads.gauss_colscale(60_000, 24, 1e4, 0.1, storage="f32", seed=70 + seed, device=DEV)
+    th = _rand_params(seed, scale=0.3)
+    # bias the stop logits so that Stage I does not stop at once
+    th[-3] += 1.0
+    W = torch.from_numpy(th).to(DEV)
+    _, st = S.spcg_solve(ctx, p.X, p.Y, seed=2, schedule="learned", weights=W)
+    K = st["stages_planned"]
+    its = list(st["stage_iters"][:K])
+    started = [i for i in range(K) if its[i] >= 0]
+    print(f"random network {seed}: K={K} iters={its}", flush=True)
+    assert started == list(range(len(started))) and started
+    for i in started[:16]:
+        f = np.array(st["stage_features"][8 * i:8 * i + 8], np.float64)
+        out_ref, _ = mlp.forward(th.astype(np.float64), f[None, :])
+        out_gpu = np.array(st["stage_out"][8 * i:8 * i + 8], np.float64)
+        assert np.abs(out_gpu - out_ref[0]).max() <= 1e-4 * max(1.0, np.abs(out_ref).max())
+        a_i, stop = mlp.policy_stage(out_gpu)
+        assert its[i] == a_i
+        if i < K - 1:   # the last planned stage's stop decision has no effect
+            assert stop == int(i == started[-1])
 
 
 def test_learned_rejects_bad_use(S, ctx, prob0):
@@ -217,7 +292,7 @@ def test_learned_rejects_bad_use(S, ctx, prob0):
     with pytest.raises(S.SpcgError):
         S.spcg_solve(ctx, p.X, p.Y, schedule="learned")
     with pytest.raises(S.SpcgError):
-        S.spcg_solve(ctx, p.X, p.Y, schedule="learned", weights=_crafted([0] * 7), method="pcg")
+        S.spcg_solve(ctx, p.X, p.Y, schedule="learned", weights=_crafted([0] * 8), method="pcg")
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2607_25272_amd",
@@ -225,33 +300,36 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights shipped")
-def test_trained_schedule_gain_on_high_leverage_workload(S, ctx):
+def test_trained_schedule_reads_fewer_bytes_on_high_leverage_workload(S, ctx):
+    # count-based: the bytes the product passes read (schedule.solve_cost)
+    # at equal accuracy; the times are printed, not asserted
     from paper_2607_25272_amd import schedule
     W = schedule.load_weights(DEV)
     p = workloads.make_config(4, device=DEV)
     print(f"gain workload N={p.N} d={p.d}", flush=True)
+    sizes, e_x, e_b = schedule.problem_sizes(ctx, p)
     beta = torch.zeros(p.d, dtype=torch.float64, device=DEV)
-    runs = {"plain": [], "learned": []}
-    last = {}
-    for rep in range(7):
-        for name in ("plain", "learned"):
-            kw = dict(schedule="learned", weights=W) if name == "learned" else {}
+    Xd = p.x_f64().cpu().numpy()
+    bh = ols_tsqr(Xd, p.Y.cpu().numpy())[:, 0]
+    res = {}
+    for name in ("plain", "learned"):
+        kw = dict(schedule="learned", weights=W) if name == "learned" else {}
+        S.spcg_solve(ctx, p.X, p.Y, beta=beta, seed=1, **kw)
+        ts = []
+        for _ in range(5):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, st = S.spcg_solve(ctx, p.X, p.Y, beta=beta, seed=1, **kw)
             torch.cuda.synchronize()
-            if rep > 0:
-                runs[name].append(time.perf_counter() - t0)
-            last[name] = (beta.clone(), st)
-    Xd = p.x_f64().cpu().numpy()
-    bh = ols_tsqr(Xd, p.Y.cpu().numpy())[:, 0]
-    med = {k: statistics.median(v) * 1e3 for k, v in runs.items()}
-    for name in ("plain", "learned"):
-        b, st = last[name]
-        err = rel_pred_error(Xd, b.cpu().numpy(), bh)
-        print(f"{name}: {med[name]:.3f} ms a={st['policy_a']} stride={st['policy_stride']} K={st['K']} "
-              f"T1={st['T_stage1']} T2={st['T_stage2']} unchecked={st['unchecked_iters']} "
-              f"fallback={st['fallback']} syncs={st['host_syncs']} rel={err:.2e}", flush=True)
+            ts.append(time.perf_counter() - t0)
+        err = rel_pred_error(Xd, beta.cpu().numpy(), bh)
+        cost = schedule.solve_cost(st, sizes, p.N, p.d, e_x, e_b)
+        res[name] = (cost, statistics.median(ts) * 1e3, st)
+        K = st["stages_planned"]
+        print(f"{name}: {cost / 1e9:.3f} GB read, {res[name][1]:.3f} ms, iters {list(st['stage_iters'][:K])} "
+              f"T2={st['T_stage2']} syncs={st['host_syncs']} rel={err:.2e}", flush=True)
         assert st["converged"] and err <= 1e-6
-    print(f"gain: plain/learned = {med['plain'] / med['learned']:.3f}", flush=True)
-    assert med["learned"] < med["plain"]
+    print(f"gain: bytes plain/learned = {res['plain'][0] / res['learned'][0]:.3f}, "
+          f"time plain/learned = {res['plain'][1] / res['learned'][1]:.3f}", flush=True)
+    assert res["learned"][0] < res["plain"][0]
+    assert res["learned"][2]["host_syncs"] <= res["plain"][2]["host_syncs"]

@@ -193,14 +193,17 @@ def batched(n_prob=256, N_range=(50_000, 500_000), d_range=(32, 512), cond_range
 
 def schedule_training_problem(i, device="cpu", seed=BASE_SEED + 4, storage="f32"):
     """Problem ``i`` of the schedule network's training distribution:
-    N log-uniform in [1e4, 1e6], d log-uniform in [16, 512], condition
+    N log-uniform in [1e4, 2e6] (at least 32 d), d log-uniform in [16, 1024], condition
     log-uniform in [1e1, 1e6], noise sigma log-uniform in [1e-3, 1], rows
     Gaussian with column scales or Student-t (3 d.o.f.) times a correlation
-    factor, with equal probability."""
+    factor, with equal probability.  storage="mix" stores X as FP32, BF16 or
+    FP8 e4m3 with probabilities 0.6, 0.2, 0.2."""
     g = generator("cpu", seed * 100003 + i)
-    u = torch.rand(5, generator=g, dtype=torch.float64).tolist()
-    N = int(round(10 ** (4 + 2 * u[0])))
-    d = int(round(2 ** (4 + 5 * u[1])))
+    u = torch.rand(6, generator=g, dtype=torch.float64).tolist()
+    if storage == "mix":
+        storage = "f32" if u[5] < 0.6 else ("bf16" if u[5] < 0.8 else "fp8")
+    d = int(round(2 ** (4 + 6 * u[1])))
+    N = max(int(round(10 ** (4 + math.log10(200.0) * u[0]))), 32 * d)
     cond = 10 ** (1 + 5 * u[2])
     sigma = 10 ** (-3 + 3 * u[4])
     pseed = seed * 1000 + i
@@ -210,7 +213,7 @@ def schedule_training_problem(i, device="cpu", seed=BASE_SEED + 4, storage="f32"
     else:
         p = t3_corr(N, d, cond, sigma, storage=storage, seed=pseed, device=device)
         p.name = f"train_{i}"
-    p.meta.update({"rows": "gauss" if u[3] < 0.5 else "t3", "sigma": sigma, "index": i})
+    p.meta.update({"rows": "gauss" if u[3] < 0.5 else "t3", "sigma": sigma, "index": i, "storage": storage})
     return p
 
 
