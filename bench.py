@@ -15,7 +15,7 @@ cfg2 (default)  the headline workload: N=4e6, d=1000, X = T C (Student-t(3)
                 precision form: the same solves with X stored BF16 and
                 FP8-e4m3 (per-column scales), each with its error against
                 the OLS estimator of the stored and of the unquantized data
-cfg2bf16 / cfg2fp8  one storage type of the same problem (SPCG vs full PCG)
+cfg2f32 / cfg2bf16 / cfg2fp8  one storage type of the same problem (SPCG vs full PCG)
 cfg1            N=1e6, d=500, FP32 storage
 cfg1cs / cfg2cs the same problems solved by SPCG-CS; SPCG-SRHT and full PCG
                 are timed beside it
@@ -53,6 +53,7 @@ WORKLOADS = {
     "cfg2": dict(cfg=2, storage="f32", headline=True,
                  desc=T3_DESC + "; X stored FP32 (the unquantized data); precision form beside it: "
                                 "X stored BF16 and FP8 e4m3 with per-column scales"),
+    "cfg2f32": dict(cfg=2, storage="f32", desc=T3_DESC + "; X stored FP32"),
     "cfg2bf16": dict(cfg=2, storage="bf16", desc=T3_DESC + "; X stored BF16"),
     "cfg2fp8": dict(cfg=2, storage="fp8", desc=T3_DESC + "; X stored FP8 e4m3 with per-column scales"),
     "cfg1": dict(cfg=1, storage="f32",
@@ -80,10 +81,10 @@ DTYPE_NAME = {"f32": "f32", "bf16": "bf16", "fp8": "fp8e4m3", "f64": "f64"}
 # kernel classes of spcg_solve_stats.kernel_* (include/spcg.h SPCG_KT_*)
 KT_NAMES = ["transform_first_pass", "transform_last_pass", "product_S", "product_G", "product_SG",
             "phase_A", "phase_B"]
-KT_KERNELS = ["fwht_pass_kernel / fwht_stream_kernel (first SRHT pass: gather X[p(k)], signs, first bits; "
-              "writes Z)",
-              "fwht_pass_kernel / fwht_stream_kernel (last SRHT pass: remaining bits, scatter to S_K X and "
-              "S_hat X)",
+KT_KERNELS = ["fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (first SRHT pass: gather X[p(k)], "
+              "signs, first bits; writes Z)",
+              "fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (last SRHT pass: remaining bits, "
+              "scatter to S_K X and S_hat X)",
               "product_ring_kernel (S mode: s = c2 A^T A p, Stage I)",
               "product_ring_kernel (G mode: stage-start gradient)",
               "product_ring_kernel (SG mode: s and the refreshed gradient, full data)",
@@ -92,7 +93,9 @@ BYTE_CLASSES = range(5)
 # HBM bytes per launch from rocprofv3 PMC runs (2.0 x FETCH_SIZE + WRITE_SIZE,
 # calibrated on a 1 GiB copy) for a kernel class and workload, taken on the
 # kernel as it now stands; everything else reports null.
-PMC_TRAFFIC = {}
+_T3_F32 = {"transform_first_pass": 3.4145e10, "transform_last_pass": 2.5914e10, "product_S": 1.6783e9,
+           "product_G": 3.3746e9, "product_SG": 1.6037e10}   # profiles/hbm_traffic_t3corr_N4e6_d1000_f32.txt
+PMC_TRAFFIC = {(k, w): v for k, v in _T3_F32.items() for w in ("cfg2", "cfg2f32")}
 
 
 def log(msg):
