@@ -895,10 +895,10 @@ struct StageHooks {
         const void* src;
         size_t bytes;
     };
-    Copy copies[4] = {};
+    Copy copies[6] = {};
     int ncopy = 0;
     void add_copy(void* dst, const void* src, size_t bytes) {
-        if (ncopy < 4 && bytes > 0) copies[ncopy++] = Copy{dst, src, bytes};
+        if (ncopy < 6 && bytes > 0) copies[ncopy++] = Copy{dst, src, bytes};
     }
     const int32_t* t1_host = nullptr;
     int t_total = 0;
@@ -2244,7 +2244,6 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
         ctl = reinterpret_cast<int32_t*>(sched + SF_CTL);
         HIP_TRY(ctx, run_features_pre(st, X->data, X->dtype, X->rows, d, X->ld, X->col_scale, pc.pR, d,
                                       sched + SF_BASE));
-        HIP_TRY(ctx, hipMemcpyAsync(host_fpre, sched + SF_BASE, 8 * sizeof(float), hipMemcpyDeviceToHost, st));
     }
     // stage features known on the host: size, Theorem 3.3 bound (omega =
     // 1/2) over the planned sizes, position
@@ -2322,8 +2321,11 @@ int spcg_solve(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg_s
     std::vector<float> host_sf(features ? 8 * SCHED_FREC : 0), host_so(learned ? 8 * SCHED_FREC : 0);
     const int nrec = std::min(Krun, SCHED_FREC);
     if (features) {
+        // the base features come back with the first stopping test (a copy
+        // to pageable host memory here would stall the host before Stage I)
         hooks.fpre = sched + SF_BASE;
         hooks.fii = sched + SF_II;
+        hooks.add_copy(host_fpre, sched + SF_BASE, 8 * sizeof(float));
         if (nrec > 0) hooks.add_copy(host_sf.data(), sched + SF_STAGE, (size_t)nrec * 8 * sizeof(float));
     }
     if (learned) {

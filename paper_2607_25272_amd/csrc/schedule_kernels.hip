@@ -251,36 +251,45 @@ __device__ __forceinline__ double load_elem<fp8_t>(const fp8_t* p, int64_t i, co
     return (double)fp8e4m3_bits_to_f32(p[i].bits) * (double)cs[c];
 }
 
-// Features known before Stage I (one block): the problem shape, the spread
-// of diag(R) and the row-norm spread over 256 evenly spaced rows.
+// Features known before Stage I (one block of 16 waves): the problem
+// shape, the spread of diag(R) and the row-norm spread over 256 evenly
+// spaced rows.  Wave w takes the sampled rows w, w + 16, ...; its lanes
+// read a row's columns in stride (coalesced), the squared norm is summed
+// per lane and across the wave.
 template <typename TS>
-__global__ __launch_bounds__(256) void features_pre_kernel(const TS* __restrict__ X, int64_t N, int64_t d, int64_t ld,
-                                                           const float* __restrict__ cs,
-                                                           const double* __restrict__ R, int64_t ldr,
-                                                           float* __restrict__ f) {
-    __shared__ double s_max[256], s_sum[256], s_dmin[256], s_dmax[256];
-    const int t = threadIdx.x;
+__global__ __launch_bounds__(1024) void features_pre_kernel(const TS* __restrict__ X, int64_t N, int64_t d,
+                                                            int64_t ld, const float* __restrict__ cs,
+                                                            const double* __restrict__ R, int64_t ldr,
+                                                            float* __restrict__ f) {
+    __shared__ double s_q[MLP_SAMPLE_ROWS];
+    __shared__ double s_max[1024], s_sum[1024], s_dmin[1024], s_dmax[1024];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const bool all = N >= MLP_SAMPLE_ROWS;
-    double q = 0.0;
-    if (all || t < N) {
-        const int64_t j = all ? ((2 * (int64_t)t + 1) * N) / (2 * MLP_SAMPLE_ROWS) : t;
-        for (int64_t c = 0; c < d; ++c) {
+    const int nrows = all ? MLP_SAMPLE_ROWS : (int)N;
+    for (int r = wave; r < nrows; r += 16) {
+        const int64_t j = all ? ((2 * (int64_t)r + 1) * N) / (2 * MLP_SAMPLE_ROWS) : r;
+        double q = 0.0;
+        for (int64_t c = lane; c < d; c += 64) {
             const double v = load_elem<TS>(X, j * ld + c, cs, c);
             q = fma(v, v, q);
         }
+        for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+        if (lane == 0) s_q[r] = q;
     }
+    __syncthreads();
     double mn = INFINITY, mx = 0.0;
-    for (int64_t c = t; c < d; c += 256) {
+    for (int64_t c = t; c < d; c += 1024) {
         const double r = fabs(R[c * ldr + c]);
         mn = fmin(mn, r);
         mx = fmax(mx, r);
     }
+    const double q = t < nrows ? s_q[t] : 0.0;
     s_max[t] = q;
     s_sum[t] = q;
     s_dmin[t] = mn;
     s_dmax[t] = mx;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if (t < o) {
             s_max[t] = fmax(s_max[t], s_max[t + o]);
             s_sum[t] += s_sum[t + o];
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(256) void features_pre_kernel(const TS* __restrict_
         __syncthreads();
     }
     if (t == 0) {
-        const double cnt = all ? (double)MLP_SAMPLE_ROWS : (double)N;
+        const double cnt = (double)nrows;
         const double sum = s_sum[0];
         f[0] = (float)(log10((double)N) - 5.0);
         f[1] = (float)(log10((double)d) - 2.0);
@@ -434,19 +443,19 @@ hipError_t run_features_pre(hipStream_t st, const void* X, int dtype, int64_t N,
                             const float* col_scale, const double* R, int64_t ldr, float* f) {
     switch (dtype) {
         case DT_F64:
-            features_pre_kernel<double><<<1, 256, 0, st>>>(static_cast<const double*>(X), N, d, ld, col_scale, R,
+            features_pre_kernel<double><<<1, 1024, 0, st>>>(static_cast<const double*>(X), N, d, ld, col_scale, R,
                                                            ldr, f);
             break;
         case DT_F32:
-            features_pre_kernel<float><<<1, 256, 0, st>>>(static_cast<const float*>(X), N, d, ld, col_scale, R, ldr,
+            features_pre_kernel<float><<<1, 1024, 0, st>>>(static_cast<const float*>(X), N, d, ld, col_scale, R, ldr,
                                                           f);
             break;
         case DT_BF16:
-            features_pre_kernel<bf16_t><<<1, 256, 0, st>>>(static_cast<const bf16_t*>(X), N, d, ld, col_scale, R,
+            features_pre_kernel<bf16_t><<<1, 1024, 0, st>>>(static_cast<const bf16_t*>(X), N, d, ld, col_scale, R,
                                                            ldr, f);
             break;
         case DT_FP8:
-            features_pre_kernel<fp8_t><<<1, 256, 0, st>>>(static_cast<const fp8_t*>(X), N, d, ld, col_scale, R, ldr,
+            features_pre_kernel<fp8_t><<<1, 1024, 0, st>>>(static_cast<const fp8_t*>(X), N, d, ld, col_scale, R, ldr,
                                                           f);
             break;
         default:
