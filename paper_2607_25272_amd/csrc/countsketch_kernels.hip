@@ -134,6 +134,94 @@ __device__ __forceinline__ void store4(void* out, int out_dtype, int64_t idx, co
     }
 }
 
+// C consecutive elements of one row, as raw 32-bit words (loaded first,
+// widened later, so that many rows' loads are in flight at once).
+template <typename TIN, int C>
+struct Piece {
+    static constexpr int EB = (int)sizeof(TIN);
+    static constexpr int NW = (C * EB + 3) / 4;
+    uint32_t w[NW];
+};
+
+// the row's elements col .. col + C - 1 (zeros past d); one vector load
+// when the piece lies inside the row and vec is set
+template <typename TIN, int C>
+__device__ __forceinline__ void load_piece(Piece<TIN, C>& pc, const void* x, int64_t row, int64_t ldx, int64_t col,
+                                           int64_t d, bool vec) {
+    constexpr int EB = (int)sizeof(TIN), BYTES = C * EB;
+    const unsigned char* p = static_cast<const unsigned char*>(x) + (row * ldx + col) * EB;
+    if (vec && col + C <= d) {
+        if constexpr (BYTES == 8) {
+            const uint2 v = *reinterpret_cast<const uint2*>(p);
+            pc.w[0] = v.x;
+            pc.w[1] = v.y;
+        } else {
+            static_assert(BYTES % 16 == 0, "8-, 16- or 32-byte pieces");
+#pragma unroll
+            for (int h = 0; h < BYTES / 16; ++h) {
+                const uint4 v = reinterpret_cast<const uint4*>(p)[h];
+                pc.w[4 * h] = v.x;
+                pc.w[4 * h + 1] = v.y;
+                pc.w[4 * h + 2] = v.z;
+                pc.w[4 * h + 3] = v.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Piece<TIN, C>::NW; ++i) pc.w[i] = 0u;
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            if (col + e < d) {
+                if constexpr (EB == 1) {
+                    pc.w[e / 4] |= (uint32_t)p[e] << (8 * (e % 4));
+                } else if constexpr (EB == 2) {
+                    pc.w[e / 2] |= (uint32_t)reinterpret_cast<const uint16_t*>(p)[e] << (16 * (e % 2));
+                } else if constexpr (EB == 4) {
+                    pc.w[e] = reinterpret_cast<const uint32_t*>(p)[e];
+                } else {
+                    pc.w[2 * e] = reinterpret_cast<const uint32_t*>(p)[2 * e];
+                    pc.w[2 * e + 1] = reinterpret_cast<const uint32_t*>(p)[2 * e + 1];
+                }
+            }
+        }
+    }
+}
+
+// exact widening of a piece (FP8 without its column scale)
+template <typename TIN, typename TZ, int C>
+__device__ __forceinline__ void widen_piece(const Piece<TIN, C>& pc, TZ* o) {
+    if constexpr (std::is_same<TIN, double>::value) {
+#pragma unroll
+        for (int e = 0; e < C; ++e) o[e] = __hiloint2double((int)pc.w[2 * e + 1], (int)pc.w[2 * e]);
+    } else if constexpr (std::is_same<TIN, float>::value) {
+#pragma unroll
+        for (int e = 0; e < C; ++e) o[e] = __uint_as_float(pc.w[e]);
+    } else if constexpr (std::is_same<TIN, bf16_t>::value) {
+#pragma unroll
+        for (int e = 0; e < C; e += 2) {
+            o[e] = __uint_as_float(pc.w[e / 2] << 16);
+            o[e + 1] = __uint_as_float(pc.w[e / 2] & 0xffff0000u);
+        }
+    } else {
+        typedef float v2f_t __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int e = 0; e < C; e += 4) {
+            const v2f_t lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)pc.w[e / 4], false);
+            const v2f_t hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)pc.w[e / 4], true);
+            o[e] = lo.x;
+            o[e + 1] = lo.y;
+            o[e + 2] = hi.x;
+            o[e + 3] = hi.y;
+        }
+    }
+}
+
+// C columns per lane: 16-byte pieces (8-byte for FP8, two 16-byte loads for
+// FP64); a lane group of LPB lanes covers a C LPB-column window.
+template <typename TIN>
+constexpr int tree_cols() {
+    return std::is_same<TIN, bf16_t>::value || std::is_same<TIN, fp8_t>::value ? 8 : 4;
+}
 struct GatherArgs {
     CsJob j;
     int nwin;      // column windows per row
@@ -142,11 +230,14 @@ struct GatherArgs {
     void* seg_out; // nseg > 1: partial sums [seg][bucket][ld] in the sum type
 };
 
-// LPB lanes take one (bucket, 4 LPB-column window) pair, so a wave holds
-// 64 / LPB buckets at once when the rows are short.
+// LPB lanes take one (bucket, C LPB-column window) pair (C = tree_cols:
+// 8 for BF16 / FP8, 4 otherwise), so a wave holds 64 / LPB buckets at once
+// when the rows are short.
 template <typename TIN, typename TZ, int LPB>
 __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) {
     constexpr int NG = 64 / LPB;
+    constexpr int C = tree_cols<TIN>();
+    constexpr bool FP8 = std::is_same<TIN, fp8_t>::value;
     const CsJob& j = a.j;
     const int lane = threadIdx.x & 63, gi = lane / LPB, sl = lane % LPB;
     const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -161,9 +252,11 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) 
         const int sg = (int)(task - rest * a.nseg);
         const int64_t b = rest / a.nwin;
         const int w = (int)(rest - b * a.nwin);
-        const int64_t c = (int64_t)w * 4 * LPB + 4 * sl;
+        const int64_t c = (int64_t)w * C * LPB + C * sl;
         const bool do_y = j.outy && w == 0;
-        TZ acc[4] = {TZ(0), TZ(0), TZ(0), TZ(0)};
+        TZ acc[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) acc[q] = TZ(0);
         double yacc = 0.0;
         for (int64_t y0 = b + sg * j.nbk; y0 < j.Np; y0 += CS_MU * step) {
             int32_t e[CS_MU];
@@ -172,35 +265,45 @@ __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_kernel(GatherArgs a) 
                 const int64_t yv = y0 + (int64_t)u * step;
                 e[u] = yv < j.Np ? j.tbl[yv] : 0x7fffffff;   // past the end: no row
             }
-            TZ v[CS_MU][4];
+            Piece<TIN, C> pc[CS_MU];
             double yv_[CS_MU];
 #pragma unroll
             for (int u = 0; u < CS_MU; ++u) {
                 const int64_t k = e[u] & 0x7fffffff;
                 yv_[u] = 0.0;
                 if (k < j.N) {
-                    Load4<TIN, TZ>::run(j.x, k, j.ldx, c, j.d, vec, j.col_scale, v[u]);
+                    load_piece<TIN, C>(pc[u], j.x, k, j.ldx, c, j.d, vec);
                     if (do_y && sl < j.k) yv_[u] = j.y[k * j.ldy_in + sl];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v[u][q] = TZ(0);
+                    for (int i = 0; i < Piece<TIN, C>::NW; ++i) pc[u].w[i] = 0u;
                 }
             }
 #pragma unroll
             for (int u = 0; u < CS_MU; ++u) {
+                TZ v[C];
+                widen_piece<TIN, TZ, C>(pc[u], v);
                 const bool neg = e[u] < 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] += neg ? -v[u][q] : v[u][q];
+                for (int q = 0; q < C; ++q) acc[q] += neg ? -v[q] : v[q];
                 yacc += neg ? -yv_[u] : yv_[u];
             }
         }
+        // FP8: the power-of-two column scales, applied to the sums (exact)
+        if constexpr (FP8) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) acc[q] *= c + q < j.d ? j.col_scale[c + q] : 0.f;
+        }
         constexpr int SUM_DT = std::is_same<TZ, double>::value ? DT_F64 : DT_F32;
         if (c < j.ld) {
-            if (a.nseg > 1) {
-                store4<TZ>(a.seg_out, SUM_DT, ((int64_t)sg * j.nbk + b) * j.ld + c, acc);
-            } else {
-                store4<TZ>(j.out, j.out_dtype, b * j.ld + c, acc);
-                if (j.work) store4<TZ>(j.work, SUM_DT, b * j.ld + c, acc);
+#pragma unroll
+            for (int q = 0; q < C; q += 4) {
+                if (a.nseg > 1) {
+                    store4<TZ>(a.seg_out, SUM_DT, ((int64_t)sg * j.nbk + b) * j.ld + c + q, acc + q);
+                } else {
+                    store4<TZ>(j.out, j.out_dtype, b * j.ld + c + q, acc + q);
+                    if (j.work) store4<TZ>(j.work, SUM_DT, b * j.ld + c + q, acc + q);
+                }
             }
         }
         if (do_y && sl < j.ldoy) j.outy[b * j.ldoy + sl] = sl < j.k ? yacc : 0.0;
@@ -262,8 +365,133 @@ struct TreeArgs {
 
 constexpr int ipow(int g, int j) { return j == 0 ? 1 : g * ipow(g, j - 1); }
 
+constexpr int TREE_MU = 2;      // slots per finest bucket loaded together
+
+// BF16 / FP8 input: 8 columns per lane (16- or 8-byte pieces) and every
+// finest bucket's TREE_MU next rows loaded together (the 4-column kernel
+// left these narrow rows latency-bound: 6.6-7.4 ms whatever the element
+// size at N = 4e6, d = 1000)
 template <typename TIN, typename TZ, int G, int J, int LPB>
 __global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree_kernel(TreeArgs a) {
+    static_assert(tree_cols<TIN>() == 8, "narrow input only");
+    constexpr int NF = ipow(G, J);   // finest buckets per coarse bucket
+    constexpr int NG = 64 / LPB;     // coarse buckets per wave (short rows)
+    constexpr int C = tree_cols<TIN>();
+    constexpr bool FP8 = std::is_same<TIN, fp8_t>::value;
+    const CsJob& j = a.j;
+    const int lane = threadIdx.x & 63, gi = lane / LPB, sl = lane % LPB;
+    const int64_t wave0 = (int64_t)blockIdx.x * CS_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nwaves = (int64_t)gridDim.x * CS_WAVES;
+    const int64_t mc = a.m[J];
+    const int64_t ntask = mc * a.nwin;
+    const bool vec = a.xvec != 0;
+    for (int64_t t0 = wave0 * NG; t0 < ntask; t0 += nwaves * NG) {
+        const int64_t task = t0 + gi;
+        if (task >= ntask) continue;
+        const int64_t c = task / a.nwin;
+        const int w = (int)(task - c * a.nwin);
+        const int64_t col = (int64_t)w * C * LPB + C * sl;
+        const bool do_y = j.outy && w == 0;
+        TZ acc[NF][C];
+        double yacc[NF];
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) acc[t][q] = TZ(0);
+            yacc[t] = 0.0;
+        }
+        // the slots of finest bucket c + t mc are c + t mc + s nbk, s =
+        // 0, 1, ...; TREE_MU slots of every finest bucket per round, all
+        // rows' loads issued before any is added, each bucket's rows added
+        // in ascending slot order
+        for (int64_t s0 = 0; c + s0 * j.nbk < j.Np; s0 += TREE_MU) {
+            int32_t e[NF][TREE_MU];
+#pragma unroll
+            for (int t = 0; t < NF; ++t) {
+#pragma unroll
+                for (int u = 0; u < TREE_MU; ++u) {
+                    const int64_t yv = c + t * mc + (s0 + u) * j.nbk;
+                    e[t][u] = yv < j.Np ? j.tbl[yv] : 0x7fffffff;   // past the end: no row
+                }
+            }
+            Piece<TIN, C> pc[NF][TREE_MU];
+            double yv_[NF][TREE_MU];
+#pragma unroll
+            for (int t = 0; t < NF; ++t) {
+#pragma unroll
+                for (int u = 0; u < TREE_MU; ++u) {
+                    const int64_t k = e[t][u] & 0x7fffffff;
+                    yv_[t][u] = 0.0;
+                    if (k < j.N) {
+                        load_piece<TIN, C>(pc[t][u], j.x, k, j.ldx, col, j.d, vec);
+                        if (do_y && sl < j.k) yv_[t][u] = j.y[k * j.ldy_in + sl];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < Piece<TIN, C>::NW; ++i) pc[t][u].w[i] = 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NF; ++t) {
+#pragma unroll
+                for (int u = 0; u < TREE_MU; ++u) {
+                    TZ v[C];
+                    widen_piece<TIN, TZ, C>(pc[t][u], v);
+                    const bool neg = e[t][u] < 0;
+#pragma unroll
+                    for (int q = 0; q < C; ++q) acc[t][q] += neg ? -v[q] : v[q];
+                    yacc[t] += neg ? -yv_[t][u] : yv_[t][u];
+                }
+            }
+        }
+        // FP8: the power-of-two column scales, applied to the sums (exact:
+        // scaling by 2^e commutes with FP32 rounding in the normal range)
+        if constexpr (FP8) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const float sc = col + q < j.d ? j.col_scale[col + q] : 0.f;
+#pragma unroll
+                for (int t = 0; t < NF; ++t) acc[t][q] *= sc;
+            }
+        }
+        auto put = [&](void* out, int dt, int64_t row, const TZ* v) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < C; q += 4) store4<TZ>(out, dt, row * j.ld + col + q, v + q);
+        };
+#pragma unroll
+        for (int t = 0; t < NF; ++t) {
+            if (col < j.ld) put(a.out[0], j.out_dtype, c + t * mc, acc[t]);
+            if (do_y && sl < j.ldoy) a.outy[0][(c + t * mc) * j.ldoy + sl] = sl < j.k ? yacc[t] : 0.0;
+        }
+        // coarser levels: bucket s of level l adds buckets s + r G^(J-l) of
+        // level l - 1 in ascending r (the folding order)
+#pragma unroll
+        for (int l = 1; l <= J; ++l) {
+            const int nb = ipow(G, J - l);
+#pragma unroll
+            for (int s2 = 0; s2 < NF; ++s2) {
+                if (s2 >= nb) continue;
+#pragma unroll
+                for (int r = 1; r < G; ++r) {
+#pragma unroll
+                    for (int q = 0; q < C; ++q) acc[s2][q] += acc[s2 + r * nb][q];
+                    yacc[s2] += yacc[s2 + r * nb];
+                }
+                if (col < j.ld) put(a.out[l], j.out_dtype, c + s2 * mc, acc[s2]);
+                if (do_y && sl < j.ldoy) a.outy[l][(c + s2 * mc) * j.ldoy + sl] = sl < j.k ? yacc[s2] : 0.0;
+            }
+        }
+        if (a.work && col < j.ld) put(a.work, std::is_same<TZ, double>::value ? DT_F64 : DT_F32, c, acc[0]);
+    }
+}
+
+// FP32 / FP64 input: 4 columns per lane, each finest bucket's rows walked
+// in turn (CS_MU at a time); at high occupancy this keeps the FP32 pass
+// near the mixed read/write ceiling, where loading every finest bucket's
+// rows together (cs_gather_tree_kernel) measured slower (9.9 against
+// 11.6 ms for the sketch phase at N = 4e6, d = 1000)
+template <typename TIN, typename TZ, int G, int J, int LPB>
+__global__ __launch_bounds__(64 * CS_WAVES) void cs_gather_tree4_kernel(TreeArgs a) {
     constexpr int NF = ipow(G, J);   // finest buckets per coarse bucket
     constexpr int NG = 64 / LPB;     // coarse buckets per wave (short rows)
     const CsJob& j = a.j;
@@ -347,7 +575,10 @@ template <typename TIN, typename TZ, int G, int J, int LPB>
 hipError_t tree_launch(hipStream_t st, const TreeArgs& a) {
     const int64_t ntask = a.m[J] * a.nwin;
     const int64_t blocks = std::min<int64_t>(ceil_div(ntask, CS_WAVES * (64 / LPB)), 65536);
-    cs_gather_tree_kernel<TIN, TZ, G, J, LPB><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+    if constexpr (tree_cols<TIN>() == 4)
+        cs_gather_tree4_kernel<TIN, TZ, G, J, LPB><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
+    else
+        cs_gather_tree_kernel<TIN, TZ, G, J, LPB><<<dim3((unsigned)blocks), dim3(64 * CS_WAVES), 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -386,10 +617,10 @@ hipError_t gather_launch(hipStream_t st, const GatherArgs& a, int lpb) {
 }
 
 // Lanes per (bucket, window): the narrowest power of two >= 16 that covers
-// the row with 4 columns per lane (and the responses, one per lane).
-int lanes_per_bucket(int64_t ld, int64_t k) {
+// the row with `cols` columns per lane (and the responses, one per lane).
+int lanes_per_bucket(int64_t ld, int64_t k, int cols = 4) {
     int lpb = 16;
-    while (lpb < 64 && (4 * lpb < ld || lpb < k)) lpb *= 2;
+    while (lpb < 64 && (cols * lpb < ld || lpb < k)) lpb *= 2;
     return lpb;
 }
 
@@ -412,8 +643,9 @@ hipError_t run_cs_gather(hipStream_t st, const CsJob& j) {
     if (j.outy && (j.k < 1 || j.k > 64 || j.ldoy < j.k || j.ldoy > 64)) return hipErrorInvalidValue;
     GatherArgs a{};
     a.j = j;
-    const int lpb = lanes_per_bucket(j.ld, j.outy ? std::max<int64_t>(j.k, j.ldoy) : 1);
-    a.nwin = (int)ceil_div(j.ld, 4 * lpb);
+    const int C = (j.in_dtype == DT_BF16 || j.in_dtype == DT_FP8) ? 8 : 4;   // tree_cols
+    const int lpb = lanes_per_bucket(j.ld, j.outy ? std::max<int64_t>(j.k, j.ldoy) : 1, C);
+    a.nwin = (int)ceil_div(j.ld, (int64_t)C * lpb);
     // few, long buckets (the preconditioner sketch at small d): split each
     // bucket's slots over segments so that enough lane groups stream rows
     a.nseg = 1;
@@ -428,7 +660,8 @@ hipError_t run_cs_gather(hipStream_t st, const CsJob& j) {
         }
     }
     const int es = dtype_bytes(j.in_dtype);
-    a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
+    const int64_t align = std::min<int64_t>(16, (int64_t)C * es);
+    a.xvec = (j.ldx * es) % align == 0 && (uintptr_t)j.x % align == 0;
     hipError_t e;
     switch (j.in_dtype) {
         case DT_F64: e = gather_launch<double, double>(st, a, lpb); break;
@@ -461,10 +694,13 @@ hipError_t run_cs_gather_tree(hipStream_t st, const CsTreeJob& t) {
     TreeArgs a{};
     a.j = j;
     a.j.outy = nullptr;
-    const int lpb = lanes_per_bucket(j.ld, t.outy[0] ? std::max<int64_t>(j.k, j.ldoy) : 1);
-    a.nwin = (int)ceil_div(j.ld, 4 * lpb);
+    // C columns per lane (tree_cols): 8 for BF16 / FP8, 4 otherwise
+    const int C = (j.in_dtype == DT_BF16 || j.in_dtype == DT_FP8) ? 8 : 4;
+    const int lpb = lanes_per_bucket(j.ld, t.outy[0] ? std::max<int64_t>(j.k, j.ldoy) : 1, C);
+    a.nwin = (int)ceil_div(j.ld, (int64_t)C * lpb);
     const int es = dtype_bytes(j.in_dtype);
-    a.xvec = (j.ldx * es) % (4 * es) == 0 && (uintptr_t)j.x % (4 * es) == 0;
+    const int64_t align = std::min<int64_t>(16, (int64_t)C * es);
+    a.xvec = (j.ldx * es) % align == 0 && (uintptr_t)j.x % align == 0;
     for (int l = 0; l <= t.levels; ++l) {
         a.out[l] = t.out[l];
         a.outy[l] = t.outy[l];
