@@ -295,7 +295,8 @@ typedef struct spcg_solve_opts {
                                  plain schedule (returned in the stats) */
     int32_t batch_direct;     /* batched form: 1 launches every pass directly; 0 (default)
                                  captures each Stage I stage, and the Stage II product and
-                                 d-space launches of each active set, in hipGraphs */
+                                 d-space launches of each active set, in hipGraphs, which the
+                                 context keeps and later calls update in place */
     int32_t batch_tasks_per_cu; /* batched form, full-data passes: tasks per CU of each
                                    row-width class launch; 0 (default) autotunes it once per
                                    context and storage type, timing one product pass with

@@ -1107,7 +1107,14 @@ struct BatchWork {
     hipEvent_t lane_join[NLANE] = {};
     DenseStatus* hstat = nullptr;
     size_t hstat_n = 0;
+    // executable graphs kept across solves, by slot (Stage I stage i: slot
+    // i; Stage II active set j: slots 64 + 2 j (products) and 65 + 2 j
+    // (d-space)); a later solve updates them in place
+    std::vector<hipGraphExec_t> gcache;
+    bool gcache_busy = false;   // a solve launched cached graphs and did not finish normally
     ~BatchWork() {
+        for (auto e : gcache)
+            if (e) (void)hipGraphExecDestroy(e);
         for (auto* p : sk) delete p;
         for (auto* p : pc) delete p;
         for (auto* c : lane) {
@@ -1283,9 +1290,15 @@ int batched_dspace(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int variant, con
 // Captures the launches of body(stream) into an executable graph, recorded
 // on the private capture stream (the library stream may be the null stream,
 // which cannot be captured).  *exec stays null when capture is unavailable;
-// the caller then launches directly.
+// the caller then launches directly.  With slot >= 0 the executable graph
+// of that slot from an earlier solve is updated in place with the new
+// capture (hipGraphExecUpdate: the same topology with new kernel arguments
+// needs no instantiation) and stays cached; a failed update instantiates
+// anew.  Cached graphs are idle here: every solve ends with a stream
+// synchronisation after its last graph launch, and slots are unique
+// within a solve.
 template <class F>
-int capture_graph(spcg_ctx* ctx, BatchWork& W, F&& body, hipGraphExec_t* exec) {
+int capture_graph(spcg_ctx* ctx, BatchWork& W, F&& body, hipGraphExec_t* exec, int slot = -1) {
     *exec = nullptr;
     if (hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
@@ -1303,6 +1316,29 @@ int capture_graph(spcg_ctx* ctx, BatchWork& W, F&& body, hipGraphExec_t* exec) {
         if (g) (void)hipGraphDestroy(g);
         return SPCG_OK;
     }
+    if (slot >= 0) {
+        if ((int)W.gcache.size() <= slot) W.gcache.resize((size_t)slot + 1, nullptr);
+        hipGraphExec_t& c = W.gcache[(size_t)slot];
+        if (c) {
+            hipGraphNode_t err_node = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            if (hipGraphExecUpdate(c, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+                (void)hipGraphDestroy(g);
+                *exec = c;
+                return SPCG_OK;
+            }
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(c);
+            c = nullptr;
+        }
+        if (hipGraphInstantiate(&c, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            c = nullptr;
+        }
+        (void)hipGraphDestroy(g);
+        *exec = c;
+        return SPCG_OK;
+    }
     const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) {
@@ -1312,18 +1348,18 @@ int capture_graph(spcg_ctx* ctx, BatchWork& W, F&& body, hipGraphExec_t* exec) {
     return SPCG_OK;
 }
 
-// Runs body once: as a captured graph launched on the library stream when
-// graphs are on (the graph is kept in *keep for destruction after the
-// solve), else directly on the library stream.
+// Runs body once: as a captured graph of the given cache slot launched on
+// the library stream when graphs are on (*launched counts it), else
+// directly on the library stream.
 template <class F>
-int run_captured(spcg_ctx* ctx, BatchWork& W, bool graphs, F&& body, std::vector<hipGraphExec_t>& keep) {
+int run_captured(spcg_ctx* ctx, BatchWork& W, bool graphs, F&& body, int slot, int* launched) {
     if (graphs) {
         hipGraphExec_t ex = nullptr;
         int rc;
-        if ((rc = capture_graph(ctx, W, body, &ex)) != SPCG_OK) return rc;
+        if ((rc = capture_graph(ctx, W, body, &ex, slot)) != SPCG_OK) return rc;
         if (ex) {
-            keep.push_back(ex);
             HIP_TRY(ctx, hipGraphLaunch(ex, ctx->stream));
+            ++*launched;
             return SPCG_OK;
         }
     }
@@ -1442,16 +1478,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     const int64_t target_tasks = 4 * (int64_t)ctx->num_cu;
     const bool graphs_on = opts->batch_direct == 0;
     if ((rc = batch_streams(ctx, W)) != SPCG_OK) return rc;
-    // executable graphs of this solve, destroyed once the stream is idle
-    struct GraphList {
-        hipStream_t st;
-        std::vector<hipGraphExec_t> g;
-        ~GraphList() {
-            if (!g.empty()) (void)hipStreamSynchronize(st);
-            for (auto e : g) (void)hipGraphExecDestroy(e);
-        }
-    } graphs{st, {}};
     int graphs_launched = 0;
+    // cached graphs may still run if an earlier solve returned early
+    if (graphs_on && W.gcache_busy) HIP_TRY(ctx, hipStreamSynchronize(st));
+    W.gcache_busy = graphs_on;
     std::vector<int> t1(nprob, 0), t2(nprob, 0), conv(nprob, 0);
     // Stage I: stage i of every problem that has one; its G pass and a_i S
     // passes form one graph
@@ -1490,9 +1520,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             }
             return SPCG_OK;
         };
-        const size_t before = graphs.g.size();
-        if ((rc = run_captured(ctx, W, graphs_on, stage, graphs.g)) != SPCG_OK) return rc;
-        graphs_launched += (int)(graphs.g.size() - before);
+        if ((rc = run_captured(ctx, W, graphs_on, stage, (int)i, &graphs_launched)) != SPCG_OK) return rc;
         for (int p = 0; p < nprob; ++p)
             if (hp[p].active) t1[p] += ai;
     }
@@ -1589,20 +1617,20 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // each active set, replayed every iteration (events around the product
     // graph time the products alone)
     hipGraphExec_t gprod = nullptr, gds = nullptr;
+    int set_index = 0;   // active sets of this Stage II, for the graph cache slots
     while (act > 0) {
         if (set_changed) {
             if ((rc = batched_setup(ctx, W, dtype, hp, full_tasks, plan)) != SPCG_OK) return rc;
             set_changed = false;
             gprod = gds = nullptr;
             if (graphs_on) {
+                const int slot = 64 + 2 * set_index++;
                 if ((rc = capture_graph(ctx, W, [&](hipStream_t s) { return batched_products(ctx, W, s, dtype, PM_SG, plan); },
-                                        &gprod)) != SPCG_OK)
+                                        &gprod, slot)) != SPCG_OK)
                     return rc;
-                if (gprod) graphs.g.push_back(gprod);
                 if ((rc = capture_graph(ctx, W, [&](hipStream_t s) { return batched_dspace(ctx, W, s, PA_REFRESH, plan); },
-                                        &gds)) != SPCG_OK)
+                                        &gds, slot + 1)) != SPCG_OK)
                     return rc;
-                if (gds) graphs.g.push_back(gds);
             }
         }
         const bool timed = opts->time_products && timer.used < MAX_TIMED;
@@ -1640,6 +1668,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             HIP_TRY(ctx, hipMemcpy2DAsync(beta[p] + c, (size_t)hp[p].k * 8, hp[p].X + (size_t)c * ldv, 8, 8, hp[p].d,
                                           hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
+    W.gcache_busy = false;
     double prod_ms = 0.0;
     for (int i = 0; i < timer.used; ++i) prod_ms += elapsed_ms(ctx->ev_prod[2 * i], ctx->ev_prod[2 * i + 1]);
     bool all = true;
