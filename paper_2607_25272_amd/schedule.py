@@ -11,11 +11,12 @@ training calls the library's forward/backward and Adam kernels
 
 Labels.  For a problem, the variants (a, pattern, j) are solved with the
 plain stopping test: every planned stage (every prefix of the sketch) but
-the last j runs a_i = a iterations ("all"), or a and 0 alternately, ending
-with a at the last stage run ("alt").  Each run is costed by the bytes its
+the last j runs a_i = a iterations ("all"), a and 0 alternately, ending
+with a at the last stage run ("alt"), or a on the first half and on the
+last stage run with 0 between ("ends").  Each run is costed by the bytes its
 product passes read (``solve_cost``).  Among the converged variants within
 2% of the cheapest, the label variant is the one that stops earliest
-(largest j), then "all" before "alt", then the largest a -- a fixed
+(largest j), then "all" before "ends" before "alt", then the largest a -- a fixed
 tie-break, so that near-equal variants do not scatter the labels.  It
 gives one sample per stage it ran (the stage features recorded in that
 run, label a_i, stop = 1 at its last stage when j > 0), and every
@@ -34,7 +35,9 @@ from . import spcg_mlp_adam, spcg_mlp_forward, spcg_mlp_loss_grad, spcg_sketch, 
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedule_weights.json")
 NA = L.SPCG_MLP_O - 3          # a_i choices 0..NA-1
 VARIANTS = ([(a, "all", j) for a in (2, 3, 4) for j in range(6)]
-            + [(4, "alt", j) for j in range(4)])
+            + [(4, "alt", j) for j in range(4)]
+            + [(a, "ends", j) for a in (3, 4) for j in range(5)])
+PATTERN_ORDER = {"all": 2, "ends": 1, "alt": 0}   # label tie-break among near-equal variants
 COST_TOL = 1.02
 PLAIN = (3, "all", 0)
 _ES = {torch.float64: 8, torch.float32: 4, torch.bfloat16: 2, torch.float8_e4m3fn: 1}
@@ -73,10 +76,16 @@ def init_weights(seed, device):
 
 
 def a_list_of(K, a, pattern, j):
-    """Per-stage iteration counts of variant (a, pattern, j) over K planned stages."""
+    """Per-stage iteration counts of variant (a, pattern, j) over K planned
+    stages: "all" a everywhere, "alt" a and 0 alternately ending with a,
+    "ends" a on the first half and on the last stage run, 0 in between (the
+    shape of the Sec. 4.3 tuned schedule: small sizes, then one large)."""
     n = K - j
     if pattern == "all":
         return [a] * n
+    if pattern == "ends":
+        h = (n + 1) // 2
+        return [a if (i < h or i == n - 1) else 0 for i in range(n)]
     return [a if (n - 1 - i) % 2 == 0 else 0 for i in range(n)]
 
 
@@ -117,7 +126,7 @@ def run_variants(ctx, prob, tol=5e-7, seed=1, beta=None):
     spcg_solve(ctx, prob.X, prob.Y, **kw)  # workspaces sized, caches warm
     out = []
     for a, pat, j in VARIANTS:
-        if j >= K or (pat == "alt" and K - j < 2):
+        if j >= K or (pat != "all" and K - j < 3):
             continue
         al = a_list_of(K, a, pat, j)
         try:
@@ -143,7 +152,7 @@ def samples_from_runs(runs):
         return [], []
     c_min = min(r["cost"] for r in ok)
     near = [r for r in ok if r["cost"] <= COST_TOL * c_min]
-    best = max(near, key=lambda r: (r["j"], r["pattern"] == "all", r["a"]))
+    best = max(near, key=lambda r: (r["j"], PATTERN_ORDER[r["pattern"]], r["a"]))
     stage = []
     n = len(best["f_stage"])
     for i in range(n):
