@@ -112,11 +112,15 @@ typedef struct spcg_sketch_opts {
     int32_t transform_segment; /* tuning: 0 = library default (10- and 9-bit passes
                                   stream 128- or 256-byte row segments through LDS
                                   in persistent blocks; the 11-bit passes of
-                                  N' = 2^21 and 2^22 transforms stage half-tiles
-                                  of 2048 rows x 128 bytes); 64, 128 or 256
+                                  N' = 2^21 and 2^22 transforms work on tiles of
+                                  2048 rows x 128 bytes, the first pass staging
+                                  quarter tiles in a ring of two buffers, the last
+                                  half tiles); -32 or -64 stages quarter or half
+                                  tiles in both 11-bit passes; 64, 128 or 256
                                   selects one tile per block with at most that
-                                  many bytes per row segment.  Results are
-                                  bit-identical either way. */
+                                  many bytes per row segment.  Any other value is
+                                  SPCG_E_INVALID_ARG.  Results are bit-identical
+                                  either way. */
     int32_t kind;     /* SPCG_SKETCH_SRHT (0) or SPCG_SKETCH_COUNT (SPCG-CS, Sec. 4.3) */
     int32_t reserved; /* set to 0 */
     const int64_t* m_list; /* optional HOST array of the stage sizes m_1 < ... < m_K (replaces

@@ -484,8 +484,8 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     // the 11-bit half-tile-staged last pass also reads both output slots per
     // row in tile order (pair table after the round tables)
     const int seg = o ? o->transform_segment : 0;
-    if (seg != 0 && seg != 64 && seg != 128 && seg != 256 && seg != -64)
-        return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128 or 256");
+    if (seg != 0 && seg != 64 && seg != 128 && seg != 256 && seg != -64 && seg != -32)
+        return fail(ctx, SPCG_E_INVALID_ARG, "transform_segment must be 0, 64, 128, 256, -32 or -64");
     const int split = fwht_split_tables(X->dtype == SPCG_F64 ? DT_F64 : DT_F32, L, sk->ld, seg);
     const size_t tsz = (size_t)3 * Np + 3 * (size_t)feistel_table_size(L);
     const size_t tpad = (size_t)round_up((int64_t)(tsz * sizeof(int32_t)), 16);

@@ -432,10 +432,10 @@ __device__ __forceinline__ void stream_lds_load4(const void* src, void* lds) {
 }
 
 template <typename TI>
-struct StageRead;   // 4 consecutive staged elements of one row -> FP32
+struct StageRead;   // 4 consecutive staged elements of one row -> FP32; scales of columns >= d read as 0
 template <>
 struct StageRead<float> {
-    __device__ static void rd(const unsigned char* p, const float*, int64_t, float* o) {
+    __device__ static void rd(const unsigned char* p, const float*, int64_t, int64_t, float* o) {
         const float4 v = *reinterpret_cast<const float4*>(p);
         o[0] = v.x;
         o[1] = v.y;
@@ -445,7 +445,7 @@ struct StageRead<float> {
 };
 template <>
 struct StageRead<bf16_t> {
-    __device__ static void rd(const unsigned char* p, const float*, int64_t, float* o) {
+    __device__ static void rd(const unsigned char* p, const float*, int64_t, int64_t, float* o) {
         const uint2 v = *reinterpret_cast<const uint2*>(p);
         o[0] = __uint_as_float(v.x << 16);
         o[1] = __uint_as_float(v.x & 0xffff0000u);
@@ -455,14 +455,14 @@ struct StageRead<bf16_t> {
 };
 template <>
 struct StageRead<fp8_t> {
-    __device__ static void rd(const unsigned char* p, const float* sc, int64_t col, float* o) {
+    __device__ static void rd(const unsigned char* p, const float* sc, int64_t col, int64_t d, float* o) {
         const int w = (int)*reinterpret_cast<const uint32_t*>(p);
         const fwht_v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
         const fwht_v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
-        o[0] = lo.x * sc[col];
-        o[1] = lo.y * sc[col + 1];
-        o[2] = hi.x * sc[col + 2];
-        o[3] = hi.y * sc[col + 3];
+        o[0] = lo.x * (col < d ? sc[col] : 0.f);
+        o[1] = lo.y * (col + 1 < d ? sc[col + 1] : 0.f);
+        o[2] = hi.x * (col + 2 < d ? sc[col + 2] : 0.f);
+        o[3] = hi.y * (col + 3 < d ? sc[col + 3] : 0.f);
     }
 };
 
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
             const int row = tile_row(bx, 0, t);
             const int64_t col0 = tl.cbase + lr * VL;
             float x[VL];
-            StageRead<TI>::rd(stg + srow(row) * ROWB + lx * VL * IB, a.col_scale, col0, x);
+            StageRead<TI>::rd(stg + srow(row) * ROWB + lx * VL * IB, a.col_scale, col0, a.d, x);
             if constexpr (FIRST) {
                 const bool valid = (int64_t)(cp[t] & 0x7fffffff) < a.N;
 #pragma unroll
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             float x[VL];
-            StageRead<TI>::rd(stg + srow(base | t) * ROWB + (lx & 7) * VL * IB, a.col_scale, col0, x);
+            StageRead<TI>::rd(stg + srow(base | t) * ROWB + (lx & 7) * VL * IB, a.col_scale, col0, a.d, x);
             if constexpr (FIRST) {
                 const bool valid = (cm >> (16 + t)) & 1u;
                 const bool neg = (cm >> t) & 1u;
@@ -1067,6 +1067,410 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
     }
 }
 
+// The 11-bit pass of fwht_split_kernel with quarter-tile staging: two 64 KB
+// quarter buffers (FP32 rows) instead of one half-tile, so the loads of the
+// quarter two ahead are in flight while a quarter goes to the registers and
+// through stages 0..6, and no phase waits for the loads it has just issued
+// (same register layout, butterflies, exchange and stores; bit-identical).
+// Its waits are explicit vmcnt(NIQ) counts and its barriers wait for LDS
+// only, so the compiler adds no vmcnt(0): the quarter buffers are separate
+// LDS objects, table entries and column scales are loaded a phase ahead
+// before a quarter's direct loads, and the stores are global, not flat.
+template <typename TIN, bool FIRST, bool LAST, int DW>
+__global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
+    constexpr int CW = 32, VL = 4, R = 16, THREADS = SPLIT_THREADS;
+    constexpr int LPR = CW / VL;                 // 8 lanes per tile row
+    constexpr int NB = 11, HALF = 1 << (NB - 1), QR = HALF / 2;   // 512 rows per quarter
+    typedef typename std::conditional<FIRST, TIN, float>::type TI;   // staged element
+    constexpr int IB = (int)sizeof(TI);
+    constexpr int ROWB = CW * IB;                // staged bytes per tile row
+    constexpr int QS = QR * ROWB;                // one quarter-tile
+    constexpr int NIQ = QS / (THREADS * DW);     // direct loads of DW bytes per thread per quarter
+    constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;
+    static_assert(NIQ >= 1 && NIQ * THREADS * DW == QS && !(FIRST && LAST) && (DW == 16 || (FIRST && DW == 4)),
+                  "ring tile shape");
+    // s_waitcnt vmcnt(n): all but the last n vector-memory loads have completed
+    constexpr int VM_NIQ = (NIQ & 0xf) | (((NIQ >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8);
+    // two quarter buffers, separate LDS objects (the compiler's waits for
+    // the direct loads into one do not hold back reads of the other)
+    __shared__ __align__(16) unsigned char stg0[QS];
+    __shared__ __align__(16) unsigned char stg1[QS];
+    // s_waitcnt lgkmcnt(0) alone, then a bare barrier: the direct loads in
+    // flight are not waited for (a block barrier with its fence would add
+    // vmcnt(0))
+    constexpr int LGKM0 = 0xf | (3 << 14) | (0x7 << 4);
+    auto lds_barrier = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(LGKM0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    };
+    __shared__ __align__(16) float exb[HALF * LPR];
+
+    const int64_t T = a.ntiles;
+    const int64_t G = gridDim.x;
+    int64_t first, stride, count;
+    if ((G & 7) == 0 && (T & 7) == 0) {
+        const int64_t per = T >> 3, M = G >> 3, m = blockIdx.x >> 3;
+        first = (int64_t)(blockIdx.x & 7) * per + m;
+        stride = M;
+        count = m < per ? (per - m + M - 1) / M : 0;
+    } else {
+        first = blockIdx.x;
+        stride = G;
+        count = (int64_t)blockIdx.x < T ? (T - blockIdx.x + G - 1) / G : 0;
+    }
+    if (count == 0) return;   // uniform over the block
+
+    const int lo = a.lo;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int myq = wave >> 2;   // the quarter whose rows this wave holds
+    auto srow = [](int row) -> int { return row ^ ((row >> 4) & SM); };
+    struct Tile {
+        int64_t rowbase;
+        int64_t cbase;
+    };
+    // tile index = o * nchunks + cc, walked incrementally (uniform scalars)
+    auto tile_at = [&](int64_t o, int64_t cc) -> Tile {
+        const int64_t olo = o & ((1ll << lo) - 1);
+        const int64_t ohi = o >> lo;
+        return Tile{(ohi << (lo + NB)) | olo, cc * CW};
+    };
+    const int64_t nch = a.nchunks;
+    int64_t o_cur = first / nch, c_cur = first - (first / nch) * nch;
+    auto advance = [&](int64_t& o, int64_t& c) {
+        c += stride;
+        while (c >= nch) {
+            c -= nch;
+            ++o;
+        }
+    };
+    auto grow = [&](const Tile& tl, int r) -> int64_t { return tl.rowbase | ((int64_t)r << lo); };
+    auto zoff = [&](int64_t k, int64_t col) -> int64_t {
+        if (a.zt_hibits == 0) return k * a.ldz + col;
+        const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
+        return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
+    };
+    // tile row of register t at load (stage bits 0..3 in registers); lx is
+    // an opaque copy of the lane index (see the loop)
+    auto load_row = [&](int t, int lx) -> int { return t | ((lx >> 3) << 4) | (wave << 7); };
+    // tile row of register t after the exchange (stage bits 7..10 in registers)
+    auto final_row = [&](int t, int lx) -> int {
+        return (wave & 1) | ((wave >> 1) & 1) << 1 | (lx >> 5) << 2 | ((lx >> 4) & 1) << 3 | ((lx >> 3) & 1) << 4 |
+               ((wave >> 2) & 1) << 5 | ((wave >> 3) & 1) << 6 | t << 7;
+    };
+    // quarter row and DW-byte piece that direct load i of this lane fetches
+    auto dma_slot = [&](int i, int lx, int& row, int& piece) {
+        const int P = ((wave * NIQ + i) * 64 + lx) * DW;
+        row = srow(P / ROWB);
+        piece = (P % ROWB) / DW;
+    };
+    // first pass: the direct loads of wave w fetch the quarter rows
+    // [32 w, 32 w + 32); lane l < 32 loads the permutation entry of row
+    // 32 w + l and each load's row entry comes from its lane by a cross-lane
+    // permute
+    auto load_dperm = [&](const Tile& tl, int q, int lx) __attribute__((always_inline)) -> int32_t {
+        return a.perm_sign[(uint32_t)grow(tl, q * QR + wave * 32 + (lx & 31))];
+    };
+    // first pass: sign (bit t) and validity (bit 16 + t) of this thread's 16
+    // consecutive rows, one word of the row-mask table
+    auto load_cmask = [&](const Tile& tl, int lx) __attribute__((always_inline)) -> uint32_t {
+        return a.row_masks[(uint32_t)grow(tl, load_row(0, lx)) >> 4];
+    };
+    auto issue_quarter = [&](const Tile& tl, int q, unsigned char* qbuf, int32_t dp, int lx)
+                             __attribute__((always_inline)) {
+        unsigned char* dst = qbuf + wave * NIQ * 64 * DW;
+#pragma unroll
+        for (int i = 0; i < NIQ; ++i) {
+            int row, piece;
+            dma_slot(i, lx, row, piece);
+            const int64_t col = tl.cbase + piece * (DW / IB);
+            const unsigned char* src;
+            if constexpr (FIRST) {
+                // rows past N and pieces past d read row 0; the reader zeroes them
+                const int32_t pe = __builtin_amdgcn_ds_bpermute((row - wave * 32) << 2, dp);
+                const int64_t sr = (int64_t)(pe & 0x7fffffff);
+                const bool ok = sr < a.N && col < a.d;
+                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+            } else {
+                src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, q * QR + row), col) * 4;
+            }
+            if constexpr (DW == 16) stream_lds_load16(src, dst + i * 1024);
+            else stream_lds_load4(src, dst + i * 256);
+        }
+    };
+
+    float v[R][VL];
+    // first pass over FP8: the column scales of this lane's 4 columns, per
+    // tile in registers (loaded a tile ahead, before a quarter's direct
+    // loads, so the waits that cover those cover them)
+    constexpr bool SCALED = FIRST && std::is_same<TIN, fp8_t>::value;
+    float scl[VL], scn[VL];
+#pragma unroll
+    for (int e = 0; e < VL; ++e) scl[e] = scn[e] = 0.f;
+    auto load_scale = [&](const Tile& tl, int lx, float* o) __attribute__((always_inline)) {
+        const int64_t c = tl.cbase + (lx & 7) * VL;
+#pragma unroll
+        for (int e = 0; e < VL; ++e) o[e] = c + e < a.d ? a.col_scale[c + e] : 0.f;
+    };
+    // this thread's rows of its quarter from quarter buffer qb
+    auto read_own = [&](const Tile& tl, const unsigned char* qb, uint32_t cm, int lx) __attribute__((always_inline)) {
+        const int64_t col0 = tl.cbase + (lx & 7) * VL;
+        const int base = (((wave & 3) << 3) | (lx >> 3)) << 4;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            float x[VL];
+            StageRead<TI>::rd(qb + srow(base | t) * ROWB + (lx & 7) * VL * IB, scl, 0, VL, x);
+            if constexpr (FIRST) {
+                const bool valid = (cm >> (16 + t)) & 1u;
+                const bool neg = (cm >> t) & 1u;
+#pragma unroll
+                for (int e = 0; e < VL; ++e) {
+                    float y = col0 + e < a.d ? x[e] : 0.f;
+                    if (neg) y = -y;
+                    v[t][e] = valid ? y : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VL; ++e) v[t][e] = x[e];
+            }
+        }
+    };
+    // stages on register bits [b0, b1), ascending
+    auto bfly = [&](int b0, int b1) __attribute__((always_inline)) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b >= b0 && b < b1) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    if (!(t & (1 << b))) {
+#pragma unroll
+                        for (int e = 0; e < VL; ++e) {
+                            const float x0 = v[t][e], x1 = v[t | (1 << b)][e];
+                            v[t][e] = x0 + x1;
+                            v[t | (1 << b)][e] = x0 - x1;
+                        }
+                    }
+                }
+            }
+        }
+    };
+    // stages 4..6 on the lane bits (see above)
+    auto lane_stages = [&](int lx) __attribute__((always_inline)) {
+        const float sg = (lx & 8) ? -1.f : 1.f;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const float p = __int_as_float(
+                    __builtin_amdgcn_update_dpp(0, __float_as_int(v[t][e]), 0x128, 0xf, 0xf, false));
+                v[t][e] = __builtin_fmaf(sg, v[t][e], p);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const auto w = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[t][e]),
+                                                                __float_as_uint(v[t + 8][e]), false, false);
+                const float xn = __uint_as_float(w[0]), yn = __uint_as_float(w[1]);
+                v[t][e] = xn + yn;
+                v[t + 8][e] = xn - yn;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            if (t & 4) continue;
+#pragma unroll
+            for (int e = 0; e < VL; ++e) {
+                const auto w = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[t][e]),
+                                                                __float_as_uint(v[t + 4][e]), false, false);
+                const float xn = __uint_as_float(w[0]), yn = __uint_as_float(w[1]);
+                v[t][e] = xn + yn;
+                v[t + 4][e] = xn - yn;
+            }
+        }
+    };
+    // row bits 7..10 into the registers: per column element, two rounds by
+    // row bit 2 (lane bit 5 before and after); exchange index of a row:
+    // r3 | r4 << 1 | r0 << 2 | r1 << 3 | r5 << 4 | r6 << 5 | r7..r10 << 6
+    auto exchange = [&](int lx) __attribute__((always_inline)) {
+        const int lrx = lx & 7, x3 = (lx >> 3) & 1, x4 = (lx >> 4) & 1, x5 = lx >> 5;
+        const int wbase = ((x4 | x3 << 1 | wave << 6) << 3) + lrx;
+        const int rbase = ((x4 | x3 << 1 | wave << 2) << 3) + lrx;
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+#pragma unroll
+            for (int rho = 0; rho < 2; ++rho) {
+                const bool active = x5 == rho;
+                if (active) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        const int off = ((t & 1) << 2 | ((t >> 1) & 1) << 3 | ((t >> 3) & 1) << 4 | ((t >> 2) & 1) << 5) << 3;
+                        exb[wbase + off] = v[t][e];
+                    }
+                }
+                lds_barrier();
+                if (active) {
+#pragma unroll
+                    for (int t = 0; t < R; ++t) v[t][e] = exb[rbase + (t << 9)];
+                }
+                lds_barrier();
+            }
+        }
+    };
+
+    // completes every pending butterfly before this point (the scheduler
+    // would otherwise sink the last stages into the store loop and keep
+    // their partial sums live)
+    auto settle = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < VL; ++e)
+            asm volatile("" : "+v"(v[0][e]), "+v"(v[1][e]), "+v"(v[2][e]), "+v"(v[3][e]), "+v"(v[4][e]),
+                         "+v"(v[5][e]), "+v"(v[6][e]), "+v"(v[7][e]), "+v"(v[8][e]), "+v"(v[9][e]),
+                         "+v"(v[10][e]), "+v"(v[11][e]), "+v"(v[12][e]), "+v"(v[13][e]), "+v"(v[14][e]),
+                         "+v"(v[15][e]));
+    };
+
+    int32_t dpn = 0;     // first pass: this lane's entry for the quarter issued next
+    uint32_t cm = 0;     // first pass: sign and validity of this thread's rows
+    uint32_t cmn = 0;    // first pass: the same for the next tile
+    {
+        const Tile t0 = tile_at(o_cur, c_cur);
+        if constexpr (FIRST) {
+            dpn = load_dperm(t0, 0, lane);
+            cm = load_cmask(t0, lane);
+            if constexpr (SCALED) load_scale(t0, lane, scl);
+            __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        }
+        issue_quarter(t0, 0, stg0, dpn, lane);
+        int32_t dp1 = 0;
+        if constexpr (FIRST) {
+            dp1 = load_dperm(t0, 1, lane);
+            __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+            // before the direct loads, so that the wait below covers it
+            dpn = load_dperm(t0, 2, lane);
+        }
+        issue_quarter(t0, 1, stg1, dp1, lane);
+    }
+    __builtin_amdgcn_s_waitcnt(VM_NIQ);   // quarter 0 has landed
+
+    for (int64_t j = 0; j < count; ++j) {
+        const Tile tl = tile_at(o_cur, c_cur);
+        int64_t o_nx = o_cur, c_nx = c_cur;
+        advance(o_nx, c_nx);
+        const Tile tn = tile_at(o_nx, c_nx);
+        const bool has_next = j + 1 < count;
+        if constexpr (FIRST) cm = j > 0 ? cmn : cm;
+        if constexpr (SCALED) {
+            if (j > 0) {
+#pragma unroll
+                for (int e = 0; e < VL; ++e) scl[e] = scn[e];
+            }
+        }
+        // an opaque copy of the lane index, renewed per phase: lane-dependent
+        // addresses are recomputed where they are used instead of being
+        // hoisted out of the loop into registers
+        int lx = lane;
+        // phases 0..3: quarter q (landed and, after the first barrier,
+        // visible) goes to the registers of waves 4q..4q+3; once its buffer
+        // is free, the quarter two ahead is issued into it (quarters 2, 3 of
+        // this tile, then 0, 1 of the next); waves 4q..4q+3 run stages 0..6;
+        // one wait then covers quarter q + 1 and leaves the new loads in
+        // flight.  Per phase the loads go in the order: table entries for
+        // the next phase, then the quarter's direct loads, so vmcnt(NIQ)
+        // covers everything but those.  Every phase issues a quarter: on a
+        // block's last tile, phases 2 and 3 reload quarters of this tile
+        // (in bounds, never read), which keeps every wait the same
+        // unconditional vmcnt(NIQ).
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned char* const qbuf = (q & 1) ? stg1 : stg0;
+            lds_barrier();   // quarter q is complete in every wave
+            asm volatile("" : "+v"(lx));
+            if (myq == q) read_own(tl, qbuf, cm, lx);
+            lds_barrier();   // buffer q & 1 is free
+            asm volatile("" : "+v"(lx));
+            const int32_t dpi = dpn;
+            if constexpr (FIRST) {
+                // the quarter issued in the next phase: (q + 3) & 3 of this
+                // tile (q = 0) or of the next
+                if (q == 0) dpn = load_dperm(tl, 3, lx);
+                else if (has_next) dpn = load_dperm(tn, (q + 3) & 3, lx);
+                if (q == 3 && has_next) {
+                    cmn = load_cmask(tn, lx);
+                    if constexpr (SCALED) load_scale(tn, lx, scn);
+                }
+            }
+            issue_quarter(q < 2 || !has_next ? tl : tn, (q + 2) & 3, qbuf, dpi, lx);
+            if (myq == q) {
+                bfly(0, 4);
+                asm volatile("" : "+v"(lx));
+                lane_stages(lx);
+            }
+            if (q < 3) __builtin_amdgcn_s_waitcnt(VM_NIQ);   // quarter q + 1 has landed
+        }
+        // ---- C: stages 7..10 and the stores
+        asm volatile("" : "+v"(lx));
+        exchange(lx);
+        if constexpr (LAST) {
+            // the output slots of this tile's rows (contiguous in slot_pairs)
+            // into the free exchange buffer
+            asm volatile("" : "+v"(lx));
+            const int2* src = a.slot_pairs + ((tl.rowbase & ((1ll << lo) - 1)) << NB) + (wave * 64 + lx) * 2;
+            stream_lds_load16(src, reinterpret_cast<unsigned char*>(exb) + wave * 1024);
+        }
+        bfly(0, 4);
+        settle();
+        // the next tile's quarter 0 (and, last pass, the slot pairs: then
+        // everything) has landed; quarter 1 stays in flight, and the stores
+        // below drain during the next tile
+        if constexpr (LAST) __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+        else __builtin_amdgcn_s_waitcnt(VM_NIQ);
+        if constexpr (LAST) lds_barrier();   // the slot pairs are visible
+        // one row at a time: the opaque lane copy keeps the compiler from
+        // computing all sixteen 64-bit store addresses up front
+        if constexpr (LAST) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                asm volatile("" : "+v"(lx));
+                const int2 pr = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+                const int64_t col0 = tl.cbase + (lx & 7) * VL;
+                if (pr.x >= 0) {
+                    if (a.b_bf16) {
+                        bf16_store4(static_cast<uint16_t*>(a.B) + (int64_t)pr.x * a.ldb + col0, v[t]);
+                    } else {
+                        ZVec<float>::st(static_cast<float*>(a.B) + (int64_t)pr.x * a.ldb + col0, v[t]);
+                    }
+                }
+                if (pr.y >= 0) ZVec<float>::st(static_cast<float*>(a.Bh) + (int64_t)pr.y * a.ldbh + col0, v[t]);
+            }
+        } else {
+            // Z offsets are linear in the register index (row step 128)
+            asm volatile("" : "+v"(lx));
+            const int64_t col0 = tl.cbase + (lx & 7) * VL;
+            const int64_t z0 = zoff(grow(tl, final_row(0, lx)), col0);
+            const int64_t zs = zoff(grow(tl, final_row(1, lx)), col0) - z0;
+            // global (not flat) stores: a flat store may address LDS, and
+            // the compiler would wait for the direct loads in flight first
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            typedef __attribute__((address_space(1))) f4v gf4v;
+            gf4v* p = reinterpret_cast<gf4v*>(reinterpret_cast<uintptr_t>(static_cast<float*>(a.zout) + z0));
+            const int64_t zs4 = zs / VL;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                *p = f4v{v[t][0], v[t][1], v[t][2], v[t][3]};
+                p += zs4;
+                asm volatile("" : "+v"(p));
+            }
+        }
+        o_cur = o_nx;
+        c_cur = c_nx;
+    }
+    // the reloads of the last tile land before the block's LDS is released
+    __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
+}
+
 // Threads per block and register window for a pass of nb bits.
 template <typename TZ, int CW>
 inline int pass_q(int nb) {
@@ -1140,6 +1544,23 @@ hipError_t launch_split(hipStream_t st, const PassArgs& a, int64_t grid, bool fi
     return hipGetLastError();
 }
 
+template <typename TIN>
+hipError_t launch_ring(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
+    const dim3 g((unsigned)grid), b(SPLIT_THREADS);
+    if (first && last) return hipErrorInvalidValue;
+    if (first && dw4) {
+        if constexpr (std::is_same<TIN, fp8_t>::value) fwht_ring_kernel<TIN, true, false, 4><<<g, b, 0, st>>>(a);
+        else return hipErrorInvalidValue;
+    } else if (first) {
+        fwht_ring_kernel<TIN, true, false, 16><<<g, b, 0, st>>>(a);
+    } else if (last) {
+        fwht_ring_kernel<TIN, false, true, 16><<<g, b, 0, st>>>(a);
+    } else {
+        fwht_ring_kernel<TIN, false, false, 16><<<g, b, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
 template <typename TIN, int CW>
 hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last) {
     if (first && last) return hipErrorInvalidValue;
@@ -1189,9 +1610,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     auto stream_cw = [&](int nb, bool first) -> int {
         if (!std::is_same<TZ, float>::value) return 0;
         // 1024 x 128 B or 512 x 256 B tiles (128 KB each); 256 x 512 B tiles
-        // for 8 bits would spill registers in the first pass.  seg_bytes = -64
-        // also streams 11-bit passes in 2048 x 64 B tiles.
-        const int scw = nb == 10 ? 32 : nb == 9 ? 64 : (nb == 11 && job.seg_bytes == -64) ? 16 : 0;
+        // for 8 bits would spill registers in the first pass
+        const int scw = nb == 10 ? 32 : nb == 9 ? 64 : 0;
         if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes > 0 || job.ldz % scw != 0 ||
             (first && !xdma))
             return 0;
@@ -1229,7 +1649,10 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             if (e != hipSuccess) return e;
         }
         if constexpr (std::is_same<TZ, float>::value) {
-            // 11-bit passes with half-tile staging (128-byte row segments)
+            // 11-bit passes of 128-byte row segments: the first stages
+            // quarter tiles in a ring, the last half tiles (measured the
+            // faster pair at N' = 2^22); seg_bytes -32 / -64 select quarter /
+            // half tiles for both
             if (nb == NB_MAX && job.stream && job.num_cu > 0 &&
                 (first ? (split & 1) && (xdma || xdma4) && job.row_masks : (split & 2) && job.slot_pairs)) {
                 a.lo = lo;
@@ -1240,7 +1663,9 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = launch_split<TIN>(st, a, grid, first, last, first && !xdma);
+                const bool ring = job.seg_bytes == -32 || (job.seg_bytes == 0 && first);
+                const hipError_t e = ring ? launch_ring<TIN>(st, a, grid, first, last, first && !xdma)
+                                          : launch_split<TIN>(st, a, grid, first, last, first && !xdma);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);
@@ -1259,9 +1684,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = scw == 32   ? launch_stream<TIN, 32>(st, a, grid, first, last)
-                                     : scw == 64 ? launch_stream<TIN, 64>(st, a, grid, first, last)
-                                                 : launch_stream<TIN, 16>(st, a, grid, first, last);
+                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
+                                               : launch_stream<TIN, 64>(st, a, grid, first, last);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);
@@ -1369,7 +1793,7 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
 int fwht_passes(int L) { return (L + NB_MAX - 1) / NB_MAX; }
 
 int fwht_split_tables(int in_dtype, int L, int64_t ldz, int seg_bytes) {
-    if (in_dtype == DT_F64 || ldz % 32 != 0 || seg_bytes != 0) return 0;
+    if (in_dtype == DT_F64 || ldz % 32 != 0 || seg_bytes > 0) return 0;
     if (L == 2 * NB_MAX) return 3;
     if (L == 2 * NB_MAX - 1) return 1;
     return 0;

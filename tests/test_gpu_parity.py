@@ -226,18 +226,20 @@ def test_sketch_split_eleven_bit_passes_match_tiled(S, ctx, storage, N, d):
     # (11 + 11 bits, both passes; d = 37: rows of X are not 16-byte aligned,
     # so only the last pass) and N' = 2^21 (the 11-bit first pass, then a
     # streamed 10-bit pass).  FP8 rows of 44 bytes are staged with 4-byte
-    # direct loads.  transform_segment = 256 runs one tile per block.  Same
-    # butterflies in the same order -> identical bits.
+    # direct loads.  transform_segment = 256 runs one tile per block, -32
+    # and -64 quarter- and half-tile staging in both passes (the default
+    # mixes them).  Same butterflies in the same order -> identical bits.
     _log(f"sketch split 11-bit {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 79)
     rows = []
-    for seg in (0, 256):
+    for seg in (0, 256, -32, -64):
         sk = S.spcg_sketch(ctx, p.X, p.Y, seed=7, col_scale=p.col_scale, transform_segment=seg)
         rows.append((_raw_rows(sk, len(sk.sizes) - 1), _raw_rows(sk, -1), sk.info.L))
         del sk
     assert rows[0][2] == (N - 1).bit_length()
-    assert np.array_equal(rows[0][0], rows[1][0])
-    assert np.array_equal(rows[0][1], rows[1][1])
+    for r in rows[1:]:
+        assert np.array_equal(rows[0][0], r[0])
+        assert np.array_equal(rows[0][1], r[1])
 
 
 def test_sketch_streaming_transform_against_oracle(S, ctx):
