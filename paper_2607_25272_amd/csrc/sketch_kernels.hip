@@ -1402,7 +1402,9 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
                     if constexpr (SCALED) load_scale(tn, lx, scn);
                 }
             }
-            issue_quarter(q < 2 || !has_next ? tl : tn, (q + 2) & 3, qbuf, dpi, lx);
+            // (the last pass issues quarter 1 of the next tile in phase C,
+            // after the slot pairs)
+            if (!(LAST && q == 3)) issue_quarter(q < 2 || !has_next ? tl : tn, (q + 2) & 3, qbuf, dpi, lx);
             if (myq == q) {
                 bfly(0, 4);
                 asm volatile("" : "+v"(lx));
@@ -1415,18 +1417,21 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
         exchange(lx);
         if constexpr (LAST) {
             // the output slots of this tile's rows (contiguous in slot_pairs)
-            // into the free exchange buffer
+            // into the free exchange buffer, then quarter 1 of the next tile
+            // into its free buffer, so that one vmcnt(NIQ) below covers the
+            // slot pairs and leaves that quarter in flight
             asm volatile("" : "+v"(lx));
             const int2* src = a.slot_pairs + ((tl.rowbase & ((1ll << lo) - 1)) << NB) + (wave * 64 + lx) * 2;
             stream_lds_load16(src, reinterpret_cast<unsigned char*>(exb) + wave * 1024);
+            asm volatile("" : "+v"(lx));
+            issue_quarter(has_next ? tn : tl, 1, stg1, 0, lx);
         }
         bfly(0, 4);
         settle();
-        // the next tile's quarter 0 (and, last pass, the slot pairs: then
-        // everything) has landed; quarter 1 stays in flight, and the stores
-        // below drain during the next tile
-        if constexpr (LAST) __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
-        else __builtin_amdgcn_s_waitcnt(VM_NIQ);
+        // the next tile's quarter 0 (and, last pass, the slot pairs) has
+        // landed; quarter 1 stays in flight, and the stores below drain
+        // during the next tile
+        __builtin_amdgcn_s_waitcnt(VM_NIQ);
         if constexpr (LAST) lds_barrier();   // the slot pairs are visible
         // one row at a time: the opaque lane copy keeps the compiler from
         // computing all sixteen 64-bit store addresses up front
