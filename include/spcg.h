@@ -318,6 +318,21 @@ typedef struct spcg_solve_opts {
                                  planned stages (after stage_stride), Stage II next;
                                  0: all.  A zero entry of a_list runs the stage's
                                  start (its gradient) and no PCG iteration. */
+    int32_t batch_shape;      /* batched form: tile shape of the product launches.
+                                 0 (default) autotunes it once per context and storage
+                                 type for every launch bucket (row-width class x
+                                 k <= 8 / k > 8), timing one product pass of the bucket
+                                 in each shape (results are discarded); 1: three
+                                 barriers per 16-row tile, 3 LDS slots; 2: two tiles
+                                 software-pipelined (the W reduction of one beside the
+                                 first GEMM of the next), 3 slots; 3: as 2 with 4 slots
+                                 (rows of at most 1 KB; wider rows use 2).  Results are
+                                 bit-identical in every shape. */
+    int32_t batch_one_launch; /* batched form: 1 runs every task of a pass in one launch
+                                 of the widest row-width class (a comparison point for
+                                 the per-bucket launches).  The tasks are then split
+                                 over one launch instead of one per bucket, so the
+                                 partial sums round differently. */
 } spcg_solve_opts;
 
 /* a_i rules.  THEORY takes the stage iteration counts from Theorems 3.3
@@ -389,6 +404,11 @@ typedef struct spcg_solve_stats {
     int32_t stage_iters[64];
     float stage_features[16 * 8];
     float stage_out[16 * 8];
+    int32_t batch_shapes[16];   /* batched form: tile shape of each launch bucket
+                                   (class * 2 + (k > 8)) in Stage II, 0 if unused */
+    float batch_tune_ms[16 * 4];/* batched form, the solve that autotuned the shapes:
+                                   one SG product pass of bucket b alone in shape s
+                                   at [b * 4 + s - 1], in ms (0: not timed) */
 } spcg_solve_stats;
 
 /* Kernel classes of spcg_solve_stats.kernel_*.  Algorithmic bytes count

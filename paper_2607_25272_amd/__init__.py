@@ -261,7 +261,7 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
                stage_stride=1, schedule="plain", weights=None, schedule_margin=0,
                record_features=False, stage_dtype=0, transform_segment=0, sketch="srht",
                batch_direct=False, batch_tasks_per_cu=0, m_list=None, a_rule="fixed", omega=0.0,
-               nested_gradient=True, stage_limit=0):
+               nested_gradient=True, stage_limit=0, batch_shape=0, batch_one_launch=False):
     """spcg_solve_opts from keyword arguments (``sketch``: "srht" or "cs",
     the CountSketch of SPCG-CS).  schedule='learned' needs
     ``weights``: a float32 device tensor of SPCG_MLP_PARAMS entries (see
@@ -275,6 +275,8 @@ def solve_opts(method="spcg", seed=1, a=3, T=100, tol=5e-7, m0=0, m_max=0, r=0, 
     o.sketch.kind = _sketch_kind(sketch)
     o.batch_direct = int(batch_direct)
     o.batch_tasks_per_cu = batch_tasks_per_cu
+    o.batch_shape = batch_shape
+    o.batch_one_launch = int(batch_one_launch)
     sizes, n_sizes = _sizes(m_list)
     if sizes is not None:
         o.sketch.m_list = ctypes.cast(sizes, ctypes.POINTER(ctypes.c_int64))

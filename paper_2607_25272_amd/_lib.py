@@ -77,7 +77,8 @@ class SolveOpts(ctypes.Structure):
                 ("time_phases", c_i32), ("time_products", c_i32), ("stage_stride", c_i32),
                 ("schedule", c_i32), ("schedule_weights", c_vp), ("schedule_margin", c_i32),
                 ("record_features", c_i32), ("batch_direct", c_i32), ("batch_tasks_per_cu", c_i32),
-                ("a_rule", c_i32), ("nested_gradient", c_i32), ("omega", c_f64), ("stage_limit", c_i32)]
+                ("a_rule", c_i32), ("nested_gradient", c_i32), ("omega", c_f64), ("stage_limit", c_i32),
+                ("batch_shape", c_i32), ("batch_one_launch", c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -93,7 +94,8 @@ class SolveStats(ctypes.Structure):
                 ("out_ii", ctypes.c_float * 8), ("batch_tasks_per_cu", c_i32), ("batch_graphs", c_i32),
                 ("kernel_ms", c_f64 * 8), ("kernel_bytes", c_f64 * 8), ("kernel_launches", c_i32 * 8),
                 ("stages_planned", c_i32), ("stage_iters", c_i32 * 64), ("stage_features", ctypes.c_float * 128),
-                ("stage_out", ctypes.c_float * 128)]
+                ("stage_out", ctypes.c_float * 128), ("batch_shapes", c_i32 * 16),
+                ("batch_tune_ms", ctypes.c_float * 64)]
 
 
 P = ctypes.POINTER

@@ -1092,12 +1092,15 @@ struct BatchWork {
     std::vector<spcg_sketch_t*> sk;
     std::vector<spcg_precond_t*> pc;
     DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal, bestx;
-    // one stream per row-width class (the class launches of a pass run
-    // concurrently), a private stream for graph capture, fork/join events
-    hipStream_t cls[MR_NCLASS] = {};
+    DevBuf rpart;   // per problem: the z slices' shares of g^T z
+    // one stream per launch bucket (row-width class x k range: the bucket
+    // launches of a pass run concurrently), a private stream for graph
+    // capture, fork/join events
+    hipStream_t cls[MR_NBUCKET] = {};
     hipStream_t cap = nullptr;
-    hipEvent_t fork = nullptr, join[MR_NCLASS] = {}, tune[2] = {};
+    hipEvent_t fork = nullptr, join[MR_NBUCKET] = {}, tune[2] = {};
     int tasks_per_cu[4] = {};   // autotuned task granularity per storage type (0: not yet)
+    int shape[4][MR_NBUCKET] = {};   // autotuned tile shape per storage type and bucket (0: not yet)
     // per-problem setup (sketch, preconditioner) is spread over NLANE lanes,
     // each a context of its own (stream and workspaces), so the small
     // transforms and the latency-bound factor chains of different problems
@@ -1184,29 +1187,38 @@ int batch_streams(spcg_ctx* ctx, BatchWork& W) {
 
 constexpr int MR_VECS = 6;   // X G Z P S Gt
 
-// Tasks grouped by row-width class (one product launch per class); the
-// tasks of a problem are contiguous, [t0, t1).  Returns the task count or a
-// negative class error.
+// Tasks grouped by launch bucket (row-width class x k range, one product
+// launch per bucket); the tasks of a problem are contiguous, [t0, t1).
+// one_launch puts every problem into the widest class that can read it
+// (one launch per pass).  Returns the task count or a negative class error.
 int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsTask>& tasks,
-                std::vector<MrhsProblem>& out, int64_t target_tasks, int* seg) {
+                std::vector<MrhsProblem>& out, int64_t target_tasks, int* seg, bool one_launch) {
     tasks.clear();
     out = hp;
-    std::vector<int> cls(hp.size(), -1);
-    int64_t class_rows[MR_NCLASS] = {};
+    std::vector<int> bkt(hp.size(), -1);
+    int64_t bucket_rows[MR_NBUCKET] = {};
     for (size_t p = 0; p < hp.size(); ++p) {
         out[p].t0 = out[p].t1 = 0;
         if (!hp[p].active) continue;
-        cls[p] = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
-        if (cls[p] < 0) return -1;
-        class_rows[cls[p]] += hp[p].m;
+        int c = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
+        if (c < 0) return -1;
+        if (one_launch) {
+            // the 4-byte, 8-load class reads every row of a 4-byte multiple
+            // stride (and at most 2 KB of data)
+            const int es = dtype == DT_F32 ? 4 : 2;
+            const bool w4 = (hp[p].lda * es) % 4 == 0 && (uintptr_t)hp[p].A % 4 == 0;
+            c = w4 ? MR_CLASS_4x8 : MR_CLASS_GENERIC;
+        }
+        bkt[p] = one_launch ? mrhs_bucket(c, 0) : mrhs_bucket(c, hp[p].k);
+        bucket_rows[bkt[p]] += hp[p].m;
     }
-    for (int c = 0; c < MR_NCLASS; ++c) {
+    for (int c = 0; c < MR_NBUCKET; ++c) {
         seg[c] = (int)tasks.size();
-        // each class is its own launch: split its rows into about
+        // each bucket is its own launch: split its rows into about
         // target_tasks tasks so that every launch fills the device
-        const int64_t rows_per_task = std::max<int64_t>(256, round_up(ceil_div(class_rows[c], target_tasks), 16));
+        const int64_t rows_per_task = std::max<int64_t>(256, round_up(ceil_div(bucket_rows[c], target_tasks), 16));
         for (size_t p = 0; p < hp.size(); ++p) {
-            if (cls[p] != c) continue;
+            if (bkt[p] != c) continue;
             out[p].t0 = (int)tasks.size();
             for (int64_t r = 0; r < hp[p].m; r += rows_per_task) {
                 MrhsTask t{};
@@ -1218,7 +1230,7 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
             out[p].t1 = (int)tasks.size();
         }
     }
-    seg[MR_NCLASS] = (int)tasks.size();
+    seg[MR_NBUCKET] = (int)tasks.size();
     return (int)tasks.size();
 }
 
@@ -1228,8 +1240,19 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
 struct BatchPlan {
     int nt = 0;
     int nprob = 0;
-    int seg[MR_NCLASS + 1] = {};
+    int seg[MR_NBUCKET + 1] = {};
+    int shape[MR_NBUCKET] = {};   // tile shape of each bucket's launch
+    bool one_launch = false;
 };
+
+// tile shape of every bucket: forced (> 0), else the context's tuned one,
+// else the two-tile pipeline with 3 slots
+void plan_shapes(const BatchWork& W, int dtype, int forced, BatchPlan& plan) {
+    for (int b = 0; b < MR_NBUCKET; ++b) {
+        const int tuned = W.shape[dtype & 3][b];
+        plan.shape[b] = forced > 0 ? forced : tuned > 0 ? tuned : MR_SHAPE_PIPE3;
+    }
+}
 
 int batched_setup(spcg_ctx* ctx, BatchWork& W, int dtype, const std::vector<MrhsProblem>& hp, int64_t target_tasks,
                   BatchPlan& plan) {
@@ -1237,7 +1260,7 @@ int batched_setup(spcg_ctx* ctx, BatchWork& W, int dtype, const std::vector<Mrhs
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<MrhsTask> tasks;
     std::vector<MrhsProblem> probs;
-    const int nt = build_tasks(dtype, hp, tasks, probs, target_tasks, plan.seg);
+    const int nt = build_tasks(dtype, hp, tasks, probs, target_tasks, plan.seg, plan.one_launch);
     if (nt < 0) return fail(ctx, SPCG_E_SHAPE, "a batched matrix has an unsupported row layout");
     plan.nt = nt;
     plan.nprob = (int)probs.size();
@@ -1255,23 +1278,26 @@ int batched_setup(spcg_ctx* ctx, BatchWork& W, int dtype, const std::vector<Mrhs
     return SPCG_OK;
 }
 
-// The product launches of one pass on stream st: each row-width class on
-// its own stream (the classes write disjoint task partials), joined back
-// into st.  Launches only: safe to capture.
-int batched_products(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int dtype, int mode, const BatchPlan& plan) {
+// The product launches of one pass on stream st: each bucket (row-width
+// class x k range) on its own stream (the buckets write disjoint task
+// partials), joined back into st; only_bucket >= 0 launches that bucket
+// alone.  Launches only: safe to capture.
+int batched_products(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int dtype, int mode, const BatchPlan& plan,
+                     int only_bucket = -1) {
     int used = 0;
-    for (int c = 0; c < MR_NCLASS; ++c) used += plan.seg[c + 1] > plan.seg[c];
+    for (int c = 0; c < MR_NBUCKET; ++c)
+        used += plan.seg[c + 1] > plan.seg[c] && (only_bucket < 0 || c == only_bucket);
     if (used > 1) HIP_TRY(ctx, hipEventRecord(W.fork, st));
-    for (int c = 0; c < MR_NCLASS; ++c) {
+    for (int c = 0; c < MR_NBUCKET; ++c) {
         const int n = plan.seg[c + 1] - plan.seg[c];
-        if (n <= 0) continue;
+        if (n <= 0 || (only_bucket >= 0 && c != only_bucket)) continue;
         hipStream_t sc = st;
         if (used > 1) {
             sc = W.cls[c];
             HIP_TRY(ctx, hipStreamWaitEvent(sc, W.fork, 0));
         }
-        HIP_TRY(ctx, run_mrhs_product(sc, dtype, mode, c, W.tasks.as<MrhsTask>(), plan.seg[c], n,
-                                      W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
+        HIP_TRY(ctx, run_mrhs_product(sc, dtype, mode, c / MR_KB, plan.shape[c], W.tasks.as<MrhsTask>(), plan.seg[c],
+                                      n, W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
                                       W.part_scal.as<float>()));
         if (used > 1) {
             HIP_TRY(ctx, hipEventRecord(W.join[c], sc));
@@ -1453,6 +1479,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     const int kmax = mrhs_max_k();
     HIP_TRY(ctx, W.vecs.ensure((size_t)nprob * MR_VECS * kmax * ldv * 8));
     HIP_TRY(ctx, W.scal.ensure((size_t)nprob * kmax * sizeof(MrhsScalars)));
+    HIP_TRY(ctx, W.rpart.ensure((size_t)nprob * MR_ZSLICES * kmax * 8));
     HIP_TRY(ctx, hipMemsetAsync(W.vecs.p, 0, (size_t)nprob * MR_VECS * kmax * ldv * 8, st));
     HIP_TRY(ctx, hipMemsetAsync(W.scal.p, 0, (size_t)nprob * kmax * sizeof(MrhsScalars), st));
     std::vector<MrhsProblem> hp(nprob);
@@ -1472,6 +1499,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         q.Gt = base + 5 * kmax * ldv;
         q.Minv = W.pc[p]->pMinv;
         q.sc = W.scal.as<MrhsScalars>() + (size_t)p * kmax;
+        q.rho_part = W.rpart.as<double>() + (size_t)p * MR_ZSLICES * kmax;
         maxK = std::max<int64_t>(maxK, W.sk[p]->K);
     }
     // tasks per launch in Stage I: about 4 per CU, never fewer than 256 rows each
@@ -1509,7 +1537,9 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         // stage rows: every problem's sketch has the same element type
         const int sdt = W.sk[0]->bdtype;
         BatchPlan plan;
+        plan.one_launch = opts->batch_one_launch != 0;
         if ((rc = batched_setup(ctx, W, sdt, hp, target_tasks, plan)) != SPCG_OK) return rc;
+        plan_shapes(W, sdt, opts->batch_shape, plan);
         auto stage = [&](hipStream_t s) -> int {
             int r;
             if ((r = batched_products(ctx, W, s, sdt, PM_G, plan)) != SPCG_OK) return r;
@@ -1541,11 +1571,49 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // by timing one product pass per candidate (the partials are discarded:
     // the d-space step is not run, so the iterates are unaffected)
     int tpc = opts->batch_tasks_per_cu > 0 ? opts->batch_tasks_per_cu : W.tasks_per_cu[dtype & 3];
+    // tile shape per bucket: tuned once per context and storage type, by
+    // timing one product pass of each bucket alone in every shape its class
+    // has (at the tuned granularity, else 4 tasks per CU)
+    bool shapes_tuned = false;
+    float tune_ms[MR_NBUCKET * 4] = {};
+    if (opts->batch_shape <= 0) {
+        for (int b = 0; b < MR_NBUCKET; ++b) shapes_tuned = shapes_tuned || W.shape[dtype & 3][b] > 0;
+    }
+    if (opts->batch_shape <= 0 && !shapes_tuned) {
+        BatchPlan tp;
+        tp.one_launch = opts->batch_one_launch != 0;
+        if ((rc = batched_setup(ctx, W, dtype, hp, (int64_t)(tpc > 0 ? tpc : 4) * ctx->num_cu, tp)) != SPCG_OK)
+            return rc;
+        plan_shapes(W, dtype, 0, tp);
+        for (int b = 0; b < MR_NBUCKET; ++b) {
+            if (tp.seg[b + 1] <= tp.seg[b] || b / MR_KB == MR_CLASS_GENERIC) continue;
+            double best_ms = INFINITY;
+            int best = MR_SHAPE_PIPE3;
+            for (int sh = MR_SHAPE_PLAIN; sh < MR_NSHAPE; ++sh) {
+                if (!mrhs_shape_native(b / MR_KB, sh)) continue;
+                tp.shape[b] = sh;
+                if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp, b)) != SPCG_OK) return rc;   // warm-up
+                HIP_TRY(ctx, hipEventRecord(W.tune[0], st));
+                if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp, b)) != SPCG_OK) return rc;
+                HIP_TRY(ctx, hipEventRecord(W.tune[1], st));
+                HIP_TRY(ctx, hipEventSynchronize(W.tune[1]));
+                const double ms = elapsed_ms(W.tune[0], W.tune[1]);
+                tune_ms[b * 4 + sh - 1] = (float)ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = sh;
+                }
+            }
+            W.shape[dtype & 3][b] = best;
+        }
+    }
     if (tpc <= 0) {
         double best_ms = INFINITY;
         for (int cand : {2, 4, 8}) {
             BatchPlan tp;
+            tp.one_launch = opts->batch_one_launch != 0;
             if ((rc = batched_setup(ctx, W, dtype, hp, (int64_t)cand * ctx->num_cu, tp)) != SPCG_OK) return rc;
+            plan_shapes(W, dtype, opts->batch_shape, tp);
             if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp)) != SPCG_OK) return rc;   // warm-up
             HIP_TRY(ctx, hipEventRecord(W.tune[0], st));
             if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp)) != SPCG_OK) return rc;
@@ -1608,7 +1676,9 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     };
     int act = 0;
     BatchPlan plan;
+    plan.one_launch = opts->batch_one_launch != 0;
     if ((rc = batched_setup(ctx, W, dtype, hp, full_tasks, plan)) != SPCG_OK) return rc;
+    plan_shapes(W, dtype, opts->batch_shape, plan);
     set_changed = false;
     if ((rc = batched_products(ctx, W, st, dtype, PM_G, plan)) != SPCG_OK) return rc;
     if ((rc = batched_dspace(ctx, W, st, PA_START, plan)) != SPCG_OK) return rc;
@@ -1621,6 +1691,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     while (act > 0) {
         if (set_changed) {
             if ((rc = batched_setup(ctx, W, dtype, hp, full_tasks, plan)) != SPCG_OK) return rc;
+            plan_shapes(W, dtype, opts->batch_shape, plan);
             set_changed = false;
             gprod = gds = nullptr;
             if (graphs_on) {
@@ -1689,6 +1760,9 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             s.qr_passes = W.pc[p]->passes;
             s.batch_tasks_per_cu = tpc;
             s.batch_graphs = graphs_launched;
+            for (int b = 0; b < MR_NBUCKET && b < 16; ++b)
+                s.batch_shapes[b] = plan.seg[b + 1] > plan.seg[b] ? plan.shape[b] : 0;
+            for (int b = 0; b < MR_NBUCKET * 4 && b < 64; ++b) s.batch_tune_ms[b] = tune_ms[b];
             s.rho_final = hs[(size_t)p * kmax].rho;
             s.ax_norm = std::sqrt(std::max(hs[(size_t)p * kmax].ax2, 0.0));
             if (timing) {
@@ -1756,6 +1830,7 @@ int mrhs_stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     HIP_TRY(ctx, hipStreamSynchronize(st));
     HIP_TRY(ctx, W.vecs.ensure((size_t)MR_VECS * kmax * ldv * 8));
     HIP_TRY(ctx, W.scal.ensure((size_t)kmax * sizeof(MrhsScalars)));
+    HIP_TRY(ctx, W.rpart.ensure((size_t)MR_ZSLICES * kmax * 8));
     HIP_TRY(ctx, hipMemsetAsync(W.vecs.p, 0, (size_t)MR_VECS * kmax * ldv * 8, st));
     HIP_TRY(ctx, hipMemsetAsync(W.scal.p, 0, (size_t)kmax * sizeof(MrhsScalars), st));
     std::vector<MrhsProblem> hp(1);
@@ -1773,6 +1848,7 @@ int mrhs_stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     q.Gt = base + 5 * kmax * ldv;
     q.Minv = pc->pMinv;
     q.sc = W.scal.as<MrhsScalars>();
+    q.rho_part = W.rpart.as<double>();
     q.A = A->data;
     q.m = A->rows;
     q.lda = A->ld;
@@ -1784,6 +1860,7 @@ int mrhs_stage_run(spcg_ctx* ctx, const spcg_mat* A, const spcg_mat* b, double c
     if ((rc = beta_to_cols(ctx, beta, d, k, q.X, ldv)) != SPCG_OK) return rc;
     BatchPlan plan;
     if ((rc = batched_setup(ctx, W, A->dtype, hp, 4 * (int64_t)ctx->num_cu, plan)) != SPCG_OK) return rc;
+    plan_shapes(W, A->dtype, 0, plan);
     std::vector<MrhsScalars> hs(kmax);
     auto read = [&]() -> int {
         HIP_TRY(ctx, hipMemcpyAsync(hs.data(), W.scal.p, (size_t)k * sizeof(MrhsScalars), hipMemcpyDeviceToHost, st));

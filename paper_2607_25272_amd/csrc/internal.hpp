@@ -235,6 +235,7 @@ struct MrhsProblem {
     double* Gt;
     const double* Minv;     // d x d
     MrhsScalars* sc;        // k entries
+    double* rho_part;       // per 128-row slice of z, 16 shares of g^T z
     int t0, t1;             // tasks of this problem in the current launch
     int active;             // 0: skip (converged or no stage)
 };
@@ -245,18 +246,34 @@ struct MrhsTask {
 };
 int mrhs_max_d();
 int mrhs_max_k();
+constexpr int MR_ZSLICES = 4;   // 128-row slices of z = M g (d <= 512)
 // Row-width classes of the product launches: load width (16 or 4 bytes) x
 // loads per row (a power of two); MR_CLASS_GENERIC reads element by element
 // (any row stride).
 enum MrhsClass : int { MR_CLASS_16x1 = 0, MR_CLASS_16x2, MR_CLASS_4x1, MR_CLASS_4x2, MR_CLASS_4x4, MR_CLASS_4x8,
                        MR_CLASS_GENERIC, MR_NCLASS };
 int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d);
-// One launch over tasks[task0 .. task0 + ntasks), all of class cls; task t
-// writes partial block t.
-hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, const MrhsTask* tasks, int task0,
-                            int ntasks, const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal);
-// One block per problem: the whole d-space step of all k columns.
-// variant: PA_START (g, z, p, rho from the G partials), PA_STEP, PA_REFRESH.
+// Tile shapes of a product launch: MR_SHAPE_PLAIN runs GEMM1, the W
+// reduction and GEMM2 of each 16-row tile between three barriers with 3 LDS
+// slots; MR_SHAPE_PIPE3 / PIPE4 software-pipeline two tiles (two barriers
+// per tile) with 3 / 4 slots.  PIPE4 exists for rows of at most 1 KB
+// (classes 16x1, 4x1, 4x2, 4x4); elsewhere it runs as PIPE3.
+enum MrhsShape : int { MR_SHAPE_PLAIN = 1, MR_SHAPE_PIPE3 = 2, MR_SHAPE_PIPE4 = 3, MR_NSHAPE = 4 };
+bool mrhs_shape_native(int cls, int shape);
+// launch buckets: row-width class x (k <= 8, k > 8)
+constexpr int MR_KB = 2;
+constexpr int MR_NBUCKET = MR_NCLASS * MR_KB;
+inline int mrhs_bucket(int cls, int k) { return cls * MR_KB + (k > 8 ? 1 : 0); }
+// One launch over tasks[task0 .. task0 + ntasks), all of class cls, in tile
+// shape `shape`; task t writes partial block t.
+hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, int shape, const MrhsTask* tasks,
+                            int task0, int ntasks, const MrhsProblem* probs, float* part_s, float* part_g,
+                            float* part_scal);
+// The d-space step of all k columns of every problem, three launches: the
+// partial sums, alpha and the x, g updates (one block per problem); z = M g
+// in 128-row slices (one block per slice and problem); rho and p (one block
+// per problem).  variant: PA_START (g, z, p, rho from the G partials),
+// PA_STEP, PA_REFRESH.
 hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs, int nprob,
                            const float* part_s, const float* part_g, const float* part_scal);
 

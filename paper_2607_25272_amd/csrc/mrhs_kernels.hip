@@ -42,7 +42,6 @@ constexpr int MT = 16;          // rows per tile (MFMA M)
 constexpr int KP = 16;          // right-hand sides per MFMA (N)
 constexpr int MR_DMAX = 512;    // columns supported
 constexpr int MRW = 8;          // waves per block
-constexpr int MR_RING = 3;      // LDS slots
 
 typedef float mv4f __attribute__((ext_vector_type(4)));
 
@@ -94,8 +93,14 @@ __device__ __forceinline__ void lds_elem4<bf16_t>(const unsigned char* row, int 
     o[3] = __uint_as_float(v.y & 0xffff0000u);
 }
 
-template <typename TS, int MODE, int DMAB, int NIR>
-__global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* __restrict__ tasks, int task0,
+// PIPE = false: per tile, GEMM1, the W partials, a barrier, the reduction,
+// a barrier and GEMM2 (three barriers per 16-row tile).  PIPE = true:
+// software-pipelined over two tiles with two barriers per tile: the
+// reduction of tile u (lanes < 32, vector ALU and LDS) runs beside GEMM1 of
+// tile u + 1 on the matrix cores, then GEMM2 of tile u.  RING LDS slots hold
+// the tiles being read and the tiles in flight (PIPE reads two at a time).
+template <typename TS, int MODE, int DMAB, int NIR, bool PIPE, int RING, int NW>
+__global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* __restrict__ tasks, int task0,
                                                                 const MrhsProblem* __restrict__ probs,
                                                                 float* part_s, float* part_g, float* part_scal) {
     constexpr bool DO_S = MODE != PM_G;
@@ -106,16 +111,18 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     constexpr int YB = DO_G ? 256 : 0;               // staged b bytes per row (k FP64 values)
     constexpr int SLOT = MT * PITCH + MT * YB;
     constexpr int AJOBS = MT * NIR;                  // A loads per tile
-    constexpr int OPS = AJOBS / MRW + (DO_G ? MT / MRW : 0);   // loads per wave per tile
-    static_assert(AJOBS % MRW == 0 && MT % MRW == 0, "even split of the loads");
+    constexpr int OPS = AJOBS / NW + (DO_G ? MT / NW : 0);   // loads per wave per tile
+    static_assert(AJOBS % NW == 0 && MT % NW == 0, "even split of the loads");
+    constexpr int RPW = MT / NW;   // tile rows whose W reduction a wave takes
     // widest row of the class: the register arrays below are sized for it
     constexpr int DCLS = NIR * 64 * DMAB / ES < MR_DMAX ? NIR * 64 * DMAB / ES : MR_DMAX;
-    constexpr int KG = (DCLS / 16 + MRW - 1) / MRW;     // 16-column K groups per wave (first GEMM)
-    constexpr int MAXT = (DCLS / 16 + MRW - 1) / MRW;   // second-GEMM output tiles per wave
-    static_assert((MR_RING - 2) * OPS < 64, "vmcnt range");
+    constexpr int KG = (DCLS / 16 + NW - 1) / NW;     // 16-column K groups per wave (first GEMM)
+    constexpr int MAXT = (DCLS / 16 + NW - 1) / NW;   // second-GEMM output tiles per wave
+    static_assert(RING >= (PIPE ? 3 : 2) && RING <= 4 && (RING - 2) * OPS < 64, "ring shape");
     __shared__ __align__(16) unsigned char sl0[SLOT];
     __shared__ __align__(16) unsigned char sl1[SLOT];
-    __shared__ __align__(16) unsigned char sl2[SLOT];
+    __shared__ __align__(16) unsigned char sl2[RING > 2 ? SLOT : 16];
+    __shared__ __align__(16) unsigned char sl3[RING > 3 ? SLOT : 16];
     // Column packing: the first GEMM's B operand is [P | x_hi | x_lo] (the
     // matrices this mode needs, k columns each) laid side by side over
     // NS1 = ceil(NM1 k / 16) 16-column slabs, and the second GEMM's is
@@ -125,10 +132,10 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     constexpr int NM2 = (DO_S ? 1 : 0) + (DO_G ? 1 : 0);
     // per-wave partials of W per slab; row pitch 20 keeps the MFMA-layout
     // stores (rows 4 lg + v, column li) conflict-free
-    __shared__ float W1[NM1][MRW][MT][KP + 4];
+    __shared__ float W1[NM1][NW][MT][KP + 4];
     // the second GEMM's packed B operand (pitch 36: its reads are conflict-free)
     __shared__ float W2[MT][2 * KP + 4];
-    __shared__ float nrm[2][MRW][32];
+    __shared__ float nrm[2][NW][32];
 
     const MrhsTask task = tasks[blockIdx.x];
     const int64_t gtask = (int64_t)task0 + blockIdx.x;
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
     const char* Abase = static_cast<const char*>(pb.A);
     const int64_t rowb = pb.lda * ES;
     const int64_t rlast = task.r1 - 1;
-    for (int e = threadIdx.x; e < MT * (2 * KP + 4); e += 64 * MRW) (&W2[0][0])[e] = 0.f;
+    for (int e = threadIdx.x; e < MT * (2 * KP + 4); e += 64 * NW) (&W2[0][0])[e] = 0.f;
 
     // constant B operands of the first GEMM: P and x = hi + lo (~48 bits),
     // zero outside d x k.  A x = A x_hi + A x_lo: the high product only
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         gdouble* base = (gdouble*)(src == 0 ? pb.P : pb.X);
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
-            const int q = wave + MRW * g;
+            const int q = wave + NW * g;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int row = 16 * q + 4 * lg + u;
@@ -190,8 +197,8 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
 
     auto issue = [&](int64_t tl, unsigned char* T) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < AJOBS / MRW; ++q) {
-            const int job = wave + MRW * q;
+        for (int q = 0; q < AJOBS / NW; ++q) {
+            const int job = wave + NW * q;
             const int r = job / NIR, c = job % NIR;
             const int64_t grow = min(task.r0 + tl * MT + r, rlast);
             const int vi = min(c * 64 + lane, nvec - 1);
@@ -201,8 +208,8 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         }
         if constexpr (DO_G) {
 #pragma unroll
-            for (int q = 0; q < MT / MRW; ++q) {
-                const int r = wave + MRW * q;
+            for (int q = 0; q < MT / NW; ++q) {
+                const int r = wave + NW * q;
                 const int64_t grow = min(task.r0 + tl * MT + r, rlast);
                 const int w = min(lane, 2 * k - 1);
                 mr_lds_load<4>(reinterpret_cast<const char*>(pb.b + grow * pb.ldb) + 4 * w,
@@ -210,19 +217,18 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
             }
         }
     };
-    auto consume = [&](int64_t tl, const unsigned char* T) __attribute__((always_inline)) {
-        // first GEMM: this wave's K groups of W = A_t [P | x_hi | x_lo] (packed)
-        mv4f w1[NM1];
+    // first GEMM: this wave's K groups of W = A_t [P | x_hi | x_lo] (packed)
+    auto gemm1 = [&](const unsigned char* T, mv4f* w1) __attribute__((always_inline)) {
 #pragma unroll
         for (int sl = 0; sl < NM1; ++sl) w1[sl] = mv4f{0.f, 0.f, 0.f, 0.f};
         const unsigned char* arow = T + li * PITCH;
         // the slab count is uniform per task: one loop body per count, so
         // the MFMA chains carry no per-instruction conditions
-        auto gemm1 = [&](auto ns_c) __attribute__((always_inline)) {
+        auto run = [&](auto ns_c) __attribute__((always_inline)) {
             constexpr int NS = decltype(ns_c)::value;
 #pragma unroll
             for (int g = 0; g < KG; ++g) {
-                const int q = wave + MRW * g;
+                const int q = wave + NW * g;
                 if (q < dt) {
                     float a4[4];
                     lds_elem4<TS>(arow, 16 * q + 4 * lg, a4);
@@ -236,43 +242,44 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
             }
         };
         if constexpr (NM1 >= 3) {
-            if (ns1 >= 3) gemm1(std::integral_constant<int, 3>{});
-            else if (ns1 == 2) gemm1(std::integral_constant<int, 2>{});
-            else gemm1(std::integral_constant<int, 1>{});
+            if (ns1 >= 3) run(std::integral_constant<int, 3>{});
+            else if (ns1 == 2) run(std::integral_constant<int, 2>{});
+            else run(std::integral_constant<int, 1>{});
         } else if constexpr (NM1 == 2) {
-            if (ns1 == 2) gemm1(std::integral_constant<int, 2>{});
-            else gemm1(std::integral_constant<int, 1>{});
+            if (ns1 == 2) run(std::integral_constant<int, 2>{});
+            else run(std::integral_constant<int, 1>{});
         } else {
-            gemm1(std::integral_constant<int, 1>{});
+            run(std::integral_constant<int, 1>{});
         }
-        // unused slabs store their zeros
+    };
+    // this wave's partials of W into LDS (unused slabs store their zeros)
+    auto store_w1 = [&](const mv4f* w1) __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
 #pragma unroll
             for (int sl = 0; sl < NM1; ++sl) W1[sl][wave][4 * lg + v][li] = w1[sl][v];
         }
-        __builtin_amdgcn_s_waitcnt(MR_LGKM0);
-        __builtin_amdgcn_s_barrier();
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // reduce-scatter: wave w sums the 8 partials of rows 2w, 2w + 1 (lane
-        // l < 32: row 2w + l / 16, right-hand side l mod 16) in a fixed
-        // order, forms the residual there once, and publishes the second
-        // GEMM's packed B operand
-        if (lane < 32) {
-            const int rr = 2 * wave + (lane >> 4), cc = lane & 15;
+    };
+    // reduce-scatter: wave w sums the NW partials of its RPW rows (lane
+    // l < 16 RPW: row RPW w + l / 16, right-hand side l mod 16) in a fixed
+    // order, forms the residual there once, and publishes the second GEMM's
+    // packed B operand
+    auto reduce = [&](int64_t tl, const unsigned char* T) __attribute__((always_inline)) {
+        if (lane < 16 * RPW) {
+            const int rr = RPW * wave + (lane >> 4), cc = lane & 15;
             if (cc < k) {
                 const bool ok = task.r0 + tl * MT + rr < task.r1;
                 if constexpr (DO_S) {
                     float t0 = 0.f;
 #pragma unroll
-                    for (int w = 0; w < MRW; ++w) t0 += W1[0][w][rr][cc];
+                    for (int w = 0; w < NW; ++w) t0 += W1[0][w][rr][cc];
                     W2[rr][cc] = ok ? t0 : 0.f;
                 }
                 if constexpr (DO_G) {
                     const int qh = (DO_S ? k : 0) + cc, ql = qh + k;
                     float t1 = 0.f, tlo = 0.f;
 #pragma unroll
-                    for (int w = 0; w < MRW; ++w) {
+                    for (int w = 0; w < NW; ++w) {
                         t1 += W1[qh >> 4][w][rr][qh & 15];
                         tlo += W1[ql >> 4][w][rr][ql & 15];
                     }
@@ -286,23 +293,22 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
                 }
             }
         }
-        __builtin_amdgcn_s_waitcnt(MR_LGKM0);
-        __builtin_amdgcn_s_barrier();
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        // second GEMM with the rows of the tile permuted: at step u lane group
-        // lg takes row 4 lg + u (conflict-free LDS reads of A_t^T)
+    };
+    // second GEMM: [S | G][:, tile mt] += A_t^T [W_p | g], with the rows of
+    // the tile permuted: at step u lane group lg takes row 4 lg + u
+    // (conflict-free LDS reads of A_t^T)
+    auto gemm2 = [&](const unsigned char* T) __attribute__((always_inline)) {
         float b2[2][4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             b2[0][u] = W2[4 * lg + u][li];
             b2[1][u] = NM2 > 1 ? W2[4 * lg + u][16 + li] : 0.f;
         }
-        // second GEMM: [S | G][:, tile mt] += A_t^T [W_p | g]
-        auto gemm2 = [&](auto ns_c) __attribute__((always_inline)) {
+        auto run = [&](auto ns_c) __attribute__((always_inline)) {
             constexpr int NS = decltype(ns_c)::value;
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
-                const int mt = wave + MRW * t;
+                const int mt = wave + NW * t;
                 if (mt < dt) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -315,29 +321,85 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
             }
         };
         if constexpr (NM2 > 1) {
-            if (ns2 > 1) gemm2(std::integral_constant<int, 2>{});
-            else gemm2(std::integral_constant<int, 1>{});
+            if (ns2 > 1) run(std::integral_constant<int, 2>{});
+            else run(std::integral_constant<int, 1>{});
         } else {
-            gemm2(std::integral_constant<int, 1>{});
+            run(std::integral_constant<int, 1>{});
         }
     };
+    auto lds_barrier = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(MR_LGKM0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    };
+    // one LDS object per slot: the slot of a step is known at compile time
+    auto slot = [&](auto i_c) __attribute__((always_inline)) -> unsigned char* {
+        constexpr int i = decltype(i_c)::value % RING;
+        if constexpr (i == 0) return sl0;
+        else if constexpr (i == 1) return sl1;
+        else if constexpr (i == 2) return sl2;
+        else return sl3;
+    };
 
-    issue(0, sl0);
-    issue(1, sl1);
-    // every step runs (rows past the task contribute zeros), so the slot of
-    // each read is known at compile time
-#define SPCG_MR_STEP(CUR, NXT, OFF)                                  \
-    __builtin_amdgcn_s_waitcnt(mr_vmcnt_imm((MR_RING - 2) * OPS));   \
-    __builtin_amdgcn_s_barrier();                                    \
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);                         \
-    issue(t + (OFF) + MR_RING - 1, NXT);                             \
-    consume(t + (OFF), CUR);
-    for (int64_t t = 0; t < ntile; t += MR_RING) {
-        SPCG_MR_STEP(sl0, sl2, 0)
-        SPCG_MR_STEP(sl1, sl0, 1)
-        SPCG_MR_STEP(sl2, sl1, 2)
+    // tiles 0 .. RING - 2 in flight; the loop issues one tile per step.
+    // The work of steps past the last tile is skipped (uniform over the
+    // block); their waits, barriers and loads (clamped rows, ignored) stay,
+    // so that every path through a step has the same loads in flight.
+    static_for<0, RING - 1>([&](auto kc) { issue(decltype(kc)::value, slot(kc)); });
+    if constexpr (!PIPE) {
+        for (int64_t t = 0; t < ntile; t += RING) {
+            // step k: wait for tile t + k (tiles up to t + k + RING - 2 are
+            // issued), refill the slot read at step k - 1
+            static_for<0, RING>([&](auto kc) {
+                constexpr int kk = decltype(kc)::value;
+                __builtin_amdgcn_s_waitcnt(mr_vmcnt_imm((RING - 2) * OPS));
+                __builtin_amdgcn_s_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                issue(t + kk + RING - 1, slot(std::integral_constant<int, kk + RING - 1>{}));
+                if (t + kk < ntile) {
+                    mv4f w1[NM1];
+                    gemm1(slot(kc), w1);
+                    store_w1(w1);
+                    lds_barrier();
+                    reduce(t + kk, slot(kc));
+                    lds_barrier();
+                    gemm2(slot(kc));
+                }
+            });
+        }
+    } else {
+        // GEMM1 of tile 0 before the loop; step u then runs the reduction
+        // of tile u beside GEMM1 of tile u + 1, and after the second
+        // barrier GEMM2 of tile u and the W partials of tile u + 1
+        __builtin_amdgcn_s_waitcnt(mr_vmcnt_imm((RING - 2) * OPS));
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        {
+            mv4f w1[NM1];
+            gemm1(sl0, w1);
+            store_w1(w1);
+        }
+        for (int64_t t = 0; t < ntile; t += RING) {
+            static_for<0, RING>([&](auto kc) {
+                constexpr int kk = decltype(kc)::value;
+                // tile u + 1 has landed (tiles up to u + RING - 2 are
+                // issued); the barrier also publishes the W partials of tile
+                // u and frees the slot GEMM2 read at step u - 1
+                __builtin_amdgcn_s_waitcnt(mr_vmcnt_imm((RING - 3) * OPS));
+                __builtin_amdgcn_s_barrier();
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                issue(t + kk + RING - 1, slot(std::integral_constant<int, kk + RING - 1>{}));
+                if (t + kk < ntile) {
+                    mv4f w1n[NM1];
+                    reduce(t + kk, slot(kc));
+                    gemm1(slot(std::integral_constant<int, kk + 1>{}), w1n);
+                    lds_barrier();   // W2 of tile u is visible; the partials of tile u are read
+                    store_w1(w1n);
+                    gemm2(slot(kc));
+                }
+            });
+        }
     }
-#undef SPCG_MR_STEP
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // partial outputs: part[task][col][c] (c < 16), unpacked from the slabs
@@ -350,7 +412,7 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         float* out = (DO_S && mi == 0) ? part_s : part_g;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-            const int mt = wave + MRW * t;
+            const int mt = wave + NW * t;
             if (mt < dt) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -361,8 +423,8 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
         }
     }
     if (DO_G) {
-        // per-column norms: the 8 waves' two row lanes, in a fixed order
-        if (lane < 32) {
+        // per-column norms: every wave's row lanes, in a fixed order
+        if (lane < 16 * RPW) {
             nrm[0][wave][lane] = r2;
             nrm[1][wave][lane] = ax2;
         }
@@ -371,9 +433,12 @@ __global__ __launch_bounds__(64 * MRW) void mrhs_product_kernel(const MrhsTask* 
             const int c = threadIdx.x;
             float a0 = 0.f, a1 = 0.f;
 #pragma unroll
-            for (int w = 0; w < MRW; ++w) {
-                a0 += nrm[0][w][c] + nrm[0][w][c + 16];
-                a1 += nrm[1][w][c] + nrm[1][w][c + 16];
+            for (int w = 0; w < NW; ++w) {
+#pragma unroll
+                for (int h = 0; h < RPW; ++h) {
+                    a0 += nrm[0][w][c + 16 * h];
+                    a1 += nrm[1][w][c + 16 * h];
+                }
             }
             part_scal[gtask * 2 * KP + c] = a0;
             part_scal[gtask * 2 * KP + KP + c] = a1;
@@ -551,28 +616,52 @@ __global__ __launch_bounds__(64 * MRG_WAVES) void mrhs_product_reg_kernel(const 
 }
 
 
-template <typename TS, int DMAB, int NIR>
-hipError_t mr_launch(hipStream_t st, int mode, const MrhsTask* tasks, int task0, int ntasks, const MrhsProblem* probs,
-                     float* ps, float* pg, float* pscal) {
-    dim3 grid(ntasks), block(64 * MRW);
+template <typename TS, int DMAB, int NIR, bool PIPE, int RING, int NW = MRW>
+hipError_t mr_launch_shape(hipStream_t st, int mode, const MrhsTask* tasks, int task0, int ntasks,
+                           const MrhsProblem* probs, float* ps, float* pg, float* pscal) {
+    dim3 grid(ntasks), block(64 * NW);
     switch (mode) {
-        case PM_S: mrhs_product_kernel<TS, PM_S, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
-        case PM_G: mrhs_product_kernel<TS, PM_G, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
-        default: mrhs_product_kernel<TS, PM_SG, DMAB, NIR><<<grid, block, 0, st>>>(tasks, task0, probs, ps, pg, pscal); break;
+        case PM_S:
+            mrhs_product_kernel<TS, PM_S, DMAB, NIR, PIPE, RING, NW><<<grid, block, 0, st>>>(tasks, task0, probs, ps,
+                                                                                             pg, pscal);
+            break;
+        case PM_G:
+            mrhs_product_kernel<TS, PM_G, DMAB, NIR, PIPE, RING, NW><<<grid, block, 0, st>>>(tasks, task0, probs, ps,
+                                                                                             pg, pscal);
+            break;
+        default:
+            mrhs_product_kernel<TS, PM_SG, DMAB, NIR, PIPE, RING, NW><<<grid, block, 0, st>>>(tasks, task0, probs,
+                                                                                              ps, pg, pscal);
+            break;
     }
     return hipGetLastError();
 }
 
+// 4 slots fit the LDS for rows of at most 1 KB
+constexpr bool mr_pipe4(int dmab, int nir) { return nir * 64 * dmab <= 1024; }
+
+template <typename TS, int DMAB, int NIR>
+hipError_t mr_launch(hipStream_t st, int mode, int shape, const MrhsTask* tasks, int task0, int ntasks,
+                     const MrhsProblem* probs, float* ps, float* pg, float* pscal) {
+    if (shape == MR_SHAPE_PLAIN)
+        return mr_launch_shape<TS, DMAB, NIR, false, 3>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+    if constexpr (mr_pipe4(DMAB, NIR)) {
+        if (shape == MR_SHAPE_PIPE4)
+            return mr_launch_shape<TS, DMAB, NIR, true, 4>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+    }
+    return mr_launch_shape<TS, DMAB, NIR, true, 3>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+}
+
 template <typename TS>
-hipError_t mr_launch_class(hipStream_t st, int mode, int cls, const MrhsTask* tasks, int task0, int ntasks,
-                           const MrhsProblem* probs, float* ps, float* pg, float* pscal) {
+hipError_t mr_launch_class(hipStream_t st, int mode, int cls, int shape, const MrhsTask* tasks, int task0,
+                           int ntasks, const MrhsProblem* probs, float* ps, float* pg, float* pscal) {
     switch (cls) {
-        case MR_CLASS_16x1: return mr_launch<TS, 16, 1>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
-        case MR_CLASS_16x2: return mr_launch<TS, 16, 2>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
-        case MR_CLASS_4x1: return mr_launch<TS, 4, 1>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
-        case MR_CLASS_4x2: return mr_launch<TS, 4, 2>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
-        case MR_CLASS_4x4: return mr_launch<TS, 4, 4>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
-        case MR_CLASS_4x8: return mr_launch<TS, 4, 8>(st, mode, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_16x1: return mr_launch<TS, 16, 1>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_16x2: return mr_launch<TS, 16, 2>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x1: return mr_launch<TS, 4, 1>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x2: return mr_launch<TS, 4, 2>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x4: return mr_launch<TS, 4, 4>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
+        case MR_CLASS_4x8: return mr_launch<TS, 4, 8>(st, mode, shape, tasks, task0, ntasks, probs, ps, pg, pscal);
         default: break;
     }
     if (cls == MR_CLASS_GENERIC) {
@@ -612,13 +701,23 @@ int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d) {
     return MR_CLASS_GENERIC;
 }
 
-hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, const MrhsTask* tasks, int task0,
-                            int ntasks, const MrhsProblem* probs, float* part_s, float* part_g, float* part_scal) {
+bool mrhs_shape_native(int cls, int shape) {
+    if (shape == MR_SHAPE_PIPE4)
+        return cls == MR_CLASS_16x1 || cls == MR_CLASS_4x1 || cls == MR_CLASS_4x2 || cls == MR_CLASS_4x4;
+    if (shape == MR_SHAPE_PIPE3) return cls != MR_CLASS_GENERIC;
+    return shape == MR_SHAPE_PLAIN;
+}
+
+hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, int shape, const MrhsTask* tasks,
+                            int task0, int ntasks, const MrhsProblem* probs, float* part_s, float* part_g,
+                            float* part_scal) {
     if (ntasks <= 0) return hipSuccess;
     if (dtype == DT_F32)
-        return mr_launch_class<float>(st, mode, cls, tasks + task0, task0, ntasks, probs, part_s, part_g, part_scal);
+        return mr_launch_class<float>(st, mode, cls, shape, tasks + task0, task0, ntasks, probs, part_s, part_g,
+                                      part_scal);
     if (dtype == DT_BF16)
-        return mr_launch_class<bf16_t>(st, mode, cls, tasks + task0, task0, ntasks, probs, part_s, part_g, part_scal);
+        return mr_launch_class<bf16_t>(st, mode, cls, shape, tasks + task0, task0, ntasks, probs, part_s, part_g,
+                                       part_scal);
     return hipErrorInvalidValue;
 }
 
@@ -755,50 +854,101 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
         pb.sc[threadIdx.x].exact = 0;
     }
     __syncthreads();
-    // 3. z = M g for every column, thread per row i, j in order.  M = W W^T
-    //    is symmetric, so row i is read as column i: the lanes of a wave take
-    //    consecutive i and each load of M is one contiguous row segment.  The
-    //    k values of g at each j come from an LDS copy (loads unrolled so that
-    //    they are in flight together).
-    {
-        __shared__ double gs[MR_DMAX][KP];
+}
+
+// z = M g for rows [ZR s, ZR s + ZR) of one problem (block (s, p)), all k
+// columns.  M = W W^T is symmetric, so row i is read as column i: the lanes
+// of a wave take consecutive i and each load of M is one contiguous row
+// segment.  The j range is split into four quarters (thread t: row t mod
+// ZR, quarter t / ZR), whose partial sums are added in quarter order; the
+// slice's share of g^T z goes to rho_part, summed over the slices in slice
+// order by the next kernel.
+constexpr int ZR = 128;
+constexpr int ZQ = DS_THREADS / ZR;
+constexpr int ZSL = MR_DMAX / ZR;
+static_assert(ZQ * ZR == DS_THREADS && ZSL * ZR == MR_DMAX && ZSL == MR_ZSLICES, "z slices");
+
+__global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_z_kernel(const MrhsProblem* __restrict__ probs) {
+    __shared__ double gs[MR_DMAX][KP];   // g, then the quarter partials of z
+    const MrhsProblem pb = probs[blockIdx.y];
+    const int s = blockIdx.x;
+    if (!pb.active || s * ZR >= pb.d) return;   // uniform over the block
+    const int d = pb.d, k = pb.k;
+    const int64_t ldv = pb.ldv;
 #pragma unroll 8
-        for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
-            const int j = e / KP, c = e % KP;
-            gs[j][c] = c < k ? pb.G[c * ldv + j] : 0.0;
-        }
-        __syncthreads();
-        // one row per thread (d <= DS_THREADS), j unrolled by 4: each block
-        // streams its own d x d M from HBM, so what bounds it is how many
-        // loads are in flight
-        static_assert(MR_DMAX <= DS_THREADS, "one row per thread");
-        const int i0 = threadIdx.x;
-        const bool h0 = i0 < d;
-        double a0[KP];
-#pragma unroll
-        for (int c = 0; c < KP; ++c) a0[c] = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < d; ++j) {
-            const double m0 = h0 ? pb.Minv[(int64_t)j * d + i0] : 0.0;
-            // every column, without branches (g is zero past k): straight-line
-            // code lets the loads of later j issue before these FMAs
-#pragma unroll
-            for (int c = 0; c < KP; ++c) a0[c] = fma(m0, gs[j][c], a0[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < KP; ++c)
-            if (c < k && h0) pb.Z[c * ldv + i0] = a0[c];
+    for (int e = threadIdx.x; e < d * KP; e += DS_THREADS) {
+        const int j = e / KP, c = e % KP;
+        gs[j][c] = c < k ? pb.G[c * ldv + j] : 0.0;
     }
     __syncthreads();
-    // 4. rho' = g^T z; p = z (start) or z + (rho'/rho) p
-    colwise_dot(pb.G, pb.Z, ldv, d, k, colv, red);
+    const int r = threadIdx.x % ZR, q = threadIdx.x / ZR;
+    const int i = s * ZR + r;
+    const bool h = i < d;
+    const int dq = (d + ZQ - 1) / ZQ;
+    const int j0 = q * dq, j1 = min(d, j0 + dq);
+    double a0[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) a0[c] = 0.0;
+    // every column, without branches (g is zero past k): straight-line code
+    // lets the loads of later j issue before these FMAs
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const double m0 = h ? pb.Minv[(int64_t)j * d + i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < KP; ++c) a0[c] = fma(m0, gs[j][c], a0[c]);
+    }
+    __syncthreads();   // gs is free: it takes the quarter partials
+    double (*zp)[ZR][KP] = reinterpret_cast<double (*)[ZR][KP]>(&gs[0][0]);
+    static_assert(ZQ * ZR <= MR_DMAX, "partials fit");
+#pragma unroll
+    for (int c = 0; c < KP; ++c) zp[q][r][c] = a0[c];
+    __syncthreads();
+    double gz[KP];
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < KP; ++c) {
+            double z = zp[0][r][c];
+#pragma unroll
+            for (int w = 1; w < ZQ; ++w) z += zp[w][r][c];
+            gz[c] = 0.0;
+            if (c < k && h) {
+                pb.Z[c * ldv + i] = z;
+                gz[c] = pb.G[c * ldv + i] * z;
+            }
+        }
+    }
+    __syncthreads();   // the partials are read: zp[1] takes the g z terms
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < KP; ++c) zp[1][r][c] = gz[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < KP) {
+        const int c = threadIdx.x;
+        double t = 0.0;
+        for (int w = 0; w < ZR; ++w) t += zp[1][w][c];
+        pb.rho_part[s * KP + c] = t;
+    }
+}
+
+// rho' = g^T z (the slices' shares in slice order); p = z (start) or
+// z + (rho'/rho) p
+__global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_p_kernel(int variant, const MrhsProblem* __restrict__ probs) {
+    __shared__ double gamma_sh[KP];
+    __shared__ int step_sh[KP];
+    const MrhsProblem pb = probs[blockIdx.x];
+    if (!pb.active) return;
+    const int d = pb.d, k = pb.k;
+    const int64_t ldv = pb.ldv;
+    const int nsl = (d + ZR - 1) / ZR;
     if (threadIdx.x < KP) {
         const int c = threadIdx.x;
         int mode = 0;
         double gm = 0.0;
         if (c < k) {
+            double rn = 0.0;
+            for (int sl = 0; sl < nsl; ++sl) rn += pb.rho_part[sl * KP + c];
             MrhsScalars& sc = pb.sc[c];
-            const double rn = colv[c];
             const bool skip = sc.breakdown || (variant != PA_START && sc.exact);
             if (!skip) {
                 if (!dfinite(rn)) {
@@ -835,6 +985,11 @@ hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs
                            const float* part_s, const float* part_g, const float* part_scal) {
     if (nprob <= 0) return hipSuccess;
     mrhs_dspace_kernel<<<nprob, DS_THREADS, 0, st>>>(variant, probs, part_s, part_g, part_scal);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    mrhs_dspace_z_kernel<<<dim3(ZSL, nprob), DS_THREADS, 0, st>>>(probs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    mrhs_dspace_p_kernel<<<nprob, DS_THREADS, 0, st>>>(variant, probs);
     return hipGetLastError();
 }
 

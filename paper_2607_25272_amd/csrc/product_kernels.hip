@@ -353,15 +353,6 @@ constexpr int ring_depth(int slot) {
 }
 constexpr int vmcnt_imm(int n) { return (n & 0xf) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8); }
 
-// f(std::integral_constant<int, I>) for I = B .. E-1, unrolled at compile time
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 template <int DMAB>
 __device__ __forceinline__ void lds_load(const void* src, void* lds) {
     void* g = const_cast<void*>(src);

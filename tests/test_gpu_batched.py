@@ -166,3 +166,53 @@ def test_batched_autotuned_granularity(S, ctx):
             _check(q, b)
     finally:
         c2.close()
+
+
+def test_batched_tile_shapes_are_bit_identical(S, ctx):
+    # The three tile shapes of the product launches (three barriers per
+    # tile; the two-tile pipeline with 3 and with 4 LDS slots) run the same
+    # MFMA chains and reductions in the same order per task, so with the
+    # same granularity they give identical bits; the autotuned shapes are
+    # reported per launch bucket (class * 2 + (k > 8)).
+    probs = _uneven(n=8, seed=13)
+    Xs, Ys = [q.X for q in probs], [q.Y for q in probs]
+    ref, st_r = S.spcg_solve_batched(ctx, Xs, Ys, seed=5, batch_tasks_per_cu=4, batch_shape=1)
+    assert all(v in (0, 1) for v in st_r[0]["batch_shapes"])
+    for shape in (2, 3):
+        got, st = S.spcg_solve_batched(ctx, Xs, Ys, seed=5, batch_tasks_per_cu=4, batch_shape=shape)
+        used = [v for v in st[0]["batch_shapes"] if v]
+        assert used and all(v == shape for v in used), (shape, used)
+        for q, a, b, s1, s2 in zip(probs, ref, got, st_r, st):
+            assert s1["T_stage2"] == s2["T_stage2"]
+            assert torch.equal(a, b), (shape, q.N, q.d, q.k)
+    for q, b, s in zip(probs, ref, st_r):
+        assert s["converged"]
+        _check(q, b)
+    # a fresh context tunes the shapes (timing passes only, iterates
+    # untouched): its tuned solve equals its fixed-shape solve
+    c2 = S.Context(0)
+    try:
+        tuned, st_t = S.spcg_solve_batched(c2, Xs, Ys, seed=5, batch_tasks_per_cu=4)
+        assert any(v > 0 for v in st_t[0]["batch_tune_ms"])
+        assert all(v in (0, 1, 2, 3) for v in st_t[0]["batch_shapes"])
+        fixed, _ = S.spcg_solve_batched(c2, Xs, Ys, seed=5, batch_tasks_per_cu=4, batch_shape=1)
+    finally:
+        c2.close()
+    for q, a, b in zip(probs, tuned, fixed):
+        assert torch.equal(a, b), (q.N, q.d, q.k)
+
+
+def test_batched_one_launch_per_pass(S, ctx):
+    # every task of a pass in one launch of the widest row-width class (the
+    # comparison point for per-bucket launches): tasks are split over one
+    # launch instead of one per bucket, so the sums round differently, and
+    # every column still reaches its OLS estimator
+    probs = _uneven(n=6, seed=14)
+    Xs, Ys = [q.X for q in probs], [q.Y for q in probs]
+    got, st = S.spcg_solve_batched(ctx, Xs, Ys, seed=6, batch_one_launch=True, batch_tasks_per_cu=4)
+    used = [b for b, v in enumerate(st[0]["batch_shapes"]) if v]
+    assert used == [10], used   # class 4x8 (5), k bucket 0
+    for q, b, s in zip(probs, got, st):
+        assert s["converged"]
+        _check(q, b)
+
