@@ -81,7 +81,7 @@ DTYPE_NAME = {"f32": "f32", "bf16": "bf16", "fp8": "fp8e4m3", "f64": "f64"}
 # kernel classes of spcg_solve_stats.kernel_* (include/spcg.h SPCG_KT_*)
 KT_NAMES = ["transform_first_pass", "transform_last_pass", "product_S", "product_G", "product_SG",
             "phase_A", "phase_B"]
-KT_KERNELS = ["fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (first SRHT pass: gather X[p(k)], "
+KT_KERNELS = ["fwht_ring_kernel / fwht_stream_kernel / fwht_pass_kernel (first SRHT pass: gather X[p(k)], "
               "signs, first bits; writes Z)",
               "fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (last SRHT pass: remaining bits, "
               "scatter to S_K X and S_hat X)",
@@ -498,6 +498,12 @@ def bench_batched(args, spcg, workloads, torch, dev):
     total_bytes = sum(q.N * q.d * 4 for q in probs)
     log(f"{len(probs)} problems, {total_bytes / 1e9:.1f} GB of X, {sum(q.k for q in probs)} right-hand sides")
     ctx = spcg.Context(0)
+    # the context's first solve tunes the task granularity and the tile
+    # shape of every launch bucket (row-width class x k range)
+    _, st0 = spcg.spcg_solve_batched(ctx, Xs, Ys, betas=betas, method="spcg", seed=1)
+    tuned_shapes = {str(b): v for b, v in enumerate(st0[0]["batch_shapes"]) if v}
+    tune_ms = {f"{b // 4}:{b % 4 + 1}": round(v, 3) for b, v in enumerate(st0[0]["batch_tune_ms"]) if v > 0}
+    log(f"tuned: {st0[0]['batch_tasks_per_cu']} tasks per CU, shapes per bucket {tuned_shapes}")
     res = {}
     for method in ("spcg", "pcg"):
         def solve(time_products=False, time_phases=False, method=method):
@@ -542,6 +548,11 @@ def bench_batched(args, spcg, workloads, torch, dev):
                           ("t_sketch_ms", "t_precond_ms", "t_stage1_ms", "t_stage2_ms", "t_total_ms")}
                       for m in res},
         "roofline": rf, "cpu_baseline": None,
+        "autotune": {"tasks_per_cu": st0[0]["batch_tasks_per_cu"],
+                     "shape_per_bucket": tuned_shapes,
+                     "bucket_shape_ms": tune_ms,
+                     "buckets": "row-width class * 2 + (k > 8); classes 16x1 16x2 4x1 4x2 4x4 4x8 generic",
+                     "shapes": "1 three barriers per tile, 2 two-tile pipeline (3 slots), 3 pipeline (4 slots)"},
     }
 
 
