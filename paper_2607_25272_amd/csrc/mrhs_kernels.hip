@@ -224,19 +224,25 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
         const unsigned char* arow = T + li * PITCH;
         // the slab count is uniform per task: one loop body per count, so
         // the MFMA chains carry no per-instruction conditions
+        // every K group's A values first (their LDS reads in flight together;
+        // groups past d read group 0 and are not used), then the MFMA chains
+        float a4[KG][4];
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+            const int q = wave + NW * g;
+            lds_elem4<TS>(arow, 16 * (q < dt ? q : 0) + 4 * lg, a4[g]);
+        }
         auto run = [&](auto ns_c) __attribute__((always_inline)) {
             constexpr int NS = decltype(ns_c)::value;
 #pragma unroll
             for (int g = 0; g < KG; ++g) {
                 const int q = wave + NW * g;
                 if (q < dt) {
-                    float a4[4];
-                    lds_elem4<TS>(arow, 16 * q + 4 * lg, a4);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
 #pragma unroll
                         for (int sl = 0; sl < NS; ++sl)
-                            w1[sl] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[u], b1[sl][g][u], w1[sl], 0, 0, 0);
+                            w1[sl] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[g][u], b1[sl][g][u], w1[sl], 0, 0, 0);
                     }
                 }
             }
@@ -264,27 +270,46 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
     // l < 16 RPW: row RPW w + l / 16, right-hand side l mod 16) in a fixed
     // order, forms the residual there once, and publishes the second GEMM's
     // packed B operand
+    // Every partial is loaded before the sums (the LDS reads in flight
+    // together); lanes with cc >= k read valid LDS (packed columns < NM1 16)
+    // and write nothing.
     auto reduce = [&](int64_t tl, const unsigned char* T) __attribute__((always_inline)) {
         if (lane < 16 * RPW) {
             const int rr = RPW * wave + (lane >> 4), cc = lane & 15;
-            if (cc < k) {
-                const bool ok = task.r0 + tl * MT + rr < task.r1;
-                if constexpr (DO_S) {
-                    float t0 = 0.f;
+            const bool act = cc < k;
+            const bool ok = task.r0 + tl * MT + rr < task.r1;
+            if constexpr (DO_S) {
+                float pp[NW];
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) t0 += W1[0][w][rr][cc];
-                    W2[rr][cc] = ok ? t0 : 0.f;
+                for (int w = 0; w < NW; ++w) pp[w] = W1[0][w][rr][cc];
+                // every partial is in a register before the first add (the
+                // scheduler would otherwise wait out each read before the next)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) asm volatile("" : "+v"(pp[w]));
+                float t0 = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) t0 += pp[w];
+                if (act) W2[rr][cc] = ok ? t0 : 0.f;
+            }
+            if constexpr (DO_G) {
+                const int qh = (DO_S ? k : 0) + cc, ql = qh + k;
+                float ph[NW], pl[NW];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    ph[w] = W1[qh >> 4][w][rr][qh & 15];
+                    pl[w] = W1[ql >> 4][w][rr][ql & 15];
                 }
-                if constexpr (DO_G) {
-                    const int qh = (DO_S ? k : 0) + cc, ql = qh + k;
-                    float t1 = 0.f, tlo = 0.f;
+                const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[cc];
 #pragma unroll
-                    for (int w = 0; w < NW; ++w) {
-                        t1 += W1[qh >> 4][w][rr][qh & 15];
-                        tlo += W1[ql >> 4][w][rr][ql & 15];
-                    }
-                    const double bv = reinterpret_cast<const double*>(T + MT * PITCH + rr * 256)[cc];
-                    const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
+                for (int w = 0; w < NW; ++w) asm volatile("" : "+v"(ph[w]), "+v"(pl[w]));
+                float t1 = 0.f, tlo = 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    t1 += ph[w];
+                    tlo += pl[w];
+                }
+                const double res = ok ? (bv - (double)t1) - (double)tlo : 0.0;
+                if (act) {
                     W2[rr][(DO_S ? k : 0) + cc] = (float)res;
                     if (ok) {
                         r2 = fmaf((float)res, (float)res, r2);
@@ -304,6 +329,15 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
             b2[0][u] = W2[4 * lg + u][li];
             b2[1][u] = NM2 > 1 ? W2[4 * lg + u][16 + li] : 0.f;
         }
+        // the A^T values of every output tile first (tiles past d read tile
+        // 0 and are not used), then the MFMA chains
+        float av[MAXT][4];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+            const int mt = wave + NW * t;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[t][u] = lds_elem<TS>(T + (4 * lg + u) * PITCH, 16 * (mt < dt ? mt : 0) + li);
+        }
         auto run = [&](auto ns_c) __attribute__((always_inline)) {
             constexpr int NS = decltype(ns_c)::value;
 #pragma unroll
@@ -312,10 +346,9 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
                 if (mt < dt) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const float av = lds_elem<TS>(T + (4 * lg + u) * PITCH, 16 * mt + li);
 #pragma unroll
                         for (int sl = 0; sl < NS; ++sl)
-                            acc[sl][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b2[sl][u], acc[sl][t], 0, 0, 0);
+                            acc[sl][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][u], b2[sl][u], acc[sl][t], 0, 0, 0);
                     }
                 }
             }
