@@ -656,7 +656,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the row-sharded multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+              "(the path has no multi-GPU form)", file=sys.stderr)
         sys.exit(2)
 
     import torch

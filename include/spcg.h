@@ -361,8 +361,8 @@ typedef struct spcg_solve_opts {
  * first stopping test; s_hat = 10 * output 7.  Stage II then runs
  * max(0, round(s_hat) - margin) iterations without host synchronisation,
  * applies the stopping test once, and, if it fails, continues with the
- * plain test (the fallback) up to the budget T.  The result is always
- * judged by the same stopping test as the plain schedule. */
+ * plain test (the fallback) up to the budget T.  The result always
+ * passes the same stopping test as the plain schedule. */
 #define SPCG_SCHEDULE_PLAIN 0
 #define SPCG_SCHEDULE_LEARNED 1
 

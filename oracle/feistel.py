@@ -5,7 +5,7 @@ and a uniformly sampled row set I; the nested construction of Sec. 2.2 needs
 I_1 c I_2 c ... c I_K.  Both come from one keyed bijection pi of [0, 2^L):
 I_i = {pi(t) : t < m_i} is nested by construction and every prefix is a
 set of distinct rows.  The paper does not fix how the permutation is drawn;
-this build uses an alternating (unbalanced when L is odd) Feistel network of
+this implementation uses an alternating (unbalanced when L is odd) Feistel network of
 ``ROUNDS`` rounds whose round function is a Philox4x64-10 output word.
 
 Definition used by both the oracle and the library (each writes its own

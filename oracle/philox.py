@@ -3,7 +3,7 @@ easy as 1, 2, 3", SC'11, Sec. 3.2 and Table 2).
 
 The SRHT needs random signs, a random permutation and uniformly sampled row
 sets (Sec. 2.1 of the SPCG paper); the paper does not name a generator, so
-this build fixes the counter-based Philox4x64 with 10 rounds.  Test
+this implementation fixes the counter-based Philox4x64 with 10 rounds.  Test
 infrastructure: see ``oracle/__init__.py``.
 
 Two implementations are given:

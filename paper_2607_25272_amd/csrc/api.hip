@@ -1202,13 +1202,11 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
         if (!hp[p].active) continue;
         int c = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
         if (c < 0) return -1;
-        if (one_launch) {
-            // the 4-byte, 8-load class reads every row of a 4-byte multiple
-            // stride (and at most 2 KB of data)
-            const int es = dtype == DT_F32 ? 4 : 2;
-            const bool w4 = (hp[p].lda * es) % 4 == 0 && (uintptr_t)hp[p].A % 4 == 0;
-            c = w4 ? MR_CLASS_4x8 : MR_CLASS_GENERIC;
-        }
+        // one launch: the 4-byte, 8-load class reads every row that a
+        // direct-load class can (4-byte aligned, its 4-byte vectors within
+        // the readable part of the row: implied by either load width; at
+        // most 2 KB of data)
+        if (one_launch && c != MR_CLASS_GENERIC) c = MR_CLASS_4x8;
         bkt[p] = one_launch ? mrhs_bucket(c, 0) : mrhs_bucket(c, hp[p].k);
         bucket_rows[bkt[p]] += hp[p].m;
     }

@@ -1,4 +1,4 @@
-"""GPU checks of the schedule options of SURVEY's NEXT-2 row: explicit stage
+"""GPU checks of the schedule options: explicit stage
 sizes (the tuned schedule of Sec. 4.3: 2^10 ... 2^16, then one larger
 transition stage, a_i = 4) and the theory-driven stage counts of Theorems
 3.3 / 3.4.  Both must keep the stated stage structure and still reach the
@@ -84,7 +84,7 @@ def test_schedule_option_errors(S, ctx, prob):
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_nested_gradient_reuse(S, ctx, storage):
-    # stage starts from the previous stage's gradient plus a
+    # Nested-gradient reuse: stage starts from the previous stage's gradient plus a
     # G pass over the new prefix rows; same stage structure, same accuracy
     print(f"nested gradient {storage}", flush=True)
     p = workloads.gauss_colscale(1 << 17, 96, 1e4, 1.0, storage=storage, seed=41, device=DEV)

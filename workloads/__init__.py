@@ -9,9 +9,9 @@ tensors to the host for the oracle.
 
 Shapes follow the experiments of Sec. 4 of the SPCG paper (X = G D with G
 Gaussian and D a diagonal of column scales chosen for a target condition
-number, beta ~ N(0, I), zeta ~ N(0, sigma^2 I)) and the extended workloads
-listed in the design doc (Haar-SVD, Student-t rows with a correlation factor,
-batched problems, high-leverage rows).
+number, beta ~ N(0, I), zeta ~ N(0, sigma^2 I)) and extended workloads
+(Haar-SVD, Student-t rows with a correlation factor, batched problems,
+high-leverage rows).
 
 Stored precisions: float64, float32, bfloat16 (torch's round-to-nearest-
 even cast) and float8_e4m3fn with a per-column power-of-two scale
