@@ -113,10 +113,9 @@ typedef struct spcg_sketch_opts {
                                   stream 128- or 256-byte row segments through LDS
                                   in persistent blocks; the 11-bit passes of
                                   N' = 2^21 and 2^22 transforms work on tiles of
-                                  2048 rows x 128 bytes, the first pass staging
-                                  quarter tiles in a ring of two buffers, the last
-                                  half tiles); -32 or -64 stages quarter or half
-                                  tiles in both 11-bit passes; 64, 128 or 256
+                                  2048 rows x 128 bytes, staging quarter tiles in
+                                  a ring of two buffers); -32 selects the same,
+                                  -64 stages half tiles instead; 64, 128 or 256
                                   selects one tile per block with at most that
                                   many bytes per row segment.  Any other value is
                                   SPCG_E_INVALID_ARG.  Results are bit-identical

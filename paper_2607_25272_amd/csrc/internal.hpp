@@ -57,7 +57,7 @@ struct FwhtJob {
     int b_bf16;               // 1: store the B rows as BF16 (round to nearest even)
     int seg_bytes;            // 0: default column segment; 64 / 128 / 256: at most this
                               // (one tile per block); -32 / -64: quarter- / half-tile
-                              // staging in both 11-bit passes
+                              // staging in the 11-bit passes (0: quarter tiles)
     int stream;               // 1: 10- and 11-bit FP32-precision passes use the streaming
                               // kernel (persistent blocks, next tile prefetched)
     int num_cu;               // compute units (grid of the streaming kernel)

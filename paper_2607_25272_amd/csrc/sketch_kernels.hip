@@ -1031,13 +1031,20 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
         // wait; the stores below drain during the next tile
         __builtin_amdgcn_s_waitcnt(stream_vmcnt0());
         if constexpr (LAST) __syncthreads();   // the slot pairs are visible
-        // one row at a time: the opaque lane copy keeps the compiler from
-        // computing all sixteen 64-bit store addresses up front
+        // the sixteen slot pairs are read together (one LDS round trip, not
+        // one per row), then one row at a time: the opaque lane copy keeps
+        // the compiler from computing all sixteen 64-bit store addresses up
+        // front
         if constexpr (LAST) {
+            int2 prs[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) prs[t] = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+#pragma unroll
+            for (int t = 0; t < R; ++t) asm volatile("" : "+v"(prs[t].x), "+v"(prs[t].y));
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 asm volatile("" : "+v"(lx));
-                const int2 pr = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+                const int2 pr = prs[t];
                 const int64_t col0 = tl.cbase + (lx & 7) * VL;
                 if (pr.x >= 0) {
                     if (a.b_bf16) {
@@ -1073,9 +1080,14 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
 // through stages 0..6, and no phase waits for the loads it has just issued
 // (same register layout, butterflies, exchange and stores; bit-identical).
 // Its waits are explicit vmcnt(NIQ) counts and its barriers wait for LDS
-// only, so the compiler adds no vmcnt(0): the quarter buffers are separate
-// LDS objects, table entries and column scales are loaded a phase ahead
-// before a quarter's direct loads, and the stores are global, not flat.
+// only, so the compiler adds no vmcnt(0) in the loop (but one before the
+// last pass's exchange): the quarter buffers are separate LDS objects,
+// table entries and column scales are loaded a phase ahead before a
+// quarter's direct loads, and the stores are global, not flat.  The last
+// pass issues the next tile's quarter 1 after its exchange, which then
+// runs through that free 64 KB quarter buffer in four rounds with every
+// lane (eight rounds of half the lanes through the 32 KB buffer
+// otherwise).
 template <typename TIN, bool FIRST, bool LAST, int DW>
 __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
     constexpr int CW = 32, VL = 4, R = 16, THREADS = SPLIT_THREADS;
@@ -1089,6 +1101,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
     constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;
     static_assert(NIQ >= 1 && NIQ * THREADS * DW == QS && !(FIRST && LAST) && (DW == 16 || (FIRST && DW == 4)),
                   "ring tile shape");
+    static_assert(!LAST || QS >= (HALF * 2) * LPR * 4, "the last pass exchanges through a quarter buffer");
     // s_waitcnt vmcnt(n): all but the last n vector-memory loads have completed
     constexpr int VM_NIQ = (NIQ & 0xf) | (((NIQ >> 4) & 3) << 14) | (0x7 << 4) | (0xf << 8);
     // two quarter buffers, separate LDS objects (the compiler's waits for
@@ -1319,6 +1332,26 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
             }
         }
     };
+    // the same exchange through a 64 KB buffer (a free quarter buffer of
+    // FP32 rows): row bit 2 (lane bit 5) picks its half, so every lane takes
+    // part in each of four rounds instead of half the lanes in eight
+    auto exchange_wide = [&](int lx, float* xb) __attribute__((always_inline)) {
+        const int lrx = lx & 7, x3 = (lx >> 3) & 1, x4 = (lx >> 4) & 1, x5 = lx >> 5;
+        const int wbase = ((x4 | x3 << 1 | wave << 6) << 3) + lrx + (x5 << 13);
+        const int rbase = ((x4 | x3 << 1 | wave << 2) << 3) + lrx + (x5 << 13);
+#pragma unroll
+        for (int e = 0; e < VL; ++e) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int off = ((t & 1) << 2 | ((t >> 1) & 1) << 3 | ((t >> 3) & 1) << 4 | ((t >> 2) & 1) << 5) << 3;
+                xb[wbase + off] = v[t][e];
+            }
+            lds_barrier();
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t][e] = xb[rbase + (t << 9)];
+            lds_barrier();
+        }
+    };
 
     // completes every pending butterfly before this point (the scheduler
     // would otherwise sink the last stages into the store loop and keep
@@ -1403,7 +1436,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
                 }
             }
             // (the last pass issues quarter 1 of the next tile in phase C,
-            // after the slot pairs)
+            // after the exchange through its buffer)
             if (!(LAST && q == 3)) issue_quarter(q < 2 || !has_next ? tl : tn, (q + 2) & 3, qbuf, dpi, lx);
             if (myq == q) {
                 bfly(0, 4);
@@ -1414,17 +1447,21 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
         }
         // ---- C: stages 7..10 and the stores
         asm volatile("" : "+v"(lx));
-        exchange(lx);
         if constexpr (LAST) {
-            // the output slots of this tile's rows (contiguous in slot_pairs)
-            // into the free exchange buffer, then quarter 1 of the next tile
-            // into its free buffer, so that one vmcnt(NIQ) below covers the
-            // slot pairs and leaves that quarter in flight
+            // quarter buffer 1 is free here (quarter 1 of the next tile is
+            // issued after the exchange): four rounds through it; then the
+            // output slots of this tile's rows (contiguous in slot_pairs)
+            // into the exchange buffer, and quarter 1, so that one
+            // vmcnt(NIQ) below covers the slot pairs and leaves that quarter
+            // in flight
+            exchange_wide(lx, reinterpret_cast<float*>(stg1));
             asm volatile("" : "+v"(lx));
             const int2* src = a.slot_pairs + ((tl.rowbase & ((1ll << lo) - 1)) << NB) + (wave * 64 + lx) * 2;
             stream_lds_load16(src, reinterpret_cast<unsigned char*>(exb) + wave * 1024);
             asm volatile("" : "+v"(lx));
             issue_quarter(has_next ? tn : tl, 1, stg1, 0, lx);
+        } else {
+            exchange(lx);
         }
         bfly(0, 4);
         settle();
@@ -1433,13 +1470,20 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
         // during the next tile
         __builtin_amdgcn_s_waitcnt(VM_NIQ);
         if constexpr (LAST) lds_barrier();   // the slot pairs are visible
-        // one row at a time: the opaque lane copy keeps the compiler from
-        // computing all sixteen 64-bit store addresses up front
+        // the sixteen slot pairs are read together (one LDS round trip, not
+        // one per row), then one row at a time: the opaque lane copy keeps
+        // the compiler from computing all sixteen 64-bit store addresses up
+        // front
         if constexpr (LAST) {
+            int2 prs[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) prs[t] = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+#pragma unroll
+            for (int t = 0; t < R; ++t) asm volatile("" : "+v"(prs[t].x), "+v"(prs[t].y));
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 asm volatile("" : "+v"(lx));
-                const int2 pr = reinterpret_cast<const int2*>(exb)[final_row(t, lx)];
+                const int2 pr = prs[t];
                 const int64_t col0 = tl.cbase + (lx & 7) * VL;
                 if (pr.x >= 0) {
                     if (a.b_bf16) {
@@ -1654,10 +1698,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             if (e != hipSuccess) return e;
         }
         if constexpr (std::is_same<TZ, float>::value) {
-            // 11-bit passes of 128-byte row segments: the first stages
-            // quarter tiles in a ring, the last half tiles (measured the
-            // faster pair at N' = 2^22); seg_bytes -32 / -64 select quarter /
-            // half tiles for both
+            // 11-bit passes of 128-byte row segments stage quarter tiles in
+            // a ring (seg_bytes -64: half tiles)
             if (nb == NB_MAX && job.stream && job.num_cu > 0 &&
                 (first ? (split & 1) && (xdma || xdma4) && job.row_masks : (split & 2) && job.slot_pairs)) {
                 a.lo = lo;
@@ -1668,7 +1710,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const bool ring = job.seg_bytes == -32 || (job.seg_bytes == 0 && first);
+                const bool ring = job.seg_bytes != -64;
                 const hipError_t e = ring ? launch_ring<TIN>(st, a, grid, first, last, first && !xdma)
                                           : launch_split<TIN>(st, a, grid, first, last, first && !xdma);
                 if (e != hipSuccess) return e;

@@ -226,9 +226,9 @@ def test_sketch_split_eleven_bit_passes_match_tiled(S, ctx, storage, N, d):
     # (11 + 11 bits, both passes; d = 37: rows of X are not 16-byte aligned,
     # so only the last pass) and N' = 2^21 (the 11-bit first pass, then a
     # streamed 10-bit pass).  FP8 rows of 44 bytes are staged with 4-byte
-    # direct loads.  transform_segment = 256 runs one tile per block, -32
-    # and -64 quarter- and half-tile staging in both passes (the default
-    # mixes them).  Same butterflies in the same order -> identical bits.
+    # direct loads.  transform_segment = 256 runs one tile per block, -64
+    # half-tile staging (the default and -32: the quarter-tile ring).  Same
+    # butterflies in the same order -> identical bits.
     _log(f"sketch split 11-bit {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 79)
     rows = []
