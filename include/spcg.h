@@ -311,6 +311,8 @@ typedef struct spcg_solve_opts {
                                  (the sketches are nested prefixes, Sec. 2.2), so each
                                  stage-start pass reads m_i - m_prev rows instead of m_i.
                                  Ignored for a CountSketch (its stages are not prefixes).
+                                 Single, multi-RHS and batched solves alike (batched:
+                                 per problem that ran the previous stage).
                                  spcg_solve_opts_default sets 1. */
     double omega;             /* SPCG_A_THEORY: the stagewise accuracy factor (0: 0.5) */
     int32_t stage_limit;      /* plain schedule: run only the first stage_limit of the

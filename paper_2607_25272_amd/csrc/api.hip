@@ -1092,6 +1092,7 @@ struct BatchWork {
     std::vector<spcg_sketch_t*> sk;
     std::vector<spcg_precond_t*> pc;
     DevBuf vecs, scal, probs, tasks, part_s, part_g, part_scal, bestx;
+    DevBuf probs2, tasks2;   // a second task list (the nested stage starts' G pass)
     DevBuf rpart;   // per problem: the z slices' shares of g^T z
     // one stream per launch bucket (row-width class x k range: the bucket
     // launches of a pass run concurrently), a private stream for graph
@@ -1241,7 +1242,10 @@ struct BatchPlan {
     int seg[MR_NBUCKET + 1] = {};
     int shape[MR_NBUCKET] = {};   // tile shape of each bucket's launch
     bool one_launch = false;
+    int set = 0;   // 0: the task and problem buffers tasks / probs, 1: tasks2 / probs2
 };
+DevBuf& plan_tasks(BatchWork& W, const BatchPlan& plan) { return plan.set ? W.tasks2 : W.tasks; }
+DevBuf& plan_probs(BatchWork& W, const BatchPlan& plan) { return plan.set ? W.probs2 : W.probs; }
 
 // tile shape of every bucket: forced (> 0), else the context's tuned one,
 // else the two-tile pipeline with 3 slots
@@ -1263,15 +1267,17 @@ int batched_setup(spcg_ctx* ctx, BatchWork& W, int dtype, const std::vector<Mrhs
     plan.nt = nt;
     plan.nprob = (int)probs.size();
     const size_t per_task = (size_t)mrhs_max_d() * mrhs_max_k();
-    HIP_TRY(ctx, W.tasks.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
-    HIP_TRY(ctx, W.probs.ensure(probs.size() * sizeof(MrhsProblem)));
+    DevBuf& tbuf = plan_tasks(W, plan);
+    DevBuf& pbuf = plan_probs(W, plan);
+    HIP_TRY(ctx, tbuf.ensure(std::max<size_t>(1, tasks.size()) * sizeof(MrhsTask)));
+    HIP_TRY(ctx, pbuf.ensure(probs.size() * sizeof(MrhsProblem)));
     HIP_TRY(ctx, W.part_s.ensure((size_t)std::max(nt, 1) * per_task * 4));
     HIP_TRY(ctx, W.part_g.ensure((size_t)std::max(nt, 1) * per_task * 4));
     HIP_TRY(ctx, W.part_scal.ensure((size_t)std::max(nt, 1) * 2 * mrhs_max_k() * 4));
     hipStream_t st = ctx->stream;
     if (nt)
-        HIP_TRY(ctx, hipMemcpyAsync(W.tasks.p, tasks.data(), tasks.size() * sizeof(MrhsTask), hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(W.probs.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
+        HIP_TRY(ctx, hipMemcpyAsync(tbuf.p, tasks.data(), tasks.size() * sizeof(MrhsTask), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(pbuf.p, probs.data(), probs.size() * sizeof(MrhsProblem), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     return SPCG_OK;
 }
@@ -1294,9 +1300,9 @@ int batched_products(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int dtype, int
             sc = W.cls[c];
             HIP_TRY(ctx, hipStreamWaitEvent(sc, W.fork, 0));
         }
-        HIP_TRY(ctx, run_mrhs_product(sc, dtype, mode, c / MR_KB, plan.shape[c], W.tasks.as<MrhsTask>(), plan.seg[c],
-                                      n, W.probs.as<MrhsProblem>(), W.part_s.as<float>(), W.part_g.as<float>(),
-                                      W.part_scal.as<float>()));
+        HIP_TRY(ctx, run_mrhs_product(sc, dtype, mode, c / MR_KB, plan.shape[c], plan_tasks(W, plan).as<MrhsTask>(),
+                                      plan.seg[c], n, plan_probs(W, plan).as<MrhsProblem>(), W.part_s.as<float>(),
+                                      W.part_g.as<float>(), W.part_scal.as<float>()));
         if (used > 1) {
             HIP_TRY(ctx, hipEventRecord(W.join[c], sc));
             HIP_TRY(ctx, hipStreamWaitEvent(st, W.join[c], 0));
@@ -1306,7 +1312,7 @@ int batched_products(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int dtype, int
 }
 
 int batched_dspace(spcg_ctx* ctx, BatchWork& W, hipStream_t st, int variant, const BatchPlan& plan) {
-    HIP_TRY(ctx, run_mrhs_dspace(st, variant, W.probs.as<MrhsProblem>(), plan.nprob, W.part_s.as<float>(),
+    HIP_TRY(ctx, run_mrhs_dspace(st, variant, plan_probs(W, plan).as<MrhsProblem>(), plan.nprob, W.part_s.as<float>(),
                                  W.part_g.as<float>(), W.part_scal.as<float>()));
     return SPCG_OK;
 }
@@ -1510,7 +1516,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     W.gcache_busy = graphs_on;
     std::vector<int> t1(nprob, 0), t2(nprob, 0), conv(nprob, 0);
     // Stage I: stage i of every problem that has one; its G pass and a_i S
-    // passes form one graph
+    // passes form one graph.  Nested SRHT prefixes: a problem that ran
+    // stage i - 1 starts stage i from its previous gradient plus a G pass
+    // over the new prefix rows only (as the single-problem path does).
+    std::vector<char> ran_prev(nprob, 0);
     for (int64_t i = 0; i < maxK; ++i) {
         int ai = a;
         if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
@@ -1530,6 +1539,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             q.b = static_cast<const double*>(b.data);
             q.ldb = b.ld;
             q.c2 = c2;
+            q.gscale = 0.0;
         }
         if (!any) continue;
         // stage rows: every problem's sketch has the same element type
@@ -1538,10 +1548,39 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         plan.one_launch = opts->batch_one_launch != 0;
         if ((rc = batched_setup(ctx, W, sdt, hp, target_tasks, plan)) != SPCG_OK) return rc;
         plan_shapes(W, sdt, opts->batch_shape, plan);
+        // the starting G pass: over the new prefix rows [m_{i-1}, m_i) of the
+        // problems that can reuse their gradient, over all rows otherwise
+        BatchPlan gplan;
+        bool nested = false;
+        if (opts->nested_gradient && i > 0) {
+            std::vector<MrhsProblem> hg = hp;
+            for (int p = 0; p < nprob; ++p) {
+                MrhsProblem& g = hg[p];
+                if (!g.active || !ran_prev[p] || W.sk[p]->kind != SPCG_SKETCH_SRHT) continue;
+                const int64_t mprev = W.sk[p]->m[i - 1];
+                if (mprev <= 0 || mprev >= g.m) continue;
+                g.A = static_cast<const char*>(g.A) + (size_t)mprev * g.lda * dtype_bytes(sdt);
+                g.b += (size_t)mprev * g.ldb;
+                g.m -= mprev;
+                g.gscale = (double)mprev / (double)hp[p].m;
+                nested = true;
+            }
+            if (nested) {
+                gplan.set = 1;
+                gplan.one_launch = plan.one_launch;
+                if ((rc = batched_setup(ctx, W, sdt, hg, target_tasks, gplan)) != SPCG_OK) return rc;
+                plan_shapes(W, sdt, opts->batch_shape, gplan);
+            }
+        }
         auto stage = [&](hipStream_t s) -> int {
             int r;
-            if ((r = batched_products(ctx, W, s, sdt, PM_G, plan)) != SPCG_OK) return r;
-            if ((r = batched_dspace(ctx, W, s, PA_START, plan)) != SPCG_OK) return r;
+            if (nested) {
+                if ((r = batched_products(ctx, W, s, sdt, PM_G, gplan)) != SPCG_OK) return r;
+                if ((r = batched_dspace(ctx, W, s, PA_START_NESTED, gplan)) != SPCG_OK) return r;
+            } else {
+                if ((r = batched_products(ctx, W, s, sdt, PM_G, plan)) != SPCG_OK) return r;
+                if ((r = batched_dspace(ctx, W, s, PA_START, plan)) != SPCG_OK) return r;
+            }
             for (int it = 0; it < ai; ++it) {
                 if ((r = batched_products(ctx, W, s, sdt, PM_S, plan)) != SPCG_OK) return r;
                 if ((r = batched_dspace(ctx, W, s, PA_STEP, plan)) != SPCG_OK) return r;
@@ -1549,8 +1588,10 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
             return SPCG_OK;
         };
         if ((rc = run_captured(ctx, W, graphs_on, stage, (int)i, &graphs_launched)) != SPCG_OK) return rc;
-        for (int p = 0; p < nprob; ++p)
+        for (int p = 0; p < nprob; ++p) {
             if (hp[p].active) t1[p] += ai;
+            ran_prev[p] = hp[p].active ? 1 : 0;
+        }
     }
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[3], st));
     // Stage II on the full data; every problem stops on its own test

@@ -236,6 +236,7 @@ struct MrhsProblem {
     const double* Minv;     // d x d
     MrhsScalars* sc;        // k entries
     double* rho_part;       // per 128-row slice of z, 16 shares of g^T z
+    double gscale;          // PA_START_NESTED: weight of the previous gradient (0: plain start)
     int t0, t1;             // tasks of this problem in the current launch
     int active;             // 0: skip (converged or no stage)
 };
@@ -273,6 +274,8 @@ hipError_t run_mrhs_product(hipStream_t st, int dtype, int mode, int cls, int sh
 // partial sums, alpha and the x, g updates (one block per problem); z = M g
 // in 128-row slices (one block per slice and problem); rho and p (one block
 // per problem).  variant: PA_START (g, z, p, rho from the G partials),
+// PA_START_NESTED (the same from g = gscale g + c2 (partials of the new
+// prefix rows), per problem; gscale 0: PA_START),
 // PA_STEP, PA_REFRESH.
 hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs, int nprob,
                            const float* part_s, const float* part_g, const float* part_scal);

@@ -795,7 +795,9 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
     if (!pb.active) return;
     const int d = pb.d, k = pb.k;
     const int64_t ldv = pb.ldv;
-    const bool want_s = variant != PA_START, want_g = variant != PA_STEP;
+    // PA_START_NESTED starts like PA_START, from g = gscale g + c2 (partials)
+    const bool start = variant == PA_START || variant == PA_START_NESTED;
+    const bool want_s = !start, want_g = variant != PA_STEP;
     // 1. reduce the task partials, each element in task order.  The task
     //    loop is outside: per task, EQ elements per thread have their loads
     //    in flight together (element-by-element it would wait out one load
@@ -824,8 +826,11 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
                 if (e >= ne) continue;
                 const int j = e / KP, c = e % KP;
                 if (c >= k) continue;
-                if (variant == PA_START) pb.G[c * ldv + j] = gg[q] * pb.c2;
-                else {
+                if (start) {
+                    const int64_t o = c * ldv + j;
+                    pb.G[o] = variant == PA_START_NESTED && pb.gscale != 0.0 ? fma(pb.gscale, pb.G[o], gg[q] * pb.c2)
+                                                                           : gg[q] * pb.c2;
+                } else {
                     pb.S[c * ldv + j] = ss[q] * pb.c2;
                     if (variant == PA_REFRESH) pb.Gt[c * ldv + j] = gg[q] * pb.c2;
                 }
@@ -848,7 +853,7 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
         pb.sc[threadIdx.x].ax2 = colw[threadIdx.x];
     }
     // 2. step: alpha = rho / p^T s; x += alpha p; g = (g or g_true) - alpha s
-    if (variant != PA_START) {
+    if (!start) {
         colwise_dot(pb.P, pb.S, ldv, d, k, colv, red);
         if (threadIdx.x < KP) {
             const int c = threadIdx.x;
@@ -982,11 +987,12 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_p_kernel(int variant, 
             double rn = 0.0;
             for (int sl = 0; sl < nsl; ++sl) rn += pb.rho_part[sl * KP + c];
             MrhsScalars& sc = pb.sc[c];
-            const bool skip = sc.breakdown || (variant != PA_START && sc.exact);
+            const bool start = variant == PA_START || variant == PA_START_NESTED;
+            const bool skip = sc.breakdown || (!start && sc.exact);
             if (!skip) {
                 if (!dfinite(rn)) {
                     sc.breakdown = 1;
-                } else if (variant == PA_START) {
+                } else if (start) {
                     sc.rho = rn;
                     sc.rho0 = rn;
                     sc.exact = rn == 0.0;

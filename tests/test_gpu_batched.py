@@ -216,3 +216,20 @@ def test_batched_one_launch_per_pass(S, ctx):
         assert s["converged"]
         _check(q, b)
 
+
+
+def test_batched_nested_gradient_start(S, ctx):
+    # Stage I stages after the first start from the previous stage's
+    # gradient plus a G pass over the new prefix rows (nested SRHT sketches,
+    # Sec. 2.2): the same stage structure as the direct start, Stage II
+    # counts within one, every column at its OLS estimator
+    probs = _uneven(n=6, seed=15)
+    Xs, Ys = [q.X for q in probs], [q.Y for q in probs]
+    nest, st_n = S.spcg_solve_batched(ctx, Xs, Ys, seed=7, batch_tasks_per_cu=4)
+    direct, st_d = S.spcg_solve_batched(ctx, Xs, Ys, seed=7, batch_tasks_per_cu=4, nested_gradient=False)
+    for q, b1, b2, s1, s2 in zip(probs, nest, direct, st_n, st_d):
+        assert s1["converged"] and s2["converged"]
+        assert s1["K"] == s2["K"] and s1["T_stage1"] == s2["T_stage1"]
+        assert abs(s1["T_stage2"] - s2["T_stage2"]) <= 1, (s1["T_stage2"], s2["T_stage2"])
+        _check(q, b1)
+        _check(q, b2)
