@@ -460,7 +460,7 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     }
     const int64_t mK = sk->K ? sk->m[sk->K - 1] : 0;
     const size_t es = sk->dtype == DT_F64 ? 8 : 4;
-    sk->ldy = sk->k == 1 ? 1 : round_up(sk->k, fwht_chunk_cols(DT_F64, 0));
+    sk->ldy = sketch_ldy(sk->k);
     sk->owns = !borrow;
     DevBuf& bB = borrow ? ctx->wsB : sk->B;
     DevBuf& bBY = borrow ? ctx->wsBY : sk->BY;
@@ -578,6 +578,8 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
         jy.B = sk->pBY;
         jy.ldb = sk->ldy;
         jy.narrow = sk->k == 1;
+        // rows of 8 or 16 columns: the tiled passes take that segment width
+        jy.seg_bytes = sk->ldy > 1 && sk->ldy < 32 ? (int)sk->ldy * 8 : 0;
         if (defer_y) {
             HIP_TRY(ctx, hipEventRecord(ctx->ev_side_fork, st));
             HIP_TRY(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_side_fork, 0));

@@ -84,6 +84,10 @@ inline int fwht_chunk_cols(int in_dtype, int narrow) {
 }
 // Row padding of the stored sketch rows (multiple of every chunk width).
 inline int64_t sketch_ld(int64_t d, bool f64) { return round_up(d, f64 ? 32 : 64); }
+// Row stride of the FP64 sketched responses and of their transform scratch:
+// one column, 8 or 16 columns (64- or 128-byte row segments) for up to 8 or
+// 16 right-hand sides, else a multiple of the 32-column chunk.
+inline int64_t sketch_ldy(int64_t k) { return k == 1 ? 1 : k <= 8 ? 8 : k <= 16 ? 16 : round_up(k, 32); }
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job);
 // Number of passes run_fwht makes over an N' = 2^L row transform.
 int fwht_passes(int L);

@@ -466,7 +466,12 @@ struct StageRead<fp8_t> {
     }
 };
 
-template <typename TIN, int CW, bool FIRST, bool LAST>
+// DW: bytes per direct load, 16, or 4 for a first pass over rows whose
+// stride is a multiple of 4 but not of 16 bytes (then each wave's loads
+// cover RW consecutive staging rows, whose permutation entries its lanes
+// hold, NE per lane, and each load takes its row's entry by a cross-lane
+// permute)
+template <typename TIN, int CW, bool FIRST, bool LAST, int DW = 16>
 __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a) {
     constexpr int VL = 4, Q = 4, R = 16, THREADS = STREAM_THREADS;
     constexpr int LPR = CW / VL;
@@ -477,11 +482,18 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     constexpr int IB = (int)sizeof(TI);
     constexpr int ROWB = CW * IB;               // staged bytes per tile row
     constexpr int STG = ROWS * ROWB;
-    constexpr int NI = STG / (THREADS * 16);    // direct loads per thread per tile
+    constexpr int NI = STG / (THREADS * DW);    // direct loads per thread per tile
+    constexpr int RW = NI * 64 * DW / ROWB;     // staging rows one wave's loads cover
+    constexpr int NE = DW == 4 ? RW / 64 : 0;   // permutation entries per lane (4-byte loads)
     constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;   // staging row swizzle
     constexpr int XM = 64 / LPR - 1;                       // exchange row swizzle
     static_assert(ROWS == (1 << NB) && !(FIRST && LAST), "stream tile shape");
-    static_assert(ROWB >= 16 && NI >= 1 && NI * THREADS * 16 == STG && SM < 16 && XM < 16, "staging");
+    static_assert(ROWB >= 16 && NI >= 1 && NI * THREADS * DW == STG && SM < 16 && XM < 16, "staging");
+    // (a 4-byte load covers 64 DW / ROWB consecutive rows, aligned to their
+    // count, and the swizzle keeps rows in their 16-row group, so all lanes
+    // of a load take the entry from the same register)
+    static_assert(DW == 16 || (FIRST && DW == 4 && NE >= 1 && NE <= 2 && NE * 64 == RW && 64 * DW / ROWB <= 16),
+                  "4-byte staging");
     // two separate LDS objects: the compiler then knows that exchange
     // traffic does not touch the buffer the direct loads are filling
     __shared__ __align__(16) unsigned char stg[STG];
@@ -539,22 +551,29 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
         const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
         return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
     };
-    // tile row and 16-byte piece that direct load i of this lane fetches
+    // tile row and DW-byte piece that direct load i of this lane fetches
     auto dma_slot = [&](int i, int& row, int& piece) {
-        const int P = ((wave * NI + i) * 64 + lane) * 16;
+        const int P = ((wave * NI + i) * 64 + lane) * DW;
         row = srow(P / ROWB);
-        piece = (P % ROWB) / 16;
+        piece = (P % ROWB) / DW;
     };
 
-    int32_t dp[NI];   // first pass: permutation entries of the rows this lane stages next
+    // first pass: permutation entries of the rows this lane stages next (16-
+    // byte loads: one per load; 4-byte loads: rows wave RW + e 64 + lane)
+    int32_t dp[DW == 16 ? NI : NE];
     int32_t cp[R];    // first pass: permutation entries of this thread's rows
     auto load_dperm = [&](int64_t j) __attribute__((always_inline)) {
         const Tile tl = tile_of(j);
+        if constexpr (DW == 16) {
 #pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            int row, piece;
-            dma_slot(i, row, piece);
-            dp[i] = a.perm_sign[grow(tl, row)];
+            for (int i = 0; i < NI; ++i) {
+                int row, piece;
+                dma_slot(i, row, piece);
+                dp[i] = a.perm_sign[grow(tl, row)];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) dp[e] = a.perm_sign[grow(tl, wave * RW + e * 64 + lane)];
         }
     };
     auto load_cperm = [&](int64_t j) __attribute__((always_inline)) {
@@ -564,23 +583,63 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     };
     auto issue_stage = [&](int64_t j) __attribute__((always_inline)) {
         const Tile tl = tile_of(j);
-        unsigned char* dst = stg + wave * NI * 1024;
+        unsigned char* dst = stg + wave * NI * 64 * DW;
+        if constexpr (DW == 16) {
 #pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            int row, piece;
-            dma_slot(i, row, piece);
-            const int64_t col = tl.cbase + piece * (16 / IB);
-            const unsigned char* src;
-            if constexpr (FIRST) {
-                // rows past N and pieces past d read row 0 instead; the
-                // reader zeroes them
-                const int64_t sr = (int64_t)(dp[i] & 0x7fffffff);
-                const bool ok = sr < a.N && col < a.d;
-                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
-            } else {
-                src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, row), col) * 4;
+            for (int i = 0; i < NI; ++i) {
+                int row, piece;
+                dma_slot(i, row, piece);
+                const int64_t col = tl.cbase + piece * (16 / IB);
+                const unsigned char* src;
+                if constexpr (FIRST) {
+                    // rows past N and pieces past d read row 0 instead; the
+                    // reader zeroes them
+                    const int64_t sr = (int64_t)(dp[i] & 0x7fffffff);
+                    const bool ok = sr < a.N && col < a.d;
+                    src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+                } else {
+                    src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, row), col) * 4;
+                }
+                stream_lds_load16(src, dst + i * 1024);
             }
-            stream_lds_load16(src, dst + i * 1024);
+        } else {
+            // 4-byte loads, in groups of G: the group's permutation entries
+            // are fetched from the lanes that hold them first, then its loads
+            // are issued (one wait per group). The row and permute offsets
+            // come from a lane index the compiler cannot see through, so that
+            // it recomputes them per tile instead of holding all of them
+            // live across the tile loop (which spills).
+            constexpr int G = 8;
+            static_assert(NI % G == 0, "4-byte load groups");
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+#pragma unroll
+            for (int g = 0; g < NI; g += G) {
+                int32_t pe[G];
+                int piece[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int P = ((wave * NI + g + u) * 64 + ln) * DW;
+                    const int row = srow(P / ROWB);
+                    piece[u] = (P % ROWB) / DW;
+                    // the row lies in this wave's [wave RW, wave RW + RW) (the
+                    // staging swizzle stays inside a 16-row group): entry
+                    // (row - wave RW) / 64 of lane (row - wave RW) mod 64
+                    const int local = row - wave * RW;
+                    pe[u] = __builtin_amdgcn_ds_bpermute((local & 63) << 2, (local >> 6) == 0 ? dp[0] : dp[NE - 1]);
+                }
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int64_t col = tl.cbase + piece[u] * (DW / IB);
+                    // rows past N and pieces past d read row 0 instead; the
+                    // reader zeroes them
+                    const int64_t sr = (int64_t)(pe[u] & 0x7fffffff);
+                    const bool ok = sr < a.N && col < a.d;
+                    stream_lds_load4(static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0),
+                                     dst + (g + u) * 256);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     };
 
@@ -1567,9 +1626,9 @@ hipError_t launch_any(hipStream_t st, const PassArgs& a, bool first, bool last) 
     return launch_pass<TIN, TZ, CW, false, false>(st, a);
 }
 
-template <typename TIN, int CW, bool FIRST, bool LAST>
+template <typename TIN, int CW, bool FIRST, bool LAST, int DW = 16>
 hipError_t launch_stream_one(hipStream_t st, const PassArgs& a, int64_t grid) {
-    auto fn = fwht_stream_kernel<TIN, CW, FIRST, LAST>;
+    auto fn = fwht_stream_kernel<TIN, CW, FIRST, LAST, DW>;
     fn<<<dim3((unsigned)grid), dim3(STREAM_THREADS), 0, st>>>(a);
     return hipGetLastError();
 }
@@ -1610,9 +1669,12 @@ hipError_t launch_ring(hipStream_t st, const PassArgs& a, int64_t grid, bool fir
     return hipGetLastError();
 }
 
+// dw4: the first pass stages rows of X with 4-byte direct loads (rows whose
+// stride is a multiple of 4 but not of 16 bytes)
 template <typename TIN, int CW>
-hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last) {
+hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
     if (first && last) return hipErrorInvalidValue;
+    if (first && dw4) return launch_stream_one<TIN, CW, true, false, 4>(st, a, grid);
     if (first) return launch_stream_one<TIN, CW, true, false>(st, a, grid);
     if (last) return launch_stream_one<TIN, CW, false, true>(st, a, grid);
     return launch_stream_one<TIN, CW, false, false>(st, a, grid);
@@ -1651,6 +1713,9 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
     // FP8 rows of a length that is a multiple of 4 bytes (4-byte direct loads)
     const bool xdma4 = std::is_same<TIN, fp8_t>::value && (uintptr_t)job.x % 4 == 0 && job.ldx % 4 == 0;
+    // rows of any type whose stride is a multiple of 4 bytes (the streaming
+    // first pass with 4-byte direct loads)
+    const bool xdma4s = (uintptr_t)job.x % 4 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 4 == 0;
     const int split = fwht_split_tables(job.in_dtype, L, job.ldz, job.seg_bytes);
     // column width of the streaming kernel for a pass (0: one tile per block).
     // 11-bit passes would need 64-byte rows (CW = 16); with chunk-major Z the
@@ -1662,7 +1727,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
         // for 8 bits would spill registers in the first pass
         const int scw = nb == 10 ? 32 : nb == 9 ? 64 : 0;
         if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes > 0 || job.ldz % scw != 0 ||
-            (first && !xdma))
+            (first && !xdma && !xdma4s))
             return 0;
         return scw;
     };
@@ -1731,8 +1796,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last)
-                                               : launch_stream<TIN, 64>(st, a, grid, first, last);
+                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last, first && !xdma)
+                                               : launch_stream<TIN, 64>(st, a, grid, first, last, first && !xdma);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);
@@ -1847,8 +1912,11 @@ int fwht_split_tables(int in_dtype, int L, int64_t ldz, int seg_bytes) {
 }
 
 hipError_t run_fwht(hipStream_t st, const FwhtJob& job) {
-    const int cw = fwht_chunk_cols(job.in_dtype, job.narrow);
-    if (job.ldz % cw != 0 || (job.B && job.ldb != job.ldz) || (job.Bh && job.ldbh != job.ldz) ||
+    // a row segment narrower than the default chunk (seg_bytes > 0) only
+    // needs rows that are a multiple of it
+    int cw = fwht_chunk_cols(job.in_dtype, job.narrow);
+    if (!job.narrow && job.seg_bytes > 0) cw = std::min(cw, job.seg_bytes / (job.in_dtype == DT_F64 ? 8 : 4));
+    if (cw < 1 || job.ldz % cw != 0 || (job.B && job.ldb != job.ldz) || (job.Bh && job.ldbh != job.ldz) ||
         job.ldz < job.d || job.L < 1 || job.L > 30)
         return hipErrorInvalidValue;
     if (job.narrow) {

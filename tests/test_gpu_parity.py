@@ -123,6 +123,22 @@ def test_sketch_rows_f64_eleven_bit_passes(S, ctx):
     assert np.array_equal(Hg.cpu().numpy(), Bh)
 
 
+@pytest.mark.parametrize("N,k", [(150_001, 3), (150_001, 8), (70_000, 9), (70_000, 16), (40_000, 17),
+                                 ((1 << 21) + 5, 5)])
+def test_sketch_multi_rhs_rows_match_oracle(S, ctx, N, k):
+    # FP64 responses of 2..8, 9..16 and more columns are transformed in rows
+    # of 8, 16 and 32-multiple columns (two passes: 9 + 9, 9 + 8, 8 + 8 and
+    # 11 + 11 bits): same butterflies in the same order -> identical bits
+    _log(f"sketch multi-rhs N={N} k={k}")
+    p = _problem(N, 5, seed=N % 97 + k, k=k)
+    big = dict(m0=1 << 12, m_max=1 << 13, r=64) if N > (1 << 20) else {}
+    sk = S.spcg_sketch(ctx, p.X, p.Y, seed=12, **big)
+    B, BY, Bh, _ = nested_srht(p.x_f64().cpu().numpy(), p.Y.cpu().numpy(), 12, sk.sizes[-1], sk.info.r)
+    _, bg, _ = sk.view_tensor(len(sk.sizes) - 1)
+    assert bg.shape == (sk.sizes[-1], k)
+    assert np.array_equal(bg.cpu().numpy(), BY)
+
+
 def test_sketch_tiny_and_multi_rhs(S, ctx):
     # N' = 8 (one 3-bit pass) and a three-column response
     X = torch.arange(10, dtype=torch.float64, device=DEV).reshape(5, 2) - 3.0
@@ -178,14 +194,16 @@ def _raw_rows(sk, stage):
 
 @pytest.mark.parametrize("storage,N,d", [("f32", 600_001, 40), ("f32", 600_001, 37),
                                          ("bf16", 700_000, 24), ("fp8", 700_000, 48),
+                                         ("bf16", 700_000, 26), ("fp8", 700_000, 44),
                                          ("f32", 1_100_000, 12)])
 def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
     # N' = 2^20 (two 10-bit passes): the default transform streams tiles
     # through LDS in persistent blocks; transform_segment = 256 forces one
     # tile per block.  Same butterflies in the same order -> identical bits
-    # (d = 37: rows whose 16-byte pieces straddle d, first pass on the tiled
-    # kernel and Z row-major; N' = 2^21: an 11-bit first pass, half-tile
-    # staged by default, with chunk-major Z in both runs)
+    # (d = 37, 26 (BF16), 44 (FP8): rows of X not 16-byte aligned, the
+    # streamed first pass stages them with 4-byte direct loads, Z row-major;
+    # N' = 2^21: an 11-bit first pass, half-tile staged by default, with
+    # chunk-major Z in both runs)
     _log(f"sketch streaming {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 89)
     rows = []
@@ -199,12 +217,13 @@ def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
 
 @pytest.mark.parametrize("storage,N,d,L", [("f32", 200_001, 40, 18), ("f32", 300_001, 37, 19),
                                            ("bf16", 150_000, 24, 18), ("fp8", 250_001, 48, 18),
-                                           ("f32", 100_001, 70, 17)])
+                                           ("f32", 200_001, 37, 18), ("bf16", 150_000, 26, 18),
+                                           ("fp8", 250_001, 44, 18), ("f32", 100_001, 70, 17)])
 def test_sketch_streaming_nine_bit_passes_match_tiled(S, ctx, storage, N, d, L):
     # 9-bit passes stream 512-row x 256-byte tiles: N' = 2^18 (9 + 9 bits,
-    # chunk-major Z), 2^19 (10 + 9: two tile widths, Z row-major; d = 37
-    # keeps the first pass on the tiled kernel) and 2^17 (9 + 8: the 8-bit
-    # pass stays tiled).  Same butterflies in the same order -> identical
+    # chunk-major Z), 2^19 (10 + 9: two tile widths, Z row-major) and 2^17
+    # (9 + 8: the 8-bit pass stays tiled); d = 37, 26 (BF16), 44 (FP8): rows
+    # of X not 16-byte aligned, staged with 4-byte direct loads.  Same butterflies in the same order -> identical
     # bits to one tile per block.
     _log(f"sketch streaming 9-bit {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 83)
