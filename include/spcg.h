@@ -322,8 +322,11 @@ typedef struct spcg_solve_opts {
     int32_t batch_shape;      /* batched form: tile shape of the product launches.
                                  0 (default) autotunes it once per context and storage
                                  type for every launch bucket (row-width class x
-                                 k <= 8 / k > 8), timing one product pass of the bucket
-                                 in each shape (results are discarded); 1: three
+                                 k <= 8 / k > 8), timing three product passes of the
+                                 bucket in each shape (results are discarded), once
+                                 for the Stage II passes over X (SG) and once for the
+                                 Stage I passes over sketch rows (S, at the largest
+                                 stage every problem has); 1: three
                                  barriers per 16-row tile, 3 LDS slots; 2: two tiles
                                  software-pipelined (the W reduction of one beside the
                                  first GEMM of the next), 3 slots; 3: as 2 with 4 slots
@@ -407,9 +410,10 @@ typedef struct spcg_solve_stats {
     float stage_out[16 * 8];
     int32_t batch_shapes[16];   /* batched form: tile shape of each launch bucket
                                    (class * 2 + (k > 8)) in Stage II, 0 if unused */
-    float batch_tune_ms[16 * 4];/* batched form, the solve that autotuned the shapes:
-                                   one SG product pass of bucket b alone in shape s
-                                   at [b * 4 + s - 1], in ms (0: not timed) */
+    float batch_tune_ms[16 * 4];/* batched form, the solve that autotuned the Stage II
+                                   shapes: one SG product pass of bucket b alone in
+                                   shape s (mean of three) at [b * 4 + s - 1], in ms
+                                   (0: not timed) */
 } spcg_solve_stats;
 
 /* Kernel classes of spcg_solve_stats.kernel_*.  Algorithmic bytes count

@@ -1104,6 +1104,8 @@ struct BatchWork {
     hipEvent_t fork = nullptr, join[MR_NBUCKET] = {}, tune[2] = {};
     int tasks_per_cu[4] = {};   // autotuned task granularity per storage type (0: not yet)
     int shape[4][MR_NBUCKET] = {};   // autotuned tile shape per storage type and bucket (0: not yet)
+    int shape1[4][MR_NBUCKET] = {};  // the same for the Stage I passes over sketch rows
+    bool tuned1[4] = {};             // Stage I shapes tuned for this storage type
     // per-problem setup (sketch, preconditioner) is spread over NLANE lanes,
     // each a context of its own (stream and workspaces), so the small
     // transforms and the latency-bound factor chains of different problems
@@ -1202,14 +1204,20 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
     int64_t bucket_rows[MR_NBUCKET] = {};
     for (size_t p = 0; p < hp.size(); ++p) {
         out[p].t0 = out[p].t1 = 0;
+        out[p].lshift = 0;
         if (!hp[p].active) continue;
-        int c = mrhs_class(dtype, hp[p].A, hp[p].lda, hp[p].dmem, hp[p].d);
+        int c = mrhs_class(dtype, hp[p].A, hp[p].m, hp[p].lda, hp[p].dmem, hp[p].d);
         if (c < 0) return -1;
         // one launch: the 4-byte, 8-load class reads every row that a
         // direct-load class can (4-byte aligned, its 4-byte vectors within
         // the readable part of the row: implied by either load width; at
         // most 2 KB of data)
         if (one_launch && c != MR_CLASS_GENERIC) c = MR_CLASS_4x8;
+        // 16-byte classes of rows that are only 4-byte aligned shift the
+        // last row's loads
+        out[p].lshift = (c == MR_CLASS_16x1 || c == MR_CLASS_16x2)
+                            ? mrhs_row_shift(dtype, hp[p].A, hp[p].m, hp[p].lda, hp[p].dmem, hp[p].d)
+                            : 0;
         bkt[p] = one_launch ? mrhs_bucket(c, 0) : mrhs_bucket(c, hp[p].k);
         bucket_rows[bkt[p]] += hp[p].m;
     }
@@ -1221,11 +1229,26 @@ int build_tasks(int dtype, const std::vector<MrhsProblem>& hp, std::vector<MrhsT
         for (size_t p = 0; p < hp.size(); ++p) {
             if (bkt[p] != c) continue;
             out[p].t0 = (int)tasks.size();
-            for (int64_t r = 0; r < hp[p].m; r += rows_per_task) {
+            // rows that are not 16-byte aligned: the last row is a task of
+            // its own (the 16-byte loads of rows that are only 4-byte
+            // aligned load it shifted; the 4-byte and 16-byte classes then
+            // split such rows alike, so their sums round alike)
+            const int es = dtype == DT_F32 ? 4 : 2;
+            const bool split_last =
+                hp[p].m > 1 && ((hp[p].lda * es) % 16 != 0 || (uintptr_t)hp[p].A % 16 != 0);
+            const int64_t mb = split_last ? hp[p].m - 1 : hp[p].m;
+            for (int64_t r = 0; r < mb; r += rows_per_task) {
                 MrhsTask t{};
                 t.prob = (int)p;
                 t.r0 = r;
-                t.r1 = std::min<int64_t>(hp[p].m, r + rows_per_task);
+                t.r1 = std::min<int64_t>(mb, r + rows_per_task);
+                tasks.push_back(t);
+            }
+            if (mb < hp[p].m) {
+                MrhsTask t{};
+                t.prob = (int)p;
+                t.r0 = mb;
+                t.r1 = hp[p].m;
                 tasks.push_back(t);
             }
             out[p].t1 = (int)tasks.size();
@@ -1251,9 +1274,9 @@ DevBuf& plan_probs(BatchWork& W, const BatchPlan& plan) { return plan.set ? W.pr
 
 // tile shape of every bucket: forced (> 0), else the context's tuned one,
 // else the two-tile pipeline with 3 slots
-void plan_shapes(const BatchWork& W, int dtype, int forced, BatchPlan& plan) {
+void plan_shapes(const BatchWork& W, int dtype, int forced, BatchPlan& plan, bool stage_rows = false) {
     for (int b = 0; b < MR_NBUCKET; ++b) {
-        const int tuned = W.shape[dtype & 3][b];
+        const int tuned = stage_rows ? W.shape1[dtype & 3][b] : W.shape[dtype & 3][b];
         plan.shape[b] = forced > 0 ? forced : tuned > 0 ? tuned : MR_SHAPE_PIPE3;
     }
 }
@@ -1522,6 +1545,11 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // stage i - 1 starts stage i from its previous gradient plus a G pass
     // over the new prefix rows only (as the single-problem path does).
     std::vector<char> ran_prev(nprob, 0);
+    // the stage at which the Stage I shapes are tuned: the largest one that
+    // every problem with a sketch has
+    int64_t i_tune = maxK - 1;
+    for (int p = 0; p < nprob; ++p)
+        if (W.sk[p]->K > 0) i_tune = std::min<int64_t>(i_tune, W.sk[p]->K - 1);
     for (int64_t i = 0; i < maxK; ++i) {
         int ai = a;
         if (opts->a_list_len > 0) ai = opts->a_list[std::min<int64_t>(i, opts->a_list_len - 1)];
@@ -1549,7 +1577,36 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         BatchPlan plan;
         plan.one_launch = opts->batch_one_launch != 0;
         if ((rc = batched_setup(ctx, W, sdt, hp, target_tasks, plan)) != SPCG_OK) return rc;
-        plan_shapes(W, sdt, opts->batch_shape, plan);
+        // Stage I tile shapes: tuned once per context and storage type at the
+        // largest stage every problem has, by timing three S passes of each
+        // bucket alone in every shape its class has (the partials are
+        // overwritten by the stage's own passes; iterates are unaffected)
+        if (opts->batch_shape <= 0 && !W.tuned1[sdt & 3] && i == i_tune) {
+            plan_shapes(W, sdt, 0, plan, true);
+            for (int b = 0; b < MR_NBUCKET; ++b) {
+                if (plan.seg[b + 1] <= plan.seg[b] || b / MR_KB == MR_CLASS_GENERIC) continue;
+                double best_ms = INFINITY;
+                int best = MR_SHAPE_PIPE3;
+                for (int sh = MR_SHAPE_PLAIN; sh < MR_NSHAPE; ++sh) {
+                    if (!mrhs_shape_native(b / MR_KB, sh)) continue;
+                    plan.shape[b] = sh;
+                    if ((rc = batched_products(ctx, W, st, sdt, PM_S, plan, b)) != SPCG_OK) return rc;   // warm-up
+                    HIP_TRY(ctx, hipEventRecord(W.tune[0], st));
+                    for (int rep = 0; rep < 3; ++rep)
+                        if ((rc = batched_products(ctx, W, st, sdt, PM_S, plan, b)) != SPCG_OK) return rc;
+                    HIP_TRY(ctx, hipEventRecord(W.tune[1], st));
+                    HIP_TRY(ctx, hipEventSynchronize(W.tune[1]));
+                    const double ms = elapsed_ms(W.tune[0], W.tune[1]) / 3.0;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = sh;
+                    }
+                }
+                W.shape1[sdt & 3][b] = best;
+            }
+            W.tuned1[sdt & 3] = true;
+        }
+        plan_shapes(W, sdt, opts->batch_shape, plan, true);
         // the starting G pass: over the new prefix rows [m_{i-1}, m_i) of the
         // problems that can reuse their gradient, over all rows otherwise
         BatchPlan gplan;
@@ -1571,7 +1628,7 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
                 gplan.set = 1;
                 gplan.one_launch = plan.one_launch;
                 if ((rc = batched_setup(ctx, W, sdt, hg, target_tasks, gplan)) != SPCG_OK) return rc;
-                plan_shapes(W, sdt, opts->batch_shape, gplan);
+                plan_shapes(W, sdt, opts->batch_shape, gplan, true);
             }
         }
         auto stage = [&](hipStream_t s) -> int {
@@ -1613,8 +1670,8 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // the d-space step is not run, so the iterates are unaffected)
     int tpc = opts->batch_tasks_per_cu > 0 ? opts->batch_tasks_per_cu : W.tasks_per_cu[dtype & 3];
     // tile shape per bucket: tuned once per context and storage type, by
-    // timing one product pass of each bucket alone in every shape its class
-    // has (at the tuned granularity, else 4 tasks per CU)
+    // timing three product passes of each bucket alone in every shape its
+    // class has (at the tuned granularity, else 4 tasks per CU)
     bool shapes_tuned = false;
     float tune_ms[MR_NBUCKET * 4] = {};
     if (opts->batch_shape <= 0) {
@@ -1635,10 +1692,11 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
                 tp.shape[b] = sh;
                 if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp, b)) != SPCG_OK) return rc;   // warm-up
                 HIP_TRY(ctx, hipEventRecord(W.tune[0], st));
-                if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp, b)) != SPCG_OK) return rc;
+                for (int rep = 0; rep < 3; ++rep)
+                    if ((rc = batched_products(ctx, W, st, dtype, PM_SG, tp, b)) != SPCG_OK) return rc;
                 HIP_TRY(ctx, hipEventRecord(W.tune[1], st));
                 HIP_TRY(ctx, hipEventSynchronize(W.tune[1]));
-                const double ms = elapsed_ms(W.tune[0], W.tune[1]);
+                const double ms = elapsed_ms(W.tune[0], W.tune[1]) / 3.0;
                 tune_ms[b * 4 + sh - 1] = (float)ms;
                 if (ms < best_ms) {
                     best_ms = ms;
@@ -1847,7 +1905,7 @@ bool mrhs_stage_ok(const spcg_mat* A, int64_t k) {
     if (A->dtype != SPCG_F32 && A->dtype != SPCG_BF16) return false;
     if (A->cols > mrhs_max_d() || k > mrhs_max_k()) return false;
     const int64_t dmem = A->reserved == 1 ? A->ld : A->cols;
-    return mrhs_class(A->dtype, A->data, A->ld, dmem, (int)A->cols) >= 0;
+    return mrhs_class(A->dtype, A->data, A->rows, A->ld, dmem, (int)A->cols) >= 0;
 }
 
 // PCG(A, b, c2, M, beta, iters) for the k columns of b at once: every

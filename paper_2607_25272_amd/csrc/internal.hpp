@@ -243,6 +243,7 @@ struct MrhsProblem {
     double gscale;          // PA_START_NESTED: weight of the previous gradient (0: plain start)
     int t0, t1;             // tasks of this problem in the current launch
     int active;             // 0: skip (converged or no stage)
+    int lshift;             // 16-byte loads of rows only 4-byte aligned: the last row's loads start this many bytes early
 };
 struct MrhsTask {
     int prob;
@@ -257,7 +258,11 @@ constexpr int MR_ZSLICES = 4;   // 128-row slices of z = M g (d <= 512)
 // (any row stride).
 enum MrhsClass : int { MR_CLASS_16x1 = 0, MR_CLASS_16x2, MR_CLASS_4x1, MR_CLASS_4x2, MR_CLASS_4x4, MR_CLASS_4x8,
                        MR_CLASS_GENERIC, MR_NCLASS };
-int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d);
+int mrhs_class(int dtype, const void* A, int64_t m, int64_t lda, int64_t dmem, int d);
+// Bytes by which the 16-byte loads of the matrix's last row start early
+// (rows only 4-byte aligned), 0 for aligned rows, -1 when 16-byte loads
+// cannot read the rows.
+int mrhs_row_shift(int dtype, const void* A, int64_t m, int64_t lda, int64_t dmem, int d);
 // Tile shapes of a product launch: MR_SHAPE_PLAIN runs GEMM1, the W
 // reduction and GEMM2 of each 16-row tile between three barriers with 3 LDS
 // slots; MR_SHAPE_PIPE3 / PIPE4 software-pipeline two tiles (two barriers

@@ -119,10 +119,16 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
     constexpr int KG = (DCLS / 16 + NW - 1) / NW;     // 16-column K groups per wave (first GEMM)
     constexpr int MAXT = (DCLS / 16 + NW - 1) / NW;   // second-GEMM output tiles per wave
     static_assert(RING >= (PIPE ? 3 : 2) && RING <= 4 && (RING - 2) * OPS < 64, "ring shape");
-    __shared__ __align__(16) unsigned char sl0[SLOT];
-    __shared__ __align__(16) unsigned char sl1[SLOT];
-    __shared__ __align__(16) unsigned char sl2[RING > 2 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char sl3[RING > 3 ? SLOT : 16];
+    // each slot starts with a 16-byte guard: the loads of a shifted last
+    // row (see issue) begin up to 12 bytes before its staging row
+    __shared__ __align__(16) unsigned char sl0_[SLOT + 16];
+    __shared__ __align__(16) unsigned char sl1_[SLOT + 16];
+    __shared__ __align__(16) unsigned char sl2_[RING > 2 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char sl3_[RING > 3 ? SLOT + 16 : 32];
+    unsigned char* const sl0 = sl0_ + 16;
+    unsigned char* const sl1 = sl1_ + 16;
+    unsigned char* const sl2 = sl2_ + 16;
+    unsigned char* const sl3 = sl3_ + 16;
     // Column packing: the first GEMM's B operand is [P | x_hi | x_lo] (the
     // matrices this mode needs, k columns each) laid side by side over
     // NS1 = ceil(NM1 k / 16) 16-column slabs, and the second GEMM's is
@@ -151,6 +157,25 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
     const int64_t rowb = pb.lda * ES;
     const int64_t rlast = task.r1 - 1;
     for (int e = threadIdx.x; e < MT * (2 * KP + 4); e += 64 * NW) (&W2[0][0])[e] = 0.f;
+    // Rows whose start is only 4-byte aligned (16-byte loads, lshift > 0):
+    // the last 16-byte vector of a row reaches up to 12 bytes into the next
+    // row, except for the matrix's last row (a task of its own), whose
+    // vectors start lshift bytes earlier (in the previous row) and land
+    // lshift bytes earlier in LDS, so that its data sits where the readers
+    // expect it.  Its last lshift staged bytes are then not written; they
+    // are read as columns past d (times zero), so they start at zero here,
+    // before any load.
+    const bool shifted_last = DMAB == 16 && pb.lshift > 0 && task.r0 == pb.m - 1;
+    const int sh = shifted_last ? pb.lshift : 0;
+    const char* const Abase_s = Abase - sh;
+    if (shifted_last) {
+        for (int e = threadIdx.x; e < RING * MT; e += 64 * NW) {
+            const int sidx = e / MT;
+            unsigned char* sb = sidx == 0 ? sl0 : sidx == 1 ? sl1 : sidx == 2 ? sl2 : sl3;
+            *reinterpret_cast<uint4*>(sb + (e % MT) * PITCH + RB - 16) = make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
+    }
 
     // constant B operands of the first GEMM: P and x = hi + lo (~48 bits),
     // zero outside d x k.  A x = A x_hi + A x_lo: the high product only
@@ -196,13 +221,15 @@ __global__ __launch_bounds__(64 * NW) void mrhs_product_kernel(const MrhsTask* _
     const int64_t ntile = (task.r1 - task.r0 + MT - 1) / MT;
 
     auto issue = [&](int64_t tl, unsigned char* T) __attribute__((always_inline)) {
+        // (a shifted last-row task: every load is of that row, sh bytes early)
+        unsigned char* Ts = T - sh;
 #pragma unroll
         for (int q = 0; q < AJOBS / NW; ++q) {
             const int job = wave + NW * q;
             const int r = job / NIR, c = job % NIR;
             const int64_t grow = min(task.r0 + tl * MT + r, rlast);
             const int vi = min(c * 64 + lane, nvec - 1);
-            mr_lds_load<DMAB>(Abase + grow * rowb + (int64_t)vi * DMAB, T + r * PITCH + c * 64 * DMAB);
+            mr_lds_load<DMAB>(Abase_s + grow * rowb + (int64_t)vi * DMAB, Ts + r * PITCH + c * 64 * DMAB);
             // keep each address computation next to its load (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -714,11 +741,26 @@ hipError_t mr_launch_class(hipStream_t st, int mode, int cls, int shape, const M
 int mrhs_max_d() { return MR_DMAX; }
 int mrhs_max_k() { return KP; }
 
-int mrhs_class(int dtype, const void* A, int64_t lda, int64_t dmem, int d) {
+// 16-byte loads from rows that are only 4-byte aligned: every byte of the
+// row stride is readable (lda == dmem), a row holds at least 16 bytes and
+// there are at least two rows.  The last vector of row r < m - 1 then ends
+// inside row r + 1; the matrix's last row is loaded lshift bytes earlier.
+int mrhs_row_shift(int dtype, const void* A, int64_t m, int64_t lda, int64_t dmem, int d) {
+    const int es = dtype == DT_F32 ? 4 : 2;
+    const int64_t nv = ((int64_t)d * es + 15) / 16;
+    const bool aligned = (lda * es) % 16 == 0 && (uintptr_t)A % 16 == 0 && nv * 16 <= dmem * es;
+    if (aligned) return 0;
+    const bool ok = (lda * es) % 4 == 0 && (uintptr_t)A % 4 == 0 && lda == dmem && (int64_t)d * es >= 16 && m >= 2 &&
+                    lda >= d;
+    return ok ? (int)(nv * 16 - (int64_t)d * es) : -1;
+}
+
+int mrhs_class(int dtype, const void* A, int64_t m, int64_t lda, int64_t dmem, int d) {
     const int es = dtype == DT_F32 ? 4 : 2;
     for (int dmab : {16, 4}) {
         const int64_t nv = ((int64_t)d * es + dmab - 1) / dmab;
-        const bool ok = (lda * es) % dmab == 0 && (uintptr_t)A % dmab == 0 && nv * dmab <= dmem * es;
+        const bool ok = dmab == 16 ? mrhs_row_shift(dtype, A, m, lda, dmem, d) >= 0
+                                   : (lda * es) % dmab == 0 && (uintptr_t)A % dmab == 0 && nv * dmab <= dmem * es;
         if (!ok) continue;
         const int64_t ni = (nv + 63) / 64;
         if (dmab == 16) {

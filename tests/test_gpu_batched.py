@@ -233,3 +233,43 @@ def test_batched_nested_gradient_start(S, ctx):
         assert abs(s1["T_stage2"] - s2["T_stage2"]) <= 1, (s1["T_stage2"], s2["T_stage2"])
         _check(q, b1)
         _check(q, b2)
+
+
+@pytest.mark.parametrize("storage,d,k,m", [("f32", 37, 3, 1000), ("f32", 50, 4, 777), ("f32", 6, 2, 300),
+                                           ("f32", 241, 2, 500), ("f32", 254, 16, 1003), ("f32", 301, 5, 600),
+                                           ("f32", 510, 9, 999), ("bf16", 38, 4, 700)])
+def test_unaligned_rows_match_padded_rows(S, ctx, storage, d, k, m):
+    # Dense rows whose byte length is a multiple of 4 but not of 16 are read
+    # with 16-byte loads from 4-byte aligned addresses (a row's last vector
+    # reaches into the next row; the matrix's last row is loaded a few bytes
+    # early, into the previous row); the same values in padded rows whose
+    # stride is not a multiple of 16 bytes take 4-byte loads.  The tiles and
+    # the MFMA order are the same, so the iterates agree bit for bit, with
+    # and without the refreshed gradient (S and SG passes).
+    print(f"unaligned rows {storage} d={d} k={k} m={m}", flush=True)
+    g = torch.Generator().manual_seed(7 * d + k)
+    dt = torch.float32 if storage == "f32" else torch.bfloat16
+    A = (torch.randn(m, d, generator=g, dtype=torch.float64) *
+         torch.logspace(0, 2, d, dtype=torch.float64)).to(dt).to(DEV)
+    dp = (d + 7) // 8 * 8 + (1 if storage == "f32" else 2)
+    Ap = torch.zeros(m, dp, dtype=dt, device=DEV)
+    Ap[:, :d] = A
+    Av = Ap[:, :d]
+    assert Av.stride(0) == dp and (dp * Av.element_size()) % 16 != 0
+    b = torch.randn(m, k, generator=g, dtype=torch.float64).to(DEV)
+    R = np.linalg.qr(A.double().cpu().numpy(), mode="r")
+    pc = S.spcg_precond_from_r(ctx, torch.from_numpy(R))
+    for refresh in (False, True):
+        outs = []
+        for X in (A, Av):
+            beta = torch.zeros(d, k, dtype=torch.float64, device=DEV)
+            st = S.spcg_pcg_stage(ctx, X, b, 1.0 / m, pc, beta, 4, refresh=refresh)
+            assert st["iters"] == 4
+            outs.append(beta.clone())
+        assert torch.equal(outs[0], outs[1]), refresh
+    # and it is the PCG of this system: 4 steps with the exact preconditioner
+    # of A reach its least-squares solution
+    Ad = A.double().cpu().numpy()
+    xs = np.linalg.lstsq(Ad, b.cpu().numpy(), rcond=None)[0]
+    err = np.abs(Ad @ (outs[0].cpu().numpy() - xs)).max() / np.abs(Ad @ xs).max()
+    assert err < 1e-4, err
