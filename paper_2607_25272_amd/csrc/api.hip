@@ -128,6 +128,7 @@ struct spcg_ctx {
     double* na_scratch = nullptr;
     // sketch and preconditioner workspaces used by spcg_solve
     DevBuf zbuf, tables, wsB, wsBY, wsBh;
+    DevBuf xlast;   // padded copy of the last input row (first transform pass)
     DevBuf wsR, wsMinv, dense_a, dense_b, dense_c, dense_q, dense_status, dense_w, dense_wd, dense_tmp;
     int64_t dense_w_elems = 0;
     // learned schedule: features and network outputs (4 x 8 floats), gradient partials
@@ -520,6 +521,19 @@ int sketch_build(spcg_ctx* ctx, const spcg_mat* X, const spcg_mat* Y, const spcg
     HIP_TRY(ctx, hipEventRecord(ctx->ev_side_join, ctx->side));
     FwhtJob jx{};
     jx.x = X->data;
+    // rows whose byte stride is a multiple of 4 but not of 16: a padded copy
+    // of the last row lets the first pass stage every row with 16-byte loads
+    if (X->dtype != SPCG_F64 && N >= 2) {
+        const int64_t eb = dtype_bytes(X->dtype), rowb = d * eb;
+        const bool a16 = (uintptr_t)X->data % 16 == 0 && (X->ld * eb) % 16 == 0;
+        const bool a4 = (uintptr_t)X->data % 4 == 0 && (X->ld * eb) % 4 == 0;
+        if (!a16 && a4) {
+            HIP_TRY(ctx, ctx->xlast.ensure((size_t)round_up(rowb, 16) + 16));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->xlast.p, static_cast<const char*>(X->data) + (N - 1) * X->ld * eb,
+                                        (size_t)rowb, hipMemcpyDeviceToDevice, st));
+            jx.x_last = ctx->xlast.p;
+        }
+    }
     jx.in_dtype = X->dtype;
     jx.N = N;
     jx.d = d;

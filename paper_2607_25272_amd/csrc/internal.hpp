@@ -40,6 +40,9 @@ hipError_t launch_sketch_export(hipStream_t st, uint64_t seed, int L, int64_t mK
 
 struct FwhtJob {
     const void* x;          // N x d input rows, element type in_dtype, leading dim ldx
+    const void* x_last;     // null, or a copy of row N - 1 readable to 16 bytes past
+                            // round_up(d * elem, 16) (lets rows that are only 4-byte
+                            // aligned take 16-byte direct loads in the first pass)
     int in_dtype;           // DT_*; TZ is double for DT_F64, float otherwise
     int64_t N, d, ldx;
     const float* col_scale; // FP8 only

@@ -197,6 +197,7 @@ struct ZVec<double> {
 struct PassArgs {
     const void* x;
     int64_t ldx;
+    const void* x_last;   // first pass, 16-byte loads of rows only 4-byte aligned: padded copy of row N - 1
     const float* col_scale;
     int64_t N, d;
     int xvec;          // X rows allow aligned VL-element loads
@@ -426,10 +427,6 @@ __device__ __forceinline__ void stream_lds_load16(const void* src, void* lds) {
     __builtin_amdgcn_global_load_lds(const_cast<void*>(src), (__attribute__((address_space(3))) void*)(lds),
                                      16, 0, 0);
 }
-__device__ __forceinline__ void stream_lds_load4(const void* src, void* lds) {
-    __builtin_amdgcn_global_load_lds(const_cast<void*>(src), (__attribute__((address_space(3))) void*)(lds),
-                                     4, 0, 0);
-}
 
 template <typename TI>
 struct StageRead;   // 4 consecutive staged elements of one row -> FP32; scales of columns >= d read as 0
@@ -466,12 +463,24 @@ struct StageRead<fp8_t> {
     }
 };
 
-// DW: bytes per direct load, 16, or 4 for a first pass over rows whose
-// stride is a multiple of 4 but not of 16 bytes (then each wave's loads
-// cover RW consecutive staging rows, whose permutation entries its lanes
-// hold, NE per lane, and each load takes its row's entry by a cross-lane
-// permute)
-template <typename TIN, int CW, bool FIRST, bool LAST, int DW = 16>
+// First pass: address of the staged piece of X row sr at column col.
+// Rows past N and pieces past d read row 0 instead (the reader zeroes
+// them).  XL: 16-byte loads of rows that are only 4-byte aligned; a piece
+// may then reach up to 12 bytes into the next row, and row N - 1 is read
+// from its copy x_last, which is padded so that no load leaves it.
+template <int IB, bool XL>
+__device__ __forceinline__ const unsigned char* x_piece(const PassArgs& a, int64_t sr, int64_t col) {
+    const bool ok = sr < a.N && col < a.d;
+    if constexpr (XL) {
+        const bool last = sr == a.N - 1;
+        const unsigned char* base = static_cast<const unsigned char*>(last ? a.x_last : a.x);
+        return base + (ok ? (last ? col : sr * a.ldx + col) * IB : 0);
+    } else {
+        return static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+    }
+}
+
+template <typename TIN, int CW, bool FIRST, bool LAST, bool XL = false>
 __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a) {
     constexpr int VL = 4, Q = 4, R = 16, THREADS = STREAM_THREADS;
     constexpr int LPR = CW / VL;
@@ -482,18 +491,11 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     constexpr int IB = (int)sizeof(TI);
     constexpr int ROWB = CW * IB;               // staged bytes per tile row
     constexpr int STG = ROWS * ROWB;
-    constexpr int NI = STG / (THREADS * DW);    // direct loads per thread per tile
-    constexpr int RW = NI * 64 * DW / ROWB;     // staging rows one wave's loads cover
-    constexpr int NE = DW == 4 ? RW / 64 : 0;   // permutation entries per lane (4-byte loads)
+    constexpr int NI = STG / (THREADS * 16);    // direct loads per thread per tile
     constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;   // staging row swizzle
     constexpr int XM = 64 / LPR - 1;                       // exchange row swizzle
     static_assert(ROWS == (1 << NB) && !(FIRST && LAST), "stream tile shape");
-    static_assert(ROWB >= 16 && NI >= 1 && NI * THREADS * DW == STG && SM < 16 && XM < 16, "staging");
-    // (a 4-byte load covers 64 DW / ROWB consecutive rows, aligned to their
-    // count, and the swizzle keeps rows in their 16-row group, so all lanes
-    // of a load take the entry from the same register)
-    static_assert(DW == 16 || (FIRST && DW == 4 && NE >= 1 && NE <= 2 && NE * 64 == RW && 64 * DW / ROWB <= 16),
-                  "4-byte staging");
+    static_assert(ROWB >= 16 && NI >= 1 && NI * THREADS * 16 == STG && SM < 16 && XM < 16, "staging");
     // two separate LDS objects: the compiler then knows that exchange
     // traffic does not touch the buffer the direct loads are filling
     __shared__ __align__(16) unsigned char stg[STG];
@@ -551,29 +553,22 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
         const int64_t klo = k & ((1ll << a.zt_lobits) - 1), khi = k >> a.zt_lobits;
         return ((((col / CW) << a.zt_lobits) | klo) << a.zt_hibits | khi) * CW + col % CW;
     };
-    // tile row and DW-byte piece that direct load i of this lane fetches
+    // tile row and 16-byte piece that direct load i of this lane fetches
     auto dma_slot = [&](int i, int& row, int& piece) {
-        const int P = ((wave * NI + i) * 64 + lane) * DW;
+        const int P = ((wave * NI + i) * 64 + lane) * 16;
         row = srow(P / ROWB);
-        piece = (P % ROWB) / DW;
+        piece = (P % ROWB) / 16;
     };
 
-    // first pass: permutation entries of the rows this lane stages next (16-
-    // byte loads: one per load; 4-byte loads: rows wave RW + e 64 + lane)
-    int32_t dp[DW == 16 ? NI : NE];
+    int32_t dp[NI];   // first pass: permutation entries of the rows this lane stages next
     int32_t cp[R];    // first pass: permutation entries of this thread's rows
     auto load_dperm = [&](int64_t j) __attribute__((always_inline)) {
         const Tile tl = tile_of(j);
-        if constexpr (DW == 16) {
 #pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                int row, piece;
-                dma_slot(i, row, piece);
-                dp[i] = a.perm_sign[grow(tl, row)];
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < NE; ++e) dp[e] = a.perm_sign[grow(tl, wave * RW + e * 64 + lane)];
+        for (int i = 0; i < NI; ++i) {
+            int row, piece;
+            dma_slot(i, row, piece);
+            dp[i] = a.perm_sign[grow(tl, row)];
         }
     };
     auto load_cperm = [&](int64_t j) __attribute__((always_inline)) {
@@ -583,63 +578,19 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
     };
     auto issue_stage = [&](int64_t j) __attribute__((always_inline)) {
         const Tile tl = tile_of(j);
-        unsigned char* dst = stg + wave * NI * 64 * DW;
-        if constexpr (DW == 16) {
+        unsigned char* dst = stg + wave * NI * 1024;
 #pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                int row, piece;
-                dma_slot(i, row, piece);
-                const int64_t col = tl.cbase + piece * (16 / IB);
-                const unsigned char* src;
-                if constexpr (FIRST) {
-                    // rows past N and pieces past d read row 0 instead; the
-                    // reader zeroes them
-                    const int64_t sr = (int64_t)(dp[i] & 0x7fffffff);
-                    const bool ok = sr < a.N && col < a.d;
-                    src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
-                } else {
-                    src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, row), col) * 4;
-                }
-                stream_lds_load16(src, dst + i * 1024);
+        for (int i = 0; i < NI; ++i) {
+            int row, piece;
+            dma_slot(i, row, piece);
+            const int64_t col = tl.cbase + piece * (16 / IB);
+            const unsigned char* src;
+            if constexpr (FIRST) {
+                src = x_piece<IB, XL>(a, (int64_t)(dp[i] & 0x7fffffff), col);
+            } else {
+                src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, row), col) * 4;
             }
-        } else {
-            // 4-byte loads, in groups of G: the group's permutation entries
-            // are fetched from the lanes that hold them first, then its loads
-            // are issued (one wait per group). The row and permute offsets
-            // come from a lane index the compiler cannot see through, so that
-            // it recomputes them per tile instead of holding all of them
-            // live across the tile loop (which spills).
-            constexpr int G = 8;
-            static_assert(NI % G == 0, "4-byte load groups");
-            int ln = lane;
-            asm volatile("" : "+v"(ln));
-#pragma unroll
-            for (int g = 0; g < NI; g += G) {
-                int32_t pe[G];
-                int piece[G];
-#pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    const int P = ((wave * NI + g + u) * 64 + ln) * DW;
-                    const int row = srow(P / ROWB);
-                    piece[u] = (P % ROWB) / DW;
-                    // the row lies in this wave's [wave RW, wave RW + RW) (the
-                    // staging swizzle stays inside a 16-row group): entry
-                    // (row - wave RW) / 64 of lane (row - wave RW) mod 64
-                    const int local = row - wave * RW;
-                    pe[u] = __builtin_amdgcn_ds_bpermute((local & 63) << 2, (local >> 6) == 0 ? dp[0] : dp[NE - 1]);
-                }
-#pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    const int64_t col = tl.cbase + piece[u] * (DW / IB);
-                    // rows past N and pieces past d read row 0 instead; the
-                    // reader zeroes them
-                    const int64_t sr = (int64_t)(pe[u] & 0x7fffffff);
-                    const bool ok = sr < a.N && col < a.d;
-                    stream_lds_load4(static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0),
-                                     dst + (g + u) * 256);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            stream_lds_load16(src, dst + i * 1024);
         }
     };
 
@@ -787,8 +738,9 @@ __global__ __launch_bounds__(STREAM_THREADS) void fwht_stream_kernel(PassArgs a)
 //      has landed), and the stores, which drain during the next A phase.
 constexpr int SPLIT_THREADS = 1024;
 
-template <typename TIN, bool FIRST, bool LAST, int DW>
+template <typename TIN, bool FIRST, bool LAST, bool XL = false>
 __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
+    constexpr int DW = 16;   // bytes per direct load
     constexpr int CW = 32, VL = 4, R = 16, THREADS = SPLIT_THREADS;
     constexpr int LPR = CW / VL;                 // 8 lanes per tile row
     constexpr int NB = 11, HALF = 1 << (NB - 1);
@@ -798,7 +750,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
     constexpr int STG = HALF * ROWB;             // one half-tile
     constexpr int NI = STG / (THREADS * DW);     // direct loads of DW bytes per thread per half-tile
     constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;
-    static_assert(NI >= 1 && NI * THREADS * DW == STG && !(FIRST && LAST) && (DW == 16 || (FIRST && DW == 4)),
+    static_assert(NI >= 1 && NI * THREADS * DW == STG && !(FIRST && LAST),
                   "split tile shape");
     __shared__ __align__(16) unsigned char stg[STG];
     __shared__ __align__(16) float exb[HALF * LPR];
@@ -882,16 +834,12 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
             const int64_t col = tl.cbase + piece * (DW / IB);
             const unsigned char* src;
             if constexpr (FIRST) {
-                // rows past N and pieces past d read row 0; the reader zeroes them
                 const int32_t pe = __builtin_amdgcn_ds_bpermute((row - wave * 64) << 2, dp);
-                const int64_t sr = (int64_t)(pe & 0x7fffffff);
-                const bool ok = sr < a.N && col < a.d;
-                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+                src = x_piece<IB, XL>(a, (int64_t)(pe & 0x7fffffff), col);
             } else {
                 src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, h * HALF + row), col) * 4;
             }
-            if constexpr (DW == 16) stream_lds_load16(src, dst + i * 1024);
-            else stream_lds_load4(src, dst + i * 256);
+            stream_lds_load16(src, dst + i * 1024);
         }
     };
 
@@ -1147,8 +1095,9 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_split_kernel(PassArgs a) {
 // runs through that free 64 KB quarter buffer in four rounds with every
 // lane (eight rounds of half the lanes through the 32 KB buffer
 // otherwise).
-template <typename TIN, bool FIRST, bool LAST, int DW>
+template <typename TIN, bool FIRST, bool LAST, bool XL = false>
 __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
+    constexpr int DW = 16;   // bytes per direct load
     constexpr int CW = 32, VL = 4, R = 16, THREADS = SPLIT_THREADS;
     constexpr int LPR = CW / VL;                 // 8 lanes per tile row
     constexpr int NB = 11, HALF = 1 << (NB - 1), QR = HALF / 2;   // 512 rows per quarter
@@ -1158,7 +1107,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
     constexpr int QS = QR * ROWB;                // one quarter-tile
     constexpr int NIQ = QS / (THREADS * DW);     // direct loads of DW bytes per thread per quarter
     constexpr int SM = ROWB < 256 ? 256 / ROWB - 1 : 0;
-    static_assert(NIQ >= 1 && NIQ * THREADS * DW == QS && !(FIRST && LAST) && (DW == 16 || (FIRST && DW == 4)),
+    static_assert(NIQ >= 1 && NIQ * THREADS * DW == QS && !(FIRST && LAST),
                   "ring tile shape");
     static_assert(!LAST || QS >= (HALF * 2) * LPR * 4, "the last pass exchanges through a quarter buffer");
     // s_waitcnt vmcnt(n): all but the last n vector-memory loads have completed
@@ -1259,16 +1208,12 @@ __global__ __launch_bounds__(SPLIT_THREADS) void fwht_ring_kernel(PassArgs a) {
             const int64_t col = tl.cbase + piece * (DW / IB);
             const unsigned char* src;
             if constexpr (FIRST) {
-                // rows past N and pieces past d read row 0; the reader zeroes them
                 const int32_t pe = __builtin_amdgcn_ds_bpermute((row - wave * 32) << 2, dp);
-                const int64_t sr = (int64_t)(pe & 0x7fffffff);
-                const bool ok = sr < a.N && col < a.d;
-                src = static_cast<const unsigned char*>(a.x) + (ok ? (sr * a.ldx + col) * IB : 0);
+                src = x_piece<IB, XL>(a, (int64_t)(pe & 0x7fffffff), col);
             } else {
                 src = static_cast<const unsigned char*>(a.zin) + zoff(grow(tl, q * QR + row), col) * 4;
             }
-            if constexpr (DW == 16) stream_lds_load16(src, dst + i * 1024);
-            else stream_lds_load4(src, dst + i * 256);
+            stream_lds_load16(src, dst + i * 1024);
         }
     };
 
@@ -1626,55 +1571,60 @@ hipError_t launch_any(hipStream_t st, const PassArgs& a, bool first, bool last) 
     return launch_pass<TIN, TZ, CW, false, false>(st, a);
 }
 
-template <typename TIN, int CW, bool FIRST, bool LAST, int DW = 16>
+template <typename TIN, int CW, bool FIRST, bool LAST, bool XL = false>
 hipError_t launch_stream_one(hipStream_t st, const PassArgs& a, int64_t grid) {
-    auto fn = fwht_stream_kernel<TIN, CW, FIRST, LAST, DW>;
+    auto fn = fwht_stream_kernel<TIN, CW, FIRST, LAST, XL>;
     fn<<<dim3((unsigned)grid), dim3(STREAM_THREADS), 0, st>>>(a);
     return hipGetLastError();
 }
 
-// dw4: the first pass stages rows of X with 4-byte direct loads (FP8 rows
-// whose length is not a multiple of 16 bytes)
+// How a first pass stages the rows of X: 16-byte direct loads of rows that
+// are 16-byte aligned, or of rows that are only 4-byte aligned with row
+// N - 1 read from its padded copy; XS_NONE: no staged first pass (such rows
+// take the tiled kernel).
+enum XStage : int { XS_16 = 0, XS_NONE = 1, XS_16L = 2 };
+
 template <typename TIN>
-hipError_t launch_split(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
+hipError_t launch_split(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, int xs) {
     const dim3 g((unsigned)grid), b(SPLIT_THREADS);
     if (first && last) return hipErrorInvalidValue;
-    if (first && dw4) {
-        if constexpr (std::is_same<TIN, fp8_t>::value) fwht_split_kernel<TIN, true, false, 4><<<g, b, 0, st>>>(a);
-        else return hipErrorInvalidValue;
+    if (first && xs == XS_NONE) {
+        return hipErrorInvalidValue;
+    } else if (first && xs == XS_16L) {
+        fwht_split_kernel<TIN, true, false, true><<<g, b, 0, st>>>(a);
     } else if (first) {
-        fwht_split_kernel<TIN, true, false, 16><<<g, b, 0, st>>>(a);
+        fwht_split_kernel<TIN, true, false><<<g, b, 0, st>>>(a);
     } else if (last) {
-        fwht_split_kernel<TIN, false, true, 16><<<g, b, 0, st>>>(a);
+        fwht_split_kernel<TIN, false, true><<<g, b, 0, st>>>(a);
     } else {
-        fwht_split_kernel<TIN, false, false, 16><<<g, b, 0, st>>>(a);
+        fwht_split_kernel<TIN, false, false><<<g, b, 0, st>>>(a);
     }
     return hipGetLastError();
 }
 
 template <typename TIN>
-hipError_t launch_ring(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
+hipError_t launch_ring(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, int xs) {
     const dim3 g((unsigned)grid), b(SPLIT_THREADS);
     if (first && last) return hipErrorInvalidValue;
-    if (first && dw4) {
-        if constexpr (std::is_same<TIN, fp8_t>::value) fwht_ring_kernel<TIN, true, false, 4><<<g, b, 0, st>>>(a);
-        else return hipErrorInvalidValue;
+    if (first && xs == XS_NONE) {
+        return hipErrorInvalidValue;
+    } else if (first && xs == XS_16L) {
+        fwht_ring_kernel<TIN, true, false, true><<<g, b, 0, st>>>(a);
     } else if (first) {
-        fwht_ring_kernel<TIN, true, false, 16><<<g, b, 0, st>>>(a);
+        fwht_ring_kernel<TIN, true, false><<<g, b, 0, st>>>(a);
     } else if (last) {
-        fwht_ring_kernel<TIN, false, true, 16><<<g, b, 0, st>>>(a);
+        fwht_ring_kernel<TIN, false, true><<<g, b, 0, st>>>(a);
     } else {
-        fwht_ring_kernel<TIN, false, false, 16><<<g, b, 0, st>>>(a);
+        fwht_ring_kernel<TIN, false, false><<<g, b, 0, st>>>(a);
     }
     return hipGetLastError();
 }
 
-// dw4: the first pass stages rows of X with 4-byte direct loads (rows whose
-// stride is a multiple of 4 but not of 16 bytes)
 template <typename TIN, int CW>
-hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, bool dw4) {
+hipError_t launch_stream(hipStream_t st, const PassArgs& a, int64_t grid, bool first, bool last, int xs) {
     if (first && last) return hipErrorInvalidValue;
-    if (first && dw4) return launch_stream_one<TIN, CW, true, false, 4>(st, a, grid);
+    if (first && xs == XS_NONE) return hipErrorInvalidValue;
+    if (first && xs == XS_16L) return launch_stream_one<TIN, CW, true, false, true>(st, a, grid);
     if (first) return launch_stream_one<TIN, CW, true, false>(st, a, grid);
     if (last) return launch_stream_one<TIN, CW, false, true>(st, a, grid);
     return launch_stream_one<TIN, CW, false, false>(st, a, grid);
@@ -1709,13 +1659,17 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
     a.row_masks = job.row_masks;
     constexpr int VL = ZVec<TZ>::VL;
     a.xvec = (job.ldx % VL == 0) && ((uintptr_t)job.x % (VL * sizeof(TIN)) == 0);
-    // the first pass stages rows of X with 16-byte direct loads
-    const bool xdma = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
-    // FP8 rows of a length that is a multiple of 4 bytes (4-byte direct loads)
-    const bool xdma4 = std::is_same<TIN, fp8_t>::value && (uintptr_t)job.x % 4 == 0 && job.ldx % 4 == 0;
-    // rows of any type whose stride is a multiple of 4 bytes (the streaming
-    // first pass with 4-byte direct loads)
-    const bool xdma4s = (uintptr_t)job.x % 4 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 4 == 0;
+    // the first pass stages rows of X with 16-byte direct loads: rows
+    // 16-byte aligned, or only 4-byte aligned when the job brings a padded
+    // copy of row N - 1 (the last piece of a row may reach into the next)
+    const bool x16 = (uintptr_t)job.x % 16 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 16 == 0;
+    const bool x4 = (uintptr_t)job.x % 4 == 0 && (job.ldx * (int64_t)sizeof(TIN)) % 4 == 0;
+    const bool x16l = !x16 && x4 && job.x_last != nullptr && job.N >= 2;
+    const bool xdma = x16 || x16l;
+    // staging of the first pass when it runs on a staged kernel (other rows
+    // take the tiled kernel)
+    const int xs = x16 ? XS_16 : x16l ? XS_16L : XS_NONE;
+    a.x_last = x16l ? job.x_last : nullptr;
     const int split = fwht_split_tables(job.in_dtype, L, job.ldz, job.seg_bytes);
     // column width of the streaming kernel for a pass (0: one tile per block).
     // 11-bit passes would need 64-byte rows (CW = 16); with chunk-major Z the
@@ -1727,7 +1681,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
         // for 8 bits would spill registers in the first pass
         const int scw = nb == 10 ? 32 : nb == 9 ? 64 : 0;
         if (!job.stream || job.num_cu <= 0 || !scw || passes < 2 || job.seg_bytes > 0 || job.ldz % scw != 0 ||
-            (first && !xdma && !xdma4s))
+            (first && !xdma))
             return 0;
         return scw;
     };
@@ -1766,7 +1720,7 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
             // 11-bit passes of 128-byte row segments stage quarter tiles in
             // a ring (seg_bytes -64: half tiles)
             if (nb == NB_MAX && job.stream && job.num_cu > 0 &&
-                (first ? (split & 1) && (xdma || xdma4) && job.row_masks : (split & 2) && job.slot_pairs)) {
+                (first ? (split & 1) && xdma && job.row_masks : (split & 2) && job.slot_pairs)) {
                 a.lo = lo;
                 a.nb = nb;
                 a.q = 4;
@@ -1776,8 +1730,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
                 const bool ring = job.seg_bytes != -64;
-                const hipError_t e = ring ? launch_ring<TIN>(st, a, grid, first, last, first && !xdma)
-                                          : launch_split<TIN>(st, a, grid, first, last, first && !xdma);
+                const hipError_t e = ring ? launch_ring<TIN>(st, a, grid, first, last, xs)
+                                          : launch_split<TIN>(st, a, grid, first, last, xs);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);
@@ -1796,8 +1750,8 @@ hipError_t run_passes(hipStream_t st, const FwhtJob& job) {
                 a.zin = job.zbuf;
                 a.zout = job.zbuf;
                 const int64_t grid = std::min<int64_t>(job.num_cu, a.ntiles);
-                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last, first && !xdma)
-                                               : launch_stream<TIN, 64>(st, a, grid, first, last, first && !xdma);
+                const hipError_t e = scw == 32 ? launch_stream<TIN, 32>(st, a, grid, first, last, xs)
+                                               : launch_stream<TIN, 64>(st, a, grid, first, last, xs);
                 if (e != hipSuccess) return e;
                 if (ev1) {
                     const hipError_t e1 = hipEventRecord(ev1, st);

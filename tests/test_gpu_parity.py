@@ -200,8 +200,9 @@ def test_sketch_streaming_transform_matches_tiled(S, ctx, storage, N, d):
     # N' = 2^20 (two 10-bit passes): the default transform streams tiles
     # through LDS in persistent blocks; transform_segment = 256 forces one
     # tile per block.  Same butterflies in the same order -> identical bits
-    # (d = 37, 26 (BF16), 44 (FP8): rows of X not 16-byte aligned, the
-    # streamed first pass stages them with 4-byte direct loads, Z row-major;
+    # (d = 37, 26 (BF16), 44 (FP8): rows of X only 4-byte aligned, staged
+    # with 16-byte loads that may reach into the next row and row N - 1 from
+    # its padded copy, Z row-major;
     # N' = 2^21: an 11-bit first pass, half-tile staged by default, with
     # chunk-major Z in both runs)
     _log(f"sketch streaming {storage} N={N} d={d}")
@@ -223,8 +224,9 @@ def test_sketch_streaming_nine_bit_passes_match_tiled(S, ctx, storage, N, d, L):
     # 9-bit passes stream 512-row x 256-byte tiles: N' = 2^18 (9 + 9 bits,
     # chunk-major Z), 2^19 (10 + 9: two tile widths, Z row-major) and 2^17
     # (9 + 8: the 8-bit pass stays tiled); d = 37, 26 (BF16), 44 (FP8): rows
-    # of X not 16-byte aligned, staged with 4-byte direct loads.  Same butterflies in the same order -> identical
-    # bits to one tile per block.
+    # of X only 4-byte aligned (16-byte loads, row N - 1 from its padded
+    # copy).  Same butterflies in the same order -> identical bits to one
+    # tile per block.
     _log(f"sketch streaming 9-bit {storage} N={N} d={d}")
     p = _problem(N, d, storage=storage, seed=N % 83)
     rows = []
@@ -242,10 +244,11 @@ def test_sketch_streaming_nine_bit_passes_match_tiled(S, ctx, storage, N, d, L):
                                          ("bf16", 1_200_000, 64)])
 def test_sketch_split_eleven_bit_passes_match_tiled(S, ctx, storage, N, d):
     # 11-bit passes stage half-tiles of 2048 rows x 128 bytes: N' = 2^22
-    # (11 + 11 bits, both passes; d = 37: rows of X are not 16-byte aligned,
-    # so only the last pass) and N' = 2^21 (the 11-bit first pass, then a
-    # streamed 10-bit pass).  FP8 rows of 44 bytes are staged with 4-byte
-    # direct loads.  transform_segment = 256 runs one tile per block, -64
+    # (11 + 11 bits, both passes) and N' = 2^21 (the 11-bit first pass, then
+    # a streamed 10-bit pass).  Rows of X only 4-byte aligned (d = 37 FP32,
+    # FP8 rows of 44 bytes) are staged with 16-byte loads that may reach
+    # into the next row, row N - 1 from its padded copy.
+    # transform_segment = 256 runs one tile per block, -64
     # half-tile staging (the default and -32: the quarter-tile ring).  Same
     # butterflies in the same order -> identical bits.
     _log(f"sketch split 11-bit {storage} N={N} d={d}")
