@@ -83,7 +83,8 @@ KT_NAMES = ["transform_first_pass", "transform_last_pass", "product_S", "product
             "phase_A", "phase_B"]
 KT_KERNELS = ["fwht_ring_kernel / fwht_stream_kernel / fwht_pass_kernel (first SRHT pass: gather X[p(k)], "
               "signs, first bits; writes Z)",
-              "fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (last SRHT pass: remaining bits, "
+              "fwht_ring_kernel / fwht_split_kernel / fwht_stream_kernel / fwht_pass_kernel (last SRHT pass: "
+              "remaining bits, "
               "scatter to S_K X and S_hat X)",
               "product_ring_kernel (S mode: s = c2 A^T A p, Stage I)",
               "product_ring_kernel (G mode: stage-start gradient)",
