@@ -825,6 +825,55 @@ __device__ void colwise_dot(const double* a, const double* b, int64_t ldv, int d
     __syncthreads();
 }
 
+// Step 1 of the d-space update: the task partials of every element summed
+// in task order, one thread per element of the d x 16 block and RS_SLICES
+// blocks per problem (a problem can have thousands of tasks when few
+// problems are active; one block per problem then waited out their loads
+// one after another).  Per element the order is the tasks' order, so the
+// sums do not depend on the launch shape.  Writes G (starts), S and Gt.
+constexpr int RS_SLICES = MR_DMAX * KP / DS_THREADS;
+__global__ __launch_bounds__(DS_THREADS) void mrhs_reduce_kernel(int variant, const MrhsProblem* __restrict__ probs,
+                                                                  const float* __restrict__ part_s,
+                                                                  const float* __restrict__ part_g) {
+    const MrhsProblem pb = probs[blockIdx.y];
+    if (!pb.active) return;
+    const int d = pb.d, k = pb.k;
+    const int e = blockIdx.x * DS_THREADS + threadIdx.x;   // element j KP + c
+    const int j = e / KP, c = e % KP;
+    if (j >= d || c >= k) return;
+    const bool start = variant == PA_START || variant == PA_START_NESTED;
+    const bool want_s = !start, want_g = variant != PA_STEP;
+    constexpr int U = 8;   // tasks whose loads are in flight together
+    double ss = 0.0, gg = 0.0;
+    int t = pb.t0;
+    for (; t + U <= pb.t1; t += U) {
+        float vs[U], vg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t o = (int64_t)(t + u) * MR_DMAX * KP + e;
+            vs[u] = want_s ? part_s[o] : 0.f;
+            vg[u] = want_g ? part_g[o] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ss += (double)vs[u];
+            gg += (double)vg[u];
+        }
+    }
+    for (; t < pb.t1; ++t) {
+        const int64_t o = (int64_t)t * MR_DMAX * KP + e;
+        if (want_s) ss += (double)part_s[o];
+        if (want_g) gg += (double)part_g[o];
+    }
+    const int64_t o = c * pb.ldv + j;
+    if (start) {
+        pb.G[o] = variant == PA_START_NESTED && pb.gscale != 0.0 ? fma(pb.gscale, pb.G[o], gg * pb.c2) : gg * pb.c2;
+    } else {
+        pb.S[o] = ss * pb.c2;
+        if (variant == PA_REFRESH) pb.Gt[o] = gg * pb.c2;
+    }
+}
+
 __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, const MrhsProblem* __restrict__ probs,
                                                                   const float* __restrict__ part_s,
                                                                   const float* __restrict__ part_g,
@@ -839,55 +888,33 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_kernel(int variant, co
     const int64_t ldv = pb.ldv;
     // PA_START_NESTED starts like PA_START, from g = gscale g + c2 (partials)
     const bool start = variant == PA_START || variant == PA_START_NESTED;
-    const bool want_s = !start, want_g = variant != PA_STEP;
-    // 1. reduce the task partials, each element in task order.  The task
-    //    loop is outside: per task, EQ elements per thread have their loads
-    //    in flight together (element-by-element it would wait out one load
-    //    latency per task and element).
-    {
-        constexpr int EQ = 16;
-        const int ne = d * KP;
-        for (int e0 = threadIdx.x; e0 < ne; e0 += EQ * DS_THREADS) {
-            double ss[EQ], gg[EQ];
-#pragma unroll
-            for (int q = 0; q < EQ; ++q) ss[q] = gg[q] = 0.0;
-            for (int t = pb.t0; t < pb.t1; ++t) {
-                const int64_t base = (int64_t)t * MR_DMAX * KP;   // element e = j KP + c of task t
-#pragma unroll
-                for (int q = 0; q < EQ; ++q) {
-                    const int e = e0 + q * DS_THREADS;
-                    if (e < ne && e % KP < k) {
-                        if (want_s) ss[q] += (double)part_s[base + e];
-                        if (want_g) gg[q] += (double)part_g[base + e];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < EQ; ++q) {
-                const int e = e0 + q * DS_THREADS;
-                if (e >= ne) continue;
-                const int j = e / KP, c = e % KP;
-                if (c >= k) continue;
-                if (start) {
-                    const int64_t o = c * ldv + j;
-                    pb.G[o] = variant == PA_START_NESTED && pb.gscale != 0.0 ? fma(pb.gscale, pb.G[o], gg[q] * pb.c2)
-                                                                           : gg[q] * pb.c2;
-                } else {
-                    pb.S[c * ldv + j] = ss[q] * pb.c2;
-                    if (variant == PA_REFRESH) pb.Gt[c * ldv + j] = gg[q] * pb.c2;
-                }
-            }
-        }
-    }
-    if (want_g && threadIdx.x < KP) {
+    const bool want_g = variant != PA_STEP;
+    // 1. the element sums are mrhs_reduce_kernel's (launched before); the
+    //    residual and fit norms of each column: 32 groups of threads take
+    //    every 32nd task in order, then the groups add in group order
+    if (want_g) {
+        constexpr int NG = DS_THREADS / KP;   // 32 groups of 16 columns
+        const int c = threadIdx.x % KP, g = threadIdx.x / KP;
         double r2 = 0.0, ax2 = 0.0;
-#pragma unroll 8
-        for (int t = pb.t0; t < pb.t1; ++t) {
-            r2 += (double)part_scal[(int64_t)t * 2 * KP + threadIdx.x];
-            ax2 += (double)part_scal[(int64_t)t * 2 * KP + KP + threadIdx.x];
+        for (int t = pb.t0 + g; t < pb.t1; t += NG) {
+            r2 += (double)part_scal[(int64_t)t * 2 * KP + c];
+            ax2 += (double)part_scal[(int64_t)t * 2 * KP + KP + c];
         }
-        colv[threadIdx.x] = r2 * pb.c2;
-        colw[threadIdx.x] = ax2 * pb.c2;
+        red[g][c] = r2;
+        __syncthreads();
+        if (threadIdx.x < KP) {
+            double v = 0.0;
+            for (int q = 0; q < NG; ++q) v += red[q][c];
+            colv[c] = v * pb.c2;
+        }
+        __syncthreads();
+        red[g][c] = ax2;
+        __syncthreads();
+        if (threadIdx.x < KP) {
+            double v = 0.0;
+            for (int q = 0; q < NG; ++q) v += red[q][c];
+            colw[c] = v * pb.c2;
+        }
     }
     __syncthreads();
     if (want_g && threadIdx.x < k) {
@@ -1065,8 +1092,11 @@ __global__ __launch_bounds__(DS_THREADS) void mrhs_dspace_p_kernel(int variant, 
 hipError_t run_mrhs_dspace(hipStream_t st, int variant, const MrhsProblem* probs, int nprob,
                            const float* part_s, const float* part_g, const float* part_scal) {
     if (nprob <= 0) return hipSuccess;
-    mrhs_dspace_kernel<<<nprob, DS_THREADS, 0, st>>>(variant, probs, part_s, part_g, part_scal);
+    mrhs_reduce_kernel<<<dim3(RS_SLICES, nprob), DS_THREADS, 0, st>>>(variant, probs, part_s, part_g);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    mrhs_dspace_kernel<<<nprob, DS_THREADS, 0, st>>>(variant, probs, part_s, part_g, part_scal);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     mrhs_dspace_z_kernel<<<dim3(ZSL, nprob), DS_THREADS, 0, st>>>(probs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
