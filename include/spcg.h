@@ -67,7 +67,11 @@ typedef struct spcg_precond_s spcg_precond_t;
 
 /* A dense row-major matrix view.  col_scale is used only for SPCG_FP8E4M3
  * (device array of cols floats, must be non-null then) and ignored
- * otherwise. */
+ * otherwise.  Any ld >= cols is accepted.  The direct-load kernels take
+ * rows whose start address and byte stride are multiples of 4 (multiples
+ * of 16 read fastest; dense rows, ld == cols, that are only 4-byte aligned
+ * also take 16-byte loads, which may read up to 12 bytes into the next
+ * row); other layouts run on slower element-wise kernels. */
 typedef struct spcg_mat {
     const void* data;
     int32_t dtype;
