@@ -166,6 +166,7 @@ struct ProdArgs {
     int64_t dpad;
     const int32_t* gate;   // optional: return at once unless *gate >= gmin
     int32_t gmin;
+    int32_t lshift;        // 16-byte loads of rows only 4-byte aligned: the last row's loads start this many bytes early
 };
 
 // a launch switched off by a device-side decision (uniform over the grid)
@@ -389,19 +390,33 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
     constexpr int RING = ring_depth(SLOT);
     static_assert(DCOLS * 8 <= NW * RW, "reduction buffers alias the ring");
     static_assert((RING - 2) * NOPS < 64, "vmcnt range");
-    // one LDS object per slot (slots past RING are 16-byte placeholders)
-    __shared__ __align__(16) unsigned char t0[SLOT];
-    __shared__ __align__(16) unsigned char t1[SLOT];
-    __shared__ __align__(16) unsigned char t2[SLOT];
-    __shared__ __align__(16) unsigned char t3[SLOT];
-    __shared__ __align__(16) unsigned char t4[RING > 4 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t5[RING > 5 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t6[RING > 6 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t7[RING > 7 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t8[RING > 8 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t9[RING > 9 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t10[RING > 10 ? SLOT : 16];
-    __shared__ __align__(16) unsigned char t11[RING > 11 ? SLOT : 16];
+    // one LDS object per slot (slots past RING are 16-byte placeholders),
+    // each after a 16-byte guard: the loads of a shifted last row (see
+    // issue) begin up to 12 bytes before its staging row
+    __shared__ __align__(16) unsigned char t0_[SLOT + 16];
+    __shared__ __align__(16) unsigned char t1_[SLOT + 16];
+    __shared__ __align__(16) unsigned char t2_[SLOT + 16];
+    __shared__ __align__(16) unsigned char t3_[SLOT + 16];
+    __shared__ __align__(16) unsigned char t4_[RING > 4 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t5_[RING > 5 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t6_[RING > 6 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t7_[RING > 7 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t8_[RING > 8 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t9_[RING > 9 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t10_[RING > 10 ? SLOT + 16 : 32];
+    __shared__ __align__(16) unsigned char t11_[RING > 11 ? SLOT + 16 : 32];
+    unsigned char* const t0 = t0_ + 16;
+    unsigned char* const t1 = t1_ + 16;
+    unsigned char* const t2 = t2_ + 16;
+    unsigned char* const t3 = t3_ + 16;
+    unsigned char* const t4 = t4_ + 16;
+    unsigned char* const t5 = t5_ + 16;
+    unsigned char* const t6 = t6_ + 16;
+    unsigned char* const t7 = t7_ + 16;
+    unsigned char* const t8 = t8_ + 16;
+    unsigned char* const t9 = t9_ + 16;
+    unsigned char* const t10 = t10_ + 16;
+    unsigned char* const t11 = t11_ + 16;
     __shared__ double red_scal[2 * NW];
     auto slot = [&](auto kc) -> unsigned char* {
         constexpr int k = decltype(kc)::value;
@@ -451,6 +466,25 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
     const char* Abase = static_cast<const char*>(a.A);
     const int64_t row_bytes = a.lda * Store<TS>::BYTES;
     const int64_t vlast = a.nvec - 1;
+    // Rows only 4-byte aligned (16-byte loads, lshift > 0): a row's last
+    // vector reaches up to 12 bytes into the next row, except for the
+    // matrix's last row (in the last block), whose vectors start lshift
+    // bytes early (in the previous row) and land lshift bytes early in LDS,
+    // so that its data sits where the reader expects it.  The last lshift
+    // bytes of its staging row are then not loaded; they are read as
+    // columns past d (times zero), so every staging row's last 16 bytes
+    // start at zero here, before any load.
+    const bool shifted = DMAB == 16 && a.lshift > 0 && r1 == a.m;
+    if (shifted) {
+        for (int e = threadIdx.x; e < RING * RPW * NW; e += 64 * NW) {
+            const int sidx = e / (RPW * NW), rowi = e % (RPW * NW);
+            unsigned char* sb = sidx == 0 ? t0 : sidx == 1 ? t1 : sidx == 2 ? t2 : sidx == 3 ? t3 : sidx == 4 ? t4
+                              : sidx == 5 ? t5 : sidx == 6 ? t6 : sidx == 7 ? t7 : sidx == 8 ? t8 : sidx == 9 ? t9
+                              : sidx == 10 ? t10 : t11;
+            *reinterpret_cast<uint4*>(sb + rowi * RW + RW - 16) = make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
+    }
 
     // row rr of this wave in tile `tile` (rows of a wave stay in order)
     auto row_of = [&](int64_t tile, int rr) -> int64_t { return r0 + (tile * RPW + rr) * NW + wave; };
@@ -458,11 +492,13 @@ __global__ __launch_bounds__(64 * NW) void product_ring_kernel(ProdArgs a) {
 #pragma unroll
         for (int rr = 0; rr < RPW; ++rr) {
             const int64_t row = min(row_of(tile, rr), rlast);
-            const char* src = Abase + row * row_bytes;
+            const int sh = (shifted && row == a.m - 1) ? a.lshift : 0;
+            const char* src = Abase + row * row_bytes - sh;
+            unsigned char* dst = T + (rr * NW + wave) * RW - sh;
 #pragma unroll
             for (int s = 0; s < NSLOT; ++s) {
                 const int64_t vi = min<int64_t>(s * 64 + lane, vlast);
-                lds_load<DMAB>(src + vi * DMAB, T + (rr * NW + wave) * RW + s * 64 * DMAB);
+                lds_load<DMAB>(src + vi * DMAB, dst + s * 64 * DMAB);
             }
             if constexpr (DO_G) {
                 lds_load<4>(reinterpret_cast<const char*>(a.b + row * a.ldbv) + 4 * (lane & 1),
@@ -693,8 +729,17 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
         if (dmab < bytes) continue;
         const int rv = dmab / bytes;
         const int64_t nv = ceil_div(j.d, rv);
-        const bool ok = (j.lda * bytes) % dmab == 0 && (uintptr_t)j.A % dmab == 0 && nv * rv <= j.dmem &&
-                        (j.mode == PM_S || j.ldbv >= 1);
+        const bool mode_ok = j.mode == PM_S || j.ldbv >= 1;
+        bool ok = (j.lda * bytes) % dmab == 0 && (uintptr_t)j.A % dmab == 0 && nv * rv <= j.dmem && mode_ok;
+        int lshift = 0;
+        if (!ok && dmab == 16 && mode_ok && (j.lda * bytes) % 4 == 0 && (uintptr_t)j.A % 4 == 0 && j.lda == j.dmem &&
+            j.d * bytes >= 16 && j.m >= 2) {
+            // rows only 4-byte aligned whose every stride byte is readable:
+            // 16-byte loads reach into the next row, the last row is loaded
+            // early (the kernel's shifted rows)
+            ok = true;
+            lshift = (int)(nv * 16 - j.d * bytes);
+        }
         if (!ok) continue;
         if (nv <= 32 || nv > 256) break;
         int ns = 1;
@@ -721,6 +766,7 @@ hipError_t run_product(hipStream_t st, const ProdJob& j, int* nblocks_out) {
         a.dpad = j.dpad;
         a.gate = j.gate;
         a.gmin = j.gmin;
+        a.lshift = lshift;
         hipError_t e;
         switch (j.dtype) {
             case DT_F64: e = launch_ring_type<double>(st, a, j.mode, (int)nb, dmab, ns); break;

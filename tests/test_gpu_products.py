@@ -26,7 +26,7 @@ CASES = [
     ("f64", 5003, 100, 100),     # staged, 16-byte loads, 1 vector per lane
     ("f64", 4099, 250, 256),     # staged, 16-byte loads, 2 vectors per lane, padded ld
     ("f32", 9001, 132, 132),     # staged, 16-byte, 1 vector
-    ("f32", 9001, 129, 129),     # staged, 4-byte loads (ld*4 not a multiple of 16), 4 per lane
+    ("f32", 9001, 129, 129),     # staged, 16-byte loads of rows only 4-byte aligned (last row shifted)
     ("f32", 20011, 500, 500),    # staged, 16-byte, 2 vectors
     ("f32", 7013, 1000, 1024),   # staged, 16-byte, 4 vectors, padded ld
     ("f32", 5000, 250, 251),     # staged, 4-byte loads, odd ld
@@ -34,7 +34,7 @@ CASES = [
     ("bf16", 12007, 1000, 1000), # staged, 16-byte, 2 vectors
     ("bf16", 6001, 300, 302),    # staged, 4-byte loads, padded ld
     ("fp8", 4003, 1024, 1024),   # staged, 16-byte, 1 vector of 16
-    ("fp8", 8009, 1000, 1000),   # staged, 4-byte loads (ld not a multiple of 16)
+    ("fp8", 8009, 1000, 1000),   # staged, 16-byte loads of rows only 4-byte aligned (last row shifted)
     ("fp8", 3001, 700, 704),     # staged, 4-byte loads (16-byte vectors would pass d)
     ("fp8", 2003, 64, 64),       # register kernel
 ]
