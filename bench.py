@@ -94,8 +94,8 @@ BYTE_CLASSES = range(5)
 # HBM bytes per launch from rocprofv3 PMC runs (2.0 x FETCH_SIZE + WRITE_SIZE,
 # calibrated on a 1 GiB copy) for a kernel class and workload, taken on the
 # kernel as it now stands; everything else reports null.
-_T3_F32 = {"transform_first_pass": 3.4605e10, "transform_last_pass": 2.5962e10, "product_S": 1.6782e9,
-           "product_G": 3.3744e9, "product_SG": 1.6036e10}   # profiles/hbm_traffic_t3corr_N4e6_d1000_f32.txt
+_T3_F32 = {"transform_first_pass": 3.4561e10, "transform_last_pass": 2.5994e10, "product_S": 1.6782e9,
+           "product_G": 3.3745e9, "product_SG": 1.6036e10}   # profiles/hbm_traffic_t3corr_N4e6_d1000_f32.txt
 PMC_TRAFFIC = {(k, w): v for k, v in _T3_F32.items() for w in ("cfg2", "cfg2f32")}
 
 
