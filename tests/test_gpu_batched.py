@@ -237,7 +237,7 @@ def test_batched_nested_gradient_start(S, ctx):
 
 @pytest.mark.parametrize("storage,d,k,m", [("f32", 37, 3, 1000), ("f32", 50, 4, 777), ("f32", 6, 2, 300),
                                            ("f32", 241, 2, 500), ("f32", 254, 16, 1003), ("f32", 301, 5, 600),
-                                           ("f32", 510, 9, 999), ("bf16", 38, 4, 700)])
+                                           ("f32", 510, 9, 999), ("bf16", 38, 4, 700), ("f32", 37, 2, 40)])
 def test_unaligned_rows_match_padded_rows(S, ctx, storage, d, k, m):
     # Dense rows whose byte length is a multiple of 4 but not of 16 are read
     # with 16-byte loads from 4-byte aligned addresses (a row's last vector

@@ -35,6 +35,7 @@ CASES = [
     ("bf16", 6001, 300, 302),    # staged, 4-byte loads, padded ld
     ("fp8", 4003, 1024, 1024),   # staged, 16-byte, 1 vector of 16
     ("fp8", 8009, 1000, 1000),   # staged, 16-byte loads of rows only 4-byte aligned (last row shifted)
+    ("fp8", 1001, 1000, 1000),   # the same with one row per block-tile tail (last block of 9 rows)
     ("fp8", 3001, 700, 704),     # staged, 4-byte loads (16-byte vectors would pass d)
     ("fp8", 2003, 64, 64),       # register kernel
 ]
