@@ -1194,6 +1194,38 @@ int lane_fail(spcg_ctx* ctx, spcg_ctx* lane, int rc) {
     return rc;
 }
 
+// The order in which the setup work of the problems is queued: round r
+// queues the r-th problem of every lane.  Problems go to lanes longest
+// first onto the least loaded lane by an estimate of their cost (what a
+// problem computes does not depend on its lane).
+std::vector<std::pair<int, int>> lane_schedule(const std::vector<double>& cost) {
+    constexpr int NL = BatchWork::NLANE;
+    const int n = (int)cost.size();
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<int>> lanes(NL);
+    double load[NL] = {};
+    for (int p : order) {
+        int best = 0;
+        for (int i = 1; i < NL; ++i)
+            if (load[i] < load[best]) best = i;
+        lanes[best].push_back(p);
+        load[best] += cost[p];
+    }
+    std::vector<std::pair<int, int>> q;   // (problem, lane)
+    for (size_t r = 0;; ++r) {
+        bool any = false;
+        for (int i = 0; i < NL; ++i)
+            if (r < lanes[i].size()) {
+                q.emplace_back(lanes[i][r], i);
+                any = true;
+            }
+        if (!any) break;
+    }
+    return q;
+}
+
 int batch_streams(spcg_ctx* ctx, BatchWork& W) {
     if (W.cap) return SPCG_OK;
     for (auto& q : W.cls) HIP_TRY(ctx, hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
@@ -1483,12 +1515,19 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
     // (problem p on lane p mod NLANE), each phase joined back into st
     if ((rc = batch_streams(ctx, W)) != SPCG_OK) return rc;
     if ((rc = batch_lanes(ctx, W)) != SPCG_OK) return rc;
+    // The sketches keep problem p on lane p mod NLANE: their phase keeps the
+    // GPU busy throughout, and balancing their estimated bytes over the lanes
+    // measured no faster.  The preconditioners are chains of small dependent
+    // kernels (a chain grows with the 64-column panels), balanced over the
+    // lanes below.
     if ((rc = lanes_fork(ctx, W, st)) != SPCG_OK) return rc;
     for (int p = 0; p < nprob; ++p) {
         spcg_ctx* ln = W.lane[p % BatchWork::NLANE];
         if ((rc = sketch_build(ln, &X[p], &Y[p], &so, false, W.sk[p])) != SPCG_OK) return lane_fail(ctx, ln, rc);
     }
     if ((rc = lanes_join(ctx, W, st)) != SPCG_OK) return rc;
+    std::vector<double> cost_pc(nprob);
+    for (int p = 0; p < nprob; ++p) cost_pc[p] = 1.0 + (double)ceil_div(X[p].cols, 64);
     if (timing) HIP_TRY(ctx, hipEventRecord(ctx->ev_phase[1], st));
     const int qmode = opts->precond.qr_passes;
     const bool defer = qmode == 0 || qmode == 1;
@@ -1500,8 +1539,9 @@ int batched_solve(spcg_ctx* ctx, int nprob, const spcg_mat* X, const spcg_mat* Y
         W.hstat_n = (size_t)nprob;
     }
     if ((rc = lanes_fork(ctx, W, st)) != SPCG_OK) return rc;
-    for (int p = 0; p < nprob; ++p) {
-        spcg_ctx* ln = W.lane[p % BatchWork::NLANE];
+    for (const auto& pl : lane_schedule(cost_pc)) {
+        const int p = pl.first;
+        spcg_ctx* ln = W.lane[pl.second];
         if ((rc = precond_build(ln, W.sk[p], &opts->precond, false, W.pc[p], defer ? &W.hstat[p] : nullptr)) !=
             SPCG_OK)
             return lane_fail(ctx, ln, rc);
